@@ -1,0 +1,262 @@
+"""Construction of the inverse database and the patch map phi (Section 3).
+
+* ``alg1_tolerance``: Algorithm 1 (patch tolerance construction), literal
+  double loop in patch order with first-match semantics.
+* ``kmeans``: Algorithm 2 (spectral clustering construction) and its variants
+  listed in Section 3.2 (entrywise k-means, spectral k-means,
+  variance-minimising clustering, bootstrapping), with the boundary
+  partitioning and proportional apportionment of Section 3.2.
+
+Readings taken where the paper is silent (each also listed in the design notes):
+* indices are 0-based; database entries are numbered in append order;
+* comparisons against the tolerance are strict (d < eps), as printed;
+* Algorithm 2's initial ``randperm(n_p, m_p)`` draws m_p distinct patches as
+  initial representatives; the draw is a partial Fisher-Yates shuffle driven by
+  SplitMix64 so that any implementation can reproduce it bit for bit;
+* argmin ties: a relative band tie_rel around the minimum; the current
+  assignment is kept if it lies in the band, else the lowest index in it;
+* an empty cluster keeps its previous centre;
+* the loop stops when no assignment changes or after max_iter passes; the
+  final database is the one used in the last assignment pass;
+* "the member which minimises the in-cluster variance" is the member whose
+  matrix is nearest (Frobenius) to the entrywise cluster mean, which equals
+  argmin_m sum_k ||A_k - A_m||_F^2; members within the relative tie band
+  of the smallest distance count as tied and the lowest patch id wins (a
+  two-member cluster is always an exact tie);
+* apportionment: largest-remainder method in exact integer arithmetic, with
+  at least one cluster per non-empty group and at most the group size.
+
+Test infrastructure only (see the package docstring).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .criterion import crit_spectral_x, crit_l1, crit_fro
+from .patch import OracleError, factor_inverse, boundary_mask
+
+_MASK64 = (1 << 64) - 1
+
+
+class SplitMix64:
+    """SplitMix64 (Steele, Lea, Flood 2014): state += golden gamma, then two
+    xor-shift-multiply rounds and a final xor-shift; arithmetic mod 2^64."""
+
+    def __init__(self, seed: int):
+        self.state = seed & _MASK64
+
+    def next(self) -> int:
+        self.state = (self.state + 0x9E3779B97F4A7C15) & _MASK64
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+        return z ^ (z >> 31)
+
+
+def _dist(crit, Ai, Bj, Xj):
+    if crit == "spectral":
+        return crit_spectral_x(Ai, Xj)
+    if crit == "l1":
+        return crit_l1(Ai, Bj)
+    if crit == "fro":
+        return crit_fro(Ai, Bj)
+    raise ValueError(crit)
+
+
+def alg1_tolerance(tiles, eps, crit="spectral"):
+    """Algorithm 1: greedy tolerance construction of the database and phi.
+
+    Visit patches in order; compare with the database entries in append order
+    and take the first with d < eps; with no match, append the patch's inverse
+    and map the patch to the new entry.
+    Returns dict(phi, reps, X, evals, margin): reps are the patch ids whose
+    inverses form the database, evals counts criterion evaluations and margin
+    is min |d - eps| / eps over every comparison made.
+    """
+    reps, X, B = [], [], []
+    phi = np.zeros(len(tiles), dtype=np.int64)
+    evals = 0
+    margin = np.inf
+    for i, Ai in enumerate(tiles):
+        match = False
+        for j in range(len(reps)):
+            d = _dist(crit, Ai, B[j], X[j])
+            evals += 1
+            if eps > 0:
+                margin = min(margin, abs(d - eps) / eps)
+            if d < eps:
+                phi[i] = j
+                match = True
+                break
+        if not match:
+            reps.append(i)
+            B.append(Ai)
+            X.append(factor_inverse(Ai))
+            phi[i] = len(reps) - 1
+    return dict(phi=phi, reps=np.asarray(reps, dtype=np.int64), X=X, evals=evals,
+                margin=margin)
+
+
+def alg1_invariants_hold(tiles_of, phi, reps, eps, crit, sample, X_of=None):
+    """Check Algorithm 1's defining properties on sampled patches i:
+    a database entry's patch matches no earlier entry; any other patch matches
+    its entry (d < eps) and no earlier entry (d >= eps).  ``tiles_of(k)``
+    returns the tile of patch k so that huge inputs need not be materialised.
+    """
+    X_of = X_of or (lambda k: factor_inverse(tiles_of(k)))
+    rep_pos = {int(r): j for j, r in enumerate(reps)}
+    for i in sample:
+        Ai = tiles_of(int(i))
+        j = int(phi[i])
+        if int(i) in rep_pos:
+            if rep_pos[int(i)] != j:
+                return False
+            earlier = range(j)
+        else:
+            if reps[j] >= i:
+                return False
+            if not _dist(crit, Ai, tiles_of(int(reps[j])), X_of(int(reps[j]))) < eps:
+                return False
+            earlier = range(j)
+        for jj in earlier:
+            r = int(reps[jj])
+            if _dist(crit, Ai, tiles_of(r), X_of(r)) < eps:
+                return False
+    return True
+
+
+def partition_groups(tiles, partition=True):
+    """Boundary partitioning (Section 3.2): group patches whose boundary
+    conditions sit in the same local rows; groups in ascending key order (the
+    interior, key 0, first); members in ascending patch id."""
+    if not partition:
+        return [(0, np.arange(len(tiles), dtype=np.int64))]
+    keys = np.array([boundary_mask(t) for t in tiles], dtype=np.int64)
+    return [(int(k), np.flatnonzero(keys == k)) for k in np.unique(keys)]
+
+
+def apportion(sizes, m_total):
+    """Split m_total clusters over groups roughly in proportion to their
+    sizes (Section 3.2).
+
+    Largest-remainder method in exact integer arithmetic: group g first gets
+    floor(m_total * n_g / N); the seats left go one each to the groups with
+    the largest remainders (ties: lower group).  A group left with none then
+    takes one from the group holding the most (ties: lower group), so every
+    group has at least one cluster and never more than its size.
+    """
+    sizes = [int(s) for s in sizes]
+    N = sum(sizes)
+    G = len(sizes)
+    if m_total < G:
+        raise OracleError("fewer clusters than boundary groups")
+    if m_total > N:
+        raise OracleError("more clusters than patches")
+    base = [(m_total * s) // N for s in sizes]
+    rem = [(m_total * s) % N for s in sizes]
+    left = m_total - sum(base)
+    for g in sorted(range(G), key=lambda g: (-rem[g], g))[:left]:
+        base[g] += 1
+    while 0 in base:
+        g0 = base.index(0)
+        donor = max(range(G), key=lambda g: (base[g], -g))
+        base[donor] -= 1
+        base[g0] += 1
+    return base
+
+
+def _initial_reps(groups, m_per, rng):
+    """Partial Fisher-Yates draw of m_g distinct members per group, groups in
+    order, one SplitMix64 stream: j = i + (u mod (len - i))."""
+    out = []
+    for (key, members), m_g in zip(groups, m_per):
+        a = list(int(x) for x in members)
+        L = len(a)
+        for i in range(m_g):
+            u = rng.next()
+            j = i + (u % (L - i))
+            a[i], a[j] = a[j], a[i]
+        out.append(a[:m_g])
+    return out
+
+
+def kmeans(tiles, m_p, variant="spectral", seed=5, max_iter=100, partition=True,
+           tie_rel=1e-9, init_reps=None):
+    """Algorithm 2 and the variants of Section 3.2.
+
+    variant: 'spectral'  d = ||I - A B^{-1}||_2, centre = entrywise mean (Eq.(6));
+             'entrywise' d = l1 difference to the mean matrix, centre = mean;
+             'varmin'    d spectral, centre = member nearest the mean;
+             'bootstrap' initial database from Algorithm 1 (``init_reps``),
+                         no partitioning, variance-minimising updates.
+    Returns dict(phi, B, X, rep_patch, iters, converged, empty_events, groups).
+    ``rep_patch[j]`` is the patch whose matrix is centre j (-1 for a mean).
+    """
+    if variant == "bootstrap":
+        if init_reps is None:
+            raise ValueError("bootstrap needs Algorithm 1's representatives")
+        groups = [(0, np.arange(len(tiles), dtype=np.int64))]
+        starts = [list(int(r) for r in init_reps)]
+        upd = "varmin"
+        crit = "spectral"
+    else:
+        groups = partition_groups(tiles, partition)
+        m_per = apportion([len(g[1]) for g in groups], m_p)
+        starts = _initial_reps(groups, m_per, SplitMix64(seed))
+        upd = "varmin" if variant == "varmin" else "mean"
+        crit = "l1" if variant == "entrywise" else "spectral"
+
+    n_p = len(tiles)
+    phi = -np.ones(n_p, dtype=np.int64)
+    B_all, X_all, rep_patch = [], [], []
+    iters, conv, empty = [], [], 0
+    for (key, members), start in zip(groups, starts):
+        off = len(B_all)
+        B = [tiles[s].copy() for s in start]
+        X = [factor_inverse(b) for b in B] if crit == "spectral" else [None] * len(B)
+        rp = list(start)
+        loc = -np.ones(len(members), dtype=np.int64)
+        it = 0
+        converged = False
+        while it < max_iter:
+            it += 1
+            changed = False
+            for t, i in enumerate(members):
+                d = np.array([_dist(crit, tiles[i], B[j], X[j]) for j in range(len(B))])
+                dmin = d.min()
+                band = np.flatnonzero(d <= dmin * (1.0 + tie_rel))
+                if loc[t] in band:
+                    continue
+                loc[t] = band[0]
+                changed = True
+            if not changed:
+                converged = True
+                break
+            if it == max_iter:
+                break
+            for j in range(len(B)):
+                mem = members[loc == j]
+                if len(mem) == 0:
+                    empty += 1
+                    continue
+                mean = np.mean(np.stack([tiles[k] for k in mem]), axis=0)
+                if upd == "mean":
+                    B[j] = mean
+                    rp[j] = -1
+                else:
+                    dist = np.array([np.sum((tiles[k] - mean) ** 2) for k in mem])
+                    near = np.flatnonzero(dist <= dist.min() * (1.0 + tie_rel))
+                    m = int(mem[near[0]])          # lowest patch id in the tie band
+                    B[j] = tiles[m].copy()
+                    rp[j] = m
+                if crit == "spectral":
+                    X[j] = factor_inverse(B[j])
+        phi[members] = loc + off
+        B_all += B
+        X_all += [factor_inverse(b) for b in B] if crit != "spectral" else X
+        rep_patch += rp
+        iters.append(it)
+        conv.append(converged)
+    return dict(phi=phi, B=B_all, X=X_all, rep_patch=np.asarray(rep_patch, dtype=np.int64),
+                iters=iters, converged=conv, empty_events=empty,
+                groups=[(k, m) for k, m in groups])

@@ -1,0 +1,174 @@
+"""Pins of the oracle's database construction (Algorithms 1 and 2)."""
+import itertools
+
+import numpy as np
+import pytest
+
+import gen
+import oracle as O
+
+
+def test_alg1_q1_finds_nine_distinct_patches():
+    P = gen.q1_poisson_2d(32)
+    t = O.patch_tiles(P.A, P.ptr, P.dofs)
+    res = O.alg1_tolerance(t, 1e-8)
+    assert len(res['reps']) == 9
+    # append order equals ascending patch id
+    assert np.all(np.diff(res['reps']) > 0)
+    assert O.alg1_invariants_hold(lambda k: t[k], res['phi'], res['reps'], 1e-8, 'spectral',
+                                  range(P.n_p))
+
+
+@pytest.mark.parametrize("make", [lambda: gen.q2_hex_diffusion(4, sigma=0.0),
+                                  lambda: gen.nedelec_hex(4, coeffs=(1, 1, 1, 1))])
+def test_alg1_constant_coefficient_cube_gives_27(make):
+    # constant coefficients on a cube: 8 corners, 12 edges, 6 faces, 1 interior
+    P = make()
+    t = O.patch_tiles(P.A, P.ptr, P.dofs)
+    for crit, eps in [('spectral', 1e-8), ('l1', 1e-7)]:
+        res = O.alg1_tolerance(t, eps, crit)
+        assert len(res['reps']) == 27
+
+
+def test_alg1_stokes_nine():
+    P = gen.taylor_hood_stokes_2d(8)
+    t = O.patch_tiles(P.A, P.ptr, P.dofs)
+    assert len(O.alg1_tolerance(t, 1e-8)['reps']) == 9
+
+
+def test_alg1_first_match_semantics_hand_example():
+    # d(B1,B0) = 0.2, d(A2,B0) = 0.1, d(A2,B1) = 1/12: at eps = 0.15 patch 2
+    # matches both entries and takes the first, although B1 is closer
+    B0 = np.diag([1.0, 1.0])
+    B1 = np.diag([1.2, 1.0])
+    A2 = np.diag([1.1, 1.0])
+    res = O.alg1_tolerance([B0, B1, A2], eps=0.15)
+    assert list(res['reps']) == [0, 1] and list(res['phi']) == [0, 1, 0]
+    res = O.alg1_tolerance([B0, B1, A2], eps=0.09)
+    # B1 does not match B0 (d = 0.2); A2 matches B1 (1/12 < 0.09) but not B0
+    assert list(res['reps']) == [0, 1] and list(res['phi']) == [0, 1, 1]
+
+
+def test_alg1_attains_brute_force_minimum_of_objective():
+    # n_p = 7 patches in 3 identical classes; small beta: Eq.(4)'s minimum over
+    # every database drawn from the patches (with the optimal phi) is attained
+    rng = np.random.default_rng(11)
+    classes = [rng.standard_normal((4, 4)) + 5 * np.eye(4) for _ in range(3)]
+    labels = [0, 1, 0, 2, 1, 1, 0]
+    tiles = [classes[c].copy() for c in labels]
+    beta = 1e-3
+    res = O.alg1_tolerance(tiles, 1e-8)
+    L_alg1 = O.objective(tiles, res['X'], res['phi'], beta)
+    Xall = [O.factor_inverse(t) for t in tiles]
+    best = np.inf
+    for m in range(1, len(tiles) + 1):
+        for sub in itertools.combinations(range(len(tiles)), m):
+            Xs = [Xall[s] for s in sub]
+            d = np.array([[np.linalg.norm(np.eye(4) - A @ X, 2) ** 2 for X in Xs] for A in tiles])
+            best = min(best, beta * m + d.min(axis=1).sum())
+    assert abs(L_alg1 - best) < 1e-12
+    assert len(res['reps']) == 3
+
+
+def test_objective_is_permutation_invariant():
+    rng = np.random.default_rng(1)
+    tiles = [rng.standard_normal((3, 3)) + 4 * np.eye(3) for _ in range(6)]
+    X = [O.factor_inverse(tiles[i]) for i in (0, 3)]
+    phi = np.array([0, 0, 1, 1, 0, 1])
+    a = O.objective(tiles, X, phi, 0.5)
+    b = O.objective(tiles, X[::-1], 1 - phi, 0.5)
+    assert abs(a - b) < 1e-12
+
+
+def test_apportion_examples():
+    assert O.apportion([900, 30, 30, 30, 10], 20) == [16, 1, 1, 1, 1]
+    assert O.apportion([50, 50], 3) == [2, 1]
+    assert O.apportion([10, 10, 10], 3) == [1, 1, 1]
+    with pytest.raises(O.OracleError):
+        O.apportion([5, 5, 5], 2)
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        sizes = list(rng.integers(1, 500, size=int(rng.integers(1, 27))))
+        m = int(rng.integers(len(sizes), sum(sizes) + 1))
+        a = O.apportion(sizes, m)
+        assert sum(a) == m and all(1 <= x <= s for x, s in zip(a, sizes))
+        # roughly proportional: within one seat of the quota, except forced minimums
+        for x, s in zip(a, sizes):
+            q = m * s / sum(sizes)
+            assert x <= np.ceil(q) + 1e-9 or x == 1
+
+
+def test_splitmix64_is_invertible_state_walk():
+    # the output mix is a bijection: undo it and recover seed + k * gamma
+    def unmix(z):
+        M = (1 << 64) - 1
+        def unxs(v, s):
+            x = v
+            for _ in range(64 // s + 1):
+                x = v ^ (x >> s)
+            return x & M
+        z = unxs(z, 31)
+        z = (z * pow(0x94D049BB133111EB, -1, 1 << 64)) & M
+        z = unxs(z, 27)
+        z = (z * pow(0xBF58476D1CE4E5B9, -1, 1 << 64)) & M
+        return unxs(z, 30)
+    g = O.SplitMix64(12345)
+    for k in range(1, 50):
+        assert unmix(g.next()) == (12345 + k * 0x9E3779B97F4A7C15) % (1 << 64)
+
+
+def test_varmin_representative_identity():
+    # member nearest the mean == argmin_m sum_k ||A_k - A_m||_F^2 (brute force)
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        mats = [rng.standard_normal((3, 3)) for _ in range(int(rng.integers(2, 9)))]
+        mean = np.mean(mats, axis=0)
+        near = np.array([np.sum((A - mean) ** 2) for A in mats])
+        pair = np.array([sum(np.sum((Ak - Am) ** 2) for Ak in mats) for Am in mats])
+        # same minimiser; with two members both are exactly tied (rounding decides)
+        band_near = set(np.flatnonzero(near <= near.min() * (1 + 1e-9)))
+        band_pair = set(np.flatnonzero(pair <= pair.min() * (1 + 1e-9)))
+        assert band_near == band_pair
+
+
+@pytest.mark.parametrize("variant", ["spectral", "entrywise", "varmin"])
+def test_kmeans_fixed_point_and_partition(variant):
+    P = gen.q2_hex_diffusion(4, sigma=0.5, seed=4)
+    t = O.patch_tiles(P.A, P.ptr, P.dofs)
+    res = O.kmeans(t, 30, variant=variant, seed=5)
+    phi = res['phi']
+    assert phi.min() >= 0
+    assert len(res['B']) == 30
+    keys = np.array([O.boundary_mask(x) for x in t])
+    # every cluster holds one boundary key only
+    for j in range(30):
+        assert len(set(keys[phi == j])) <= 1
+    # fixed point: at exit each patch sits in its tie band
+    if all(res['converged']):
+        for i in range(len(t)):
+            grp = [j for j in range(30) if len(set(keys[phi == j]) | {keys[i]}) == 1 or j == phi[i]]
+            same = [j for j in range(30) if np.any((phi == j)) and keys[phi == j][0] == keys[i]]
+            d = [O.criterion('l1' if variant == 'entrywise' else 'spectral', t[i], res['B'][j],
+                             res['X'][j]) for j in same]
+            dmin = min(d)
+            assert O.criterion('l1' if variant == 'entrywise' else 'spectral', t[i],
+                               res['B'][phi[i]], res['X'][phi[i]]) <= dmin * (1 + 1e-9)
+
+
+def test_bootstrap_from_identical_classes_converges_at_once():
+    P = gen.q2_hex_diffusion(4, sigma=0.0)
+    t = O.patch_tiles(P.A, P.ptr, P.dofs)
+    a1 = O.alg1_tolerance(t, 1e-8)
+    res = O.kmeans(t, len(a1['reps']), variant='bootstrap', init_reps=a1['reps'])
+    assert res['iters'] == [2] and all(res['converged'])
+    assert np.array_equal(res['phi'], a1['phi'])
+
+
+def test_kmeans_initial_draw_reproducible():
+    P = gen.q1_poisson_2d(8)
+    t = O.patch_tiles(P.A, P.ptr, P.dofs)
+    a = O.kmeans(t, 10, seed=9, max_iter=1)
+    b = O.kmeans(t, 10, seed=9, max_iter=1)
+    assert np.array_equal(a['rep_patch'], b['rep_patch'])
+    c = O.kmeans(t, 10, seed=10, max_iter=1)
+    assert not np.array_equal(a['rep_patch'], c['rep_patch'])
