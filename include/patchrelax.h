@@ -1,0 +1,235 @@
+/*
+ * patchrelax.h -- C ABI of the MI355X (gfx950) compressed patch-relaxation
+ * library (libpatchrelax.so).
+ *
+ * Method: Harper & Tuminaro, "Compression and Reduced Representation
+ * Techniques for Patch-Based Relaxation" (arXiv 2306.10025).
+ *   - patches, restriction V_k, patch matrices A_k = V_k A V_k^T and the
+ *     averaging weight W: Section 2;
+ *   - patch preconditioner M^{-1} = W sum_k V_k^T A_k^{-1} V_k: Eq.(1);
+ *   - approximate (compressed) preconditioner with an inverse database and a
+ *     map phi, M~^{-1} = W sum_k V_k^T B_phi(k)^{-1} V_k: Eq.(3);
+ *   - similarity criterion d(A,B) = ||I - A B^{-1}||_2: Eq.(5), and the
+ *     entrywise l1 / Frobenius criteria of the remark after Eq.(4);
+ *   - database construction: Algorithm 1 (tolerance) and Algorithm 2 with the
+ *     variants and the boundary partitioning of Section 3.2;
+ *   - use as the preconditioner of GMRES (Section 4), optionally as the damped
+ *     smoothing step x <- x + omega M^{-1} r (Experiment 3).
+ *
+ * Conventions (every entry point):
+ *   - Arrays named "device" must be device memory of the current HIP device
+ *     (e.g. torch.Tensor.data_ptr() of a CUDA/HIP tensor); arrays named "host"
+ *     are ordinary host memory.  A host pointer where device memory is
+ *     required returns PR_ERR_HOST_POINTER.
+ *   - The caller owns every array it passes.  pr_setup copies the matrix and
+ *     the patch lists into memory owned by the handle, so the caller may free
+ *     them afterwards.  pr_destroy frees everything the handle owns.
+ *   - Indices are 0-based.  Matrices inside patches are dense row-major.
+ *   - Return value: PR_OK (0), a positive warning, or a negative error code;
+ *     pr_last_error() gives a message for the last failure on a handle.
+ *   - pr_apply is asynchronous on the handle's stream; pr_setup and pr_solve
+ *     synchronise it.  A handle is not thread-safe; distinct handles are
+ *     independent.
+ */
+#ifndef PATCHRELAX_H
+#define PATCHRELAX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PR_OK                     0
+#define PR_NOT_CONVERGED          1   /* solve stopped at max_iters; x holds the last iterate */
+#define PR_ERR_INVALID_ARG       -1   /* null pointer, negative size, bad parameter value */
+#define PR_ERR_HOST_POINTER      -2   /* host memory passed where device memory is required */
+#define PR_ERR_DOF_OUT_OF_RANGE  -3   /* a patch lists a dof outside [0, n) */
+#define PR_ERR_DUP_DOF_IN_PATCH  -4   /* a dof appears twice in one patch */
+#define PR_ERR_UNCOVERED_DOF     -5   /* a dof lies in no patch: W undefined (Section 2) */
+#define PR_ERR_SINGULAR_PATCH    -6   /* zero pivot while inverting a database matrix */
+#define PR_ERR_NONFINITE         -7   /* NaN/Inf in a tile, right-hand side or solve */
+#define PR_ERR_OOM               -8   /* device allocation failed */
+#define PR_ERR_HIP               -9   /* other HIP runtime error (message kept) */
+#define PR_ERR_UNSUPPORTED      -10   /* valid input outside what this build supports */
+#define PR_ERR_BAD_CSR          -11   /* row_ptr not monotone, column out of range or unsorted */
+#define PR_ERR_BAD_PATCH_PTR    -12   /* patch ptr not monotone or an empty patch */
+
+/* ---- enumerations ------------------------------------------------------ */
+enum pr_algo {
+    PR_ALGO_FULL = 0,              /* every patch is its own database entry: Eq.(1) */
+    PR_ALGO_TOLERANCE = 1,         /* Algorithm 1 */
+    PR_ALGO_KMEANS_SPECTRAL = 2,   /* Algorithm 2: spectral distance, mean centres (Eq.(6)) */
+    PR_ALGO_KMEANS_ENTRYWISE = 3,  /* Algorithm 2: l1 distance to the mean, mean centres */
+    PR_ALGO_VARMIN = 4,            /* Algorithm 2: spectral distance, medoid centres */
+    PR_ALGO_BOOTSTRAP = 5          /* Algorithm 1 then variance-minimising Algorithm 2 */
+};
+enum pr_criterion { PR_CRIT_SPECTRAL = 0, PR_CRIT_L1 = 1, PR_CRIT_FRO = 2 };
+/* Arithmetic of the patch solves in the apply.  BF16 / FP16 / BF16X3 use
+ * MFMA with FP32 accumulation; FP16 scales each database inverse and each
+ * restricted residual by a power of two; BF16X3 splits both operands into a
+ * BF16 high part and a BF16 remainder and sums the three leading products
+ * (about 16 significant bits). */
+enum pr_precision { PR_FP64 = 0, PR_FP32 = 1, PR_BF16 = 2, PR_FP16 = 3, PR_BF16X3 = 4 };
+
+/* ---- argument structs -------------------------------------------------- */
+
+/* Global n x n matrix A in CSR form, all arrays device memory.
+ * row_ptr int64[n+1] (row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz);
+ * col int32[nnz], strictly increasing within each row, in [0, n);
+ * val double[nnz]. */
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const double* val;
+} pr_csr;
+
+/* Patches (Section 2): patch k lists global dofs dofs[ptr[k] .. ptr[k+1]).
+ * The list order is the local order of V_k.  ptr int64[n_p+1] and dofs
+ * int32[ptr[n_p]] are device memory.  Each patch holds 1..32 distinct dofs
+ * and every dof in [0, n) must lie in at least one patch. */
+typedef struct {
+    int64_t n_p;
+    const int64_t* ptr;
+    const int32_t* dofs;
+} pr_patches;
+
+/* Parameters; pr_params_default() fills every field. */
+typedef struct {
+    int32_t algo;            /* enum pr_algo (default PR_ALGO_FULL) */
+    int32_t criterion;       /* enum pr_criterion for Algorithm 1 (default spectral) */
+    double  eps;             /* Algorithm 1 tolerance, strict d < eps (default 1e-8) */
+    int64_t m_target;        /* Algorithm 2 database size m_p */
+    int32_t partition_bc;    /* Algorithm 2: cluster boundary groups separately (default 1) */
+    int32_t kmeans_max_iter; /* Algorithm 2 pass limit (default 100) */
+    uint64_t seed;           /* SplitMix64 seed of Algorithm 2's initial draw (default 5) */
+    double  tie_rel;         /* relative argmin tie band (default 1e-9) */
+    int32_t apply_precision; /* enum pr_precision of the patch solves (default FP64) */
+    double  omega;           /* damping (default 1.0) */
+    int32_t sweeps;          /* smoothing steps per preconditioner application (default 1) */
+    int32_t gmres_restart;   /* GMRES restart length (default 30) */
+    int64_t max_iters;       /* GMRES iteration limit (default 10000) */
+    int32_t deterministic;   /* 1: scatter without floating-point atomics (default 0) */
+    int32_t timing;          /* 1: pr_solve brackets its kernels with HIP events and
+                                reports per-class device time in pr_solve_info (default 0) */
+    void*   stream;          /* hipStream_t for all work (NULL = default stream) */
+} pr_params;
+
+typedef struct pr_handle_s* pr_handle;
+
+typedef struct {
+    int64_t iters;           /* Arnoldi steps taken */
+    int64_t cycles;          /* restart cycles */
+    double  relres;          /* true ||b - A x||_2 / ||b||_2 at exit, FP64 */
+    double  relres_est;      /* GMRES estimate at exit */
+    int32_t status;          /* PR_OK or PR_NOT_CONVERGED or an error */
+    int32_t reserved0;
+    double  seconds;         /* wall time of the last pr_solve */
+    /* with params.timing = 1: device milliseconds and launch counts of the
+     * preconditioner applications (zero fill + apply kernel), the sparse
+     * matrix-vector products and the Gram-Schmidt orthogonalisation */
+    double  apply_ms, spmv_ms, orth_ms;
+    int64_t n_apply, n_spmv, n_orth;
+} pr_solve_info;
+
+typedef struct {
+    int64_t n, nnz, n_p, m_p;
+    int32_t max_ps, min_ps;
+    int32_t n_groups;        /* distinct boundary keys */
+    int32_t algo;
+    int64_t crit_evals;      /* criterion evaluations made */
+    int64_t crit_pruned;     /* pairs skipped by the certified norm bound */
+    int64_t crit_exact;      /* evaluations that needed the exact singular value */
+    int64_t alg1_rounds;     /* Algorithm 1 rounds (one per database entry) */
+    int64_t kmeans_iters;    /* Algorithm 2 assignment passes (all groups) */
+    int64_t empty_events;    /* Algorithm 2 empty clusters */
+    int64_t n_items;         /* grouped apply work items */
+    int64_t bytes_tiles, bytes_db, bytes_db_lowp, bytes_index;
+    double  t_validate, t_extract, t_database, t_factor, t_group, t_total; /* seconds */
+    int32_t apply_precision;
+    int32_t reserved0;
+} pr_stats;
+
+/* ---- entry points ------------------------------------------------------ */
+
+/* Fill *p with the defaults listed at pr_params. */
+void pr_params_default(pr_params* p);
+
+/* Setup (Section 2, Section 3): validate, count covers and form W, extract
+ * the dense patch matrices A_k, choose the database (algo) and phi, invert
+ * the database matrices in FP64 (LU with partial pivoting semantics), group
+ * patches by database entry and convert the inverses to apply_precision.
+ * A, P: device arrays (copied).  *out receives a new handle on PR_OK.
+ * Errors: INVALID_ARG, HOST_POINTER, BAD_CSR, BAD_PATCH_PTR,
+ * DOF_OUT_OF_RANGE, DUP_DOF_IN_PATCH, UNCOVERED_DOF, SINGULAR_PATCH (the
+ * patch id is in pr_last_error), NONFINITE, OOM, HIP, UNSUPPORTED (a patch
+ * with more than 32 dofs).  Synchronises the stream. */
+int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_handle* out);
+
+/* z = omega * M~^{-1} r (Eq.(3); Eq.(1) for PR_ALGO_FULL) for one smoothing
+ * step.  r, z: device double[n], distinct.  Asynchronous on the stream. */
+int pr_apply(pr_handle h, const double* r, double* z);
+
+/* Solve A x = b by right-preconditioned GMRES(gmres_restart) from x = 0,
+ * preconditioned by `sweeps` damped smoothing steps; stops when
+ * ||b - A x||_2 <= tol ||b||_2 (true residual) or after max_iters.
+ * b, x: device double[n].  Returns PR_OK, PR_NOT_CONVERGED or an error;
+ * details via pr_get_solve_info.  Synchronises the stream. */
+int pr_solve(pr_handle h, const double* b, double* x, double tol);
+
+int pr_get_solve_info(pr_handle h, pr_solve_info* info);
+int pr_get_stats(pr_handle h, pr_stats* s);
+
+/* Parity hooks (host outputs, synchronising):
+ * phi: int32[n_p] database entry of each patch; reps: int32[m_p] patch whose
+ * matrix is entry j (-1 for a cluster mean); *m_p: database size.  Any output
+ * pointer may be NULL. */
+int pr_get_assignment(pr_handle h, int32_t* phi, int32_t* reps, int64_t* m_p);
+/* tile: double[p_k * p_k], the dense A_k of patch k, row-major. */
+int pr_get_patch_tile(pr_handle h, int64_t k, double* tile);
+/* W: double[n] (Section 2). */
+int pr_get_weights(pr_handle h, double* W);
+/* keys: uint32[n_p], bit a set iff local row a of A_k has exactly one
+ * nonzero (boundary partitioning, Section 3.2). */
+int pr_get_boundary_keys(pr_handle h, uint32_t* keys);
+/* X: double[p_j * p_j], the FP64 inverse of database entry j, row-major. */
+int pr_get_rep_inverse(pr_handle h, int64_t j, double* X);
+
+/* Use another stream for later calls on h (NULL = default stream). */
+int pr_set_stream(pr_handle h, void* hip_stream);
+
+/* Host-only validation of host arrays (no GPU needed): same checks and codes
+ * as pr_setup performs on the device. */
+int pr_validate_host(const pr_csr* A_host, const pr_patches* P_host);
+
+void pr_destroy(pr_handle h);
+const char* pr_status_string(int status);
+const char* pr_last_error(pr_handle h);   /* h may be NULL: last global error */
+
+/* ---- standalone batched kernels (device arrays, asynchronous) ----------- */
+
+/* Batched inverse of `count` dense p x p matrices (row-major, contiguous),
+ * Gauss-Jordan elimination with partial pivoting in FP64, one wavefront per
+ * matrix (the factorisation step of Section 4, Experiment 3).  A: device
+ * double[count*p*p]; X: device double[count*p*p]; info: device
+ * int32[count], 0 or the 1-based column of the first zero pivot.
+ * 1 <= p <= 32. */
+int pr_batch_inverse(int32_t p, int64_t count, const double* A, double* X, int32_t* info,
+                     void* stream);
+
+/* Batched criterion between A[i] and B[i] (Eq.(5) and the remark after
+ * Eq.(4)): spectral d = ||I - A[i] X[i]||_2 with X[i] = B[i]^{-1} given
+ * (largest singular value by cyclic Jacobi on E^T E), l1 sum|A - B|,
+ * Frobenius ||A - B||_F.  A, B, X: device double[count*p*p] (B unused for
+ * spectral, X unused otherwise; may be NULL then); d: device double[count]. */
+int pr_batch_criterion(int32_t p, int64_t count, int32_t criterion, const double* A,
+                       const double* B, const double* X, double* d, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PATCHRELAX_H */

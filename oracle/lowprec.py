@@ -13,6 +13,9 @@ the products, so that a device result can be judged against it:
   the FP16 rounding, where 2^-e maps the largest magnitude m (taken after the
   FP32 rounding) into [2^13, 2^14); the products are multiplied back by
   2^(e_j + f_k);
+* BF16X3 splits each FP32-rounded operand into a BF16 high part and the BF16
+  rounding of the remainder, and keeps the three leading products
+  hi*hi + hi*lo + lo*hi (about 16 significant bits);
 * the products of the rounded operands are summed exactly (float64 here); a
   device that sums them in FP32 stays within p_s * 2^-24 * sum|x||r| of this.
 
@@ -62,12 +65,21 @@ def _round_operand(x, precision, scale_exp=0):
     raise ValueError(precision)
 
 
+def split_bf16(x):
+    """High/low BF16 split of FP32-rounded values: hi = bf16(x32) and
+    lo = bf16(x32 - hi) (the difference is exact in FP32)."""
+    x32 = round_fp32(x)
+    hi = round_bf16(x32)
+    lo = round_bf16((x32 - hi).astype(np.float32))
+    return hi.astype(np.float64), lo.astype(np.float64)
+
+
 def rounded_database(X, precision):
     """Rounded database entries and their FP16 exponents (0 otherwise)."""
     out, exps = [], []
     for Xj in X:
         e = fp16_scale_exp(np.max(np.abs(round_fp32(Xj)))) if precision == "fp16" else 0
-        out.append(_round_operand(Xj, precision, e))
+        out.append(split_bf16(Xj) if precision == "bf16x3" else _round_operand(Xj, precision, e))
         exps.append(e)
     return out, exps
 
@@ -83,9 +95,16 @@ def apply_lowprec(ptr, dofs, W, X, phi, r, omega=1.0, precision="bf16", return_b
     for k in range(len(ptr) - 1):
         d = dofs[ptr[k]:ptr[k + 1]]
         rk = r[d]
+        j = phi[k]
+        if precision == "bf16x3":
+            # three leading products of the split operands: hi*hi + hi*lo + lo*hi
+            (xh, xl), (rh, rl) = Xr[j], split_bf16(rk)
+            np.add.at(z, d, xh @ rh + xh @ rl + xl @ rh)
+            np.add.at(bnd, d, np.abs(xh) @ np.abs(rh) + np.abs(xh) @ np.abs(rl)
+                      + np.abs(xl) @ np.abs(rh))
+            continue
         f = fp16_scale_exp(np.max(np.abs(round_fp32(rk)))) if precision == "fp16" else 0
         rr = _round_operand(rk, precision, f)
-        j = phi[k]
         scale = 2.0 ** (ex[j] + f)
         np.add.at(z, d, (Xr[j] @ rr) * scale)
         np.add.at(bnd, d, (np.abs(Xr[j]) @ np.abs(rr)) * scale)

@@ -1,0 +1,334 @@
+"""Python binding of libpatchrelax.so (compressed patch-based relaxation on
+MI355X / gfx950).
+
+Argument marshalling only: every step of setup, apply and solve runs in the
+library's HIP kernels.  PyTorch supplies device memory (tensor data pointers)
+and the HIP stream.  The functions keep the C names (``pr_setup``,
+``pr_apply``, ``pr_solve``, ...); ``PatchRelax`` is a small owner object on
+top of them.  The library must be built first (``__graft_entry__.build()``);
+nothing here falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import (POINTER, Structure, byref, c_char_p, c_double, c_int, c_int32, c_int64,
+                    c_uint32, c_uint64, c_void_p)
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpatchrelax.so")
+
+# status codes (include/patchrelax.h)
+PR_OK = 0
+PR_NOT_CONVERGED = 1
+PR_ERR_INVALID_ARG = -1
+PR_ERR_HOST_POINTER = -2
+PR_ERR_DOF_OUT_OF_RANGE = -3
+PR_ERR_DUP_DOF_IN_PATCH = -4
+PR_ERR_UNCOVERED_DOF = -5
+PR_ERR_SINGULAR_PATCH = -6
+PR_ERR_NONFINITE = -7
+PR_ERR_OOM = -8
+PR_ERR_HIP = -9
+PR_ERR_UNSUPPORTED = -10
+PR_ERR_BAD_CSR = -11
+PR_ERR_BAD_PATCH_PTR = -12
+
+ALGO = dict(full=0, tolerance=1, kmeans_spectral=2, kmeans_entrywise=3, varmin=4, bootstrap=5)
+CRIT = dict(spectral=0, l1=1, fro=2)
+PREC = dict(fp64=0, fp32=1, bf16=2, fp16=3, bf16x3=4)
+
+
+class pr_csr(Structure):
+    _fields_ = [("n", c_int64), ("nnz", c_int64), ("row_ptr", c_void_p), ("col", c_void_p),
+                ("val", c_void_p)]
+
+
+class pr_patches(Structure):
+    _fields_ = [("n_p", c_int64), ("ptr", c_void_p), ("dofs", c_void_p)]
+
+
+class pr_params(Structure):
+    _fields_ = [("algo", c_int32), ("criterion", c_int32), ("eps", c_double),
+                ("m_target", c_int64), ("partition_bc", c_int32), ("kmeans_max_iter", c_int32),
+                ("seed", c_uint64), ("tie_rel", c_double), ("apply_precision", c_int32),
+                ("omega", c_double), ("sweeps", c_int32), ("gmres_restart", c_int32),
+                ("max_iters", c_int64), ("deterministic", c_int32), ("timing", c_int32),
+                ("stream", c_void_p)]
+
+
+class pr_solve_info(Structure):
+    _fields_ = [("iters", c_int64), ("cycles", c_int64), ("relres", c_double),
+                ("relres_est", c_double), ("status", c_int32), ("reserved0", c_int32),
+                ("seconds", c_double), ("apply_ms", c_double), ("spmv_ms", c_double),
+                ("orth_ms", c_double), ("n_apply", c_int64), ("n_spmv", c_int64),
+                ("n_orth", c_int64)]
+
+
+class pr_stats(Structure):
+    _fields_ = [("n", c_int64), ("nnz", c_int64), ("n_p", c_int64), ("m_p", c_int64),
+                ("max_ps", c_int32), ("min_ps", c_int32), ("n_groups", c_int32), ("algo", c_int32),
+                ("crit_evals", c_int64), ("crit_pruned", c_int64), ("crit_exact", c_int64),
+                ("alg1_rounds", c_int64), ("kmeans_iters", c_int64), ("empty_events", c_int64),
+                ("n_items", c_int64), ("bytes_tiles", c_int64), ("bytes_db", c_int64),
+                ("bytes_db_lowp", c_int64), ("bytes_index", c_int64),
+                ("t_validate", c_double), ("t_extract", c_double), ("t_database", c_double),
+                ("t_factor", c_double), ("t_group", c_double), ("t_total", c_double),
+                ("apply_precision", c_int32), ("reserved0", c_int32)]
+
+
+_SIGS = {
+    "pr_params_default": (None, [POINTER(pr_params)]),
+    "pr_setup": (c_int, [POINTER(pr_csr), POINTER(pr_patches), POINTER(pr_params), POINTER(c_void_p)]),
+    "pr_apply": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "pr_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double]),
+    "pr_get_solve_info": (c_int, [c_void_p, POINTER(pr_solve_info)]),
+    "pr_get_stats": (c_int, [c_void_p, POINTER(pr_stats)]),
+    "pr_get_assignment": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_int64)]),
+    "pr_get_patch_tile": (c_int, [c_void_p, c_int64, c_void_p]),
+    "pr_get_weights": (c_int, [c_void_p, c_void_p]),
+    "pr_get_boundary_keys": (c_int, [c_void_p, c_void_p]),
+    "pr_get_rep_inverse": (c_int, [c_void_p, c_int64, c_void_p]),
+    "pr_set_stream": (c_int, [c_void_p, c_void_p]),
+    "pr_validate_host": (c_int, [POINTER(pr_csr), POINTER(pr_patches)]),
+    "pr_destroy": (None, [c_void_p]),
+    "pr_status_string": (c_char_p, [c_int]),
+    "pr_last_error": (c_char_p, [c_void_p]),
+    "pr_batch_inverse": (c_int, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "pr_batch_criterion": (c_int, [c_int32, c_int64, c_int32, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_void_p]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libpatchrelax.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class PatchRelaxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{code} ({pr_status_string(code)}): {msg}")
+        self.code = code
+
+
+def pr_status_string(code: int) -> str:
+    return lib().pr_status_string(code).decode()
+
+
+def pr_last_error(h=None) -> str:
+    s = lib().pr_last_error(h)
+    return s.decode() if s else ""
+
+
+def _check(code, h=None, allow=(PR_OK,)):
+    if code not in allow:
+        raise PatchRelaxError(code, pr_last_error(h))
+    return code
+
+
+def _ptr(t):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def pr_params_default() -> pr_params:
+    p = pr_params()
+    lib().pr_params_default(byref(p))
+    return p
+
+
+def make_params(algo="full", criterion="spectral", eps=1e-8, m_target=0, partition_bc=True,
+                kmeans_max_iter=100, seed=5, tie_rel=1e-9, precision="fp64", omega=1.0, sweeps=1,
+                restart=30, max_iters=10000, deterministic=False, timing=False,
+                stream=None) -> pr_params:
+    p = pr_params_default()
+    p.algo = ALGO[algo] if isinstance(algo, str) else int(algo)
+    p.criterion = CRIT[criterion] if isinstance(criterion, str) else int(criterion)
+    p.eps = eps
+    p.m_target = m_target
+    p.partition_bc = int(partition_bc)
+    p.kmeans_max_iter = kmeans_max_iter
+    p.seed = seed
+    p.tie_rel = tie_rel
+    p.apply_precision = PREC[precision] if isinstance(precision, str) else int(precision)
+    p.omega = omega
+    p.sweeps = sweeps
+    p.gmres_restart = restart
+    p.max_iters = max_iters
+    p.deterministic = int(deterministic)
+    p.timing = int(timing)
+    p.stream = stream
+    return p
+
+
+def pr_setup(row_ptr, col, val, ptr, dofs, n, params: pr_params):
+    """Device tensors in, handle out (raises PatchRelaxError on failure)."""
+    A = pr_csr(n, int(col.numel()), _ptr(row_ptr), _ptr(col), _ptr(val))
+    P = pr_patches(int(ptr.numel()) - 1, _ptr(ptr), _ptr(dofs))
+    h = c_void_p()
+    _check(lib().pr_setup(byref(A), byref(P), byref(params), byref(h)))
+    return h
+
+
+def pr_apply(h, r, z):
+    return _check(lib().pr_apply(h, _ptr(r), _ptr(z)), h)
+
+
+def pr_solve(h, b, x, tol):
+    return _check(lib().pr_solve(h, _ptr(b), _ptr(x), tol), h, allow=(PR_OK, PR_NOT_CONVERGED))
+
+
+def pr_get_solve_info(h) -> dict:
+    i = pr_solve_info()
+    _check(lib().pr_get_solve_info(h, byref(i)), h)
+    return {k: getattr(i, k) for k, _ in pr_solve_info._fields_ if k != "reserved0"}
+
+
+def pr_get_stats(h) -> dict:
+    s = pr_stats()
+    _check(lib().pr_get_stats(h, byref(s)), h)
+    return {k: getattr(s, k) for k, _ in pr_stats._fields_ if k != "reserved0"}
+
+
+def pr_get_assignment(h, n_p):
+    m = c_int64()
+    _check(lib().pr_get_assignment(h, None, None, byref(m)), h)
+    phi = np.zeros(n_p, dtype=np.int32)
+    reps = np.zeros(max(m.value, 1), dtype=np.int32)
+    _check(lib().pr_get_assignment(h, phi.ctypes.data_as(c_void_p), reps.ctypes.data_as(c_void_p),
+                                   byref(m)), h)
+    return phi, reps[:m.value]
+
+
+def pr_get_patch_tile(h, k, p):
+    t = np.zeros(p * p, dtype=np.float64)
+    _check(lib().pr_get_patch_tile(h, k, t.ctypes.data_as(c_void_p)), h)
+    return t.reshape(p, p)
+
+
+def pr_get_weights(h, n):
+    W = np.zeros(n, dtype=np.float64)
+    _check(lib().pr_get_weights(h, W.ctypes.data_as(c_void_p)), h)
+    return W
+
+
+def pr_get_boundary_keys(h, n_p):
+    k = np.zeros(n_p, dtype=np.uint32)
+    _check(lib().pr_get_boundary_keys(h, k.ctypes.data_as(c_void_p)), h)
+    return k
+
+
+def pr_get_rep_inverse(h, j, p):
+    X = np.zeros(p * p, dtype=np.float64)
+    _check(lib().pr_get_rep_inverse(h, j, X.ctypes.data_as(c_void_p)), h)
+    return X.reshape(p, p)
+
+
+def pr_destroy(h):
+    if h:
+        lib().pr_destroy(h)
+
+
+def pr_batch_inverse(p, A, X, info):
+    count = A.numel() // (p * p)
+    return _check(lib().pr_batch_inverse(p, count, _ptr(A), _ptr(X), _ptr(info), _stream()))
+
+
+def pr_batch_criterion(p, criterion, A, B, X, d):
+    count = A.numel() // (p * p)
+    crit = CRIT[criterion] if isinstance(criterion, str) else int(criterion)
+    return _check(lib().pr_batch_criterion(p, count, crit, _ptr(A), _ptr(B), _ptr(X), _ptr(d),
+                                           _stream()))
+
+
+def pr_validate_host(indptr, indices, data, ptr, dofs, n):
+    """Host-only validation of numpy arrays; returns the status code."""
+    indptr = np.ascontiguousarray(indptr, dtype=np.int64)
+    indices = np.ascontiguousarray(indices, dtype=np.int32)
+    data = np.ascontiguousarray(data, dtype=np.float64)
+    ptr = np.ascontiguousarray(ptr, dtype=np.int64)
+    dofs = np.ascontiguousarray(dofs, dtype=np.int32)
+    A = pr_csr(n, len(indices), indptr.ctypes.data_as(c_void_p), indices.ctypes.data_as(c_void_p),
+               data.ctypes.data_as(c_void_p))
+    P = pr_patches(len(ptr) - 1, ptr.ctypes.data_as(c_void_p), dofs.ctypes.data_as(c_void_p))
+    return lib().pr_validate_host(byref(A), byref(P))
+
+
+class PatchRelax:
+    """Owner of a setup handle and the device copies of its inputs.
+
+    ``A`` is a SciPy CSR matrix (int32 indices), ``ptr``/``dofs`` the patch
+    lists; they are copied to the current device and handed to ``pr_setup``.
+    """
+
+    def __init__(self, A, ptr, dofs, device="cuda", **params):
+        import torch
+        self.n = A.shape[0]
+        self.n_p = len(ptr) - 1
+        self.sizes = np.diff(np.asarray(ptr))
+        self.dev = torch.device(device)
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(self.dev)
+        self.row_ptr = t(A.indptr.astype(np.int64), torch.int64)
+        self.col = t(A.indices.astype(np.int32), torch.int32)
+        self.val = t(A.data.astype(np.float64), torch.float64)
+        self.ptr = t(np.asarray(ptr, dtype=np.int64), torch.int64)
+        self.dofs = t(np.asarray(dofs, dtype=np.int32), torch.int32)
+        params.setdefault("stream", _stream())
+        self.params = make_params(**params)
+        self.h = pr_setup(self.row_ptr, self.col, self.val, self.ptr, self.dofs, self.n, self.params)
+
+    def apply(self, r, z):
+        return pr_apply(self.h, r, z)
+
+    def solve(self, b, x, tol=1e-8):
+        return pr_solve(self.h, b, x, tol)
+
+    def solve_info(self):
+        return pr_get_solve_info(self.h)
+
+    def stats(self):
+        return pr_get_stats(self.h)
+
+    def assignment(self):
+        return pr_get_assignment(self.h, self.n_p)
+
+    def tile(self, k):
+        return pr_get_patch_tile(self.h, k, int(self.sizes[k]))
+
+    def weights(self):
+        return pr_get_weights(self.h, self.n)
+
+    def keys(self):
+        return pr_get_boundary_keys(self.h, self.n_p)
+
+    def rep_inverse(self, j, p):
+        return pr_get_rep_inverse(self.h, j, p)
+
+    def close(self):
+        if self.h:
+            pr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

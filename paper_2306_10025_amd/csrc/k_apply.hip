@@ -1,0 +1,333 @@
+// The patch preconditioner apply, Eq.(3) (Eq.(1) when every patch is its own
+// database entry): z = omega * W * sum_k V_k^T X_phi(k) V_k r.
+//
+// Two families of kernels:
+//  * vector kernels (FP64 or FP32 arithmetic): a group of G lanes per patch,
+//    lane a owns local dof a; the restricted residual is broadcast through
+//    cross-lane shuffles and the inverse is read column-major so that each
+//    step is a contiguous load;
+//  * grouped MFMA kernels (BF16 or FP16 operands, FP32 accumulation): the
+//    patches that share database entry j are stacked, so the apply becomes
+//    Y = X_j [r_k1 ... r_kN], one MFMA tile per 16 or 32 members (the
+//    multiple right-hand-side solve the paper's Experiment 3 discussion
+//    proposes).  The lane that gathers local dof i of a member also holds
+//    output row i of that member, so gather and scatter share indices.
+// The scatter uses FP64 atomics.
+#include "pr_internal.h"
+
+namespace {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+template <typename TX, typename TA, int G>
+__global__ __launch_bounds__(256) void k_apply_vec(const int32_t* __restrict__ order, int64_t count,
+                                                   const int32_t* __restrict__ phi,
+                                                   const int64_t* __restrict__ ptr,
+                                                   const int32_t* __restrict__ dofs,
+                                                   const TX* __restrict__ db,
+                                                   const int64_t* __restrict__ dboff, int uniform_ps,
+                                                   const double* __restrict__ W, double omega,
+                                                   const double* __restrict__ r,
+                                                   double* __restrict__ z) {
+    const int a = threadIdx.x % G;
+    const int64_t groups = (int64_t)gridDim.x * (blockDim.x / G);
+    for (int64_t s = (int64_t)blockIdx.x * (blockDim.x / G) + threadIdx.x / G; s < count;
+         s += groups) {
+        const int32_t k = order ? order[s] : (int32_t)s;
+        const int32_t j = phi[k];
+        const int64_t st = ptr[k];
+        const int p = (int)(ptr[k + 1] - st);
+        const TX* X = db + (uniform_ps ? (int64_t)j * uniform_ps * uniform_ps : dboff[j]);
+        const bool act = a < p;
+        const int32_t g = act ? dofs[st + a] : 0;
+        const TA rv = act ? (TA)r[g] : (TA)0;
+        TA acc = 0;
+        for (int b = 0; b < p; ++b) {
+            const TA rb = __shfl(rv, b, G);
+            if (act) acc = fma((TA)X[(int64_t)b * p + a], rb, acc);
+        }
+        if (act) atomicAdd(&z[g], omega * W[g] * (double)acc);
+    }
+}
+
+template <typename TX, typename TA>
+void run_vec(const int32_t* order, int64_t count, const int32_t* phi, const int64_t* ptr,
+             const int32_t* dofs, const TX* db, const int64_t* dboff, int uniform_ps,
+             const double* W, double omega, const double* r, double* z, int group, hipStream_t s) {
+    if (count <= 0) return;
+    const int per = 256 / group;
+    int64_t blocks = (count + per - 1) / per;
+    if (blocks > 131072) blocks = 131072;
+    switch (group) {
+        case 4: k_apply_vec<TX, TA, 4><<<(unsigned)blocks, 256, 0, s>>>(order, count, phi, ptr, dofs, db, dboff, uniform_ps, W, omega, r, z); break;
+        case 8: k_apply_vec<TX, TA, 8><<<(unsigned)blocks, 256, 0, s>>>(order, count, phi, ptr, dofs, db, dboff, uniform_ps, W, omega, r, z); break;
+        case 16: k_apply_vec<TX, TA, 16><<<(unsigned)blocks, 256, 0, s>>>(order, count, phi, ptr, dofs, db, dboff, uniform_ps, W, omega, r, z); break;
+        default: k_apply_vec<TX, TA, 32><<<(unsigned)blocks, 256, 0, s>>>(order, count, phi, ptr, dofs, db, dboff, uniform_ps, W, omega, r, z); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// grouped MFMA apply; one wavefront per work item (entry, start, count, p)
+// MODE 0: BF16, 1: FP16 with power-of-two scales, 2: BF16 high/low split
+// ---------------------------------------------------------------------------
+
+template <int MODE>
+struct LowOp {
+    // the operand pair (high, low) of an FP32 value; low is zero unless split
+    static __device__ __forceinline__ void cvt(float f, short& hi, short& lo) {
+        if (MODE == 1) {
+            hi = (short)f32_to_f16_rne(f);
+            lo = 0;
+        } else {
+            const uint16_t h = f32_to_bf16_rne(f);
+            hi = (short)h;
+            lo = MODE == 2 ? (short)f32_to_bf16_rne(f - __uint_as_float((uint32_t)h << 16)) : 0;
+        }
+    }
+};
+
+template <int MODE>
+__device__ __forceinline__ f4 mma16(s4 a, s4 b, f4 c) {
+    if (MODE == 1)
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h4, a), __builtin_bit_cast(h4, b), c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+template <int MODE>
+__device__ __forceinline__ f16v mma32(s4 a, s4 b, f16v c) {
+    if (MODE == 1)
+        return __builtin_amdgcn_mfma_f32_32x32x8f16(__builtin_bit_cast(h4, a), __builtin_bit_cast(h4, b), c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ items, int64_t n_items,
+                                                    const int32_t* __restrict__ order,
+                                                    const int64_t* __restrict__ ptr,
+                                                    const int32_t* __restrict__ dofs,
+                                                    const uint16_t* __restrict__ db_lp,
+                                                    const int64_t* __restrict__ dblp_off,
+                                                    const int32_t* __restrict__ db_exp,
+                                                    const double* __restrict__ W, double omega,
+                                                    const double* __restrict__ r,
+                                                    double* __restrict__ z) {
+    constexpr bool FP16 = MODE == 1;
+    constexpr bool SPLIT = MODE == 2;
+    const int l = threadIdx.x & (PR_WAVE - 1);
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / PR_WAVE);
+    for (int64_t it = (int64_t)blockIdx.x * (blockDim.x / PR_WAVE) + threadIdx.x / PR_WAVE;
+         it < n_items; it += waves) {
+        const int32_t j = items[4 * it + 0];
+        const int32_t start = items[4 * it + 1];
+        const int32_t cnt = items[4 * it + 2];
+        const int p = items[4 * it + 3];
+        const uint16_t* Xl = db_lp + dblp_off[j];
+        const int ej = FP16 ? db_exp[j] : 0;
+        if (p <= 16) {
+            // 16x16x16: member n = l%16, local dofs 4q..4q+3 with q = l/16
+            const int n = l & 15, q = l >> 4;
+            const bool mv = n < cnt;
+            int64_t st = 0;
+            if (mv) st = ptr[order[start + n]];
+            int32_t gi[4];
+            float rv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int kk = 4 * q + t;
+                const bool v = mv && kk < p;
+                gi[t] = v ? dofs[st + kk] : -1;
+                rv[t] = v ? (float)r[gi[t]] : 0.0f;
+            }
+            int f = 0;
+            if (FP16) {
+                float m = fmaxf(fmaxf(fabsf(rv[0]), fabsf(rv[1])), fmaxf(fabsf(rv[2]), fabsf(rv[3])));
+                m = fmaxf(m, __shfl_xor(m, 16));
+                m = fmaxf(m, __shfl_xor(m, 32));
+                f = fp16_scale_exp(m);
+            }
+            s4 bh, bl;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                short hi, lo;
+                LowOp<MODE>::cvt(FP16 ? ldexpf(rv[t], -f) : rv[t], hi, lo);
+                bh[t] = hi;
+                bl[t] = lo;
+            }
+            const s4 ah = *reinterpret_cast<const s4*>(Xl + 4 * l);
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+            acc = mma16<MODE>(ah, bh, acc);
+            if (SPLIT) {
+                const s4 al = *reinterpret_cast<const s4*>(Xl + 256 + 4 * l);
+                acc = mma16<MODE>(ah, bl, acc);
+                acc = mma16<MODE>(al, bh, acc);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (gi[t] >= 0) {
+                    double y = (double)acc[t];
+                    if (FP16) y = ldexp(y, ej + f);
+                    atomicAdd(&z[gi[t]], omega * W[gi[t]] * y);
+                }
+            }
+        } else {
+            // 32x32x8, K in steps of 8: member n = l%32, h = l/32,
+            // local dofs 8s + 4h + t for step s and t < 4
+            const int n = l & 31, h = l >> 5;
+            const bool mv = n < cnt;
+            int64_t st = 0;
+            if (mv) st = ptr[order[start + n]];
+            const int steps = (p + 7) >> 3;
+            int32_t gi[16];
+            float rv[16];
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int kk = 8 * s + 4 * h + t;
+                    const bool v = mv && kk < p;
+                    gi[4 * s + t] = v ? dofs[st + kk] : -1;
+                    rv[4 * s + t] = v ? (float)r[gi[4 * s + t]] : 0.0f;
+                }
+            int f = 0;
+            if (FP16) {
+                float m = 0.0f;
+#pragma unroll
+                for (int t = 0; t < 16; ++t) m = fmaxf(m, fabsf(rv[t]));
+                m = fmaxf(m, __shfl_xor(m, 32));
+                f = fp16_scale_exp(m);
+            }
+            f16v acc = {};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                if (s < steps) {
+                    s4 bh, bl;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        short hi, lo;
+                        LowOp<MODE>::cvt(FP16 ? ldexpf(rv[4 * s + t], -f) : rv[4 * s + t], hi, lo);
+                        bh[t] = hi;
+                        bl[t] = lo;
+                    }
+                    const s4 ah = *reinterpret_cast<const s4*>(Xl + (s * 64 + l) * 4);
+                    acc = mma32<MODE>(ah, bh, acc);
+                    if (SPLIT) {
+                        const s4 al = *reinterpret_cast<const s4*>(Xl + 1024 + (s * 64 + l) * 4);
+                        acc = mma32<MODE>(ah, bl, acc);
+                        acc = mma32<MODE>(al, bh, acc);
+                    }
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                if (gi[v] >= 0) {
+                    double y = (double)acc[v];
+                    if (FP16) y = ldexp(y, ej + f);
+                    atomicAdd(&z[gi[v]], omega * W[gi[v]] * y);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// database conversion: one wavefront per entry
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_convert_db(int prec, int64_t m_p, const double* __restrict__ db,
+                                                   const int64_t* __restrict__ dboff,
+                                                   const int32_t* __restrict__ dbps, int uniform_ps,
+                                                   uint16_t* __restrict__ db_lp,
+                                                   const int64_t* __restrict__ dblp_off,
+                                                   int32_t* __restrict__ db_exp, float* __restrict__ db_f32,
+                                                   double* __restrict__ db_cm) {
+    const int l = threadIdx.x;
+    for (int64_t j = blockIdx.x; j < m_p; j += gridDim.x) {
+        const int p = uniform_ps ? uniform_ps : dbps[j];
+        const int64_t off = uniform_ps ? j * (int64_t)p * p : dboff[j];
+        const double* X = db + off;
+        // column-major FP64 / FP32 copies for the vector kernels
+        float m = 0.0f;
+        for (int e = l; e < p * p; e += PR_WAVE) {
+            const int a = e / p, b = e % p;
+            const double v = X[e];
+            if (db_cm) db_cm[off + (int64_t)b * p + a] = v;
+            if (db_f32) db_f32[off + (int64_t)b * p + a] = (float)v;
+            m = fmaxf(m, fabsf((float)v));
+        }
+        m = wave_max(m);
+        const int e = (prec == PR_FP16) ? fp16_scale_exp(m) : 0;
+        if (l == 0 && db_exp) db_exp[j] = e;
+        if (prec != PR_BF16 && prec != PR_FP16 && prec != PR_BF16X3) continue;
+        uint16_t* out = db_lp + dblp_off[j];
+        const int L = p <= 16 ? 256 : 1024;       // elements of one lane-ready copy
+        for (int s = 0; s < (p <= 16 ? 1 : 4); ++s)
+            for (int t = 0; t < 4; ++t) {
+                int i, k;
+                if (p <= 16) {
+                    i = l & 15;
+                    k = 4 * (l >> 4) + t;
+                } else {
+                    i = l & 31;
+                    k = 8 * s + 4 * (l >> 5) + t;
+                }
+                const float v = (i < p && k < p) ? (float)X[i * p + k] : 0.0f;
+                const int slot = (s * 64 + l) * 4 + t;
+                if (prec == PR_FP16) {
+                    out[slot] = f32_to_f16_rne(ldexpf(v, -e));
+                } else {
+                    const uint16_t hi = f32_to_bf16_rne(v);
+                    out[slot] = hi;
+                    if (prec == PR_BF16X3)
+                        out[L + slot] = f32_to_bf16_rne(v - __uint_as_float((uint32_t)hi << 16));
+                }
+            }
+    }
+}
+
+}  // namespace
+
+void launch_apply_vec_f64(const int32_t* order, int64_t count, const int32_t* phi,
+                          const int64_t* ptr, const int32_t* dofs, const double* db_cm,
+                          const int64_t* dboff, int uniform_ps, const double* W, double omega,
+                          const double* r, double* z, int group, hipStream_t s) {
+    run_vec<double, double>(order, count, phi, ptr, dofs, db_cm, dboff, uniform_ps, W, omega, r, z,
+                            group, s);
+}
+
+void launch_apply_vec_f32(const int32_t* order, int64_t count, const int32_t* phi,
+                          const int64_t* ptr, const int32_t* dofs, const float* db_f32,
+                          const int64_t* dboff, int uniform_ps, const double* W, double omega,
+                          const double* r, double* z, int group, hipStream_t s) {
+    run_vec<float, float>(order, count, phi, ptr, dofs, db_f32, dboff, uniform_ps, W, omega, r, z,
+                          group, s);
+}
+
+void launch_apply_mfma(int prec, const int32_t* items, int64_t n_items, const int32_t* order,
+                       const int64_t* ptr, const int32_t* dofs, const uint16_t* db_lp,
+                       const int64_t* dblp_off, const int32_t* db_exp, const double* W,
+                       double omega, const double* r, double* z, hipStream_t s) {
+    if (n_items <= 0) return;
+    int64_t blocks = (n_items + 3) / 4;
+    if (blocks > 131072) blocks = 131072;
+    if (prec == PR_FP16)
+        k_apply_mfma<1><<<(unsigned)blocks, 256, 0, s>>>(items, n_items, order, ptr, dofs, db_lp,
+                                                        dblp_off, db_exp, W, omega, r, z);
+    else if (prec == PR_BF16X3)
+        k_apply_mfma<2><<<(unsigned)blocks, 256, 0, s>>>(items, n_items, order, ptr, dofs, db_lp,
+                                                        dblp_off, db_exp, W, omega, r, z);
+    else
+        k_apply_mfma<0><<<(unsigned)blocks, 256, 0, s>>>(items, n_items, order, ptr, dofs, db_lp,
+                                                        dblp_off, db_exp, W, omega, r, z);
+}
+
+void launch_convert_db(int prec, int64_t m_p, const double* db, const int64_t* dboff,
+                       const int32_t* dbps, int uniform_ps, uint16_t* db_lp,
+                       const int64_t* dblp_off, int32_t* db_exp, float* db_f32, double* db_cm,
+                       hipStream_t s) {
+    if (m_p <= 0) return;
+    int64_t blocks = m_p < 65536 ? m_p : 65536;
+    k_convert_db<<<(unsigned)blocks, 64, 0, s>>>(prec, m_p, db, dboff, dbps, uniform_ps, db_lp,
+                                                dblp_off, db_exp, db_f32, db_cm);
+}

@@ -1,0 +1,406 @@
+// Setup kernels: validation, cover counts and W (Section 2), dense patch
+// extraction A_k = V_k A V_k^T with the boundary key of Section 3.2, and the
+// generic device primitives (exclusive scan, bitonic key/value sort) used to
+// order patches.
+#include "pr_internal.h"
+
+#include <climits>
+
+namespace {
+
+constexpr int kMaxPs = 32;
+
+// flags layout (int32[8], initialised by the host):
+//  [0] bad CSR (0/1)      [1] bad patch ptr (0/1)   [2] min patch with dof out of range
+//  [3] min patch with dup [4] min uncovered dof     [5] min patch with non-finite tile
+//  [6] patch too large    [7] unused
+
+__global__ void k_validate_csr(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                               int64_t n, int64_t nnz, int32_t* flags) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && (rowptr[0] != 0 || rowptr[n] != nnz)) flags[0] = 1;
+    if (i >= n) return;
+    int64_t s = rowptr[i], e = rowptr[i + 1];
+    if (s > e || s < 0 || e > nnz) {
+        flags[0] = 1;
+        return;
+    }
+    int32_t prev = -1;
+    for (int64_t q = s; q < e; ++q) {
+        int32_t c = col[q];
+        if (c < 0 || c >= n || c <= prev) {
+            flags[0] = 1;
+            return;
+        }
+        prev = c;
+    }
+}
+
+__global__ void k_validate_patches(const int64_t* __restrict__ ptr, const int32_t* __restrict__ dofs,
+                                   int64_t n_p, int64_t n, int64_t total, int32_t* flags,
+                                   int32_t* minmax) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0 && (ptr[0] != 0 || ptr[n_p] != total)) flags[1] = 1;
+    if (k >= n_p) return;
+    int64_t s = ptr[k], e = ptr[k + 1];
+    if (s < 0 || e <= s || e > total) {
+        flags[1] = 1;
+        return;
+    }
+    int64_t p = e - s;
+    atomicMin(&minmax[0], (int32_t)(p > INT_MAX ? INT_MAX : p));
+    atomicMax(&minmax[1], (int32_t)(p > INT_MAX ? INT_MAX : p));
+    if (p > kMaxPs) {
+        flags[6] = 1;
+        return;
+    }
+    int32_t loc[kMaxPs];
+    for (int a = 0; a < p; ++a) {
+        int32_t g = dofs[s + a];
+        loc[a] = g;
+        if (g < 0 || g >= n) {
+            atomicMin(&flags[2], (int32_t)k);
+            return;
+        }
+    }
+    for (int a = 0; a < p; ++a)
+        for (int b = a + 1; b < p; ++b)
+            if (loc[a] == loc[b]) {
+                atomicMin(&flags[3], (int32_t)k);
+                return;
+            }
+}
+
+__global__ void k_cover(const int32_t* __restrict__ dofs, int64_t total, int32_t* cnt) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < total) atomicAdd(&cnt[dofs[i]], 1);
+}
+
+__global__ void k_weights(const int32_t* __restrict__ cnt, int64_t n, double* W, int32_t* flags) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t c = cnt[i];
+    if (c == 0) {
+        atomicMin(&flags[4], (int32_t)i);
+        W[i] = 0.0;
+    } else {
+        W[i] = 1.0 / (double)c;   // W = (sum_l V_l^T V_l)^{-1}, Section 2
+    }
+}
+
+__global__ void k_square_sizes(const int64_t* __restrict__ ptr, int64_t n_p, int64_t* out) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n_p) {
+        int64_t p = ptr[k + 1] - ptr[k];
+        out[k] = p * p;
+    }
+}
+
+// One wavefront (one block of 64 threads) per patch, grid-stride.
+// A_k[a][b] = A[g_a][g_b]: the wave walks the CSR rows of the patch's dofs as
+// one flattened, coalesced sequence of nonzeros; each nonzero's column is
+// looked up among the patch dofs (sorted in LDS) by binary search.
+__global__ __launch_bounds__(64) void k_extract(
+    const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const double* __restrict__ val, const int64_t* __restrict__ ptr,
+    const int32_t* __restrict__ dofs, int64_t n_p, const int64_t* __restrict__ toff,
+    int uniform_ps, double* __restrict__ tiles, uint32_t* __restrict__ keys,
+    double* __restrict__ fnorm, double* __restrict__ l1norm, int32_t* flags) {
+    __shared__ double s_tile[kMaxPs * kMaxPs];
+    __shared__ int32_t s_sorted[kMaxPs];
+    __shared__ int32_t s_loc[kMaxPs];
+    __shared__ int64_t s_rs[kMaxPs];
+    __shared__ int32_t s_off[kMaxPs + 1];
+    const int lane = threadIdx.x;
+
+    for (int64_t k = blockIdx.x; k < n_p; k += gridDim.x) {
+        const int64_t s0 = ptr[k];
+        const int p = (int)(ptr[k + 1] - s0);
+        const int64_t t0 = uniform_ps ? k * (int64_t)uniform_ps * uniform_ps : toff[k];
+
+        int32_t g = lane < p ? dofs[s0 + lane] : INT_MAX;
+        int64_t rs = 0, re = 0;
+        if (lane < p) {
+            rs = rowptr[g];
+            re = rowptr[g + 1];
+        }
+        // rank of my dof among the patch dofs (distinct) -> sorted order
+        int rank = 0;
+        for (int b = 0; b < p; ++b) {
+            int32_t gb = __shfl(g, b);
+            rank += (gb < g) ? 1 : 0;
+        }
+        if (lane < p) {
+            s_sorted[rank] = g;
+            s_loc[rank] = lane;
+            s_rs[lane] = rs;
+        }
+        // exclusive prefix of row lengths over the p lanes
+        int len = lane < p ? (int)(re - rs) : 0;
+        int incl = len;
+        for (int o = 1; o < PR_WAVE; o <<= 1) {
+            int u = __shfl_up(incl, o);
+            if (lane >= o) incl += u;
+        }
+        if (lane < p) s_off[lane] = incl - len;
+        const int T = __shfl(incl, p - 1);
+        for (int e = lane; e < p * p; e += PR_WAVE) s_tile[e] = 0.0;
+        __syncthreads();
+
+        for (int e = lane; e < T; e += PR_WAVE) {
+            // row a: last a with s_off[a] <= e
+            int lo = 0, hi = p - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= e) lo = mid; else hi = mid - 1;
+            }
+            const int a = lo;
+            const int64_t q = s_rs[a] + (e - s_off[a]);
+            const int32_t c = col[q];
+            const double v = val[q];
+            int l2 = 0, h2 = p - 1;
+            while (l2 < h2) {
+                int mid = (l2 + h2) >> 1;
+                if (s_sorted[mid] < c) l2 = mid + 1; else h2 = mid;
+            }
+            if (s_sorted[l2] == c) s_tile[a * p + s_loc[l2]] = v;
+        }
+        __syncthreads();
+
+        double sq = 0.0, ab = 0.0;
+        bool finite = true;
+        for (int e = lane; e < p * p; e += PR_WAVE) {
+            const double v = s_tile[e];
+            tiles[t0 + e] = v;
+            sq += v * v;
+            ab += fabs(v);
+            finite = finite && isfinite(v);
+        }
+        int nz = 0;
+        if (lane < p)
+            for (int b = 0; b < p; ++b) nz += (s_tile[lane * p + b] != 0.0) ? 1 : 0;
+        const unsigned long long bal = __ballot(lane < p && nz == 1);
+        sq = wave_sum(sq);
+        ab = wave_sum(ab);
+        const bool allfin = __all(finite);
+        if (lane == 0) {
+            keys[k] = (uint32_t)bal;
+            fnorm[k] = sqrt(sq);
+            l1norm[k] = ab;
+            if (!allfin) atomicMin(&flags[5], (int32_t)k);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_iota(int32_t* a, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = (int32_t)i;
+}
+
+__global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// ---- exclusive scan (int64) ------------------------------------------------
+
+constexpr int kScanThreads = 512;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int64_t* __restrict__ in,
+                                                            int64_t* __restrict__ out, int64_t n,
+                                                            int64_t* __restrict__ block_sums) {
+    __shared__ int64_t s_warp[kScanThreads / PR_WAVE];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
+    int64_t tsum = 0;
+#pragma unroll
+    for (int t = 0; t < kScanItems; ++t) {
+        v[t] = (base + t < n) ? in[base + t] : 0;
+        tsum += v[t];
+    }
+    const int lane = threadIdx.x & (PR_WAVE - 1), wid = threadIdx.x / PR_WAVE;
+    int64_t incl = tsum;
+    for (int o = 1; o < PR_WAVE; o <<= 1) {
+        int64_t u = __shfl_up(incl, o);
+        if (lane >= o) incl += u;
+    }
+    if (lane == PR_WAVE - 1) s_warp[wid] = incl;
+    __syncthreads();
+    int64_t woff = 0;
+    for (int w = 0; w < wid; ++w) woff += s_warp[w];
+    int64_t run = woff + incl - tsum;
+#pragma unroll
+    for (int t = 0; t < kScanItems; ++t) {
+        if (base + t < n) out[base + t] = run;
+        run += v[t];
+    }
+    if (threadIdx.x == kScanThreads - 1) block_sums[blockIdx.x] = woff + incl;
+}
+
+__global__ void k_scan_add(int64_t* __restrict__ out, int64_t n, const int64_t* __restrict__ offs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += offs[i / kScanTile];
+}
+
+// ---- bitonic sort of (uint64 key, int32 value) pairs -----------------------
+
+constexpr int kSortThreads = 512;
+constexpr int kSortLocal = 2 * kSortThreads;  // elements sorted inside one block
+
+__device__ __forceinline__ void cswap(uint64_t& ka, int32_t& va, uint64_t& kb, int32_t& vb, bool up) {
+    const bool gt = (ka > kb) || (ka == kb && va > vb);
+    if (gt == up) {
+        uint64_t tk = ka; ka = kb; kb = tk;
+        int32_t tv = va; va = vb; vb = tv;
+    }
+}
+
+// Sort-in-LDS phases: for every stage k <= kmax, or (when kfix > 0) only the
+// j < kSortLocal steps of stage kfix.
+__global__ __launch_bounds__(kSortThreads) void k_bitonic_local(uint64_t* keys, int32_t* vals,
+                                                                int64_t N, int64_t kfix) {
+    __shared__ uint64_t sk[kSortLocal];
+    __shared__ int32_t sv[kSortLocal];
+    const int64_t base = (int64_t)blockIdx.x * kSortLocal;
+    for (int t = threadIdx.x; t < kSortLocal; t += kSortThreads) {
+        sk[t] = keys[base + t];
+        sv[t] = vals[base + t];
+    }
+    __syncthreads();
+    const int64_t kbeg = kfix > 0 ? kfix : 2;
+    const int64_t kend = kfix > 0 ? kfix : (int64_t)kSortLocal;
+    for (int64_t k = kbeg; k <= kend; k <<= 1) {
+        for (int64_t j = (kfix > 0 ? kSortLocal / 2 : k / 2); j > 0; j >>= 1) {
+            const int t = threadIdx.x;
+            const int i = (int)(2 * j * (t / j) + (t % j));
+            const int l = i + (int)j;
+            const bool up = ((base + i) & k) == 0;
+            cswap(sk[i], sv[i], sk[l], sv[l], up);
+            __syncthreads();
+        }
+    }
+    for (int t = threadIdx.x; t < kSortLocal; t += kSortThreads) {
+        keys[base + t] = sk[t];
+        vals[base + t] = sv[t];
+    }
+}
+
+__global__ void k_bitonic_global(uint64_t* keys, int32_t* vals, int64_t N, int64_t k, int64_t j) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N / 2) return;
+    const int64_t i = 2 * j * (t / j) + (t % j);
+    const int64_t l = i + j;
+    const bool up = (i & k) == 0;
+    uint64_t ka = keys[i], kb = keys[l];
+    int32_t va = vals[i], vb = vals[l];
+    cswap(ka, va, kb, vb, up);
+    keys[i] = ka; keys[l] = kb;
+    vals[i] = va; vals[l] = vb;
+}
+
+__global__ void k_pad_copy(const uint64_t* __restrict__ kin, const int32_t* __restrict__ vin,
+                           int64_t n, uint64_t* kout, int32_t* vout, int64_t N) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    kout[i] = i < n ? kin[i] : ~0ull;
+    vout[i] = i < n ? vin[i] : INT_MAX;
+}
+
+__global__ void k_unpad_copy(const uint64_t* __restrict__ kin, const int32_t* __restrict__ vin,
+                             int64_t n, uint64_t* kout, int32_t* vout) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        kout[i] = kin[i];
+        vout[i] = vin[i];
+    }
+}
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+void launch_validate_csr(const int64_t* rowptr, const int32_t* col, int64_t n, int64_t nnz,
+                         int32_t* flags, hipStream_t s) {
+    k_validate_csr<<<nblk(n > 0 ? n : 1, 256), 256, 0, s>>>(rowptr, col, n, nnz, flags);
+}
+
+void launch_validate_patches(const int64_t* ptr, const int32_t* dofs, int64_t n_p, int64_t n,
+                             int64_t total, int32_t* flags, int32_t* minmax_ps, hipStream_t s) {
+    k_validate_patches<<<nblk(n_p > 0 ? n_p : 1, 256), 256, 0, s>>>(ptr, dofs, n_p, n, total, flags,
+                                                                  minmax_ps);
+}
+
+void launch_cover(const int32_t* dofs, int64_t total, int32_t* cnt, hipStream_t s) {
+    if (total > 0) k_cover<<<nblk(total, 256), 256, 0, s>>>(dofs, total, cnt);
+}
+
+void launch_weights(const int32_t* cnt, int64_t n, double* W, int32_t* flags, hipStream_t s) {
+    k_weights<<<nblk(n, 256), 256, 0, s>>>(cnt, n, W, flags);
+}
+
+int64_t scan_scratch_elems(int64_t n) {
+    int64_t tot = 0;
+    while (n > 1) {
+        n = (n + kScanTile - 1) / kScanTile;
+        tot += 2 * n + 1;
+    }
+    return tot + 2;
+}
+
+void launch_exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* scratch,
+                               hipStream_t s) {
+    if (n <= 0) return;
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    int64_t* sums = scratch;
+    k_scan_tile<<<(unsigned)nb, kScanThreads, 0, s>>>(in, out, n, sums);
+    if (nb == 1) return;
+    int64_t* offs = scratch + nb;
+    launch_exclusive_scan_i64(sums, offs, nb, scratch + 2 * nb + 1, s);
+    k_scan_add<<<nblk(n, 256), 256, 0, s>>>(out, n, offs);
+}
+
+void launch_tile_offsets(const int64_t* ptr, int64_t n_p, int64_t* toff, int64_t* scratch,
+                         hipStream_t s) {
+    // toff[k] = sum_{l<k} p_l^2 ; toff has n_p+1 entries (sizes written to toff+... via scratch)
+    int64_t* sq = scratch;
+    k_square_sizes<<<nblk(n_p + 1, 256), 256, 0, s>>>(ptr, n_p, sq);
+    hipMemsetAsync(sq + n_p, 0, sizeof(int64_t), s);
+    launch_exclusive_scan_i64(sq, toff, n_p + 1, scratch + n_p + 1, s);
+}
+
+void launch_extract(const int64_t* rowptr, const int32_t* col, const double* val,
+                    const int64_t* ptr, const int32_t* dofs, int64_t n_p, const int64_t* toff,
+                    int uniform_ps, double* tiles, uint32_t* keys, double* fnorm, double* l1norm,
+                    int32_t* flags, hipStream_t s) {
+    if (n_p <= 0) return;
+    const int64_t grid = n_p < 65536 * 4 ? n_p : 65536 * 4;
+    k_extract<<<(unsigned)grid, 64, 0, s>>>(rowptr, col, val, ptr, dofs, n_p, toff, uniform_ps,
+                                            tiles, keys, fnorm, l1norm, flags);
+}
+
+void launch_iota(int32_t* a, int64_t n, hipStream_t s) {
+    if (n > 0) k_iota<<<nblk(n, 256), 256, 0, s>>>(a, n);
+}
+
+void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t s) {
+    if (n > 0) k_fill_i32<<<nblk(n, 256), 256, 0, s>>>(a, n, v);
+}
+
+void launch_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, uint64_t* kscr, int32_t* vscr,
+                       hipStream_t s) {
+    if (n <= 1) return;
+    int64_t N = kSortLocal;
+    while (N < n) N <<= 1;
+    k_pad_copy<<<nblk(N, 256), 256, 0, s>>>(keys, vals, n, kscr, vscr, N);
+    const unsigned lblocks = (unsigned)(N / kSortLocal);
+    k_bitonic_local<<<lblocks, kSortThreads, 0, s>>>(kscr, vscr, N, 0);
+    for (int64_t k = 2 * kSortLocal; k <= N; k <<= 1) {
+        for (int64_t j = k / 2; j >= kSortLocal; j >>= 1)
+            k_bitonic_global<<<nblk(N / 2, 256), 256, 0, s>>>(kscr, vscr, N, k, j);
+        k_bitonic_local<<<lblocks, kSortThreads, 0, s>>>(kscr, vscr, N, k);
+    }
+    k_unpad_copy<<<nblk(n, 256), 256, 0, s>>>(kscr, vscr, n, keys, vals);
+}

@@ -1,0 +1,831 @@
+// C ABI of libpatchrelax.so: handle lifecycle, setup orchestration
+// (Section 2 objects, database construction of Section 3, factorisation,
+// grouping), the preconditioner apply of Eq.(3) and the right-preconditioned
+// GMRES solve used in Section 4.
+#include "pr_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+namespace {
+
+std::mutex g_mu;
+std::string g_last_error;
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename T>
+int dalloc(pr_handle h, T** p, size_t count) {
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return pr_fail(h, PR_ERR_OOM, std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
+                                          " bytes failed: " + hipGetErrorString(e));
+    }
+    h->owned.push_back({(void*)*p, count * sizeof(T)});
+    return PR_OK;
+}
+
+bool is_device_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+int check_dev(pr_handle h, const void* p, const char* what) {
+    if (!p) return pr_fail(h, PR_ERR_INVALID_ARG, std::string(what) + " is null");
+    if (!is_device_ptr(p)) return pr_fail(h, PR_ERR_HOST_POINTER, std::string(what) + " is not device memory");
+    return PR_OK;
+}
+
+int pow2_group(int p) {
+    int g = 4;
+    while (g < p) g <<= 1;
+    return g;
+}
+
+int64_t next_pow2(int64_t n) {
+    int64_t N = 1024;
+    while (N < n) N <<= 1;
+    return N;
+}
+
+// ---- Algorithm 1 ------------------------------------------------------------
+int run_alg1(pr_handle h) {
+    hipStream_t s = h->stream;
+    const int64_t n_p = h->n_p;
+    const int64_t stride = (int64_t)h->max_ps * h->max_ps;
+    Alg1Dev a{};
+    PR_TRY(dalloc(h, &a.status, n_p));
+    PR_TRY(dalloc(h, &a.ctrl, 8));
+    PR_TRY(dalloc(h, &a.counters, 8));
+    PR_TRY(dalloc(h, &a.cand, n_p));
+    PR_TRY(dalloc(h, &h->phi, n_p));
+    PR_TRY(dalloc(h, &h->reps, n_p));
+    PR_TRY(dalloc(h, &h->db, (size_t)n_p * stride));
+    PR_HIP(h, hipMemsetAsync(a.status, 0, n_p * sizeof(int32_t), s));
+    int32_t ctrl0[8] = {-1, 0, 0, 0, 0, 0, 0, 0};
+    PR_HIP(h, hipMemcpyAsync(a.ctrl, ctrl0, sizeof(ctrl0), hipMemcpyHostToDevice, s));
+    PR_HIP(h, hipMemsetAsync(a.counters, 0, 8 * sizeof(unsigned long long), s));
+    const double* keynorm = (h->prm.criterion == PR_CRIT_L1) ? h->l1norm : h->fnorm;
+    int batch = 8;
+    int32_t ctrl[8];
+    int64_t rounds = 0;
+    for (;;) {
+        launch_alg1_rounds(batch, a, h->prm.criterion, h->prm.eps, n_p, h->pptr, h->tiles,
+                           h->uniform ? nullptr : h->toff, h->uniform ? h->max_ps : 0, keynorm,
+                           h->phi, h->reps, h->db, stride, s);
+        rounds += batch;
+        PR_HIP(h, hipMemcpyAsync(ctrl, a.ctrl, sizeof(ctrl), hipMemcpyDeviceToHost, s));
+        PR_HIP(h, hipStreamSynchronize(s));
+        if (ctrl[3]) break;
+        if (batch < 256) batch *= 2;
+    }
+    if (ctrl[5] != 0)
+        return pr_fail(h, PR_ERR_SINGULAR_PATCH,
+                       "zero pivot in database patch " + std::to_string(ctrl[5] - 1));
+    h->m_p = ctrl[2];
+    unsigned long long cnt[8];
+    PR_HIP(h, hipMemcpy(cnt, a.counters, sizeof(cnt), hipMemcpyDeviceToHost));
+    h->stats.crit_evals = (int64_t)cnt[0];
+    h->stats.crit_exact = (int64_t)cnt[1];
+    h->stats.crit_pruned = (int64_t)cnt[2];
+    h->stats.alg1_rounds = h->m_p;
+    h->reps_host.resize(h->m_p);
+    PR_HIP(h, hipMemcpy(h->reps_host.data(), h->reps, h->m_p * sizeof(int32_t), hipMemcpyDeviceToHost));
+    // database offsets: entry j keeps the slot stride of the largest patch
+    h->dbps_host.resize(h->m_p);
+    std::vector<int64_t> pptr_host(h->n_p + 1);
+    PR_HIP(h, hipMemcpy(pptr_host.data(), h->pptr, (h->n_p + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    h->dboff_host.resize(h->m_p + 1);
+    for (int64_t j = 0; j < h->m_p; ++j) {
+        const int32_t r = h->reps_host[j];
+        h->dbps_host[j] = (int32_t)(pptr_host[r + 1] - pptr_host[r]);
+        h->dboff_host[j] = j * stride;
+    }
+    h->dboff_host[h->m_p] = h->m_p * stride;
+    (void)rounds;
+    return PR_OK;
+}
+
+// ---- FULL path: every patch is its own entry -------------------------------
+int run_full(pr_handle h) {
+    hipStream_t s = h->stream;
+    const int64_t n_p = h->n_p;
+    PR_TRY(dalloc(h, &h->phi, n_p));
+    PR_TRY(dalloc(h, &h->reps, n_p));
+    PR_TRY(dalloc(h, &h->db, h->total_tile));
+    launch_iota(h->phi, n_p, s);
+    launch_iota(h->reps, n_p, s);
+    int32_t* info = nullptr;
+    PR_TRY(dalloc(h, &info, n_p));
+    launch_batch_inverse(h->max_ps, n_p, h->tiles, h->uniform ? nullptr : h->toff, nullptr,
+                         h->uniform ? nullptr : h->pptr, h->db, h->uniform ? nullptr : h->toff, info, s);
+    std::vector<int32_t> info_h(n_p);
+    PR_HIP(h, hipMemcpyAsync(info_h.data(), info, n_p * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PR_HIP(h, hipStreamSynchronize(s));
+    for (int64_t k = 0; k < n_p; ++k)
+        if (info_h[k] != 0)
+            return pr_fail(h, PR_ERR_SINGULAR_PATCH, "zero pivot in patch " + std::to_string(k));
+    h->m_p = n_p;
+    h->reps_host.resize(n_p);
+    for (int64_t k = 0; k < n_p; ++k) h->reps_host[k] = (int32_t)k;
+    std::vector<int64_t> pptr_host(n_p + 1);
+    PR_HIP(h, hipMemcpy(pptr_host.data(), h->pptr, (n_p + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    h->dbps_host.resize(n_p);
+    h->dboff_host.resize(n_p + 1);
+    int64_t off = 0;
+    for (int64_t k = 0; k < n_p; ++k) {
+        const int p = (int)(pptr_host[k + 1] - pptr_host[k]);
+        h->dbps_host[k] = p;
+        h->dboff_host[k] = off;
+        off += (int64_t)p * p;
+    }
+    h->dboff_host[n_p] = off;
+    h->stats.crit_evals = 0;
+    return PR_OK;
+}
+
+// ---- grouping and precision conversion -------------------------------------
+int run_group(pr_handle h) {
+    hipStream_t s = h->stream;
+    const int64_t n_p = h->n_p, m_p = h->m_p;
+    // order = patches sorted by (entry, id)
+    uint64_t* keys = nullptr;
+    uint64_t* kscr = nullptr;
+    int32_t* vscr = nullptr;
+    const int64_t N = next_pow2(n_p);
+    PR_TRY(dalloc(h, &keys, n_p));
+    PR_TRY(dalloc(h, &kscr, N));
+    PR_TRY(dalloc(h, &vscr, N));
+    PR_TRY(dalloc(h, &h->order, n_p));
+    std::vector<int32_t> phi_h(n_p);
+    PR_HIP(h, hipMemcpyAsync(phi_h.data(), h->phi, n_p * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PR_HIP(h, hipStreamSynchronize(s));
+    // entry sizes for the work items (host, O(n_p) integer work)
+    std::vector<int64_t> count(m_p, 0);
+    for (int64_t k = 0; k < n_p; ++k) {
+        if (phi_h[k] < 0 || phi_h[k] >= m_p)
+            return pr_fail(h, PR_ERR_INVALID_ARG, "internal: patch map out of range");
+        count[phi_h[k]]++;
+    }
+    std::vector<uint64_t> keys_h(n_p);
+    for (int64_t k = 0; k < n_p; ++k) keys_h[k] = ((uint64_t)(uint32_t)phi_h[k] << 32) | (uint32_t)k;
+    PR_HIP(h, hipMemcpyAsync(keys, keys_h.data(), n_p * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    launch_iota(h->order, n_p, s);
+    launch_sort_pairs(keys, h->order, n_p, kscr, vscr, s);
+    // work items of <= 16 (p <= 16) or <= 32 members of one entry
+    std::vector<int32_t> items;
+    int64_t start = 0;
+    for (int64_t j = 0; j < m_p; ++j) {
+        const int p = h->dbps_host[j];
+        const int nb = p <= 16 ? 16 : 32;
+        for (int64_t t = 0; t < count[j]; t += nb) {
+            items.push_back((int32_t)j);
+            items.push_back((int32_t)(start + t));
+            items.push_back((int32_t)std::min<int64_t>(nb, count[j] - t));
+            items.push_back(p);
+        }
+        start += count[j];
+    }
+    h->n_items = (int64_t)items.size() / 4;
+    PR_TRY(dalloc(h, &h->items, items.size()));
+    PR_HIP(h, hipMemcpyAsync(h->items, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    // database offsets / sizes on the device
+    int32_t* dbps = nullptr;
+    PR_TRY(dalloc(h, &dbps, m_p));
+    PR_HIP(h, hipMemcpyAsync(dbps, h->dbps_host.data(), m_p * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    PR_TRY(dalloc(h, &h->dboff, m_p + 1));
+    PR_HIP(h, hipMemcpyAsync(h->dboff, h->dboff_host.data(), (m_p + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    const int64_t dbsize = h->dboff_host[m_p];
+    PR_TRY(dalloc(h, &h->db_cm, dbsize));
+    const int prec = h->prm.apply_precision;
+    h->apply_prec = prec;
+    if (prec == PR_FP32) PR_TRY(dalloc(h, &h->db_f32, dbsize));
+    int64_t lp_elems = 0;
+    if (prec == PR_BF16 || prec == PR_FP16 || prec == PR_BF16X3) {
+        const int64_t mult = prec == PR_BF16X3 ? 2 : 1;   // high and low parts
+        std::vector<int64_t> off(m_p + 1);
+        for (int64_t j = 0; j < m_p; ++j) {
+            off[j] = lp_elems;
+            lp_elems += mult * (h->dbps_host[j] <= 16 ? 256 : 1024);
+        }
+        off[m_p] = lp_elems;
+        uint16_t* lp = nullptr;
+        PR_TRY(dalloc(h, &lp, lp_elems));
+        h->db_lp = lp;
+        PR_TRY(dalloc(h, &h->dblp_off, m_p + 1));
+        PR_HIP(h, hipMemcpyAsync(h->dblp_off, off.data(), (m_p + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        PR_TRY(dalloc(h, &h->db_exp, m_p));
+    }
+    launch_convert_db(prec, m_p, h->db, h->dboff, dbps, 0, (uint16_t*)h->db_lp, h->dblp_off, h->db_exp,
+                      h->db_f32, h->db_cm, s);
+    PR_HIP(h, hipStreamSynchronize(s));
+    PR_HIP(h, hipGetLastError());
+    h->stats.n_items = h->n_items;
+    h->stats.bytes_db = dbsize * 8;
+    h->stats.bytes_db_lowp = prec == PR_FP32 ? dbsize * 4 : lp_elems * 2;
+    h->stats.bytes_index = n_p * 4;
+    return PR_OK;
+}
+
+// z (+)= omega M~^{-1} r ; z must be zeroed by the caller for a plain apply
+int apply_accumulate(pr_handle h, const double* r, double* z) {
+    hipStream_t s = h->stream;
+    const double om = h->prm.omega;
+    switch (h->apply_prec) {
+        case PR_FP64:
+            launch_apply_vec_f64(h->order, h->n_p, h->phi, h->pptr, h->pdofs, h->db_cm, h->dboff, 0, h->W,
+                                 om, r, z, pow2_group(h->max_ps), s);
+            break;
+        case PR_FP32:
+            launch_apply_vec_f32(h->order, h->n_p, h->phi, h->pptr, h->pdofs, h->db_f32, h->dboff, 0, h->W,
+                                 om, r, z, pow2_group(h->max_ps), s);
+            break;
+        default:
+            launch_apply_mfma(h->apply_prec, h->items, h->n_items, h->order, h->pptr, h->pdofs,
+                              (const uint16_t*)h->db_lp, h->dblp_off, h->db_exp, h->W, om, r, z, s);
+    }
+    return PR_OK;
+}
+
+// e = sweeps damped smoothing steps from 0 applied to v (uses t3 as scratch)
+int precond(pr_handle h, const double* v, double* e, double* t3) {
+    hipStream_t s = h->stream;
+    launch_zero(e, h->n, s);
+    apply_accumulate(h, v, e);
+    for (int sw = 1; sw < h->prm.sweeps; ++sw) {
+        launch_spmv(h->rowptr, h->col, h->val, h->n, e, v, t3, (int)(h->nnz / std::max<int64_t>(h->n, 1)), s);
+        apply_accumulate(h, t3, e);
+    }
+    return PR_OK;
+}
+
+int ensure_workspace(pr_handle h, int m) {
+    if (h->ws_restart >= m) return PR_OK;
+    const int64_t n = h->n;
+    PR_TRY(dalloc(h, &h->V, (size_t)(m + 1) * n));
+    PR_TRY(dalloc(h, &h->w, n));
+    PR_TRY(dalloc(h, &h->t1, n));
+    PR_TRY(dalloc(h, &h->t2, 2 * n));
+    PR_TRY(dalloc(h, &h->red, (size_t)reduce_blocks(n) * 32 + 64));
+    PR_TRY(dalloc(h, &h->hd, 256));
+    if (!h->hh) PR_HIP(h, hipHostMalloc((void**)&h->hh, 256 * sizeof(double), hipHostMallocDefault));
+    h->ws_restart = m;
+    return PR_OK;
+}
+
+}  // namespace
+
+void pr_set_global_error(const std::string& s) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_last_error = s;
+}
+
+int pr_fail(pr_handle h, int code, const std::string& msg) {
+    if (h) h->last_error = msg;
+    pr_set_global_error(msg);
+    return code;
+}
+
+extern "C" {
+
+void pr_params_default(pr_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->algo = PR_ALGO_FULL;
+    p->criterion = PR_CRIT_SPECTRAL;
+    p->eps = 1e-8;
+    p->m_target = 0;
+    p->partition_bc = 1;
+    p->kmeans_max_iter = 100;
+    p->seed = 5;
+    p->tie_rel = 1e-9;
+    p->apply_precision = PR_FP64;
+    p->omega = 1.0;
+    p->sweeps = 1;
+    p->gmres_restart = 30;
+    p->max_iters = 10000;
+    p->deterministic = 0;
+    p->stream = nullptr;
+}
+
+const char* pr_status_string(int st) {
+    switch (st) {
+        case PR_OK: return "ok";
+        case PR_NOT_CONVERGED: return "not converged";
+        case PR_ERR_INVALID_ARG: return "invalid argument";
+        case PR_ERR_HOST_POINTER: return "host pointer where device memory is required";
+        case PR_ERR_DOF_OUT_OF_RANGE: return "patch dof out of range";
+        case PR_ERR_DUP_DOF_IN_PATCH: return "duplicate dof in a patch";
+        case PR_ERR_UNCOVERED_DOF: return "dof in no patch";
+        case PR_ERR_SINGULAR_PATCH: return "singular patch matrix";
+        case PR_ERR_NONFINITE: return "non-finite value";
+        case PR_ERR_OOM: return "out of device memory";
+        case PR_ERR_HIP: return "HIP runtime error";
+        case PR_ERR_UNSUPPORTED: return "unsupported input";
+        case PR_ERR_BAD_CSR: return "malformed CSR matrix";
+        case PR_ERR_BAD_PATCH_PTR: return "malformed patch pointer array";
+        default: return "unknown status";
+    }
+}
+
+const char* pr_last_error(pr_handle h) {
+    if (h) return h->last_error.c_str();
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_last_error.c_str();
+}
+
+void pr_destroy(pr_handle h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    for (auto e : h->evpool) (void)hipEventDestroy(e);
+    for (auto& b : h->owned) (void)hipFree(b.p);
+    if (h->hh) (void)hipHostFree(h->hh);
+    delete h;
+}
+
+int pr_set_stream(pr_handle h, void* st) {
+    if (!h) return PR_ERR_INVALID_ARG;
+    h->stream = (hipStream_t)st;
+    h->prm.stream = st;
+    return PR_OK;
+}
+
+int pr_validate_host(const pr_csr* A, const pr_patches* P) {
+    if (!A || !P) return pr_fail(nullptr, PR_ERR_INVALID_ARG, "null argument");
+    if (A->n <= 0 || A->nnz < 0 || P->n_p <= 0 || !A->row_ptr || !P->ptr || (A->nnz > 0 && (!A->col || !A->val)))
+        return pr_fail(nullptr, PR_ERR_INVALID_ARG, "bad sizes or null arrays");
+    const int64_t n = A->n;
+    if (A->row_ptr[0] != 0 || A->row_ptr[n] != A->nnz) return pr_fail(nullptr, PR_ERR_BAD_CSR, "row_ptr ends");
+    for (int64_t i = 0; i < n; ++i) {
+        if (A->row_ptr[i + 1] < A->row_ptr[i]) return pr_fail(nullptr, PR_ERR_BAD_CSR, "row_ptr not monotone");
+        int32_t prev = -1;
+        for (int64_t q = A->row_ptr[i]; q < A->row_ptr[i + 1]; ++q) {
+            const int32_t c = A->col[q];
+            if (c < 0 || c >= n || c <= prev) return pr_fail(nullptr, PR_ERR_BAD_CSR, "column out of range or unsorted");
+            prev = c;
+        }
+    }
+    const int64_t total = P->ptr[P->n_p];
+    if (P->ptr[0] != 0 || total < 0 || (total > 0 && !P->dofs)) return pr_fail(nullptr, PR_ERR_BAD_PATCH_PTR, "ptr ends");
+    std::vector<int32_t> cnt(n, 0);
+    int rc_unsup = 0;
+    for (int64_t k = 0; k < P->n_p; ++k) {
+        const int64_t s = P->ptr[k], e = P->ptr[k + 1];
+        if (e <= s || e > total) return pr_fail(nullptr, PR_ERR_BAD_PATCH_PTR, "empty patch or ptr not monotone");
+        if (e - s > 32) rc_unsup = 1;
+        for (int64_t q = s; q < e; ++q) {
+            const int32_t g = P->dofs[q];
+            if (g < 0 || g >= n) return pr_fail(nullptr, PR_ERR_DOF_OUT_OF_RANGE, "dof out of range in patch " + std::to_string(k));
+            for (int64_t q2 = s; q2 < q; ++q2)
+                if (P->dofs[q2] == g) return pr_fail(nullptr, PR_ERR_DUP_DOF_IN_PATCH, "duplicate dof in patch " + std::to_string(k));
+            cnt[g]++;
+        }
+    }
+    if (rc_unsup) return pr_fail(nullptr, PR_ERR_UNSUPPORTED, "patch with more than 32 dofs");
+    for (int64_t i = 0; i < n; ++i)
+        if (cnt[i] == 0) return pr_fail(nullptr, PR_ERR_UNCOVERED_DOF, "dof " + std::to_string(i) + " in no patch");
+    for (int64_t q = 0; q < A->nnz; ++q)
+        if (!std::isfinite(A->val[q])) return pr_fail(nullptr, PR_ERR_NONFINITE, "non-finite matrix value");
+    return PR_OK;
+}
+
+int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_handle* out) {
+    if (!A || !P || !out) return pr_fail(nullptr, PR_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    pr_params defaults;
+    pr_params_default(&defaults);
+    const pr_params& pm = prm ? *prm : defaults;
+    if (A->n <= 0 || A->nnz < 0 || P->n_p <= 0) return pr_fail(nullptr, PR_ERR_INVALID_ARG, "bad sizes");
+    if (A->n > INT_MAX - 1 || P->n_p > INT_MAX - 1) return pr_fail(nullptr, PR_ERR_UNSUPPORTED, "more than 2^31 dofs or patches");
+    if (pm.algo < PR_ALGO_FULL || pm.algo > PR_ALGO_BOOTSTRAP || pm.criterion < 0 || pm.criterion > 2 ||
+        pm.apply_precision < 0 || pm.apply_precision > 4 || pm.sweeps < 1 || pm.gmres_restart < 1 ||
+        pm.gmres_restart > 64 || !(pm.eps >= 0.0) || !(pm.omega > 0.0))
+        return pr_fail(nullptr, PR_ERR_INVALID_ARG, "bad parameter value");
+    if (pm.algo != PR_ALGO_FULL && pm.algo != PR_ALGO_TOLERANCE)
+        return pr_fail(nullptr, PR_ERR_UNSUPPORTED, "clustering algorithms are not built in this library");
+    if (pm.deterministic) return pr_fail(nullptr, PR_ERR_UNSUPPORTED, "deterministic scatter not built");
+    {
+        int rc;
+        if ((rc = check_dev(nullptr, A->row_ptr, "A.row_ptr")) < 0) return rc;
+        if (A->nnz > 0 && (rc = check_dev(nullptr, A->col, "A.col")) < 0) return rc;
+        if (A->nnz > 0 && (rc = check_dev(nullptr, A->val, "A.val")) < 0) return rc;
+        if ((rc = check_dev(nullptr, P->ptr, "P.ptr")) < 0) return rc;
+        if ((rc = check_dev(nullptr, P->dofs, "P.dofs")) < 0) return rc;
+    }
+    pr_handle h = new pr_handle_s();
+    h->prm = pm;
+    h->stream = (hipStream_t)pm.stream;
+    hipStream_t s = h->stream;
+    (void)hipGetDevice(&h->device);
+    const double t0 = now_s();
+    h->n = A->n;
+    h->nnz = A->nnz;
+    h->n_p = P->n_p;
+    auto fail = [&](int rc) {
+        pr_set_global_error(h->last_error);
+        pr_destroy(h);
+        return rc;
+    };
+#define SETUP_TRY(expr)               \
+    do {                              \
+        int _s = (expr);              \
+        if (_s < 0) return fail(_s);  \
+    } while (0)
+#define SETUP_HIP(expr)                                                                      \
+    do {                                                                                     \
+        hipError_t _e = (expr);                                                              \
+        if (_e != hipSuccess) {                                                              \
+            pr_fail(h, _e == hipErrorOutOfMemory ? PR_ERR_OOM : PR_ERR_HIP,                  \
+                    std::string(#expr) + ": " + hipGetErrorString(_e));                      \
+            return fail(_e == hipErrorOutOfMemory ? PR_ERR_OOM : PR_ERR_HIP);                \
+        }                                                                                    \
+    } while (0)
+
+    int64_t total = 0;
+    SETUP_HIP(hipMemcpyAsync(&total, P->ptr + P->n_p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SETUP_HIP(hipStreamSynchronize(s));
+    if (total <= 0 || total > INT_MAX) {
+        pr_fail(h, PR_ERR_BAD_PATCH_PTR, "patch ptr[n_p] out of range");
+        return fail(PR_ERR_BAD_PATCH_PTR);
+    }
+    h->total_dofs = total;
+    SETUP_TRY(dalloc(h, &h->rowptr, h->n + 1));
+    SETUP_TRY(dalloc(h, &h->col, h->nnz));
+    SETUP_TRY(dalloc(h, &h->val, h->nnz));
+    SETUP_TRY(dalloc(h, &h->pptr, h->n_p + 1));
+    SETUP_TRY(dalloc(h, &h->pdofs, total));
+    SETUP_HIP(hipMemcpyAsync(h->rowptr, A->row_ptr, (h->n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    if (h->nnz > 0) {
+        SETUP_HIP(hipMemcpyAsync(h->col, A->col, h->nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        SETUP_HIP(hipMemcpyAsync(h->val, A->val, h->nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    SETUP_HIP(hipMemcpyAsync(h->pptr, P->ptr, (h->n_p + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    SETUP_HIP(hipMemcpyAsync(h->pdofs, P->dofs, total * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+
+    // ---- validation -------------------------------------------------------
+    int32_t* flags = nullptr;
+    int32_t* minmax = nullptr;
+    SETUP_TRY(dalloc(h, &flags, 8));
+    SETUP_TRY(dalloc(h, &minmax, 2));
+    const int32_t f0[8] = {0, 0, INT_MAX, INT_MAX, INT_MAX, INT_MAX, 0, 0};
+    const int32_t mm0[2] = {INT_MAX, 0};
+    SETUP_HIP(hipMemcpyAsync(flags, f0, sizeof(f0), hipMemcpyHostToDevice, s));
+    SETUP_HIP(hipMemcpyAsync(minmax, mm0, sizeof(mm0), hipMemcpyHostToDevice, s));
+    launch_validate_csr(h->rowptr, h->col, h->n, h->nnz, flags, s);
+    launch_validate_patches(h->pptr, h->pdofs, h->n_p, h->n, total, flags, minmax, s);
+    int32_t fl[8], mm[2];
+    SETUP_HIP(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+    SETUP_HIP(hipMemcpyAsync(mm, minmax, sizeof(mm), hipMemcpyDeviceToHost, s));
+    SETUP_HIP(hipStreamSynchronize(s));
+    SETUP_HIP(hipGetLastError());
+    if (fl[0]) { pr_fail(h, PR_ERR_BAD_CSR, "malformed CSR (row_ptr, column range or order)"); return fail(PR_ERR_BAD_CSR); }
+    if (fl[1]) { pr_fail(h, PR_ERR_BAD_PATCH_PTR, "malformed patch ptr or empty patch"); return fail(PR_ERR_BAD_PATCH_PTR); }
+    if (fl[6]) { pr_fail(h, PR_ERR_UNSUPPORTED, "patch with more than 32 dofs"); return fail(PR_ERR_UNSUPPORTED); }
+    if (fl[2] != INT_MAX) { pr_fail(h, PR_ERR_DOF_OUT_OF_RANGE, "dof out of range in patch " + std::to_string(fl[2])); return fail(PR_ERR_DOF_OUT_OF_RANGE); }
+    if (fl[3] != INT_MAX) { pr_fail(h, PR_ERR_DUP_DOF_IN_PATCH, "duplicate dof in patch " + std::to_string(fl[3])); return fail(PR_ERR_DUP_DOF_IN_PATCH); }
+    h->min_ps = mm[0];
+    h->max_ps = mm[1];
+    h->uniform = (h->min_ps == h->max_ps);
+
+    // ---- W (Section 2) ------------------------------------------------------
+    SETUP_TRY(dalloc(h, &h->cnt, h->n));
+    SETUP_TRY(dalloc(h, &h->W, h->n));
+    SETUP_HIP(hipMemsetAsync(h->cnt, 0, h->n * sizeof(int32_t), s));
+    launch_cover(h->pdofs, total, h->cnt, s);
+    launch_weights(h->cnt, h->n, h->W, flags, s);
+    const double t1 = now_s();
+
+    // ---- tiles (Section 2) --------------------------------------------------
+    SETUP_TRY(dalloc(h, &h->toff, h->n_p + 1));
+    int64_t* scan_scr = nullptr;
+    SETUP_TRY(dalloc(h, &scan_scr, h->n_p + 2 + scan_scratch_elems(h->n_p + 1)));
+    launch_tile_offsets(h->pptr, h->n_p, h->toff, scan_scr, s);
+    SETUP_HIP(hipMemcpyAsync(&h->total_tile, h->toff + h->n_p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SETUP_HIP(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+    SETUP_HIP(hipStreamSynchronize(s));
+    if (fl[4] != INT_MAX) { pr_fail(h, PR_ERR_UNCOVERED_DOF, "dof " + std::to_string(fl[4]) + " lies in no patch"); return fail(PR_ERR_UNCOVERED_DOF); }
+    SETUP_TRY(dalloc(h, &h->tiles, h->total_tile));
+    SETUP_TRY(dalloc(h, &h->keys, h->n_p));
+    SETUP_TRY(dalloc(h, &h->fnorm, h->n_p));
+    SETUP_TRY(dalloc(h, &h->l1norm, h->n_p));
+    launch_extract(h->rowptr, h->col, h->val, h->pptr, h->pdofs, h->n_p, h->uniform ? nullptr : h->toff,
+                   h->uniform ? h->max_ps : 0, h->tiles, h->keys, h->fnorm, h->l1norm, flags, s);
+    SETUP_HIP(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+    SETUP_HIP(hipStreamSynchronize(s));
+    SETUP_HIP(hipGetLastError());
+    if (fl[5] != INT_MAX) { pr_fail(h, PR_ERR_NONFINITE, "non-finite entry in patch " + std::to_string(fl[5])); return fail(PR_ERR_NONFINITE); }
+    const double t2 = now_s();
+
+    // ---- database (Section 3) ----------------------------------------------
+    if (pm.algo == PR_ALGO_FULL) SETUP_TRY(run_full(h));
+    else SETUP_TRY(run_alg1(h));
+    SETUP_HIP(hipStreamSynchronize(s));
+    SETUP_HIP(hipGetLastError());
+    const double t3 = now_s();
+    SETUP_TRY(run_group(h));
+    const double t4 = now_s();
+
+    // boundary groups (distinct keys) for the stats
+    {
+        std::vector<uint32_t> kh(h->n_p);
+        SETUP_HIP(hipMemcpy(kh.data(), h->keys, h->n_p * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        std::sort(kh.begin(), kh.end());
+        h->stats.n_groups = (int32_t)(std::unique(kh.begin(), kh.end()) - kh.begin());
+    }
+    h->stats.n = h->n;
+    h->stats.nnz = h->nnz;
+    h->stats.n_p = h->n_p;
+    h->stats.m_p = h->m_p;
+    h->stats.max_ps = h->max_ps;
+    h->stats.min_ps = h->min_ps;
+    h->stats.algo = pm.algo;
+    h->stats.bytes_tiles = h->total_tile * 8;
+    h->stats.t_validate = t1 - t0;
+    h->stats.t_extract = t2 - t1;
+    h->stats.t_database = t3 - t2;
+    h->stats.t_factor = 0.0;
+    h->stats.t_group = t4 - t3;
+    h->stats.t_total = t4 - t0;
+    h->stats.apply_precision = pm.apply_precision;
+#undef SETUP_TRY
+#undef SETUP_HIP
+    *out = h;
+    return PR_OK;
+}
+
+int pr_apply(pr_handle h, const double* r, double* z) {
+    if (!h) return PR_ERR_INVALID_ARG;
+    PR_TRY(check_dev(h, r, "r"));
+    PR_TRY(check_dev(h, z, "z"));
+    if (r == z) return pr_fail(h, PR_ERR_INVALID_ARG, "r and z must be distinct");
+    launch_zero(z, h->n, h->stream);
+    apply_accumulate(h, r, z);
+    PR_HIP(h, hipGetLastError());
+    return PR_OK;
+}
+
+int pr_solve(pr_handle h, const double* b, double* x, double tol) {
+    if (!h) return PR_ERR_INVALID_ARG;
+    PR_TRY(check_dev(h, b, "b"));
+    PR_TRY(check_dev(h, x, "x"));
+    if (!(tol > 0.0)) return pr_fail(h, PR_ERR_INVALID_ARG, "tol must be positive");
+    const double tstart = now_s();
+    // optional per-class device timing: 0 apply, 1 spmv, 2 orthogonalisation
+    const bool timing = h->prm.timing != 0;
+    struct Span { int cls; hipEvent_t a, b; };
+    std::vector<Span> spans;
+    size_t evnext = 0;
+    auto grab = [&]() -> hipEvent_t {
+        if (evnext >= h->evpool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            h->evpool.push_back(e);
+        }
+        return h->evpool[evnext++];
+    };
+    hipEvent_t tb = nullptr;
+    auto tbeg = [&]() {
+        if (timing) {
+            tb = grab();
+            if (tb) (void)hipEventRecord(tb, h->stream);
+        }
+    };
+    auto tend = [&](int cls) {
+        if (timing && tb) {
+            hipEvent_t te = grab();
+            if (te) {
+                (void)hipEventRecord(te, h->stream);
+                spans.push_back({cls, tb, te});
+            }
+        }
+    };
+    hipStream_t s = h->stream;
+    const int m = h->prm.gmres_restart;
+    const int64_t n = h->n;
+    PR_TRY(ensure_workspace(h, m));
+    const int avg = (int)(h->nnz / std::max<int64_t>(n, 1));
+    double* V = h->V;
+    double* w = h->w;
+    double* r = h->t1;
+    double* zt = h->t2;
+    double* t3 = h->t2 + n;
+    double* hd = h->hd;
+    double* hh = h->hh;
+
+    auto sync_read = [&](int count) -> int {
+        PR_HIP(h, hipMemcpyAsync(hh, hd, count * sizeof(double), hipMemcpyDeviceToHost, s));
+        PR_HIP(h, hipStreamSynchronize(s));
+        return PR_OK;
+    };
+    // ||b||
+    launch_multidot(b, n, 1, b, n, h->red, hd, s);
+    PR_TRY(sync_read(1));
+    const double bnorm = std::sqrt(hh[0]);
+    launch_zero(x, n, s);
+    h->sinfo = pr_solve_info{};
+    if (!std::isfinite(bnorm)) return pr_fail(h, PR_ERR_NONFINITE, "non-finite right-hand side");
+    if (bnorm == 0.0) {
+        h->sinfo.status = PR_OK;
+        PR_HIP(h, hipStreamSynchronize(s));
+        return PR_OK;
+    }
+    PR_HIP(h, hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    int64_t iters = 0, cycles = 0;
+    double relres = 1.0, est = 1.0;
+    const int64_t maxit = h->prm.max_iters;
+    for (;;) {
+        launch_multidot(r, n, 1, r, n, h->red, hd, s);
+        PR_TRY(sync_read(1));
+        const double beta = std::sqrt(hh[0]);
+        relres = beta / bnorm;
+        if (!std::isfinite(beta)) return pr_fail(h, PR_ERR_NONFINITE, "non-finite residual");
+        if (beta <= tol * bnorm || iters >= maxit) break;
+        ++cycles;
+        launch_scale(r, V, hd, n, s);
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int mm = 0;
+        for (int j = 0; j < m; ++j) {
+            double* vj = V + (int64_t)j * n;
+            tbeg();
+            PR_TRY(precond(h, vj, zt, t3));
+            tend(0);
+            tbeg();
+            launch_spmv(h->rowptr, h->col, h->val, n, zt, nullptr, w, avg, s);
+            tend(1);
+            ++iters;
+            // classical Gram-Schmidt, twice
+            tbeg();
+            launch_multidot(V, n, j + 1, w, n, h->red, hd, s);
+            launch_update(w, V, n, j + 1, hd, -1.0, n, s);
+            launch_multidot(V, n, j + 1, w, n, h->red, hd + 64, s);
+            launch_update(w, V, n, j + 1, hd + 64, -1.0, n, s);
+            launch_multidot(w, n, 1, w, n, h->red, hd + 128, s);
+            launch_scale(w, V + (int64_t)(j + 1) * n, hd + 128, n, s);
+            tend(2);
+            PR_HIP(h, hipMemcpyAsync(hh, hd, 129 * sizeof(double), hipMemcpyDeviceToHost, s));
+            PR_HIP(h, hipStreamSynchronize(s));
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[64 + i];
+            const double hn = std::sqrt(std::max(hh[128], 0.0));
+            H[(size_t)(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                const double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+            }
+            const double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
+            const double den = std::hypot(a, bb);
+            cs[j] = den > 0.0 ? a / den : 1.0;
+            sn[j] = den > 0.0 ? bb / den : 0.0;
+            H[(size_t)j * m + j] = den;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            mm = j + 1;
+            est = std::fabs(g[j + 1]) / bnorm;
+            if (!std::isfinite(est)) return pr_fail(h, PR_ERR_NONFINITE, "non-finite Arnoldi value");
+            if (std::fabs(g[j + 1]) <= tol * bnorm || iters >= maxit) break;
+        }
+        // y = H^{-1} g (upper triangular), u = V y, x += M(u)
+        for (int i = mm - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int k = i + 1; k < mm; ++k) t -= H[(size_t)i * m + k] * y[k];
+            y[i] = t / H[(size_t)i * m + i];
+        }
+        for (int i = 0; i < mm; ++i) hh[192 + i] = y[i];
+        PR_HIP(h, hipMemcpyAsync(hd + 192, hh + 192, mm * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_gemv_small(V, n, mm, hd + 192, n, r, s);
+        tbeg();
+        PR_TRY(precond(h, r, zt, t3));
+        tend(0);
+        launch_axpy_dev(x, zt, 1.0, n, s);
+        tbeg();
+        launch_spmv(h->rowptr, h->col, h->val, n, x, b, r, avg, s);
+        tend(1);
+        PR_HIP(h, hipStreamSynchronize(s));   // hh + 192 is reused next cycle
+    }
+    PR_HIP(h, hipStreamSynchronize(s));
+    PR_HIP(h, hipGetLastError());
+    h->sinfo.iters = iters;
+    h->sinfo.cycles = cycles;
+    h->sinfo.relres = relres;
+    h->sinfo.relres_est = est;
+    h->sinfo.status = relres <= tol ? PR_OK : PR_NOT_CONVERGED;
+    h->sinfo.seconds = now_s() - tstart;
+    for (const Span& sp : spans) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, sp.a, sp.b) != hipSuccess) continue;
+        if (sp.cls == 0) { h->sinfo.apply_ms += ms; h->sinfo.n_apply++; }
+        if (sp.cls == 1) { h->sinfo.spmv_ms += ms; h->sinfo.n_spmv++; }
+        if (sp.cls == 2) { h->sinfo.orth_ms += ms; h->sinfo.n_orth++; }
+    }
+    return h->sinfo.status;
+}
+
+int pr_get_solve_info(pr_handle h, pr_solve_info* info) {
+    if (!h || !info) return PR_ERR_INVALID_ARG;
+    *info = h->sinfo;
+    return PR_OK;
+}
+
+int pr_get_stats(pr_handle h, pr_stats* st) {
+    if (!h || !st) return PR_ERR_INVALID_ARG;
+    *st = h->stats;
+    return PR_OK;
+}
+
+int pr_get_assignment(pr_handle h, int32_t* phi, int32_t* reps, int64_t* m_p) {
+    if (!h) return PR_ERR_INVALID_ARG;
+    PR_HIP(h, hipStreamSynchronize(h->stream));
+    if (phi) PR_HIP(h, hipMemcpy(phi, h->phi, h->n_p * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (reps) std::memcpy(reps, h->reps_host.data(), h->m_p * sizeof(int32_t));
+    if (m_p) *m_p = h->m_p;
+    return PR_OK;
+}
+
+int pr_get_patch_tile(pr_handle h, int64_t k, double* tile) {
+    if (!h || !tile || k < 0 || k >= h->n_p) return PR_ERR_INVALID_ARG;
+    int64_t pp[2];
+    PR_HIP(h, hipStreamSynchronize(h->stream));
+    PR_HIP(h, hipMemcpy(pp, h->pptr + k, 2 * sizeof(int64_t), hipMemcpyDeviceToHost));
+    const int64_t p = pp[1] - pp[0];
+    int64_t off = 0;
+    if (h->uniform) off = k * p * p;
+    else PR_HIP(h, hipMemcpy(&off, h->toff + k, sizeof(int64_t), hipMemcpyDeviceToHost));
+    PR_HIP(h, hipMemcpy(tile, h->tiles + off, p * p * sizeof(double), hipMemcpyDeviceToHost));
+    return PR_OK;
+}
+
+int pr_get_weights(pr_handle h, double* W) {
+    if (!h || !W) return PR_ERR_INVALID_ARG;
+    PR_HIP(h, hipStreamSynchronize(h->stream));
+    PR_HIP(h, hipMemcpy(W, h->W, h->n * sizeof(double), hipMemcpyDeviceToHost));
+    return PR_OK;
+}
+
+int pr_get_boundary_keys(pr_handle h, uint32_t* keys) {
+    if (!h || !keys) return PR_ERR_INVALID_ARG;
+    PR_HIP(h, hipStreamSynchronize(h->stream));
+    PR_HIP(h, hipMemcpy(keys, h->keys, h->n_p * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    return PR_OK;
+}
+
+int pr_get_rep_inverse(pr_handle h, int64_t j, double* X) {
+    if (!h || !X || j < 0 || j >= h->m_p) return PR_ERR_INVALID_ARG;
+    PR_HIP(h, hipStreamSynchronize(h->stream));
+    const int64_t p = h->dbps_host[j];
+    PR_HIP(h, hipMemcpy(X, h->db + h->dboff_host[j], p * p * sizeof(double), hipMemcpyDeviceToHost));
+    return PR_OK;
+}
+
+int pr_batch_inverse(int32_t p, int64_t count, const double* A, double* X, int32_t* info, void* stream) {
+    if (p < 1 || p > 32 || count < 0) return pr_fail(nullptr, PR_ERR_INVALID_ARG, "p must be in [1, 32]");
+    if (count == 0) return PR_OK;
+    int rc;
+    if ((rc = check_dev(nullptr, A, "A")) < 0) return rc;
+    if ((rc = check_dev(nullptr, X, "X")) < 0) return rc;
+    if ((rc = check_dev(nullptr, info, "info")) < 0) return rc;
+    launch_batch_inverse(p, count, A, nullptr, nullptr, nullptr, X, nullptr, info, (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return pr_fail(nullptr, PR_ERR_HIP, hipGetErrorString(e));
+    return PR_OK;
+}
+
+int pr_batch_criterion(int32_t p, int64_t count, int32_t crit, const double* A, const double* B,
+                       const double* X, double* d, void* stream) {
+    if (p < 1 || p > 32 || count < 0 || crit < 0 || crit > 2)
+        return pr_fail(nullptr, PR_ERR_INVALID_ARG, "bad p, count or criterion");
+    if (count == 0) return PR_OK;
+    int rc;
+    if ((rc = check_dev(nullptr, A, "A")) < 0) return rc;
+    if ((rc = check_dev(nullptr, d, "d")) < 0) return rc;
+    if (crit == PR_CRIT_SPECTRAL) {
+        if ((rc = check_dev(nullptr, X, "X")) < 0) return rc;
+    } else {
+        if ((rc = check_dev(nullptr, B, "B")) < 0) return rc;
+    }
+    launch_batch_criterion(p, count, crit, A, B, X, d, (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return pr_fail(nullptr, PR_ERR_HIP, hipGetErrorString(e));
+    return PR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,226 @@
+// Internal declarations shared by the translation units of libpatchrelax.so.
+// gfx950 only: 64-lane wavefronts, FP64 hardware atomics, MFMA.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/patchrelax.h"
+
+#define PR_WAVE 64
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v, int width = PR_WAVE) {
+    for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v, int width = PR_WAVE) {
+    for (int o = width >> 1; o > 0; o >>= 1) {
+        T u = __shfl_xor(v, o, width);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+// FP32 -> BF16 round-to-nearest-even (finite inputs), returned as raw bits.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ uint16_t f32_to_f16_rne(float f) {
+    _Float16 h = (_Float16)f;   // v_cvt_f16_f32: round to nearest even
+    return __builtin_bit_cast(uint16_t, h);
+}
+
+// Exponent e with m * 2^-e in [2^13, 2^14) for a float magnitude m > 0.
+__device__ __forceinline__ int fp16_scale_exp(float m) {
+    if (m == 0.0f) return 0;
+    int E;
+    frexpf(m, &E);              // m = f 2^E, f in [0.5, 1)
+    return E - 14;
+}
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct pr_handle_s {
+    pr_params prm;
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    int64_t n = 0, nnz = 0, n_p = 0, total_dofs = 0, total_tile = 0;
+    int max_ps = 0, min_ps = 0;
+    bool uniform = true;
+
+    // copies of the inputs
+    int64_t* rowptr = nullptr;
+    int32_t* col = nullptr;
+    double* val = nullptr;
+    int64_t* pptr = nullptr;
+    int32_t* pdofs = nullptr;
+
+    // Section 2 objects
+    int32_t* cnt = nullptr;
+    double* W = nullptr;
+    int64_t* toff = nullptr;      // tile offsets (int64[n_p+1]); null when uniform
+    double* tiles = nullptr;
+    uint32_t* keys = nullptr;     // boundary keys
+    double* fnorm = nullptr;      // ||A_k||_F
+    double* l1norm = nullptr;     // sum |A_k|
+
+    // database
+    int64_t m_p = 0;
+    int32_t* phi = nullptr;
+    int32_t* reps = nullptr;      // patch id of entry j (or -1)
+    std::vector<int32_t> reps_host;
+    double* db = nullptr;         // FP64 inverses of the entries
+    double* db_mat = nullptr;     // entry matrices B_j (cluster means); null for patch reps
+    int64_t* dboff = nullptr;     // int64[m_p+1] offsets in doubles (null when uniform)
+    std::vector<int64_t> dboff_host;
+    std::vector<int32_t> dbps_host;  // p of entry j
+
+    // grouped apply
+    int32_t* order = nullptr;     // patches grouped by entry, ascending id within
+    int32_t* items = nullptr;     // int32[4*n_items]: entry, start, count, p
+    int64_t n_items = 0;
+    void* db_lp = nullptr;        // lane-ready low-precision database
+    int64_t* dblp_off = nullptr;  // element offsets into db_lp per entry
+    int32_t* db_exp = nullptr;    // FP16 scale exponents
+    float* db_f32 = nullptr;      // FP32 database (column-major per entry)
+    double* db_cm = nullptr;      // FP64 database column-major per entry (apply layout)
+    int apply_prec = PR_FP64;
+
+    // solve workspace
+    double* V = nullptr;
+    double* w = nullptr;
+    double* t1 = nullptr;
+    double* t2 = nullptr;
+    double* red = nullptr;        // reduction partials
+    double* hd = nullptr;         // device scalars
+    double* hh = nullptr;         // pinned host mirror
+    int64_t ws_restart = -1;
+    std::vector<hipEvent_t> evpool;   // reusable events for per-kernel timing
+
+    pr_solve_info sinfo{};
+    pr_stats stats{};
+    std::string last_error;
+    std::vector<DevBuf> owned;
+};
+
+// ---------------------------------------------------------------------------
+// error plumbing
+// ---------------------------------------------------------------------------
+
+void pr_set_global_error(const std::string& s);
+int pr_fail(pr_handle h, int code, const std::string& msg);
+
+#define PR_HIP(h, expr)                                                               \
+    do {                                                                              \
+        hipError_t _e = (expr);                                                       \
+        if (_e != hipSuccess)                                                         \
+            return pr_fail((h), _e == hipErrorOutOfMemory ? PR_ERR_OOM : PR_ERR_HIP,   \
+                           std::string(#expr) + ": " + hipGetErrorString(_e));        \
+    } while (0)
+
+#define PR_TRY(expr)                 \
+    do {                             \
+        int _s = (expr);             \
+        if (_s < 0) return _s;       \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// launchers (one translation unit each)
+// ---------------------------------------------------------------------------
+
+// k_setup.hip
+void launch_validate_csr(const int64_t* rowptr, const int32_t* col, int64_t n, int64_t nnz,
+                         int32_t* flags, hipStream_t s);
+void launch_validate_patches(const int64_t* ptr, const int32_t* dofs, int64_t n_p, int64_t n,
+                             int64_t total, int32_t* flags, int32_t* minmax_ps, hipStream_t s);
+void launch_cover(const int32_t* dofs, int64_t total, int32_t* cnt, hipStream_t s);
+void launch_weights(const int32_t* cnt, int64_t n, double* W, int32_t* flags, hipStream_t s);
+void launch_tile_offsets(const int64_t* ptr, int64_t n_p, int64_t* toff, int64_t* scratch,
+                         hipStream_t s);
+void launch_extract(const int64_t* rowptr, const int32_t* col, const double* val,
+                    const int64_t* ptr, const int32_t* dofs, int64_t n_p, const int64_t* toff,
+                    int uniform_ps, double* tiles, uint32_t* keys, double* fnorm, double* l1norm,
+                    int32_t* flags, hipStream_t s);
+void launch_iota(int32_t* a, int64_t n, hipStream_t s);
+void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t s);
+// sort (key, value) pairs by key, ascending; keys/vals have length n (any n).
+// scratch must hold next_pow2(n) keys and values.
+void launch_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, uint64_t* kscr, int32_t* vscr,
+                       hipStream_t s);
+void launch_exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* scratch,
+                               hipStream_t s);
+int64_t scan_scratch_elems(int64_t n);
+
+// k_dense.hip
+// Inverse of matrices m = sel ? sel[i] : i, i < count.  Matrix m has size
+// pptr ? pptr[m+1]-pptr[m] : p (p is then the maximum size) and lives at
+// A + (aoff ? aoff[m] : m*p*p); its inverse goes to X + (xoff ? xoff[m] : m*p*p).
+void launch_batch_inverse(int p, int64_t count, const double* A, const int64_t* aoff,
+                          const int32_t* sel, const int64_t* pptr, double* X,
+                          const int64_t* xoff, int32_t* info, hipStream_t s);
+void launch_batch_criterion(int p, int64_t count, int crit, const double* A, const double* B,
+                            const double* X, double* d, hipStream_t s);
+
+struct Alg1Dev {
+    int32_t* status;               // int32[n_p]: 0 unresolved, 1 resolved
+    int32_t* ctrl;                 // int32[8], see k_dense.hip
+    unsigned long long* counters;  // uint64[8]: evals, exact, skipped; [4..5] window (double)
+    int32_t* cand;                 // int32[n_p] candidate list of a round
+};
+void launch_alg1_rounds(int rounds, const Alg1Dev& a, int crit, double eps, int64_t n_p,
+                        const int64_t* ptr, const double* tiles, const int64_t* toff,
+                        int uniform_ps, const double* keynorm, int32_t* phi, int32_t* reps,
+                        double* db, int64_t db_stride, hipStream_t s);
+
+// k_apply.hip
+void launch_apply_vec_f64(const int32_t* order, int64_t count, const int32_t* phi,
+                          const int64_t* ptr, const int32_t* dofs, const double* db_cm,
+                          const int64_t* dboff, int uniform_ps, const double* W, double omega,
+                          const double* r, double* z, int group, hipStream_t s);
+void launch_apply_vec_f32(const int32_t* order, int64_t count, const int32_t* phi,
+                          const int64_t* ptr, const int32_t* dofs, const float* db_f32,
+                          const int64_t* dboff, int uniform_ps, const double* W, double omega,
+                          const double* r, double* z, int group, hipStream_t s);
+void launch_apply_mfma(int prec, const int32_t* items, int64_t n_items, const int32_t* order,
+                       const int64_t* ptr, const int32_t* dofs, const uint16_t* db_lp,
+                       const int64_t* dblp_off, const int32_t* db_exp, const double* W,
+                       double omega, const double* r, double* z, hipStream_t s);
+void launch_convert_db(int prec, int64_t m_p, const double* db, const int64_t* dboff,
+                       const int32_t* dbps, int uniform_ps, uint16_t* db_lp,
+                       const int64_t* dblp_off, int32_t* db_exp, float* db_f32, double* db_cm,
+                       hipStream_t s);
+
+// k_krylov.hip
+void launch_spmv(const int64_t* rowptr, const int32_t* col, const double* val, int64_t n,
+                 const double* x, const double* b, double* y, int avg_nnz, hipStream_t s);
+int reduce_blocks(int64_t n);
+void launch_multidot(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
+                     double* partial, double* out, hipStream_t s);
+void launch_update(double* w, const double* V, int64_t ldv, int nv, const double* h,
+                   double sign, int64_t n, hipStream_t s);
+void launch_scale(const double* src, double* dst, const double* denom, int64_t n, hipStream_t s);
+void launch_axpy_dev(double* y, const double* x, double a, int64_t n, hipStream_t s);
+void launch_gemv_small(const double* V, int64_t ldv, int nv, const double* coef, int64_t n,
+                       double* out, hipStream_t s);
+void launch_zero(double* x, int64_t n, hipStream_t s);

@@ -1,0 +1,407 @@
+"""GPU parity: every step of the HIP path against the CPU oracle, through the
+C ABI, on seeded inputs.
+
+Bars: bit-exact for W, tiles, boundary keys, database choice and patch map;
+FP64 inverses within a condition-number bound; the FP64 apply within 1e-12
+(relative to the largest entry); reduced-precision applies within the FP32
+accumulation bound around the oracle's emulation of the same rounding; GMRES
+iteration counts within one of the oracle's.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2306_10025_amd as pr  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dt(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(DEV, dtype=dtype)
+
+
+SMALL = {
+    "q1_32": lambda: gen.q1_poisson_2d(32),
+    "stokes_8": lambda: gen.taylor_hood_stokes_2d(8),
+    "nedelec_6": lambda: gen.nedelec_hex(6),
+    "q2hex_4": lambda: gen.q2_hex_diffusion(4),
+    "batch_5": lambda: gen.uneven_stokes_batch(n_sys=5, nmin=2, nmax=6),
+}
+
+
+@pytest.fixture(scope="module", params=list(SMALL))
+def problem(request):
+    say("problem", request.param)
+    return request.param, SMALL[request.param]()
+
+
+# ---- Section 2 objects -----------------------------------------------------
+
+def test_weights_tiles_keys_bit_exact(problem):
+    name, P = problem
+    h = pr.PatchRelax(P.A, P.ptr, P.dofs)
+    cnt, W = O.cover_weights(P.n, P.ptr, P.dofs)
+    assert np.array_equal(h.weights(), W)
+    tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
+    keys = h.keys()
+    for k in range(P.n_p):
+        assert np.array_equal(h.tile(k), tiles[k]), (name, k)
+        assert keys[k] == O.boundary_mask(tiles[k]), (name, k)
+    st = h.stats()
+    assert st["n_groups"] == len(set(O.boundary_mask(t) for t in tiles))
+    h.close()
+
+
+# ---- batched inverse -------------------------------------------------------
+
+@pytest.mark.parametrize("p", [1, 3, 4, 12, 16, 22, 27, 32])
+def test_batch_inverse_matches_oracle(p):
+    rng = np.random.default_rng(p)
+    count = 37
+    A = rng.standard_normal((count, p, p)) + p * np.eye(p)
+    A[0] = np.eye(p)[::-1] * 2.0 + 0.1 * rng.standard_normal((p, p))     # needs pivoting
+    At = dt(A, torch.float64)
+    X = torch.empty_like(At)
+    info = torch.full((count,), -1, dtype=torch.int32, device=DEV)
+    pr.pr_batch_inverse(p, At, X, info)
+    torch.cuda.synchronize()
+    Xg = X.cpu().numpy()
+    assert np.all(info.cpu().numpy() == 0)
+    for i in range(count):
+        Xo = O.factor_inverse(A[i])
+        kappa = np.linalg.cond(A[i])
+        err = np.abs(Xg[i] - Xo).max() / np.abs(Xo).max()
+        assert err <= 8 * p * kappa * 2.2e-16, (p, i, err, kappa)
+
+
+def test_batch_inverse_reports_zero_pivot():
+    p = 5
+    A = np.stack([np.eye(p), np.eye(p)])
+    A[1, 2, :] = 0.0                        # row 2 zero: column 3 has no pivot left
+    A[1, :, 2] = 0.0
+    At = dt(A, torch.float64)
+    X = torch.empty_like(At)
+    info = torch.zeros(2, dtype=torch.int32, device=DEV)
+    pr.pr_batch_inverse(p, At, X, info)
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [0, 3]
+
+
+def test_stokes_tile_inverses():
+    P = gen.taylor_hood_stokes_2d(4)
+    tiles = np.stack(O.patch_tiles(P.A, P.ptr, P.dofs))
+    At = dt(tiles, torch.float64)
+    X = torch.empty_like(At)
+    info = torch.zeros(P.n_p, dtype=torch.int32, device=DEV)
+    pr.pr_batch_inverse(22, At, X, info)
+    torch.cuda.synchronize()
+    Xg = X.cpu().numpy()
+    assert np.all(info.cpu().numpy() == 0)
+    for k in range(P.n_p):
+        Xo = O.factor_inverse(tiles[k])
+        kappa = np.linalg.cond(tiles[k])
+        assert np.abs(Xg[k] - Xo).max() / np.abs(Xo).max() <= 8 * 22 * kappa * 2.2e-16
+
+
+# ---- criterion -------------------------------------------------------------
+
+@pytest.mark.parametrize("p", [2, 4, 12, 22, 27, 32])
+def test_batch_criterion_matches_oracle(p):
+    rng = np.random.default_rng(100 + p)
+    count = 24
+    B = rng.standard_normal((count, p, p)) + p * np.eye(p)
+    A = B * (1.0 + rng.uniform(-0.3, 0.3, size=(count, 1, 1))) + \
+        rng.standard_normal((count, p, p)) * rng.uniform(0, 0.5, size=(count, 1, 1))
+    A[0] = B[0]                                          # identical pair
+    A[1] = 2.5 * B[1]                                    # d = 1.5 exactly
+    X = np.stack([O.factor_inverse(b) for b in B])
+    d = torch.zeros(count, dtype=torch.float64, device=DEV)
+    pr.pr_batch_criterion(p, "spectral", dt(A, torch.float64), None, dt(X, torch.float64), d)
+    torch.cuda.synchronize()
+    dg = d.cpu().numpy()
+    for i in range(count):
+        do = O.crit_spectral_x(A[i], X[i])
+        assert abs(dg[i] - do) <= 1e-12 * max(do, 1.0) + 1e-14, (p, i, dg[i], do)
+    assert abs(dg[1] - 1.5) < 1e-12
+    for crit, fn in [("l1", O.crit_l1), ("fro", O.crit_fro)]:
+        pr.pr_batch_criterion(p, crit, dt(A, torch.float64), dt(B, torch.float64), None, d)
+        torch.cuda.synchronize()
+        dg = d.cpu().numpy()
+        for i in range(count):
+            do = fn(A[i], B[i])
+            assert abs(dg[i] - do) <= 1e-13 * max(do, 1e-300) + 1e-300
+
+
+# ---- Algorithm 1 -----------------------------------------------------------
+
+ALG1_CASES = {
+    "q1_32_spec": (lambda: gen.q1_poisson_2d(32), "spectral", 1e-8),
+    "stokes_8_spec": (lambda: gen.taylor_hood_stokes_2d(8), "spectral", 1e-8),
+    "nedelec_6_spec": (lambda: gen.nedelec_hex(6), "spectral", 1e-8),
+    "nedelec_6_l1": (lambda: gen.nedelec_hex(6), "l1", 1e-7),
+    "q2hex_const_4_fro": (lambda: gen.q2_hex_diffusion(4, sigma=0.0), "fro", 1e-7),
+    "q2hex_4_spec_loose": (lambda: gen.q2_hex_diffusion(4), "spectral", 0.5),
+    "batch_5_spec": (lambda: gen.uneven_stokes_batch(n_sys=5, nmin=2, nmax=6), "spectral", 1e-8),
+}
+
+
+@pytest.mark.parametrize("case", list(ALG1_CASES))
+def test_alg1_assignment_bit_exact(case):
+    make, crit, eps = ALG1_CASES[case]
+    say("alg1", case)
+    P = make()
+    tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
+    if len(set(t.shape[0] for t in tiles)) > 1:
+        # Algorithm 1 runs on each patch size on its own (Section 2 remark)
+        phi_o = np.zeros(P.n_p, dtype=np.int64)
+        reps_o = []
+        sizes = np.diff(P.ptr)
+        for s in sorted(set(sizes)):
+            ids = np.flatnonzero(sizes == s)
+            r = O.alg1_tolerance([tiles[i] for i in ids], eps, crit)
+            reps_o += [(ids[x], s) for x in r['reps']]
+            phi_o[ids] = -1 - ids[r['reps']][r['phi']]
+        reps_sorted = sorted(x[0] for x in reps_o)
+        pos = {r: j for j, r in enumerate(reps_sorted)}
+        phi_o = np.array([pos[-1 - v] for v in phi_o])
+        reps_o = np.array(reps_sorted)
+    else:
+        res = O.alg1_tolerance(tiles, eps, crit)
+        phi_o, reps_o = res['phi'], res['reps']
+        if crit == "spectral" and eps < 1e-3:
+            assert res['margin'] > 1e-6      # no decision within rounding of eps
+    h = pr.PatchRelax(P.A, P.ptr, P.dofs, algo="tolerance", criterion=crit, eps=eps)
+    phi, reps = h.assignment()
+    assert np.array_equal(reps, reps_o), (case, len(reps), len(reps_o))
+    assert np.array_equal(phi, phi_o), case
+    st = h.stats()
+    assert st["m_p"] == len(reps_o)
+    h.close()
+
+
+def test_alg1_pruning_is_certified_and_counts():
+    P = gen.nedelec_hex(6)
+    h = pr.PatchRelax(P.A, P.ptr, P.dofs, algo="tolerance", eps=1e-8)
+    st = h.stats()
+    phi, reps = h.assignment()
+    # pairs the sequential algorithm compares: patch i against entries 0..phi(i)
+    # (0..phi(i)-1 for an entry's own patch)
+    is_rep = np.zeros(P.n_p, bool)
+    is_rep[reps] = True
+    naive = int(np.sum(np.where(is_rep, phi, phi + 1)))
+    assert st["crit_evals"] + st["crit_pruned"] == naive
+    assert st["crit_evals"] < naive
+    h.close()
+
+
+# ---- apply ------------------------------------------------------------------
+
+def _rhs(n, seed=0):
+    return gen.rhs(n, seed)
+
+
+def test_apply_fp64_full_matches_oracle(problem):
+    name, P = problem
+    omega = 0.7
+    h = pr.PatchRelax(P.A, P.ptr, P.dofs, omega=omega)
+    cnt, W = O.cover_weights(P.n, P.ptr, P.dofs)
+    tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
+    X = [O.factor_inverse(t) for t in tiles]
+    kappa = max(np.linalg.cond(t) for t in tiles)
+    for seed in (0, 1):
+        r = _rhs(P.n, seed)
+        z_o = O.apply_patch(P.ptr, P.dofs, W, X, np.arange(P.n_p), r, omega)
+        rt = dt(r, torch.float64)
+        z = torch.full_like(rt, np.nan)
+        h.apply(rt, z)
+        torch.cuda.synchronize()
+        zg = z.cpu().numpy()
+        ps = int(np.diff(P.ptr).max())
+        tol = max(1e-12, 8 * ps * kappa * 2.2e-16)
+        err = np.abs(zg - z_o).max() / np.abs(z_o).max()
+        say(name, "fp64 apply err", err, "kappa", kappa)
+        assert err <= tol, (name, err, tol)
+    h.close()
+
+
+def test_apply_compressed_fp64_matches_oracle(problem):
+    name, P = problem
+    h = pr.PatchRelax(P.A, P.ptr, P.dofs, algo="tolerance", eps=1e-8)
+    phi, reps = h.assignment()
+    cnt, W = O.cover_weights(P.n, P.ptr, P.dofs)
+    tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
+    # oracle database: its own inverses of the entries' patches
+    Xdb = [O.factor_inverse(tiles[r]) for r in reps]
+    r = _rhs(P.n, 3)
+    z_o = O.apply_patch(P.ptr, P.dofs, W, Xdb, phi, r)
+    rt = dt(r, torch.float64)
+    z = torch.zeros_like(rt)
+    h.apply(rt, z)
+    torch.cuda.synchronize()
+    kappa = max(np.linalg.cond(tiles[r]) for r in reps)
+    err = np.abs(z.cpu().numpy() - z_o).max() / np.abs(z_o).max()
+    assert err <= max(1e-12, 8 * 32 * kappa * 2.2e-16), (name, err)
+    h.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16", "bf16x3"])
+def test_apply_lowprec_matches_emulation(problem, precision):
+    name, P = problem
+    omega = 0.9
+    h = pr.PatchRelax(P.A, P.ptr, P.dofs, algo="tolerance", eps=1e-8, precision=precision,
+                      omega=omega)
+    phi, reps = h.assignment()
+    cnt, W = O.cover_weights(P.n, P.ptr, P.dofs)
+    tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
+    Xdb = [O.factor_inverse(tiles[r]) for r in reps]
+    r = _rhs(P.n, 5) * np.exp(np.random.default_rng(9).uniform(-3, 3, P.n))  # mixed magnitudes
+    z_e, bound = O.apply_lowprec(P.ptr, P.dofs, W, Xdb, phi, r, omega, precision, return_bound=True)
+    rt = dt(r, torch.float64)
+    z = torch.zeros_like(rt)
+    h.apply(rt, z)
+    torch.cuda.synchronize()
+    zg = z.cpu().numpy()
+    ps = int(np.diff(P.ptr).max())
+    tol = (ps + 4) * 2.0 ** -24 * bound + 1e-300
+    bad = np.abs(zg - z_e) > tol
+    say(name, precision, "max |dz|/bound", np.max(np.abs(zg - z_e) / np.maximum(bound, 1e-300)))
+    assert not bad.any(), (name, precision, int(bad.sum()))
+    # and the reduced-precision operator is close to the FP64 one
+    z64 = O.apply_patch(P.ptr, P.dofs, W, Xdb, phi, r, omega)
+    rel = np.linalg.norm(zg - z64) / np.linalg.norm(z64)
+    assert rel < {"fp32": 1e-5, "bf16": 3e-2, "fp16": 3e-3, "bf16x3": 2e-4}[precision]
+    h.close()
+
+
+# ---- GMRES -------------------------------------------------------------------
+
+SOLVE_CASES = {
+    "q1_32_full": (lambda: gen.q1_poisson_2d(32), dict(algo="full", omega=0.7)),
+    "q1_32_alg1": (lambda: gen.q1_poisson_2d(32), dict(algo="tolerance")),
+    "q2hex_4_full": (lambda: gen.q2_hex_diffusion(4), dict(algo="full")),
+    "q2hex_6_sweeps2": (lambda: gen.q2_hex_diffusion(6), dict(algo="full", sweeps=2, omega=0.8)),
+}
+
+
+@pytest.mark.parametrize("case", list(SOLVE_CASES))
+def test_gmres_matches_oracle(case):
+    make, kw = SOLVE_CASES[case]
+    say("solve", case)
+    P = make()
+    h = pr.PatchRelax(P.A, P.ptr, P.dofs, **kw)
+    phi, reps = h.assignment()
+    cnt, W = O.cover_weights(P.n, P.ptr, P.dofs)
+    tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
+    Xdb = [O.factor_inverse(tiles[r]) for r in reps]
+    b = _rhs(P.n)
+    prec = O.make_preconditioner(P.A, P.ptr, P.dofs, W, Xdb, phi, omega=kw.get("omega", 1.0),
+                                 sweeps=kw.get("sweeps", 1))
+    x_o, info_o = O.gmres(lambda v: P.A @ v, prec, b, tol=1e-8, restart=30)
+    bt = dt(b, torch.float64)
+    x = torch.zeros_like(bt)
+    rc = h.solve(bt, x, 1e-8)
+    info = h.solve_info()
+    xg = x.cpu().numpy()
+    relres = np.linalg.norm(b - P.A @ xg) / np.linalg.norm(b)
+    say(case, "iters gpu", info["iters"], "oracle", info_o["iters"], "relres", relres)
+    assert rc == pr.PR_OK
+    assert relres <= 1e-8
+    assert abs(info["iters"] - info_o["iters"]) <= 1
+    assert abs(info["relres"] - relres) <= 1e-10
+    assert np.linalg.norm(xg - x_o) / np.linalg.norm(x_o) < 1e-5
+    h.close()
+
+
+def test_gmres_bf16_compressed_within_iteration_bound():
+    P = gen.q1_poisson_2d(32)
+    b = _rhs(P.n)
+    bt = dt(b, torch.float64)
+    its = {}
+    for prec in ("fp64", "bf16", "fp16", "bf16x3"):
+        h = pr.PatchRelax(P.A, P.ptr, P.dofs, algo="tolerance", precision=prec)
+        x = torch.zeros_like(bt)
+        rc = h.solve(bt, x, 1e-8)
+        assert rc == pr.PR_OK
+        xg = x.cpu().numpy()
+        assert np.linalg.norm(b - P.A @ xg) / np.linalg.norm(b) <= 1e-8
+        its[prec] = h.solve_info()["iters"]
+        h.close()
+    say("iterations", its)
+    # scaled FP16 and split BF16 meet the +10% bar; plain BF16 (8-bit
+    # significand) is slower to converge and is only held to +30%
+    assert its["fp16"] <= 1.10 * its["fp64"]
+    assert its["bf16x3"] <= 1.10 * its["fp64"]
+    assert its["bf16"] <= 1.30 * its["fp64"]
+
+
+def test_omega_invariance_on_gpu():
+    P = gen.q1_poisson_2d(16)
+    b = _rhs(P.n)
+    bt = dt(b, torch.float64)
+    res = []
+    for om in (1.0, 0.7):
+        h = pr.PatchRelax(P.A, P.ptr, P.dofs, omega=om)
+        x = torch.zeros_like(bt)
+        h.solve(bt, x, 1e-8)
+        res.append((h.solve_info()["iters"], x.cpu().numpy()))
+        h.close()
+    assert res[0][0] == res[1][0]
+    assert np.allclose(res[0][1], res[1][1], rtol=1e-6, atol=1e-9)
+
+
+# ---- failure handling (conditions forced from the host) ----------------------
+
+def _setup_rc(A, ptr, dofs, **kw):
+    try:
+        h = pr.PatchRelax(A, ptr, dofs, **kw)
+    except pr.PatchRelaxError as e:
+        return e.code
+    h.close()
+    return pr.PR_OK
+
+
+def test_error_codes_on_device():
+    P = gen.q1_poisson_2d(6)
+    d = P.dofs.copy()
+    d[5] = P.n + 3
+    assert _setup_rc(P.A, P.ptr, d) == pr.PR_ERR_DOF_OUT_OF_RANGE
+    d = P.dofs.copy()
+    d[1] = d[0]
+    assert _setup_rc(P.A, P.ptr, d) == pr.PR_ERR_DUP_DOF_IN_PATCH
+    assert _setup_rc(P.A, P.ptr[:-1], P.dofs[:P.ptr[-2]]) == pr.PR_ERR_UNCOVERED_DOF
+    A = P.A.copy()
+    A.data = A.data.copy()
+    A.data[10] = np.inf
+    assert _setup_rc(A, P.ptr, P.dofs) == pr.PR_ERR_NONFINITE
+    A = P.A.copy().tolil()
+    A[8, :] = 0.0                              # a zero row inside a patch
+    A = A.tocsr()
+    A.indices = A.indices.astype(np.int32)
+    A.indptr = A.indptr.astype(np.int64)
+    assert _setup_rc(A, P.ptr, P.dofs) == pr.PR_ERR_SINGULAR_PATCH
+    assert _setup_rc(A, P.ptr, P.dofs, algo="tolerance") == pr.PR_ERR_SINGULAR_PATCH
+
+
+def test_apply_rejects_host_pointer():
+    P = gen.q1_poisson_2d(4)
+    h = pr.PatchRelax(P.A, P.ptr, P.dofs)
+    r = torch.zeros(P.n, dtype=torch.float64)                # host tensor
+    z = torch.zeros(P.n, dtype=torch.float64, device=DEV)
+    with pytest.raises(pr.PatchRelaxError) as e:
+        h.apply(r, z)
+    assert e.value.code == pr.PR_ERR_HOST_POINTER
+    h.close()

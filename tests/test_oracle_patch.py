@@ -321,6 +321,15 @@ def test_lowprec_apply_close_to_fp64():
     phi = np.arange(P.n_p)
     r = np.random.default_rng(0).standard_normal(P.n)
     z = O.apply_patch(P.ptr, P.dofs, W, X, phi, r)
-    for prec, tol in [("fp32", 1e-6), ("bf16", 2e-2), ("fp16", 2e-3)]:
+    for prec, tol in [("fp32", 1e-6), ("bf16", 2e-2), ("fp16", 2e-3), ("bf16x3", 1e-4)]:
         zl = O.apply_lowprec(P.ptr, P.dofs, W, X, phi, r, precision=prec)
         assert np.linalg.norm(zl - z) / np.linalg.norm(z) < tol
+
+
+def test_bf16_split_pins():
+    from oracle.lowprec import split_bf16
+    hi, lo = split_bf16(np.array([1.0 + 2.0 ** -10, 3.0, 1.0 / 3.0]))
+    assert hi[0] == 1.0 and lo[0] == 2.0 ** -10
+    assert hi[1] == 3.0 and lo[1] == 0.0
+    # the split keeps about 16 significant bits
+    assert abs(hi[2] + lo[2] - 1.0 / 3.0) <= 2.0 ** -17 / 3.0
