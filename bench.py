@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--eps", type=float, default=1e-8, help="Algorithm 1 tolerance")
     ap.add_argument("--precision", default="bf16x3")
+    ap.add_argument("--scatter", default="atomic", choices=["atomic", "two-stage"],
+                    help="FP64 atomics or the deterministic two-stage slot sum")
     ap.add_argument("--no-full", action="store_true", help="skip the full FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-size", type=int, default=12, help="cells per direction of the CPU sample")
@@ -116,12 +118,12 @@ def run_gpu(args, P, b_np):
 
     comp = pr.make_params(algo="tolerance", criterion="spectral", eps=args.eps,
                           precision=args.precision, restart=30, max_iters=args.iters,
-                          timing=True, stream=stream)
+                          deterministic=args.scatter == "two-stage", timing=True, stream=stream)
     sec_c, rec_c = timed(comp, "compressed " + args.precision, args.steps, args.warmup)
     out = dict(sec=sec_c, rec=rec_c)
     if not args.no_full:
         full = pr.make_params(algo="full", precision="fp64", restart=30, max_iters=args.iters,
-                              timing=True, stream=stream)
+                              deterministic=args.scatter == "two-stage", timing=True, stream=stream)
         sec_f, rec_f = timed(full, "full fp64", max(1, min(args.steps, 2)), 1)
         out.update(sec_full=sec_f, rec_full=rec_f)
     return out
@@ -233,6 +235,7 @@ def main():
             "n": P.n, "nnz": int(P.A.nnz), "n_p": P.n_p, "p_s": 12, "m_p": m_p,
             "database": f"algorithm 1, spectral criterion, eps={args.eps}",
             "apply_precision": args.precision, "setup_precision": "f64", "krylov": "f64 GMRES(30)",
+            "scatter": args.scatter,
             "tol": args.tol, "max_iters": args.iters, "parallelism": "single GPU",
         },
         "setup_s": round(float(np.mean([s["t_total"] for _, s in g["rec"]])), 4),

@@ -1,0 +1,163 @@
+// Dense per-patch device routines shared by the batched kernels and
+// Algorithm 1: Gauss-Jordan inversion with partial pivoting and the
+// criterion building blocks (E = I - A X, its Frobenius norm, a column-norm
+// lower bound, and the exact largest singular value).
+#pragma once
+
+#include "pr_internal.h"
+
+namespace pr_dev {
+
+constexpr int kMaxPs = 32;
+
+// ---------------------------------------------------------------------------
+// Gauss-Jordan inverse of one p x p matrix per group of G lanes; lane r of the
+// group holds row r of [A | I] in registers.  Pivot: largest |a_ik| over rows
+// not yet used, ties to the lowest row.  Row piv_k ends as row k of A^{-1}.
+// ---------------------------------------------------------------------------
+template <int MAXP, int G>
+__device__ __forceinline__ int gj_invert(const double* __restrict__ A, double* __restrict__ X,
+                                         int p, int r) {
+    double a[MAXP], x[MAXP];
+    const bool act = r < p;
+#pragma unroll
+    for (int c = 0; c < MAXP; ++c) {
+        a[c] = (act && c < p) ? A[(int64_t)r * p + c] : 0.0;
+        x[c] = (act && c == r) ? 1.0 : 0.0;
+    }
+    bool used = !act;
+    int mycol = -1;
+    int info = 0;
+#pragma unroll
+    for (int k = 0; k < MAXP; ++k) {
+        if (k < p) {
+            double cv = used ? -1.0 : fabs(a[k]);
+            int ci = r;
+#pragma unroll
+            for (int o = G / 2; o > 0; o >>= 1) {
+                const double ov = __shfl_xor(cv, o, G);
+                const int oi = __shfl_xor(ci, o, G);
+                if (ov > cv || (ov == cv && oi < ci)) {
+                    cv = ov;
+                    ci = oi;
+                }
+            }
+            const int piv = ci;
+            if (!(cv > 0.0) && info == 0) info = k + 1;
+            const double pk = __shfl(a[k], piv, G);
+            const double inv = 1.0 / pk;
+            const double f = (r == piv) ? 0.0 : a[k] * inv;
+#pragma unroll
+            for (int c = 0; c < MAXP; ++c) {
+                if (c < p) {
+                    const double pa = __shfl(a[c], piv, G);
+                    const double px = __shfl(x[c], piv, G);
+                    if (r == piv) {
+                        a[c] = pa * inv;
+                        x[c] = px * inv;
+                    } else {
+                        a[c] = fma(-f, pa, a[c]);
+                        x[c] = fma(-f, px, x[c]);
+                    }
+                }
+            }
+            if (r == piv) {
+                used = true;
+                mycol = k;
+            }
+        }
+    }
+    if (act && mycol >= 0) {
+#pragma unroll
+        for (int c = 0; c < MAXP; ++c)
+            if (c < p) X[(int64_t)mycol * p + c] = x[c];
+    }
+    return info;
+}
+
+// ---------------------------------------------------------------------------
+// criterion helpers (one wavefront; LDS buffers of kMaxPs^2 doubles)
+// ---------------------------------------------------------------------------
+
+// E = I - A X into sE; returns ||E||_F^2 (wave-reduced).
+__device__ __forceinline__ double form_E(const double* sA, const double* sX, double* sE, int p,
+                                         int lane) {
+    double fro2 = 0.0;
+    for (int e = lane; e < p * p; e += PR_WAVE) {
+        const int a = e / p, b = e % p;
+        double acc = 0.0;
+        for (int c = 0; c < p; ++c) acc = fma(sA[a * p + c], sX[c * p + b], acc);
+        const double v = (a == b ? 1.0 : 0.0) - acc;
+        sE[e] = v;
+        fro2 += v * v;
+    }
+    return wave_sum(fro2);
+}
+
+// Largest column 2-norm of E squared (a lower bound on sigma_max^2).
+__device__ __forceinline__ double max_col2(const double* sE, int p, int lane) {
+    double m = 0.0;
+    if (lane < p) {
+        double s = 0.0;
+        for (int a = 0; a < p; ++a) s += sE[a * p + lane] * sE[a * p + lane];
+        m = s;
+    }
+    return wave_max(m);
+}
+
+// sigma_max(E)^2 as the largest eigenvalue of G = E^T E by cyclic Jacobi
+// rotations; sG is overwritten.  Requires a one-wave block (uses barriers).
+__device__ inline double sigma_max2_jacobi(const double* sE, double* sG, int p, int lane) {
+    for (int e = lane; e < p * p; e += PR_WAVE) {
+        const int a = e / p, b = e % p;
+        double acc = 0.0;
+        for (int c = 0; c < p; ++c) acc = fma(sE[c * p + a], sE[c * p + b], acc);
+        sG[e] = acc;
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        double off = 0.0, dia = 0.0;
+        for (int e = lane; e < p * p; e += PR_WAVE) {
+            const int a = e / p, b = e % p;
+            const double v = sG[e];
+            if (a == b) dia += v * v; else off += v * v;
+        }
+        off = wave_sum(off);
+        dia = wave_sum(dia);
+        if (off <= 1e-32 * dia || off == 0.0) break;
+        for (int i = 0; i < p - 1; ++i) {
+            for (int j = i + 1; j < p; ++j) {
+                const double gij = sG[i * p + j];
+                if (fabs(gij) <= 1e-300) continue;      // uniform: every lane reads the same value
+                const double gii = sG[i * p + i], gjj = sG[j * p + j];
+                const double theta = (gjj - gii) / (2.0 * gij);
+                double t;
+                if (fabs(theta) > 1e150) {
+                    t = 0.5 / theta;
+                } else {
+                    t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
+                }
+                const double c = 1.0 / sqrt(1.0 + t * t);
+                const double s = t * c;
+                __syncthreads();
+                if (lane < p) {
+                    const double gki = sG[lane * p + i], gkj = sG[lane * p + j];
+                    sG[lane * p + i] = c * gki - s * gkj;
+                    sG[lane * p + j] = s * gki + c * gkj;
+                }
+                __syncthreads();
+                if (lane < p) {
+                    const double gik = sG[i * p + lane], gjk = sG[j * p + lane];
+                    sG[i * p + lane] = c * gik - s * gjk;
+                    sG[j * p + lane] = s * gik + c * gjk;
+                }
+                __syncthreads();
+            }
+        }
+    }
+    double m = lane < p ? sG[lane * p + lane] : 0.0;
+    m = wave_max(m);
+    return m > 0.0 ? m : 0.0;
+}
+
+}  // namespace pr_dev

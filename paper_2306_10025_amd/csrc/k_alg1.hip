@@ -1,0 +1,347 @@
+// Algorithm 1 (patch tolerance construction, Section 3.1) on the device.
+//
+// The sequential algorithm visits patches in order, compares each with the
+// database entries in append order and keeps the first entry within eps, or
+// appends the patch.  Pairs that cannot match are known in advance from a
+// certified bound on a cheap per-patch key (the subset search suggested
+// after Algorithm 1):
+//   spectral: d(A,B) = ||(B-A)B^{-1}||_2 >= ||B-A||_2/||B||_2
+//             >= | ||A||_F - ||B||_F | / (sqrt(p) ||B||_F),
+//   l1 / Frobenius: d(A,B) >= | key(A) - key(B) | with key the same norm.
+// Sorting patches by (size, key) and cutting wherever two neighbours are
+// further apart than any match allows splits the patches into components
+// that never match across.  Algorithm 1 restricted to one component gives
+// exactly the sequential result for its patches (entries of other components
+// never match them), so all components run their rounds at once:
+//   round: the lowest unresolved member of each component becomes an entry;
+//          it is inverted; every unresolved member is tested against it and
+//          resolved on a match.
+// A member is thus compared with its component's entries in append order
+// until the first match, as in the sequential algorithm.  Entries are
+// finally numbered in ascending patch id (the append order).
+#include "dense_dev.h"
+
+#include <climits>
+
+namespace {
+
+using namespace pr_dev;
+
+// ctl (int32[8]): [0] entries so far  [1] active components this round
+//                 [2] done            [3] candidates this round
+//                 [4] rounds started  [5] first singular entry patch + 1
+
+__global__ void k_a1_keys(int64_t n_p, const int64_t* __restrict__ ptr,
+                          const double* __restrict__ keynorm, uint64_t* __restrict__ keys,
+                          int32_t* __restrict__ vals) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_p) return;
+    const uint64_t p = (uint64_t)(ptr[s + 1] - ptr[s]);
+    const uint64_t bits = (uint64_t)__double_as_longlong(keynorm[s]);  // key >= 0: monotone
+    keys[s] = (p << 58) | (bits >> 5);
+    vals[s] = (int32_t)s;
+}
+
+__global__ void k_a1_comp_flags(int64_t n_p, const int32_t* __restrict__ sidx,
+                                const int64_t* __restrict__ ptr, const double* __restrict__ keynorm,
+                                int crit, double eps, int64_t* __restrict__ flag) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s > n_p) return;
+    if (s == n_p) {
+        flag[s] = 0;
+        return;
+    }
+    if (s == 0) {
+        flag[s] = 1;
+        return;
+    }
+    const int32_t i = sidx[s], j = sidx[s - 1];
+    const int pi = (int)(ptr[i + 1] - ptr[i]), pj = (int)(ptr[j + 1] - ptr[j]);
+    const double ks = keynorm[i], kp = keynorm[j];
+    const double c = (pi * pi + 64) * 2.3e-16;
+    const double half = (crit == PR_CRIT_SPECTRAL) ? (eps * sqrt((double)pi) * (1.0 + 1e-10) + c) * ks
+                                                   : eps * (1.0 + 1e-10) + c * ks;
+    flag[s] = (pi != pj || ks - kp > half) ? 1 : 0;
+}
+
+__global__ void k_a1_key2(int64_t n_p, const int64_t* __restrict__ flag,
+                          const int64_t* __restrict__ excl, const int32_t* __restrict__ sidx,
+                          uint64_t* __restrict__ key2, int32_t* __restrict__ val2) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_p) return;
+    const uint64_t comp = (uint64_t)(excl[s] + flag[s] - 1);
+    key2[s] = (comp << 32) | (uint32_t)sidx[s];
+    val2[s] = sidx[s];
+}
+
+__global__ void k_a1_cstart(int64_t n_p, int64_t n_comp, const uint64_t* __restrict__ key2,
+                            int32_t* __restrict__ pos_comp, int32_t* __restrict__ cstart,
+                            int32_t* __restrict__ next) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_p) return;
+    const int32_t c = (int32_t)(key2[s] >> 32);
+    pos_comp[s] = c;
+    if (s == 0 || (int32_t)(key2[s - 1] >> 32) != c) {
+        cstart[c] = (int32_t)s;
+        next[c] = (int32_t)s;
+    }
+    if (s == 0) cstart[n_comp] = (int32_t)n_p;
+}
+
+__global__ void k_a1_begin(int32_t* ctl) {
+    if (ctl[2]) return;
+    if (ctl[4] > 0 && ctl[1] == 0) {
+        ctl[2] = 1;
+        return;
+    }
+    ctl[1] = 0;
+    ctl[3] = 0;
+    ctl[4] += 1;
+}
+
+// lowest unresolved member of each component becomes its next entry
+__global__ void k_a1_pick(int64_t n_comp, int32_t* ctl, const int32_t* __restrict__ cstart,
+                          int32_t* __restrict__ next, const int32_t* __restrict__ mem,
+                          int32_t* __restrict__ status, int32_t* __restrict__ rep_slot,
+                          int32_t* __restrict__ rep_patch, int32_t* __restrict__ slot_of_patch,
+                          int32_t* __restrict__ repof, int32_t* __restrict__ active) {
+    if (ctl[2]) return;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_comp) return;
+    const int32_t s = next[c];
+    if (s < cstart[c + 1]) {
+        status[s] = 1;
+        const int32_t pid = mem[s];
+        const int32_t slot = atomicAdd(&ctl[0], 1);
+        rep_slot[c] = slot;
+        rep_patch[slot] = pid;
+        slot_of_patch[pid] = slot;
+        repof[pid] = pid;
+        active[atomicAdd(&ctl[1], 1)] = (int32_t)c;
+        next[c] = cstart[c + 1];      // lowered by the evaluation to the next unresolved member
+    } else {
+        rep_slot[c] = -1;
+    }
+}
+
+template <int MAXP, int G>
+__global__ __launch_bounds__(256) void k_a1_invert(const int32_t* ctl, const int32_t* __restrict__ active,
+                                                   const int32_t* __restrict__ rep_slot,
+                                                   const int32_t* __restrict__ rep_patch,
+                                                   const int64_t* __restrict__ ptr,
+                                                   const double* __restrict__ tiles,
+                                                   const int64_t* __restrict__ toff, int uniform_ps,
+                                                   double* __restrict__ dbt, int64_t stride,
+                                                   int32_t* sing) {
+    if (ctl[2]) return;
+    const int na = ctl[1];
+    const int64_t gsz = 256 / G;
+    const int r = threadIdx.x % G;
+    for (int64_t g = (int64_t)blockIdx.x * gsz + threadIdx.x / G; g < na; g += (int64_t)gridDim.x * gsz) {
+        const int32_t c = active[g];
+        const int32_t slot = rep_slot[c];
+        const int32_t pid = rep_patch[slot];
+        const int p = (int)(ptr[pid + 1] - ptr[pid]);
+        const double* A = tiles + (uniform_ps ? (int64_t)pid * uniform_ps * uniform_ps : toff[pid]);
+        const int inf = gj_invert<MAXP, G>(A, dbt + (int64_t)slot * stride, p, r);
+        if (r == 0 && inf != 0) atomicCAS(sing, 0, pid + 1);
+    }
+}
+
+// unresolved members of the components that opened an entry this round
+__global__ void k_a1_filter(int64_t n_p, int32_t* ctl, const int32_t* __restrict__ status,
+                            const int32_t* __restrict__ pos_comp, const int32_t* __restrict__ rep_slot,
+                            int32_t* __restrict__ cand) {
+    if (ctl[2]) return;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool want = s < n_p && status[s] == 0 && rep_slot[pos_comp[s]] >= 0;
+    const unsigned long long m = __ballot(want);
+    if (m == 0) return;
+    const int lane = threadIdx.x & (PR_WAVE - 1);
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&ctl[3], (int)__popcll(m));
+    base = __shfl(base, leader);
+    if (want) cand[base + (int)__popcll(m & ((1ull << lane) - 1ull))] = (int32_t)s;
+}
+
+// one wavefront per candidate: test against its component's current entry
+__global__ __launch_bounds__(64) void k_a1_eval(const int32_t* ctl, int crit, double eps,
+                                                const int32_t* __restrict__ cand,
+                                                const int32_t* __restrict__ mem,
+                                                const int32_t* __restrict__ pos_comp,
+                                                const int32_t* __restrict__ rep_slot,
+                                                const int32_t* __restrict__ rep_patch,
+                                                const int64_t* __restrict__ ptr,
+                                                const double* __restrict__ tiles,
+                                                const int64_t* __restrict__ toff, int uniform_ps,
+                                                const double* __restrict__ dbt, int64_t stride,
+                                                int32_t* __restrict__ status, int32_t* __restrict__ repof,
+                                                int32_t* __restrict__ next,
+                                                unsigned long long* __restrict__ counters) {
+    if (ctl[2]) return;
+    const int nc = ctl[3];
+    if ((int)blockIdx.x >= nc) return;
+    __shared__ double sA[kMaxPs * kMaxPs];
+    __shared__ double sX[kMaxPs * kMaxPs];
+    __shared__ double sE[kMaxPs * kMaxPs];
+    const int lane = threadIdx.x;
+    unsigned long long nev = 0, nex = 0;
+    for (int q = blockIdx.x; q < nc; q += gridDim.x) {
+        const int32_t s = cand[q];
+        const int32_t i = mem[s];
+        const int32_t comp = pos_comp[s];
+        const int32_t slot = rep_slot[comp];
+        const int32_t r = rep_patch[slot];
+        const int p = (int)(ptr[i + 1] - ptr[i]);
+        const int pp = p * p;
+        const double* Ai = tiles + (uniform_ps ? (int64_t)i * uniform_ps * uniform_ps : toff[i]);
+        const double* Br = (crit == PR_CRIT_SPECTRAL)
+                               ? dbt + (int64_t)slot * stride
+                               : tiles + (uniform_ps ? (int64_t)r * uniform_ps * uniform_ps : toff[r]);
+        for (int e = lane; e < pp; e += PR_WAVE) {
+            sA[e] = Ai[e];
+            sX[e] = Br[e];
+        }
+        __syncthreads();
+        bool match;
+        ++nev;
+        if (crit == PR_CRIT_SPECTRAL) {
+            const double fro2 = form_E(sA, sX, sE, p, lane);
+            __syncthreads();
+            const double lb2 = max_col2(sE, p, lane);
+            const double e2 = eps * eps;
+            if (fro2 * (1.0 + 1e-12) < e2) {
+                match = true;                       // sigma_max <= ||E||_F < eps
+            } else if (lb2 * (1.0 - 1e-12) >= e2) {
+                match = false;                      // sigma_max >= largest column norm >= eps
+            } else {
+                match = sqrt(sigma_max2_jacobi(sE, sA, p, lane)) < eps;
+                ++nex;
+            }
+        } else {
+            double acc = 0.0;
+            for (int e = lane; e < pp; e += PR_WAVE) {
+                const double v = sA[e] - sX[e];
+                acc += (crit == PR_CRIT_L1) ? fabs(v) : v * v;
+            }
+            acc = wave_sum(acc);
+            match = ((crit == PR_CRIT_L1) ? acc : sqrt(acc)) < eps;
+        }
+        if (lane == 0) {
+            if (match) {
+                status[s] = 1;
+                repof[i] = r;
+            } else {
+                atomicMin(&next[comp], s);
+            }
+        }
+        __syncthreads();
+    }
+    if (lane == 0) {
+        atomicAdd(&counters[0], nev);
+        if (nex) atomicAdd(&counters[1], nex);
+    }
+}
+
+__global__ void k_a1_repflags(int64_t n_p, const int32_t* __restrict__ repof, int64_t* __restrict__ f) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_p) f[i] = (repof[i] == (int32_t)i) ? 1 : 0;
+    else if (i == n_p) f[i] = 0;
+}
+
+__global__ void k_a1_finish(int64_t n_p, const int32_t* __restrict__ repof,
+                            const int64_t* __restrict__ rank, int32_t* __restrict__ phi,
+                            int32_t* __restrict__ reps) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_p) return;
+    const int32_t r = repof[i];
+    phi[i] = (int32_t)rank[r];
+    if (r == (int32_t)i) reps[rank[i]] = (int32_t)i;
+}
+
+// entry j (ascending patch id) <- its temporary slot
+__global__ void k_a1_copy_db(int64_t m_p, const int32_t* __restrict__ reps,
+                             const int32_t* __restrict__ slot_of_patch, const int64_t* __restrict__ ptr,
+                             const double* __restrict__ dbt, double* __restrict__ db, int64_t stride) {
+    for (int64_t j = blockIdx.x; j < m_p; j += gridDim.x) {
+        const int32_t pid = reps[j];
+        const int p = (int)(ptr[pid + 1] - ptr[pid]);
+        const double* src = dbt + (int64_t)slot_of_patch[pid] * stride;
+        for (int e = threadIdx.x; e < p * p; e += blockDim.x) db[j * stride + e] = src[e];
+    }
+}
+
+inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <int MAXP, int G>
+void run_a1_invert(int64_t n_comp, const int32_t* ctl, const int32_t* active, const int32_t* rep_slot,
+                   const int32_t* rep_patch, const int64_t* ptr, const double* tiles, const int64_t* toff,
+                   int uniform_ps, double* dbt, int64_t stride, int32_t* sing, hipStream_t s) {
+    const int per = 256 / G;
+    int64_t blocks = (n_comp + per - 1) / per;
+    if (blocks > 4096) blocks = 4096;
+    k_a1_invert<MAXP, G><<<(unsigned)blocks, 256, 0, s>>>(ctl, active, rep_slot, rep_patch, ptr, tiles,
+                                                         toff, uniform_ps, dbt, stride, sing);
+}
+
+}  // namespace
+
+void launch_a1_keys(int64_t n_p, const int64_t* ptr, const double* keynorm, uint64_t* keys,
+                    int32_t* vals, hipStream_t s) {
+    k_a1_keys<<<nb(n_p, 256), 256, 0, s>>>(n_p, ptr, keynorm, keys, vals);
+}
+
+void launch_a1_comp_flags(int64_t n_p, const int32_t* sidx, const int64_t* ptr, const double* keynorm,
+                          int crit, double eps, int64_t* flag, hipStream_t s) {
+    k_a1_comp_flags<<<nb(n_p + 1, 256), 256, 0, s>>>(n_p, sidx, ptr, keynorm, crit, eps, flag);
+}
+
+void launch_a1_key2(int64_t n_p, const int64_t* flag, const int64_t* excl, const int32_t* sidx,
+                    uint64_t* key2, int32_t* val2, hipStream_t s) {
+    k_a1_key2<<<nb(n_p, 256), 256, 0, s>>>(n_p, flag, excl, sidx, key2, val2);
+}
+
+void launch_a1_cstart(int64_t n_p, int64_t n_comp, const uint64_t* key2, int32_t* pos_comp,
+                      int32_t* cstart, int32_t* next, hipStream_t s) {
+    k_a1_cstart<<<nb(n_p, 256), 256, 0, s>>>(n_p, n_comp, key2, pos_comp, cstart, next);
+}
+
+void launch_a1_rounds(int rounds, const A1Dev& d, int crit, double eps, int max_ps, hipStream_t s) {
+    const unsigned cb = nb(d.n_comp, 256);
+    const unsigned fb = nb(d.n_p, 256);
+    const unsigned eb = (unsigned)(d.n_p < 8192 ? d.n_p : 8192);
+    for (int t = 0; t < rounds; ++t) {
+        k_a1_begin<<<1, 1, 0, s>>>(d.ctl);
+        k_a1_pick<<<cb, 256, 0, s>>>(d.n_comp, d.ctl, d.cstart, d.next, d.mem, d.status, d.rep_slot,
+                                     d.rep_patch, d.slot_of_patch, d.repof, d.active);
+        if (max_ps <= 4)
+            run_a1_invert<4, 4>(d.n_comp, d.ctl, d.active, d.rep_slot, d.rep_patch, d.ptr, d.tiles, d.toff, d.uniform_ps, d.dbt, d.stride, d.ctl + 5, s);
+        else if (max_ps <= 12)
+            run_a1_invert<12, 16>(d.n_comp, d.ctl, d.active, d.rep_slot, d.rep_patch, d.ptr, d.tiles, d.toff, d.uniform_ps, d.dbt, d.stride, d.ctl + 5, s);
+        else if (max_ps <= 16)
+            run_a1_invert<16, 16>(d.n_comp, d.ctl, d.active, d.rep_slot, d.rep_patch, d.ptr, d.tiles, d.toff, d.uniform_ps, d.dbt, d.stride, d.ctl + 5, s);
+        else if (max_ps <= 24)
+            run_a1_invert<24, 32>(d.n_comp, d.ctl, d.active, d.rep_slot, d.rep_patch, d.ptr, d.tiles, d.toff, d.uniform_ps, d.dbt, d.stride, d.ctl + 5, s);
+        else
+            run_a1_invert<32, 32>(d.n_comp, d.ctl, d.active, d.rep_slot, d.rep_patch, d.ptr, d.tiles, d.toff, d.uniform_ps, d.dbt, d.stride, d.ctl + 5, s);
+        k_a1_filter<<<fb, 256, 0, s>>>(d.n_p, d.ctl, d.status, d.pos_comp, d.rep_slot, d.cand);
+        k_a1_eval<<<eb, 64, 0, s>>>(d.ctl, crit, eps, d.cand, d.mem, d.pos_comp, d.rep_slot, d.rep_patch,
+                                    d.ptr, d.tiles, d.toff, d.uniform_ps, d.dbt, d.stride, d.status,
+                                    d.repof, d.next, d.counters);
+    }
+}
+
+void launch_a1_finish(int64_t n_p, const int32_t* repof, int64_t* flags, int64_t* rank, int64_t* scr,
+                      int32_t* phi, int32_t* reps, hipStream_t s) {
+    k_a1_repflags<<<nb(n_p + 1, 256), 256, 0, s>>>(n_p, repof, flags);
+    launch_exclusive_scan_i64(flags, rank, n_p + 1, scr, s);
+    k_a1_finish<<<nb(n_p, 256), 256, 0, s>>>(n_p, repof, rank, phi, reps);
+}
+
+void launch_a1_copy_db(int64_t m_p, const int32_t* reps, const int32_t* slot_of_patch, const int64_t* ptr,
+                       const double* dbt, double* db, int64_t stride, hipStream_t s) {
+    if (m_p <= 0) return;
+    k_a1_copy_db<<<(unsigned)(m_p < 65536 ? m_p : 65536), 256, 0, s>>>(m_p, reps, slot_of_patch, ptr, dbt,
+                                                                     db, stride);
+}

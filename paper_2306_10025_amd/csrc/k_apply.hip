@@ -3,16 +3,19 @@
 //
 // Two families of kernels:
 //  * vector kernels (FP64 or FP32 arithmetic): a group of G lanes per patch,
-//    lane a owns local dof a; the restricted residual is broadcast through
-//    cross-lane shuffles and the inverse is read column-major so that each
-//    step is a contiguous load;
+//    lane a owns local dof a and reads row a of the inverse (row-major, so a
+//    group streams the whole matrix contiguously); the restricted residual
+//    is broadcast through cross-lane shuffles;
 //  * grouped MFMA kernels (BF16 or FP16 operands, FP32 accumulation): the
 //    patches that share database entry j are stacked, so the apply becomes
 //    Y = X_j [r_k1 ... r_kN], one MFMA tile per 16 or 32 members (the
 //    multiple right-hand-side solve the paper's Experiment 3 discussion
 //    proposes).  The lane that gathers local dof i of a member also holds
 //    output row i of that member, so gather and scatter share indices.
-// The scatter uses FP64 atomics.
+// Patches are visited in grouped order (by database entry, then patch id)
+// through a grouped copy of the dof lists.  The scatter either adds into z
+// with FP64 atomics, or (deterministic mode) writes each patch row to a slot
+// buffer Y that a second kernel sums per dof in a fixed order.
 #include "pr_internal.h"
 
 namespace {
@@ -22,51 +25,75 @@ typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 
-template <typename TX, typename TA, int G>
-__global__ __launch_bounds__(256) void k_apply_vec(const int32_t* __restrict__ order, int64_t count,
-                                                   const int32_t* __restrict__ phi,
-                                                   const int64_t* __restrict__ ptr,
-                                                   const int32_t* __restrict__ dofs,
-                                                   const TX* __restrict__ db,
-                                                   const int64_t* __restrict__ dboff, int uniform_ps,
-                                                   const double* __restrict__ W, double omega,
-                                                   const double* __restrict__ r,
-                                                   double* __restrict__ z) {
+struct ApplyGeom {
+    const int32_t* gdofs;   // dof lists in grouped order
+    const int64_t* goff;    // grouped offsets (null: position s starts at s * pst)
+    int pst;
+    const int32_t* gphi;    // database entry of grouped position s
+    const int64_t* dboff;   // database offsets (null: entry j at j * dbst)
+    int64_t dbst;
+};
+
+template <typename TX, typename TA, typename TY, int MAXP, int G, bool TWO>
+__global__ __launch_bounds__(256) void k_apply_rows(int64_t count, ApplyGeom g, const TX* __restrict__ db,
+                                                    const double* __restrict__ W, double omega,
+                                                    const double* __restrict__ r,
+                                                    double* __restrict__ z, TY* __restrict__ Y) {
     const int a = threadIdx.x % G;
     const int64_t groups = (int64_t)gridDim.x * (blockDim.x / G);
     for (int64_t s = (int64_t)blockIdx.x * (blockDim.x / G) + threadIdx.x / G; s < count;
          s += groups) {
-        const int32_t k = order ? order[s] : (int32_t)s;
-        const int32_t j = phi[k];
-        const int64_t st = ptr[k];
-        const int p = (int)(ptr[k + 1] - st);
-        const TX* X = db + (uniform_ps ? (int64_t)j * uniform_ps * uniform_ps : dboff[j]);
+        const int64_t o = g.goff ? g.goff[s] : s * g.pst;
+        const int p = g.goff ? (int)(g.goff[s + 1] - o) : g.pst;
+        const int32_t j = g.gphi[s];
+        const TX* X = db + (g.dboff ? g.dboff[j] : (int64_t)j * g.dbst);
         const bool act = a < p;
-        const int32_t g = act ? dofs[st + a] : 0;
-        const TA rv = act ? (TA)r[g] : (TA)0;
+        const int32_t gd = act ? g.gdofs[o + a] : 0;
+        const TA rv = act ? (TA)r[gd] : (TA)0;
+        TX xr[MAXP];
+#pragma unroll
+        for (int b = 0; b < MAXP; ++b) xr[b] = (act && b < p) ? X[(int64_t)a * p + b] : (TX)0;
         TA acc = 0;
-        for (int b = 0; b < p; ++b) {
-            const TA rb = __shfl(rv, b, G);
-            if (act) acc = fma((TA)X[(int64_t)b * p + a], rb, acc);
+#pragma unroll
+        for (int b = 0; b < MAXP; ++b) {
+            if (b < p) {
+                const TA rb = __shfl(rv, b, G);
+                acc = fma((TA)xr[b], rb, acc);
+            }
         }
-        if (act) atomicAdd(&z[g], omega * W[g] * (double)acc);
+        if (act) {
+            if (TWO) Y[o + a] = (TY)acc;
+            else atomicAdd(&z[gd], omega * W[gd] * (double)acc);
+        }
     }
 }
 
-template <typename TX, typename TA>
-void run_vec(const int32_t* order, int64_t count, const int32_t* phi, const int64_t* ptr,
-             const int32_t* dofs, const TX* db, const int64_t* dboff, int uniform_ps,
-             const double* W, double omega, const double* r, double* z, int group, hipStream_t s) {
+template <typename TX, typename TA, typename TY, bool TWO>
+void run_rows(int64_t count, const ApplyGeom& g, const TX* db, const double* W, double omega,
+              const double* r, double* z, TY* Y, int maxp, hipStream_t s) {
     if (count <= 0) return;
-    const int per = 256 / group;
+    const int G = maxp <= 4 ? 4 : maxp <= 16 ? 16 : 32;
+    const int per = 256 / G;
     int64_t blocks = (count + per - 1) / per;
-    if (blocks > 131072) blocks = 131072;
-    switch (group) {
-        case 4: k_apply_vec<TX, TA, 4><<<(unsigned)blocks, 256, 0, s>>>(order, count, phi, ptr, dofs, db, dboff, uniform_ps, W, omega, r, z); break;
-        case 8: k_apply_vec<TX, TA, 8><<<(unsigned)blocks, 256, 0, s>>>(order, count, phi, ptr, dofs, db, dboff, uniform_ps, W, omega, r, z); break;
-        case 16: k_apply_vec<TX, TA, 16><<<(unsigned)blocks, 256, 0, s>>>(order, count, phi, ptr, dofs, db, dboff, uniform_ps, W, omega, r, z); break;
-        default: k_apply_vec<TX, TA, 32><<<(unsigned)blocks, 256, 0, s>>>(order, count, phi, ptr, dofs, db, dboff, uniform_ps, W, omega, r, z); break;
-    }
+    if (blocks > 262144) blocks = 262144;
+    const unsigned nb = (unsigned)blocks;
+    if (maxp <= 4) k_apply_rows<TX, TA, TY, 4, 4, TWO><<<nb, 256, 0, s>>>(count, g, db, W, omega, r, z, Y);
+    else if (maxp <= 12) k_apply_rows<TX, TA, TY, 12, 16, TWO><<<nb, 256, 0, s>>>(count, g, db, W, omega, r, z, Y);
+    else if (maxp <= 16) k_apply_rows<TX, TA, TY, 16, 16, TWO><<<nb, 256, 0, s>>>(count, g, db, W, omega, r, z, Y);
+    else if (maxp <= 24) k_apply_rows<TX, TA, TY, 24, 32, TWO><<<nb, 256, 0, s>>>(count, g, db, W, omega, r, z, Y);
+    else k_apply_rows<TX, TA, TY, 32, 32, TWO><<<nb, 256, 0, s>>>(count, g, db, W, omega, r, z, Y);
+}
+
+// z_i = omega W_i sum over the slots of dof i (fixed order)
+template <typename TY>
+__global__ void k_slot_sum(int64_t n, const int64_t* __restrict__ dof_ptr,
+                           const int32_t* __restrict__ dof_slots, const TY* __restrict__ Y,
+                           const double* __restrict__ W, double omega, double* __restrict__ z) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int64_t t = dof_ptr[i]; t < dof_ptr[i + 1]; ++t) acc += (double)Y[dof_slots[t]];
+    z[i] = omega * W[i] * acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -103,17 +130,15 @@ __device__ __forceinline__ f16v mma32(s4 a, s4 b, f16v c) {
     return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
 }
 
-template <int MODE>
+template <int MODE, bool TWO>
 __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ items, int64_t n_items,
-                                                    const int32_t* __restrict__ order,
-                                                    const int64_t* __restrict__ ptr,
-                                                    const int32_t* __restrict__ dofs,
+                                                    ApplyGeom g,
                                                     const uint16_t* __restrict__ db_lp,
                                                     const int64_t* __restrict__ dblp_off,
                                                     const int32_t* __restrict__ db_exp,
                                                     const double* __restrict__ W, double omega,
                                                     const double* __restrict__ r,
-                                                    double* __restrict__ z) {
+                                                    double* __restrict__ z, float* __restrict__ Y) {
     constexpr bool FP16 = MODE == 1;
     constexpr bool SPLIT = MODE == 2;
     const int l = threadIdx.x & (PR_WAVE - 1);
@@ -131,14 +156,14 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
             const int n = l & 15, q = l >> 4;
             const bool mv = n < cnt;
             int64_t st = 0;
-            if (mv) st = ptr[order[start + n]];
+            if (mv) st = g.goff ? g.goff[start + n] : (int64_t)(start + n) * g.pst;
             int32_t gi[4];
             float rv[4];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int kk = 4 * q + t;
                 const bool v = mv && kk < p;
-                gi[t] = v ? dofs[st + kk] : -1;
+                gi[t] = v ? g.gdofs[st + kk] : -1;
                 rv[t] = v ? (float)r[gi[t]] : 0.0f;
             }
             int f = 0;
@@ -167,9 +192,13 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 if (gi[t] >= 0) {
-                    double y = (double)acc[t];
-                    if (FP16) y = ldexp(y, ej + f);
-                    atomicAdd(&z[gi[t]], omega * W[gi[t]] * y);
+                    if (TWO) {
+                        Y[st + 4 * q + t] = FP16 ? ldexpf(acc[t], ej + f) : acc[t];
+                    } else {
+                        double y = (double)acc[t];
+                        if (FP16) y = ldexp(y, ej + f);
+                        atomicAdd(&z[gi[t]], omega * W[gi[t]] * y);
+                    }
                 }
             }
         } else {
@@ -178,7 +207,7 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
             const int n = l & 31, h = l >> 5;
             const bool mv = n < cnt;
             int64_t st = 0;
-            if (mv) st = ptr[order[start + n]];
+            if (mv) st = g.goff ? g.goff[start + n] : (int64_t)(start + n) * g.pst;
             const int steps = (p + 7) >> 3;
             int32_t gi[16];
             float rv[16];
@@ -188,7 +217,7 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
                 for (int t = 0; t < 4; ++t) {
                     const int kk = 8 * s + 4 * h + t;
                     const bool v = mv && kk < p;
-                    gi[4 * s + t] = v ? dofs[st + kk] : -1;
+                    gi[4 * s + t] = v ? g.gdofs[st + kk] : -1;
                     rv[4 * s + t] = v ? (float)r[gi[4 * s + t]] : 0.0f;
                 }
             int f = 0;
@@ -223,9 +252,13 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 if (gi[v] >= 0) {
-                    double y = (double)acc[v];
-                    if (FP16) y = ldexp(y, ej + f);
-                    atomicAdd(&z[gi[v]], omega * W[gi[v]] * y);
+                    if (TWO) {
+                        Y[st + 8 * (v >> 2) + 4 * h + (v & 3)] = FP16 ? ldexpf(acc[v], ej + f) : acc[v];
+                    } else {
+                        double y = (double)acc[v];
+                        if (FP16) y = ldexp(y, ej + f);
+                        atomicAdd(&z[gi[v]], omega * W[gi[v]] * y);
+                    }
                 }
             }
         }
@@ -240,20 +273,17 @@ __global__ __launch_bounds__(64) void k_convert_db(int prec, int64_t m_p, const 
                                                    const int32_t* __restrict__ dbps, int uniform_ps,
                                                    uint16_t* __restrict__ db_lp,
                                                    const int64_t* __restrict__ dblp_off,
-                                                   int32_t* __restrict__ db_exp, float* __restrict__ db_f32,
-                                                   double* __restrict__ db_cm) {
+                                                   int32_t* __restrict__ db_exp, float* __restrict__ db_f32) {
     const int l = threadIdx.x;
     for (int64_t j = blockIdx.x; j < m_p; j += gridDim.x) {
         const int p = uniform_ps ? uniform_ps : dbps[j];
         const int64_t off = uniform_ps ? j * (int64_t)p * p : dboff[j];
         const double* X = db + off;
-        // column-major FP64 / FP32 copies for the vector kernels
+        // row-major FP32 copy for the FP32 vector kernel
         float m = 0.0f;
         for (int e = l; e < p * p; e += PR_WAVE) {
-            const int a = e / p, b = e % p;
             const double v = X[e];
-            if (db_cm) db_cm[off + (int64_t)b * p + a] = v;
-            if (db_f32) db_f32[off + (int64_t)b * p + a] = (float)v;
+            if (db_f32) db_f32[off + e] = (float)v;
             m = fmaxf(m, fabsf((float)v));
         }
         m = wave_max(m);
@@ -288,46 +318,43 @@ __global__ __launch_bounds__(64) void k_convert_db(int prec, int64_t m_p, const 
 
 }  // namespace
 
-void launch_apply_vec_f64(const int32_t* order, int64_t count, const int32_t* phi,
-                          const int64_t* ptr, const int32_t* dofs, const double* db_cm,
-                          const int64_t* dboff, int uniform_ps, const double* W, double omega,
-                          const double* r, double* z, int group, hipStream_t s) {
-    run_vec<double, double>(order, count, phi, ptr, dofs, db_cm, dboff, uniform_ps, W, omega, r, z,
-                            group, s);
-}
-
-void launch_apply_vec_f32(const int32_t* order, int64_t count, const int32_t* phi,
-                          const int64_t* ptr, const int32_t* dofs, const float* db_f32,
-                          const int64_t* dboff, int uniform_ps, const double* W, double omega,
-                          const double* r, double* z, int group, hipStream_t s) {
-    run_vec<float, float>(order, count, phi, ptr, dofs, db_f32, dboff, uniform_ps, W, omega, r, z,
-                          group, s);
-}
-
-void launch_apply_mfma(int prec, const int32_t* items, int64_t n_items, const int32_t* order,
-                       const int64_t* ptr, const int32_t* dofs, const uint16_t* db_lp,
-                       const int64_t* dblp_off, const int32_t* db_exp, const double* W,
-                       double omega, const double* r, double* z, hipStream_t s) {
-    if (n_items <= 0) return;
-    int64_t blocks = (n_items + 3) / 4;
-    if (blocks > 131072) blocks = 131072;
-    if (prec == PR_FP16)
-        k_apply_mfma<1><<<(unsigned)blocks, 256, 0, s>>>(items, n_items, order, ptr, dofs, db_lp,
-                                                        dblp_off, db_exp, W, omega, r, z);
-    else if (prec == PR_BF16X3)
-        k_apply_mfma<2><<<(unsigned)blocks, 256, 0, s>>>(items, n_items, order, ptr, dofs, db_lp,
-                                                        dblp_off, db_exp, W, omega, r, z);
-    else
-        k_apply_mfma<0><<<(unsigned)blocks, 256, 0, s>>>(items, n_items, order, ptr, dofs, db_lp,
-                                                        dblp_off, db_exp, W, omega, r, z);
+void launch_apply(int prec, bool two_stage, const ApplyLaunch& a, hipStream_t s) {
+    ApplyGeom g{a.gdofs, a.goff, a.pst, a.gphi, a.dboff, a.dbst};
+    if (prec == PR_FP64) {
+        if (two_stage) run_rows<double, double, double, true>(a.n_p, g, a.db, a.W, a.omega, a.r, a.z, (double*)a.Y, a.maxp, s);
+        else run_rows<double, double, double, false>(a.n_p, g, a.db, a.W, a.omega, a.r, a.z, (double*)nullptr, a.maxp, s);
+    } else if (prec == PR_FP32) {
+        if (two_stage) run_rows<float, float, float, true>(a.n_p, g, a.db_f32, a.W, a.omega, a.r, a.z, (float*)a.Y, a.maxp, s);
+        else run_rows<float, float, float, false>(a.n_p, g, a.db_f32, a.W, a.omega, a.r, a.z, (float*)nullptr, a.maxp, s);
+    } else {
+        if (a.n_items > 0) {
+            int64_t blocks = (a.n_items + 3) / 4;
+            if (blocks > 262144) blocks = 262144;
+            const unsigned nb = (unsigned)blocks;
+#define PR_MFMA(MODE, TWO) k_apply_mfma<MODE, TWO><<<nb, 256, 0, s>>>(a.items, a.n_items, g, a.db_lp, a.dblp_off, a.db_exp, a.W, a.omega, a.r, a.z, (float*)a.Y)
+            const int mode = prec == PR_FP16 ? 1 : prec == PR_BF16X3 ? 2 : 0;
+            if (two_stage) {
+                if (mode == 0) PR_MFMA(0, true); else if (mode == 1) PR_MFMA(1, true); else PR_MFMA(2, true);
+            } else {
+                if (mode == 0) PR_MFMA(0, false); else if (mode == 1) PR_MFMA(1, false); else PR_MFMA(2, false);
+            }
+#undef PR_MFMA
+        }
+    }
+    if (two_stage) {
+        const unsigned nb = (unsigned)((a.n + 255) / 256);
+        if (prec == PR_FP64)
+            k_slot_sum<double><<<nb, 256, 0, s>>>(a.n, a.dof_ptr, a.dof_slots, (const double*)a.Y, a.W, a.omega, a.z);
+        else
+            k_slot_sum<float><<<nb, 256, 0, s>>>(a.n, a.dof_ptr, a.dof_slots, (const float*)a.Y, a.W, a.omega, a.z);
+    }
 }
 
 void launch_convert_db(int prec, int64_t m_p, const double* db, const int64_t* dboff,
                        const int32_t* dbps, int uniform_ps, uint16_t* db_lp,
-                       const int64_t* dblp_off, int32_t* db_exp, float* db_f32, double* db_cm,
-                       hipStream_t s) {
+                       const int64_t* dblp_off, int32_t* db_exp, float* db_f32, hipStream_t s) {
     if (m_p <= 0) return;
     int64_t blocks = m_p < 65536 ? m_p : 65536;
     k_convert_db<<<(unsigned)blocks, 64, 0, s>>>(prec, m_p, db, dboff, dbps, uniform_ps, db_lp,
-                                                dblp_off, db_exp, db_f32, db_cm);
+                                                dblp_off, db_exp, db_f32);
 }

@@ -108,6 +108,110 @@ __global__ void k_zero(double* x, int64_t n) {
     if (q < n) x[q] = 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// Fused Gram-Schmidt passes (classical Gram-Schmidt applied twice):
+//   MODE 0: out_i = V_i . w                       (i < nv)
+//   MODE 1: w <- w - sum_i c_i V_i ; out_i = V_i . w   (each V_i loaded once)
+//   MODE 2: w <- w - sum_i c_i V_i ; out_0 = w . w
+// Each block reduces its rows; the last block to finish (ticket counter)
+// sums the block partials in a fixed order, so results do not depend on
+// timing.  The counter is returned to zero by that block.
+// ---------------------------------------------------------------------------
+constexpr int kGsThreads = 256;
+
+template <int MODE>
+__global__ __launch_bounds__(kGsThreads) void k_gs(const double* __restrict__ V, int64_t ldv, int nv,
+                                                   double* __restrict__ w, int64_t n,
+                                                   const double* __restrict__ c,
+                                                   double* __restrict__ partial,
+                                                   unsigned int* __restrict__ counter,
+                                                   double* __restrict__ out) {
+    constexpr int NO = (MODE == 2) ? 1 : kMaxVec;
+    __shared__ double s_red[kGsThreads / PR_WAVE][kMaxVec];
+    __shared__ bool s_last;
+    const int nout = (MODE == 2) ? 1 : nv;
+    double cf[kMaxVec];
+    if (MODE >= 1) {
+#pragma unroll
+        for (int i = 0; i < kMaxVec; ++i) cf[i] = (i < nv) ? c[i] : 0.0;
+    }
+    double acc[NO];
+#pragma unroll
+    for (int i = 0; i < NO; ++i) acc[i] = 0.0;
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t hi = lo + per < n ? lo + per : n;
+    for (int64_t q = lo + threadIdx.x; q < hi; q += kGsThreads) {
+        double wq = w[q];
+        if (MODE == 0) {
+#pragma unroll
+            for (int i = 0; i < kMaxVec; ++i)
+                if (i < nv) acc[i] = fma(V[(int64_t)i * ldv + q], wq, acc[i]);
+        } else {
+            double v[kMaxVec];
+#pragma unroll
+            for (int i = 0; i < kMaxVec; ++i) v[i] = (i < nv) ? V[(int64_t)i * ldv + q] : 0.0;
+#pragma unroll
+            for (int i = 0; i < kMaxVec; ++i)
+                if (i < nv) wq = fma(-cf[i], v[i], wq);
+            w[q] = wq;
+            if (MODE == 1) {
+#pragma unroll
+                for (int i = 0; i < kMaxVec; ++i)
+                    if (i < nv) acc[i] = fma(v[i], wq, acc[i]);
+            } else {
+                acc[0] = fma(wq, wq, acc[0]);
+            }
+        }
+    }
+    const int lane = threadIdx.x & (PR_WAVE - 1), wid = threadIdx.x / PR_WAVE;
+#pragma unroll
+    for (int i = 0; i < NO; ++i) {
+        if (i < nout) {
+            const double t = wave_sum(acc[i]);
+            if (lane == 0) s_red[wid][i] = t;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < nout) {
+        double t = 0.0;
+        for (int w2 = 0; w2 < kGsThreads / PR_WAVE; ++w2) t += s_red[w2][threadIdx.x];
+        partial[(int64_t)blockIdx.x * kMaxVec + threadIdx.x] = t;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int ticket = atomicAdd(counter, 1u);
+        s_last = (ticket == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    // last block: out_i = sum_b partial[b][i], fixed partition and tree
+    double tot[NO];
+#pragma unroll
+    for (int i = 0; i < NO; ++i) tot[i] = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kGsThreads) {
+#pragma unroll
+        for (int i = 0; i < NO; ++i)
+            if (i < nout) tot[i] += partial[(int64_t)b * kMaxVec + i];
+    }
+#pragma unroll
+    for (int i = 0; i < NO; ++i) {
+        if (i < nout) {
+            const double t = wave_sum(tot[i]);
+            if (lane == 0) s_red[wid][i] = t;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < nout) {
+        double t = 0.0;
+        for (int w2 = 0; w2 < kGsThreads / PR_WAVE; ++w2) t += s_red[w2][threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+    if (threadIdx.x == 0) *counter = 0u;
+}
+
 inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -162,4 +266,29 @@ void launch_gemv_small(const double* V, int64_t ldv, int nv, const double* coef,
 
 void launch_zero(double* x, int64_t n, hipStream_t s) {
     if (n > 0) k_zero<<<nb(n, 256), 256, 0, s>>>(x, n);
+}
+
+int gs_blocks(int64_t n) {
+    int64_t b = (n + 2047) / 2048;
+    if (b > 1024) b = 1024;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+// mode 0: out = V^T w ; mode 1: w -= V c, out = V^T w ; mode 2: w -= V c, out[0] = w.w
+// partial: gs_blocks(n) * 32 doubles; counter: one zeroed unsigned int.
+void launch_gs(int mode, const double* V, int64_t ldv, int nv, double* w, int64_t n, const double* c,
+               double* partial, unsigned int* counter, double* out, hipStream_t s) {
+    const int nbk = gs_blocks(n);
+    for (int base = 0; base < nv || (nv == 0 && base == 0); base += kMaxVec) {
+        const int cnt = nv - base < kMaxVec ? nv - base : kMaxVec;
+        const double* Vb = V + (int64_t)base * ldv;
+        if (mode == 0)
+            k_gs<0><<<nbk, kGsThreads, 0, s>>>(Vb, ldv, cnt, w, n, c, partial, counter, out + base);
+        else if (mode == 1)
+            k_gs<1><<<nbk, kGsThreads, 0, s>>>(Vb, ldv, cnt, w, n, c + base, partial, counter, out + base);
+        else
+            k_gs<2><<<nbk, kGsThreads, 0, s>>>(Vb, ldv, cnt, w, n, c + base, partial, counter, out);
+        if (nv == 0) break;
+    }
 }

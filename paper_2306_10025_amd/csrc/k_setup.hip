@@ -318,6 +318,65 @@ __global__ void k_unpad_copy(const uint64_t* __restrict__ kin, const int32_t* __
     }
 }
 
+// ---- grouped order ------------------------------------------------------------
+
+__global__ void k_group_sizes(const int32_t* __restrict__ order, int64_t n_p,
+                              const int64_t* __restrict__ ptr, int64_t* __restrict__ sizes) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n_p) {
+        const int32_t k = order[s];
+        sizes[s] = ptr[k + 1] - ptr[k];
+    } else if (s == n_p) {
+        sizes[s] = 0;
+    }
+}
+
+__global__ void k_group_gather(const int32_t* __restrict__ order, int64_t n_p,
+                               const int64_t* __restrict__ ptr, const int32_t* __restrict__ dofs,
+                               const int64_t* __restrict__ goff, int pst, int32_t* __restrict__ gdofs,
+                               int32_t* __restrict__ gphi, const int32_t* __restrict__ phi) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_p) return;
+    const int32_t k = order[s];
+    const int64_t a0 = ptr[k], a1 = ptr[k + 1];
+    const int64_t o = goff ? goff[s] : s * (int64_t)pst;
+    for (int64_t q = a0; q < a1; ++q) gdofs[o + (q - a0)] = dofs[q];
+    gphi[s] = phi[k];
+}
+
+__global__ void k_transpose_fill(const int32_t* __restrict__ gdofs, int64_t total,
+                                 const int64_t* __restrict__ dof_ptr, int32_t* __restrict__ fill,
+                                 int32_t* __restrict__ dof_slots) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int32_t g = gdofs[t];
+    const int32_t pos = atomicAdd(&fill[g], 1);
+    dof_slots[dof_ptr[g] + pos] = (int32_t)t;
+}
+
+// each dof's slot list in ascending slot order (fixed summation order)
+__global__ void k_transpose_sort(int64_t n, const int64_t* __restrict__ dof_ptr,
+                                 int32_t* __restrict__ dof_slots) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t a = dof_ptr[i], b = dof_ptr[i + 1];
+    for (int64_t x = a + 1; x < b; ++x) {
+        const int32_t v = dof_slots[x];
+        int64_t y = x - 1;
+        while (y >= a && dof_slots[y] > v) {
+            dof_slots[y + 1] = dof_slots[y];
+            --y;
+        }
+        dof_slots[y + 1] = v;
+    }
+}
+
+__global__ void k_i32_to_i64(const int32_t* __restrict__ in, int64_t* __restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[i];
+    else if (i == n) out[i] = 0;
+}
+
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -403,4 +462,29 @@ void launch_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, uint64_t* kscr,
         k_bitonic_local<<<lblocks, kSortThreads, 0, s>>>(kscr, vscr, N, k);
     }
     k_unpad_copy<<<nblk(n, 256), 256, 0, s>>>(kscr, vscr, n, keys, vals);
+}
+
+void launch_group_sizes(const int32_t* order, int64_t n_p, const int64_t* ptr, int64_t* sizes,
+                        hipStream_t s) {
+    k_group_sizes<<<nblk(n_p + 1, 256), 256, 0, s>>>(order, n_p, ptr, sizes);
+}
+
+void launch_group_gather(const int32_t* order, int64_t n_p, const int64_t* ptr, const int32_t* dofs,
+                         const int64_t* goff, int pst, int32_t* gdofs, int32_t* gphi,
+                         const int32_t* phi, hipStream_t s) {
+    if (n_p > 0)
+        k_group_gather<<<nblk(n_p, 256), 256, 0, s>>>(order, n_p, ptr, dofs, goff, pst, gdofs, gphi, phi);
+}
+
+void launch_transpose_fill(const int32_t* gdofs, int64_t total, const int64_t* dof_ptr,
+                           int32_t* fill, int32_t* dof_slots, hipStream_t s) {
+    if (total > 0) k_transpose_fill<<<nblk(total, 256), 256, 0, s>>>(gdofs, total, dof_ptr, fill, dof_slots);
+}
+
+void launch_transpose_sort(int64_t n, const int64_t* dof_ptr, int32_t* dof_slots, hipStream_t s) {
+    if (n > 0) k_transpose_sort<<<nblk(n, 256), 256, 0, s>>>(n, dof_ptr, dof_slots);
+}
+
+void launch_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, hipStream_t s) {
+    k_i32_to_i64<<<nblk(n + 1, 256), 256, 0, s>>>(in, out, n);
 }

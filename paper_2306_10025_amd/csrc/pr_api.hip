@@ -51,12 +51,6 @@ int check_dev(pr_handle h, const void* p, const char* what) {
     return PR_OK;
 }
 
-int pow2_group(int p) {
-    int g = 4;
-    while (g < p) g <<= 1;
-    return g;
-}
-
 int64_t next_pow2(int64_t n) {
     int64_t N = 1024;
     while (N < n) N <<= 1;
@@ -68,48 +62,126 @@ int run_alg1(pr_handle h) {
     hipStream_t s = h->stream;
     const int64_t n_p = h->n_p;
     const int64_t stride = (int64_t)h->max_ps * h->max_ps;
-    Alg1Dev a{};
-    PR_TRY(dalloc(h, &a.status, n_p));
-    PR_TRY(dalloc(h, &a.ctrl, 8));
-    PR_TRY(dalloc(h, &a.counters, 8));
-    PR_TRY(dalloc(h, &a.cand, n_p));
+    const int crit = h->prm.criterion;
+    const double* keynorm = (crit == PR_CRIT_L1) ? h->l1norm : h->fnorm;
+    const int64_t N = next_pow2(n_p);
+    uint64_t *keys = nullptr, *kscr = nullptr;
+    int32_t *sidx = nullptr, *vscr = nullptr;
+    int64_t *flag = nullptr, *excl = nullptr, *scr = nullptr;
+    PR_TRY(dalloc(h, &keys, n_p));
+    PR_TRY(dalloc(h, &kscr, N));
+    PR_TRY(dalloc(h, &sidx, n_p));
+    PR_TRY(dalloc(h, &vscr, N));
+    PR_TRY(dalloc(h, &flag, n_p + 1));
+    PR_TRY(dalloc(h, &excl, n_p + 1));
+    PR_TRY(dalloc(h, &scr, scan_scratch_elems(n_p + 1) + 2));
+    // 1. sort by (size, key); 2. components where no match can cross a gap
+    launch_a1_keys(n_p, h->pptr, keynorm, keys, sidx, s);
+    launch_sort_pairs(keys, sidx, n_p, kscr, vscr, s);
+    launch_a1_comp_flags(n_p, sidx, h->pptr, keynorm, crit, h->prm.eps, flag, s);
+    launch_exclusive_scan_i64(flag, excl, n_p + 1, scr, s);
+    int64_t n_comp = 0;
+    PR_HIP(h, hipMemcpyAsync(&n_comp, excl + n_p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    PR_HIP(h, hipStreamSynchronize(s));
+    // 3. members of each component in ascending patch id
+    A1Dev d{};
+    d.n_p = n_p;
+    d.n_comp = n_comp;
+    d.ptr = h->pptr;
+    d.tiles = h->tiles;
+    d.toff = h->uniform ? nullptr : h->toff;
+    d.uniform_ps = h->uniform ? h->max_ps : 0;
+    d.stride = stride;
+    int32_t *mem = nullptr, *pos_comp = nullptr, *cstart = nullptr, *next = nullptr, *status = nullptr;
+    int32_t *rep_slot = nullptr, *rep_patch = nullptr, *slot_of_patch = nullptr, *repof = nullptr;
+    int32_t *active = nullptr, *cand = nullptr, *ctl = nullptr;
+    unsigned long long* counters = nullptr;
+    double* dbt = nullptr;
+    PR_TRY(dalloc(h, &mem, n_p));
+    PR_TRY(dalloc(h, &pos_comp, n_p));
+    PR_TRY(dalloc(h, &cstart, n_comp + 1));
+    PR_TRY(dalloc(h, &next, n_comp));
+    PR_TRY(dalloc(h, &status, n_p));
+    PR_TRY(dalloc(h, &rep_slot, n_comp));
+    PR_TRY(dalloc(h, &rep_patch, n_p));
+    PR_TRY(dalloc(h, &slot_of_patch, n_p));
+    PR_TRY(dalloc(h, &repof, n_p));
+    PR_TRY(dalloc(h, &active, n_comp));
+    PR_TRY(dalloc(h, &cand, n_p));
+    PR_TRY(dalloc(h, &ctl, 8));
+    PR_TRY(dalloc(h, &counters, 4));
+    PR_TRY(dalloc(h, &dbt, (size_t)n_p * stride));
+    launch_a1_key2(n_p, flag, excl, sidx, keys, mem, s);
+    launch_sort_pairs(keys, mem, n_p, kscr, vscr, s);
+    launch_a1_cstart(n_p, n_comp, keys, pos_comp, cstart, next, s);
+    PR_HIP(h, hipMemsetAsync(status, 0, n_p * sizeof(int32_t), s));
+    PR_HIP(h, hipMemsetAsync(ctl, 0, 8 * sizeof(int32_t), s));
+    PR_HIP(h, hipMemsetAsync(counters, 0, 4 * sizeof(unsigned long long), s));
+    d.ctl = ctl;
+    d.counters = counters;
+    d.cstart = cstart;
+    d.next = next;
+    d.mem = mem;
+    d.pos_comp = pos_comp;
+    d.status = status;
+    d.rep_slot = rep_slot;
+    d.rep_patch = rep_patch;
+    d.slot_of_patch = slot_of_patch;
+    d.repof = repof;
+    d.active = active;
+    d.cand = cand;
+    d.dbt = dbt;
+    // 4. rounds, all components at once, until no component opens an entry
+    int batch = 2;
+    int32_t c8[8];
+    for (;;) {
+        launch_a1_rounds(batch, d, crit, h->prm.eps, h->max_ps, s);
+        PR_HIP(h, hipMemcpyAsync(c8, ctl, sizeof(c8), hipMemcpyDeviceToHost, s));
+        PR_HIP(h, hipStreamSynchronize(s));
+        if (c8[2]) break;
+        if (batch < 64) batch *= 2;
+    }
+    PR_HIP(h, hipGetLastError());
+    if (c8[5] != 0)
+        return pr_fail(h, PR_ERR_SINGULAR_PATCH, "zero pivot in database patch " + std::to_string(c8[5] - 1));
+    h->m_p = c8[0];
+    // 5. entries numbered by ascending patch id
     PR_TRY(dalloc(h, &h->phi, n_p));
     PR_TRY(dalloc(h, &h->reps, n_p));
-    PR_TRY(dalloc(h, &h->db, (size_t)n_p * stride));
-    PR_HIP(h, hipMemsetAsync(a.status, 0, n_p * sizeof(int32_t), s));
-    int32_t ctrl0[8] = {-1, 0, 0, 0, 0, 0, 0, 0};
-    PR_HIP(h, hipMemcpyAsync(a.ctrl, ctrl0, sizeof(ctrl0), hipMemcpyHostToDevice, s));
-    PR_HIP(h, hipMemsetAsync(a.counters, 0, 8 * sizeof(unsigned long long), s));
-    const double* keynorm = (h->prm.criterion == PR_CRIT_L1) ? h->l1norm : h->fnorm;
-    int batch = 8;
-    int32_t ctrl[8];
-    int64_t rounds = 0;
-    for (;;) {
-        launch_alg1_rounds(batch, a, h->prm.criterion, h->prm.eps, n_p, h->pptr, h->tiles,
-                           h->uniform ? nullptr : h->toff, h->uniform ? h->max_ps : 0, keynorm,
-                           h->phi, h->reps, h->db, stride, s);
-        rounds += batch;
-        PR_HIP(h, hipMemcpyAsync(ctrl, a.ctrl, sizeof(ctrl), hipMemcpyDeviceToHost, s));
-        PR_HIP(h, hipStreamSynchronize(s));
-        if (ctrl[3]) break;
-        if (batch < 256) batch *= 2;
-    }
-    if (ctrl[5] != 0)
-        return pr_fail(h, PR_ERR_SINGULAR_PATCH,
-                       "zero pivot in database patch " + std::to_string(ctrl[5] - 1));
-    h->m_p = ctrl[2];
-    unsigned long long cnt[8];
-    PR_HIP(h, hipMemcpy(cnt, a.counters, sizeof(cnt), hipMemcpyDeviceToHost));
+    PR_TRY(dalloc(h, &h->db, (size_t)h->m_p * stride));
+    launch_a1_finish(n_p, repof, flag, excl, scr, h->phi, h->reps, s);
+    launch_a1_copy_db(h->m_p, h->reps, slot_of_patch, h->pptr, dbt, h->db, stride, s);
+    unsigned long long cnt[4];
+    PR_HIP(h, hipMemcpyAsync(cnt, counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    h->reps_host.resize(h->m_p);
+    PR_HIP(h, hipMemcpyAsync(h->reps_host.data(), h->reps, h->m_p * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    std::vector<int64_t> pptr_host(n_p + 1);
+    PR_HIP(h, hipMemcpyAsync(pptr_host.data(), h->pptr, (n_p + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    std::vector<int32_t> phi_h(n_p);
+    PR_HIP(h, hipMemcpyAsync(phi_h.data(), h->phi, n_p * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PR_HIP(h, hipStreamSynchronize(s));
     h->stats.crit_evals = (int64_t)cnt[0];
     h->stats.crit_exact = (int64_t)cnt[1];
-    h->stats.crit_pruned = (int64_t)cnt[2];
-    h->stats.alg1_rounds = h->m_p;
-    h->reps_host.resize(h->m_p);
-    PR_HIP(h, hipMemcpy(h->reps_host.data(), h->reps, h->m_p * sizeof(int32_t), hipMemcpyDeviceToHost));
-    // database offsets: entry j keeps the slot stride of the largest patch
+    h->stats.alg1_rounds = c8[4];
+    // pairs the sequential algorithm compares: patch i against the entries of
+    // its size up to its own (excluded for an entry's patch); the rest were
+    // skipped by the certified bound
+    {
+        std::vector<int64_t> before(h->m_p);       // earlier entries of the same size
+        std::vector<int64_t> seen(33, 0);
+        for (int64_t j = 0; j < h->m_p; ++j) {
+            const int r = h->reps_host[j];
+            const int p = (int)(pptr_host[r + 1] - pptr_host[r]);
+            before[j] = seen[p]++;
+        }
+        int64_t naive = 0;
+        for (int64_t i = 0; i < n_p; ++i) {
+            const int j = phi_h[i];
+            naive += before[j] + (h->reps_host[j] == (int32_t)i ? 0 : 1);
+        }
+        h->stats.crit_pruned = naive - h->stats.crit_evals;
+    }
     h->dbps_host.resize(h->m_p);
-    std::vector<int64_t> pptr_host(h->n_p + 1);
-    PR_HIP(h, hipMemcpy(pptr_host.data(), h->pptr, (h->n_p + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
     h->dboff_host.resize(h->m_p + 1);
     for (int64_t j = 0; j < h->m_p; ++j) {
         const int32_t r = h->reps_host[j];
@@ -117,7 +189,6 @@ int run_alg1(pr_handle h) {
         h->dboff_host[j] = j * stride;
     }
     h->dboff_host[h->m_p] = h->m_p * stride;
-    (void)rounds;
     return PR_OK;
 }
 
@@ -187,6 +258,40 @@ int run_group(pr_handle h) {
     PR_HIP(h, hipMemcpyAsync(keys, keys_h.data(), n_p * sizeof(uint64_t), hipMemcpyHostToDevice, s));
     launch_iota(h->order, n_p, s);
     launch_sort_pairs(keys, h->order, n_p, kscr, vscr, s);
+    // grouped copy of the dof lists and the entry of each grouped position
+    PR_TRY(dalloc(h, &h->gdofs, h->total_dofs));
+    PR_TRY(dalloc(h, &h->gphi, n_p));
+    if (!h->uniform) {
+        int64_t* sizes = nullptr;
+        int64_t* scr = nullptr;
+        PR_TRY(dalloc(h, &sizes, n_p + 1));
+        PR_TRY(dalloc(h, &scr, scan_scratch_elems(n_p + 1) + 2));
+        PR_TRY(dalloc(h, &h->goff, n_p + 1));
+        launch_group_sizes(h->order, n_p, h->pptr, sizes, s);
+        launch_exclusive_scan_i64(sizes, h->goff, n_p + 1, scr, s);
+    }
+    launch_group_gather(h->order, n_p, h->pptr, h->pdofs, h->goff, h->uniform ? h->max_ps : 0, h->gdofs,
+                        h->gphi, h->phi, s);
+    if (h->prm.deterministic) {
+        // dof -> grouped slots, ascending (fixed summation order)
+        int64_t* cnt64 = nullptr;
+        int64_t* scr = nullptr;
+        int32_t* fill = nullptr;
+        PR_TRY(dalloc(h, &cnt64, h->n + 1));
+        PR_TRY(dalloc(h, &scr, scan_scratch_elems(h->n + 1) + 2));
+        PR_TRY(dalloc(h, &fill, h->n));
+        PR_TRY(dalloc(h, &h->dof_ptr, h->n + 1));
+        PR_TRY(dalloc(h, &h->dof_slots, h->total_dofs));
+        launch_i32_to_i64(h->cnt, cnt64, h->n, s);
+        launch_exclusive_scan_i64(cnt64, h->dof_ptr, h->n + 1, scr, s);
+        PR_HIP(h, hipMemsetAsync(fill, 0, h->n * sizeof(int32_t), s));
+        launch_transpose_fill(h->gdofs, h->total_dofs, h->dof_ptr, fill, h->dof_slots, s);
+        launch_transpose_sort(h->n, h->dof_ptr, h->dof_slots, s);
+        const size_t ybytes = h->prm.apply_precision == PR_FP64 ? 8 : 4;
+        char* yb = nullptr;
+        PR_TRY(dalloc(h, &yb, h->total_dofs * ybytes));
+        h->Ybuf = yb;
+    }
     // work items of <= 16 (p <= 16) or <= 32 members of one entry
     std::vector<int32_t> items;
     int64_t start = 0;
@@ -211,7 +316,6 @@ int run_group(pr_handle h) {
     PR_TRY(dalloc(h, &h->dboff, m_p + 1));
     PR_HIP(h, hipMemcpyAsync(h->dboff, h->dboff_host.data(), (m_p + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
     const int64_t dbsize = h->dboff_host[m_p];
-    PR_TRY(dalloc(h, &h->db_cm, dbsize));
     const int prec = h->prm.apply_precision;
     h->apply_prec = prec;
     if (prec == PR_FP32) PR_TRY(dalloc(h, &h->db_f32, dbsize));
@@ -232,7 +336,7 @@ int run_group(pr_handle h) {
         PR_TRY(dalloc(h, &h->db_exp, m_p));
     }
     launch_convert_db(prec, m_p, h->db, h->dboff, dbps, 0, (uint16_t*)h->db_lp, h->dblp_off, h->db_exp,
-                      h->db_f32, h->db_cm, s);
+                      h->db_f32, s);
     PR_HIP(h, hipStreamSynchronize(s));
     PR_HIP(h, hipGetLastError());
     h->stats.n_items = h->n_items;
@@ -242,34 +346,53 @@ int run_group(pr_handle h) {
     return PR_OK;
 }
 
-// z (+)= omega M~^{-1} r ; z must be zeroed by the caller for a plain apply
-int apply_accumulate(pr_handle h, const double* r, double* z) {
+// z = omega M~^{-1} r, or z += omega M~^{-1} r when accumulate (tmp: n doubles,
+// used by the deterministic scatter, which overwrites its output)
+int apply_op(pr_handle h, const double* r, double* z, bool accumulate, double* tmp) {
     hipStream_t s = h->stream;
-    const double om = h->prm.omega;
-    switch (h->apply_prec) {
-        case PR_FP64:
-            launch_apply_vec_f64(h->order, h->n_p, h->phi, h->pptr, h->pdofs, h->db_cm, h->dboff, 0, h->W,
-                                 om, r, z, pow2_group(h->max_ps), s);
-            break;
-        case PR_FP32:
-            launch_apply_vec_f32(h->order, h->n_p, h->phi, h->pptr, h->pdofs, h->db_f32, h->dboff, 0, h->W,
-                                 om, r, z, pow2_group(h->max_ps), s);
-            break;
-        default:
-            launch_apply_mfma(h->apply_prec, h->items, h->n_items, h->order, h->pptr, h->pdofs,
-                              (const uint16_t*)h->db_lp, h->dblp_off, h->db_exp, h->W, om, r, z, s);
+    const bool two = h->prm.deterministic != 0;
+    ApplyLaunch a{};
+    a.n = h->n;
+    a.n_p = h->n_p;
+    a.gdofs = h->gdofs;
+    a.goff = h->goff;
+    a.pst = h->uniform ? h->max_ps : 0;
+    a.gphi = h->gphi;
+    a.maxp = h->max_ps;
+    a.db = h->db;
+    a.db_f32 = h->db_f32;
+    a.dboff = h->dboff;
+    a.dbst = 0;
+    a.db_lp = (const uint16_t*)h->db_lp;
+    a.dblp_off = h->dblp_off;
+    a.db_exp = h->db_exp;
+    a.items = h->items;
+    a.n_items = h->n_items;
+    a.W = h->W;
+    a.omega = h->prm.omega;
+    a.r = r;
+    a.Y = h->Ybuf;
+    a.dof_ptr = h->dof_ptr;
+    a.dof_slots = h->dof_slots;
+    if (two) {
+        a.z = accumulate ? tmp : z;
+        launch_apply(h->apply_prec, true, a, s);
+        if (accumulate) launch_axpy_dev(z, tmp, 1.0, h->n, s);
+    } else {
+        if (!accumulate) launch_zero(z, h->n, s);
+        a.z = z;
+        launch_apply(h->apply_prec, false, a, s);
     }
     return PR_OK;
 }
 
-// e = sweeps damped smoothing steps from 0 applied to v (uses t3 as scratch)
+// e = `sweeps` damped smoothing steps from 0 applied to v (t3: 2n doubles scratch)
 int precond(pr_handle h, const double* v, double* e, double* t3) {
     hipStream_t s = h->stream;
-    launch_zero(e, h->n, s);
-    apply_accumulate(h, v, e);
+    PR_TRY(apply_op(h, v, e, false, nullptr));
     for (int sw = 1; sw < h->prm.sweeps; ++sw) {
         launch_spmv(h->rowptr, h->col, h->val, h->n, e, v, t3, (int)(h->nnz / std::max<int64_t>(h->n, 1)), s);
-        apply_accumulate(h, t3, e);
+        PR_TRY(apply_op(h, t3, e, true, t3 + h->n));
     }
     return PR_OK;
 }
@@ -277,11 +400,14 @@ int precond(pr_handle h, const double* v, double* e, double* t3) {
 int ensure_workspace(pr_handle h, int m) {
     if (h->ws_restart >= m) return PR_OK;
     const int64_t n = h->n;
-    PR_TRY(dalloc(h, &h->V, (size_t)(m + 1) * n));
+    h->ldv = (n + 63) / 64 * 64;   // 512-byte aligned basis columns
+    PR_TRY(dalloc(h, &h->V, (size_t)(m + 1) * h->ldv));
     PR_TRY(dalloc(h, &h->w, n));
     PR_TRY(dalloc(h, &h->t1, n));
-    PR_TRY(dalloc(h, &h->t2, 2 * n));
-    PR_TRY(dalloc(h, &h->red, (size_t)reduce_blocks(n) * 32 + 64));
+    PR_TRY(dalloc(h, &h->t2, 3 * n));   // preconditioned vector, sweep residual, scratch
+    PR_TRY(dalloc(h, &h->red, (size_t)std::max(reduce_blocks(n), gs_blocks(n)) * 32 + 64));
+    PR_TRY(dalloc(h, &h->gs_counter, 1));
+    PR_HIP(h, hipMemsetAsync(h->gs_counter, 0, sizeof(unsigned int), h->stream));
     PR_TRY(dalloc(h, &h->hd, 256));
     if (!h->hh) PR_HIP(h, hipHostMalloc((void**)&h->hh, 256 * sizeof(double), hipHostMallocDefault));
     h->ws_restart = m;
@@ -419,7 +545,6 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
         return pr_fail(nullptr, PR_ERR_INVALID_ARG, "bad parameter value");
     if (pm.algo != PR_ALGO_FULL && pm.algo != PR_ALGO_TOLERANCE)
         return pr_fail(nullptr, PR_ERR_UNSUPPORTED, "clustering algorithms are not built in this library");
-    if (pm.deterministic) return pr_fail(nullptr, PR_ERR_UNSUPPORTED, "deterministic scatter not built");
     {
         int rc;
         if ((rc = check_dev(nullptr, A->row_ptr, "A.row_ptr")) < 0) return rc;
@@ -574,8 +699,7 @@ int pr_apply(pr_handle h, const double* r, double* z) {
     PR_TRY(check_dev(h, r, "r"));
     PR_TRY(check_dev(h, z, "z"));
     if (r == z) return pr_fail(h, PR_ERR_INVALID_ARG, "r and z must be distinct");
-    launch_zero(z, h->n, h->stream);
-    apply_accumulate(h, r, z);
+    PR_TRY(apply_op(h, r, z, false, nullptr));
     PR_HIP(h, hipGetLastError());
     return PR_OK;
 }
@@ -634,7 +758,10 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
         return PR_OK;
     };
     // ||b||
-    launch_multidot(b, n, 1, b, n, h->red, hd, s);
+    const int64_t ldv = h->ldv;
+    double* red = h->red;
+    unsigned int* ctr = h->gs_counter;
+    launch_gs(0, b, n, 1, const_cast<double*>(b), n, nullptr, red, ctr, hd, s);
     PR_TRY(sync_read(1));
     const double bnorm = std::sqrt(hh[0]);
     launch_zero(x, n, s);
@@ -651,7 +778,7 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
     double relres = 1.0, est = 1.0;
     const int64_t maxit = h->prm.max_iters;
     for (;;) {
-        launch_multidot(r, n, 1, r, n, h->red, hd, s);
+        launch_gs(0, r, n, 1, r, n, nullptr, red, ctr, hd, s);
         PR_TRY(sync_read(1));
         const double beta = std::sqrt(hh[0]);
         relres = beta / bnorm;
@@ -664,7 +791,7 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
         g[0] = beta;
         int mm = 0;
         for (int j = 0; j < m; ++j) {
-            double* vj = V + (int64_t)j * n;
+            double* vj = V + (int64_t)j * ldv;
             tbeg();
             PR_TRY(precond(h, vj, zt, t3));
             tend(0);
@@ -674,12 +801,12 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
             ++iters;
             // classical Gram-Schmidt, twice
             tbeg();
-            launch_multidot(V, n, j + 1, w, n, h->red, hd, s);
-            launch_update(w, V, n, j + 1, hd, -1.0, n, s);
-            launch_multidot(V, n, j + 1, w, n, h->red, hd + 64, s);
-            launch_update(w, V, n, j + 1, hd + 64, -1.0, n, s);
-            launch_multidot(w, n, 1, w, n, h->red, hd + 128, s);
-            launch_scale(w, V + (int64_t)(j + 1) * n, hd + 128, n, s);
+            // pass 1: h1 = V^T w ; pass 2: w -= V h1, h2 = V^T w ;
+            // pass 3: w -= V h2, ||w||^2 ; then v_{j+1} = w / ||w||
+            launch_gs(0, V, ldv, j + 1, w, n, nullptr, red, ctr, hd, s);
+            launch_gs(1, V, ldv, j + 1, w, n, hd, red, ctr, hd + 64, s);
+            launch_gs(2, V, ldv, j + 1, w, n, hd + 64, red, ctr, hd + 128, s);
+            launch_scale(w, V + (int64_t)(j + 1) * ldv, hd + 128, n, s);
             tend(2);
             PR_HIP(h, hipMemcpyAsync(hh, hd, 129 * sizeof(double), hipMemcpyDeviceToHost, s));
             PR_HIP(h, hipStreamSynchronize(s));
@@ -712,7 +839,7 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
         }
         for (int i = 0; i < mm; ++i) hh[192 + i] = y[i];
         PR_HIP(h, hipMemcpyAsync(hd + 192, hh + 192, mm * sizeof(double), hipMemcpyHostToDevice, s));
-        launch_gemv_small(V, n, mm, hd + 192, n, r, s);
+        launch_gemv_small(V, ldv, mm, hd + 192, n, r, s);
         tbeg();
         PR_TRY(precond(h, r, zt, t3));
         tend(0);

@@ -103,9 +103,14 @@ struct pr_handle_s {
     void* db_lp = nullptr;        // lane-ready low-precision database
     int64_t* dblp_off = nullptr;  // element offsets into db_lp per entry
     int32_t* db_exp = nullptr;    // FP16 scale exponents
-    float* db_f32 = nullptr;      // FP32 database (column-major per entry)
-    double* db_cm = nullptr;      // FP64 database column-major per entry (apply layout)
+    float* db_f32 = nullptr;      // FP32 database (row-major per entry)
     int apply_prec = PR_FP64;
+    int32_t* gdofs = nullptr;     // dof lists in grouped order
+    int64_t* goff = nullptr;      // grouped offsets (uneven sizes only)
+    int32_t* gphi = nullptr;      // entry of each grouped position
+    int64_t* dof_ptr = nullptr;   // dof -> grouped slots (deterministic scatter)
+    int32_t* dof_slots = nullptr;
+    void* Ybuf = nullptr;         // slot values of the deterministic scatter
 
     // solve workspace
     double* V = nullptr;
@@ -113,6 +118,8 @@ struct pr_handle_s {
     double* t1 = nullptr;
     double* t2 = nullptr;
     double* red = nullptr;        // reduction partials
+    unsigned int* gs_counter = nullptr;  // last-block ticket of the fused reductions
+    int64_t ldv = 0;              // leading dimension of the Krylov basis
     double* hd = nullptr;         // device scalars
     double* hh = nullptr;         // pinned host mirror
     int64_t ws_restart = -1;
@@ -182,34 +189,88 @@ void launch_batch_inverse(int p, int64_t count, const double* A, const int64_t* 
 void launch_batch_criterion(int p, int64_t count, int crit, const double* A, const double* B,
                             const double* X, double* d, hipStream_t s);
 
-struct Alg1Dev {
-    int32_t* status;               // int32[n_p]: 0 unresolved, 1 resolved
-    int32_t* ctrl;                 // int32[8], see k_dense.hip
-    unsigned long long* counters;  // uint64[8]: evals, exact, skipped; [4..5] window (double)
-    int32_t* cand;                 // int32[n_p] candidate list of a round
+// k_alg1.hip: Algorithm 1 by independent components (see that file)
+struct A1Dev {
+    int64_t n_p, n_comp;
+    const int64_t* ptr;
+    const double* tiles;
+    const int64_t* toff;      // null when uniform
+    int uniform_ps;
+    int32_t* ctl;             // int32[8]
+    unsigned long long* counters;  // [0] evaluations [1] exact singular values
+    const int32_t* cstart;    // int32[n_comp+1] first sorted position of each component
+    int32_t* next;            // int32[n_comp] lowest unresolved position
+    const int32_t* mem;       // patch at each sorted position (component, then id)
+    const int32_t* pos_comp;  // component of each sorted position
+    int32_t* status;          // int32[n_p] per sorted position
+    int32_t* rep_slot;        // int32[n_comp] temporary slot of the current entry
+    int32_t* rep_patch;       // int32[n_p] patch of each slot
+    int32_t* slot_of_patch;   // int32[n_p]
+    int32_t* repof;           // int32[n_p] entry patch of each patch
+    int32_t* active;          // int32[n_comp]
+    int32_t* cand;            // int32[n_p]
+    double* dbt;              // inverses by slot, stride doubles each
+    int64_t stride;
 };
-void launch_alg1_rounds(int rounds, const Alg1Dev& a, int crit, double eps, int64_t n_p,
-                        const int64_t* ptr, const double* tiles, const int64_t* toff,
-                        int uniform_ps, const double* keynorm, int32_t* phi, int32_t* reps,
-                        double* db, int64_t db_stride, hipStream_t s);
+void launch_a1_keys(int64_t n_p, const int64_t* ptr, const double* keynorm, uint64_t* keys,
+                    int32_t* vals, hipStream_t s);
+void launch_a1_comp_flags(int64_t n_p, const int32_t* sidx, const int64_t* ptr, const double* keynorm,
+                          int crit, double eps, int64_t* flag, hipStream_t s);
+void launch_a1_key2(int64_t n_p, const int64_t* flag, const int64_t* excl, const int32_t* sidx,
+                    uint64_t* key2, int32_t* val2, hipStream_t s);
+void launch_a1_cstart(int64_t n_p, int64_t n_comp, const uint64_t* key2, int32_t* pos_comp,
+                      int32_t* cstart, int32_t* next, hipStream_t s);
+void launch_a1_rounds(int rounds, const A1Dev& d, int crit, double eps, int max_ps, hipStream_t s);
+void launch_a1_finish(int64_t n_p, const int32_t* repof, int64_t* flags, int64_t* rank, int64_t* scr,
+                      int32_t* phi, int32_t* reps, hipStream_t s);
+void launch_a1_copy_db(int64_t m_p, const int32_t* reps, const int32_t* slot_of_patch, const int64_t* ptr,
+                       const double* dbt, double* db, int64_t stride, hipStream_t s);
 
 // k_apply.hip
-void launch_apply_vec_f64(const int32_t* order, int64_t count, const int32_t* phi,
-                          const int64_t* ptr, const int32_t* dofs, const double* db_cm,
-                          const int64_t* dboff, int uniform_ps, const double* W, double omega,
-                          const double* r, double* z, int group, hipStream_t s);
-void launch_apply_vec_f32(const int32_t* order, int64_t count, const int32_t* phi,
-                          const int64_t* ptr, const int32_t* dofs, const float* db_f32,
-                          const int64_t* dboff, int uniform_ps, const double* W, double omega,
-                          const double* r, double* z, int group, hipStream_t s);
-void launch_apply_mfma(int prec, const int32_t* items, int64_t n_items, const int32_t* order,
-                       const int64_t* ptr, const int32_t* dofs, const uint16_t* db_lp,
-                       const int64_t* dblp_off, const int32_t* db_exp, const double* W,
-                       double omega, const double* r, double* z, hipStream_t s);
+struct ApplyLaunch {
+    int64_t n, n_p;
+    // grouped geometry
+    const int32_t* gdofs;
+    const int64_t* goff;   // null when every patch has pst dofs
+    int pst;
+    const int32_t* gphi;
+    int maxp;
+    // database
+    const double* db;          // FP64 row-major
+    const float* db_f32;       // FP32 row-major
+    const int64_t* dboff;      // null: entry j at j * dbst
+    int64_t dbst;
+    const uint16_t* db_lp;     // lane-ready MFMA operands
+    const int64_t* dblp_off;
+    const int32_t* db_exp;
+    const int32_t* items;
+    int64_t n_items;
+    // vectors
+    const double* W;
+    double omega;
+    const double* r;
+    double* z;
+    // deterministic scatter
+    void* Y;
+    const int64_t* dof_ptr;
+    const int32_t* dof_slots;
+};
+// z (+)= omega M~^{-1} r.  Atomic mode accumulates into z (caller zeroes it);
+// two-stage mode overwrites z.
+void launch_apply(int prec, bool two_stage, const ApplyLaunch& a, hipStream_t s);
 void launch_convert_db(int prec, int64_t m_p, const double* db, const int64_t* dboff,
                        const int32_t* dbps, int uniform_ps, uint16_t* db_lp,
-                       const int64_t* dblp_off, int32_t* db_exp, float* db_f32, double* db_cm,
-                       hipStream_t s);
+                       const int64_t* dblp_off, int32_t* db_exp, float* db_f32, hipStream_t s);
+// grouped dof lists and the dof -> slot transpose
+void launch_group_gather(const int32_t* order, int64_t n_p, const int64_t* ptr, const int32_t* dofs,
+                         const int64_t* goff, int pst, int32_t* gdofs, int32_t* gphi,
+                         const int32_t* phi, hipStream_t s);
+void launch_group_sizes(const int32_t* order, int64_t n_p, const int64_t* ptr, int64_t* sizes,
+                        hipStream_t s);
+void launch_transpose_fill(const int32_t* gdofs, int64_t total, const int64_t* dof_ptr,
+                           int32_t* fill, int32_t* dof_slots, hipStream_t s);
+void launch_transpose_sort(int64_t n, const int64_t* dof_ptr, int32_t* dof_slots, hipStream_t s);
+void launch_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, hipStream_t s);
 
 // k_krylov.hip
 void launch_spmv(const int64_t* rowptr, const int32_t* col, const double* val, int64_t n,
@@ -224,3 +285,6 @@ void launch_axpy_dev(double* y, const double* x, double a, int64_t n, hipStream_
 void launch_gemv_small(const double* V, int64_t ldv, int nv, const double* coef, int64_t n,
                        double* out, hipStream_t s);
 void launch_zero(double* x, int64_t n, hipStream_t s);
+int gs_blocks(int64_t n);
+void launch_gs(int mode, const double* V, int64_t ldv, int nv, double* w, int64_t n, const double* c,
+               double* partial, unsigned int* counter, double* out, hipStream_t s);

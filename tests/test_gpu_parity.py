@@ -405,3 +405,50 @@ def test_apply_rejects_host_pointer():
         h.apply(r, z)
     assert e.value.code == pr.PR_ERR_HOST_POINTER
     h.close()
+
+
+# ---- deterministic (two-stage) scatter ----------------------------------------
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "fp16"])
+def test_deterministic_apply_repeats_bitwise_and_matches(problem, precision):
+    name, P = problem
+    h = pr.PatchRelax(P.A, P.ptr, P.dofs, algo="tolerance", eps=1e-8, precision=precision,
+                      deterministic=True, omega=0.8)
+    phi, reps = h.assignment()
+    cnt, W = O.cover_weights(P.n, P.ptr, P.dofs)
+    tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
+    Xdb = [O.factor_inverse(tiles[r]) for r in reps]
+    r = _rhs(P.n, 11)
+    rt = dt(r, torch.float64)
+    z1 = torch.full_like(rt, np.nan)
+    z2 = torch.full_like(rt, np.nan)
+    h.apply(rt, z1)
+    h.apply(rt, z2)
+    torch.cuda.synchronize()
+    a, b = z1.cpu().numpy(), z2.cpu().numpy()
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64)), name
+    if precision == "fp64":
+        z_o = O.apply_patch(P.ptr, P.dofs, W, Xdb, phi, r, 0.8)
+        kappa = max(np.linalg.cond(tiles[x]) for x in reps)
+        assert np.abs(a - z_o).max() / np.abs(z_o).max() <= max(1e-12, 8 * 32 * kappa * 2.2e-16)
+    else:
+        z_e, bound = O.apply_lowprec(P.ptr, P.dofs, W, Xdb, phi, r, 0.8, precision, return_bound=True)
+        ps = int(np.diff(P.ptr).max())
+        # FP32 slot values: one more rounding per slot than the atomic path
+        assert np.all(np.abs(a - z_e) <= (ps + 8) * 2.0 ** -24 * bound + 1e-300), name
+    h.close()
+
+
+def test_deterministic_solve_matches_atomic_iterations():
+    P = gen.q1_poisson_2d(32)
+    b = _rhs(P.n)
+    bt = dt(b, torch.float64)
+    its = []
+    for det in (False, True):
+        h = pr.PatchRelax(P.A, P.ptr, P.dofs, algo="tolerance", precision="bf16x3",
+                          deterministic=det)
+        x = torch.zeros_like(bt)
+        assert h.solve(bt, x, 1e-8) == pr.PR_OK
+        its.append(h.solve_info()["iters"])
+        h.close()
+    assert abs(its[0] - its[1]) <= 1
