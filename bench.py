@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--eps", type=float, default=1e-8, help="Algorithm 1 tolerance")
     ap.add_argument("--precision", default="bf16x3")
-    ap.add_argument("--scatter", default="atomic", choices=["atomic", "two-stage"],
+    ap.add_argument("--scatter", default="two-stage", choices=["atomic", "two-stage"],
                     help="FP64 atomics or the deterministic two-stage slot sum")
     ap.add_argument("--no-full", action="store_true", help="skip the full FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

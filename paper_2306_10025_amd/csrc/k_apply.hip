@@ -32,13 +32,17 @@ struct ApplyGeom {
     const int32_t* gphi;    // database entry of grouped position s
     const int64_t* dboff;   // database offsets (null: entry j at j * dbst)
     int64_t dbst;
+    const int32_t* stop;    // optional device flag: return at once when set
 };
+
+__device__ __forceinline__ bool skip(const ApplyGeom& g) { return g.stop && *g.stop; }
 
 template <typename TX, typename TA, typename TY, int MAXP, int G, bool TWO>
 __global__ __launch_bounds__(256) void k_apply_rows(int64_t count, ApplyGeom g, const TX* __restrict__ db,
                                                     const double* __restrict__ W, double omega,
                                                     const double* __restrict__ r,
                                                     double* __restrict__ z, TY* __restrict__ Y) {
+    if (skip(g)) return;
     const int a = threadIdx.x % G;
     const int64_t groups = (int64_t)gridDim.x * (blockDim.x / G);
     for (int64_t s = (int64_t)blockIdx.x * (blockDim.x / G) + threadIdx.x / G; s < count;
@@ -51,8 +55,19 @@ __global__ __launch_bounds__(256) void k_apply_rows(int64_t count, ApplyGeom g, 
         const int32_t gd = act ? g.gdofs[o + a] : 0;
         const TA rv = act ? (TA)r[gd] : (TA)0;
         TX xr[MAXP];
+        if (sizeof(TX) == 8 && (p & 1) == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0) {
+            // even p and an aligned matrix: rows start on 16-byte boundaries, load pairs
+            const double2* X2 = reinterpret_cast<const double2*>(X + (int64_t)a * p);
 #pragma unroll
-        for (int b = 0; b < MAXP; ++b) xr[b] = (act && b < p) ? X[(int64_t)a * p + b] : (TX)0;
+            for (int b = 0; b < MAXP / 2; ++b) {
+                const double2 v = (act && 2 * b < p) ? X2[b] : make_double2(0.0, 0.0);
+                xr[2 * b] = (TX)v.x;
+                xr[2 * b + 1] = (TX)v.y;
+            }
+        } else {
+#pragma unroll
+            for (int b = 0; b < MAXP; ++b) xr[b] = (act && b < p) ? X[(int64_t)a * p + b] : (TX)0;
+        }
         TA acc = 0;
 #pragma unroll
         for (int b = 0; b < MAXP; ++b) {
@@ -84,15 +99,33 @@ void run_rows(int64_t count, const ApplyGeom& g, const TX* db, const double* W, 
     else k_apply_rows<TX, TA, TY, 32, 32, TWO><<<nb, 256, 0, s>>>(count, g, db, W, omega, r, z, Y);
 }
 
-// z_i = omega W_i sum over the slots of dof i (fixed order)
+// z_i = omega W_i sum over the slots of dof i (ascending slot order)
 template <typename TY>
-__global__ void k_slot_sum(int64_t n, const int64_t* __restrict__ dof_ptr,
-                           const int32_t* __restrict__ dof_slots, const TY* __restrict__ Y,
-                           const double* __restrict__ W, double omega, double* __restrict__ z) {
+__global__ __launch_bounds__(256) void k_slot_sum(int64_t n, const int64_t* __restrict__ dof_ptr,
+                                                  const int32_t* __restrict__ dof_slots,
+                                                  const TY* __restrict__ Y, const double* __restrict__ W,
+                                                  double omega, double* __restrict__ z,
+                                                  const int32_t* __restrict__ stop) {
+    if (stop && *stop) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int64_t a = dof_ptr[i], b = dof_ptr[i + 1];
     double acc = 0.0;
-    for (int64_t t = dof_ptr[i]; t < dof_ptr[i + 1]; ++t) acc += (double)Y[dof_slots[t]];
+    if (b - a <= 8) {
+        // short list (the usual case): one round of independent loads
+        const int rem = (int)(b - a);
+        int32_t sl[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sl[u] = u < rem ? dof_slots[a + u] : 0;
+        TY yv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) yv[u] = u < rem ? Y[sl[u]] : (TY)0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (u < rem) acc += (double)yv[u];
+    } else {
+        for (int64_t t = a; t < b; ++t) acc += (double)Y[dof_slots[t]];
+    }
     z[i] = omega * W[i] * acc;
 }
 
@@ -139,6 +172,7 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
                                                     const double* __restrict__ W, double omega,
                                                     const double* __restrict__ r,
                                                     double* __restrict__ z, float* __restrict__ Y) {
+    if (skip(g)) return;
     constexpr bool FP16 = MODE == 1;
     constexpr bool SPLIT = MODE == 2;
     const int l = threadIdx.x & (PR_WAVE - 1);
@@ -319,7 +353,7 @@ __global__ __launch_bounds__(64) void k_convert_db(int prec, int64_t m_p, const 
 }  // namespace
 
 void launch_apply(int prec, bool two_stage, const ApplyLaunch& a, hipStream_t s) {
-    ApplyGeom g{a.gdofs, a.goff, a.pst, a.gphi, a.dboff, a.dbst};
+    ApplyGeom g{a.gdofs, a.goff, a.pst, a.gphi, a.dboff, a.dbst, a.stop};
     if (prec == PR_FP64) {
         if (two_stage) run_rows<double, double, double, true>(a.n_p, g, a.db, a.W, a.omega, a.r, a.z, (double*)a.Y, a.maxp, s);
         else run_rows<double, double, double, false>(a.n_p, g, a.db, a.W, a.omega, a.r, a.z, (double*)nullptr, a.maxp, s);
@@ -344,9 +378,9 @@ void launch_apply(int prec, bool two_stage, const ApplyLaunch& a, hipStream_t s)
     if (two_stage) {
         const unsigned nb = (unsigned)((a.n + 255) / 256);
         if (prec == PR_FP64)
-            k_slot_sum<double><<<nb, 256, 0, s>>>(a.n, a.dof_ptr, a.dof_slots, (const double*)a.Y, a.W, a.omega, a.z);
+            k_slot_sum<double><<<nb, 256, 0, s>>>(a.n, a.dof_ptr, a.dof_slots, (const double*)a.Y, a.W, a.omega, a.z, a.stop);
         else
-            k_slot_sum<float><<<nb, 256, 0, s>>>(a.n, a.dof_ptr, a.dof_slots, (const float*)a.Y, a.W, a.omega, a.z);
+            k_slot_sum<float><<<nb, 256, 0, s>>>(a.n, a.dof_ptr, a.dof_slots, (const float*)a.Y, a.W, a.omega, a.z, a.stop);
     }
 }
 

@@ -1,111 +1,87 @@
-// FP64 vector kernels of the outer GMRES solve: CSR sparse matrix-vector
-// product (optionally fused with a residual), block-partitioned multi-dot
-// products with a fixed reduction order (results do not depend on timing),
-// Gram-Schmidt updates, scaling and small basis combinations.
+// FP64 kernels of the outer GMRES solve (right preconditioning, Section 4):
+// sliced-ELL sparse matrix-vector product (optionally fused with a residual),
+// fused classical Gram-Schmidt passes with block-partitioned reductions in a
+// fixed order (results do not depend on timing), the Givens rotations and
+// the small triangular solve on the device, and basis combinations.
+//
+// Kernels that run inside an Arnoldi step take a `stop` flag (device int);
+// once the device-side Givens update has met the stopping test they return
+// at once, so the host can enqueue a whole restart cycle without waiting.
 #include "pr_internal.h"
 
 namespace {
 
-constexpr int kRedThreads = 256;
-constexpr int kMaxVec = 32;   // Krylov vectors per multidot call
+constexpr int kMaxVec = 32;   // Krylov vectors per Gram-Schmidt launch
+constexpr int kGsThreads = 256;
 
-// y = A x (b == nullptr) or y = b - A x; L lanes per row.
-template <int L>
-__global__ __launch_bounds__(256) void k_spmv(const int64_t* __restrict__ rowptr,
-                                              const int32_t* __restrict__ col,
-                                              const double* __restrict__ val, int64_t n,
-                                              const double* __restrict__ x,
-                                              const double* __restrict__ b, double* __restrict__ y) {
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / L;
-    const int sub = threadIdx.x % L;
-    if (row >= n) return;
-    const int64_t s = rowptr[row], e = rowptr[row + 1];
-    double acc = 0.0;
-    for (int64_t q = s + sub; q < e; q += L) acc = fma(val[q], x[col[q]], acc);
-#pragma unroll
-    for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
-    if (sub == 0) y[row] = b ? b[row] - acc : acc;
+__device__ __forceinline__ bool stopped(const int32_t* stop) { return stop && *stop; }
+
+// ---------------------------------------------------------------------------
+// Sliced ELLPACK copy of A (slices of 64 rows, one wavefront each; column-
+// major inside a slice, padded to the slice's longest row): every lane
+// streams its row's values and columns at unit stride across the wave.
+// ---------------------------------------------------------------------------
+__global__ void k_sell_len(const int64_t* __restrict__ rowptr, int64_t n, int64_t* __restrict__ slen) {
+    const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ns = (n + 63) / 64;
+    if (sl > ns) return;
+    if (sl == ns) {
+        slen[sl] = 0;
+        return;
+    }
+    int64_t m = 0;
+    for (int64_t r = sl * 64; r < sl * 64 + 64 && r < n; ++r) {
+        const int64_t l = rowptr[r + 1] - rowptr[r];
+        m = l > m ? l : m;
+    }
+    slen[sl] = 64 * m;
 }
 
-// partial[blk * nv + i] = sum over the block's rows of V_i * w ; then a
-// second kernel sums the block partials in fixed order.
-__global__ __launch_bounds__(kRedThreads) void k_multidot(const double* __restrict__ V, int64_t ldv,
-                                                          int nv, const double* __restrict__ w,
-                                                          int64_t n, double* __restrict__ partial) {
-    __shared__ double s_red[kRedThreads / PR_WAVE][kMaxVec];
-    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
-    const int64_t lo = (int64_t)blockIdx.x * per;
-    const int64_t hi = lo + per < n ? lo + per : n;
-    double acc[kMaxVec];
-#pragma unroll
-    for (int i = 0; i < kMaxVec; ++i) acc[i] = 0.0;
-    for (int64_t q = lo + threadIdx.x; q < hi; q += kRedThreads) {
-        const double wv = w[q];
-#pragma unroll
-        for (int i = 0; i < kMaxVec; ++i)
-            if (i < nv) acc[i] = fma(V[(int64_t)i * ldv + q], wv, acc[i]);
-    }
-    const int lane = threadIdx.x & (PR_WAVE - 1), wid = threadIdx.x / PR_WAVE;
-#pragma unroll
-    for (int i = 0; i < kMaxVec; ++i) {
-        if (i < nv) {
-            const double v = wave_sum(acc[i]);
-            if (lane == 0) s_red[wid][i] = v;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < nv) {
-        double t = 0.0;
-        for (int w2 = 0; w2 < kRedThreads / PR_WAVE; ++w2) t += s_red[w2][threadIdx.x];
-        partial[(int64_t)blockIdx.x * nv + threadIdx.x] = t;
+__global__ void k_sell_fill(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                            const double* __restrict__ val, int64_t n, const int64_t* __restrict__ soff,
+                            double* __restrict__ sval, int32_t* __restrict__ scol) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int64_t sl = r / 64, lane = r % 64;
+    const int64_t off = soff[sl];
+    const int64_t len = (soff[sl + 1] - off) / 64;
+    const int64_t a = rowptr[r], l = rowptr[r + 1] - a;
+    for (int64_t k = 0; k < len; ++k) {
+        const bool v = k < l;
+        sval[off + k * 64 + lane] = v ? val[a + k] : 0.0;
+        scol[off + k * 64 + lane] = v ? col[a + k] : (int32_t)r;
     }
 }
 
-__global__ void k_reduce_partials(const double* __restrict__ partial, int nblk, int nv,
-                                  double* __restrict__ out) {
-    const int i = threadIdx.x;
-    if (i >= nv) return;
-    double t = 0.0;
-    for (int b = 0; b < nblk; ++b) t += partial[(int64_t)b * nv + i];
-    out[i] = t;
-}
-
-// w += sign * sum_i h_i V_i
-__global__ void k_update(double* __restrict__ w, const double* __restrict__ V, int64_t ldv, int nv,
-                         const double* __restrict__ h, double sign, int64_t n) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    double acc = w[q];
-    for (int i = 0; i < nv; ++i) acc = fma(sign * h[i], V[(int64_t)i * ldv + q], acc);
-    w[q] = acc;
-}
-
-// dst = src / sqrt(denom[0])   (denom holds a squared norm)
-__global__ void k_scale(const double* __restrict__ src, double* __restrict__ dst,
-                        const double* __restrict__ denom, int64_t n) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    const double d = sqrt(denom[0]);
-    dst[q] = d > 0.0 ? src[q] / d : 0.0;
-}
-
-__global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, int64_t n) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < n) y[q] = fma(a, x[q], y[q]);
-}
-
-__global__ void k_gemv_small(const double* __restrict__ V, int64_t ldv, int nv,
-                             const double* __restrict__ c, int64_t n, double* __restrict__ out) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    double acc = 0.0;
-    for (int i = 0; i < nv; ++i) acc = fma(c[i], V[(int64_t)i * ldv + q], acc);
-    out[q] = acc;
-}
-
-__global__ void k_zero(double* x, int64_t n) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < n) x[q] = 0.0;
+// y = A x (b == nullptr) or y = b - A x; one thread per row, 64-row slices
+__global__ __launch_bounds__(256) void k_spmv_sell(const int64_t* __restrict__ soff,
+                                                   const double* __restrict__ sval,
+                                                   const int32_t* __restrict__ scol, int64_t n,
+                                                   const double* __restrict__ x,
+                                                   const double* __restrict__ b, double* __restrict__ y,
+                                                   const int32_t* __restrict__ stop) {
+    if (stopped(stop)) return;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;      // padding lanes of the last slice hold no entries
+    const int64_t sl = r / 64;
+    const int lane = (int)(r % 64);
+    const int64_t off = soff[sl];
+    const int len = (int)((soff[sl + 1] - off) / 64);
+    const double* vp = sval + off + lane;
+    const int32_t* cp = scol + off + lane;
+    double acc0 = 0.0, acc1 = 0.0;
+    int k = 0;
+    for (; k + 4 <= len; k += 4) {
+        const double v0 = vp[(k + 0) * 64], v1 = vp[(k + 1) * 64], v2 = vp[(k + 2) * 64], v3 = vp[(k + 3) * 64];
+        const int32_t c0 = cp[(k + 0) * 64], c1 = cp[(k + 1) * 64], c2 = cp[(k + 2) * 64], c3 = cp[(k + 3) * 64];
+        acc0 = fma(v0, x[c0], acc0);
+        acc1 = fma(v1, x[c1], acc1);
+        acc0 = fma(v2, x[c2], acc0);
+        acc1 = fma(v3, x[c3], acc1);
+    }
+    for (; k < len; ++k) acc0 = fma(vp[k * 64], x[cp[k * 64]], acc0);
+    const double acc = acc0 + acc1;
+    y[r] = b ? b[r] - acc : acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -113,22 +89,18 @@ __global__ void k_zero(double* x, int64_t n) {
 //   MODE 0: out_i = V_i . w                       (i < nv)
 //   MODE 1: w <- w - sum_i c_i V_i ; out_i = V_i . w   (each V_i loaded once)
 //   MODE 2: w <- w - sum_i c_i V_i ; out_0 = w . w
-// Each block reduces its rows; the last block to finish (ticket counter)
-// sums the block partials in a fixed order, so results do not depend on
-// timing.  The counter is returned to zero by that block.
+// Each block writes its row-range partial sums; k_gs_final adds the block
+// partials of one output per block in a fixed tree.
 // ---------------------------------------------------------------------------
-constexpr int kGsThreads = 256;
-
 template <int MODE>
 __global__ __launch_bounds__(kGsThreads) void k_gs(const double* __restrict__ V, int64_t ldv, int nv,
                                                    double* __restrict__ w, int64_t n,
                                                    const double* __restrict__ c,
                                                    double* __restrict__ partial,
-                                                   unsigned int* __restrict__ counter,
-                                                   double* __restrict__ out) {
+                                                   const int32_t* __restrict__ stop) {
+    if (stopped(stop)) return;
     constexpr int NO = (MODE == 2) ? 1 : kMaxVec;
     __shared__ double s_red[kGsThreads / PR_WAVE][kMaxVec];
-    __shared__ bool s_last;
     const int nout = (MODE == 2) ? 1 : nv;
     double cf[kMaxVec];
     if (MODE >= 1) {
@@ -178,117 +150,174 @@ __global__ __launch_bounds__(kGsThreads) void k_gs(const double* __restrict__ V,
         for (int w2 = 0; w2 < kGsThreads / PR_WAVE; ++w2) t += s_red[w2][threadIdx.x];
         partial[(int64_t)blockIdx.x * kMaxVec + threadIdx.x] = t;
     }
-    __threadfence();
+}
+
+// out[i] = sum over blocks of partial[b][i]; one block per output
+__global__ __launch_bounds__(256) void k_gs_final(const double* __restrict__ partial, int nblk,
+                                                  double* __restrict__ out,
+                                                  const int32_t* __restrict__ stop) {
+    if (stopped(stop)) return;
+    __shared__ double s_w[256 / PR_WAVE];
+    const int i = blockIdx.x;
+    double t = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) t += partial[(int64_t)b * kMaxVec + i];
+    t = wave_sum(t);
+    if ((threadIdx.x & (PR_WAVE - 1)) == 0) s_w[threadIdx.x / PR_WAVE] = t;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned int ticket = atomicAdd(counter, 1u);
-        s_last = (ticket == gridDim.x - 1);
+        double u = 0.0;
+        for (int w2 = 0; w2 < 256 / PR_WAVE; ++w2) u += s_w[w2];
+        out[i] = u;
     }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    // last block: out_i = sum_b partial[b][i], fixed partition and tree
-    double tot[NO];
-#pragma unroll
-    for (int i = 0; i < NO; ++i) tot[i] = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kGsThreads) {
-#pragma unroll
-        for (int i = 0; i < NO; ++i)
-            if (i < nout) tot[i] += partial[(int64_t)b * kMaxVec + i];
+}
+
+// dst = src / sqrt(denom[0])   (denom holds a squared norm)
+__global__ void k_scale(const double* __restrict__ src, double* __restrict__ dst,
+                        const double* __restrict__ denom, int64_t n, const int32_t* __restrict__ stop) {
+    if (stopped(stop)) return;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const double d = sqrt(denom[0]);
+    dst[q] = d > 0.0 ? src[q] / d : 0.0;
+}
+
+__global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, int64_t n) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) y[q] = fma(a, x[q], y[q]);
+}
+
+// out = sum_{i < nv} c_i V_i with nv read from the device
+__global__ void k_gemv_small(const double* __restrict__ V, int64_t ldv, const int32_t* __restrict__ nvp,
+                             const double* __restrict__ c, int64_t n, double* __restrict__ out) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int nv = *nvp;
+    double acc = 0.0;
+    for (int i = 0; i < nv; ++i) acc = fma(c[i], V[(int64_t)i * ldv + q], acc);
+    out[q] = acc;
+}
+
+__global__ void k_zero(double* x, int64_t n, const int32_t* __restrict__ stop) {
+    if (stopped(stop)) return;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) x[q] = 0.0;
+}
+
+// One Arnoldi column j: h = h1 + h2 (two Gram-Schmidt passes) and
+// h_{j+1} = ||w||; apply the previous rotations, form the new one, update
+// the residual vector g; stop when |g_{j+1}| <= tol_abs (or not finite) or
+// the iteration limit is reached.  Single thread: j <= 64.
+// gctl: [0] stop  [1] columns done this cycle
+__global__ void k_givens(int j, int m, const double* __restrict__ hd, double* __restrict__ R,
+                         double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
+                         double* __restrict__ est, int32_t* __restrict__ gctl, double tol_abs,
+                         int64_t iters_base, int64_t max_iters) {
+    if (threadIdx.x != 0 || gctl[0]) return;
+    for (int i = 0; i <= j; ++i) R[(int64_t)i * m + j] = hd[i] + hd[64 + i];
+    const double hn = sqrt(fmax(hd[128], 0.0));
+    for (int i = 0; i < j; ++i) {
+        const double a = R[(int64_t)i * m + j], b = R[(int64_t)(i + 1) * m + j];
+        R[(int64_t)i * m + j] = cs[i] * a + sn[i] * b;
+        R[(int64_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
     }
-#pragma unroll
-    for (int i = 0; i < NO; ++i) {
-        if (i < nout) {
-            const double t = wave_sum(tot[i]);
-            if (lane == 0) s_red[wid][i] = t;
-        }
+    const double a = R[(int64_t)j * m + j];
+    const double den = hypot(a, hn);
+    cs[j] = den > 0.0 ? a / den : 1.0;
+    sn[j] = den > 0.0 ? hn / den : 0.0;
+    R[(int64_t)j * m + j] = den;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    gctl[1] = j + 1;
+    est[0] = fabs(g[j + 1]);
+    if (!(fabs(g[j + 1]) > tol_abs) || iters_base + j + 1 >= max_iters || j + 1 >= m) gctl[0] = 1;
+}
+
+// y = R^{-1} g over the columns done (upper triangular back substitution)
+__global__ void k_trisolve(int m, const double* __restrict__ R, const double* __restrict__ g,
+                           double* __restrict__ y, const int32_t* __restrict__ gctl) {
+    if (threadIdx.x != 0) return;
+    const int mm = gctl[1];
+    for (int i = mm - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int k = i + 1; k < mm; ++k) t -= R[(int64_t)i * m + k] * y[k];
+        y[i] = t / R[(int64_t)i * m + i];
     }
-    __syncthreads();
-    if (threadIdx.x < nout) {
-        double t = 0.0;
-        for (int w2 = 0; w2 < kGsThreads / PR_WAVE; ++w2) t += s_red[w2][threadIdx.x];
-        out[threadIdx.x] = t;
-    }
-    if (threadIdx.x == 0) *counter = 0u;
 }
 
 inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
 
-void launch_spmv(const int64_t* rowptr, const int32_t* col, const double* val, int64_t n,
-                 const double* x, const double* b, double* y, int avg_nnz, hipStream_t s) {
-    if (n <= 0) return;
-    if (avg_nnz <= 6)
-        k_spmv<4><<<nb(n * 4, 256), 256, 0, s>>>(rowptr, col, val, n, x, b, y);
-    else if (avg_nnz <= 14)
-        k_spmv<8><<<nb(n * 8, 256), 256, 0, s>>>(rowptr, col, val, n, x, b, y);
-    else if (avg_nnz <= 40)
-        k_spmv<16><<<nb(n * 16, 256), 256, 0, s>>>(rowptr, col, val, n, x, b, y);
-    else
-        k_spmv<32><<<nb(n * 32, 256), 256, 0, s>>>(rowptr, col, val, n, x, b, y);
+void launch_sell_len(const int64_t* rowptr, int64_t n, int64_t* slen, hipStream_t s) {
+    const int64_t ns = (n + 63) / 64;
+    k_sell_len<<<nb(ns + 1, 256), 256, 0, s>>>(rowptr, n, slen);
 }
 
-int reduce_blocks(int64_t n) {
-    int64_t b = (n + 4095) / 4096;
-    if (b > 1024) b = 1024;
-    if (b < 1) b = 1;
-    return (int)b;
+void launch_sell_fill(const int64_t* rowptr, const int32_t* col, const double* val, int64_t n,
+                      const int64_t* soff, double* sval, int32_t* scol, hipStream_t s) {
+    k_sell_fill<<<nb(n, 256), 256, 0, s>>>(rowptr, col, val, n, soff, sval, scol);
 }
 
-void launch_multidot(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
-                     double* partial, double* out, hipStream_t s) {
-    const int nbk = reduce_blocks(n);
-    for (int base = 0; base < nv; base += kMaxVec) {
-        const int cnt = nv - base < kMaxVec ? nv - base : kMaxVec;
-        k_multidot<<<nbk, kRedThreads, 0, s>>>(V + (int64_t)base * ldv, ldv, cnt, w, n, partial);
-        k_reduce_partials<<<1, kMaxVec, 0, s>>>(partial, nbk, cnt, out + base);
-    }
-}
-
-void launch_update(double* w, const double* V, int64_t ldv, int nv, const double* h, double sign,
-                   int64_t n, hipStream_t s) {
-    if (n > 0 && nv > 0) k_update<<<nb(n, 256), 256, 0, s>>>(w, V, ldv, nv, h, sign, n);
-}
-
-void launch_scale(const double* src, double* dst, const double* denom, int64_t n, hipStream_t s) {
-    if (n > 0) k_scale<<<nb(n, 256), 256, 0, s>>>(src, dst, denom, n);
-}
-
-void launch_axpy_dev(double* y, const double* x, double a, int64_t n, hipStream_t s) {
-    if (n > 0) k_axpy<<<nb(n, 256), 256, 0, s>>>(y, x, a, n);
-}
-
-void launch_gemv_small(const double* V, int64_t ldv, int nv, const double* coef, int64_t n,
-                       double* out, hipStream_t s) {
-    if (n > 0) k_gemv_small<<<nb(n, 256), 256, 0, s>>>(V, ldv, nv, coef, n, out);
-}
-
-void launch_zero(double* x, int64_t n, hipStream_t s) {
-    if (n > 0) k_zero<<<nb(n, 256), 256, 0, s>>>(x, n);
+void launch_spmv_sell(const int64_t* soff, const double* sval, const int32_t* scol, int64_t n,
+                      const double* x, const double* b, double* y, hipStream_t s, const int32_t* stop) {
+    const int64_t ns = (n + 63) / 64;
+    k_spmv_sell<<<nb(ns * 64, 256), 256, 0, s>>>(soff, sval, scol, n, x, b, y, stop);
 }
 
 int gs_blocks(int64_t n) {
-    int64_t b = (n + 2047) / 2048;
+    int64_t b = (n + 511) / 512;          // >= 4 waves per SIMD on 256 CUs when n is large
     if (b > 1024) b = 1024;
     if (b < 1) b = 1;
     return (int)b;
 }
 
 // mode 0: out = V^T w ; mode 1: w -= V c, out = V^T w ; mode 2: w -= V c, out[0] = w.w
-// partial: gs_blocks(n) * 32 doubles; counter: one zeroed unsigned int.
+// partial: gs_blocks(n) * 32 doubles.
 void launch_gs(int mode, const double* V, int64_t ldv, int nv, double* w, int64_t n, const double* c,
-               double* partial, unsigned int* counter, double* out, hipStream_t s) {
+               double* partial, double* out, hipStream_t s, const int32_t* stop) {
     const int nbk = gs_blocks(n);
     for (int base = 0; base < nv || (nv == 0 && base == 0); base += kMaxVec) {
         const int cnt = nv - base < kMaxVec ? nv - base : kMaxVec;
         const double* Vb = V + (int64_t)base * ldv;
-        if (mode == 0)
-            k_gs<0><<<nbk, kGsThreads, 0, s>>>(Vb, ldv, cnt, w, n, c, partial, counter, out + base);
-        else if (mode == 1)
-            k_gs<1><<<nbk, kGsThreads, 0, s>>>(Vb, ldv, cnt, w, n, c + base, partial, counter, out + base);
-        else
-            k_gs<2><<<nbk, kGsThreads, 0, s>>>(Vb, ldv, cnt, w, n, c + base, partial, counter, out);
+        if (mode == 0) {
+            k_gs<0><<<nbk, kGsThreads, 0, s>>>(Vb, ldv, cnt, w, n, c, partial, stop);
+            k_gs_final<<<cnt, 256, 0, s>>>(partial, nbk, out + base, stop);
+        } else if (mode == 1) {
+            k_gs<1><<<nbk, kGsThreads, 0, s>>>(Vb, ldv, cnt, w, n, c + base, partial, stop);
+            k_gs_final<<<cnt, 256, 0, s>>>(partial, nbk, out + base, stop);
+        } else {
+            k_gs<2><<<nbk, kGsThreads, 0, s>>>(Vb, ldv, cnt, w, n, c + base, partial, stop);
+            k_gs_final<<<1, 256, 0, s>>>(partial, nbk, out, stop);
+        }
         if (nv == 0) break;
     }
+}
+
+void launch_scale(const double* src, double* dst, const double* denom, int64_t n, hipStream_t s,
+                  const int32_t* stop) {
+    if (n > 0) k_scale<<<nb(n, 256), 256, 0, s>>>(src, dst, denom, n, stop);
+}
+
+void launch_axpy_dev(double* y, const double* x, double a, int64_t n, hipStream_t s) {
+    if (n > 0) k_axpy<<<nb(n, 256), 256, 0, s>>>(y, x, a, n);
+}
+
+void launch_gemv_small(const double* V, int64_t ldv, const int32_t* nvp, const double* coef, int64_t n,
+                       double* out, hipStream_t s) {
+    if (n > 0) k_gemv_small<<<nb(n, 256), 256, 0, s>>>(V, ldv, nvp, coef, n, out);
+}
+
+void launch_zero(double* x, int64_t n, hipStream_t s, const int32_t* stop) {
+    if (n > 0) k_zero<<<nb(n, 256), 256, 0, s>>>(x, n, stop);
+}
+
+void launch_givens(int j, int m, const double* hd, double* R, double* cs, double* sn, double* g,
+                   double* est, int32_t* gctl, double tol_abs, int64_t iters_base, int64_t max_iters,
+                   hipStream_t s) {
+    k_givens<<<1, 64, 0, s>>>(j, m, hd, R, cs, sn, g, est, gctl, tol_abs, iters_base, max_iters);
+}
+
+void launch_trisolve(int m, const double* R, const double* g, double* y, const int32_t* gctl,
+                     hipStream_t s) {
+    k_trisolve<<<1, 64, 0, s>>>(m, R, g, y, gctl);
 }

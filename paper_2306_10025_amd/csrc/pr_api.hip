@@ -297,7 +297,7 @@ int run_group(pr_handle h) {
     int64_t start = 0;
     for (int64_t j = 0; j < m_p; ++j) {
         const int p = h->dbps_host[j];
-        const int nb = p <= 16 ? 16 : 32;
+        const int nb = p <= 16 ? 16 : 32;           // MFMA tile: 16x16x16 or 32x32x8
         for (int64_t t = 0; t < count[j]; t += nb) {
             items.push_back((int32_t)j);
             items.push_back((int32_t)(start + t));
@@ -348,10 +348,12 @@ int run_group(pr_handle h) {
 
 // z = omega M~^{-1} r, or z += omega M~^{-1} r when accumulate (tmp: n doubles,
 // used by the deterministic scatter, which overwrites its output)
-int apply_op(pr_handle h, const double* r, double* z, bool accumulate, double* tmp) {
+int apply_op(pr_handle h, const double* r, double* z, bool accumulate, double* tmp,
+             const int32_t* stop = nullptr) {
     hipStream_t s = h->stream;
     const bool two = h->prm.deterministic != 0;
     ApplyLaunch a{};
+    a.stop = stop;
     a.n = h->n;
     a.n_p = h->n_p;
     a.gdofs = h->gdofs;
@@ -379,7 +381,7 @@ int apply_op(pr_handle h, const double* r, double* z, bool accumulate, double* t
         launch_apply(h->apply_prec, true, a, s);
         if (accumulate) launch_axpy_dev(z, tmp, 1.0, h->n, s);
     } else {
-        if (!accumulate) launch_zero(z, h->n, s);
+        if (!accumulate) launch_zero(z, h->n, s, stop);
         a.z = z;
         launch_apply(h->apply_prec, false, a, s);
     }
@@ -387,12 +389,12 @@ int apply_op(pr_handle h, const double* r, double* z, bool accumulate, double* t
 }
 
 // e = `sweeps` damped smoothing steps from 0 applied to v (t3: 2n doubles scratch)
-int precond(pr_handle h, const double* v, double* e, double* t3) {
+int precond(pr_handle h, const double* v, double* e, double* t3, const int32_t* stop = nullptr) {
     hipStream_t s = h->stream;
-    PR_TRY(apply_op(h, v, e, false, nullptr));
+    PR_TRY(apply_op(h, v, e, false, nullptr, stop));
     for (int sw = 1; sw < h->prm.sweeps; ++sw) {
-        launch_spmv(h->rowptr, h->col, h->val, h->n, e, v, t3, (int)(h->nnz / std::max<int64_t>(h->n, 1)), s);
-        PR_TRY(apply_op(h, t3, e, true, t3 + h->n));
+        launch_spmv_sell(h->soff, h->sval, h->scol, h->n, e, v, t3, s, stop);
+        PR_TRY(apply_op(h, t3, e, true, t3 + h->n, stop));
     }
     return PR_OK;
 }
@@ -405,9 +407,9 @@ int ensure_workspace(pr_handle h, int m) {
     PR_TRY(dalloc(h, &h->w, n));
     PR_TRY(dalloc(h, &h->t1, n));
     PR_TRY(dalloc(h, &h->t2, 3 * n));   // preconditioned vector, sweep residual, scratch
-    PR_TRY(dalloc(h, &h->red, (size_t)std::max(reduce_blocks(n), gs_blocks(n)) * 32 + 64));
-    PR_TRY(dalloc(h, &h->gs_counter, 1));
-    PR_HIP(h, hipMemsetAsync(h->gs_counter, 0, sizeof(unsigned int), h->stream));
+    PR_TRY(dalloc(h, &h->red, (size_t)gs_blocks(n) * 32 + 64));
+    PR_TRY(dalloc(h, &h->gm, 8192));
+    PR_TRY(dalloc(h, &h->gctl, 4));
     PR_TRY(dalloc(h, &h->hd, 256));
     if (!h->hh) PR_HIP(h, hipHostMalloc((void**)&h->hh, 256 * sizeof(double), hipHostMallocDefault));
     h->ws_restart = m;
@@ -663,6 +665,23 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
     SETUP_HIP(hipStreamSynchronize(s));
     SETUP_HIP(hipGetLastError());
     const double t3 = now_s();
+    // sliced-ELL copy of A for the solve (64-row slices, padded per slice)
+    {
+        const int64_t ns = (h->n + 63) / 64;
+        int64_t* slen = nullptr;
+        int64_t* sscr = nullptr;
+        SETUP_TRY(dalloc(h, &slen, ns + 1));
+        SETUP_TRY(dalloc(h, &sscr, scan_scratch_elems(ns + 1) + 2));
+        SETUP_TRY(dalloc(h, &h->soff, ns + 1));
+        launch_sell_len(h->rowptr, h->n, slen, s);
+        launch_exclusive_scan_i64(slen, h->soff, ns + 1, sscr, s);
+        int64_t stot = 0;
+        SETUP_HIP(hipMemcpyAsync(&stot, h->soff + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        SETUP_HIP(hipStreamSynchronize(s));
+        SETUP_TRY(dalloc(h, &h->sval, stot));
+        SETUP_TRY(dalloc(h, &h->scol, stot));
+        launch_sell_fill(h->rowptr, h->col, h->val, h->n, h->soff, h->sval, h->scol, s);
+    }
     SETUP_TRY(run_group(h));
     const double t4 = now_s();
 
@@ -743,7 +762,6 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
     const int m = h->prm.gmres_restart;
     const int64_t n = h->n;
     PR_TRY(ensure_workspace(h, m));
-    const int avg = (int)(h->nnz / std::max<int64_t>(n, 1));
     double* V = h->V;
     double* w = h->w;
     double* r = h->t1;
@@ -751,6 +769,17 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
     double* t3 = h->t2 + n;
     double* hd = h->hd;
     double* hh = h->hh;
+    const int64_t ldv = h->ldv;
+    double* red = h->red;
+    // device GMRES state: R ((m+1) x m), rotations, residual vector g, y, estimate
+    double* R = h->gm;
+    double* cs = R + (int64_t)(m + 1) * m;
+    double* sn = cs + m;
+    double* g = sn + m;
+    double* y = g + m + 1;
+    double* est_d = y + m;
+    int32_t* gctl = h->gctl;
+    int32_t* gctl_h = reinterpret_cast<int32_t*>(hh + 240);   // pinned mirror of gctl
 
     auto sync_read = [&](int count) -> int {
         PR_HIP(h, hipMemcpyAsync(hh, hd, count * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -758,10 +787,7 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
         return PR_OK;
     };
     // ||b||
-    const int64_t ldv = h->ldv;
-    double* red = h->red;
-    unsigned int* ctr = h->gs_counter;
-    launch_gs(0, b, n, 1, const_cast<double*>(b), n, nullptr, red, ctr, hd, s);
+    launch_gs(0, b, n, 1, const_cast<double*>(b), n, nullptr, red, hd, s);
     PR_TRY(sync_read(1));
     const double bnorm = std::sqrt(hh[0]);
     launch_zero(x, n, s);
@@ -773,81 +799,59 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
         return PR_OK;
     }
     PR_HIP(h, hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
     int64_t iters = 0, cycles = 0;
     double relres = 1.0, est = 1.0;
     const int64_t maxit = h->prm.max_iters;
     for (;;) {
-        launch_gs(0, r, n, 1, r, n, nullptr, red, ctr, hd, s);
+        // true residual norm; one host wait per restart cycle
+        launch_gs(0, r, n, 1, r, n, nullptr, red, hd, s);
         PR_TRY(sync_read(1));
+        if (cycles > 0) {
+            iters += gctl_h[1];
+            est = hh[239] / bnorm;
+        }
         const double beta = std::sqrt(hh[0]);
         relres = beta / bnorm;
         if (!std::isfinite(beta)) return pr_fail(h, PR_ERR_NONFINITE, "non-finite residual");
         if (beta <= tol * bnorm || iters >= maxit) break;
         ++cycles;
+        // cycle start: g = (beta, 0, ...), stop = 0, V_0 = r / beta
+        for (int i = 0; i <= m; ++i) hh[128 + i] = (i == 0) ? beta : 0.0;
+        PR_HIP(h, hipMemcpyAsync(g, hh + 128, (m + 1) * sizeof(double), hipMemcpyHostToDevice, s));
+        PR_HIP(h, hipMemsetAsync(gctl, 0, 4 * sizeof(int32_t), s));
         launch_scale(r, V, hd, n, s);
-        std::fill(H.begin(), H.end(), 0.0);
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
-        int mm = 0;
         for (int j = 0; j < m; ++j) {
             double* vj = V + (int64_t)j * ldv;
             tbeg();
-            PR_TRY(precond(h, vj, zt, t3));
+            PR_TRY(precond(h, vj, zt, t3, gctl));
             tend(0);
             tbeg();
-            launch_spmv(h->rowptr, h->col, h->val, n, zt, nullptr, w, avg, s);
+            launch_spmv_sell(h->soff, h->sval, h->scol, n, zt, nullptr, w, s, gctl);
             tend(1);
-            ++iters;
-            // classical Gram-Schmidt, twice
-            tbeg();
+            // classical Gram-Schmidt, twice:
             // pass 1: h1 = V^T w ; pass 2: w -= V h1, h2 = V^T w ;
             // pass 3: w -= V h2, ||w||^2 ; then v_{j+1} = w / ||w||
-            launch_gs(0, V, ldv, j + 1, w, n, nullptr, red, ctr, hd, s);
-            launch_gs(1, V, ldv, j + 1, w, n, hd, red, ctr, hd + 64, s);
-            launch_gs(2, V, ldv, j + 1, w, n, hd + 64, red, ctr, hd + 128, s);
-            launch_scale(w, V + (int64_t)(j + 1) * ldv, hd + 128, n, s);
+            tbeg();
+            launch_gs(0, V, ldv, j + 1, w, n, nullptr, red, hd, s, gctl);
+            launch_gs(1, V, ldv, j + 1, w, n, hd, red, hd + 64, s, gctl);
+            launch_gs(2, V, ldv, j + 1, w, n, hd + 64, red, hd + 128, s, gctl);
+            launch_scale(w, V + (int64_t)(j + 1) * ldv, hd + 128, n, s, gctl);
             tend(2);
-            PR_HIP(h, hipMemcpyAsync(hh, hd, 129 * sizeof(double), hipMemcpyDeviceToHost, s));
-            PR_HIP(h, hipStreamSynchronize(s));
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[64 + i];
-            const double hn = std::sqrt(std::max(hh[128], 0.0));
-            H[(size_t)(j + 1) * m + j] = hn;
-            for (int i = 0; i < j; ++i) {
-                const double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
-                H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
-                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
-            }
-            const double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
-            const double den = std::hypot(a, bb);
-            cs[j] = den > 0.0 ? a / den : 1.0;
-            sn[j] = den > 0.0 ? bb / den : 0.0;
-            H[(size_t)j * m + j] = den;
-            H[(size_t)(j + 1) * m + j] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            mm = j + 1;
-            est = std::fabs(g[j + 1]) / bnorm;
-            if (!std::isfinite(est)) return pr_fail(h, PR_ERR_NONFINITE, "non-finite Arnoldi value");
-            if (std::fabs(g[j + 1]) <= tol * bnorm || iters >= maxit) break;
+            // rotations and the stopping test on the device
+            launch_givens(j, m, hd, R, cs, sn, g, est_d, gctl, tol * bnorm, iters, maxit, s);
         }
-        // y = H^{-1} g (upper triangular), u = V y, x += M(u)
-        for (int i = mm - 1; i >= 0; --i) {
-            double t = g[i];
-            for (int k = i + 1; k < mm; ++k) t -= H[(size_t)i * m + k] * y[k];
-            y[i] = t / H[(size_t)i * m + i];
-        }
-        for (int i = 0; i < mm; ++i) hh[192 + i] = y[i];
-        PR_HIP(h, hipMemcpyAsync(hd + 192, hh + 192, mm * sizeof(double), hipMemcpyHostToDevice, s));
-        launch_gemv_small(V, ldv, mm, hd + 192, n, r, s);
+        // y = R^{-1} g over the columns done, u = V y, x += M(u), r = b - A x
+        launch_trisolve(m, R, g, y, gctl, s);
+        launch_gemv_small(V, ldv, gctl + 1, y, n, r, s);
         tbeg();
         PR_TRY(precond(h, r, zt, t3));
         tend(0);
         launch_axpy_dev(x, zt, 1.0, n, s);
         tbeg();
-        launch_spmv(h->rowptr, h->col, h->val, n, x, b, r, avg, s);
+        launch_spmv_sell(h->soff, h->sval, h->scol, n, x, b, r, s);
         tend(1);
-        PR_HIP(h, hipStreamSynchronize(s));   // hh + 192 is reused next cycle
+        PR_HIP(h, hipMemcpyAsync(gctl_h, gctl, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        PR_HIP(h, hipMemcpyAsync(hh + 239, est_d, sizeof(double), hipMemcpyDeviceToHost, s));
     }
     PR_HIP(h, hipStreamSynchronize(s));
     PR_HIP(h, hipGetLastError());

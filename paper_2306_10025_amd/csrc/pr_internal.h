@@ -76,6 +76,11 @@ struct pr_handle_s {
     int64_t* pptr = nullptr;
     int32_t* pdofs = nullptr;
 
+    // sliced-ELL copy of A for the solve's SpMV (64-row slices)
+    int64_t* soff = nullptr;
+    double* sval = nullptr;
+    int32_t* scol = nullptr;
+
     // Section 2 objects
     int32_t* cnt = nullptr;
     double* W = nullptr;
@@ -118,7 +123,8 @@ struct pr_handle_s {
     double* t1 = nullptr;
     double* t2 = nullptr;
     double* red = nullptr;        // reduction partials
-    unsigned int* gs_counter = nullptr;  // last-block ticket of the fused reductions
+    double* gm = nullptr;         // device GMRES state: R, cs, sn, g, y, estimate
+    int32_t* gctl = nullptr;      // device GMRES control: stop flag, columns done
     int64_t ldv = 0;              // leading dimension of the Krylov basis
     double* hd = nullptr;         // device scalars
     double* hh = nullptr;         // pinned host mirror
@@ -254,6 +260,7 @@ struct ApplyLaunch {
     void* Y;
     const int64_t* dof_ptr;
     const int32_t* dof_slots;
+    const int32_t* stop;       // optional device flag: skip the work when set
 };
 // z (+)= omega M~^{-1} r.  Atomic mode accumulates into z (caller zeroes it);
 // two-stage mode overwrites z.
@@ -272,19 +279,24 @@ void launch_transpose_fill(const int32_t* gdofs, int64_t total, const int64_t* d
 void launch_transpose_sort(int64_t n, const int64_t* dof_ptr, int32_t* dof_slots, hipStream_t s);
 void launch_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, hipStream_t s);
 
-// k_krylov.hip
-void launch_spmv(const int64_t* rowptr, const int32_t* col, const double* val, int64_t n,
-                 const double* x, const double* b, double* y, int avg_nnz, hipStream_t s);
-int reduce_blocks(int64_t n);
-void launch_multidot(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
-                     double* partial, double* out, hipStream_t s);
-void launch_update(double* w, const double* V, int64_t ldv, int nv, const double* h,
-                   double sign, int64_t n, hipStream_t s);
-void launch_scale(const double* src, double* dst, const double* denom, int64_t n, hipStream_t s);
+// k_krylov.hip  (kernels with a `stop` argument return at once when *stop != 0)
+void launch_scale(const double* src, double* dst, const double* denom, int64_t n, hipStream_t s,
+                  const int32_t* stop = nullptr);
 void launch_axpy_dev(double* y, const double* x, double a, int64_t n, hipStream_t s);
-void launch_gemv_small(const double* V, int64_t ldv, int nv, const double* coef, int64_t n,
+void launch_gemv_small(const double* V, int64_t ldv, const int32_t* nvp, const double* coef, int64_t n,
                        double* out, hipStream_t s);
-void launch_zero(double* x, int64_t n, hipStream_t s);
+void launch_zero(double* x, int64_t n, hipStream_t s, const int32_t* stop = nullptr);
 int gs_blocks(int64_t n);
+void launch_sell_len(const int64_t* rowptr, int64_t n, int64_t* slen, hipStream_t s);
+void launch_sell_fill(const int64_t* rowptr, const int32_t* col, const double* val, int64_t n,
+                      const int64_t* soff, double* sval, int32_t* scol, hipStream_t s);
+void launch_spmv_sell(const int64_t* soff, const double* sval, const int32_t* scol, int64_t n,
+                      const double* x, const double* b, double* y, hipStream_t s,
+                      const int32_t* stop = nullptr);
 void launch_gs(int mode, const double* V, int64_t ldv, int nv, double* w, int64_t n, const double* c,
-               double* partial, unsigned int* counter, double* out, hipStream_t s);
+               double* partial, double* out, hipStream_t s, const int32_t* stop = nullptr);
+void launch_givens(int j, int m, const double* hd, double* R, double* cs, double* sn, double* g,
+                   double* est, int32_t* gctl, double tol_abs, int64_t iters_base, int64_t max_iters,
+                   hipStream_t s);
+void launch_trisolve(int m, const double* R, const double* g, double* y, const int32_t* gctl,
+                     hipStream_t s);
