@@ -144,7 +144,7 @@ typedef struct {
     int64_t crit_pruned;     /* pairs skipped by the certified norm bound */
     int64_t crit_exact;      /* evaluations that needed the exact singular value */
     int64_t alg1_rounds;     /* Algorithm 1 rounds (one per database entry) */
-    int64_t kmeans_iters;    /* Algorithm 2 assignment passes (all groups) */
+    int64_t kmeans_iters;    /* Algorithm 2: most assignment passes of any group */
     int64_t empty_events;    /* Algorithm 2 empty clusters */
     int64_t n_items;         /* grouped apply work items */
     int64_t bytes_tiles, bytes_db, bytes_db_lowp, bytes_index;
@@ -166,7 +166,27 @@ void pr_params_default(pr_params* p);
  * Errors: INVALID_ARG, HOST_POINTER, BAD_CSR, BAD_PATCH_PTR,
  * DOF_OUT_OF_RANGE, DUP_DOF_IN_PATCH, UNCOVERED_DOF, SINGULAR_PATCH (the
  * patch id is in pr_last_error), NONFINITE, OOM, HIP, UNSUPPORTED (a patch
- * with more than 32 dofs).  Synchronises the stream. */
+ * with more than 32 dofs).  Synchronises the stream.
+ *
+ * Clustering algorithms (Algorithm 2, Section 3.2): patches are grouped by
+ * size and, with partition_bc = 1, by boundary key (PR_ALGO_BOOTSTRAP never
+ * partitions); m_target clusters are apportioned to the groups by largest
+ * remainders (at least one per group; INVALID_ARG unless groups <= m_target
+ * <= n_p); the initial centres are drawn per group, groups in ascending
+ * (size, key) order, by a partial Fisher-Yates shuffle of the group's
+ * members in ascending patch id, driven by one SplitMix64 stream seeded with
+ * `seed` (position i takes the member at i + (u mod (L - i))).
+ * PR_ALGO_BOOTSTRAP starts from Algorithm 1's entries (criterion, eps).  A
+ * pass assigns every patch of a still-active group to the centre of least
+ * distance, keeping its current centre if that lies in the tie band
+ * d <= d_min (1 + tie_rel) + tie_rel s (s = 1 for the spectral distance,
+ * sum |A_i| for the l1 distance), else the lowest centre in it; a group stops
+ * when no assignment changes or after kmeans_max_iter passes, otherwise its
+ * centres are updated (entrywise mean in ascending member id, or for
+ * VARMIN/BOOTSTRAP the member nearest the mean in Frobenius norm, lowest id
+ * among squared distances <= min (1 + tie_rel) + tie_rel^2 ||mean||_F^2); an
+ * empty cluster keeps its centre.  Singular centre:
+ * SINGULAR_PATCH.  The criterion field is used only by Algorithm 1. */
 int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_handle* out);
 
 /* z = omega * M~^{-1} r (Eq.(3); Eq.(1) for PR_ALGO_FULL) for one smoothing
@@ -197,6 +217,9 @@ int pr_get_weights(pr_handle h, double* W);
 int pr_get_boundary_keys(pr_handle h, uint32_t* keys);
 /* X: double[p_j * p_j], the FP64 inverse of database entry j, row-major. */
 int pr_get_rep_inverse(pr_handle h, int64_t j, double* X);
+/* B: double[p_j * p_j], the matrix of database entry j (a patch matrix, or
+ * the cluster mean of Eq.(6)), row-major. */
+int pr_get_entry_matrix(pr_handle h, int64_t j, double* B);
 
 /* Use another stream for later calls on h (NULL = default stream). */
 int pr_set_stream(pr_handle h, void* hip_stream);

@@ -13,16 +13,20 @@ Readings taken where the paper is silent (each also listed in the design notes):
 * Algorithm 2's initial ``randperm(n_p, m_p)`` draws m_p distinct patches as
   initial representatives; the draw is a partial Fisher-Yates shuffle driven by
   SplitMix64 so that any implementation can reproduce it bit for bit;
-* argmin ties: a relative band tie_rel around the minimum; the current
-  assignment is kept if it lies in the band, else the lowest index in it;
+* argmin ties: a band around the minimum, d_j <= d_min (1 + tie) + tie s_i,
+  with s_i = 1 for the spectral distance (a dimensionless quantity) and
+  s_i = sum |A_i| for the entrywise l1 distance; the absolute term makes
+  distances at rounding level (a patch equal to a centre up to rounding) tie
+  instead of being ordered by rounding noise; the current assignment is kept
+  if it lies in the band, else the lowest index in it;
 * an empty cluster keeps its previous centre;
 * the loop stops when no assignment changes or after max_iter passes; the
   final database is the one used in the last assignment pass;
 * "the member which minimises the in-cluster variance" is the member whose
   matrix is nearest (Frobenius) to the entrywise cluster mean, which equals
-  argmin_m sum_k ||A_k - A_m||_F^2; members within the relative tie band
-  of the smallest distance count as tied and the lowest patch id wins (a
-  two-member cluster is always an exact tie);
+  argmin_m sum_k ||A_k - A_m||_F^2; members whose squared distance lies
+  within delta_min (1 + tie) + tie^2 ||mean||_F^2 count as tied and the
+  lowest patch id wins (a two-member cluster is always an exact tie);
 * apportionment: largest-remainder method in exact integer arithmetic, with
   at least one cluster per non-empty group and at most the group size.
 
@@ -128,11 +132,20 @@ def alg1_invariants_hold(tiles_of, phi, reps, eps, crit, sample, X_of=None):
 def partition_groups(tiles, partition=True):
     """Boundary partitioning (Section 3.2): group patches whose boundary
     conditions sit in the same local rows; groups in ascending key order (the
-    interior, key 0, first); members in ascending patch id."""
-    if not partition:
-        return [(0, np.arange(len(tiles), dtype=np.int64))]
-    keys = np.array([boundary_mask(t) for t in tiles], dtype=np.int64)
-    return [(int(k), np.flatnonzero(keys == k)) for k in np.unique(keys)]
+    interior, key 0, first); members in ascending patch id.
+
+    Patches of different sizes are never compared (a matrix of another size
+    is no candidate, remark in Section 2), so groups are first split by size:
+    the group key is (size, boundary mask), or the size alone without
+    partitioning.  With one patch size this is the partition of Section 3.2."""
+    sizes = np.array([t.shape[0] for t in tiles], dtype=np.int64)
+    if partition:
+        masks = np.array([boundary_mask(t) for t in tiles], dtype=np.int64)
+    else:
+        masks = np.zeros(len(tiles), dtype=np.int64)
+    pairs = sorted(set(zip(sizes.tolist(), masks.tolist())))
+    return [((int(s), int(m)) if partition else int(s),
+             np.flatnonzero((sizes == s) & (masks == m))) for s, m in pairs]
 
 
 def apportion(sizes, m_total):
@@ -195,8 +208,8 @@ def kmeans(tiles, m_p, variant="spectral", seed=5, max_iter=100, partition=True,
     if variant == "bootstrap":
         if init_reps is None:
             raise ValueError("bootstrap needs Algorithm 1's representatives")
-        groups = [(0, np.arange(len(tiles), dtype=np.int64))]
-        starts = [list(int(r) for r in init_reps)]
+        groups = partition_groups(tiles, partition=False)
+        starts = [[int(r) for r in init_reps if tiles[int(r)].shape[0] == key] for key, _ in groups]
         upd = "varmin"
         crit = "spectral"
     else:
@@ -224,7 +237,8 @@ def kmeans(tiles, m_p, variant="spectral", seed=5, max_iter=100, partition=True,
             for t, i in enumerate(members):
                 d = np.array([_dist(crit, tiles[i], B[j], X[j]) for j in range(len(B))])
                 dmin = d.min()
-                band = np.flatnonzero(d <= dmin * (1.0 + tie_rel))
+                scale = 1.0 if crit == "spectral" else float(np.sum(np.abs(tiles[i])))
+                band = np.flatnonzero(d <= dmin * (1.0 + tie_rel) + tie_rel * scale)
                 if loc[t] in band:
                     continue
                 loc[t] = band[0]
@@ -245,7 +259,8 @@ def kmeans(tiles, m_p, variant="spectral", seed=5, max_iter=100, partition=True,
                     rp[j] = -1
                 else:
                     dist = np.array([np.sum((tiles[k] - mean) ** 2) for k in mem])
-                    near = np.flatnonzero(dist <= dist.min() * (1.0 + tie_rel))
+                    floor = tie_rel * tie_rel * float(np.sum(mean * mean))
+                    near = np.flatnonzero(dist <= dist.min() * (1.0 + tie_rel) + floor)
                     m = int(mem[near[0]])          # lowest patch id in the tie band
                     B[j] = tiles[m].copy()
                     rp[j] = m

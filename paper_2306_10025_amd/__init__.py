@@ -91,6 +91,7 @@ _SIGS = {
     "pr_get_weights": (c_int, [c_void_p, c_void_p]),
     "pr_get_boundary_keys": (c_int, [c_void_p, c_void_p]),
     "pr_get_rep_inverse": (c_int, [c_void_p, c_int64, c_void_p]),
+    "pr_get_entry_matrix": (c_int, [c_void_p, c_int64, c_void_p]),
     "pr_set_stream": (c_int, [c_void_p, c_void_p]),
     "pr_validate_host": (c_int, [POINTER(pr_csr), POINTER(pr_patches)]),
     "pr_destroy": (None, [c_void_p]),
@@ -242,6 +243,12 @@ def pr_get_rep_inverse(h, j, p):
     return X.reshape(p, p)
 
 
+def pr_get_entry_matrix(h, j, p):
+    B = np.zeros(p * p, dtype=np.float64)
+    _check(lib().pr_get_entry_matrix(h, j, B.ctypes.data_as(c_void_p)), h)
+    return B.reshape(p, p)
+
+
 def pr_destroy(h):
     if h:
         lib().pr_destroy(h)
@@ -321,6 +328,9 @@ class PatchRelax:
 
     def rep_inverse(self, j, p):
         return pr_get_rep_inverse(self.h, j, p)
+
+    def entry_matrix(self, j, p):
+        return pr_get_entry_matrix(self.h, j, p)
 
     def close(self):
         if self.h:

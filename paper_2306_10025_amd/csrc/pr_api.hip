@@ -10,6 +10,8 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <numeric>
+#include <unordered_map>
 
 namespace {
 
@@ -227,6 +229,284 @@ int run_full(pr_handle h) {
     }
     h->dboff_host[n_p] = off;
     h->stats.crit_evals = 0;
+    return PR_OK;
+}
+
+// ---- Algorithm 2 and its variants (Section 3.2) ----------------------------
+
+// SplitMix64 (Steele, Lea and Flood, 2014): the state advances by the golden
+// gamma, the output is two xor-shift-multiply rounds and a final xor-shift.
+uint64_t splitmix64_next(uint64_t& state) {
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Clusters per group in proportion to the group sizes: floor shares, the
+// remaining seats to the largest remainders (lower group on ties), then every
+// empty group takes one seat from the fullest group (lower group on ties).
+bool apportion_clusters(const std::vector<int64_t>& sizes, int64_t m_total, std::vector<int64_t>& out) {
+    const int64_t N = std::accumulate(sizes.begin(), sizes.end(), (int64_t)0);
+    const int64_t G = (int64_t)sizes.size();
+    if (m_total < G || m_total > N) return false;
+    out.assign(G, 0);
+    std::vector<int64_t> rem(G);
+    int64_t used = 0;
+    for (int64_t g = 0; g < G; ++g) {
+        const __int128 prod = (__int128)m_total * sizes[g];
+        out[g] = (int64_t)(prod / N);
+        rem[g] = (int64_t)(prod % N);
+        used += out[g];
+    }
+    std::vector<int64_t> ord(G);
+    std::iota(ord.begin(), ord.end(), (int64_t)0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return rem[a] > rem[b]; });
+    for (int64_t t = 0; t < m_total - used; ++t) out[ord[t]] += 1;
+    for (;;) {
+        int64_t g0 = -1;
+        for (int64_t g = 0; g < G && g0 < 0; ++g)
+            if (out[g] == 0) g0 = g;
+        if (g0 < 0) break;
+        int64_t donor = 0;
+        for (int64_t g = 1; g < G; ++g)
+            if (out[g] > out[donor]) donor = g;
+        out[donor] -= 1;
+        out[g0] += 1;
+    }
+    return true;
+}
+
+int run_kmeans(pr_handle h) {
+    hipStream_t s = h->stream;
+    const int64_t n_p = h->n_p;
+    const int algo = h->prm.algo;
+    const bool boot = algo == PR_ALGO_BOOTSTRAP;
+    const int64_t stride = (int64_t)h->max_ps * h->max_ps;
+    const int crit = (algo == PR_ALGO_KMEANS_ENTRYWISE) ? PR_CRIT_L1 : PR_CRIT_SPECTRAL;
+    const int medoid = (algo == PR_ALGO_VARMIN || boot) ? 1 : 0;
+    const double tie = h->prm.tie_rel;
+    const int max_iter = h->prm.kmeans_max_iter;
+    const int ups = h->uniform ? h->max_ps : 0;
+    const int64_t* toff = h->uniform ? nullptr : h->toff;
+
+    std::vector<int32_t> boot_reps, boot_ps;
+    int64_t boot_evals = 0, boot_exact = 0, boot_pruned = 0;
+    if (boot) {
+        // initial database from Algorithm 1
+        PR_TRY(run_alg1(h));
+        boot_reps = h->reps_host;
+        boot_ps = h->dbps_host;
+        boot_evals = h->stats.crit_evals;
+        boot_exact = h->stats.crit_exact;
+        boot_pruned = h->stats.crit_pruned;
+    }
+
+    // 1. groups: (size, boundary key), or size alone; members in ascending id
+    const int partition = (!boot && h->prm.partition_bc) ? 1 : 0;
+    const int64_t N = next_pow2(n_p);
+    uint64_t *keys = nullptr, *kscr = nullptr;
+    int32_t *vals = nullptr, *vscr = nullptr, *pg = nullptr, *gp = nullptr;
+    int64_t *flag = nullptr, *excl = nullptr, *scr = nullptr, *gstart = nullptr;
+    PR_TRY(dalloc(h, &keys, n_p));
+    PR_TRY(dalloc(h, &kscr, N));
+    PR_TRY(dalloc(h, &vals, n_p));
+    PR_TRY(dalloc(h, &vscr, N));
+    PR_TRY(dalloc(h, &flag, n_p + 1));
+    PR_TRY(dalloc(h, &excl, n_p + 1));
+    PR_TRY(dalloc(h, &scr, scan_scratch_elems(n_p + 1) + 2));
+    PR_TRY(dalloc(h, &pg, n_p));
+    PR_TRY(dalloc(h, &gstart, n_p + 1));
+    PR_TRY(dalloc(h, &gp, n_p));
+    launch_km_key1(n_p, h->pptr, h->keys, partition, keys, vals, s);
+    launch_sort_pairs(keys, vals, n_p, kscr, vscr, s);
+    launch_km_flags(n_p, keys, flag, s);
+    launch_exclusive_scan_i64(flag, excl, n_p + 1, scr, s);
+    launch_km_gid(n_p, keys, vals, flag, excl, pg, gstart, gp, s);
+    int64_t G = 0;
+    PR_HIP(h, hipMemcpyAsync(&G, excl + n_p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    PR_HIP(h, hipStreamSynchronize(s));
+    std::vector<int64_t> gstart_h(G + 1);
+    std::vector<int32_t> gp_h(G);
+    PR_HIP(h, hipMemcpyAsync(gstart_h.data(), gstart, (G + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    PR_HIP(h, hipMemcpyAsync(gp_h.data(), gp, G * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    launch_km_key2(n_p, pg, keys, vals, s);
+    launch_sort_pairs(keys, vals, n_p, kscr, vscr, s);   // vals: members by (group, id)
+    PR_HIP(h, hipStreamSynchronize(s));
+
+    // 2. initial centres
+    std::vector<int64_t> m_per(G, 0);
+    std::vector<int32_t> rep0_h;          // boot: patch ids; else sorted positions (gathered below)
+    std::vector<int64_t> pos_h;
+    if (boot) {
+        for (int64_t g = 0; g < G; ++g)
+            for (size_t j = 0; j < boot_reps.size(); ++j)
+                if (boot_ps[j] == gp_h[g]) {
+                    rep0_h.push_back(boot_reps[j]);
+                    m_per[g] += 1;
+                }
+    } else {
+        std::vector<int64_t> sizes(G);
+        for (int64_t g = 0; g < G; ++g) sizes[g] = gstart_h[g + 1] - gstart_h[g];
+        if (!apportion_clusters(sizes, h->prm.m_target, m_per))
+            return pr_fail(h, PR_ERR_INVALID_ARG,
+                           "m_target must lie between the number of groups (" + std::to_string(G) +
+                               ") and the number of patches");
+        // partial Fisher-Yates draw per group, groups in order, one stream:
+        // position i swaps with i + (u mod (L - i))
+        uint64_t st = h->prm.seed;
+        for (int64_t g = 0; g < G; ++g) {
+            const int64_t L = sizes[g];
+            std::unordered_map<int64_t, int64_t> moved;
+            auto at = [&](int64_t x) {
+                auto it = moved.find(x);
+                return it == moved.end() ? x : it->second;
+            };
+            for (int64_t i = 0; i < m_per[g]; ++i) {
+                const uint64_t u = splitmix64_next(st);
+                const int64_t j = i + (int64_t)(u % (uint64_t)(L - i));
+                const int64_t vi = at(i), vj = at(j);
+                moved[i] = vj;
+                moved[j] = vi;
+                pos_h.push_back(gstart_h[g] + vj);
+            }
+        }
+    }
+    const int64_t m_p = std::accumulate(m_per.begin(), m_per.end(), (int64_t)0);
+    if (m_p <= 0) return pr_fail(h, PR_ERR_INVALID_ARG, "empty database");
+    std::vector<int32_t> cgroup_h(m_p), cps_h(m_p), gc0_h(G), gc1_h(G);
+    int64_t lbld = 0;
+    {
+        int64_t j = 0;
+        for (int64_t g = 0; g < G; ++g) {
+            gc0_h[g] = (int32_t)j;
+            for (int64_t t = 0; t < m_per[g]; ++t, ++j) {
+                cgroup_h[j] = (int32_t)g;
+                cps_h[j] = gp_h[g];
+            }
+            gc1_h[g] = (int32_t)j;
+            lbld = std::max(lbld, m_per[g]);
+        }
+    }
+    int32_t *rep = nullptr, *cgroup = nullptr, *cps = nullptr, *gc0 = nullptr, *gc1 = nullptr;
+    int32_t *gactive = nullptr, *gupd = nullptr, *gchanged = nullptr, *info = nullptr, *phi = nullptr;
+    int32_t* mem = nullptr;
+    int64_t *cptr = nullptr, *coff = nullptr, *csz = nullptr;
+    unsigned long long *counters = nullptr, *ccount = nullptr;
+    double *B = nullptr, *X = nullptr, *lbscr = nullptr;
+    PR_TRY(dalloc(h, &rep, m_p));
+    PR_TRY(dalloc(h, &cgroup, m_p));
+    PR_TRY(dalloc(h, &cps, m_p));
+    PR_TRY(dalloc(h, &gc0, G));
+    PR_TRY(dalloc(h, &gc1, G));
+    PR_TRY(dalloc(h, &gactive, G));
+    PR_TRY(dalloc(h, &gupd, G));
+    PR_TRY(dalloc(h, &gchanged, G));
+    PR_TRY(dalloc(h, &info, m_p));
+    PR_TRY(dalloc(h, &phi, n_p));
+    PR_TRY(dalloc(h, &mem, n_p));
+    PR_TRY(dalloc(h, &cptr, m_p + 1));
+    PR_TRY(dalloc(h, &ccount, m_p + 1));
+    PR_TRY(dalloc(h, &counters, 4));
+    PR_TRY(dalloc(h, &B, (size_t)m_p * stride));
+    PR_TRY(dalloc(h, &X, (size_t)m_p * stride));
+    if (boot) {
+        PR_HIP(h, hipMemcpyAsync(rep, rep0_h.data(), m_p * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    } else {
+        int64_t* pos = nullptr;
+        PR_TRY(dalloc(h, &pos, m_p));
+        PR_HIP(h, hipMemcpyAsync(pos, pos_h.data(), m_p * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        launch_gather_i32(m_p, vals, pos, rep, s);
+    }
+    PR_HIP(h, hipMemcpyAsync(cgroup, cgroup_h.data(), m_p * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    PR_HIP(h, hipMemcpyAsync(cps, cps_h.data(), m_p * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    PR_HIP(h, hipMemcpyAsync(gc0, gc0_h.data(), G * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    PR_HIP(h, hipMemcpyAsync(gc1, gc1_h.data(), G * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (!h->uniform) {
+        // centre j: size cps[j], stored at j * stride
+        std::vector<int64_t> csz_h(m_p + 1), coff_h(m_p + 1);
+        csz_h[0] = 0;
+        for (int64_t j = 0; j < m_p; ++j) {
+            csz_h[j + 1] = csz_h[j] + cps_h[j];
+            coff_h[j] = j * stride;
+        }
+        coff_h[m_p] = m_p * stride;
+        PR_TRY(dalloc(h, &csz, m_p + 1));
+        PR_TRY(dalloc(h, &coff, m_p + 1));
+        PR_HIP(h, hipMemcpyAsync(csz, csz_h.data(), (m_p + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        PR_HIP(h, hipMemcpyAsync(coff, coff_h.data(), (m_p + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    }
+    launch_km_init(m_p, rep, h->pptr, h->tiles, toff, ups, B, stride, s);
+    launch_fill_i32(phi, n_p, -1, s);
+    PR_HIP(h, hipMemsetAsync(counters, 0, 4 * sizeof(unsigned long long), s));
+    const int64_t grid = km_assign_grid(n_p, lbld);
+    PR_TRY(dalloc(h, &lbscr, (size_t)grid * lbld));
+
+    auto invert = [&](double* dst) -> int {
+        launch_batch_inverse(h->max_ps, m_p, B, coff, nullptr, csz, dst, coff, info, s);
+        std::vector<int32_t> info_h(m_p);
+        PR_HIP(h, hipMemcpyAsync(info_h.data(), info, m_p * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        PR_HIP(h, hipStreamSynchronize(s));
+        for (int64_t j = 0; j < m_p; ++j)
+            if (info_h[j] != 0)
+                return pr_fail(h, PR_ERR_SINGULAR_PATCH, "singular cluster centre " + std::to_string(j));
+        return PR_OK;
+    };
+
+    // 3. assignment / update passes, each group until no assignment changes
+    std::vector<int32_t> act(G, 1), upd(G, 0), changed(G, 0);
+    std::vector<int64_t> its(G, 0);
+    for (;;) {
+        for (int64_t g = 0; g < G; ++g)
+            if (act[g]) its[g] += 1;
+        if (crit == PR_CRIT_SPECTRAL) PR_TRY(invert(X));
+        PR_HIP(h, hipMemcpyAsync(gactive, act.data(), G * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        PR_HIP(h, hipMemsetAsync(gchanged, 0, G * sizeof(int32_t), s));
+        launch_km_assign(grid, n_p, h->pptr, h->tiles, toff, ups, pg, gc0, gc1, gactive, crit, h->l1norm,
+                         crit == PR_CRIT_SPECTRAL ? X : B, stride, tie, phi, gchanged, lbscr, lbld, counters, s);
+        PR_HIP(h, hipMemcpyAsync(changed.data(), gchanged, G * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        PR_HIP(h, hipStreamSynchronize(s));
+        PR_HIP(h, hipGetLastError());
+        bool any = false;
+        for (int64_t g = 0; g < G; ++g) {
+            upd[g] = 0;
+            if (!act[g]) continue;
+            if (changed[g] == 0 || its[g] >= max_iter) continue;   // converged, or out of passes
+            upd[g] = 1;
+            any = true;
+        }
+        if (!any) break;
+        PR_HIP(h, hipMemcpyAsync(gupd, upd.data(), G * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        PR_HIP(h, hipMemsetAsync(ccount, 0, (m_p + 1) * sizeof(unsigned long long), s));
+        launch_km_keys(n_p, phi, pg, gupd, keys, mem, ccount, s);
+        launch_sort_pairs(keys, mem, n_p, kscr, vscr, s);
+        launch_exclusive_scan_i64((const int64_t*)ccount, cptr, m_p + 1, scr, s);
+        launch_km_update(m_p, cgroup, gupd, cptr, mem, cps, medoid, h->tiles, toff, ups, B, stride, rep, tie,
+                         counters, s);
+        act = upd;
+    }
+
+    // 4. the database: inverses of the final centres
+    PR_TRY(dalloc(h, &h->db, (size_t)m_p * stride));
+    PR_TRY(invert(h->db));
+    unsigned long long cnt[4];
+    PR_HIP(h, hipMemcpyAsync(cnt, counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    h->m_p = m_p;
+    h->phi = phi;
+    h->reps = rep;
+    h->db_mat = B;
+    h->reps_host.resize(m_p);
+    PR_HIP(h, hipMemcpyAsync(h->reps_host.data(), rep, m_p * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PR_HIP(h, hipStreamSynchronize(s));
+    h->stats.crit_evals = (int64_t)cnt[0] + boot_evals;
+    h->stats.crit_exact = (int64_t)cnt[1] + boot_exact;
+    h->stats.crit_pruned = boot_pruned;
+    h->stats.empty_events = (int64_t)cnt[2];
+    h->stats.kmeans_iters = (int32_t)*std::max_element(its.begin(), its.end());
+    h->dbps_host = cps_h;
+    h->dboff_host.resize(m_p + 1);
+    for (int64_t j = 0; j <= m_p; ++j) h->dboff_host[j] = j * stride;
     return PR_OK;
 }
 
@@ -545,8 +825,9 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
         pm.apply_precision < 0 || pm.apply_precision > 4 || pm.sweeps < 1 || pm.gmres_restart < 1 ||
         pm.gmres_restart > 64 || !(pm.eps >= 0.0) || !(pm.omega > 0.0))
         return pr_fail(nullptr, PR_ERR_INVALID_ARG, "bad parameter value");
-    if (pm.algo != PR_ALGO_FULL && pm.algo != PR_ALGO_TOLERANCE)
-        return pr_fail(nullptr, PR_ERR_UNSUPPORTED, "clustering algorithms are not built in this library");
+    if (pm.algo != PR_ALGO_FULL && pm.algo != PR_ALGO_TOLERANCE &&
+        (pm.kmeans_max_iter < 1 || !(pm.tie_rel >= 0.0)))
+        return pr_fail(nullptr, PR_ERR_INVALID_ARG, "bad clustering parameter");
     {
         int rc;
         if ((rc = check_dev(nullptr, A->row_ptr, "A.row_ptr")) < 0) return rc;
@@ -661,7 +942,8 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
 
     // ---- database (Section 3) ----------------------------------------------
     if (pm.algo == PR_ALGO_FULL) SETUP_TRY(run_full(h));
-    else SETUP_TRY(run_alg1(h));
+    else if (pm.algo == PR_ALGO_TOLERANCE) SETUP_TRY(run_alg1(h));
+    else SETUP_TRY(run_kmeans(h));
     SETUP_HIP(hipStreamSynchronize(s));
     SETUP_HIP(hipGetLastError());
     const double t3 = now_s();
@@ -924,6 +1206,15 @@ int pr_get_rep_inverse(pr_handle h, int64_t j, double* X) {
     PR_HIP(h, hipStreamSynchronize(h->stream));
     const int64_t p = h->dbps_host[j];
     PR_HIP(h, hipMemcpy(X, h->db + h->dboff_host[j], p * p * sizeof(double), hipMemcpyDeviceToHost));
+    return PR_OK;
+}
+
+int pr_get_entry_matrix(pr_handle h, int64_t j, double* B) {
+    if (!h || !B || j < 0 || j >= h->m_p) return PR_ERR_INVALID_ARG;
+    if (!h->db_mat) return pr_get_patch_tile(h, h->reps_host[j], B);
+    PR_HIP(h, hipStreamSynchronize(h->stream));
+    const int64_t p = h->dbps_host[j];
+    PR_HIP(h, hipMemcpy(B, h->db_mat + h->dboff_host[j], p * p * sizeof(double), hipMemcpyDeviceToHost));
     return PR_OK;
 }
 

@@ -232,6 +232,29 @@ void launch_a1_finish(int64_t n_p, const int32_t* repof, int64_t* flags, int64_t
 void launch_a1_copy_db(int64_t m_p, const int32_t* reps, const int32_t* slot_of_patch, const int64_t* ptr,
                        const double* dbt, double* db, int64_t stride, hipStream_t s);
 
+// k_kmeans.hip: Algorithm 2 and its variants (see that file)
+int64_t km_assign_grid(int64_t n_p, int64_t lbld);
+void launch_km_assign(int64_t grid, int64_t n_p, const int64_t* ptr, const double* tiles, const int64_t* toff,
+                      int uniform_ps, const int32_t* pg, const int32_t* gc0, const int32_t* gc1,
+                      const int32_t* gactive, int crit, const double* l1n, const double* cen, int64_t stride,
+                      double tie, int32_t* phi, int32_t* gchanged, double* lbscr, int64_t lbld,
+                      unsigned long long* counters, hipStream_t s);
+void launch_km_update(int64_t m_p, const int32_t* cgroup, const int32_t* gupd, const int64_t* cptr,
+                      const int32_t* mem, const int32_t* cps, int medoid, const double* tiles,
+                      const int64_t* toff, int uniform_ps, double* B, int64_t stride, int32_t* rep_patch,
+                      double tie, unsigned long long* counters, hipStream_t s);
+void launch_km_init(int64_t m_p, const int32_t* rep, const int64_t* ptr, const double* tiles,
+                    const int64_t* toff, int uniform_ps, double* B, int64_t stride, hipStream_t s);
+void launch_km_keys(int64_t n_p, const int32_t* phi, const int32_t* pg, const int32_t* gupd, uint64_t* keys,
+                    int32_t* vals, unsigned long long* ccount, hipStream_t s);
+void launch_km_key1(int64_t n_p, const int64_t* ptr, const uint32_t* bkeys, int partition, uint64_t* keys,
+                    int32_t* vals, hipStream_t s);
+void launch_km_flags(int64_t n, const uint64_t* keys, int64_t* flag, hipStream_t s);
+void launch_km_gid(int64_t n, const uint64_t* keys, const int32_t* vals, const int64_t* flag,
+                   const int64_t* excl, int32_t* pg, int64_t* gstart, int32_t* gp, hipStream_t s);
+void launch_km_key2(int64_t n_p, const int32_t* pg, uint64_t* keys, int32_t* vals, hipStream_t s);
+void launch_gather_i32(int64_t n, const int32_t* src, const int64_t* idx, int32_t* out, hipStream_t s);
+
 // k_apply.hip
 struct ApplyLaunch {
     int64_t n, n_p;

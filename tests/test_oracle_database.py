@@ -151,8 +151,9 @@ def test_kmeans_fixed_point_and_partition(variant):
             d = [O.criterion('l1' if variant == 'entrywise' else 'spectral', t[i], res['B'][j],
                              res['X'][j]) for j in same]
             dmin = min(d)
+            s = np.sum(np.abs(t[i])) if variant == 'entrywise' else 1.0
             assert O.criterion('l1' if variant == 'entrywise' else 'spectral', t[i],
-                               res['B'][phi[i]], res['X'][phi[i]]) <= dmin * (1 + 1e-9)
+                               res['B'][phi[i]], res['X'][phi[i]]) <= dmin * (1 + 1e-9) + 1e-9 * s
 
 
 def test_bootstrap_from_identical_classes_converges_at_once():
@@ -172,3 +173,37 @@ def test_kmeans_initial_draw_reproducible():
     assert np.array_equal(a['rep_patch'], b['rep_patch'])
     c = O.kmeans(t, 10, seed=10, max_iter=1)
     assert not np.array_equal(a['rep_patch'], c['rep_patch'])
+
+
+@pytest.mark.parametrize("variant,vals,centres", [
+    # 1x1 patches: entrywise k-means is Lloyd's algorithm on the line
+    ("entrywise", [1.0, 2.0, 3.0, 10.0, 11.0, 12.0], [2.0, 11.0]),
+    # spectral distance |1 - a/b| of 1x1 patches: two clusters a decade apart
+    ("spectral", [1.0, 1.1, 1.2, 100.0, 110.0, 120.0], [1.1, 110.0]),
+])
+def test_kmeans_two_separated_triples_from_every_draw(variant, vals, centres):
+    # from any two distinct initial centres the passes end with the two triples
+    # and their means as centres (worked by hand for every initial pair)
+    tiles = [np.array([[v]]) for v in vals]
+    seen = set()
+    for seed in range(40):
+        res = O.kmeans(tiles, 2, variant=variant, seed=seed, partition=False)
+        seen.add(tuple(sorted(int(r) for r in res['rep_patch'] if r >= 0)))
+        phi = res['phi']
+        assert len(set(phi[:3])) == 1 and len(set(phi[3:])) == 1 and phi[0] != phi[3]
+        got = sorted(float(b[0, 0]) for b in res['B'])
+        assert np.allclose(got, centres, rtol=1e-14, atol=0)
+        assert all(res['converged'])
+    assert len(seen) <= 1      # centres became means, no patch representative left
+
+
+def test_kmeans_groups_never_mix_sizes():
+    rng = np.random.default_rng(2)
+    tiles = [rng.standard_normal((p, p)) + 4 * np.eye(p) for p in (2, 3, 2, 3, 3, 2, 2)]
+    g = O.partition_groups(tiles, partition=False)
+    assert [k for k, _ in g] == [2, 3]
+    assert [list(m) for _, m in g] == [[0, 2, 5, 6], [1, 3, 4]]
+    res = O.kmeans(tiles, 3, variant="spectral", seed=1, partition=False)
+    for j in range(3):
+        sizes = {tiles[i].shape[0] for i in np.flatnonzero(res['phi'] == j)}
+        assert len(sizes) <= 1
