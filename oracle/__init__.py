@@ -20,7 +20,8 @@ from .patch import (OracleError, cover_weights, patch_tiles, boundary_mask,
                     objective)
 from .criterion import crit_spectral, crit_spectral_x, crit_l1, crit_fro, criterion
 from .database import (alg1_tolerance, kmeans, partition_groups, apportion,
-                       SplitMix64, alg1_invariants_hold)
+                       SplitMix64, alg1_invariants_hold, alg1_with_predictions)
+from . import mlp
 from .krylov import gmres, make_preconditioner
 from .lowprec import round_fp32, round_bf16, round_fp16, apply_lowprec, fp16_scale_exp
 
@@ -29,6 +30,6 @@ __all__ = [
     "apply_patch", "apply_operator_dense", "storage_bytes", "objective",
     "crit_spectral", "crit_spectral_x", "crit_l1", "crit_fro", "criterion",
     "alg1_tolerance", "kmeans", "partition_groups", "apportion", "SplitMix64",
-    "alg1_invariants_hold", "gmres", "make_preconditioner",
+    "alg1_invariants_hold", "alg1_with_predictions", "mlp", "gmres", "make_preconditioner",
     "round_fp32", "round_bf16", "round_fp16", "apply_lowprec", "fp16_scale_exp",
 ]

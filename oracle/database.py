@@ -101,6 +101,71 @@ def alg1_tolerance(tiles, eps, crit="spectral"):
                 margin=margin)
 
 
+def alg1_with_predictions(tiles, eps, crit, train, cand):
+    """Algorithm 1 with a predictor of the matching entry (the learned
+    shortcut suggested by the closing remarks of Section 3.2).
+
+    1. Algorithm 1 runs on the training patches ``train`` alone (ascending
+       id); its entries are the predictor's classes.
+    2. Every other patch i, in ascending id, tries the entries ``cand[i]``
+       (indices into the training database, most probable first) and takes the
+       first with d < eps;
+    3. failing that, it scans the current database in append order (the
+       training entries, then the entries appended in this step) and takes
+       the first with d < eps, or is appended as a new entry.
+    Entries of another patch size are never compared.  With ``train`` a
+    prefix of the patch ids and no predictions this is Algorithm 1 itself.
+    Returns dict(phi, reps, n_train_entries, accepted, scanned, appended,
+    evals).
+    """
+    n = len(tiles)
+    train = sorted(int(t) for t in train)
+    sub = alg1_tolerance([tiles[i] for i in train], eps, crit)
+    reps = [train[int(r)] for r in sub["reps"]]
+    X = list(sub["X"])
+    phi = -np.ones(n, dtype=np.int64)
+    phi[train] = sub["phi"]
+    n0 = len(reps)
+    evals = int(sub["evals"])
+    accepted = scanned = appended = 0
+    in_train = np.zeros(n, dtype=bool)
+    in_train[train] = True
+    for i in range(n):
+        if in_train[i]:
+            continue
+        Ai = tiles[i]
+        hit = -1
+        for j in cand[i]:
+            j = int(j)
+            if j < 0 or j >= n0 or tiles[reps[j]].shape != Ai.shape:
+                continue
+            evals += 1
+            if _dist(crit, Ai, tiles[reps[j]], X[j]) < eps:
+                hit = j
+                break
+        if hit >= 0:
+            phi[i] = hit
+            accepted += 1
+            continue
+        for j in range(len(reps)):
+            if tiles[reps[j]].shape != Ai.shape:
+                continue
+            evals += 1
+            if _dist(crit, Ai, tiles[reps[j]], X[j]) < eps:
+                hit = j
+                break
+        if hit >= 0:
+            scanned += 1
+        else:
+            reps.append(i)
+            X.append(factor_inverse(Ai))
+            hit = len(reps) - 1
+            appended += 1
+        phi[i] = hit
+    return dict(phi=phi, reps=np.asarray(reps, dtype=np.int64), n_train_entries=n0,
+                accepted=accepted, scanned=scanned, appended=appended, evals=evals)
+
+
 def alg1_invariants_hold(tiles_of, phi, reps, eps, crit, sample, X_of=None):
     """Check Algorithm 1's defining properties on sampled patches i:
     a database entry's patch matches no earlier entry; any other patch matches
