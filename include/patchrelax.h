@@ -116,6 +116,16 @@ typedef struct {
     int32_t timing;          /* 1: pr_solve brackets its kernels with HIP events and
                                 reports per-class device time in pr_solve_info (default 0) */
     void*   stream;          /* hipStream_t for all work (NULL = default stream) */
+    /* learned entry predictor for Algorithm 1 (pr_setup, PR_ALGO_TOLERANCE) */
+    int32_t mlp;             /* 1: Algorithm 1 with predictions (default 0) */
+    int32_t mlp_topk;        /* candidates tried per patch, 1..8 (default 4) */
+    double  mlp_train_frac;  /* fraction of patches in the training set, (0, 1] (default 0.1) */
+    int32_t mlp_epochs;      /* passes over the training set (default 60) */
+    int32_t mlp_hidden;      /* width of both hidden layers, 1..1024 (default 64) */
+    uint64_t mlp_seed;       /* SplitMix64 seed: sample, weights, shuffles (default 6) */
+    double  mlp_lr;          /* Adam learning rate (default 3e-3) */
+    int32_t mlp_batch;       /* minibatch rows (default 256) */
+    int32_t mlp_precision;   /* PR_FP16 (MFMA, FP32 accumulate; default) or PR_FP32 */
 } pr_params;
 
 typedef struct pr_handle_s* pr_handle;
@@ -151,6 +161,15 @@ typedef struct {
     double  t_validate, t_extract, t_database, t_factor, t_group, t_total; /* seconds */
     int32_t apply_precision;
     int32_t reserved0;
+    /* Algorithm 1 with predictions (params.mlp = 1) */
+    int64_t mlp_train;       /* training patches */
+    int64_t mlp_classes;     /* entries of the training database (network classes) */
+    int64_t mlp_accepted;    /* patches matched by a predicted candidate */
+    int64_t mlp_scanned;     /* patches matched by the in-order scan */
+    int64_t mlp_fallback;    /* patches left to Algorithm 1 (matched nothing) */
+    double  mlp_loss;        /* mean cross-entropy on the training set after training */
+    double  mlp_train_acc;   /* top-1 accuracy on the training set */
+    double  t_mlp_train;     /* seconds: features, training and the accuracy pass */
 } pr_stats;
 
 /* ---- entry points ------------------------------------------------------ */
@@ -220,6 +239,18 @@ int pr_get_rep_inverse(pr_handle h, int64_t j, double* X);
 /* B: double[p_j * p_j], the matrix of database entry j (a patch matrix, or
  * the cluster mean of Eq.(6)), row-major. */
 int pr_get_entry_matrix(pr_handle h, int64_t j, double* B);
+/* Algorithm 1 with predictions (params.mlp = 1): train receives the
+ * stats.mlp_train training patch ids (ascending); cand receives
+ * int32[n_p * mlp_topk], row i the predicted entries of patch i (indices
+ * into the training database, most probable first; -1 for training patches
+ * and unused slots).  Either pointer may be NULL.  INVALID_ARG without a
+ * predictor. */
+int pr_get_mlp_candidates(pr_handle h, int32_t* train, int32_t* cand);
+/* The predictor's raw (not standardised) features: *F = 3 p_max + 1 and, if X
+ * is not NULL, X: host float[n_p * F], row k for patch k (A_aa / m, then
+ * sum_b |A_ab| / m, then the single-entry row bits, then log m, with
+ * m = mean_a |A_aa|, slots beyond p_k zero).  INVALID_ARG without a predictor. */
+int pr_get_mlp_features(pr_handle h, float* X, int32_t* F);
 
 /* Use another stream for later calls on h (NULL = default stream). */
 int pr_set_stream(pr_handle h, void* hip_stream);
@@ -250,6 +281,29 @@ int pr_batch_inverse(int32_t p, int64_t count, const double* A, double* X, int32
  * spectral, X unused otherwise; may be NULL then); d: device double[count]. */
 int pr_batch_criterion(int32_t p, int64_t count, int32_t criterion, const double* A,
                        const double* B, const double* X, double* d, void* stream);
+
+/* The learned entry predictor's network (the neural shortcut to building
+ * the database that the closing remarks of Section 3.2 point to):
+ * h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2), logits = h2 W3 + b3, loss =
+ * mean over rows of logsumexp(l) - l[y], the sum over the classes c with
+ * class_key[c] == row_key[r] (all classes when both keys are NULL).
+ * params, grads: device float[F*H + H + H*H + H + H*C + C], packed W1 (F x H,
+ * row-major), b1, W2 (H x H), b2, W3 (H x C), b3.  X: device float[rows*F]
+ * row-major; y: device int32[rows]; row_key: device int32[rows]; class_key:
+ * device int32[C].  precision: PR_FP32 (FMA) or PR_FP16 (operands rounded
+ * to FP16, MFMA, FP32 accumulation).  *loss: host double.  Synchronises
+ * the stream.  Errors: INVALID_ARG (sizes, precision, a key missing),
+ * HOST_POINTER, OOM. */
+int pr_mlp_loss_grad(int32_t precision, int64_t rows, int32_t F, int32_t H, int32_t C, const float* X,
+                     const int32_t* y, const int32_t* row_key, const int32_t* class_key,
+                     const float* params, float* grads, double* loss, void* stream);
+/* Forward pass of the same network: logits (device float[rows*C], may be
+ * NULL) and the k (0..8, at most C) allowed classes of largest logit per row,
+ * largest first, lower index on ties (device int32[rows*k]; -1 when fewer
+ * than k classes are allowed).  Synchronises the stream. */
+int pr_mlp_predict(int32_t precision, int64_t rows, int32_t F, int32_t H, int32_t C, const float* X,
+                   const int32_t* row_key, const int32_t* class_key, const float* params, int32_t k,
+                   float* logits, int32_t* topk, void* stream);
 
 #ifdef __cplusplus
 }

@@ -72,7 +72,10 @@ def alg1_tolerance(tiles, eps, crit="spectral"):
 
     Visit patches in order; compare with the database entries in append order
     and take the first with d < eps; with no match, append the patch's inverse
-    and map the patch to the new entry.
+    and map the patch to the new entry.  Entries of another patch size are
+    never compared (a matrix of another size is no candidate, remark in
+    Section 2), so with several sizes each size runs Algorithm 1 on its own
+    while entries keep one append order.
     Returns dict(phi, reps, X, evals, margin): reps are the patch ids whose
     inverses form the database, evals counts criterion evaluations and margin
     is min |d - eps| / eps over every comparison made.
@@ -84,6 +87,8 @@ def alg1_tolerance(tiles, eps, crit="spectral"):
     for i, Ai in enumerate(tiles):
         match = False
         for j in range(len(reps)):
+            if B[j].shape != Ai.shape:
+                continue
             d = _dist(crit, Ai, B[j], X[j])
             evals += 1
             if eps > 0:
@@ -115,8 +120,9 @@ def alg1_with_predictions(tiles, eps, crit, train, cand):
        the first with d < eps, or is appended as a new entry.
     Entries of another patch size are never compared.  With ``train`` a
     prefix of the patch ids and no predictions this is Algorithm 1 itself.
-    Returns dict(phi, reps, n_train_entries, accepted, scanned, appended,
-    evals).
+    Returns dict(phi, reps, n_train_entries, accepted, scanned,
+    scanned_train, appended, evals): scanned counts the patches placed by the
+    scan, scanned_train those among them placed on a training entry.
     """
     n = len(tiles)
     train = sorted(int(t) for t in train)
@@ -127,7 +133,7 @@ def alg1_with_predictions(tiles, eps, crit, train, cand):
     phi[train] = sub["phi"]
     n0 = len(reps)
     evals = int(sub["evals"])
-    accepted = scanned = appended = 0
+    accepted = scanned = scanned_train = appended = 0
     in_train = np.zeros(n, dtype=bool)
     in_train[train] = True
     for i in range(n):
@@ -156,6 +162,7 @@ def alg1_with_predictions(tiles, eps, crit, train, cand):
                 break
         if hit >= 0:
             scanned += 1
+            scanned_train += 1 if hit < n0 else 0
         else:
             reps.append(i)
             X.append(factor_inverse(Ai))
@@ -163,7 +170,8 @@ def alg1_with_predictions(tiles, eps, crit, train, cand):
             appended += 1
         phi[i] = hit
     return dict(phi=phi, reps=np.asarray(reps, dtype=np.int64), n_train_entries=n0,
-                accepted=accepted, scanned=scanned, appended=appended, evals=evals)
+                accepted=accepted, scanned=scanned, scanned_train=scanned_train,
+                appended=appended, evals=evals)
 
 
 def alg1_invariants_hold(tiles_of, phi, reps, eps, crit, sample, X_of=None):

@@ -65,22 +65,41 @@ def init_params(F, H, C, seed=0):
     }
 
 
-def forward(P, X):
-    z1 = X @ P["W1"] + P["b1"]
+def round_sig(a, bits):
+    """Round to ``bits`` significant bits, to nearest with ties to even, with
+    no exponent limit: the significand rounding of a narrow float format
+    without its range (FP16 has 11 bits)."""
+    a = np.asarray(a, dtype=np.float64)
+    m, e = np.frexp(a)
+    return np.ldexp(np.round(m * 2.0 ** bits) / 2.0 ** bits, e)
+
+
+def _mm(A, B, rnd):
+    return rnd(A) @ rnd(B)
+
+
+def forward(P, X, operand_bits=None):
+    """Forward pass; with operand_bits every factor of every matrix product
+    is first rounded to that many significant bits (reduced-precision
+    operands, exact sums)."""
+    rnd = (lambda a: a) if operand_bits is None else (lambda a: round_sig(a, operand_bits))
+    z1 = _mm(X, P["W1"], rnd) + P["b1"]
     h1 = np.maximum(z1, 0.0)
-    z2 = h1 @ P["W2"] + P["b2"]
+    z2 = _mm(h1, P["W2"], rnd) + P["b2"]
     h2 = np.maximum(z2, 0.0)
-    logits = h2 @ P["W3"] + P["b3"]
+    logits = _mm(h2, P["W3"], rnd) + P["b3"]
     return dict(X=X, h1=h1, h2=h2, logits=logits)
 
 
-def loss_and_grads(P, X, y, allowed=None):
+def loss_and_grads(P, X, y, allowed=None, operand_bits=None):
     """Mean cross-entropy over the rows and its gradient for every parameter.
 
     allowed: optional boolean [rows, classes]; classes outside it take no
     probability (their logits are dropped from the log-sum-exp).
+    operand_bits: as in ``forward``, for every product of the backward pass too.
     """
-    c = forward(P, X)
+    rnd = (lambda a: a) if operand_bits is None else (lambda a: round_sig(a, operand_bits))
+    c = forward(P, X, operand_bits)
     L = c["logits"].copy()
     if allowed is not None:
         L[~allowed] = -np.inf
@@ -93,12 +112,12 @@ def loss_and_grads(P, X, y, allowed=None):
     G3 = e / s
     G3[rows, y] -= 1.0
     G3 /= B
-    g = {"W3": c["h2"].T @ G3, "b3": G3.sum(axis=0)}
-    G2 = (G3 @ P["W3"].T) * (c["h2"] > 0.0)
-    g["W2"] = c["h1"].T @ G2
+    g = {"W3": _mm(c["h2"].T, G3, rnd), "b3": G3.sum(axis=0)}
+    G2 = _mm(G3, P["W3"].T, rnd) * (c["h2"] > 0.0)
+    g["W2"] = _mm(c["h1"].T, G2, rnd)
     g["b2"] = G2.sum(axis=0)
-    G1 = (G2 @ P["W2"].T) * (c["h1"] > 0.0)
-    g["W1"] = X.T @ G1
+    G1 = _mm(G2, P["W2"].T, rnd) * (c["h1"] > 0.0)
+    g["W1"] = _mm(X.T, G1, rnd)
     g["b1"] = G1.sum(axis=0)
     return loss, g
 

@@ -56,7 +56,10 @@ class pr_params(Structure):
                 ("seed", c_uint64), ("tie_rel", c_double), ("apply_precision", c_int32),
                 ("omega", c_double), ("sweeps", c_int32), ("gmres_restart", c_int32),
                 ("max_iters", c_int64), ("deterministic", c_int32), ("timing", c_int32),
-                ("stream", c_void_p)]
+                ("stream", c_void_p), ("mlp", c_int32), ("mlp_topk", c_int32),
+                ("mlp_train_frac", c_double), ("mlp_epochs", c_int32), ("mlp_hidden", c_int32),
+                ("mlp_seed", c_uint64), ("mlp_lr", c_double), ("mlp_batch", c_int32),
+                ("mlp_precision", c_int32)]
 
 
 class pr_solve_info(Structure):
@@ -76,7 +79,10 @@ class pr_stats(Structure):
                 ("bytes_db_lowp", c_int64), ("bytes_index", c_int64),
                 ("t_validate", c_double), ("t_extract", c_double), ("t_database", c_double),
                 ("t_factor", c_double), ("t_group", c_double), ("t_total", c_double),
-                ("apply_precision", c_int32), ("reserved0", c_int32)]
+                ("apply_precision", c_int32), ("reserved0", c_int32),
+                ("mlp_train", c_int64), ("mlp_classes", c_int64), ("mlp_accepted", c_int64),
+                ("mlp_scanned", c_int64), ("mlp_fallback", c_int64), ("mlp_loss", c_double),
+                ("mlp_train_acc", c_double), ("t_mlp_train", c_double)]
 
 
 _SIGS = {
@@ -100,6 +106,12 @@ _SIGS = {
     "pr_batch_inverse": (c_int, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
     "pr_batch_criterion": (c_int, [c_int32, c_int64, c_int32, c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_void_p]),
+    "pr_get_mlp_candidates": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "pr_get_mlp_features": (c_int, [c_void_p, c_void_p, POINTER(c_int32)]),
+    "pr_mlp_loss_grad": (c_int, [c_int32, c_int64, c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                                 c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double), c_void_p]),
+    "pr_mlp_predict": (c_int, [c_int32, c_int64, c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                               c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
 }
 
 _lib = None
@@ -159,8 +171,19 @@ def pr_params_default() -> pr_params:
 def make_params(algo="full", criterion="spectral", eps=1e-8, m_target=0, partition_bc=True,
                 kmeans_max_iter=100, seed=5, tie_rel=1e-9, precision="fp64", omega=1.0, sweeps=1,
                 restart=30, max_iters=10000, deterministic=False, timing=False,
-                stream=None) -> pr_params:
+                stream=None, mlp=False, mlp_topk=4, mlp_train_frac=0.1, mlp_epochs=60,
+                mlp_hidden=64, mlp_seed=6, mlp_lr=3e-3, mlp_batch=256,
+                mlp_precision="fp16") -> pr_params:
     p = pr_params_default()
+    p.mlp = int(mlp)
+    p.mlp_topk = mlp_topk
+    p.mlp_train_frac = mlp_train_frac
+    p.mlp_epochs = mlp_epochs
+    p.mlp_hidden = mlp_hidden
+    p.mlp_seed = mlp_seed
+    p.mlp_lr = mlp_lr
+    p.mlp_batch = mlp_batch
+    p.mlp_precision = PREC[mlp_precision] if isinstance(mlp_precision, str) else int(mlp_precision)
     p.algo = ALGO[algo] if isinstance(algo, str) else int(algo)
     p.criterion = CRIT[criterion] if isinstance(criterion, str) else int(criterion)
     p.eps = eps
@@ -249,6 +272,38 @@ def pr_get_entry_matrix(h, j, p):
     return B.reshape(p, p)
 
 
+def pr_get_mlp_candidates(h, n_p, n_train, k):
+    train = np.zeros(max(n_train, 1), dtype=np.int32)
+    cand = np.zeros(n_p * k, dtype=np.int32)
+    _check(lib().pr_get_mlp_candidates(h, train.ctypes.data_as(c_void_p), cand.ctypes.data_as(c_void_p)), h)
+    return train[:n_train], cand.reshape(n_p, k)
+
+
+def pr_get_mlp_features(h, n_p):
+    F = c_int32()
+    _check(lib().pr_get_mlp_features(h, None, byref(F)), h)
+    X = np.zeros(n_p * F.value, dtype=np.float32)
+    _check(lib().pr_get_mlp_features(h, X.ctypes.data_as(c_void_p), byref(F)), h)
+    return X.reshape(n_p, F.value)
+
+
+def pr_mlp_loss_grad(precision, X, y, params, grads, F, H, C, row_key=None, class_key=None):
+    """Mean cross-entropy and its gradient (device tensors; returns the loss)."""
+    prec = PREC[precision] if isinstance(precision, str) else int(precision)
+    loss = c_double()
+    _check(lib().pr_mlp_loss_grad(prec, int(y.numel()), F, H, C, _ptr(X), _ptr(y), _ptr(row_key),
+                                  _ptr(class_key), _ptr(params), _ptr(grads), byref(loss), _stream()))
+    return loss.value
+
+
+def pr_mlp_predict(precision, X, params, F, H, C, k, logits=None, topk=None, row_key=None,
+                   class_key=None):
+    prec = PREC[precision] if isinstance(precision, str) else int(precision)
+    rows = int(X.numel()) // F
+    return _check(lib().pr_mlp_predict(prec, rows, F, H, C, _ptr(X), _ptr(row_key), _ptr(class_key),
+                                       _ptr(params), k, _ptr(logits), _ptr(topk), _stream()))
+
+
 def pr_destroy(h):
     if h:
         lib().pr_destroy(h)
@@ -331,6 +386,13 @@ class PatchRelax:
 
     def entry_matrix(self, j, p):
         return pr_get_entry_matrix(self.h, j, p)
+
+    def mlp_features(self):
+        return pr_get_mlp_features(self.h, self.n_p)
+
+    def mlp_candidates(self):
+        st = self.stats()
+        return pr_get_mlp_candidates(self.h, self.n_p, int(st["mlp_train"]), self.params.mlp_topk)
 
     def close(self):
         if self.h:

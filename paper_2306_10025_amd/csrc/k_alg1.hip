@@ -31,15 +31,17 @@ using namespace pr_dev;
 //                 [2] done            [3] candidates this round
 //                 [4] rounds started  [5] first singular entry patch + 1
 
-__global__ void k_a1_keys(int64_t n_p, const int64_t* __restrict__ ptr,
+// position s holds patch subset[s] (patch s without a subset)
+__global__ void k_a1_keys(int64_t n_p, const int32_t* __restrict__ subset, const int64_t* __restrict__ ptr,
                           const double* __restrict__ keynorm, uint64_t* __restrict__ keys,
                           int32_t* __restrict__ vals) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n_p) return;
-    const uint64_t p = (uint64_t)(ptr[s + 1] - ptr[s]);
-    const uint64_t bits = (uint64_t)__double_as_longlong(keynorm[s]);  // key >= 0: monotone
+    const int32_t i = subset ? subset[s] : (int32_t)s;
+    const uint64_t p = (uint64_t)(ptr[i + 1] - ptr[i]);
+    const uint64_t bits = (uint64_t)__double_as_longlong(keynorm[i]);  // key >= 0: monotone
     keys[s] = (p << 58) | (bits >> 5);
-    vals[s] = (int32_t)s;
+    vals[s] = i;
 }
 
 __global__ void k_a1_comp_flags(int64_t n_p, const int32_t* __restrict__ sidx,
@@ -260,6 +262,23 @@ __global__ void k_a1_finish(int64_t n_p, const int32_t* __restrict__ repof,
     if (r == (int32_t)i) reps[rank[i]] = (int32_t)i;
 }
 
+// subset form of the numbering: entries of the subset in ascending patch id
+__global__ void k_a1_subflags(int64_t ns, const int32_t* __restrict__ subset, const int32_t* __restrict__ repof,
+                              int64_t* __restrict__ f) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < ns) f[s] = (repof[subset[s]] == subset[s]) ? 1 : 0;
+    else if (s == ns) f[s] = 0;
+}
+
+__global__ void k_a1_subrank(int64_t ns, const int32_t* __restrict__ subset, const int64_t* __restrict__ f,
+                             const int64_t* __restrict__ rank, int32_t base, int32_t* __restrict__ entries,
+                             int32_t* __restrict__ rank_of_patch) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ns || !f[s]) return;
+    entries[rank[s]] = subset[s];
+    rank_of_patch[subset[s]] = base + (int32_t)rank[s];
+}
+
 // entry j (ascending patch id) <- its temporary slot
 __global__ void k_a1_copy_db(int64_t m_p, const int32_t* __restrict__ reps,
                              const int32_t* __restrict__ slot_of_patch, const int64_t* __restrict__ ptr,
@@ -287,9 +306,17 @@ void run_a1_invert(int64_t n_comp, const int32_t* ctl, const int32_t* active, co
 
 }  // namespace
 
-void launch_a1_keys(int64_t n_p, const int64_t* ptr, const double* keynorm, uint64_t* keys,
-                    int32_t* vals, hipStream_t s) {
-    k_a1_keys<<<nb(n_p, 256), 256, 0, s>>>(n_p, ptr, keynorm, keys, vals);
+void launch_a1_keys(int64_t n_p, const int32_t* subset, const int64_t* ptr, const double* keynorm,
+                    uint64_t* keys, int32_t* vals, hipStream_t s) {
+    k_a1_keys<<<nb(n_p, 256), 256, 0, s>>>(n_p, subset, ptr, keynorm, keys, vals);
+}
+
+void launch_a1_subset_entries(int64_t ns, const int32_t* subset, const int32_t* repof, int64_t* flags,
+                              int64_t* rank, int64_t* scr, int32_t base, int32_t* entries,
+                              int32_t* rank_of_patch, hipStream_t s) {
+    k_a1_subflags<<<nb(ns + 1, 256), 256, 0, s>>>(ns, subset, repof, flags);
+    launch_exclusive_scan_i64(flags, rank, ns + 1, scr, s);
+    k_a1_subrank<<<nb(ns, 256), 256, 0, s>>>(ns, subset, flags, rank, base, entries, rank_of_patch);
 }
 
 void launch_a1_comp_flags(int64_t n_p, const int32_t* sidx, const int64_t* ptr, const double* keynorm,

@@ -23,19 +23,6 @@ double now_s() {
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-template <typename T>
-int dalloc(pr_handle h, T** p, size_t count) {
-    if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
-    if (e != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return pr_fail(h, PR_ERR_OOM, std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
-                                          " bytes failed: " + hipGetErrorString(e));
-    }
-    h->owned.push_back({(void*)*p, count * sizeof(T)});
-    return PR_OK;
-}
 
 bool is_device_ptr(const void* p) {
     if (!p) return false;
@@ -53,108 +40,21 @@ int check_dev(pr_handle h, const void* p, const char* what) {
     return PR_OK;
 }
 
-int64_t next_pow2(int64_t n) {
-    int64_t N = 1024;
-    while (N < n) N <<= 1;
-    return N;
-}
 
 // ---- Algorithm 1 ------------------------------------------------------------
 int run_alg1(pr_handle h) {
     hipStream_t s = h->stream;
     const int64_t n_p = h->n_p;
     const int64_t stride = (int64_t)h->max_ps * h->max_ps;
-    const int crit = h->prm.criterion;
-    const double* keynorm = (crit == PR_CRIT_L1) ? h->l1norm : h->fnorm;
-    const int64_t N = next_pow2(n_p);
-    uint64_t *keys = nullptr, *kscr = nullptr;
-    int32_t *sidx = nullptr, *vscr = nullptr;
-    int64_t *flag = nullptr, *excl = nullptr, *scr = nullptr;
-    PR_TRY(dalloc(h, &keys, n_p));
-    PR_TRY(dalloc(h, &kscr, N));
-    PR_TRY(dalloc(h, &sidx, n_p));
-    PR_TRY(dalloc(h, &vscr, N));
-    PR_TRY(dalloc(h, &flag, n_p + 1));
-    PR_TRY(dalloc(h, &excl, n_p + 1));
-    PR_TRY(dalloc(h, &scr, scan_scratch_elems(n_p + 1) + 2));
-    // 1. sort by (size, key); 2. components where no match can cross a gap
-    launch_a1_keys(n_p, h->pptr, keynorm, keys, sidx, s);
-    launch_sort_pairs(keys, sidx, n_p, kscr, vscr, s);
-    launch_a1_comp_flags(n_p, sidx, h->pptr, keynorm, crit, h->prm.eps, flag, s);
-    launch_exclusive_scan_i64(flag, excl, n_p + 1, scr, s);
-    int64_t n_comp = 0;
-    PR_HIP(h, hipMemcpyAsync(&n_comp, excl + n_p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    PR_HIP(h, hipStreamSynchronize(s));
-    // 3. members of each component in ascending patch id
-    A1Dev d{};
-    d.n_p = n_p;
-    d.n_comp = n_comp;
-    d.ptr = h->pptr;
-    d.tiles = h->tiles;
-    d.toff = h->uniform ? nullptr : h->toff;
-    d.uniform_ps = h->uniform ? h->max_ps : 0;
-    d.stride = stride;
-    int32_t *mem = nullptr, *pos_comp = nullptr, *cstart = nullptr, *next = nullptr, *status = nullptr;
-    int32_t *rep_slot = nullptr, *rep_patch = nullptr, *slot_of_patch = nullptr, *repof = nullptr;
-    int32_t *active = nullptr, *cand = nullptr, *ctl = nullptr;
-    unsigned long long* counters = nullptr;
-    double* dbt = nullptr;
-    PR_TRY(dalloc(h, &mem, n_p));
-    PR_TRY(dalloc(h, &pos_comp, n_p));
-    PR_TRY(dalloc(h, &cstart, n_comp + 1));
-    PR_TRY(dalloc(h, &next, n_comp));
-    PR_TRY(dalloc(h, &status, n_p));
-    PR_TRY(dalloc(h, &rep_slot, n_comp));
-    PR_TRY(dalloc(h, &rep_patch, n_p));
-    PR_TRY(dalloc(h, &slot_of_patch, n_p));
-    PR_TRY(dalloc(h, &repof, n_p));
-    PR_TRY(dalloc(h, &active, n_comp));
-    PR_TRY(dalloc(h, &cand, n_p));
-    PR_TRY(dalloc(h, &ctl, 8));
-    PR_TRY(dalloc(h, &counters, 4));
-    PR_TRY(dalloc(h, &dbt, (size_t)n_p * stride));
-    launch_a1_key2(n_p, flag, excl, sidx, keys, mem, s);
-    launch_sort_pairs(keys, mem, n_p, kscr, vscr, s);
-    launch_a1_cstart(n_p, n_comp, keys, pos_comp, cstart, next, s);
-    PR_HIP(h, hipMemsetAsync(status, 0, n_p * sizeof(int32_t), s));
-    PR_HIP(h, hipMemsetAsync(ctl, 0, 8 * sizeof(int32_t), s));
-    PR_HIP(h, hipMemsetAsync(counters, 0, 4 * sizeof(unsigned long long), s));
-    d.ctl = ctl;
-    d.counters = counters;
-    d.cstart = cstart;
-    d.next = next;
-    d.mem = mem;
-    d.pos_comp = pos_comp;
-    d.status = status;
-    d.rep_slot = rep_slot;
-    d.rep_patch = rep_patch;
-    d.slot_of_patch = slot_of_patch;
-    d.repof = repof;
-    d.active = active;
-    d.cand = cand;
-    d.dbt = dbt;
-    // 4. rounds, all components at once, until no component opens an entry
-    int batch = 2;
-    int32_t c8[8];
-    for (;;) {
-        launch_a1_rounds(batch, d, crit, h->prm.eps, h->max_ps, s);
-        PR_HIP(h, hipMemcpyAsync(c8, ctl, sizeof(c8), hipMemcpyDeviceToHost, s));
-        PR_HIP(h, hipStreamSynchronize(s));
-        if (c8[2]) break;
-        if (batch < 64) batch *= 2;
-    }
-    PR_HIP(h, hipGetLastError());
-    if (c8[5] != 0)
-        return pr_fail(h, PR_ERR_SINGULAR_PATCH, "zero pivot in database patch " + std::to_string(c8[5] - 1));
-    h->m_p = c8[0];
-    // 5. entries numbered by ascending patch id
+    A1Run R;
+    PR_TRY(alg1_core(h, nullptr, n_p, R));
+    h->m_p = R.m;
+    // entries numbered by ascending patch id
     PR_TRY(dalloc(h, &h->phi, n_p));
     PR_TRY(dalloc(h, &h->reps, n_p));
     PR_TRY(dalloc(h, &h->db, (size_t)h->m_p * stride));
-    launch_a1_finish(n_p, repof, flag, excl, scr, h->phi, h->reps, s);
-    launch_a1_copy_db(h->m_p, h->reps, slot_of_patch, h->pptr, dbt, h->db, stride, s);
-    unsigned long long cnt[4];
-    PR_HIP(h, hipMemcpyAsync(cnt, counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    launch_a1_finish(n_p, R.repof, R.flag, R.excl, R.scr, h->phi, h->reps, s);
+    launch_a1_copy_db(h->m_p, h->reps, R.slot_of_patch, h->pptr, R.dbt, h->db, stride, s);
     h->reps_host.resize(h->m_p);
     PR_HIP(h, hipMemcpyAsync(h->reps_host.data(), h->reps, h->m_p * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     std::vector<int64_t> pptr_host(n_p + 1);
@@ -162,9 +62,9 @@ int run_alg1(pr_handle h) {
     std::vector<int32_t> phi_h(n_p);
     PR_HIP(h, hipMemcpyAsync(phi_h.data(), h->phi, n_p * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     PR_HIP(h, hipStreamSynchronize(s));
-    h->stats.crit_evals = (int64_t)cnt[0];
-    h->stats.crit_exact = (int64_t)cnt[1];
-    h->stats.alg1_rounds = c8[4];
+    h->stats.crit_evals = (int64_t)R.cnt[0];
+    h->stats.crit_exact = (int64_t)R.cnt[1];
+    h->stats.alg1_rounds = R.rounds;
     // pairs the sequential algorithm compares: patch i against the entries of
     // its size up to its own (excluded for an entry's patch); the rest were
     // skipped by the certified bound
@@ -698,6 +598,99 @@ int ensure_workspace(pr_handle h, int m) {
 
 }  // namespace
 
+// Algorithm 1 on subset[0..ns) (all patches when subset is null).
+int alg1_core(pr_handle h, const int32_t* subset, int64_t ns, A1Run& R) {
+    hipStream_t s = h->stream;
+    const int64_t n_p = h->n_p;
+    const int64_t stride = (int64_t)h->max_ps * h->max_ps;
+    const int crit = h->prm.criterion;
+    const double* keynorm = (crit == PR_CRIT_L1) ? h->l1norm : h->fnorm;
+    const int64_t N = next_pow2(ns);
+    uint64_t *keys = nullptr, *kscr = nullptr;
+    int32_t *sidx = nullptr, *vscr = nullptr;
+    PR_TRY(dalloc(h, &keys, ns));
+    PR_TRY(dalloc(h, &kscr, N));
+    PR_TRY(dalloc(h, &sidx, ns));
+    PR_TRY(dalloc(h, &vscr, N));
+    PR_TRY(dalloc(h, &R.flag, ns + 1));
+    PR_TRY(dalloc(h, &R.excl, ns + 1));
+    PR_TRY(dalloc(h, &R.scr, scan_scratch_elems(ns + 1) + 2));
+    // 1. sort by (size, key); 2. components where no match can cross a gap
+    launch_a1_keys(ns, subset, h->pptr, keynorm, keys, sidx, s);
+    launch_sort_pairs(keys, sidx, ns, kscr, vscr, s);
+    launch_a1_comp_flags(ns, sidx, h->pptr, keynorm, crit, h->prm.eps, R.flag, s);
+    launch_exclusive_scan_i64(R.flag, R.excl, ns + 1, R.scr, s);
+    int64_t n_comp = 0;
+    PR_HIP(h, hipMemcpyAsync(&n_comp, R.excl + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    PR_HIP(h, hipStreamSynchronize(s));
+    // 3. members of each component in ascending patch id
+    A1Dev d{};
+    d.n_p = ns;
+    d.n_comp = n_comp;
+    d.ptr = h->pptr;
+    d.tiles = h->tiles;
+    d.toff = h->uniform ? nullptr : h->toff;
+    d.uniform_ps = h->uniform ? h->max_ps : 0;
+    d.stride = stride;
+    int32_t *mem = nullptr, *pos_comp = nullptr, *cstart = nullptr, *next = nullptr, *status = nullptr;
+    int32_t *rep_slot = nullptr, *rep_patch = nullptr;
+    int32_t *active = nullptr, *cand = nullptr, *ctl = nullptr;
+    unsigned long long* counters = nullptr;
+    PR_TRY(dalloc(h, &mem, ns));
+    PR_TRY(dalloc(h, &pos_comp, ns));
+    PR_TRY(dalloc(h, &cstart, n_comp + 1));
+    PR_TRY(dalloc(h, &next, n_comp));
+    PR_TRY(dalloc(h, &status, ns));
+    PR_TRY(dalloc(h, &rep_slot, n_comp));
+    PR_TRY(dalloc(h, &rep_patch, ns));
+    PR_TRY(dalloc(h, &R.slot_of_patch, n_p));
+    PR_TRY(dalloc(h, &R.repof, n_p));
+    PR_TRY(dalloc(h, &active, n_comp));
+    PR_TRY(dalloc(h, &cand, ns));
+    PR_TRY(dalloc(h, &ctl, 8));
+    PR_TRY(dalloc(h, &counters, 4));
+    PR_TRY(dalloc(h, &R.dbt, (size_t)ns * stride));
+    launch_a1_key2(ns, R.flag, R.excl, sidx, keys, mem, s);
+    launch_sort_pairs(keys, mem, ns, kscr, vscr, s);
+    launch_a1_cstart(ns, n_comp, keys, pos_comp, cstart, next, s);
+    PR_HIP(h, hipMemsetAsync(status, 0, ns * sizeof(int32_t), s));
+    PR_HIP(h, hipMemsetAsync(ctl, 0, 8 * sizeof(int32_t), s));
+    PR_HIP(h, hipMemsetAsync(counters, 0, 4 * sizeof(unsigned long long), s));
+    d.ctl = ctl;
+    d.counters = counters;
+    d.cstart = cstart;
+    d.next = next;
+    d.mem = mem;
+    d.pos_comp = pos_comp;
+    d.status = status;
+    d.rep_slot = rep_slot;
+    d.rep_patch = rep_patch;
+    d.slot_of_patch = R.slot_of_patch;
+    d.repof = R.repof;
+    d.active = active;
+    d.cand = cand;
+    d.dbt = R.dbt;
+    // 4. rounds, all components at once, until no component opens an entry
+    int batch = 2;
+    int32_t c8[8];
+    for (;;) {
+        launch_a1_rounds(batch, d, crit, h->prm.eps, h->max_ps, s);
+        PR_HIP(h, hipMemcpyAsync(c8, ctl, sizeof(c8), hipMemcpyDeviceToHost, s));
+        PR_HIP(h, hipStreamSynchronize(s));
+        if (c8[2]) break;
+        if (batch < 64) batch *= 2;
+    }
+    PR_HIP(h, hipGetLastError());
+    if (c8[5] != 0)
+        return pr_fail(h, PR_ERR_SINGULAR_PATCH, "zero pivot in database patch " + std::to_string(c8[5] - 1));
+    R.m = c8[0];
+    R.rounds = c8[4];
+    PR_HIP(h, hipMemcpyAsync(R.cnt, counters, sizeof(R.cnt), hipMemcpyDeviceToHost, s));
+    PR_HIP(h, hipStreamSynchronize(s));
+    return PR_OK;
+}
+
+
 void pr_set_global_error(const std::string& s) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_last_error = s;
@@ -729,6 +722,15 @@ void pr_params_default(pr_params* p) {
     p->max_iters = 10000;
     p->deterministic = 0;
     p->stream = nullptr;
+    p->mlp = 0;
+    p->mlp_topk = 4;
+    p->mlp_train_frac = 0.1;
+    p->mlp_epochs = 60;
+    p->mlp_hidden = 64;
+    p->mlp_seed = 6;
+    p->mlp_lr = 3e-3;
+    p->mlp_batch = 256;
+    p->mlp_precision = PR_FP16;
 }
 
 const char* pr_status_string(int st) {
@@ -828,6 +830,11 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
     if (pm.algo != PR_ALGO_FULL && pm.algo != PR_ALGO_TOLERANCE &&
         (pm.kmeans_max_iter < 1 || !(pm.tie_rel >= 0.0)))
         return pr_fail(nullptr, PR_ERR_INVALID_ARG, "bad clustering parameter");
+    if (pm.mlp && (pm.algo != PR_ALGO_TOLERANCE || pm.mlp_topk < 1 || pm.mlp_topk > 8 ||
+                   !(pm.mlp_train_frac > 0.0 && pm.mlp_train_frac <= 1.0) || pm.mlp_epochs < 0 ||
+                   pm.mlp_hidden < 1 || pm.mlp_hidden > 1024 || pm.mlp_batch < 1 || !(pm.mlp_lr > 0.0) ||
+                   (pm.mlp_precision != PR_FP16 && pm.mlp_precision != PR_FP32)))
+        return pr_fail(nullptr, PR_ERR_INVALID_ARG, "bad predictor parameter");
     {
         int rc;
         if ((rc = check_dev(nullptr, A->row_ptr, "A.row_ptr")) < 0) return rc;
@@ -942,6 +949,7 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
 
     // ---- database (Section 3) ----------------------------------------------
     if (pm.algo == PR_ALGO_FULL) SETUP_TRY(run_full(h));
+    else if (pm.algo == PR_ALGO_TOLERANCE && pm.mlp) SETUP_TRY(run_alg1_mlp(h));
     else if (pm.algo == PR_ALGO_TOLERANCE) SETUP_TRY(run_alg1(h));
     else SETUP_TRY(run_kmeans(h));
     SETUP_HIP(hipStreamSynchronize(s));

@@ -131,6 +131,17 @@ struct pr_handle_s {
     int64_t ws_restart = -1;
     std::vector<hipEvent_t> evpool;   // reusable events for per-kernel timing
 
+    // learned predictor (Algorithm 1 with predictions): training patches,
+    // the other patches and their top-k candidate entries
+    float* mlp_X = nullptr;       // raw features, float[n_p][mlp_F]
+    int mlp_F = 0;
+    int32_t* mlp_train = nullptr;
+    int64_t mlp_ns = 0;
+    int32_t* mlp_q = nullptr;
+    int64_t mlp_nq = 0;
+    int32_t* mlp_cand = nullptr;
+    int mlp_k = 0;
+
     pr_solve_info sinfo{};
     pr_stats stats{};
     std::string last_error;
@@ -157,6 +168,42 @@ int pr_fail(pr_handle h, int code, const std::string& msg);
         int _s = (expr);             \
         if (_s < 0) return _s;       \
     } while (0)
+
+// device allocation owned by the handle (freed by pr_destroy)
+template <typename T>
+int dalloc(pr_handle h, T** p, size_t count) {
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return pr_fail(h, PR_ERR_OOM, std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
+                                          " bytes failed: " + hipGetErrorString(e));
+    }
+    h->owned.push_back({(void*)*p, count * sizeof(T)});
+    return PR_OK;
+}
+
+inline int64_t next_pow2(int64_t n) {
+    int64_t N = 1024;
+    while (N < n) N <<= 1;
+    return N;
+}
+
+// Algorithm 1 on a subset of the patches (pr_api.hip).  subset: device
+// int32[ns] of patch ids in ascending order, or null for all patches.
+struct A1Run {
+    int64_t m = 0;                     // entries found
+    int32_t* repof = nullptr;          // int32[n_p]: entry patch of each subset patch
+    int32_t* slot_of_patch = nullptr;  // int32[n_p]: slot of an entry's inverse in dbt
+    double* dbt = nullptr;             // FP64 inverses by slot
+    int64_t* flag = nullptr;           // int64[ns+1] scratch
+    int64_t* excl = nullptr;           // int64[ns+1] scratch
+    int64_t* scr = nullptr;            // scan scratch
+    unsigned long long cnt[4] = {0, 0, 0, 0};   // evaluations, exact singular values
+    int rounds = 0;
+};
+int alg1_core(pr_handle h, const int32_t* subset, int64_t ns, A1Run& R);
 
 // ---------------------------------------------------------------------------
 // launchers (one translation unit each)
@@ -218,8 +265,13 @@ struct A1Dev {
     double* dbt;              // inverses by slot, stride doubles each
     int64_t stride;
 };
-void launch_a1_keys(int64_t n_p, const int64_t* ptr, const double* keynorm, uint64_t* keys,
-                    int32_t* vals, hipStream_t s);
+void launch_a1_keys(int64_t n_p, const int32_t* subset, const int64_t* ptr, const double* keynorm,
+                    uint64_t* keys, int32_t* vals, hipStream_t s);
+// entries of a subset run in ascending patch id: entries[r] and
+// rank_of_patch[entry] = base + r
+void launch_a1_subset_entries(int64_t ns, const int32_t* subset, const int32_t* repof, int64_t* flags,
+                              int64_t* rank, int64_t* scr, int32_t base, int32_t* entries,
+                              int32_t* rank_of_patch, hipStream_t s);
 void launch_a1_comp_flags(int64_t n_p, const int32_t* sidx, const int64_t* ptr, const double* keynorm,
                           int crit, double eps, int64_t* flag, hipStream_t s);
 void launch_a1_key2(int64_t n_p, const int64_t* flag, const int64_t* excl, const int32_t* sidx,
@@ -254,6 +306,46 @@ void launch_km_gid(int64_t n, const uint64_t* keys, const int32_t* vals, const i
                    const int64_t* excl, int32_t* pg, int64_t* gstart, int32_t* gp, hipStream_t s);
 void launch_km_key2(int64_t n_p, const int32_t* pg, uint64_t* keys, int32_t* vals, hipStream_t s);
 void launch_gather_i32(int64_t n, const int32_t* src, const int64_t* idx, int32_t* out, hipStream_t s);
+
+// k_mlp.hip: learned entry predictor (see that file)
+void launch_mlp_features(int64_t n_p, const int64_t* ptr, const double* tiles, const int64_t* toff, int ups,
+                         const uint32_t* bkeys, int pmax, float* out, hipStream_t s);
+void launch_mlp_moments(int64_t nrows, const int32_t* rows, const float* X, int F, float* mu, float* sd,
+                        hipStream_t s);
+void launch_mlp_gather(int64_t nrows, const int32_t* rows, const float* X, int F, const float* mu,
+                       const float* sd, float* Xn, const int32_t* lab_src, int32_t* lab, const int32_t* key_src,
+                       int32_t* key, hipStream_t s);
+void launch_gemm(int prec, bool ta, bool tb, int M, int N, int K, const float* A, int lda, const float* B,
+                 int ldb, float* C, int ldc, float alpha, const float* bias, int relu, const float* mask,
+                 int ldm, hipStream_t s);
+void launch_softmax_ce(int B, int C, const float* L, int ldl, const int32_t* y, const int32_t* rkey,
+                       const int32_t* ckey, float* G, int ldg, double* loss_rows, float scale, hipStream_t s);
+void launch_colsum(int B, int N, const float* G, int ldg, float scale, float* out, hipStream_t s);
+void launch_adam(int64_t n, float* P, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
+                 float bc1, float bc2, hipStream_t s);
+void launch_init_uniform(int64_t n, float* W, float a, uint64_t seed, uint64_t base, hipStream_t s);
+void launch_topk(int64_t R, int C, const float* L, int ldl, int k, const int32_t* rkey, const int32_t* ckey,
+                 int32_t* out, hipStream_t s);
+void launch_mlp_match(int mode, int64_t nq, const int32_t* qids, const int32_t* cand, int k,
+                      const int64_t* ptr, const double* tiles, const int64_t* toff, int ups,
+                      const int32_t* entries, int64_t n0, const double* X0, int64_t stride, int crit, double eps,
+                      const double* keynorm, int32_t* repof, int32_t* resolved, unsigned long long* counters,
+                      hipStream_t s);
+void launch_compact_flags(int64_t n, const int32_t* keep, int want, int64_t* f, hipStream_t s);
+void launch_compact(int64_t n, const int32_t* ids, const int64_t* f, const int64_t* pos, int32_t* out,
+                    hipStream_t s);
+void launch_copy_at(int64_t n, const int32_t* ids, const int32_t* src, int32_t* dst, hipStream_t s);
+void launch_map_at(int64_t n, const int32_t* ids, const int32_t* src, const int32_t* map, int32_t* out,
+                   hipStream_t s);
+void launch_sizes(int64_t n, const int32_t* ids, const int64_t* ptr, int32_t* out, hipStream_t s);
+void launch_count_eq(int64_t n, const int32_t* a, int sa, const int32_t* b, unsigned long long* cnt,
+                     hipStream_t s);
+void launch_rows_gather(int64_t n, const int32_t* idx, const float* src, int F, float* dst, const int32_t* lsrc,
+                        int32_t* ldst, const int32_t* ksrc, int32_t* kdst, hipStream_t s);
+void launch_set_at(int64_t n, const int32_t* ids, int32_t v, int32_t* dst, hipStream_t s);
+
+// pr_mlp.hip: Algorithm 1 with the learned predictor
+int run_alg1_mlp(pr_handle h);
 
 // k_apply.hip
 struct ApplyLaunch {

@@ -4,6 +4,7 @@ status codes."""
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -13,6 +14,7 @@ import paper_2306_10025_amd as pr
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "patchrelax.h")
+INCLUDE = HEADER
 
 pytestmark = pytest.mark.skipif(not os.path.exists(pr.LIB_PATH),
                                 reason="libpatchrelax.so not built (run __graft_entry__.build())")
@@ -45,7 +47,29 @@ def test_param_defaults_and_struct_layout():
     assert p.algo == 0 and p.criterion == 0 and p.eps == 1e-8 and p.kmeans_max_iter == 100
     assert p.seed == 5 and p.tie_rel == 1e-9 and p.omega == 1.0 and p.sweeps == 1
     assert p.gmres_restart == 30 and p.max_iters == 10000 and p.partition_bc == 1
-    assert ctypes.sizeof(pr.pr_params) == 96
+    assert p.mlp == 0 and p.mlp_topk == 4 and p.mlp_train_frac == 0.1 and p.mlp_hidden == 64
+    assert p.mlp_precision == pr.PREC["fp16"]
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    # the binding's ctypes structs against gcc's layout of the header
+    structs = [pr.pr_params, pr.pr_stats, pr.pr_solve_info, pr.pr_csr, pr.pr_patches]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{INCLUDE}"', 'int main(void) {']
+    for S in structs:
+        lines.append(f'printf("{S.__name__} %zu\\n", sizeof({S.__name__}));')
+        for f, _ in S._fields_:
+            lines.append(f'printf("{S.__name__}.{f} %zu\\n", offsetof({S.__name__}, {f}));')
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-o", str(exe), str(src)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for S in structs:
+        assert int(got[S.__name__]) == ctypes.sizeof(S), S.__name__
+        for f, _ in S._fields_:
+            assert int(got[f"{S.__name__}.{f}"]) == getattr(S, f).offset, (S.__name__, f)
 
 
 def test_status_strings():

@@ -207,3 +207,21 @@ def test_kmeans_groups_never_mix_sizes():
     for j in range(3):
         sizes = {tiles[i].shape[0] for i in np.flatnonzero(res['phi'] == j)}
         assert len(sizes) <= 1
+
+
+def test_alg1_mixed_sizes_runs_each_size_on_its_own():
+    # interleaved sizes: the joint run equals the per-size runs, with entries
+    # numbered in one ascending-id order
+    P = gen.uneven_stokes_batch(n_sys=3, nmin=2, nmax=4)
+    t = O.patch_tiles(P.A, P.ptr, P.dofs)
+    res = O.alg1_tolerance(t, 1e-8)
+    sizes = np.array([x.shape[0] for x in t])
+    assert len(set(sizes)) > 1
+    rep_of = {}
+    for s in sorted(set(sizes)):
+        ids = np.flatnonzero(sizes == s)
+        r = O.alg1_tolerance([t[i] for i in ids], 1e-8)
+        for q, i in enumerate(ids):
+            rep_of[int(i)] = int(ids[r["reps"][r["phi"][q]]])
+    assert sorted(set(rep_of.values())) == list(res["reps"])
+    assert all(int(res["reps"][res["phi"][i]]) == rep_of[i] for i in range(len(t)))

@@ -123,3 +123,24 @@ def test_predictions_keep_the_tolerance_invariant():
     assert r["accepted"] + r["scanned"] + r["appended"] == n - len(train)
     # entries are the training entries followed by appended patches, ascending
     assert np.all(np.diff(r["reps"][r["n_train_entries"]:]) > 0)
+
+
+def test_round_sig_is_ieee_half_rounding_in_range():
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(20000) * 10.0 ** rng.uniform(-4, 4, 20000)
+    x = x[(np.abs(x) >= 2.0 ** -14) & (np.abs(x) <= 60000)]
+    assert np.array_equal(M.round_sig(x, 11), x.astype(np.float16).astype(np.float64))
+    # ties go to even
+    assert M.round_sig(1.0 + 2.0 ** -11, 11) == 1.0
+    assert M.round_sig(1.0 + 3 * 2.0 ** -11, 11) == 1.0 + 2 * 2.0 ** -10
+    # no range: far below FP16's smallest normal the significand still has 11 bits
+    assert M.round_sig(3.0e-9, 11) == np.ldexp(np.round(np.frexp(3.0e-9)[0] * 2048) / 2048, np.frexp(3.0e-9)[1])
+
+
+def test_operand_rounding_changes_only_the_products():
+    P, X, y, allowed = _rand_problem(4)
+    l0, g0 = M.loss_and_grads(P, X, y, allowed)
+    l1, g1 = M.loss_and_grads(P, X, y, allowed, operand_bits=53)
+    assert l0 == l1 and all(np.array_equal(g0[k], g1[k]) for k in g0)
+    l2, g2 = M.loss_and_grads(P, X, y, allowed, operand_bits=11)
+    assert abs(l2 - l0) < 1e-2 * abs(l0) and abs(l2 - l0) > 0
