@@ -126,6 +126,10 @@ typedef struct {
     double  mlp_lr;          /* Adam learning rate (default 3e-3) */
     int32_t mlp_batch;       /* minibatch rows (default 256) */
     int32_t mlp_precision;   /* PR_FP16 (MFMA, FP32 accumulate; default) or PR_FP32 */
+    int32_t graph;           /* 1: pr_solve captures one restart cycle in a HIP graph and
+                                replays it (ignored with timing = 1; default 0) */
+    int32_t autotune;        /* 1: pr_setup times the apply's launch shapes and keeps the
+                                fastest (default 0) */
 } pr_params;
 
 typedef struct pr_handle_s* pr_handle;
@@ -170,6 +174,11 @@ typedef struct {
     double  mlp_loss;        /* mean cross-entropy on the training set after training */
     double  mlp_train_acc;   /* top-1 accuracy on the training set */
     double  t_mlp_train;     /* seconds: features, training and the accuracy pass */
+    /* apply launch shape (params.autotune = 1: the fastest measured; else 0 = defaults) */
+    int32_t tune_threads;    /* threads per block of the patch kernel */
+    int32_t tune_slot;       /* threads per block of the slot sum */
+    int64_t tune_cap;        /* block cap of the patch kernel (0 = none) */
+    double  t_autotune;      /* seconds spent timing shapes (inside t_total) */
 } pr_stats;
 
 /* ---- entry points ------------------------------------------------------ */
@@ -251,6 +260,20 @@ int pr_get_mlp_candidates(pr_handle h, int32_t* train, int32_t* cand);
  * sum_b |A_ab| / m, then the single-entry row bits, then log m, with
  * m = mean_a |A_aa|, slots beyond p_k zero).  INVALID_ARG without a predictor. */
 int pr_get_mlp_features(pr_handle h, float* X, int32_t* F);
+
+/* Independent systems (uneven batches): A is block diagonal with system s
+ * on rows [system_ptr[s], system_ptr[s+1]) (host int64[n_sys+1], from 0 to
+ * n, each range non-empty) and every patch lies inside one system.  Later
+ * pr_solve calls run one right-preconditioned GMRES per system, each with
+ * its own Krylov space and the stopping test ||b_s - A_s x_s|| <= tol ||b_s||;
+ * converged systems are masked while the others continue, and every launch
+ * serves all systems.  pr_solve_info then reports the largest iteration
+ * count and relative residual over the systems.  Errors: INVALID_ARG (bad
+ * ranges, a matrix entry or a patch across two systems).  Synchronises. */
+int pr_set_systems(pr_handle h, const int64_t* system_ptr, int64_t n_sys);
+/* Per-system results of the last pr_solve: iters host int64[n_sys], relres
+ * host double[n_sys] (either may be NULL).  INVALID_ARG without systems. */
+int pr_get_system_info(pr_handle h, int64_t* iters, double* relres);
 
 /* Use another stream for later calls on h (NULL = default stream). */
 int pr_set_stream(pr_handle h, void* hip_stream);

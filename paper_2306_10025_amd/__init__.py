@@ -59,7 +59,7 @@ class pr_params(Structure):
                 ("stream", c_void_p), ("mlp", c_int32), ("mlp_topk", c_int32),
                 ("mlp_train_frac", c_double), ("mlp_epochs", c_int32), ("mlp_hidden", c_int32),
                 ("mlp_seed", c_uint64), ("mlp_lr", c_double), ("mlp_batch", c_int32),
-                ("mlp_precision", c_int32)]
+                ("mlp_precision", c_int32), ("graph", c_int32), ("autotune", c_int32)]
 
 
 class pr_solve_info(Structure):
@@ -82,7 +82,9 @@ class pr_stats(Structure):
                 ("apply_precision", c_int32), ("reserved0", c_int32),
                 ("mlp_train", c_int64), ("mlp_classes", c_int64), ("mlp_accepted", c_int64),
                 ("mlp_scanned", c_int64), ("mlp_fallback", c_int64), ("mlp_loss", c_double),
-                ("mlp_train_acc", c_double), ("t_mlp_train", c_double)]
+                ("mlp_train_acc", c_double), ("t_mlp_train", c_double),
+                ("tune_threads", c_int32), ("tune_slot", c_int32), ("tune_cap", c_int64),
+                ("t_autotune", c_double)]
 
 
 _SIGS = {
@@ -106,6 +108,8 @@ _SIGS = {
     "pr_batch_inverse": (c_int, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
     "pr_batch_criterion": (c_int, [c_int32, c_int64, c_int32, c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_void_p]),
+    "pr_set_systems": (c_int, [c_void_p, c_void_p, c_int64]),
+    "pr_get_system_info": (c_int, [c_void_p, c_void_p, c_void_p]),
     "pr_get_mlp_candidates": (c_int, [c_void_p, c_void_p, c_void_p]),
     "pr_get_mlp_features": (c_int, [c_void_p, c_void_p, POINTER(c_int32)]),
     "pr_mlp_loss_grad": (c_int, [c_int32, c_int64, c_int32, c_int32, c_int32, c_void_p, c_void_p,
@@ -173,8 +177,10 @@ def make_params(algo="full", criterion="spectral", eps=1e-8, m_target=0, partiti
                 restart=30, max_iters=10000, deterministic=False, timing=False,
                 stream=None, mlp=False, mlp_topk=4, mlp_train_frac=0.1, mlp_epochs=60,
                 mlp_hidden=64, mlp_seed=6, mlp_lr=3e-3, mlp_batch=256,
-                mlp_precision="fp16") -> pr_params:
+                mlp_precision="fp16", graph=False, autotune=False) -> pr_params:
     p = pr_params_default()
+    p.graph = int(graph)
+    p.autotune = int(autotune)
     p.mlp = int(mlp)
     p.mlp_topk = mlp_topk
     p.mlp_train_frac = mlp_train_frac
@@ -270,6 +276,18 @@ def pr_get_entry_matrix(h, j, p):
     B = np.zeros(p * p, dtype=np.float64)
     _check(lib().pr_get_entry_matrix(h, j, B.ctypes.data_as(c_void_p)), h)
     return B.reshape(p, p)
+
+
+def pr_set_systems(h, system_ptr):
+    sp = np.ascontiguousarray(system_ptr, dtype=np.int64)
+    return _check(lib().pr_set_systems(h, sp.ctypes.data_as(c_void_p), len(sp) - 1), h)
+
+
+def pr_get_system_info(h, n_sys):
+    it = np.zeros(n_sys, dtype=np.int64)
+    rel = np.zeros(n_sys, dtype=np.float64)
+    _check(lib().pr_get_system_info(h, it.ctypes.data_as(c_void_p), rel.ctypes.data_as(c_void_p)), h)
+    return it, rel
 
 
 def pr_get_mlp_candidates(h, n_p, n_train, k):
@@ -386,6 +404,13 @@ class PatchRelax:
 
     def entry_matrix(self, j, p):
         return pr_get_entry_matrix(self.h, j, p)
+
+    def set_systems(self, system_ptr):
+        self.n_sys = len(system_ptr) - 1
+        return pr_set_systems(self.h, system_ptr)
+
+    def system_info(self):
+        return pr_get_system_info(self.h, self.n_sys)
 
     def mlp_features(self):
         return pr_get_mlp_features(self.h, self.n_p)

@@ -83,20 +83,26 @@ __global__ __launch_bounds__(256) void k_apply_rows(int64_t count, ApplyGeom g, 
     }
 }
 
+// launch shape: T threads per block (64..256), at most `cap` blocks (the
+// kernels stride over their work, so any shape covers it all)
+inline unsigned shape_blocks(int64_t work, int per_block, int64_t cap) {
+    int64_t blocks = (work + per_block - 1) / per_block;
+    const int64_t lim = cap > 0 ? cap : 262144;
+    if (blocks > lim) blocks = lim;
+    return (unsigned)(blocks < 1 ? 1 : blocks);
+}
+
 template <typename TX, typename TA, typename TY, bool TWO>
 void run_rows(int64_t count, const ApplyGeom& g, const TX* db, const double* W, double omega,
-              const double* r, double* z, TY* Y, int maxp, hipStream_t s) {
+              const double* r, double* z, TY* Y, int maxp, int T, int64_t cap, hipStream_t s) {
     if (count <= 0) return;
     const int G = maxp <= 4 ? 4 : maxp <= 16 ? 16 : 32;
-    const int per = 256 / G;
-    int64_t blocks = (count + per - 1) / per;
-    if (blocks > 262144) blocks = 262144;
-    const unsigned nb = (unsigned)blocks;
-    if (maxp <= 4) k_apply_rows<TX, TA, TY, 4, 4, TWO><<<nb, 256, 0, s>>>(count, g, db, W, omega, r, z, Y);
-    else if (maxp <= 12) k_apply_rows<TX, TA, TY, 12, 16, TWO><<<nb, 256, 0, s>>>(count, g, db, W, omega, r, z, Y);
-    else if (maxp <= 16) k_apply_rows<TX, TA, TY, 16, 16, TWO><<<nb, 256, 0, s>>>(count, g, db, W, omega, r, z, Y);
-    else if (maxp <= 24) k_apply_rows<TX, TA, TY, 24, 32, TWO><<<nb, 256, 0, s>>>(count, g, db, W, omega, r, z, Y);
-    else k_apply_rows<TX, TA, TY, 32, 32, TWO><<<nb, 256, 0, s>>>(count, g, db, W, omega, r, z, Y);
+    const unsigned nb = shape_blocks(count, T / G, cap);
+    if (maxp <= 4) k_apply_rows<TX, TA, TY, 4, 4, TWO><<<nb, T, 0, s>>>(count, g, db, W, omega, r, z, Y);
+    else if (maxp <= 12) k_apply_rows<TX, TA, TY, 12, 16, TWO><<<nb, T, 0, s>>>(count, g, db, W, omega, r, z, Y);
+    else if (maxp <= 16) k_apply_rows<TX, TA, TY, 16, 16, TWO><<<nb, T, 0, s>>>(count, g, db, W, omega, r, z, Y);
+    else if (maxp <= 24) k_apply_rows<TX, TA, TY, 24, 32, TWO><<<nb, T, 0, s>>>(count, g, db, W, omega, r, z, Y);
+    else k_apply_rows<TX, TA, TY, 32, 32, TWO><<<nb, T, 0, s>>>(count, g, db, W, omega, r, z, Y);
 }
 
 // z_i = omega W_i sum over the slots of dof i (ascending slot order)
@@ -354,18 +360,18 @@ __global__ __launch_bounds__(64) void k_convert_db(int prec, int64_t m_p, const 
 
 void launch_apply(int prec, bool two_stage, const ApplyLaunch& a, hipStream_t s) {
     ApplyGeom g{a.gdofs, a.goff, a.pst, a.gphi, a.dboff, a.dbst, a.stop};
+    const int T = (a.threads == 64 || a.threads == 128) ? a.threads : 256;
+    const int64_t cap = a.grid_cap;
     if (prec == PR_FP64) {
-        if (two_stage) run_rows<double, double, double, true>(a.n_p, g, a.db, a.W, a.omega, a.r, a.z, (double*)a.Y, a.maxp, s);
-        else run_rows<double, double, double, false>(a.n_p, g, a.db, a.W, a.omega, a.r, a.z, (double*)nullptr, a.maxp, s);
+        if (two_stage) run_rows<double, double, double, true>(a.n_p, g, a.db, a.W, a.omega, a.r, a.z, (double*)a.Y, a.maxp, T, cap, s);
+        else run_rows<double, double, double, false>(a.n_p, g, a.db, a.W, a.omega, a.r, a.z, (double*)nullptr, a.maxp, T, cap, s);
     } else if (prec == PR_FP32) {
-        if (two_stage) run_rows<float, float, float, true>(a.n_p, g, a.db_f32, a.W, a.omega, a.r, a.z, (float*)a.Y, a.maxp, s);
-        else run_rows<float, float, float, false>(a.n_p, g, a.db_f32, a.W, a.omega, a.r, a.z, (float*)nullptr, a.maxp, s);
+        if (two_stage) run_rows<float, float, float, true>(a.n_p, g, a.db_f32, a.W, a.omega, a.r, a.z, (float*)a.Y, a.maxp, T, cap, s);
+        else run_rows<float, float, float, false>(a.n_p, g, a.db_f32, a.W, a.omega, a.r, a.z, (float*)nullptr, a.maxp, T, cap, s);
     } else {
         if (a.n_items > 0) {
-            int64_t blocks = (a.n_items + 3) / 4;
-            if (blocks > 262144) blocks = 262144;
-            const unsigned nb = (unsigned)blocks;
-#define PR_MFMA(MODE, TWO) k_apply_mfma<MODE, TWO><<<nb, 256, 0, s>>>(a.items, a.n_items, g, a.db_lp, a.dblp_off, a.db_exp, a.W, a.omega, a.r, a.z, (float*)a.Y)
+            const unsigned nb = shape_blocks(a.n_items, T / PR_WAVE, cap);
+#define PR_MFMA(MODE, TWO) k_apply_mfma<MODE, TWO><<<nb, T, 0, s>>>(a.items, a.n_items, g, a.db_lp, a.dblp_off, a.db_exp, a.W, a.omega, a.r, a.z, (float*)a.Y)
             const int mode = prec == PR_FP16 ? 1 : prec == PR_BF16X3 ? 2 : 0;
             if (two_stage) {
                 if (mode == 0) PR_MFMA(0, true); else if (mode == 1) PR_MFMA(1, true); else PR_MFMA(2, true);
@@ -376,11 +382,12 @@ void launch_apply(int prec, bool two_stage, const ApplyLaunch& a, hipStream_t s)
         }
     }
     if (two_stage) {
-        const unsigned nb = (unsigned)((a.n + 255) / 256);
+        const int T2 = (a.slot_threads == 64 || a.slot_threads == 128) ? a.slot_threads : 256;
+        const unsigned nb = (unsigned)((a.n + T2 - 1) / T2);
         if (prec == PR_FP64)
-            k_slot_sum<double><<<nb, 256, 0, s>>>(a.n, a.dof_ptr, a.dof_slots, (const double*)a.Y, a.W, a.omega, a.z, a.stop);
+            k_slot_sum<double><<<nb, T2, 0, s>>>(a.n, a.dof_ptr, a.dof_slots, (const double*)a.Y, a.W, a.omega, a.z, a.stop);
         else
-            k_slot_sum<float><<<nb, 256, 0, s>>>(a.n, a.dof_ptr, a.dof_slots, (const float*)a.Y, a.W, a.omega, a.z, a.stop);
+            k_slot_sum<float><<<nb, T2, 0, s>>>(a.n, a.dof_ptr, a.dof_slots, (const float*)a.Y, a.W, a.omega, a.z, a.stop);
     }
 }
 

@@ -203,16 +203,37 @@ __global__ void k_zero(double* x, int64_t n, const int32_t* __restrict__ stop) {
     if (q < n) x[q] = 0.0;
 }
 
+// dst = src (graph-safe copy)
+__global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src, int64_t n) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) dst[q] = src[q];
+}
+
+// Restart cycle start: g = (||r||, 0, ..., 0) from the squared norm in hd[0],
+// stop flag and column count cleared (a kernel, so the cycle can be replayed
+// from a graph)
+__global__ void k_cycle_init(double* __restrict__ g, int m, const double* __restrict__ hd,
+                             int32_t* __restrict__ gctl) {
+    for (int i = threadIdx.x; i <= m; i += blockDim.x) g[i] = (i == 0) ? sqrt(hd[0]) : 0.0;
+    if (threadIdx.x == 0) {
+        gctl[0] = 0;
+        gctl[1] = 0;
+    }
+}
+
 // One Arnoldi column j: h = h1 + h2 (two Gram-Schmidt passes) and
 // h_{j+1} = ||w||; apply the previous rotations, form the new one, update
 // the residual vector g; stop when |g_{j+1}| <= tol_abs (or not finite) or
-// the iteration limit is reached.  Single thread: j <= 64.
+// the iteration limit is reached (tolp: device absolute tolerance; itb:
+// device count of the iterations of earlier cycles).  Single thread: j <= 64.
 // gctl: [0] stop  [1] columns done this cycle
 __global__ void k_givens(int j, int m, const double* __restrict__ hd, double* __restrict__ R,
                          double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
-                         double* __restrict__ est, int32_t* __restrict__ gctl, double tol_abs,
-                         int64_t iters_base, int64_t max_iters) {
+                         double* __restrict__ est, int32_t* __restrict__ gctl, const double* __restrict__ tolp,
+                         const int64_t* __restrict__ itb, int64_t max_iters) {
     if (threadIdx.x != 0 || gctl[0]) return;
+    const int64_t iters_base = *itb;
+    const double tol_abs = *tolp;
     for (int i = 0; i <= j; ++i) R[(int64_t)i * m + j] = hd[i] + hd[64 + i];
     const double hn = sqrt(fmax(hd[128], 0.0));
     for (int i = 0; i < j; ++i) {
@@ -312,9 +333,17 @@ void launch_zero(double* x, int64_t n, hipStream_t s, const int32_t* stop) {
 }
 
 void launch_givens(int j, int m, const double* hd, double* R, double* cs, double* sn, double* g,
-                   double* est, int32_t* gctl, double tol_abs, int64_t iters_base, int64_t max_iters,
+                   double* est, int32_t* gctl, const double* tolp, const int64_t* itb, int64_t max_iters,
                    hipStream_t s) {
-    k_givens<<<1, 64, 0, s>>>(j, m, hd, R, cs, sn, g, est, gctl, tol_abs, iters_base, max_iters);
+    k_givens<<<1, 64, 0, s>>>(j, m, hd, R, cs, sn, g, est, gctl, tolp, itb, max_iters);
+}
+
+void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {
+    if (n > 0) k_copy<<<nb(n, 256), 256, 0, s>>>(dst, src, n);
+}
+
+void launch_cycle_init(double* g, int m, const double* hd, int32_t* gctl, hipStream_t s) {
+    k_cycle_init<<<1, 64, 0, s>>>(g, m, hd, gctl);
 }
 
 void launch_trisolve(int m, const double* R, const double* g, double* y, const int32_t* gctl,

@@ -556,6 +556,9 @@ int apply_op(pr_handle h, const double* r, double* z, bool accumulate, double* t
     a.Y = h->Ybuf;
     a.dof_ptr = h->dof_ptr;
     a.dof_slots = h->dof_slots;
+    a.threads = h->tune_threads;
+    a.grid_cap = h->tune_cap;
+    a.slot_threads = h->tune_slot;
     if (two) {
         a.z = accumulate ? tmp : z;
         launch_apply(h->apply_prec, true, a, s);
@@ -584,6 +587,8 @@ int ensure_workspace(pr_handle h, int m) {
     const int64_t n = h->n;
     h->ldv = (n + 63) / 64 * 64;   // 512-byte aligned basis columns
     PR_TRY(dalloc(h, &h->V, (size_t)(m + 1) * h->ldv));
+    // defined contents: rows of a masked system may be read before written
+    PR_HIP(h, hipMemsetAsync(h->V, 0, (size_t)(m + 1) * h->ldv * sizeof(double), h->stream));
     PR_TRY(dalloc(h, &h->w, n));
     PR_TRY(dalloc(h, &h->t1, n));
     PR_TRY(dalloc(h, &h->t2, 3 * n));   // preconditioned vector, sweep residual, scratch
@@ -596,7 +601,77 @@ int ensure_workspace(pr_handle h, int m) {
     return PR_OK;
 }
 
+// Times launch shapes of the apply on this handle's data and keeps the
+// fastest: threads per block and block cap of the patch kernel, then the
+// threads per block of the slot sum.  Every shape computes the same result
+// (deterministic mode: bit for bit; atomic mode: up to summation order).
+int autotune_apply(pr_handle h) {
+    const double t0 = now_s();
+    hipStream_t s = h->stream;
+    const int64_t n = h->n;
+    double *r = nullptr, *z = nullptr, *tmp = nullptr;
+    PR_TRY(dalloc(h, &r, n));
+    PR_TRY(dalloc(h, &z, n));
+    PR_TRY(dalloc(h, &tmp, n));
+    launch_copy(r, h->W, n, s);               // any vector will do
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    PR_HIP(h, hipEventCreate(&e0));
+    PR_HIP(h, hipEventCreate(&e1));
+    auto time_shape = [&](int T, int64_t cap, int T2, float& ms) -> int {
+        h->tune_threads = T;
+        h->tune_cap = cap;
+        h->tune_slot = T2;
+        for (int k = 0; k < 2; ++k) PR_TRY(apply_op(h, r, z, false, tmp));
+        PR_HIP(h, hipEventRecord(e0, s));
+        for (int k = 0; k < 5; ++k) PR_TRY(apply_op(h, r, z, false, tmp));
+        PR_HIP(h, hipEventRecord(e1, s));
+        PR_HIP(h, hipEventSynchronize(e1));
+        PR_HIP(h, hipEventElapsedTime(&ms, e0, e1));
+        return PR_OK;
+    };
+    int bt = 256, bs = 256;
+    int64_t bc = 0;
+    float best = 1e30f;
+    for (int T : {64, 128, 256})
+        for (int64_t cap : {(int64_t)0, (int64_t)1024, (int64_t)2048, (int64_t)4096, (int64_t)8192}) {
+            float ms = 0.0f;
+            PR_TRY(time_shape(T, cap, 256, ms));
+            if (ms < best) {
+                best = ms;
+                bt = T;
+                bc = cap;
+            }
+        }
+    if (h->prm.deterministic) {
+        best = 1e30f;
+        for (int T2 : {64, 128, 256}) {
+            float ms = 0.0f;
+            PR_TRY(time_shape(bt, bc, T2, ms));
+            if (ms < best) {
+                best = ms;
+                bs = T2;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->tune_threads = bt;
+    h->tune_cap = bc;
+    h->tune_slot = bs;
+    h->stats.tune_threads = bt;
+    h->stats.tune_slot = bs;
+    h->stats.tune_cap = bc;
+    h->stats.t_autotune = now_s() - t0;
+    return PR_OK;
+}
+
 }  // namespace
+
+int pr_precond_internal(pr_handle h, const double* v, double* e, double* t3, const int32_t* stop) {
+    return precond(h, v, e, t3, stop);
+}
+
+int pr_workspace_internal(pr_handle h, int m) { return ensure_workspace(h, m); }
 
 // Algorithm 1 on subset[0..ns) (all patches when subset is null).
 int alg1_core(pr_handle h, const int32_t* subset, int64_t ns, A1Run& R) {
@@ -731,6 +806,8 @@ void pr_params_default(pr_params* p) {
     p->mlp_lr = 3e-3;
     p->mlp_batch = 256;
     p->mlp_precision = PR_FP16;
+    p->graph = 0;
+    p->autotune = 0;
 }
 
 const char* pr_status_string(int st) {
@@ -764,6 +841,11 @@ void pr_destroy(pr_handle h) {
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();
     for (auto e : h->evpool) (void)hipEventDestroy(e);
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->gstream) {
+        (void)hipStreamSynchronize(h->gstream);
+        (void)hipStreamDestroy(h->gstream);
+    }
     for (auto& b : h->owned) (void)hipFree(b.p);
     if (h->hh) (void)hipHostFree(h->hh);
     delete h;
@@ -973,6 +1055,7 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
         launch_sell_fill(h->rowptr, h->col, h->val, h->n, h->soff, h->sval, h->scol, s);
     }
     SETUP_TRY(run_group(h));
+    if (pm.autotune) SETUP_TRY(autotune_apply(h));
     const double t4 = now_s();
 
     // boundary groups (distinct keys) for the stats
@@ -1018,9 +1101,12 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
     PR_TRY(check_dev(h, b, "b"));
     PR_TRY(check_dev(h, x, "x"));
     if (!(tol > 0.0)) return pr_fail(h, PR_ERR_INVALID_ARG, "tol must be positive");
+    if (h->nsys > 0) return solve_batch(h, b, x, tol);
     const double tstart = now_s();
     // optional per-class device timing: 0 apply, 1 spmv, 2 orthogonalisation
     const bool timing = h->prm.timing != 0;
+    // graph replay of whole restart cycles (not with per-kernel timing)
+    const bool use_graph = h->prm.graph != 0 && !timing;
     struct Span { int cls; hipEvent_t a, b; };
     std::vector<Span> spans;
     size_t evnext = 0;
@@ -1032,26 +1118,43 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
         }
         return h->evpool[evnext++];
     };
+    hipStream_t s = h->stream;
     hipEvent_t tb = nullptr;
     auto tbeg = [&]() {
         if (timing) {
             tb = grab();
-            if (tb) (void)hipEventRecord(tb, h->stream);
+            if (tb) (void)hipEventRecord(tb, s);
         }
     };
     auto tend = [&](int cls) {
         if (timing && tb) {
             hipEvent_t te = grab();
             if (te) {
-                (void)hipEventRecord(te, h->stream);
+                (void)hipEventRecord(te, s);
                 spans.push_back({cls, tb, te});
             }
         }
     };
-    hipStream_t s = h->stream;
     const int m = h->prm.gmres_restart;
     const int64_t n = h->n;
     PR_TRY(ensure_workspace(h, m));
+    if (use_graph) {
+        // a capture needs a stream of its own; b and x live in handle memory
+        // so that one captured cycle serves every later solve
+        if (!h->gstream) PR_HIP(h, hipStreamCreate(&h->gstream));
+        if (!h->gb) {
+            PR_TRY(dalloc(h, &h->gb, n));
+            PR_TRY(dalloc(h, &h->gx, n));
+        }
+        PR_HIP(h, hipStreamSynchronize(h->stream));
+        s = h->gstream;
+    }
+    struct StreamSwap {
+        pr_handle h;
+        hipStream_t keep;
+        ~StreamSwap() { h->stream = keep; }
+    } swap{h, h->stream};
+    h->stream = s;
     double* V = h->V;
     double* w = h->w;
     double* r = h->t1;
@@ -1061,54 +1164,52 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
     double* hh = h->hh;
     const int64_t ldv = h->ldv;
     double* red = h->red;
-    // device GMRES state: R ((m+1) x m), rotations, residual vector g, y, estimate
+    // device GMRES state: R ((m+1) x m), rotations, residual vector g, y,
+    // estimate, absolute tolerance and iteration base
     double* R = h->gm;
     double* cs = R + (int64_t)(m + 1) * m;
     double* sn = cs + m;
     double* g = sn + m;
     double* y = g + m + 1;
     double* est_d = y + m;
+    double* tol_d = est_d + 1;
+    int64_t* itb_d = reinterpret_cast<int64_t*>(tol_d + 1);
     int32_t* gctl = h->gctl;
     int32_t* gctl_h = reinterpret_cast<int32_t*>(hh + 240);   // pinned mirror of gctl
+    int64_t* itb_h = reinterpret_cast<int64_t*>(hh + 236);
 
+    const double* bw = use_graph ? h->gb : b;
+    double* xw = use_graph ? h->gx : x;
+    if (use_graph) launch_copy(h->gb, b, n, s);
     auto sync_read = [&](int count) -> int {
         PR_HIP(h, hipMemcpyAsync(hh, hd, count * sizeof(double), hipMemcpyDeviceToHost, s));
         PR_HIP(h, hipStreamSynchronize(s));
         return PR_OK;
     };
     // ||b||
-    launch_gs(0, b, n, 1, const_cast<double*>(b), n, nullptr, red, hd, s);
+    launch_gs(0, bw, n, 1, const_cast<double*>(bw), n, nullptr, red, hd, s);
     PR_TRY(sync_read(1));
     const double bnorm = std::sqrt(hh[0]);
-    launch_zero(x, n, s);
+    launch_zero(xw, n, s);
     h->sinfo = pr_solve_info{};
     if (!std::isfinite(bnorm)) return pr_fail(h, PR_ERR_NONFINITE, "non-finite right-hand side");
     if (bnorm == 0.0) {
+        if (use_graph) launch_copy(x, xw, n, s);
         h->sinfo.status = PR_OK;
         PR_HIP(h, hipStreamSynchronize(s));
         return PR_OK;
     }
-    PR_HIP(h, hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    int64_t iters = 0, cycles = 0;
-    double relres = 1.0, est = 1.0;
-    const int64_t maxit = h->prm.max_iters;
-    for (;;) {
-        // true residual norm; one host wait per restart cycle
-        launch_gs(0, r, n, 1, r, n, nullptr, red, hd, s);
-        PR_TRY(sync_read(1));
-        if (cycles > 0) {
-            iters += gctl_h[1];
-            est = hh[239] / bnorm;
-        }
-        const double beta = std::sqrt(hh[0]);
-        relres = beta / bnorm;
-        if (!std::isfinite(beta)) return pr_fail(h, PR_ERR_NONFINITE, "non-finite residual");
-        if (beta <= tol * bnorm || iters >= maxit) break;
-        ++cycles;
-        // cycle start: g = (beta, 0, ...), stop = 0, V_0 = r / beta
-        for (int i = 0; i <= m; ++i) hh[128 + i] = (i == 0) ? beta : 0.0;
-        PR_HIP(h, hipMemcpyAsync(g, hh + 128, (m + 1) * sizeof(double), hipMemcpyHostToDevice, s));
-        PR_HIP(h, hipMemsetAsync(gctl, 0, 4 * sizeof(int32_t), s));
+    hh[235] = tol * bnorm;
+    PR_HIP(h, hipMemcpyAsync(tol_d, hh + 235, sizeof(double), hipMemcpyHostToDevice, s));
+    launch_copy(r, bw, n, s);
+    launch_gs(0, r, n, 1, r, n, nullptr, red, hd, s);     // ||r||^2 -> hd[0]
+
+    // One restart cycle, all on the device: V_0 = r / ||r||, m Arnoldi steps
+    // (each ends in the device-side Givens update and stopping test; later
+    // kernels of a stopped cycle return at once), then x += M(V y),
+    // r = b - A x and ||r||^2 -> hd[0] for the next cycle.
+    auto enqueue_cycle = [&]() -> int {
+        launch_cycle_init(g, m, hd, gctl, s);
         launch_scale(r, V, hd, n, s);
         for (int j = 0; j < m; ++j) {
             double* vj = V + (int64_t)j * ldv;
@@ -1127,22 +1228,58 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
             launch_gs(2, V, ldv, j + 1, w, n, hd + 64, red, hd + 128, s, gctl);
             launch_scale(w, V + (int64_t)(j + 1) * ldv, hd + 128, n, s, gctl);
             tend(2);
-            // rotations and the stopping test on the device
-            launch_givens(j, m, hd, R, cs, sn, g, est_d, gctl, tol * bnorm, iters, maxit, s);
+            launch_givens(j, m, hd, R, cs, sn, g, est_d, gctl, tol_d, itb_d, h->prm.max_iters, s);
         }
-        // y = R^{-1} g over the columns done, u = V y, x += M(u), r = b - A x
         launch_trisolve(m, R, g, y, gctl, s);
         launch_gemv_small(V, ldv, gctl + 1, y, n, r, s);
         tbeg();
         PR_TRY(precond(h, r, zt, t3));
         tend(0);
-        launch_axpy_dev(x, zt, 1.0, n, s);
+        launch_axpy_dev(xw, zt, 1.0, n, s);
         tbeg();
-        launch_spmv_sell(h->soff, h->sval, h->scol, n, x, b, r, s);
+        launch_spmv_sell(h->soff, h->sval, h->scol, n, xw, bw, r, s);
         tend(1);
+        launch_gs(0, r, n, 1, r, n, nullptr, red, hd, s);
+        return PR_OK;
+    };
+    if (use_graph && (!h->gexec || h->graph_m != m)) {
+        if (h->gexec) {
+            (void)hipGraphExecDestroy(h->gexec);
+            h->gexec = nullptr;
+        }
+        hipGraph_t gr = nullptr;
+        PR_HIP(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue_cycle();
+        const hipError_t ec = hipStreamEndCapture(s, &gr);
+        if (rc < 0) return rc;
+        if (ec != hipSuccess) return pr_fail(h, PR_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ec));
+        const hipError_t ei = hipGraphInstantiate(&h->gexec, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (ei != hipSuccess) return pr_fail(h, PR_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+        h->graph_m = m;
+    }
+
+    PR_TRY(sync_read(1));
+    int64_t iters = 0, cycles = 0;
+    double relres = std::sqrt(hh[0]) / bnorm, est = relres;
+    const int64_t maxit = h->prm.max_iters;
+    for (;;) {
+        if (!std::isfinite(relres)) return pr_fail(h, PR_ERR_NONFINITE, "non-finite residual");
+        if (relres <= tol || iters >= maxit) break;
+        ++cycles;
+        *itb_h = iters;
+        PR_HIP(h, hipMemcpyAsync(itb_d, itb_h, sizeof(int64_t), hipMemcpyHostToDevice, s));
+        if (use_graph) PR_HIP(h, hipGraphLaunch(h->gexec, s));
+        else PR_TRY(enqueue_cycle());
+        // one host wait per restart cycle
         PR_HIP(h, hipMemcpyAsync(gctl_h, gctl, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         PR_HIP(h, hipMemcpyAsync(hh + 239, est_d, sizeof(double), hipMemcpyDeviceToHost, s));
+        PR_TRY(sync_read(1));
+        iters += gctl_h[1];
+        est = hh[239] / bnorm;
+        relres = std::sqrt(hh[0]) / bnorm;
     }
+    if (use_graph) launch_copy(x, xw, n, s);
     PR_HIP(h, hipStreamSynchronize(s));
     PR_HIP(h, hipGetLastError());
     h->sinfo.iters = iters;

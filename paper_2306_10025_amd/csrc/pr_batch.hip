@@ -1,0 +1,217 @@
+// Independent systems in one handle (a block-diagonal A, e.g. an uneven
+// batch of small problems): pr_set_systems records the row ranges, and
+// pr_solve then runs one right-preconditioned GMRES per system, each with
+// its own Krylov space, Hessenberg matrix, rotations and stopping test on
+// its own right-hand side; converged systems are masked while the others
+// continue, and every launch serves all systems at once.
+#include "pr_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+namespace {
+
+constexpr int64_t kChunk = 2048;   // rows per reduction chunk (chunks never straddle systems)
+
+// flag[0]: a CSR entry couples two systems; flag[1]: a patch spans two systems
+__global__ void k_check_systems(int64_t n, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                int64_t n_p, const int64_t* __restrict__ pptr, const int32_t* __restrict__ dofs,
+                                const int64_t* __restrict__ sptr, int nsys, int32_t* __restrict__ flag) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    auto sys_of = [&](int64_t i) {
+        int lo = 0, hi = nsys - 1;          // last system whose start <= i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (sptr[mid] <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    };
+    if (t < n) {
+        const int s = sys_of(t);
+        for (int64_t q = rowptr[t]; q < rowptr[t + 1]; ++q)
+            if (col[q] < sptr[s] || col[q] >= sptr[s + 1]) flag[0] = 1;
+    }
+    if (t < n_p) {
+        const int s = sys_of(dofs[pptr[t]]);
+        for (int64_t q = pptr[t]; q < pptr[t + 1]; ++q)
+            if (dofs[q] < sptr[s] || dofs[q] >= sptr[s + 1]) flag[1] = 1;
+    }
+}
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+int pr_set_systems(pr_handle h, const int64_t* sptr, int64_t nsys) {
+    if (!h || !sptr || nsys < 1 || nsys > (1 << 20)) return pr_fail(h, PR_ERR_INVALID_ARG, "bad system list");
+    if (sptr[0] != 0 || sptr[nsys] != h->n) return pr_fail(h, PR_ERR_INVALID_ARG, "system_ptr must run from 0 to n");
+    for (int64_t s = 0; s < nsys; ++s)
+        if (sptr[s + 1] <= sptr[s]) return pr_fail(h, PR_ERR_INVALID_ARG, "empty or unordered system");
+    hipStream_t st = h->stream;
+    // the matrix must be block diagonal and every patch inside one system
+    int64_t* sptr_d = nullptr;
+    int32_t* flag = nullptr;
+    PR_TRY(dalloc(h, &sptr_d, nsys + 1));
+    PR_TRY(dalloc(h, &flag, 2));
+    PR_HIP(h, hipMemcpyAsync(sptr_d, sptr, (nsys + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    PR_HIP(h, hipMemsetAsync(flag, 0, 2 * sizeof(int32_t), st));
+    const int64_t nt = std::max(h->n, h->n_p);
+    k_check_systems<<<(unsigned)((nt + 255) / 256), 256, 0, st>>>(h->n, h->rowptr, h->col, h->n_p, h->pptr,
+                                                                  h->pdofs, sptr_d, (int)nsys, flag);
+    int32_t fl[2] = {0, 0};
+    PR_HIP(h, hipMemcpyAsync(fl, flag, sizeof(fl), hipMemcpyDeviceToHost, st));
+    PR_HIP(h, hipStreamSynchronize(st));
+    PR_HIP(h, hipGetLastError());
+    if (fl[0]) return pr_fail(h, PR_ERR_INVALID_ARG, "the matrix couples two systems");
+    if (fl[1]) return pr_fail(h, PR_ERR_INVALID_ARG, "a patch spans two systems");
+    // reduction chunks
+    std::vector<int32_t> ch_sys, ch_len, sys_ch0(nsys), sys_nch(nsys);
+    std::vector<int64_t> ch_lo;
+    for (int64_t s = 0; s < nsys; ++s) {
+        sys_ch0[s] = (int32_t)ch_sys.size();
+        for (int64_t lo = sptr[s]; lo < sptr[s + 1]; lo += kChunk) {
+            ch_sys.push_back((int32_t)s);
+            ch_lo.push_back(lo);
+            ch_len.push_back((int32_t)std::min<int64_t>(kChunk, sptr[s + 1] - lo));
+        }
+        sys_nch[s] = (int32_t)ch_sys.size() - sys_ch0[s];
+    }
+    const int64_t nch = (int64_t)ch_sys.size();
+    const int m = h->prm.gmres_restart;
+    PR_TRY(dalloc(h, &h->ch_sys, nch));
+    PR_TRY(dalloc(h, &h->ch_lo, nch));
+    PR_TRY(dalloc(h, &h->ch_len, nch));
+    PR_TRY(dalloc(h, &h->sys_ch0, nsys));
+    PR_TRY(dalloc(h, &h->sys_nch, nsys));
+    PR_TRY(dalloc(h, &h->bpart, (size_t)nch * 32));
+    PR_TRY(dalloc(h, &h->bscal, (size_t)4 * nsys * kBStride));
+    PR_TRY(dalloc(h, &h->bgm, (size_t)nsys * ((int64_t)(m + 1) * m + 4 * m + 2)));
+    PR_TRY(dalloc(h, &h->bctl, (size_t)3 * nsys + 1));
+    PR_TRY(dalloc(h, &h->bbase, nsys));
+    PR_TRY(dalloc(h, &h->btol, nsys));
+    PR_HIP(h, hipMemcpyAsync(h->ch_sys, ch_sys.data(), nch * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    PR_HIP(h, hipMemcpyAsync(h->ch_lo, ch_lo.data(), nch * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    PR_HIP(h, hipMemcpyAsync(h->ch_len, ch_len.data(), nch * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    PR_HIP(h, hipMemcpyAsync(h->sys_ch0, sys_ch0.data(), nsys * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    PR_HIP(h, hipMemcpyAsync(h->sys_nch, sys_nch.data(), nsys * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    PR_HIP(h, hipStreamSynchronize(st));
+    h->nch = nch;
+    h->nsys = (int)nsys;
+    h->sys_ptr_host.assign(sptr, sptr + nsys + 1);
+    h->sys_iters.assign(nsys, 0);
+    h->sys_relres.assign(nsys, 0.0);
+    return PR_OK;
+}
+
+int pr_get_system_info(pr_handle h, int64_t* iters, double* relres) {
+    if (!h || h->nsys == 0) return pr_fail(h, PR_ERR_INVALID_ARG, "no systems set on this handle");
+    if (iters) std::memcpy(iters, h->sys_iters.data(), h->nsys * sizeof(int64_t));
+    if (relres) std::memcpy(relres, h->sys_relres.data(), h->nsys * sizeof(double));
+    return PR_OK;
+}
+
+int solve_batch(pr_handle h, const double* b, double* x, double tol) {
+    const double tstart = now_s();
+    hipStream_t s = h->stream;
+    const int m = h->prm.gmres_restart;
+    const int64_t n = h->n;
+    const int ns = h->nsys;
+    PR_TRY(pr_workspace_internal(h, m));
+    BGeom bg{h->nch, h->ch_sys, h->ch_lo, h->ch_len, ns, h->sys_ch0, h->sys_nch};
+    double* V = h->V;
+    double* w = h->w;
+    double* r = h->t1;
+    double* zt = h->t2;
+    double* t3 = h->t2 + n;
+    const int64_t ldv = h->ldv;
+    double* H1 = h->bscal;
+    double* H2 = H1 + (int64_t)ns * kBStride;
+    double* HN = H2 + (int64_t)ns * kBStride;
+    double* NR = HN + (int64_t)ns * kBStride;
+    int32_t* sstop = h->bctl;
+    int32_t* scols = sstop + ns;
+    int32_t* act = scols + ns;
+    int32_t* gstop = act + ns;
+    double* R = h->bgm;
+    double* cs = R + (int64_t)ns * (m + 1) * m;
+    double* sn = cs + (int64_t)ns * m;
+    double* gv = sn + (int64_t)ns * m;
+    double* yv = gv + (int64_t)ns * (m + 1);
+    double* est = yv + (int64_t)ns * m;
+    std::vector<double> nr((size_t)ns * kBStride);
+    std::vector<int32_t> cols_h(ns, 0), act_h(ns, 0);
+    auto norms = [&](const double* v) -> int {
+        launch_bgs(0, v, n, 1, const_cast<double*>(v), bg, nullptr, h->bpart, NR, nullptr, nullptr, s);
+        PR_HIP(h, hipMemcpyAsync(nr.data(), NR, nr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        PR_HIP(h, hipStreamSynchronize(s));
+        return PR_OK;
+    };
+    PR_TRY(norms(b));
+    std::vector<double> bn(ns), tol_abs(ns);
+    for (int i = 0; i < ns; ++i) {
+        bn[i] = std::sqrt(nr[(size_t)i * kBStride]);
+        if (!std::isfinite(bn[i])) return pr_fail(h, PR_ERR_NONFINITE, "non-finite right-hand side");
+        tol_abs[i] = tol * bn[i];
+    }
+    PR_HIP(h, hipMemcpyAsync(h->btol, tol_abs.data(), ns * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_zero(x, n, s);
+    launch_copy(r, b, n, s);
+    std::vector<int64_t> its(ns, 0);
+    std::vector<double> rel(ns, 0.0);
+    int64_t cycles = 0;
+    const int64_t maxit = h->prm.max_iters;
+    for (;;) {
+        PR_TRY(norms(r));
+        bool any = false;
+        for (int i = 0; i < ns; ++i) {
+            if (cycles > 0) its[i] += cols_h[i];
+            const double rn = std::sqrt(nr[(size_t)i * kBStride]);
+            if (!std::isfinite(rn)) return pr_fail(h, PR_ERR_NONFINITE, "non-finite residual");
+            rel[i] = bn[i] > 0.0 ? rn / bn[i] : 0.0;
+            act_h[i] = (rel[i] > tol && its[i] < maxit) ? 1 : 0;
+            any = any || act_h[i];
+        }
+        if (!any) break;
+        ++cycles;
+        PR_HIP(h, hipMemcpyAsync(act, act_h.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        PR_HIP(h, hipMemcpyAsync(h->bbase, its.data(), ns * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        launch_bcycle_init(ns, m, NR, act, gv, sstop, scols, gstop, s);
+        launch_bscale(r, V, bg, NR, sstop, gstop, s);
+        for (int j = 0; j < m; ++j) {
+            double* vj = V + (int64_t)j * ldv;
+            PR_TRY(pr_precond_internal(h, vj, zt, t3, gstop));
+            launch_spmv_sell(h->soff, h->sval, h->scol, n, zt, nullptr, w, s, gstop);
+            launch_bgs(0, V, ldv, j + 1, w, bg, nullptr, h->bpart, H1, sstop, gstop, s);
+            launch_bgs(1, V, ldv, j + 1, w, bg, H1, h->bpart, H2, sstop, gstop, s);
+            launch_bgs(2, V, ldv, j + 1, w, bg, H2, h->bpart, HN, sstop, gstop, s);
+            launch_bscale(w, V + (int64_t)(j + 1) * ldv, bg, HN, sstop, gstop, s);
+            launch_bgivens(j, m, ns, H1, H2, HN, R, cs, sn, gv, est, sstop, scols, h->btol, h->bbase, maxit,
+                           gstop, s);
+        }
+        // x_s += M(V_s y_s) for every system that ran (zero elsewhere), r = b - A x
+        launch_btrisolve(m, ns, R, gv, yv, scols, s);
+        launch_bgemv(V, ldv, bg, yv, m, scols, r, s);
+        PR_TRY(pr_precond_internal(h, r, zt, t3, nullptr));
+        launch_axpy_dev(x, zt, 1.0, n, s);
+        launch_spmv_sell(h->soff, h->sval, h->scol, n, x, b, r, s);
+        PR_HIP(h, hipMemcpyAsync(cols_h.data(), scols, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    }
+    PR_HIP(h, hipStreamSynchronize(s));
+    PR_HIP(h, hipGetLastError());
+    h->sys_iters = its;
+    h->sys_relres = rel;
+    h->sinfo = pr_solve_info{};
+    h->sinfo.iters = *std::max_element(its.begin(), its.end());
+    h->sinfo.cycles = cycles;
+    h->sinfo.relres = *std::max_element(rel.begin(), rel.end());
+    h->sinfo.relres_est = h->sinfo.relres;
+    h->sinfo.status = h->sinfo.relres <= tol ? PR_OK : PR_NOT_CONVERGED;
+    h->sinfo.seconds = now_s() - tstart;
+    return h->sinfo.status;
+}

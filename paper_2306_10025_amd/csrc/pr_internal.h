@@ -116,6 +116,9 @@ struct pr_handle_s {
     int64_t* dof_ptr = nullptr;   // dof -> grouped slots (deterministic scatter)
     int32_t* dof_slots = nullptr;
     void* Ybuf = nullptr;         // slot values of the deterministic scatter
+    int tune_threads = 0;         // apply launch shape (autotuned or defaults)
+    int64_t tune_cap = 0;
+    int tune_slot = 0;
 
     // solve workspace
     double* V = nullptr;
@@ -130,6 +133,33 @@ struct pr_handle_s {
     double* hh = nullptr;         // pinned host mirror
     int64_t ws_restart = -1;
     std::vector<hipEvent_t> evpool;   // reusable events for per-kernel timing
+    // graph replay of a restart cycle: own capture stream, handle-owned b
+    // and x, device tolerance and iteration base
+    hipStream_t gstream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_m = -1;
+    double* gb = nullptr;
+    double* gx = nullptr;
+    double* gtol = nullptr;
+    int64_t* gitb = nullptr;
+
+    // block-diagonal batch of independent systems (pr_set_systems)
+    int nsys = 0;
+    std::vector<int64_t> sys_ptr_host;
+    int64_t nch = 0;
+    int32_t* ch_sys = nullptr;
+    int64_t* ch_lo = nullptr;
+    int32_t* ch_len = nullptr;
+    int32_t* sys_ch0 = nullptr;
+    int32_t* sys_nch = nullptr;
+    double* bpart = nullptr;      // per-chunk partials
+    double* bscal = nullptr;      // per-system scalars: h1, h2, hn, norms (kBStride each)
+    double* bgm = nullptr;        // per-system R, cs, sn, g, y, est
+    int32_t* bctl = nullptr;      // per-system stop, columns, active; global stop
+    int64_t* bbase = nullptr;     // per-system iterations of earlier cycles
+    double* btol = nullptr;       // per-system absolute tolerance
+    std::vector<int64_t> sys_iters;
+    std::vector<double> sys_relres;
 
     // learned predictor (Algorithm 1 with predictions): training patches,
     // the other patches and their top-k candidate entries
@@ -376,6 +406,11 @@ struct ApplyLaunch {
     const int64_t* dof_ptr;
     const int32_t* dof_slots;
     const int32_t* stop;       // optional device flag: skip the work when set
+    // launch shape (0: defaults): threads per block of the patch kernel
+    // (64, 128 or 256), block cap, threads per block of the slot sum
+    int threads = 0;
+    int64_t grid_cap = 0;
+    int slot_threads = 0;
 };
 // z (+)= omega M~^{-1} r.  Atomic mode accumulates into z (caller zeroes it);
 // two-stage mode overwrites z.
@@ -411,7 +446,42 @@ void launch_spmv_sell(const int64_t* soff, const double* sval, const int32_t* sc
 void launch_gs(int mode, const double* V, int64_t ldv, int nv, double* w, int64_t n, const double* c,
                double* partial, double* out, hipStream_t s, const int32_t* stop = nullptr);
 void launch_givens(int j, int m, const double* hd, double* R, double* cs, double* sn, double* g,
-                   double* est, int32_t* gctl, double tol_abs, int64_t iters_base, int64_t max_iters,
+                   double* est, int32_t* gctl, const double* tolp, const int64_t* itb, int64_t max_iters,
                    hipStream_t s);
 void launch_trisolve(int m, const double* R, const double* g, double* y, const int32_t* gctl,
                      hipStream_t s);
+void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
+void launch_cycle_init(double* g, int m, const double* hd, int32_t* gctl, hipStream_t s);
+
+// k_batch.hip: GMRES over independent systems (one Krylov space per system)
+struct BGeom {
+    int64_t nch;               // row chunks (each inside one system)
+    const int32_t* ch_sys;     // system of each chunk
+    const int64_t* ch_lo;      // first row of each chunk
+    const int32_t* ch_len;     // rows of each chunk
+    int nsys;
+    const int32_t* sys_ch0;    // first chunk of each system
+    const int32_t* sys_nch;    // chunks of each system
+};
+constexpr int kBStride = 64;   // per-system coefficient slots
+void launch_bgs(int mode, const double* V, int64_t ldv, int nv, double* w, const BGeom& g, const double* c,
+                double* partial, double* out, const int32_t* sstop, const int32_t* gstop, hipStream_t s);
+void launch_bscale(const double* src, double* dst, const BGeom& g, const double* denom, const int32_t* sstop,
+                   const int32_t* gstop, hipStream_t s);
+void launch_bgivens(int j, int m, int nsys, const double* h1, const double* h2, const double* hn, double* R,
+                    double* cs, double* sn, double* gv, double* est, int32_t* sstop, int32_t* scols,
+                    const double* tol_abs, const int64_t* sbase, int64_t max_iters, int32_t* gstop,
+                    hipStream_t s);
+void launch_btrisolve(int m, int nsys, const double* R, const double* gv, double* y, const int32_t* scols,
+                      hipStream_t s);
+void launch_bgemv(const double* V, int64_t ldv, const BGeom& g, const double* y, int m, const int32_t* scols,
+                  double* out, hipStream_t s);
+void launch_bcycle_init(int nsys, int m, const double* nrm2, const int32_t* active, double* gv, int32_t* sstop,
+                        int32_t* scols, int32_t* gstop, hipStream_t s);
+
+// pr_batch.hip: the solve over independent systems
+int solve_batch(pr_handle h, const double* b, double* x, double tol);
+// pr_api.hip: preconditioner (sweeps damped steps from 0) and the Krylov
+// workspace, shared with the batched solve
+int pr_precond_internal(pr_handle h, const double* v, double* e, double* t3, const int32_t* stop);
+int pr_workspace_internal(pr_handle h, int m);
