@@ -1,27 +1,39 @@
 #!/usr/bin/env python3
 """Benchmark of compressed patch-based relaxation on one MI355X.
 
-Workload: curl curl u + 1e-3 u on the unit cube, lowest-order hexahedral edge
-elements on 64^3 cells (811,200 dofs, 262,144 twelve-dof cell patches), four
-seeded Voronoi materials with coefficients {1, 10, 100, 1000}; b ~ N(0, 1).
+Default workload (nedelec_hex): curl curl u + 1e-3 u on the unit cube,
+lowest-order hexahedral edge elements on 64^3 cells (811,200 dofs, 262,144
+twelve-dof cell patches), four seeded Voronoi materials with coefficients
+{1, 10, 100, 1000}; b ~ N(0, 1).  Other workloads (--workload):
+  stokes_batch      independent Taylor-Hood Stokes systems of seeded uneven
+                    sizes (--nsys, meshes n x n with n in [16, 128]), solved
+                    system by system in shared launches; FP32 apply of every
+                    patch's inverse, autotuned launch shape;
+  q2_hex_lognormal  Q2 diffusion on 32^3 hexes with a lognormal coefficient;
+                    spectral k-means database of 5 % of the patches.
 
 One step is the whole hot path on resident device data: setup (validation,
-cover counts and W, patch extraction, Algorithm 1 with the spectral criterion,
-FP64 inverses of the database, grouping, conversion of the database to the
-apply precision) followed by a right-preconditioned GMRES(30) solve to
-relative residual 1e-8, capped at --iters outer iterations.  The same step is
-timed for the full-patch FP64 path (every patch factored, FP64 apply).
+cover counts and W, patch extraction, the database, FP64 inverses, grouping,
+conversion to the apply precision) followed by a right-preconditioned
+GMRES(30) solve to relative residual 1e-8, capped at --iters outer
+iterations.  The same step is timed for the full-patch FP64 path (every
+patch factored, FP64 apply).
 
 Printed: one JSON line.  value = n * (preconditioner applications) / (step
-wall time), in GDoF/s, for the compressed path; the dominant kernel's
-roofline from HIP events recorded inside the timed steps; the oracle's rate on
-a bounded sample of the same workload on the host cores.
+wall time), in GDoF/s, for the compressed path.  roofline: the patch apply
+(one application = the patch kernel and, in deterministic mode, the slot
+sum), algorithmic bytes per application over its average duration from HIP
+events recorded on the solve's stream inside the timed steps; traffic from
+the committed hardware-counter summary when the apply's source is unchanged.
+cpu_baseline: the oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,6 +42,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "patch-relax GDoF/s + setup s, compressed BF16 vs full FP64, equal-iter tol"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_traffic_nedelec_hex_64.md")
+APPLY_SRC = os.path.join(ROOT, "paper_2306_10025_amd", "csrc", "k_apply.hip")
 
 
 def log(*a):
@@ -41,20 +55,62 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--size", type=int, default=64, help="cells per direction")
+    ap.add_argument("--workload", default="nedelec_hex",
+                    choices=["nedelec_hex", "stokes_batch", "q2_hex_lognormal"])
+    ap.add_argument("--size", type=int, default=None, help="cells per direction")
+    ap.add_argument("--nsys", type=int, default=256, help="systems of the stokes_batch workload")
     ap.add_argument("--iters", type=int, default=300, help="GMRES iteration cap per step")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--eps", type=float, default=1e-8, help="Algorithm 1 tolerance")
-    ap.add_argument("--precision", default="bf16x3")
+    ap.add_argument("--precision", default=None, help="apply precision of the compressed path")
     ap.add_argument("--scatter", default="two-stage", choices=["atomic", "two-stage"],
                     help="FP64 atomics or the deterministic two-stage slot sum")
+    ap.add_argument("--mlp", action="store_true", help="Algorithm 1 with the learned predictor")
+    ap.add_argument("--graph", action="store_true", help="replay restart cycles from a HIP graph")
     ap.add_argument("--no-full", action="store_true", help="skip the full FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-size", type=int, default=12, help="cells per direction of the CPU sample")
-    return ap.parse_args()
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="after the steps, copy this many MiB on the device (hardware-counter calibration)")
+    a = ap.parse_args()
+    if a.size is None:
+        a.size = {"nedelec_hex": 64, "stokes_batch": 128, "q2_hex_lognormal": 32}[a.workload]
+    if a.precision is None:
+        a.precision = "fp32" if a.workload == "stokes_batch" else "bf16x3"
+    return a
 
 
-def algorithmic_bytes(P, m_p, precision, n_items):
+def make_workload(args):
+    import gen
+    if args.workload == "nedelec_hex":
+        P = gen.nedelec_hex(args.size)
+        name = f"nedelec_hex_{args.size}"
+    elif args.workload == "stokes_batch":
+        P = gen.uneven_stokes_batch(n_sys=args.nsys, nmin=min(16, args.size), nmax=args.size)
+        name = f"stokes_batch_{args.nsys}x[16..{args.size}]"
+    else:
+        P = gen.q2_hex_diffusion(args.size)
+        name = f"q2_hex_lognormal_{args.size}"
+    return P, name
+
+
+def path_params(args, P, compressed):
+    """Setup parameters of the two paths."""
+    det = args.scatter == "two-stage"
+    common = dict(restart=30, max_iters=args.iters, deterministic=det, timing=not args.graph,
+                  graph=args.graph)
+    if not compressed:
+        return dict(algo="full", precision="fp64", **common)
+    if args.workload == "stokes_batch":
+        return dict(algo="full", precision=args.precision, autotune=True, **common)
+    if args.workload == "q2_hex_lognormal" and not args.mlp:
+        return dict(algo="kmeans_spectral", m_target=max(1, int(0.05 * P.n_p)), precision=args.precision,
+                    **common)
+    return dict(algo="tolerance", criterion="spectral", eps=args.eps, precision=args.precision,
+                mlp=args.mlp, **common)
+
+
+def algorithmic_bytes(P, m_p, precision, n_items, n_p_entries):
     """Bytes one preconditioner application must move at minimum, by kernel
     class (HBM model; each array read or written once)."""
     import numpy as np
@@ -62,16 +118,39 @@ def algorithmic_bytes(P, m_p, precision, n_items):
     sum_ps = int(P.ptr[-1])
     ps = np.diff(P.ptr)
     x_bytes = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2, "bf16x3": 4}[precision]
-    db = int(np.sum(ps[:1] ** 2)) * m_p * x_bytes if m_p < n_p else int(np.sum(ps ** 2)) * x_bytes
+    db = int(np.sum(ps ** 2)) * x_bytes if m_p >= n_p else int(np.max(ps)) ** 2 * m_p * x_bytes
     apply = (4 * sum_ps          # patch dof lists
              + 8 * n             # r
              + 8 * n             # W
              + 8 * n             # z (one write)
-             + 4 * n_p + 8 * n_p  # grouped order, patch offsets
+             + 4 * n_p           # entry of each patch
              + 16 * n_items      # work items (grouped kernels)
              + db)               # database inverses
     spmv = 12 * P.A.nnz + 8 * (n + 1) + 8 * n + 8 * n
     return apply, spmv
+
+
+def orth_bytes(n, m=30):
+    """Average HBM bytes of the Gram-Schmidt work of one Arnoldi step over a
+    GMRES(m) cycle: three passes over the j+1 basis vectors (two reads, one
+    read plus the update), reads and writes of w, the new basis vector."""
+    j_avg = (m - 1) / 2.0
+    return 8 * n * (3 * (j_avg + 1) + 2 * 3 + 2)
+
+
+def traffic_from_profile():
+    """HBM bytes per application of the apply from the committed counter
+    summary, or None when the apply's source changed since it was taken."""
+    try:
+        txt = open(TRAFFIC_FILE).read()
+        m = re.search(r"```json\n(.*?)\n```", txt, flags=re.S)
+        rec = json.loads(m.group(1))
+        sha = hashlib.sha1(open(APPLY_SRC, "rb").read()).hexdigest()
+        if rec.get("source_sha1") != sha:
+            return None
+        return int(rec["hbm_bytes_per_apply"])
+    except Exception:
+        return None
 
 
 def run_gpu(args, P, b_np):
@@ -90,10 +169,13 @@ def run_gpu(args, P, b_np):
     b = t(b_np, torch.float64)
     x = torch.zeros_like(b)
     stream = pr._stream()
+    sptr = P.meta.get("system_ptr") if args.workload == "stokes_batch" else None
 
     def step(params):
         h = pr.pr_setup(row_ptr, col, val, ptr, dofs, P.n, params)
         try:
+            if sptr is not None:
+                pr.pr_set_systems(h, sptr)
             pr.pr_solve(h, b, x, args.tol)
             return pr.pr_get_solve_info(h), pr.pr_get_stats(h)
         finally:
@@ -116,37 +198,41 @@ def run_gpu(args, P, b_np):
         t1 = time.perf_counter()
         return (t1 - t0) / steps, rec
 
-    comp = pr.make_params(algo="tolerance", criterion="spectral", eps=args.eps,
-                          precision=args.precision, restart=30, max_iters=args.iters,
-                          deterministic=args.scatter == "two-stage", timing=True, stream=stream)
+    comp = pr.make_params(stream=stream, **path_params(args, P, True))
     sec_c, rec_c = timed(comp, "compressed " + args.precision, args.steps, args.warmup)
     out = dict(sec=sec_c, rec=rec_c)
     if not args.no_full:
-        full = pr.make_params(algo="full", precision="fp64", restart=30, max_iters=args.iters,
-                              deterministic=args.scatter == "two-stage", timing=True, stream=stream)
+        full = pr.make_params(stream=stream, **path_params(args, P, False))
         sec_f, rec_f = timed(full, "full fp64", max(1, min(args.steps, 2)), 1)
         out.update(sec_full=sec_f, rec_full=rec_f)
+    if args.copy_calib > 0:
+        # a plain device copy of known size, for scaling the HBM byte counters
+        nb = args.copy_calib << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {args.copy_calib} MiB")
     return out
 
 
 def summarize_classes(P, rec, precision, m_p, n_items):
-    """Per-kernel-class device time per step and rooflines from the events
-    recorded inside the timed steps."""
-    apply_b, spmv_b = algorithmic_bytes(P, m_p, precision, n_items)
+    """Per-kernel-class device time per step and the average duration of one
+    launch of each class, from the events recorded inside the timed steps."""
+    apply_b, spmv_b = algorithmic_bytes(P, m_p, precision, n_items, m_p)
     tot = {"apply": [0.0, 0], "spmv": [0.0, 0], "orth": [0.0, 0]}
     for info, st in rec:
-        tot["apply"][0] += info["apply_ms"]
-        tot["apply"][1] += info["n_apply"]
-        tot["spmv"][0] += info["spmv_ms"]
-        tot["spmv"][1] += info["n_spmv"]
-        tot["orth"][0] += info["orth_ms"]
-        tot["orth"][1] += info["n_orth"]
+        for k in tot:
+            tot[k][0] += info[k + "_ms"]
+            tot[k][1] += info["n_" + k]
     res = {}
     for k, (ms, cnt) in tot.items():
         res[k] = dict(total_ms=ms / max(len(rec), 1), launches=cnt / max(len(rec), 1),
                       avg_us=1000.0 * ms / max(cnt, 1))
     res["apply"]["bytes"] = apply_b
     res["spmv"]["bytes"] = spmv_b
+    res["orth"]["bytes"] = orth_bytes(P.n)
     return res
 
 
@@ -158,11 +244,9 @@ def roofline(name, bytes_per_launch, avg_us, traffic=None):
 
 
 def cpu_baseline(args):
-    """The oracle (unchanged) on a bounded sample of the same workload: the
-    Nedelec problem at --cpu-size^3 cells, patch extraction + Algorithm 1 +
-    FP64 GMRES(30) capped at 60 iterations; rate = n * applies / wall time."""
-    import numpy as np
-
+    """The oracle (unchanged) on a bounded sample of the same workload: cover
+    counts, tiles, Algorithm 1 and FP64 GMRES(30) capped at 60 iterations;
+    rate = n * applies / wall time."""
     import gen
     import oracle as O
     try:
@@ -170,12 +254,20 @@ def cpu_baseline(args):
         blas = sum(i.get("num_threads", 1) for i in threadpool_info()) or 1
     except Exception:
         blas = 1
-    P = gen.nedelec_hex(args.cpu_size)
+    if args.workload == "nedelec_hex":
+        P = gen.nedelec_hex(args.cpu_size)
+        name, eps = f"nedelec_hex_{args.cpu_size}", args.eps
+    elif args.workload == "stokes_batch":
+        P = gen.uneven_stokes_batch(n_sys=4, nmin=8, nmax=24)
+        name, eps = "stokes_batch_4x[8..24]", 1e-8
+    else:
+        P = gen.q2_hex_diffusion(8)
+        name, eps = "q2_hex_lognormal_8", 0.99
     b = gen.rhs(P.n)
     t0 = time.perf_counter()
     cnt, W = O.cover_weights(P.n, P.ptr, P.dofs)
     tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
-    res = O.alg1_tolerance(tiles, args.eps, "spectral")
+    res = O.alg1_tolerance(tiles, eps, "spectral")
     t_setup = time.perf_counter() - t0
     napply = [0]
     base = O.make_preconditioner(P.A, P.ptr, P.dofs, W, res["X"], res["phi"])
@@ -187,9 +279,9 @@ def cpu_baseline(args):
     t_all = time.perf_counter() - t0
     rate = P.n * napply[0] / t_all / 1e9
     return {"value": rate, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
-            "sample": (f"nedelec_hex_{args.cpu_size} (n={P.n}, n_p={P.n_p}, m_p={len(res['reps'])}): "
-                       f"oracle setup {t_setup:.2f}s + GMRES(30) {info['iters']} iters, "
-                       f"{napply[0]} FP64 applies, {t_all:.2f}s wall; single Python thread "
+            "sample": (f"{name} (n={P.n}, n_p={P.n_p}, m_p={len(res['reps'])}): "
+                       f"oracle setup (Algorithm 1, eps={eps}) {t_setup:.2f}s + GMRES(30) {info['iters']} "
+                       f"iters, {napply[0]} FP64 applies, {t_all:.2f}s wall; single Python thread "
                        f"(BLAS pool {blas}, host cpu_count {os.cpu_count()})")}
 
 
@@ -203,9 +295,9 @@ def main():
 
     import gen
     t0 = time.perf_counter()
-    P = gen.nedelec_hex(args.size)
+    P, wname = make_workload(args)
     b = gen.rhs(P.n)
-    log(f"workload nedelec_hex_{args.size}: n={P.n} nnz={P.A.nnz} n_p={P.n_p} "
+    log(f"workload {wname}: n={P.n} nnz={P.A.nnz} n_p={P.n_p} "
         f"(generated in {time.perf_counter() - t0:.1f}s)")
     g = run_gpu(args, P, b)
     info, st = g["rec"][-1]
@@ -214,9 +306,15 @@ def main():
     value = P.n * applies / g["sec"] / 1e9
     cls = summarize_classes(P, g["rec"], args.precision, m_p, n_items)
     dom = max(("apply", "spmv", "orth"), key=lambda k: cls[k]["total_ms"])
-    rl_apply = roofline("patch apply (" + args.precision + ")", cls["apply"]["bytes"],
-                        cls["apply"]["avg_us"])
-    rl_spmv = roofline("csr spmv (fp64)", cls["spmv"]["bytes"], cls["spmv"]["avg_us"])
+    traffic = traffic_from_profile() if (wname == "nedelec_hex_64" and args.precision == "bf16x3"
+                                         and args.scatter == "two-stage") else None
+    kname = "patch apply (" + args.precision + ("" if args.scatter == "atomic" else ", two-stage") + ")"
+    rl_apply = roofline(kname, cls["apply"]["bytes"], cls["apply"]["avg_us"], traffic)
+    rl_spmv = roofline("sell spmv (fp64)", cls["spmv"]["bytes"], cls["spmv"]["avg_us"])
+    rl_orth = roofline("gram-schmidt per arnoldi step (fp64)", cls["orth"]["bytes"], cls["orth"]["avg_us"])
+    database = {"tolerance": f"algorithm 1, spectral criterion, eps={args.eps}" + (" with the learned predictor" if args.mlp else ""),
+                "kmeans_spectral": "algorithm 2 spectral k-means, m_p = 5 % of n_p",
+                "full": "every patch (FP32 inverses)"}[path_params(args, P, True)["algo"]]
     line = {
         "metric": METRIC,
         "value": round(value, 4),
@@ -231,11 +329,11 @@ def main():
         "dtype": "bf16" if args.precision.startswith("bf16") else args.precision,
         "data": "synthetic",
         "config": {
-            "workload": f"nedelec_hex_{args.size}",
-            "n": P.n, "nnz": int(P.A.nnz), "n_p": P.n_p, "p_s": 12, "m_p": m_p,
-            "database": f"algorithm 1, spectral criterion, eps={args.eps}",
+            "workload": wname,
+            "n": P.n, "nnz": int(P.A.nnz), "n_p": P.n_p, "p_s": int(np.max(np.diff(P.ptr))), "m_p": m_p,
+            "database": database,
             "apply_precision": args.precision, "setup_precision": "f64", "krylov": "f64 GMRES(30)",
-            "scatter": args.scatter,
+            "scatter": args.scatter, "graph": args.graph,
             "tol": args.tol, "max_iters": args.iters, "parallelism": "single GPU",
         },
         "setup_s": round(float(np.mean([s["t_total"] for _, s in g["rec"]])), 4),
@@ -245,24 +343,17 @@ def main():
         "applies_per_step": float(applies),
         "apply_gdofs": round(P.n / (cls["apply"]["avg_us"] * 1e-6) / 1e9, 3) if cls["apply"]["avg_us"] else None,
         "kernel_ms_per_step": {k: round(cls[k]["total_ms"], 3) for k in ("apply", "spmv", "orth")},
-        "dominant": dom,
-        "roofline": rl_spmv if dom == "spmv" else rl_apply if dom == "apply" else None,
-        "roofline_apply": rl_apply,
+        "dominant_by_time": dom,
+        "roofline": rl_apply,
         "roofline_spmv": rl_spmv,
+        "roofline_orth": rl_orth,
     }
-    if line["roofline"] is None:
-        # orthogonalisation dominates: report its measured rate against HBM
-        n = P.n
-        per_iter_bytes = None
-        o = cls["orth"]
-        if info["iters"]:
-            j_avg = 15.5  # mean basis size over a GMRES(30) cycle
-            per_iter_bytes = 8 * n * (2 * (j_avg + 1) + 2 * (j_avg + 2) + 1 + 2)
-        line["roofline"] = roofline("gram-schmidt (fp64)", per_iter_bytes or 0, o["avg_us"])
+    if st.get("tune_threads"):
+        line["config"]["apply_shape"] = [st["tune_threads"], st["tune_cap"], st["tune_slot"]]
     if "rec_full" in g:
         fi, fs = g["rec_full"][-1]
         fcls = summarize_classes(P, g["rec_full"], "fp64", P.n_p, fs["n_items"])
-        f_applies = np.mean([i["n_apply"] for i, _ in g["rec_full"]])
+        f_applies = np.mean([i["n_apply"] if i["n_apply"] else i["iters"] + i["cycles"] for i, _ in g["rec_full"]])
         line["full_fp64"] = {
             "ms_per_step": round(g["sec_full"] * 1000.0, 3),
             "gdofs": round(P.n * f_applies / g["sec_full"] / 1e9, 4),
@@ -275,7 +366,8 @@ def main():
         }
         line["e2e_speedup_vs_full"] = round(g["sec_full"] / g["sec"], 3)
         line["setup_speedup_vs_full"] = round(line["full_fp64"]["setup_s"] / max(line["setup_s"], 1e-9), 3)
-        line["apply_speedup_vs_full"] = round(fcls["apply"]["avg_us"] / max(cls["apply"]["avg_us"], 1e-9), 3)
+        if cls["apply"]["avg_us"] and fcls["apply"]["avg_us"]:
+            line["apply_speedup_vs_full"] = round(fcls["apply"]["avg_us"] / cls["apply"]["avg_us"], 3)
     if not args.no_cpu:
         log("cpu baseline (oracle on a bounded sample) ...")
         line["cpu_baseline"] = cpu_baseline(args)

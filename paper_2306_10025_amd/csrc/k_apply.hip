@@ -33,7 +33,16 @@ struct ApplyGeom {
     const int64_t* dboff;   // database offsets (null: entry j at j * dbst)
     int64_t dbst;
     const int32_t* stop;    // optional device flag: return at once when set
+    int ypm;                // slot buffer tiles: 16 patches x ypm local rows (see yslot)
 };
+
+// Slot of local row a of grouped patch s: patches in tiles of 16, inside a
+// tile row-plane by row-plane (16 consecutive patches' row a contiguous).
+// A block or an MFMA item writes whole tiles, and the per-dof sum finds the
+// rows of neighbouring patches next to each other.
+__device__ __forceinline__ int64_t yslot(int64_t s, int a, int pmax) {
+    return (((s >> 4) * pmax + a) << 4) + (s & 15);
+}
 
 __device__ __forceinline__ bool skip(const ApplyGeom& g) { return g.stop && *g.stop; }
 
@@ -45,8 +54,7 @@ __global__ __launch_bounds__(256) void k_apply_rows(int64_t count, ApplyGeom g, 
     if (skip(g)) return;
     const int a = threadIdx.x % G;
     const int64_t groups = (int64_t)gridDim.x * (blockDim.x / G);
-    for (int64_t s = (int64_t)blockIdx.x * (blockDim.x / G) + threadIdx.x / G; s < count;
-         s += groups) {
+    for (int64_t s = (int64_t)blockIdx.x * (blockDim.x / G) + threadIdx.x / G; s < count; s += groups) {
         const int64_t o = g.goff ? g.goff[s] : s * g.pst;
         const int p = g.goff ? (int)(g.goff[s + 1] - o) : g.pst;
         const int32_t j = g.gphi[s];
@@ -77,7 +85,7 @@ __global__ __launch_bounds__(256) void k_apply_rows(int64_t count, ApplyGeom g, 
             }
         }
         if (act) {
-            if (TWO) Y[o + a] = (TY)acc;
+            if (TWO) Y[yslot(s, a, g.ypm)] = (TY)acc;
             else atomicAdd(&z[gd], omega * W[gd] * (double)acc);
         }
     }
@@ -183,8 +191,8 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
     constexpr bool SPLIT = MODE == 2;
     const int l = threadIdx.x & (PR_WAVE - 1);
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / PR_WAVE);
-    for (int64_t it = (int64_t)blockIdx.x * (blockDim.x / PR_WAVE) + threadIdx.x / PR_WAVE;
-         it < n_items; it += waves) {
+    for (int64_t it = (int64_t)blockIdx.x * (blockDim.x / PR_WAVE) + threadIdx.x / PR_WAVE; it < n_items;
+         it += waves) {
         const int32_t j = items[4 * it + 0];
         const int32_t start = items[4 * it + 1];
         const int32_t cnt = items[4 * it + 2];
@@ -233,7 +241,7 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
             for (int t = 0; t < 4; ++t) {
                 if (gi[t] >= 0) {
                     if (TWO) {
-                        Y[st + 4 * q + t] = FP16 ? ldexpf(acc[t], ej + f) : acc[t];
+                        Y[yslot(start + n, 4 * q + t, g.ypm)] = FP16 ? ldexpf(acc[t], ej + f) : acc[t];
                     } else {
                         double y = (double)acc[t];
                         if (FP16) y = ldexp(y, ej + f);
@@ -293,7 +301,8 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
             for (int v = 0; v < 16; ++v) {
                 if (gi[v] >= 0) {
                     if (TWO) {
-                        Y[st + 8 * (v >> 2) + 4 * h + (v & 3)] = FP16 ? ldexpf(acc[v], ej + f) : acc[v];
+                        Y[yslot(start + n, 8 * (v >> 2) + 4 * h + (v & 3), g.ypm)] =
+                            FP16 ? ldexpf(acc[v], ej + f) : acc[v];
                     } else {
                         double y = (double)acc[v];
                         if (FP16) y = ldexp(y, ej + f);
@@ -359,7 +368,7 @@ __global__ __launch_bounds__(64) void k_convert_db(int prec, int64_t m_p, const 
 }  // namespace
 
 void launch_apply(int prec, bool two_stage, const ApplyLaunch& a, hipStream_t s) {
-    ApplyGeom g{a.gdofs, a.goff, a.pst, a.gphi, a.dboff, a.dbst, a.stop};
+    ApplyGeom g{a.gdofs, a.goff, a.pst, a.gphi, a.dboff, a.dbst, a.stop, a.maxp};
     const int T = (a.threads == 64 || a.threads == 128) ? a.threads : 256;
     const int64_t cap = a.grid_cap;
     if (prec == PR_FP64) {

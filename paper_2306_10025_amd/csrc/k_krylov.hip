@@ -225,32 +225,50 @@ __global__ void k_cycle_init(double* __restrict__ g, int m, const double* __rest
 // h_{j+1} = ||w||; apply the previous rotations, form the new one, update
 // the residual vector g; stop when |g_{j+1}| <= tol_abs (or not finite) or
 // the iteration limit is reached (tolp: device absolute tolerance; itb:
-// device count of the iterations of earlier cycles).  Single thread: j <= 64.
+// device count of the iterations of earlier cycles).  One wavefront: the
+// column and the rotations are staged in LDS by all lanes, one lane runs the
+// sequential rotation chain, all lanes write the column back.  j < 64.
 // gctl: [0] stop  [1] columns done this cycle
-__global__ void k_givens(int j, int m, const double* __restrict__ hd, double* __restrict__ R,
-                         double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
-                         double* __restrict__ est, int32_t* __restrict__ gctl, const double* __restrict__ tolp,
-                         const int64_t* __restrict__ itb, int64_t max_iters) {
-    if (threadIdx.x != 0 || gctl[0]) return;
-    const int64_t iters_base = *itb;
-    const double tol_abs = *tolp;
-    for (int i = 0; i <= j; ++i) R[(int64_t)i * m + j] = hd[i] + hd[64 + i];
-    const double hn = sqrt(fmax(hd[128], 0.0));
-    for (int i = 0; i < j; ++i) {
-        const double a = R[(int64_t)i * m + j], b = R[(int64_t)(i + 1) * m + j];
-        R[(int64_t)i * m + j] = cs[i] * a + sn[i] * b;
-        R[(int64_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+__global__ __launch_bounds__(64) void k_givens(int j, int m, const double* __restrict__ hd,
+                                               double* __restrict__ R, double* __restrict__ cs,
+                                               double* __restrict__ sn, double* __restrict__ g,
+                                               double* __restrict__ est, int32_t* __restrict__ gctl,
+                                               const double* __restrict__ tolp,
+                                               const int64_t* __restrict__ itb, int64_t max_iters) {
+    __shared__ double col[65], c_s[64], s_s[64];
+    if (gctl[0]) return;
+    const int t = threadIdx.x;
+    if (t <= j) col[t] = hd[t] + hd[64 + t];
+    if (t < j) {
+        c_s[t] = cs[t];
+        s_s[t] = sn[t];
     }
-    const double a = R[(int64_t)j * m + j];
-    const double den = hypot(a, hn);
-    cs[j] = den > 0.0 ? a / den : 1.0;
-    sn[j] = den > 0.0 ? hn / den : 0.0;
-    R[(int64_t)j * m + j] = den;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
-    gctl[1] = j + 1;
-    est[0] = fabs(g[j + 1]);
-    if (!(fabs(g[j + 1]) > tol_abs) || iters_base + j + 1 >= max_iters || j + 1 >= m) gctl[0] = 1;
+    __syncthreads();
+    if (t == 0) {
+        const int64_t iters_base = *itb;
+        const double tol_abs = *tolp;
+        const double hn = sqrt(fmax(hd[128], 0.0));
+        for (int i = 0; i < j; ++i) {
+            const double a = col[i], b = col[i + 1];
+            col[i] = c_s[i] * a + s_s[i] * b;
+            col[i + 1] = -s_s[i] * a + c_s[i] * b;
+        }
+        const double a = col[j];
+        const double den = hypot(a, hn);
+        const double cj = den > 0.0 ? a / den : 1.0;
+        const double sj = den > 0.0 ? hn / den : 0.0;
+        cs[j] = cj;
+        sn[j] = sj;
+        col[j] = den;
+        const double gj = g[j];
+        g[j + 1] = -sj * gj;
+        g[j] = cj * gj;
+        gctl[1] = j + 1;
+        est[0] = fabs(g[j + 1]);
+        if (!(fabs(g[j + 1]) > tol_abs) || iters_base + j + 1 >= max_iters || j + 1 >= m) gctl[0] = 1;
+    }
+    __syncthreads();
+    if (t <= j) R[(int64_t)t * m + j] = col[t];
 }
 
 // y = R^{-1} g over the columns done (upper triangular back substitution)

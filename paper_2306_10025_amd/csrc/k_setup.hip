@@ -344,14 +344,21 @@ __global__ void k_group_gather(const int32_t* __restrict__ order, int64_t n_p,
     gphi[s] = phi[k];
 }
 
-__global__ void k_transpose_fill(const int32_t* __restrict__ gdofs, int64_t total,
-                                 const int64_t* __restrict__ dof_ptr, int32_t* __restrict__ fill,
-                                 int32_t* __restrict__ dof_slots) {
+// slot of local row a of grouped patch s: tiles of 16 patches, row-planes
+// inside a tile, ((s / 16) * pmax + a) * 16 + s % 16 (the apply's layout)
+__global__ void k_transpose_fill(const int32_t* __restrict__ gdofs, const int64_t* __restrict__ goff, int pst,
+                                 int64_t n_p, int pmax, const int64_t* __restrict__ dof_ptr,
+                                 int32_t* __restrict__ fill, int32_t* __restrict__ dof_slots) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= total) return;
-    const int32_t g = gdofs[t];
+    if (t >= n_p * pmax) return;
+    const int64_t s = t / pmax;
+    const int a = (int)(t % pmax);
+    const int64_t o = goff ? goff[s] : s * pst;
+    const int p = goff ? (int)(goff[s + 1] - o) : pst;
+    if (a >= p) return;
+    const int32_t g = gdofs[o + a];
     const int32_t pos = atomicAdd(&fill[g], 1);
-    dof_slots[dof_ptr[g] + pos] = (int32_t)t;
+    dof_slots[dof_ptr[g] + pos] = (int32_t)((((s >> 4) * pmax + a) << 4) + (s & 15));
 }
 
 // each dof's slot list in ascending slot order (fixed summation order)
@@ -476,9 +483,11 @@ void launch_group_gather(const int32_t* order, int64_t n_p, const int64_t* ptr, 
         k_group_gather<<<nblk(n_p, 256), 256, 0, s>>>(order, n_p, ptr, dofs, goff, pst, gdofs, gphi, phi);
 }
 
-void launch_transpose_fill(const int32_t* gdofs, int64_t total, const int64_t* dof_ptr,
-                           int32_t* fill, int32_t* dof_slots, hipStream_t s) {
-    if (total > 0) k_transpose_fill<<<nblk(total, 256), 256, 0, s>>>(gdofs, total, dof_ptr, fill, dof_slots);
+void launch_transpose_fill(const int32_t* gdofs, const int64_t* goff, int pst, int64_t n_p, int pmax,
+                           const int64_t* dof_ptr, int32_t* fill, int32_t* dof_slots, hipStream_t s) {
+    const int64_t total = n_p * pmax;
+    if (total > 0)
+        k_transpose_fill<<<nblk(total, 256), 256, 0, s>>>(gdofs, goff, pst, n_p, pmax, dof_ptr, fill, dof_slots);
 }
 
 void launch_transpose_sort(int64_t n, const int64_t* dof_ptr, int32_t* dof_slots, hipStream_t s) {

@@ -465,11 +465,14 @@ int run_group(pr_handle h) {
         launch_i32_to_i64(h->cnt, cnt64, h->n, s);
         launch_exclusive_scan_i64(cnt64, h->dof_ptr, h->n + 1, scr, s);
         PR_HIP(h, hipMemsetAsync(fill, 0, h->n * sizeof(int32_t), s));
-        launch_transpose_fill(h->gdofs, h->total_dofs, h->dof_ptr, fill, h->dof_slots, s);
+        // slots in tiles of 16 grouped patches, row-plane by row-plane (the
+        // rows of neighbouring patches are contiguous)
+        launch_transpose_fill(h->gdofs, h->goff, h->uniform ? h->max_ps : 0, n_p, h->max_ps, h->dof_ptr, fill,
+                              h->dof_slots, s);
         launch_transpose_sort(h->n, h->dof_ptr, h->dof_slots, s);
         const size_t ybytes = h->prm.apply_precision == PR_FP64 ? 8 : 4;
         char* yb = nullptr;
-        PR_TRY(dalloc(h, &yb, h->total_dofs * ybytes));
+        PR_TRY(dalloc(h, &yb, (size_t)((n_p + 15) / 16) * 16 * h->max_ps * ybytes));
         h->Ybuf = yb;
     }
     // work items of <= 16 (p <= 16) or <= 32 members of one entry

@@ -119,6 +119,35 @@ int pr_get_system_info(pr_handle h, int64_t* iters, double* relres) {
 int solve_batch(pr_handle h, const double* b, double* x, double tol) {
     const double tstart = now_s();
     hipStream_t s = h->stream;
+    // optional per-class device timing: 0 apply, 1 spmv, 2 orthogonalisation
+    const bool timing = h->prm.timing != 0;
+    struct Span { int cls; hipEvent_t a, b; };
+    std::vector<Span> spans;
+    size_t evnext = 0;
+    auto grab = [&]() -> hipEvent_t {
+        if (evnext >= h->evpool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            h->evpool.push_back(e);
+        }
+        return h->evpool[evnext++];
+    };
+    hipEvent_t tb = nullptr;
+    auto tbeg = [&]() {
+        if (timing) {
+            tb = grab();
+            if (tb) (void)hipEventRecord(tb, s);
+        }
+    };
+    auto tend = [&](int cls) {
+        if (timing && tb) {
+            hipEvent_t te = grab();
+            if (te) {
+                (void)hipEventRecord(te, s);
+                spans.push_back({cls, tb, te});
+            }
+        }
+    };
     const int m = h->prm.gmres_restart;
     const int64_t n = h->n;
     const int ns = h->nsys;
@@ -185,12 +214,18 @@ int solve_batch(pr_handle h, const double* b, double* x, double tol) {
         launch_bscale(r, V, bg, NR, sstop, gstop, s);
         for (int j = 0; j < m; ++j) {
             double* vj = V + (int64_t)j * ldv;
+            tbeg();
             PR_TRY(pr_precond_internal(h, vj, zt, t3, gstop));
+            tend(0);
+            tbeg();
             launch_spmv_sell(h->soff, h->sval, h->scol, n, zt, nullptr, w, s, gstop);
+            tend(1);
+            tbeg();
             launch_bgs(0, V, ldv, j + 1, w, bg, nullptr, h->bpart, H1, sstop, gstop, s);
             launch_bgs(1, V, ldv, j + 1, w, bg, H1, h->bpart, H2, sstop, gstop, s);
             launch_bgs(2, V, ldv, j + 1, w, bg, H2, h->bpart, HN, sstop, gstop, s);
             launch_bscale(w, V + (int64_t)(j + 1) * ldv, bg, HN, sstop, gstop, s);
+            tend(2);
             launch_bgivens(j, m, ns, H1, H2, HN, R, cs, sn, gv, est, sstop, scols, h->btol, h->bbase, maxit,
                            gstop, s);
         }
@@ -213,5 +248,12 @@ int solve_batch(pr_handle h, const double* b, double* x, double tol) {
     h->sinfo.relres_est = h->sinfo.relres;
     h->sinfo.status = h->sinfo.relres <= tol ? PR_OK : PR_NOT_CONVERGED;
     h->sinfo.seconds = now_s() - tstart;
+    for (const Span& sp : spans) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, sp.a, sp.b) != hipSuccess) continue;
+        if (sp.cls == 0) { h->sinfo.apply_ms += ms; h->sinfo.n_apply++; }
+        if (sp.cls == 1) { h->sinfo.spmv_ms += ms; h->sinfo.n_spmv++; }
+        if (sp.cls == 2) { h->sinfo.orth_ms += ms; h->sinfo.n_orth++; }
+    }
     return h->sinfo.status;
 }

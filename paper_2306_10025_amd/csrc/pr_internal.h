@@ -424,8 +424,8 @@ void launch_group_gather(const int32_t* order, int64_t n_p, const int64_t* ptr, 
                          const int32_t* phi, hipStream_t s);
 void launch_group_sizes(const int32_t* order, int64_t n_p, const int64_t* ptr, int64_t* sizes,
                         hipStream_t s);
-void launch_transpose_fill(const int32_t* gdofs, int64_t total, const int64_t* dof_ptr,
-                           int32_t* fill, int32_t* dof_slots, hipStream_t s);
+void launch_transpose_fill(const int32_t* gdofs, const int64_t* goff, int pst, int64_t n_p, int pmax,
+                           const int64_t* dof_ptr, int32_t* fill, int32_t* dof_slots, hipStream_t s);
 void launch_transpose_sort(int64_t n, const int64_t* dof_ptr, int32_t* dof_slots, hipStream_t s);
 void launch_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, hipStream_t s);
 
