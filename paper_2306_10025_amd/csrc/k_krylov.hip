@@ -91,22 +91,29 @@ __global__ __launch_bounds__(256) void k_spmv_sell(const int64_t* __restrict__ s
 //   MODE 2: w <- w - sum_i c_i V_i ; out_0 = w . w
 // Each block writes its row-range partial sums; k_gs_final adds the block
 // partials of one output per block in a fixed tree.
+// NC = ceil(nv / 8) is a template parameter: the NC * 8 vector loads of a
+// row carry no branches between them (indices past nv repeat vector nv - 1
+// and their terms are dropped), so they are all in flight at once.
 // ---------------------------------------------------------------------------
-template <int MODE>
+template <int MODE, int NC>
 __global__ __launch_bounds__(kGsThreads) void k_gs(const double* __restrict__ V, int64_t ldv, int nv,
                                                    double* __restrict__ w, int64_t n,
                                                    const double* __restrict__ c,
                                                    double* __restrict__ partial,
                                                    const int32_t* __restrict__ stop) {
     if (stopped(stop)) return;
-    constexpr int NO = (MODE == 2) ? 1 : kMaxVec;
+    constexpr int NV = 8 * NC;
+    constexpr int NO = (MODE == 2) ? 1 : NV;
     __shared__ double s_red[kGsThreads / PR_WAVE][kMaxVec];
     const int nout = (MODE == 2) ? 1 : nv;
-    double cf[kMaxVec];
+    double cf[NV];
     if (MODE >= 1) {
 #pragma unroll
-        for (int i = 0; i < kMaxVec; ++i) cf[i] = (i < nv) ? c[i] : 0.0;
+        for (int i = 0; i < NV; ++i) cf[i] = (i < nv) ? c[i] : 0.0;
     }
+    int64_t vo[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) vo[i] = (int64_t)(i < nv ? i : (nv > 0 ? nv - 1 : 0)) * ldv;
     double acc[NO];
 #pragma unroll
     for (int i = 0; i < NO; ++i) acc[i] = 0.0;
@@ -115,22 +122,19 @@ __global__ __launch_bounds__(kGsThreads) void k_gs(const double* __restrict__ V,
     const int64_t hi = lo + per < n ? lo + per : n;
     for (int64_t q = lo + threadIdx.x; q < hi; q += kGsThreads) {
         double wq = w[q];
+        double v[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = V[vo[i] + q];
         if (MODE == 0) {
 #pragma unroll
-            for (int i = 0; i < kMaxVec; ++i)
-                if (i < nv) acc[i] = fma(V[(int64_t)i * ldv + q], wq, acc[i]);
+            for (int i = 0; i < NV; ++i) acc[i] = fma(v[i], wq, acc[i]);
         } else {
-            double v[kMaxVec];
 #pragma unroll
-            for (int i = 0; i < kMaxVec; ++i) v[i] = (i < nv) ? V[(int64_t)i * ldv + q] : 0.0;
-#pragma unroll
-            for (int i = 0; i < kMaxVec; ++i)
-                if (i < nv) wq = fma(-cf[i], v[i], wq);
+            for (int i = 0; i < NV; ++i) wq = fma(-cf[i], v[i], wq);    // cf = 0 past nv
             w[q] = wq;
             if (MODE == 1) {
 #pragma unroll
-                for (int i = 0; i < kMaxVec; ++i)
-                    if (i < nv) acc[i] = fma(v[i], wq, acc[i]);
+                for (int i = 0; i < NV; ++i) acc[i] = fma(v[i], wq, acc[i]);
             } else {
                 acc[0] = fma(wq, wq, acc[0]);
             }
@@ -304,8 +308,8 @@ void launch_spmv_sell(const int64_t* soff, const double* sval, const int32_t* sc
 }
 
 int gs_blocks(int64_t n) {
-    int64_t b = (n + 511) / 512;          // >= 4 waves per SIMD on 256 CUs when n is large
-    if (b > 1024) b = 1024;
+    int64_t b = (n + 1023) / 1024;        // several rows per thread: the loads of
+    if (b > 512) b = 512;                 // consecutive rows overlap (measured best)
     if (b < 1) b = 1;
     return (int)b;
 }
@@ -318,16 +322,26 @@ void launch_gs(int mode, const double* V, int64_t ldv, int nv, double* w, int64_
     for (int base = 0; base < nv || (nv == 0 && base == 0); base += kMaxVec) {
         const int cnt = nv - base < kMaxVec ? nv - base : kMaxVec;
         const double* Vb = V + (int64_t)base * ldv;
+        const int nc = cnt <= 0 ? 1 : (cnt + 7) / 8;
+#define PR_GS(M, CC)                                                                                 \
+    k_gs<M, CC><<<nbk, kGsThreads, 0, s>>>(Vb, ldv, cnt, w, n, (M) == 0 ? c : c + base, partial, stop)
+#define PR_GS_NC(M)                 \
+    if (nc == 1) PR_GS(M, 1);       \
+    else if (nc == 2) PR_GS(M, 2);  \
+    else if (nc == 3) PR_GS(M, 3);  \
+    else PR_GS(M, 4)
         if (mode == 0) {
-            k_gs<0><<<nbk, kGsThreads, 0, s>>>(Vb, ldv, cnt, w, n, c, partial, stop);
+            PR_GS_NC(0);
             k_gs_final<<<cnt, 256, 0, s>>>(partial, nbk, out + base, stop);
         } else if (mode == 1) {
-            k_gs<1><<<nbk, kGsThreads, 0, s>>>(Vb, ldv, cnt, w, n, c + base, partial, stop);
+            PR_GS_NC(1);
             k_gs_final<<<cnt, 256, 0, s>>>(partial, nbk, out + base, stop);
         } else {
-            k_gs<2><<<nbk, kGsThreads, 0, s>>>(Vb, ldv, cnt, w, n, c + base, partial, stop);
+            PR_GS_NC(2);
             k_gs_final<<<1, 256, 0, s>>>(partial, nbk, out, stop);
         }
+#undef PR_GS_NC
+#undef PR_GS
         if (nv == 0) break;
     }
 }
