@@ -129,7 +129,10 @@ typedef struct {
     int32_t graph;           /* 1: pr_solve captures one restart cycle in a HIP graph and
                                 replays it (ignored with timing = 1; default 0) */
     int32_t autotune;        /* 1: pr_setup times the apply's launch shapes and keeps the
-                                fastest (default 0) */
+                                fastest (default 0).  The choice is kept per process, keyed
+                                on the device and the apply's shape (n, patches, entries,
+                                groups, patch sizes, precision, scatter mode); a later setup
+                                of the same shape reuses it without timing */
 } pr_params;
 
 typedef struct pr_handle_s* pr_handle;

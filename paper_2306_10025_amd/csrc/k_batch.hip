@@ -19,22 +19,28 @@ __device__ __forceinline__ bool gstopped(const int32_t* gstop) { return gstop &&
 
 // MODE 0: out_i = V_i . w ; MODE 1: w -= sum c_i V_i, out_i = V_i . w ;
 // MODE 2: w -= sum c_i V_i, out_0 = w . w   (c and out per system)
-template <int MODE>
+// NC = ceil(nv / 8): the vector loads of a row carry no branches between
+// them (indices past nv repeat vector nv - 1, whose terms are dropped).
+template <int MODE, int NC>
 __global__ __launch_bounds__(kThreads) void k_bgs(const double* __restrict__ V, int64_t ldv, int nv,
                                                   double* __restrict__ w, BGeom g, const double* __restrict__ c,
                                                   double* __restrict__ partial, const int32_t* __restrict__ sstop,
                                                   const int32_t* __restrict__ gstop) {
     if (gstopped(gstop)) return;
-    constexpr int NO = (MODE == 2) ? 1 : kMaxVec;
+    constexpr int NV = 8 * NC;
+    constexpr int NO = (MODE == 2) ? 1 : NV;
     __shared__ double s_red[kThreads / PR_WAVE][kMaxVec];
     const int nout = (MODE == 2) ? 1 : nv;
+    int64_t vo[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) vo[i] = (int64_t)(i < nv ? i : (nv > 0 ? nv - 1 : 0)) * ldv;
     for (int64_t ch = blockIdx.x; ch < g.nch; ch += gridDim.x) {
         const int sys = g.ch_sys[ch];
         if (sstop && sstop[sys]) continue;
-        double cf[kMaxVec];
+        double cf[NV];
         if (MODE >= 1) {
 #pragma unroll
-            for (int i = 0; i < kMaxVec; ++i) cf[i] = (i < nv) ? c[(int64_t)sys * kBStride + i] : 0.0;
+            for (int i = 0; i < NV; ++i) cf[i] = (i < nv) ? c[(int64_t)sys * kBStride + i] : 0.0;
         }
         double acc[NO];
 #pragma unroll
@@ -42,22 +48,19 @@ __global__ __launch_bounds__(kThreads) void k_bgs(const double* __restrict__ V, 
         const int64_t lo = g.ch_lo[ch], hi = lo + g.ch_len[ch];
         for (int64_t q = lo + threadIdx.x; q < hi; q += kThreads) {
             double wq = w[q];
+            double v[NV];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) v[i] = V[vo[i] + q];
             if (MODE == 0) {
 #pragma unroll
-                for (int i = 0; i < kMaxVec; ++i)
-                    if (i < nv) acc[i] = fma(V[(int64_t)i * ldv + q], wq, acc[i]);
+                for (int i = 0; i < NV; ++i) acc[i] = fma(v[i], wq, acc[i]);
             } else {
-                double v[kMaxVec];
 #pragma unroll
-                for (int i = 0; i < kMaxVec; ++i) v[i] = (i < nv) ? V[(int64_t)i * ldv + q] : 0.0;
-#pragma unroll
-                for (int i = 0; i < kMaxVec; ++i)
-                    if (i < nv) wq = fma(-cf[i], v[i], wq);
+                for (int i = 0; i < NV; ++i) wq = fma(-cf[i], v[i], wq);    // cf = 0 past nv
                 w[q] = wq;
                 if (MODE == 1) {
 #pragma unroll
-                    for (int i = 0; i < kMaxVec; ++i)
-                        if (i < nv) acc[i] = fma(v[i], wq, acc[i]);
+                    for (int i = 0; i < NV; ++i) acc[i] = fma(v[i], wq, acc[i]);
                 } else {
                     acc[0] = fma(wq, wq, acc[0]);
                 }
@@ -222,9 +225,23 @@ void launch_bgs(int mode, const double* V, int64_t ldv, int nv, double* w, const
         const int cnt = nv - base < kMaxVec ? nv - base : kMaxVec;
         const double* Vb = V + (int64_t)base * ldv;
         const int nout = mode == 2 ? 1 : cnt;
-        if (mode == 0) k_bgs<0><<<grid, kThreads, 0, s>>>(Vb, ldv, cnt, w, g, c, partial, sstop, gstop);
-        else if (mode == 1) k_bgs<1><<<grid, kThreads, 0, s>>>(Vb, ldv, cnt, w, g, c + base, partial, sstop, gstop);
-        else k_bgs<2><<<grid, kThreads, 0, s>>>(Vb, ldv, cnt, w, g, c + base, partial, sstop, gstop);
+        const int nc = (cnt + 7) / 8;
+#define PR_BGS(M, CC) \
+    k_bgs<M, CC><<<grid, kThreads, 0, s>>>(Vb, ldv, cnt, w, g, (M) == 0 ? c : c + base, partial, sstop, gstop)
+#define PR_BGS_NC(M)                \
+    if (nc <= 1) PR_BGS(M, 1);      \
+    else if (nc == 2) PR_BGS(M, 2); \
+    else if (nc == 3) PR_BGS(M, 3); \
+    else PR_BGS(M, 4)
+        if (mode == 0) {
+            PR_BGS_NC(0);
+        } else if (mode == 1) {
+            PR_BGS_NC(1);
+        } else {
+            PR_BGS_NC(2);
+        }
+#undef PR_BGS_NC
+#undef PR_BGS
         const int64_t nt = (int64_t)g.nsys * nout;
         k_bgs_final<<<(unsigned)((nt + 255) / 256), 256, 0, s>>>(nout, g, partial, out, mode == 2 ? 0 : base,
                                                                  sstop, gstop);

@@ -5,10 +5,12 @@
 #include "pr_internal.h"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <numeric>
 #include <unordered_map>
@@ -608,18 +610,58 @@ int ensure_workspace(pr_handle h, int m) {
 // fastest: threads per block and block cap of the patch kernel, then the
 // threads per block of the slot sum.  Every shape computes the same result
 // (deterministic mode: bit for bit; atomic mode: up to summation order).
+//
+// The choice depends only on the shape of the grouped apply, so it is kept
+// per process, keyed on that shape, and a later setup of the same shape on
+// the same device reuses it without timing.
+using TuneKey = std::array<int64_t, 11>;
+std::mutex g_tune_mu;
+std::map<TuneKey, std::array<int64_t, 3>> g_tune_cache;
+
 int autotune_apply(pr_handle h) {
     const double t0 = now_s();
+    const TuneKey key = {h->device,   h->n,      h->n_p,           h->total_dofs, h->m_p,
+                         h->n_items,  h->max_ps, h->min_ps,        h->apply_prec,
+                         h->prm.deterministic,   h->uniform ? 1 : 0};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            h->tune_threads = h->stats.tune_threads = (int)it->second[0];
+            h->tune_cap = h->stats.tune_cap = it->second[1];
+            h->tune_slot = h->stats.tune_slot = (int)it->second[2];
+            h->stats.t_autotune = now_s() - t0;
+            return PR_OK;
+        }
+    }
     hipStream_t s = h->stream;
     const int64_t n = h->n;
-    double *r = nullptr, *z = nullptr, *tmp = nullptr;
-    PR_TRY(dalloc(h, &r, n));
-    PR_TRY(dalloc(h, &z, n));
-    PR_TRY(dalloc(h, &tmp, n));
+    // three vectors (argument, result, scratch) that live only while timing
+    struct Scratch {
+        hipStream_t s;
+        double* buf = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Scratch() {
+            (void)hipStreamSynchronize(s);
+            if (buf) (void)hipFree(buf);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } sc{s};
+    {
+        hipError_t e = hipMalloc((void**)&sc.buf, (size_t)3 * (n > 0 ? n : 1) * sizeof(double));
+        if (e != hipSuccess) {
+            sc.buf = nullptr;
+            (void)hipGetLastError();
+            return pr_fail(h, PR_ERR_OOM, std::string("hipMalloc of the autotune vectors failed: ") +
+                                              hipGetErrorString(e));
+        }
+    }
+    double *r = sc.buf, *z = sc.buf + n, *tmp = sc.buf + 2 * n;
     launch_copy(r, h->W, n, s);               // any vector will do
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    PR_HIP(h, hipEventCreate(&e0));
-    PR_HIP(h, hipEventCreate(&e1));
+    PR_HIP(h, hipEventCreate(&sc.e0));
+    PR_HIP(h, hipEventCreate(&sc.e1));
+    hipEvent_t e0 = sc.e0, e1 = sc.e1;
     auto time_shape = [&](int T, int64_t cap, int T2, float& ms) -> int {
         h->tune_threads = T;
         h->tune_cap = cap;
@@ -656,8 +698,6 @@ int autotune_apply(pr_handle h) {
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     h->tune_threads = bt;
     h->tune_cap = bc;
     h->tune_slot = bs;
@@ -665,6 +705,8 @@ int autotune_apply(pr_handle h) {
     h->stats.tune_slot = bs;
     h->stats.tune_cap = bc;
     h->stats.t_autotune = now_s() - t0;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = {bt, bc, bs};
     return PR_OK;
 }
 

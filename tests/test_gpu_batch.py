@@ -213,5 +213,16 @@ def test_autotuned_apply_is_bit_identical(precision):
     tuned.apply(r, z2)
     torch.cuda.synchronize()
     assert torch.equal(z1, z2)
+    # a second setup of the same shape reuses the choice without timing
+    again = pr.PatchRelax(P.A, P.ptr, P.dofs, autotune=True, **kw)
+    st2 = again.stats()
+    assert (st2["tune_threads"], st2["tune_cap"], st2["tune_slot"]) == \
+        (st["tune_threads"], st["tune_cap"], st["tune_slot"])
+    assert st2["t_autotune"] < 0.25 * st["t_autotune"]
+    z3 = torch.full_like(r, np.nan)
+    again.apply(r, z3)
+    torch.cuda.synchronize()
+    assert torch.equal(z1, z3)
     plain.close()
     tuned.close()
+    again.close()
