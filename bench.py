@@ -23,7 +23,10 @@ Printed: one JSON line.  value = n * (preconditioner applications) / (step
 wall time), in GDoF/s, for the compressed path.  roofline: the patch apply
 (one application = the patch kernel and, in deterministic mode, the slot
 sum), algorithmic bytes per application over its average duration from HIP
-events recorded on the solve's stream inside the timed steps; traffic from
+events recorded on the solve's stream inside the timed steps (around the
+kernels of every 7th Arnoldi step: an event adds a gap of a few
+microseconds between kernels, so bracketing every step would slow the
+step measured for value); traffic from
 the committed hardware-counter summary when the apply's source is unchanged.
 cpu_baseline: the oracle on a bounded sample of the same workload.
 """
@@ -42,6 +45,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "patch-relax GDoF/s + setup s, compressed BF16 vs full FP64, equal-iter tol"
 HBM_PEAK_GBS = 8000.0
+TIMING_STRIDE = 7
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_traffic_nedelec_hex_64.md")
 APPLY_SRC = os.path.join(ROOT, "paper_2306_10025_amd", "csrc", "k_apply.hip")
 
@@ -97,7 +101,9 @@ def make_workload(args):
 def path_params(args, P, compressed):
     """Setup parameters of the two paths."""
     det = args.scatter == "two-stage"
-    common = dict(restart=30, max_iters=args.iters, deterministic=det, timing=not args.graph,
+    # kernels of every 7th Arnoldi step are bracketed by events (7 and the
+    # restart length 30 are coprime, so the sample covers every basis size)
+    common = dict(restart=30, max_iters=args.iters, deterministic=det, timing=0 if args.graph else TIMING_STRIDE,
                   graph=args.graph)
     if not compressed:
         return dict(algo="full", precision="fp64", **common)
@@ -217,19 +223,31 @@ def run_gpu(args, P, b_np):
     return out
 
 
+def launches_per_solve(info):
+    """Launches of each class in one solve: an apply and an SpMV per Arnoldi
+    step and per restart cycle end, one orthogonalisation per step."""
+    return {"apply": info["iters"] + info["cycles"], "spmv": info["iters"] + info["cycles"],
+            "orth": info["iters"]}
+
+
 def summarize_classes(P, rec, precision, m_p, n_items):
-    """Per-kernel-class device time per step and the average duration of one
-    launch of each class, from the events recorded inside the timed steps."""
+    """Average duration of one launch of each kernel class, from the events
+    recorded inside the timed steps (a sample of the Arnoldi steps), and the
+    device time per step it implies."""
     apply_b, spmv_b = algorithmic_bytes(P, m_p, precision, n_items, m_p)
-    tot = {"apply": [0.0, 0], "spmv": [0.0, 0], "orth": [0.0, 0]}
+    tot = {"apply": [0.0, 0, 0], "spmv": [0.0, 0, 0], "orth": [0.0, 0, 0]}
     for info, st in rec:
+        lps = launches_per_solve(info)
         for k in tot:
             tot[k][0] += info[k + "_ms"]
             tot[k][1] += info["n_" + k]
+            tot[k][2] += lps[k]
     res = {}
-    for k, (ms, cnt) in tot.items():
-        res[k] = dict(total_ms=ms / max(len(rec), 1), launches=cnt / max(len(rec), 1),
-                      avg_us=1000.0 * ms / max(cnt, 1))
+    for k, (ms, cnt, launches) in tot.items():
+        avg_us = 1000.0 * ms / max(cnt, 1)
+        steps = max(len(rec), 1)
+        res[k] = dict(total_ms=avg_us * launches / steps / 1000.0, launches=launches / steps,
+                      timed_launches=cnt / steps, avg_us=avg_us)
     res["apply"]["bytes"] = apply_b
     res["spmv"]["bytes"] = spmv_b
     res["orth"]["bytes"] = orth_bytes(P.n)
@@ -302,7 +320,7 @@ def main():
     g = run_gpu(args, P, b)
     info, st = g["rec"][-1]
     m_p, n_items = st["m_p"], st["n_items"]
-    applies = np.mean([i["n_apply"] if i["n_apply"] else i["iters"] + i["cycles"] for i, _ in g["rec"]])
+    applies = np.mean([launches_per_solve(i)["apply"] for i, _ in g["rec"]])
     value = P.n * applies / g["sec"] / 1e9
     cls = summarize_classes(P, g["rec"], args.precision, m_p, n_items)
     dom = max(("apply", "spmv", "orth"), key=lambda k: cls[k]["total_ms"])
@@ -353,7 +371,7 @@ def main():
     if "rec_full" in g:
         fi, fs = g["rec_full"][-1]
         fcls = summarize_classes(P, g["rec_full"], "fp64", P.n_p, fs["n_items"])
-        f_applies = np.mean([i["n_apply"] if i["n_apply"] else i["iters"] + i["cycles"] for i, _ in g["rec_full"]])
+        f_applies = np.mean([launches_per_solve(i)["apply"] for i, _ in g["rec_full"]])
         line["full_fp64"] = {
             "ms_per_step": round(g["sec_full"] * 1000.0, 3),
             "gdofs": round(P.n * f_applies / g["sec_full"] / 1e9, 4),

@@ -72,6 +72,7 @@ enum pr_criterion { PR_CRIT_SPECTRAL = 0, PR_CRIT_L1 = 1, PR_CRIT_FRO = 2 };
  * BF16 high part and a BF16 remainder and sums the three leading products
  * (about 16 significant bits). */
 enum pr_precision { PR_FP64 = 0, PR_FP32 = 1, PR_BF16 = 2, PR_FP16 = 3, PR_BF16X3 = 4 };
+enum pr_apply_form { PR_FORM_AUTO = 0, PR_FORM_GENERAL = 1 };
 
 /* ---- argument structs -------------------------------------------------- */
 
@@ -114,7 +115,9 @@ typedef struct {
     int64_t max_iters;       /* GMRES iteration limit (default 10000) */
     int32_t deterministic;   /* 1: scatter without floating-point atomics (default 0) */
     int32_t timing;          /* 1: pr_solve brackets its kernels with HIP events and
-                                reports per-class device time in pr_solve_info (default 0) */
+                                reports per-class device time in pr_solve_info; k > 1:
+                                only the kernels of every k-th Arnoldi step (an event adds
+                                a few microseconds between kernels) (default 0) */
     void*   stream;          /* hipStream_t for all work (NULL = default stream) */
     /* learned entry predictor for Algorithm 1 (pr_setup, PR_ALGO_TOLERANCE) */
     int32_t mlp;             /* 1: Algorithm 1 with predictions (default 0) */
@@ -127,12 +130,18 @@ typedef struct {
     int32_t mlp_batch;       /* minibatch rows (default 256) */
     int32_t mlp_precision;   /* PR_FP16 (MFMA, FP32 accumulate; default) or PR_FP32 */
     int32_t graph;           /* 1: pr_solve captures one restart cycle in a HIP graph and
-                                replays it (ignored with timing = 1; default 0) */
+                                replays it (ignored with timing != 0; default 0) */
     int32_t autotune;        /* 1: pr_setup times the apply's launch shapes and keeps the
                                 fastest (default 0).  The choice is kept per process, keyed
                                 on the device and the apply's shape (n, patches, entries,
                                 groups, patch sizes, precision, scatter mode); a later setup
                                 of the same shape reuses it without timing */
+    int32_t apply_form;      /* PR_FORM_AUTO (default): when every patch has the same size,
+                                the MFMA apply runs over fixed tiles of 16 or 32 grouped
+                                patches, and when no dof lies in more than 8 patches the
+                                deterministic slot sum reads a padded per-dof slot table;
+                                PR_FORM_GENERAL: work items per database entry and CSR slot
+                                lists.  Both give the same bits */
 } pr_params;
 
 typedef struct pr_handle_s* pr_handle;
@@ -145,7 +154,7 @@ typedef struct {
     int32_t status;          /* PR_OK or PR_NOT_CONVERGED or an error */
     int32_t reserved0;
     double  seconds;         /* wall time of the last pr_solve */
-    /* with params.timing = 1: device milliseconds and launch counts of the
+    /* with params.timing != 0: device milliseconds and launch counts of the
      * preconditioner applications (zero fill + apply kernel), the sparse
      * matrix-vector products and the Gram-Schmidt orthogonalisation */
     double  apply_ms, spmv_ms, orth_ms;
@@ -182,6 +191,10 @@ typedef struct {
     int32_t tune_slot;       /* threads per block of the slot sum */
     int64_t tune_cap;        /* block cap of the patch kernel (0 = none) */
     double  t_autotune;      /* seconds spent timing shapes (inside t_total) */
+    int64_t tune_tiles_per_wave;  /* fixed-tile MFMA kernel: tiles per wavefront (1 or 2;
+                                     0 = default, which is 1) */
+    int64_t tune_xcd_remap;  /* 1: fixed-tile kernel and padded slot sum give each XCD one
+                                contiguous range of blocks (0 = launch order) */
 } pr_stats;
 
 /* ---- entry points ------------------------------------------------------ */

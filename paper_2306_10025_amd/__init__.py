@@ -39,6 +39,7 @@ PR_ERR_BAD_PATCH_PTR = -12
 ALGO = dict(full=0, tolerance=1, kmeans_spectral=2, kmeans_entrywise=3, varmin=4, bootstrap=5)
 CRIT = dict(spectral=0, l1=1, fro=2)
 PREC = dict(fp64=0, fp32=1, bf16=2, fp16=3, bf16x3=4)
+FORM = dict(auto=0, general=1)
 
 
 class pr_csr(Structure):
@@ -59,7 +60,8 @@ class pr_params(Structure):
                 ("stream", c_void_p), ("mlp", c_int32), ("mlp_topk", c_int32),
                 ("mlp_train_frac", c_double), ("mlp_epochs", c_int32), ("mlp_hidden", c_int32),
                 ("mlp_seed", c_uint64), ("mlp_lr", c_double), ("mlp_batch", c_int32),
-                ("mlp_precision", c_int32), ("graph", c_int32), ("autotune", c_int32)]
+                ("mlp_precision", c_int32), ("graph", c_int32), ("autotune", c_int32),
+                ("apply_form", c_int32)]
 
 
 class pr_solve_info(Structure):
@@ -84,7 +86,8 @@ class pr_stats(Structure):
                 ("mlp_scanned", c_int64), ("mlp_fallback", c_int64), ("mlp_loss", c_double),
                 ("mlp_train_acc", c_double), ("t_mlp_train", c_double),
                 ("tune_threads", c_int32), ("tune_slot", c_int32), ("tune_cap", c_int64),
-                ("t_autotune", c_double)]
+                ("t_autotune", c_double), ("tune_tiles_per_wave", c_int64),
+                ("tune_xcd_remap", c_int64)]
 
 
 _SIGS = {
@@ -177,10 +180,11 @@ def make_params(algo="full", criterion="spectral", eps=1e-8, m_target=0, partiti
                 restart=30, max_iters=10000, deterministic=False, timing=False,
                 stream=None, mlp=False, mlp_topk=4, mlp_train_frac=0.1, mlp_epochs=60,
                 mlp_hidden=64, mlp_seed=6, mlp_lr=3e-3, mlp_batch=256,
-                mlp_precision="fp16", graph=False, autotune=False) -> pr_params:
+                mlp_precision="fp16", graph=False, autotune=False, apply_form="auto") -> pr_params:
     p = pr_params_default()
     p.graph = int(graph)
     p.autotune = int(autotune)
+    p.apply_form = FORM[apply_form] if isinstance(apply_form, str) else int(apply_form)
     p.mlp = int(mlp)
     p.mlp_topk = mlp_topk
     p.mlp_train_frac = mlp_train_frac

@@ -34,6 +34,7 @@ struct ApplyGeom {
     int64_t dbst;
     const int32_t* stop;    // optional device flag: return at once when set
     int ypm;                // slot buffer tiles: 16 patches x ypm local rows (see yslot)
+    int remap;              // XCD-aware block order (block_id)
 };
 
 // Slot of local row a of grouped patch s: patches in tiles of 16, inside a
@@ -45,6 +46,17 @@ __device__ __forceinline__ int64_t yslot(int64_t s, int a, int pmax) {
 }
 
 __device__ __forceinline__ bool skip(const ApplyGeom& g) { return g.stop && *g.stop; }
+
+// Block order for an XCD-aware launch: workgroups go to the 8 XCDs round-
+// robin, so block b runs on XCD b % 8; this bijection gives XCD x one
+// contiguous range of logical blocks, so neighbouring tiles share that XCD's
+// L2 (the residual entries they gather stay in one cache).
+__device__ __forceinline__ int64_t block_id(bool remap) {
+    const int64_t b = blockIdx.x;
+    if (!remap) return b;
+    const int64_t nb = gridDim.x, per = nb >> 3, rem = nb & 7, x = b & 7, i = b >> 3;
+    return x * per + (x < rem ? x : rem) + i;
+}
 
 template <typename TX, typename TA, typename TY, int MAXP, int G, bool TWO>
 __global__ __launch_bounds__(256) void k_apply_rows(int64_t count, ApplyGeom g, const TX* __restrict__ db,
@@ -315,6 +327,235 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// grouped MFMA apply over fixed tiles (every patch has p dofs): tile t is the
+// NB consecutive grouped positions t*NB .. t*NB+NB-1 (NB = 16 for p <= 16,
+// 32 for p <= 32), one wavefront per tile, no work-item list.  A tile may
+// straddle database entries: column n of an MFMA product depends on column n
+// of the right operand only, so the wave runs one product per distinct entry
+// of the tile (grouped order keeps them in runs) and each member keeps the
+// columns of its own entry.  Results are bit-identical to the item kernel.
+// ---------------------------------------------------------------------------
+template <int MODE, bool TWO, bool BIG, int TPW>
+__global__ __launch_bounds__(256) void k_apply_tiles(int64_t n_p, int p, ApplyGeom g,
+                                                     const uint16_t* __restrict__ db_lp, int64_t lp_stride,
+                                                     const int32_t* __restrict__ db_exp,
+                                                     const double* __restrict__ W, double omega,
+                                                     const double* __restrict__ r,
+                                                     double* __restrict__ z, float* __restrict__ Y) {
+    if (skip(g)) return;
+    constexpr bool FP16 = MODE == 1;
+    constexpr bool SPLIT = MODE == 2;
+    constexpr int NB = BIG ? 32 : 16;      // members per tile
+    constexpr int NV = BIG ? 16 : 4;       // rows held per lane
+    constexpr int NC = NV / 4;             // K steps (groups of 4 rows) per lane
+    constexpr int L = BIG ? 1024 : 256;    // elements of one lane-ready operand copy
+    constexpr int EB = BIG ? 2 : 4;        // entries per operand batch
+    typedef float accv __attribute__((ext_vector_type(NV)));   // f4 or f16v
+    const int l = threadIdx.x & (PR_WAVE - 1);
+    const int n = l & (NB - 1), h = l / NB;
+    const bool vec4 = (p & 3) == 0;        // rows in aligned groups of 4 dofs
+    const int steps = (p + 7) >> 3;
+    const int64_t n_tiles = (n_p + NB - 1) / NB;
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / PR_WAVE) * TPW;
+    // TPW tiles per wave, loaded together (more loads in flight per wave)
+    for (int64_t t0 = (block_id(g.remap) * (blockDim.x / PR_WAVE) + threadIdx.x / PR_WAVE) * TPW;
+         t0 < n_tiles; t0 += stride) {
+        int32_t jm[TPW], gi[TPW][NV];
+        bool mv[TPW];
+        // 1: entry and dof list of each member
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            const int64_t s = (t0 + u) * NB + n;
+            mv[u] = s < n_p;                                 // false for the whole tile past the end
+            jm[u] = mv[u] ? g.gphi[s] : 0x7fffffff;
+            const int32_t* gd = g.gdofs + (mv[u] ? s : 0) * p;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int row0 = BIG ? 8 * c + 4 * h : 4 * h;   // rows row0 .. row0+3
+                if (vec4) {
+                    int4 v4 = make_int4(-1, -1, -1, -1);
+                    if (mv[u] && row0 < p) v4 = *reinterpret_cast<const int4*>(gd + row0);
+                    gi[u][4 * c + 0] = v4.x;
+                    gi[u][4 * c + 1] = v4.y;
+                    gi[u][4 * c + 2] = v4.z;
+                    gi[u][4 * c + 3] = v4.w;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) gi[u][4 * c + e] = (mv[u] && row0 + e < p) ? gd[row0 + e] : -1;
+                }
+            }
+        }
+        // 2: residual gathers, and the operand of each tile's first entry
+        float rv[TPW][NV];
+        int32_t cur[TPW];
+        s4 ah[TPW][NC], al[TPW][NC];
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) rv[u][v] = gi[u][v] >= 0 ? (float)r[gi[u][v]] : 0.0f;
+            cur[u] = __builtin_amdgcn_readfirstlane(jm[u]);    // member 0's entry (lane 0)
+            const uint16_t* Xl = db_lp + (int64_t)(t0 + u < n_tiles ? cur[u] : 0) * lp_stride;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const bool need = (t0 + u < n_tiles) && (!BIG || c < steps);
+                ah[u][c] = need ? *reinterpret_cast<const s4*>(Xl + (c * 64 + l) * 4) : s4{0, 0, 0, 0};
+                if (SPLIT) al[u][c] = need ? *reinterpret_cast<const s4*>(Xl + L + (c * 64 + l) * 4) : s4{0, 0, 0, 0};
+            }
+        }
+        // 3: products, one per distinct entry of a tile; 4: slot writes
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            if (t0 + u >= n_tiles) break;
+            int f = 0;
+            if (FP16) {
+                float m = 0.0f;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) m = fmaxf(m, fabsf(rv[u][v]));
+                if (!BIG) m = fmaxf(m, __shfl_xor(m, 16));
+                m = fmaxf(m, __shfl_xor(m, 32));
+                f = fp16_scale_exp(m);
+            }
+            s4 bh[NC], bl[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    short hi, lo;
+                    LowOp<MODE>::cvt(FP16 ? ldexpf(rv[u][4 * c + e], -f) : rv[u][4 * c + e], hi, lo);
+                    bh[c][e] = hi;
+                    bl[c][e] = lo;
+                }
+            accv out = {};
+            int oe = 0;
+            // distinct entries of the tile in batches of EB, the operands of a
+            // batch loaded together (a tile over many small groups would
+            // otherwise wait for one load per entry)
+            int32_t j = cur[u];
+            bool first = true;
+            while (true) {
+                int32_t e[EB];
+                bool ex[EB];
+                e[0] = j;
+                ex[0] = true;
+#pragma unroll
+                for (int k = 1; k < EB; ++k) {
+                    const uint64_t more = __ballot(mv[u] && jm[u] > e[k - 1]);
+                    ex[k] = ex[k - 1] && more != 0;
+                    e[k] = ex[k] ? __shfl(jm[u], (int)__builtin_ctzll(more)) : e[k - 1];
+                }
+                s4 xa[EB][NC], xb[EB][NC];
+                int ee[EB];
+#pragma unroll
+                for (int k = 0; k < EB; ++k) {
+                    const uint16_t* Xl = db_lp + (int64_t)e[k] * lp_stride;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        if (k == 0 && first) {
+                            xa[k][c] = ah[u][c];
+                            if (SPLIT) xb[k][c] = al[u][c];
+                        } else {
+                            const bool need = ex[k] && (!BIG || c < steps);
+                            xa[k][c] = need ? *reinterpret_cast<const s4*>(Xl + (c * 64 + l) * 4) : s4{0, 0, 0, 0};
+                            if (SPLIT) xb[k][c] = need ? *reinterpret_cast<const s4*>(Xl + L + (c * 64 + l) * 4) : s4{0, 0, 0, 0};
+                        }
+                    }
+                    ee[k] = (FP16 && ex[k]) ? db_exp[e[k]] : 0;
+                }
+#pragma unroll
+                for (int k = 0; k < EB; ++k) {
+                    if (!ex[k]) break;
+                    accv acc = {};
+                    if constexpr (BIG) {
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) {
+                            if (c < steps) {
+                                acc = mma32<MODE>(xa[k][c], bh[c], acc);
+                                if (SPLIT) {
+                                    acc = mma32<MODE>(xa[k][c], bl[c], acc);
+                                    acc = mma32<MODE>(xb[k][c], bh[c], acc);
+                                }
+                            }
+                        }
+                    } else {
+                        acc = mma16<MODE>(xa[k][0], bh[0], acc);
+                        if (SPLIT) {
+                            acc = mma16<MODE>(xa[k][0], bl[0], acc);
+                            acc = mma16<MODE>(xb[k][0], bh[0], acc);
+                        }
+                    }
+                    if (jm[u] == e[k]) {
+                        out = acc;
+                        if (FP16) oe = ee[k] + f;
+                    }
+                }
+                if (!ex[EB - 1]) break;
+                const uint64_t more = __ballot(mv[u] && jm[u] > e[EB - 1]);
+                if (more == 0) break;
+                j = __shfl(jm[u], (int)__builtin_ctzll(more));
+                first = false;
+            }
+            const int64_t s = (t0 + u) * NB + n;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                if (gi[u][v] >= 0) {
+                    const int row = BIG ? 8 * (v >> 2) + 4 * h + (v & 3) : 4 * h + v;
+                    if (TWO) {
+                        Y[yslot(s, row, g.ypm)] = FP16 ? ldexpf(out[v], oe) : out[v];
+                    } else {
+                        double y = (double)out[v];
+                        if (FP16) y = ldexp(y, oe);
+                        atomicAdd(&z[gi[u][v]], omega * W[gi[u][v]] * y);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// z_i = omega / c_i * sum of the c_i slots of dof i, from a padded table of
+// C slots per dof (ascending, -1 after the last); 1 / c_i is W_i.  Same
+// summation order, hence the same bits, as k_slot_sum.
+template <typename TY, int C>
+__global__ __launch_bounds__(256) void k_slot_sum_ell(int64_t n, const int32_t* __restrict__ ell,
+                                                      const TY* __restrict__ Y, double omega,
+                                                      double* __restrict__ z, const int32_t* __restrict__ stop,
+                                                      int remap) {
+    if (stop && *stop) return;
+    const int64_t i = block_id(remap) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t sl[C];
+    if (C >= 4) {
+#pragma unroll
+        for (int u = 0; u < C; u += 4) {
+            const int4 v = *reinterpret_cast<const int4*>(ell + i * C + u);
+            sl[u] = v.x;
+            sl[u + 1] = v.y;
+            sl[u + 2] = v.z;
+            sl[u + 3] = v.w;
+        }
+    } else if (C == 2) {
+        const int2 v = *reinterpret_cast<const int2*>(ell + i * 2);
+        sl[0] = v.x;
+        sl[C - 1] = v.y;
+    } else {
+        sl[0] = ell[i];
+    }
+    TY yv[C];
+#pragma unroll
+    for (int u = 0; u < C; ++u) yv[u] = sl[u] >= 0 ? Y[sl[u]] : (TY)0;
+    double acc = 0.0;
+    int c = 0;
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+        if (sl[u] >= 0) {
+            acc += (double)yv[u];
+            ++c;
+        }
+    }
+    z[i] = omega * (1.0 / (double)c) * acc;
+}
+
+// ---------------------------------------------------------------------------
 // database conversion: one wavefront per entry
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_convert_db(int prec, int64_t m_p, const double* __restrict__ db,
@@ -368,7 +609,7 @@ __global__ __launch_bounds__(64) void k_convert_db(int prec, int64_t m_p, const 
 }  // namespace
 
 void launch_apply(int prec, bool two_stage, const ApplyLaunch& a, hipStream_t s) {
-    ApplyGeom g{a.gdofs, a.goff, a.pst, a.gphi, a.dboff, a.dbst, a.stop, a.maxp};
+    ApplyGeom g{a.gdofs, a.goff, a.pst, a.gphi, a.dboff, a.dbst, a.stop, a.maxp, a.xcd_remap};
     const int T = (a.threads == 64 || a.threads == 128) ? a.threads : 256;
     const int64_t cap = a.grid_cap;
     if (prec == PR_FP64) {
@@ -377,6 +618,32 @@ void launch_apply(int prec, bool two_stage, const ApplyLaunch& a, hipStream_t s)
     } else if (prec == PR_FP32) {
         if (two_stage) run_rows<float, float, float, true>(a.n_p, g, a.db_f32, a.W, a.omega, a.r, a.z, (float*)a.Y, a.maxp, T, cap, s);
         else run_rows<float, float, float, false>(a.n_p, g, a.db_f32, a.W, a.omega, a.r, a.z, (float*)nullptr, a.maxp, T, cap, s);
+    } else if (a.tile_p > 0) {
+        // every patch has tile_p dofs: fixed tiles, no work items
+        const bool big = a.tile_p > 16;
+        const int NB = big ? 32 : 16;
+        const int64_t n_tiles = (a.n_p + NB - 1) / NB;
+        const int mode = prec == PR_FP16 ? 1 : prec == PR_BF16X3 ? 2 : 0;
+        const int64_t lp_stride = (mode == 2 ? 2 : 1) * (big ? 1024 : 256);
+        // tiles per wave: 1 unless the shape asks for 2 (16-member tiles only)
+        const int tpw = (!big && a.tiles_per_wave == 2) ? 2 : 1;
+        if (n_tiles > 0) {
+            const unsigned nb = shape_blocks((n_tiles + tpw - 1) / tpw, T / PR_WAVE, cap);
+#define PR_TILE(MODE, TWO, BIG, U) k_apply_tiles<MODE, TWO, BIG, U><<<nb, T, 0, s>>>(a.n_p, a.tile_p, g, a.db_lp, lp_stride, a.db_exp, a.W, a.omega, a.r, a.z, (float*)a.Y)
+#define PR_TILE_M(TWO, BIG, U) \
+    if (mode == 0) PR_TILE(0, TWO, BIG, U); else if (mode == 1) PR_TILE(1, TWO, BIG, U); else PR_TILE(2, TWO, BIG, U)
+            if (two_stage) {
+                if (big) { PR_TILE_M(true, true, 1); }
+                else if (tpw == 2) { PR_TILE_M(true, false, 2); }
+                else { PR_TILE_M(true, false, 1); }
+            } else {
+                if (big) { PR_TILE_M(false, true, 1); }
+                else if (tpw == 2) { PR_TILE_M(false, false, 2); }
+                else { PR_TILE_M(false, false, 1); }
+            }
+#undef PR_TILE_M
+#undef PR_TILE
+        }
     } else {
         if (a.n_items > 0) {
             const unsigned nb = shape_blocks(a.n_items, T / PR_WAVE, cap);
@@ -393,7 +660,14 @@ void launch_apply(int prec, bool two_stage, const ApplyLaunch& a, hipStream_t s)
     if (two_stage) {
         const int T2 = (a.slot_threads == 64 || a.slot_threads == 128) ? a.slot_threads : 256;
         const unsigned nb = (unsigned)((a.n + T2 - 1) / T2);
-        if (prec == PR_FP64)
+        if (a.ell_c > 0) {
+#define PR_ELL(TY, C) k_slot_sum_ell<TY, C><<<nb, T2, 0, s>>>(a.n, a.ell, (const TY*)a.Y, a.omega, a.z, a.stop, a.xcd_remap)
+#define PR_ELL_C(TY) \
+    if (a.ell_c == 1) PR_ELL(TY, 1); else if (a.ell_c == 2) PR_ELL(TY, 2); else if (a.ell_c == 4) PR_ELL(TY, 4); else PR_ELL(TY, 8)
+            if (prec == PR_FP64) { PR_ELL_C(double); } else { PR_ELL_C(float); }
+#undef PR_ELL_C
+#undef PR_ELL
+        } else if (prec == PR_FP64)
             k_slot_sum<double><<<nb, T2, 0, s>>>(a.n, a.dof_ptr, a.dof_slots, (const double*)a.Y, a.W, a.omega, a.z, a.stop);
         else
             k_slot_sum<float><<<nb, T2, 0, s>>>(a.n, a.dof_ptr, a.dof_slots, (const float*)a.Y, a.W, a.omega, a.z, a.stop);

@@ -378,6 +378,23 @@ __global__ void k_transpose_sort(int64_t n, const int64_t* __restrict__ dof_ptr,
     }
 }
 
+// largest count (one atomic per wavefront)
+__global__ void k_max_i32(const int32_t* __restrict__ a, int64_t n, int32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t v = i < n ? a[i] : 0;
+    v = wave_max(v);
+    if ((threadIdx.x & (PR_WAVE - 1)) == 0) atomicMax(out, v);
+}
+
+// padded copy of the dof -> slot lists: C entries per dof, -1 after the last
+__global__ void k_build_ell(int64_t n, const int64_t* __restrict__ dof_ptr,
+                            const int32_t* __restrict__ dof_slots, int C, int32_t* __restrict__ ell) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t a = dof_ptr[i], c = dof_ptr[i + 1] - a;
+    for (int u = 0; u < C; ++u) ell[i * C + u] = u < c ? dof_slots[a + u] : -1;
+}
+
 __global__ void k_i32_to_i64(const int32_t* __restrict__ in, int64_t* __restrict__ out, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = in[i];
@@ -492,6 +509,15 @@ void launch_transpose_fill(const int32_t* gdofs, const int64_t* goff, int pst, i
 
 void launch_transpose_sort(int64_t n, const int64_t* dof_ptr, int32_t* dof_slots, hipStream_t s) {
     if (n > 0) k_transpose_sort<<<nblk(n, 256), 256, 0, s>>>(n, dof_ptr, dof_slots);
+}
+
+void launch_max_i32(const int32_t* a, int64_t n, int32_t* out, hipStream_t s) {
+    if (n > 0) k_max_i32<<<nblk(n, 256), 256, 0, s>>>(a, n, out);
+}
+
+void launch_build_ell(int64_t n, const int64_t* dof_ptr, const int32_t* dof_slots, int C, int32_t* ell,
+                      hipStream_t s) {
+    if (n > 0) k_build_ell<<<nblk(n, 256), 256, 0, s>>>(n, dof_ptr, dof_slots, C, ell);
 }
 
 void launch_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, hipStream_t s) {

@@ -472,6 +472,22 @@ int run_group(pr_handle h) {
         launch_transpose_fill(h->gdofs, h->goff, h->uniform ? h->max_ps : 0, n_p, h->max_ps, h->dof_ptr, fill,
                               h->dof_slots, s);
         launch_transpose_sort(h->n, h->dof_ptr, h->dof_slots, s);
+        if (h->prm.apply_form == PR_FORM_AUTO) {
+            // padded table when no dof lies in more than 8 patches
+            int32_t* cmax = nullptr;
+            PR_TRY(dalloc(h, &cmax, 1));
+            PR_HIP(h, hipMemsetAsync(cmax, 0, sizeof(int32_t), s));
+            launch_max_i32(h->cnt, h->n, cmax, s);
+            int32_t c = 0;
+            PR_HIP(h, hipMemcpyAsync(&c, cmax, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            PR_HIP(h, hipStreamSynchronize(s));
+            if (c >= 1 && c <= 8) {
+                const int C = c <= 1 ? 1 : c <= 2 ? 2 : c <= 4 ? 4 : 8;
+                PR_TRY(dalloc(h, &h->dof_ell, (size_t)h->n * C));
+                launch_build_ell(h->n, h->dof_ptr, h->dof_slots, C, h->dof_ell, s);
+                h->ell_c = C;
+            }
+        }
         const size_t ybytes = h->prm.apply_precision == PR_FP64 ? 8 : 4;
         char* yb = nullptr;
         PR_TRY(dalloc(h, &yb, (size_t)((n_p + 15) / 16) * 16 * h->max_ps * ybytes));
@@ -492,6 +508,8 @@ int run_group(pr_handle h) {
         start += count[j];
     }
     h->n_items = (int64_t)items.size() / 4;
+    // every patch of one size: the MFMA apply runs over fixed tiles instead
+    h->tile_p = (h->uniform && h->prm.apply_form == PR_FORM_AUTO && h->max_ps <= 32) ? h->max_ps : 0;
     PR_TRY(dalloc(h, &h->items, items.size()));
     PR_HIP(h, hipMemcpyAsync(h->items, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     // database offsets / sizes on the device
@@ -561,8 +579,13 @@ int apply_op(pr_handle h, const double* r, double* z, bool accumulate, double* t
     a.Y = h->Ybuf;
     a.dof_ptr = h->dof_ptr;
     a.dof_slots = h->dof_slots;
+    a.ell = h->dof_ell;
+    a.ell_c = h->ell_c;
+    a.tile_p = h->tile_p;
     a.threads = h->tune_threads;
     a.grid_cap = h->tune_cap;
+    a.tiles_per_wave = h->tune_tpw;
+    a.xcd_remap = h->tune_remap;
     a.slot_threads = h->tune_slot;
     if (two) {
         a.z = accumulate ? tmp : z;
@@ -616,7 +639,7 @@ int ensure_workspace(pr_handle h, int m) {
 // the same device reuses it without timing.
 using TuneKey = std::array<int64_t, 11>;
 std::mutex g_tune_mu;
-std::map<TuneKey, std::array<int64_t, 3>> g_tune_cache;
+std::map<TuneKey, std::array<int64_t, 5>> g_tune_cache;
 
 int autotune_apply(pr_handle h) {
     const double t0 = now_s();
@@ -630,6 +653,9 @@ int autotune_apply(pr_handle h) {
             h->tune_threads = h->stats.tune_threads = (int)it->second[0];
             h->tune_cap = h->stats.tune_cap = it->second[1];
             h->tune_slot = h->stats.tune_slot = (int)it->second[2];
+            h->tune_tpw = (int)it->second[3];
+            h->stats.tune_tiles_per_wave = it->second[3];
+            h->tune_remap = h->stats.tune_xcd_remap = (int)it->second[4];
             h->stats.t_autotune = now_s() - t0;
             return PR_OK;
         }
@@ -662,10 +688,12 @@ int autotune_apply(pr_handle h) {
     PR_HIP(h, hipEventCreate(&sc.e0));
     PR_HIP(h, hipEventCreate(&sc.e1));
     hipEvent_t e0 = sc.e0, e1 = sc.e1;
-    auto time_shape = [&](int T, int64_t cap, int T2, float& ms) -> int {
+    auto time_shape = [&](int T, int64_t cap, int T2, int tpw, int rm, float& ms) -> int {
         h->tune_threads = T;
         h->tune_cap = cap;
         h->tune_slot = T2;
+        h->tune_tpw = tpw;
+        h->tune_remap = rm;
         for (int k = 0; k < 2; ++k) PR_TRY(apply_op(h, r, z, false, tmp));
         PR_HIP(h, hipEventRecord(e0, s));
         for (int k = 0; k < 5; ++k) PR_TRY(apply_op(h, r, z, false, tmp));
@@ -674,24 +702,37 @@ int autotune_apply(pr_handle h) {
         PR_HIP(h, hipEventElapsedTime(&ms, e0, e1));
         return PR_OK;
     };
-    int bt = 256, bs = 256;
+    int bt = 256, bs = 256, bu = 0, br = 0;
     int64_t bc = 0;
     float best = 1e30f;
-    for (int T : {64, 128, 256})
-        for (int64_t cap : {(int64_t)0, (int64_t)1024, (int64_t)2048, (int64_t)4096, (int64_t)8192}) {
-            float ms = 0.0f;
-            PR_TRY(time_shape(T, cap, 256, ms));
-            if (ms < best) {
-                best = ms;
-                bt = T;
-                bc = cap;
-            }
+    // tiles per wave is a choice of the fixed-tile kernel for 16-member tiles only
+    const bool tpw_choice = h->tile_p > 0 && h->tile_p <= 16 && h->apply_prec != PR_FP64 &&
+                            h->apply_prec != PR_FP32;
+    // XCD-contiguous block order: a choice of the fixed-tile kernel and the padded slot sum
+    const bool remap_choice = h->tile_p > 0 || h->ell_c > 0;
+    for (int rm : {0, 1}) {
+        if (rm == 1 && !remap_choice) break;
+        for (int u : {1, 2}) {
+            if (u == 2 && !tpw_choice) break;
+            for (int T : {64, 128, 256})
+                for (int64_t cap : {(int64_t)0, (int64_t)1024, (int64_t)2048, (int64_t)4096, (int64_t)8192}) {
+                    float ms = 0.0f;
+                    PR_TRY(time_shape(T, cap, 256, tpw_choice ? u : 0, rm, ms));
+                    if (ms < best) {
+                        best = ms;
+                        bt = T;
+                        bc = cap;
+                        bu = tpw_choice ? u : 0;
+                        br = rm;
+                    }
+                }
         }
+    }
     if (h->prm.deterministic) {
         best = 1e30f;
         for (int T2 : {64, 128, 256}) {
             float ms = 0.0f;
-            PR_TRY(time_shape(bt, bc, T2, ms));
+            PR_TRY(time_shape(bt, bc, T2, bu, br, ms));
             if (ms < best) {
                 best = ms;
                 bs = T2;
@@ -701,12 +742,16 @@ int autotune_apply(pr_handle h) {
     h->tune_threads = bt;
     h->tune_cap = bc;
     h->tune_slot = bs;
+    h->tune_tpw = bu;
+    h->stats.tune_tiles_per_wave = bu;
+    h->tune_remap = br;
+    h->stats.tune_xcd_remap = br;
     h->stats.tune_threads = bt;
     h->stats.tune_slot = bs;
     h->stats.tune_cap = bc;
     h->stats.t_autotune = now_s() - t0;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = {bt, bc, bs};
+    g_tune_cache[key] = {bt, bc, bs, bu, br};
     return PR_OK;
 }
 
@@ -853,6 +898,7 @@ void pr_params_default(pr_params* p) {
     p->mlp_precision = PR_FP16;
     p->graph = 0;
     p->autotune = 0;
+    p->apply_form = PR_FORM_AUTO;
 }
 
 const char* pr_status_string(int st) {
@@ -952,7 +998,8 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
     if (A->n > INT_MAX - 1 || P->n_p > INT_MAX - 1) return pr_fail(nullptr, PR_ERR_UNSUPPORTED, "more than 2^31 dofs or patches");
     if (pm.algo < PR_ALGO_FULL || pm.algo > PR_ALGO_BOOTSTRAP || pm.criterion < 0 || pm.criterion > 2 ||
         pm.apply_precision < 0 || pm.apply_precision > 4 || pm.sweeps < 1 || pm.gmres_restart < 1 ||
-        pm.gmres_restart > 64 || !(pm.eps >= 0.0) || !(pm.omega > 0.0))
+        pm.gmres_restart > 64 || !(pm.eps >= 0.0) || !(pm.omega > 0.0) ||
+        (pm.apply_form != PR_FORM_AUTO && pm.apply_form != PR_FORM_GENERAL))
         return pr_fail(nullptr, PR_ERR_INVALID_ARG, "bad parameter value");
     if (pm.algo != PR_ALGO_FULL && pm.algo != PR_ALGO_TOLERANCE &&
         (pm.kmeans_max_iter < 1 || !(pm.tie_rel >= 0.0)))
@@ -1150,10 +1197,19 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
     const double tstart = now_s();
     // optional per-class device timing: 0 apply, 1 spmv, 2 orthogonalisation
     const bool timing = h->prm.timing != 0;
+    // timing = k > 1: only every k-th Arnoldi step is bracketed (the events
+    // themselves add a gap between kernels)
+    const int tstride = h->prm.timing > 1 ? h->prm.timing : 1;
+    bool tsel = timing;
     // graph replay of whole restart cycles (not with per-kernel timing)
     const bool use_graph = h->prm.graph != 0 && !timing;
-    struct Span { int cls; hipEvent_t a, b; };
+    // a span records the cycle and Arnoldi step it belongs to (-1: cycle end),
+    // so that the steps a stopped cycle skipped are not counted
+    struct Span { int cls; hipEvent_t a, b; int64_t cyc; int j; };
     std::vector<Span> spans;
+    std::vector<int64_t> done_cols;   // Arnoldi steps that ran, per cycle
+    int64_t tcyc = -1;
+    int tj = -1;
     size_t evnext = 0;
     auto grab = [&]() -> hipEvent_t {
         if (evnext >= h->evpool.size()) {
@@ -1166,17 +1222,17 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
     hipStream_t s = h->stream;
     hipEvent_t tb = nullptr;
     auto tbeg = [&]() {
-        if (timing) {
+        if (tsel) {
             tb = grab();
             if (tb) (void)hipEventRecord(tb, s);
         }
     };
     auto tend = [&](int cls) {
-        if (timing && tb) {
+        if (tsel && tb) {
             hipEvent_t te = grab();
             if (te) {
                 (void)hipEventRecord(te, s);
-                spans.push_back({cls, tb, te});
+                spans.push_back({cls, tb, te, tcyc, tj});
             }
         }
     };
@@ -1254,9 +1310,12 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
     // kernels of a stopped cycle return at once), then x += M(V y),
     // r = b - A x and ||r||^2 -> hd[0] for the next cycle.
     auto enqueue_cycle = [&]() -> int {
+        ++tcyc;
         launch_cycle_init(g, m, hd, gctl, s);
         launch_scale(r, V, hd, n, s);
         for (int j = 0; j < m; ++j) {
+            tsel = timing && (tcyc * m + j) % tstride == 0;
+            tj = j;
             double* vj = V + (int64_t)j * ldv;
             tbeg();
             PR_TRY(precond(h, vj, zt, t3, gctl));
@@ -1275,6 +1334,8 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
             tend(2);
             launch_givens(j, m, hd, R, cs, sn, g, est_d, gctl, tol_d, itb_d, h->prm.max_iters, s);
         }
+        tsel = timing && tstride == 1;
+        tj = -1;
         launch_trisolve(m, R, g, y, gctl, s);
         launch_gemv_small(V, ldv, gctl + 1, y, n, r, s);
         tbeg();
@@ -1321,6 +1382,7 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
         PR_HIP(h, hipMemcpyAsync(hh + 239, est_d, sizeof(double), hipMemcpyDeviceToHost, s));
         PR_TRY(sync_read(1));
         iters += gctl_h[1];
+        done_cols.push_back(gctl_h[1]);
         est = hh[239] / bnorm;
         relres = std::sqrt(hh[0]) / bnorm;
     }
@@ -1335,6 +1397,7 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
     h->sinfo.seconds = now_s() - tstart;
     for (const Span& sp : spans) {
         float ms = 0.0f;
+        if (sp.j >= 0 && (sp.cyc >= (int64_t)done_cols.size() || sp.j >= done_cols[sp.cyc])) continue;
         if (hipEventElapsedTime(&ms, sp.a, sp.b) != hipSuccess) continue;
         if (sp.cls == 0) { h->sinfo.apply_ms += ms; h->sinfo.n_apply++; }
         if (sp.cls == 1) { h->sinfo.spmv_ms += ms; h->sinfo.n_spmv++; }

@@ -121,8 +121,17 @@ int solve_batch(pr_handle h, const double* b, double* x, double tol) {
     hipStream_t s = h->stream;
     // optional per-class device timing: 0 apply, 1 spmv, 2 orthogonalisation
     const bool timing = h->prm.timing != 0;
-    struct Span { int cls; hipEvent_t a, b; };
+    // timing = k > 1: only every k-th Arnoldi step is bracketed (the events
+    // themselves add a gap between kernels)
+    const int tstride = h->prm.timing > 1 ? h->prm.timing : 1;
+    bool tsel = timing;
+    // a span records the cycle and Arnoldi step it belongs to, so that the
+    // steps after every system stopped are not counted
+    struct Span { int cls; hipEvent_t a, b; int64_t cyc; int j; };
     std::vector<Span> spans;
+    std::vector<int64_t> done_cols;   // steps that ran (largest over the systems), per cycle
+    int64_t tcyc = -1;
+    int tj = -1;
     size_t evnext = 0;
     auto grab = [&]() -> hipEvent_t {
         if (evnext >= h->evpool.size()) {
@@ -134,17 +143,17 @@ int solve_batch(pr_handle h, const double* b, double* x, double tol) {
     };
     hipEvent_t tb = nullptr;
     auto tbeg = [&]() {
-        if (timing) {
+        if (tsel) {
             tb = grab();
             if (tb) (void)hipEventRecord(tb, s);
         }
     };
     auto tend = [&](int cls) {
-        if (timing && tb) {
+        if (tsel && tb) {
             hipEvent_t te = grab();
             if (te) {
                 (void)hipEventRecord(te, s);
-                spans.push_back({cls, tb, te});
+                spans.push_back({cls, tb, te, tcyc, tj});
             }
         }
     };
@@ -197,6 +206,7 @@ int solve_batch(pr_handle h, const double* b, double* x, double tol) {
     const int64_t maxit = h->prm.max_iters;
     for (;;) {
         PR_TRY(norms(r));
+        if (cycles > 0) done_cols.push_back(*std::max_element(cols_h.begin(), cols_h.end()));
         bool any = false;
         for (int i = 0; i < ns; ++i) {
             if (cycles > 0) its[i] += cols_h[i];
@@ -208,11 +218,14 @@ int solve_batch(pr_handle h, const double* b, double* x, double tol) {
         }
         if (!any) break;
         ++cycles;
+        ++tcyc;
         PR_HIP(h, hipMemcpyAsync(act, act_h.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, s));
         PR_HIP(h, hipMemcpyAsync(h->bbase, its.data(), ns * sizeof(int64_t), hipMemcpyHostToDevice, s));
         launch_bcycle_init(ns, m, NR, act, gv, sstop, scols, gstop, s);
         launch_bscale(r, V, bg, NR, sstop, gstop, s);
         for (int j = 0; j < m; ++j) {
+            tsel = timing && (tcyc * m + j) % tstride == 0;
+            tj = j;
             double* vj = V + (int64_t)j * ldv;
             tbeg();
             PR_TRY(pr_precond_internal(h, vj, zt, t3, gstop));
@@ -250,6 +263,7 @@ int solve_batch(pr_handle h, const double* b, double* x, double tol) {
     h->sinfo.seconds = now_s() - tstart;
     for (const Span& sp : spans) {
         float ms = 0.0f;
+        if (sp.j >= 0 && (sp.cyc >= (int64_t)done_cols.size() || sp.j >= done_cols[sp.cyc])) continue;
         if (hipEventElapsedTime(&ms, sp.a, sp.b) != hipSuccess) continue;
         if (sp.cls == 0) { h->sinfo.apply_ms += ms; h->sinfo.n_apply++; }
         if (sp.cls == 1) { h->sinfo.spmv_ms += ms; h->sinfo.n_spmv++; }

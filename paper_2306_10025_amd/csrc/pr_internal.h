@@ -115,10 +115,15 @@ struct pr_handle_s {
     int32_t* gphi = nullptr;      // entry of each grouped position
     int64_t* dof_ptr = nullptr;   // dof -> grouped slots (deterministic scatter)
     int32_t* dof_slots = nullptr;
+    int32_t* dof_ell = nullptr;   // padded dof -> slots table (ell_c per dof) or null
+    int ell_c = 0;
+    int tile_p = 0;               // > 0: MFMA apply over fixed tiles of patches with tile_p dofs
     void* Ybuf = nullptr;         // slot values of the deterministic scatter
     int tune_threads = 0;         // apply launch shape (autotuned or defaults)
     int64_t tune_cap = 0;
     int tune_slot = 0;
+    int tune_tpw = 0;             // tiles per wave of the fixed-tile kernel (0: default)
+    int tune_remap = 0;           // XCD-contiguous block order (fixed tiles, padded slot sum)
 
     // solve workspace
     double* V = nullptr;
@@ -396,6 +401,7 @@ struct ApplyLaunch {
     const int32_t* db_exp;
     const int32_t* items;
     int64_t n_items;
+    int tile_p = 0;            // > 0: every patch has tile_p dofs (fixed MFMA tiles, no items)
     // vectors
     const double* W;
     double omega;
@@ -405,12 +411,16 @@ struct ApplyLaunch {
     void* Y;
     const int64_t* dof_ptr;
     const int32_t* dof_slots;
+    const int32_t* ell = nullptr;  // padded dof -> slots table (ell_c per dof), or null
+    int ell_c = 0;
     const int32_t* stop;       // optional device flag: skip the work when set
     // launch shape (0: defaults): threads per block of the patch kernel
     // (64, 128 or 256), block cap, threads per block of the slot sum
     int threads = 0;
     int64_t grid_cap = 0;
     int slot_threads = 0;
+    int tiles_per_wave = 0;    // fixed-tile MFMA kernel: 1 or 2 (0: default)
+    int xcd_remap = 0;         // fixed-tile kernel and padded slot sum: XCD-contiguous block order
 };
 // z (+)= omega M~^{-1} r.  Atomic mode accumulates into z (caller zeroes it);
 // two-stage mode overwrites z.
@@ -428,6 +438,11 @@ void launch_transpose_fill(const int32_t* gdofs, const int64_t* goff, int pst, i
                            const int64_t* dof_ptr, int32_t* fill, int32_t* dof_slots, hipStream_t s);
 void launch_transpose_sort(int64_t n, const int64_t* dof_ptr, int32_t* dof_slots, hipStream_t s);
 void launch_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, hipStream_t s);
+// *out = max(*out, max_i a[i]) (caller initialises *out)
+void launch_max_i32(const int32_t* a, int64_t n, int32_t* out, hipStream_t s);
+// ell[i*C + u] = u-th slot of dof i, -1 past its count (C >= every count)
+void launch_build_ell(int64_t n, const int64_t* dof_ptr, const int32_t* dof_slots, int C, int32_t* ell,
+                      hipStream_t s);
 
 // k_krylov.hip  (kernels with a `stop` argument return at once when *stop != 0)
 void launch_scale(const double* src, double* dst, const double* denom, int64_t n, hipStream_t s,

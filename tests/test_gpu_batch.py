@@ -196,14 +196,18 @@ def test_graph_replay_matches_eager(case):
     graph.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
-def test_autotuned_apply_is_bit_identical(precision):
-    P = gen.uneven_stokes_batch(n_sys=6, nmin=2, nmax=7)
+@pytest.mark.parametrize("precision,shape", [("fp64", "uneven"), ("fp32", "uneven"), ("bf16x3", "uneven"),
+                                             ("bf16x3", "uniform"), ("fp16", "uniform")])
+def test_autotuned_apply_is_bit_identical(precision, shape):
+    P = gen.uneven_stokes_batch(n_sys=6, nmin=2, nmax=7) if shape == "uneven" else gen.nedelec_hex(7)
     kw = dict(algo="tolerance", precision=precision, deterministic=True)
     plain = pr.PatchRelax(P.A, P.ptr, P.dofs, **kw)
     tuned = pr.PatchRelax(P.A, P.ptr, P.dofs, autotune=True, **kw)
     st = tuned.stats()
-    say(precision, "tuned shape", st["tune_threads"], st["tune_cap"], st["tune_slot"], "in %.4f s" % st["t_autotune"])
+    say(precision, shape, "tuned shape", st["tune_threads"], st["tune_cap"], st["tune_slot"],
+        st["tune_tiles_per_wave"], "in %.4f s" % st["t_autotune"])
+    assert st["tune_tiles_per_wave"] in ((1, 2) if shape == "uniform" and precision != "fp64" else (0,))
+    assert st["tune_xcd_remap"] in (0, 1)
     assert st["tune_threads"] in (64, 128, 256) and st["tune_slot"] in (64, 128, 256)
     assert st["tune_cap"] in (0, 1024, 2048, 4096, 8192)
     r = torch.as_tensor(gen.rhs(P.n, 7)).to(DEV)
@@ -216,8 +220,8 @@ def test_autotuned_apply_is_bit_identical(precision):
     # a second setup of the same shape reuses the choice without timing
     again = pr.PatchRelax(P.A, P.ptr, P.dofs, autotune=True, **kw)
     st2 = again.stats()
-    assert (st2["tune_threads"], st2["tune_cap"], st2["tune_slot"]) == \
-        (st["tune_threads"], st["tune_cap"], st["tune_slot"])
+    assert (st2["tune_threads"], st2["tune_cap"], st2["tune_slot"], st2["tune_tiles_per_wave"]) == \
+        (st["tune_threads"], st["tune_cap"], st["tune_slot"], st["tune_tiles_per_wave"])
     assert st2["t_autotune"] < 0.25 * st["t_autotune"]
     z3 = torch.full_like(r, np.nan)
     again.apply(r, z3)

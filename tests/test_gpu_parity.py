@@ -326,6 +326,35 @@ def test_gmres_matches_oracle(case):
     h.close()
 
 
+@pytest.mark.parametrize("stride", [1, 7])
+def test_solve_timing_counts_the_steps_that_ran(stride):
+    """Per-class event timing counts every launch that did work (stride 1) or
+    the launches of every stride-th Arnoldi step; the steps a converged cycle
+    skips are never counted.  Timing does not change the iterates."""
+    P = gen.q1_poisson_2d(32)
+    b = dt(_rhs(P.n), torch.float64)
+    h0 = pr.PatchRelax(P.A, P.ptr, P.dofs, algo="tolerance", deterministic=True)
+    ht = pr.PatchRelax(P.A, P.ptr, P.dofs, algo="tolerance", deterministic=True, timing=stride)
+    x0 = torch.zeros_like(b)
+    xt = torch.zeros_like(b)
+    h0.solve(b, x0, 1e-8)
+    ht.solve(b, xt, 1e-8)
+    i0, it = h0.solve_info(), ht.solve_info()
+    assert it["iters"] == i0["iters"] and torch.equal(x0, xt)
+    iters, cycles = it["iters"], it["cycles"]
+    say("timing stride", stride, "iters", iters, "cycles", cycles, "timed", it["n_apply"], it["n_spmv"], it["n_orth"])
+    assert iters % 30 != 0                      # the last cycle stopped early
+    if stride == 1:
+        assert (it["n_apply"], it["n_spmv"], it["n_orth"]) == (iters + cycles, iters + cycles, iters)
+    else:
+        k = -(-iters // stride)                  # steps 0, 7, 14, ... below iters
+        assert (it["n_apply"], it["n_spmv"], it["n_orth"]) == (k, k, k)
+    assert it["apply_ms"] > 0 and it["spmv_ms"] > 0 and it["orth_ms"] > 0
+    assert i0["n_apply"] == 0
+    h0.close()
+    ht.close()
+
+
 def test_gmres_bf16_compressed_within_iteration_bound():
     P = gen.q1_poisson_2d(32)
     b = _rhs(P.n)
@@ -452,3 +481,65 @@ def test_deterministic_solve_matches_atomic_iterations():
         its.append(h.solve_info()["iters"])
         h.close()
     assert abs(its[0] - its[1]) <= 1
+
+
+# ---- apply forms: fixed tiles + padded slot table vs work items + CSR lists ----
+
+def _dup_patches(P, times):
+    """The same problem with every patch listed `times` times (dofs then lie in
+    up to 4 * times patches: the padded slot table no longer applies)."""
+    lists = [P.patch(k) for k in range(P.n_p)] * times
+    ptr = np.zeros(len(lists) + 1, dtype=np.int64)
+    ptr[1:] = np.cumsum([len(d) for d in lists])
+    return gen.Problem(P.name + "_dup", P.A, ptr, np.concatenate(lists).astype(np.int32), dict(P.meta))
+
+
+FORM_CASES = {
+    "q1_32": lambda: gen.q1_poisson_2d(32),            # p 4, whole tiles
+    "nedelec_6": lambda: gen.nedelec_hex(6),           # p 12, ragged last tile
+    "stokes_7": lambda: gen.taylor_hood_stokes_2d(7),  # p 22 (32-member tiles), ragged
+    "q2hex_5": lambda: gen.q2_hex_diffusion(5),        # p 27, ragged, 8 slots per vertex dof
+    "q1_8_dup3": lambda: _dup_patches(gen.q1_poisson_2d(8), 3),  # 12 slots per dof: CSR lists
+    "batch_5": lambda: gen.uneven_stokes_batch(n_sys=5, nmin=2, nmax=6),  # uneven: items
+}
+
+
+@pytest.mark.parametrize("case", list(FORM_CASES))
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16", "fp16", "bf16x3"])
+def test_apply_forms_are_bit_identical(case, precision):
+    P = FORM_CASES[case]()
+    kw = dict(algo="tolerance", eps=1e-8, precision=precision, deterministic=True, omega=0.9)
+    ha = pr.PatchRelax(P.A, P.ptr, P.dofs, **kw)
+    hg = pr.PatchRelax(P.A, P.ptr, P.dofs, apply_form="general", **kw)
+    r = _rhs(P.n, 4) * np.exp(np.random.default_rng(3).uniform(-3, 3, P.n))
+    rt = dt(r, torch.float64)
+    za = torch.full_like(rt, np.nan)
+    zg = torch.full_like(rt, np.nan)
+    ha.apply(rt, za)
+    hg.apply(rt, zg)
+    torch.cuda.synchronize()
+    a, g = za.cpu().numpy(), zg.cpu().numpy()
+    assert np.array_equal(a.view(np.uint64), g.view(np.uint64)), (case, precision)
+    # and both are the operator of the oracle
+    phi, reps = ha.assignment()
+    _, W = O.cover_weights(P.n, P.ptr, P.dofs)
+    tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
+    Xdb = [O.factor_inverse(tiles[x]) for x in reps]
+    ps = int(np.diff(P.ptr).max())
+    if precision == "fp64":
+        z_o = O.apply_patch(P.ptr, P.dofs, W, Xdb, phi, r, 0.9)
+        kappa = max(np.linalg.cond(tiles[x]) for x in reps)
+        assert np.abs(a - z_o).max() / np.abs(z_o).max() <= max(1e-12, 8 * 32 * kappa * 2.2e-16)
+    else:
+        z_e, bound = O.apply_lowprec(P.ptr, P.dofs, W, Xdb, phi, r, 0.9, precision, return_bound=True)
+        assert np.all(np.abs(a - z_e) <= (ps + 8) * 2.0 ** -24 * bound + 1e-300), (case, precision)
+    # atomic scatter through the tile kernel: the same operator up to summation order
+    hat = pr.PatchRelax(P.A, P.ptr, P.dofs, algo="tolerance", eps=1e-8, precision=precision, omega=0.9)
+    zt = torch.zeros_like(rt)
+    hat.apply(rt, zt)
+    torch.cuda.synchronize()
+    t = zt.cpu().numpy()
+    assert np.abs(t - a).max() <= 1e-10 * np.abs(a).max(), (case, precision)
+    ha.close()
+    hg.close()
+    hat.close()
