@@ -199,7 +199,7 @@ def run_gpu(args, P, b_np):
             info, st = step(params)
             rec.append((info, st))
             log(f"[{label}] step {i}: setup {st['t_total']:.3f}s solve {info['seconds']:.3f}s "
-                f"iters {info['iters']} relres {info['relres']:.3e}")
+                f"iters {info['iters']} relres {info['relres']:.3e} reorth {info['reorth']}")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         return (t1 - t0) / steps, rec
@@ -357,6 +357,7 @@ def main():
         "setup_s": round(float(np.mean([s["t_total"] for _, s in g["rec"]])), 4),
         "solve_s": round(float(np.mean([i["seconds"] for i, _ in g["rec"]])), 4),
         "iters": int(info["iters"]),
+        "reorth_steps": int(info["reorth"]),
         "relres": info["relres"],
         "applies_per_step": float(applies),
         "apply_gdofs": round(P.n / (cls["apply"]["avg_us"] * 1e-6) / 1e9, 3) if cls["apply"]["avg_us"] else None,

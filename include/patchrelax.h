@@ -152,7 +152,9 @@ typedef struct {
     double  relres;          /* true ||b - A x||_2 / ||b||_2 at exit, FP64 */
     double  relres_est;      /* GMRES estimate at exit */
     int32_t status;          /* PR_OK or PR_NOT_CONVERGED or an error */
-    int32_t reserved0;
+    int32_t reorth;          /* Arnoldi steps that took the second Gram-Schmidt projection
+                                (selective reorthogonalisation; every step beyond 31 basis
+                                vectors and every step of a batch solve counts) */
     double  seconds;         /* wall time of the last pr_solve */
     /* with params.timing != 0: device milliseconds and launch counts of the
      * preconditioner applications (zero fill + apply kernel), the sparse

@@ -66,7 +66,7 @@ class pr_params(Structure):
 
 class pr_solve_info(Structure):
     _fields_ = [("iters", c_int64), ("cycles", c_int64), ("relres", c_double),
-                ("relres_est", c_double), ("status", c_int32), ("reserved0", c_int32),
+                ("relres_est", c_double), ("status", c_int32), ("reorth", c_int32),
                 ("seconds", c_double), ("apply_ms", c_double), ("spmv_ms", c_double),
                 ("orth_ms", c_double), ("n_apply", c_int64), ("n_spmv", c_int64),
                 ("n_orth", c_int64)]

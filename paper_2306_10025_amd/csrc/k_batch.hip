@@ -51,6 +51,7 @@ __global__ __launch_bounds__(kThreads) void k_bgs(const double* __restrict__ V, 
             double v[NV];
 #pragma unroll
             for (int i = 0; i < NV; ++i) v[i] = V[vo[i] + q];
+            __builtin_amdgcn_sched_barrier(0);   // all loads of the row in flight together
             if (MODE == 0) {
 #pragma unroll
                 for (int i = 0; i < NV; ++i) acc[i] = fma(v[i], wq, acc[i]);

@@ -84,6 +84,16 @@ __global__ __launch_bounds__(256) void k_spmv_sell(const int64_t* __restrict__ s
     y[r] = b ? b[r] - acc : acc;
 }
 
+// Selective reorthogonalisation (the test of Daniel, Gragg, Kaufman and
+// Stewart, 1976): after w' = w - V (V^T w), a second projection is needed
+// only when ||w'||^2 < ||w||^2 / 2, i.e. the first lost more than a factor
+// sqrt(2) to cancellation.  sel[kSelIn] = ||w||^2, sel[kSelProj] = ||w'||^2;
+// every kernel that depends on the decision evaluates this same predicate.
+constexpr int kSelIn = 32, kSelProj = 96;
+__device__ __forceinline__ bool reorth_needed(const double* sel) {
+    return !(sel[kSelProj] >= 0.5 * sel[kSelIn]);
+}
+
 // ---------------------------------------------------------------------------
 // Fused Gram-Schmidt passes (classical Gram-Schmidt applied twice):
 //   MODE 0: out_i = V_i . w                       (i < nv)
@@ -100,12 +110,15 @@ __global__ __launch_bounds__(kGsThreads) void k_gs(const double* __restrict__ V,
                                                    double* __restrict__ w, int64_t n,
                                                    const double* __restrict__ c,
                                                    double* __restrict__ partial,
-                                                   const int32_t* __restrict__ stop) {
+                                                   const int32_t* __restrict__ stop, int extra,
+                                                   const double* __restrict__ sel) {
     if (stopped(stop)) return;
+    if (MODE == 2 && sel && !reorth_needed(sel)) return;
     constexpr int NV = 8 * NC;
     constexpr int NO = (MODE == 2) ? 1 : NV;
     __shared__ double s_red[kGsThreads / PR_WAVE][kMaxVec];
     const int nout = (MODE == 2) ? 1 : nv;
+    double accw = 0.0;       // extra output nv: w . w (MODE 0) or the updated w . w (MODE 1)
     double cf[NV];
     if (MODE >= 1) {
 #pragma unroll
@@ -125,9 +138,14 @@ __global__ __launch_bounds__(kGsThreads) void k_gs(const double* __restrict__ V,
         double v[NV];
 #pragma unroll
         for (int i = 0; i < NV; ++i) v[i] = V[vo[i] + q];
+        // keep every load of the row ahead of the arithmetic: left to itself
+        // the scheduler interleaves them to save registers and keeps only
+        // two loads in flight per wave
+        __builtin_amdgcn_sched_barrier(0);
         if (MODE == 0) {
 #pragma unroll
             for (int i = 0; i < NV; ++i) acc[i] = fma(v[i], wq, acc[i]);
+            accw = fma(wq, wq, accw);
         } else {
 #pragma unroll
             for (int i = 0; i < NV; ++i) wq = fma(-cf[i], v[i], wq);    // cf = 0 past nv
@@ -135,6 +153,7 @@ __global__ __launch_bounds__(kGsThreads) void k_gs(const double* __restrict__ V,
             if (MODE == 1) {
 #pragma unroll
                 for (int i = 0; i < NV; ++i) acc[i] = fma(v[i], wq, acc[i]);
+                accw = fma(wq, wq, accw);
             } else {
                 acc[0] = fma(wq, wq, acc[0]);
             }
@@ -148,19 +167,33 @@ __global__ __launch_bounds__(kGsThreads) void k_gs(const double* __restrict__ V,
             if (lane == 0) s_red[wid][i] = t;
         }
     }
+    if (MODE != 2 && extra) {
+        const double t = wave_sum(accw);
+        if (lane == 0) s_red[wid][nout] = t;
+    }
     __syncthreads();
-    if (threadIdx.x < nout) {
+    const int nall = nout + ((MODE != 2 && extra) ? 1 : 0);
+    if (threadIdx.x < nall) {
         double t = 0.0;
         for (int w2 = 0; w2 < kGsThreads / PR_WAVE; ++w2) t += s_red[w2][threadIdx.x];
         partial[(int64_t)blockIdx.x * kMaxVec + threadIdx.x] = t;
     }
 }
 
-// out[i] = sum over blocks of partial[b][i]; one block per output
-__global__ __launch_bounds__(256) void k_gs_final(const double* __restrict__ partial, int nblk,
+// out[i] = sum over blocks of partial[b][i]; one block per output (a fixed
+// tree).  With sel (a skipped second projection): out[0] = the norm of the
+// first.  (A last-block-reduces variant inside k_gs needs a device-scope
+// release per block, an L2 write-back on this GPU; it measured twice as
+// slow as this separate launch.)
+__global__ __launch_bounds__(256) void k_gs_final(const double* __restrict__ partial, int nblk, int nreg,
                                                   double* __restrict__ out,
-                                                  const int32_t* __restrict__ stop) {
+                                                  const int32_t* __restrict__ stop,
+                                                  const double* __restrict__ sel) {
     if (stopped(stop)) return;
+    if (sel && !reorth_needed(sel)) {
+        if (threadIdx.x == 0) out[0] = sel[kSelProj];
+        return;
+    }
     __shared__ double s_w[256 / PR_WAVE];
     const int i = blockIdx.x;
     double t = 0.0;
@@ -171,7 +204,7 @@ __global__ __launch_bounds__(256) void k_gs_final(const double* __restrict__ par
     if (threadIdx.x == 0) {
         double u = 0.0;
         for (int w2 = 0; w2 < 256 / PR_WAVE; ++w2) u += s_w[w2];
-        out[i] = u;
+        out[i < nreg ? i : kMaxVec] = u;      // the extra norm output goes to out[32]
     }
 }
 
@@ -222,6 +255,7 @@ __global__ void k_cycle_init(double* __restrict__ g, int m, const double* __rest
     if (threadIdx.x == 0) {
         gctl[0] = 0;
         gctl[1] = 0;
+        gctl[2] = 0;      // steps of this cycle that took the second projection
     }
 }
 
@@ -233,7 +267,7 @@ __global__ void k_cycle_init(double* __restrict__ g, int m, const double* __rest
 // column and the rotations are staged in LDS by all lanes, one lane runs the
 // sequential rotation chain, all lanes write the column back.  j < 64.
 // gctl: [0] stop  [1] columns done this cycle
-__global__ __launch_bounds__(64) void k_givens(int j, int m, const double* __restrict__ hd,
+__global__ __launch_bounds__(64) void k_givens(int j, int m, const double* __restrict__ hd, int sel,
                                                double* __restrict__ R, double* __restrict__ cs,
                                                double* __restrict__ sn, double* __restrict__ g,
                                                double* __restrict__ est, int32_t* __restrict__ gctl,
@@ -242,7 +276,10 @@ __global__ __launch_bounds__(64) void k_givens(int j, int m, const double* __res
     __shared__ double col[65], c_s[64], s_s[64];
     if (gctl[0]) return;
     const int t = threadIdx.x;
-    if (t <= j) col[t] = hd[t] + hd[64 + t];
+    // selective mode (sel): the second projection's coefficients count only
+    // when it ran; hd[128] holds the final norm either way
+    const bool h2 = !sel || reorth_needed(hd);
+    if (t <= j) col[t] = hd[t] + (h2 ? hd[64 + t] : 0.0);
     if (t < j) {
         c_s[t] = cs[t];
         s_s[t] = sn[t];
@@ -268,6 +305,7 @@ __global__ __launch_bounds__(64) void k_givens(int j, int m, const double* __res
         g[j + 1] = -sj * gj;
         g[j] = cj * gj;
         gctl[1] = j + 1;
+        if (h2) gctl[2] += 1;
         est[0] = fabs(g[j + 1]);
         if (!(fabs(g[j + 1]) > tol_abs) || iters_base + j + 1 >= max_iters || j + 1 >= m) gctl[0] = 1;
     }
@@ -317,14 +355,17 @@ int gs_blocks(int64_t n) {
 // mode 0: out = V^T w ; mode 1: w -= V c, out = V^T w ; mode 2: w -= V c, out[0] = w.w
 // partial: gs_blocks(n) * 32 doubles.
 void launch_gs(int mode, const double* V, int64_t ldv, int nv, double* w, int64_t n, const double* c,
-               double* partial, double* out, hipStream_t s, const int32_t* stop) {
+               double* partial, double* out, hipStream_t s, const int32_t* stop, bool extra,
+               const double* sel) {
     const int nbk = gs_blocks(n);
+    // the extra norm output (at out[32]) needs one chunk with a free slot
+    const int ex = (extra && mode != 2 && nv < kMaxVec) ? 1 : 0;
     for (int base = 0; base < nv || (nv == 0 && base == 0); base += kMaxVec) {
         const int cnt = nv - base < kMaxVec ? nv - base : kMaxVec;
         const double* Vb = V + (int64_t)base * ldv;
         const int nc = cnt <= 0 ? 1 : (cnt + 7) / 8;
 #define PR_GS(M, CC)                                                                                 \
-    k_gs<M, CC><<<nbk, kGsThreads, 0, s>>>(Vb, ldv, cnt, w, n, (M) == 0 ? c : c + base, partial, stop)
+    k_gs<M, CC><<<nbk, kGsThreads, 0, s>>>(Vb, ldv, cnt, w, n, (M) == 0 ? c : c + base, partial, stop, ex, sel)
 #define PR_GS_NC(M)                 \
     if (nc == 1) PR_GS(M, 1);       \
     else if (nc == 2) PR_GS(M, 2);  \
@@ -332,13 +373,13 @@ void launch_gs(int mode, const double* V, int64_t ldv, int nv, double* w, int64_
     else PR_GS(M, 4)
         if (mode == 0) {
             PR_GS_NC(0);
-            k_gs_final<<<cnt, 256, 0, s>>>(partial, nbk, out + base, stop);
+            k_gs_final<<<cnt + ex, 256, 0, s>>>(partial, nbk, cnt, out + base, stop, nullptr);
         } else if (mode == 1) {
             PR_GS_NC(1);
-            k_gs_final<<<cnt, 256, 0, s>>>(partial, nbk, out + base, stop);
+            k_gs_final<<<cnt + ex, 256, 0, s>>>(partial, nbk, cnt, out + base, stop, nullptr);
         } else {
             PR_GS_NC(2);
-            k_gs_final<<<1, 256, 0, s>>>(partial, nbk, out, stop);
+            k_gs_final<<<1, 256, 0, s>>>(partial, nbk, 1, out, stop, sel);
         }
 #undef PR_GS_NC
 #undef PR_GS
@@ -366,8 +407,8 @@ void launch_zero(double* x, int64_t n, hipStream_t s, const int32_t* stop) {
 
 void launch_givens(int j, int m, const double* hd, double* R, double* cs, double* sn, double* g,
                    double* est, int32_t* gctl, const double* tolp, const int64_t* itb, int64_t max_iters,
-                   hipStream_t s) {
-    k_givens<<<1, 64, 0, s>>>(j, m, hd, R, cs, sn, g, est, gctl, tolp, itb, max_iters);
+                   hipStream_t s, bool sel) {
+    k_givens<<<1, 64, 0, s>>>(j, m, hd, sel ? 1 : 0, R, cs, sn, g, est, gctl, tolp, itb, max_iters);
 }
 
 void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {

@@ -1323,16 +1323,19 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
             tbeg();
             launch_spmv_sell(h->soff, h->sval, h->scol, n, zt, nullptr, w, s, gctl);
             tend(1);
-            // classical Gram-Schmidt, twice:
-            // pass 1: h1 = V^T w ; pass 2: w -= V h1, h2 = V^T w ;
-            // pass 3: w -= V h2, ||w||^2 ; then v_{j+1} = w / ||w||
+            // classical Gram-Schmidt with selective reorthogonalisation:
+            // pass 1: h1 = V^T w, ||w||^2 ; pass 2: w -= V h1, h2 = V^T w, ||w||^2 ;
+            // pass 3 (only when pass 2 lost more than a factor sqrt(2)):
+            // w -= V h2, ||w||^2 ; then v_{j+1} = w / ||w||.  Beyond 31 basis
+            // vectors every step takes all three passes.
+            const bool sel = j + 1 < 32;
             tbeg();
-            launch_gs(0, V, ldv, j + 1, w, n, nullptr, red, hd, s, gctl);
-            launch_gs(1, V, ldv, j + 1, w, n, hd, red, hd + 64, s, gctl);
-            launch_gs(2, V, ldv, j + 1, w, n, hd + 64, red, hd + 128, s, gctl);
+            launch_gs(0, V, ldv, j + 1, w, n, nullptr, red, hd, s, gctl, sel);
+            launch_gs(1, V, ldv, j + 1, w, n, hd, red, hd + 64, s, gctl, sel);
+            launch_gs(2, V, ldv, j + 1, w, n, hd + 64, red, hd + 128, s, gctl, false, sel ? hd : nullptr);
             launch_scale(w, V + (int64_t)(j + 1) * ldv, hd + 128, n, s, gctl);
             tend(2);
-            launch_givens(j, m, hd, R, cs, sn, g, est_d, gctl, tol_d, itb_d, h->prm.max_iters, s);
+            launch_givens(j, m, hd, R, cs, sn, g, est_d, gctl, tol_d, itb_d, h->prm.max_iters, s, sel);
         }
         tsel = timing && tstride == 1;
         tj = -1;
@@ -1366,7 +1369,7 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
     }
 
     PR_TRY(sync_read(1));
-    int64_t iters = 0, cycles = 0;
+    int64_t iters = 0, cycles = 0, reorth = 0;
     double relres = std::sqrt(hh[0]) / bnorm, est = relres;
     const int64_t maxit = h->prm.max_iters;
     for (;;) {
@@ -1382,6 +1385,7 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
         PR_HIP(h, hipMemcpyAsync(hh + 239, est_d, sizeof(double), hipMemcpyDeviceToHost, s));
         PR_TRY(sync_read(1));
         iters += gctl_h[1];
+        reorth += gctl_h[2];
         done_cols.push_back(gctl_h[1]);
         est = hh[239] / bnorm;
         relres = std::sqrt(hh[0]) / bnorm;
@@ -1391,6 +1395,7 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
     PR_HIP(h, hipGetLastError());
     h->sinfo.iters = iters;
     h->sinfo.cycles = cycles;
+    h->sinfo.reorth = (int32_t)reorth;
     h->sinfo.relres = relres;
     h->sinfo.relres_est = est;
     h->sinfo.status = relres <= tol ? PR_OK : PR_NOT_CONVERGED;

@@ -257,6 +257,7 @@ int solve_batch(pr_handle h, const double* b, double* x, double tol) {
     h->sinfo = pr_solve_info{};
     h->sinfo.iters = *std::max_element(its.begin(), its.end());
     h->sinfo.cycles = cycles;
+    h->sinfo.reorth = (int32_t)h->sinfo.iters;   // the batch solve always projects twice
     h->sinfo.relres = *std::max_element(rel.begin(), rel.end());
     h->sinfo.relres_est = h->sinfo.relres;
     h->sinfo.status = h->sinfo.relres <= tol ? PR_OK : PR_NOT_CONVERGED;

@@ -458,11 +458,18 @@ void launch_sell_fill(const int64_t* rowptr, const int32_t* col, const double* v
 void launch_spmv_sell(const int64_t* soff, const double* sval, const int32_t* scol, int64_t n,
                       const double* x, const double* b, double* y, hipStream_t s,
                       const int32_t* stop = nullptr);
+// Gram-Schmidt passes.  extra (modes 0 and 1, nv < 32): also out[32] = w . w
+// (mode 1: of the updated w).  sel (mode 2): the pass runs only when the
+// selective-reorthogonalisation test on sel[32], sel[96] asks for it; else
+// out[0] = sel[96].
 void launch_gs(int mode, const double* V, int64_t ldv, int nv, double* w, int64_t n, const double* c,
-               double* partial, double* out, hipStream_t s, const int32_t* stop = nullptr);
+               double* partial, double* out, hipStream_t s, const int32_t* stop = nullptr,
+               bool extra = false, const double* sel = nullptr);
+// sel: the column is hd[0..j] plus hd[64..64+j] only when the second
+// projection ran (same test as launch_gs)
 void launch_givens(int j, int m, const double* hd, double* R, double* cs, double* sn, double* g,
                    double* est, int32_t* gctl, const double* tolp, const int64_t* itb, int64_t max_iters,
-                   hipStream_t s);
+                   hipStream_t s, bool sel = false);
 void launch_trisolve(int m, const double* R, const double* g, double* y, const int32_t* gctl,
                      hipStream_t s);
 void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);

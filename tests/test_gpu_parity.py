@@ -317,12 +317,36 @@ def test_gmres_matches_oracle(case):
     info = h.solve_info()
     xg = x.cpu().numpy()
     relres = np.linalg.norm(b - P.A @ xg) / np.linalg.norm(b)
-    say(case, "iters gpu", info["iters"], "oracle", info_o["iters"], "relres", relres)
+    say(case, "iters gpu", info["iters"], "oracle", info_o["iters"], "relres", relres, "reorth", info["reorth"])
+    assert 0 <= info["reorth"] <= info["iters"]
     assert rc == pr.PR_OK
     assert relres <= 1e-8
     assert abs(info["iters"] - info_o["iters"]) <= 1
     assert abs(info["relres"] - relres) <= 1e-10
     assert np.linalg.norm(xg - x_o) / np.linalg.norm(x_o) < 1e-5
+    h.close()
+
+
+def test_gmres_long_restart_matches_oracle():
+    """Restart 40: steps beyond 31 basis vectors take both projections."""
+    P = gen.q2_hex_diffusion(5)
+    h = pr.PatchRelax(P.A, P.ptr, P.dofs, algo="full", restart=40)
+    cnt, W = O.cover_weights(P.n, P.ptr, P.dofs)
+    tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
+    phi, reps = h.assignment()
+    Xdb = [O.factor_inverse(tiles[r]) for r in reps]
+    b = _rhs(P.n)
+    prec = O.make_preconditioner(P.A, P.ptr, P.dofs, W, Xdb, phi)
+    x_o, info_o = O.gmres(lambda v: P.A @ v, prec, b, tol=1e-8, restart=40)
+    bt = dt(b, torch.float64)
+    x = torch.zeros_like(bt)
+    assert h.solve(bt, x, 1e-8) == pr.PR_OK
+    info = h.solve_info()
+    xg = x.cpu().numpy()
+    say("restart 40: iters gpu", info["iters"], "oracle", info_o["iters"], "reorth", info["reorth"])
+    assert abs(info["iters"] - info_o["iters"]) <= 1
+    assert np.linalg.norm(b - P.A @ xg) / np.linalg.norm(b) <= 1e-8
+    assert info["reorth"] >= max(0, info["iters"] - 31)
     h.close()
 
 
