@@ -71,6 +71,7 @@ def parse():
                     help="FP64 atomics or the deterministic two-stage slot sum")
     ap.add_argument("--mlp", action="store_true", help="Algorithm 1 with the learned predictor")
     ap.add_argument("--graph", action="store_true", help="replay restart cycles from a HIP graph")
+    ap.add_argument("--no-autotune", action="store_true", help="default apply launch shapes")
     ap.add_argument("--no-full", action="store_true", help="skip the full FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-size", type=int, default=12, help="cells per direction of the CPU sample")
@@ -103,12 +104,14 @@ def path_params(args, P, compressed):
     det = args.scatter == "two-stage"
     # kernels of every 7th Arnoldi step are bracketed by events (7 and the
     # restart length 30 are coprime, so the sample covers every basis size)
+    # both paths tune the apply's launch shape; the library keeps the choice
+    # per process and shape, so the warm-up step pays for the timing
     common = dict(restart=30, max_iters=args.iters, deterministic=det, timing=0 if args.graph else TIMING_STRIDE,
-                  graph=args.graph)
+                  graph=args.graph, autotune=not args.no_autotune)
     if not compressed:
         return dict(algo="full", precision="fp64", **common)
     if args.workload == "stokes_batch":
-        return dict(algo="full", precision=args.precision, autotune=True, **common)
+        return dict(algo="full", precision=args.precision, **common)
     if args.workload == "q2_hex_lognormal" and not args.mlp:
         return dict(algo="kmeans_spectral", m_target=max(1, int(0.05 * P.n_p)), precision=args.precision,
                     **common)
@@ -368,7 +371,10 @@ def main():
         "roofline_orth": rl_orth,
     }
     if st.get("tune_threads"):
-        line["config"]["apply_shape"] = [st["tune_threads"], st["tune_cap"], st["tune_slot"]]
+        line["config"]["apply_shape"] = {"threads": st["tune_threads"], "block_cap": st["tune_cap"],
+                                         "slot_threads": st["tune_slot"],
+                                         "tiles_per_wave": st["tune_tiles_per_wave"],
+                                         "xcd_remap": st["tune_xcd_remap"]}
     if "rec_full" in g:
         fi, fs = g["rec_full"][-1]
         fcls = summarize_classes(P, g["rec_full"], "fp64", P.n_p, fs["n_items"])
