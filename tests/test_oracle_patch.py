@@ -1,11 +1,24 @@
 """Pins of the oracle's patch objects, criterion, factorisation and apply
 against closed forms, brute force and the properties the paper states."""
+import os
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
 
 import gen
 import oracle as O
+
+
+def _golden(name):
+    """key value pairs of a fixture under tests/golden (comments start with #)."""
+    out = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].split()
+            if line:
+                out[line[0]] = float(line[1])
+    return out
 
 
 def _c1(nc=32):
@@ -72,16 +85,17 @@ def test_tiles_brute_force_boolean_products(make):
 # ---- boundary keys (Section 3.2) -----------------------------------------
 
 def test_boundary_groups_2d_and_3d():
-    # 9 groups on a square (4 corners, 4 edges, interior), 27 on a cube
+    # the counts Section 3.2 prints: 9 groups on a square, 27 on a cube
+    g = _golden("boundary_groups.txt")
     P = gen.taylor_hood_stokes_2d(8)
     t = O.patch_tiles(P.A, P.ptr, P.dofs)
-    assert len(O.partition_groups(t)) == 9
+    assert len(O.partition_groups(t)) == g["square"]
     P = gen.q2_hex_diffusion(4, sigma=0.0)
     t = O.patch_tiles(P.A, P.ptr, P.dofs)
-    assert len(O.partition_groups(t)) == 27
+    assert len(O.partition_groups(t)) == g["cube"]
     P = gen.nedelec_hex(4)
     t = O.patch_tiles(P.A, P.ptr, P.dofs)
-    assert len(O.partition_groups(t)) == 27
+    assert len(O.partition_groups(t)) == g["cube"]
 
 
 def test_boundary_key_q1_corner_degenerates():
@@ -282,12 +296,18 @@ def test_gmres_omega_invariance():
 # ---- storage accounting (Experiment 3) -----------------------------------
 
 def test_storage_arithmetic_experiment3():
-    s = O.storage_bytes(n_p=8000, p_s=216, m_p=27, n=101 ** 3)
-    assert round(s['database'] / 2 ** 20, 2) == 9.61
-    assert s['indices'] / 2 ** 10 == 62.5
-    assert round(s['full'] / 2 ** 30, 2) == 2.78
-    assert round(s['jacobi'] / 2 ** 20, 2) == 7.86
-    assert 101 ** 3 == 1030301
+    g = _golden("experiment3_storage.txt")
+    s = O.storage_bytes(n_p=int(g["n_patches"]), p_s=int(g["patch_size"]), m_p=int(g["database_entries"]),
+                        n=int(g["matrix_rows"]), value_bytes=int(g["bytes_per_value"]))
+    # the paper prints one decimal (two significant digits for 62.5)
+    assert round(s['database'] / 2 ** 20, 1) == g["database_MiB"]
+    assert s['indices'] / 2 ** 10 == g["indices_KiB"]
+    assert round(s['full'] / 2 ** 30, 1) == g["full_GiB"]
+    assert round(s['jacobi'] / 2 ** 20, 1) == g["jacobi_MiB"]
+    # the matrix is the degree-5 Q-mesh of 20^3 cells: (5 * 20 + 1)^3 nodes
+    assert (5 * 20 + 1) ** 3 == int(g["matrix_rows"])
+    # and a patch is one cell's (5 + 1)^3 nodes
+    assert (5 + 1) ** 3 == int(g["patch_size"])
 
 
 # ---- reduced-precision emulation -----------------------------------------
