@@ -197,6 +197,8 @@ typedef struct {
                                      0 = default, which is 1) */
     int64_t tune_xcd_remap;  /* 1: fixed-tile kernel and padded slot sum give each XCD one
                                 contiguous range of blocks (0 = launch order) */
+    int64_t crit_refined;    /* spectral evaluations the cheap bracket left open and the
+                                repeated-squaring bracket then decided or narrowed */
 } pr_stats;
 
 /* ---- entry points ------------------------------------------------------ */

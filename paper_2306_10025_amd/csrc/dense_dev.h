@@ -9,6 +9,9 @@
 namespace pr_dev {
 
 constexpr int kMaxPs = 32;
+// squarings of the criterion bracket before the exact singular value
+// (a bracket of relative width at most log(p) / 2^12 < 0.1 % in sigma^2)
+constexpr int kSquarings = 12;
 
 // ---------------------------------------------------------------------------
 // Gauss-Jordan inverse of one p x p matrix per group of G lanes; lane r of the
@@ -79,6 +82,24 @@ __device__ __forceinline__ int gj_invert(const double* __restrict__ A, double* _
 // criterion helpers (one wavefront; LDS buffers of kMaxPs^2 doubles)
 // ---------------------------------------------------------------------------
 
+// dst[0..n) = src[0..n) for one wavefront, n <= kMaxPs^2: all loads are
+// issued (from clamped, valid addresses) before the first store, instead of
+// one load-wait-store round per element stride.
+__device__ __forceinline__ void lds_load(double* dst, const double* __restrict__ src, int n, int lane) {
+    constexpr int U = kMaxPs * kMaxPs / PR_WAVE;
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int e = lane + u * PR_WAVE;
+        v[u] = src[e < n ? e : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int e = lane + u * PR_WAVE;
+        if (e < n) dst[e] = v[u];
+    }
+}
+
 // E = I - A X into sE; returns ||E||_F^2 (wave-reduced).
 __device__ __forceinline__ double form_E(const double* sA, const double* sX, double* sE, int p,
                                          int lane) {
@@ -103,6 +124,68 @@ __device__ __forceinline__ double max_col2(const double* sE, int p, int lane) {
         m = s;
     }
     return wave_max(m);
+}
+
+// Bracket [lo2, hi2] of lambda = sigma_max(E)^2 tightened by repeated
+// squaring of G = E^T E, which is symmetric positive semidefinite with
+// eigenvalues l_1 >= ... >= l_p >= 0.  With N_0 = G / tr G and
+// N_k = N_{k-1}^2 / tr(N_{k-1}^2) (so N_k = G^(2^k) / tr G^(2^k)):
+//   l_1^(2^k) <= tr G^(2^k)             (every other eigenvalue is >= 0),
+//   l_1^(2^k) >= max_j (G^(2^k))_jj     (no diagonal entry of a PSD matrix
+//                                        exceeds its largest eigenvalue),
+// so log l_1 lies in [U_k + log(max_j (N_k)_jj) / 2^k, U_k], where
+// U_k = log tr G + sum_{i=1..k} log tr(N_{i-1}^2) / 2^i, a bracket of width
+// at most log(p) / 2^k.  done(lo2, hi2) is asked after each step; at most
+// kmax squarings.  One wavefront; sG and sH are p x p LDS scratch; sE may be
+// the same buffer as sH (E is consumed once G is formed).  Returns false
+// when E is zero (then lo2 = hi2 = 0).
+template <class Done>
+__device__ bool sigma2_bracket(const double* sE, double* sG, double* sH, int p, int lane, int kmax,
+                               double& lo2, double& hi2, Done done) {
+    for (int e = lane; e < p * p; e += PR_WAVE) {
+        const int a = e / p, b = e % p;
+        double acc = 0.0;
+        for (int c = 0; c < p; ++c) acc = fma(sE[c * p + a], sE[c * p + b], acc);
+        sG[e] = acc;
+    }
+    __syncthreads();
+    const double tr = wave_sum(lane < p ? sG[lane * p + lane] : 0.0);
+    if (!(tr > 0.0)) {
+        lo2 = hi2 = 0.0;
+        return false;
+    }
+    hi2 = fmin(hi2, tr);
+    lo2 = fmax(lo2, wave_max(lane < p ? sG[lane * p + lane] : 0.0));
+    if (done(lo2, hi2)) return true;
+    const double itr = 1.0 / tr;
+    for (int e = lane; e < p * p; e += PR_WAVE) sG[e] *= itr;
+    __syncthreads();
+    double U = log(tr), w = 0.5;
+    double* cur = sG;
+    double* nxt = sH;
+    for (int k = 1; k <= kmax; ++k) {
+        for (int e = lane; e < p * p; e += PR_WAVE) {
+            const int a = e / p, b = e % p;
+            double acc = 0.0;
+            for (int c = 0; c < p; ++c) acc = fma(cur[c * p + a], cur[c * p + b], acc);   // N symmetric
+            nxt[e] = acc;
+        }
+        __syncthreads();
+        const double t = wave_sum(lane < p ? nxt[lane * p + lane] : 0.0);   // in [1/p, 1]
+        const double it = 1.0 / t;
+        for (int e = lane; e < p * p; e += PR_WAVE) nxt[e] *= it;
+        __syncthreads();
+        U += w * log(t);
+        const double md = wave_max(lane < p ? nxt[lane * p + lane] : 0.0);
+        hi2 = fmin(hi2, exp(U));
+        lo2 = fmax(lo2, exp(U + w * log(md)));
+        w *= 0.5;
+        double* tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+        if (done(lo2, hi2)) break;
+    }
+    return true;
 }
 
 // sigma_max(E)^2 as the largest eigenvalue of G = E^T E by cyclic Jacobi

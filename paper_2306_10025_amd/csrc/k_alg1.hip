@@ -188,7 +188,7 @@ __global__ __launch_bounds__(64) void k_a1_eval(const int32_t* ctl, int crit, do
     __shared__ double sX[kMaxPs * kMaxPs];
     __shared__ double sE[kMaxPs * kMaxPs];
     const int lane = threadIdx.x;
-    unsigned long long nev = 0, nex = 0;
+    unsigned long long nev = 0, nex = 0, nsq = 0;
     for (int q = blockIdx.x; q < nc; q += gridDim.x) {
         const int32_t s = cand[q];
         const int32_t i = mem[s];
@@ -201,10 +201,8 @@ __global__ __launch_bounds__(64) void k_a1_eval(const int32_t* ctl, int crit, do
         const double* Br = (crit == PR_CRIT_SPECTRAL)
                                ? dbt + (int64_t)slot * stride
                                : tiles + (uniform_ps ? (int64_t)r * uniform_ps * uniform_ps : toff[r]);
-        for (int e = lane; e < pp; e += PR_WAVE) {
-            sA[e] = Ai[e];
-            sX[e] = Br[e];
-        }
+        lds_load(sA, Ai, pp, lane);
+        lds_load(sX, Br, pp, lane);
         __syncthreads();
         bool match;
         ++nev;
@@ -213,11 +211,20 @@ __global__ __launch_bounds__(64) void k_a1_eval(const int32_t* ctl, int crit, do
             __syncthreads();
             const double lb2 = max_col2(sE, p, lane);
             const double e2 = eps * eps;
-            if (fro2 * (1.0 + 1e-12) < e2) {
-                match = true;                       // sigma_max <= ||E||_F < eps
-            } else if (lb2 * (1.0 - 1e-12) >= e2) {
-                match = false;                      // sigma_max >= largest column norm >= eps
+            // decided when the bracket clears eps^2 by a rounding margin
+            auto decided = [e2](double lo, double hi) {
+                return hi * (1.0 + 1e-11) < e2 || lo * (1.0 - 1e-11) >= e2;
+            };
+            double lo = lb2, hi = fro2;   // largest column norm^2 <= sigma_max^2 <= ||E||_F^2
+            if (!decided(lo, hi)) {
+                __syncthreads();
+                sigma2_bracket(sE, sA, sX, p, lane, kSquarings, lo, hi, decided);
+                ++nsq;
+            }
+            if (decided(lo, hi)) {
+                match = hi * (1.0 + 1e-11) < e2;
             } else {
+                __syncthreads();
                 match = sqrt(sigma_max2_jacobi(sE, sA, p, lane)) < eps;
                 ++nex;
             }
@@ -243,6 +250,7 @@ __global__ __launch_bounds__(64) void k_a1_eval(const int32_t* ctl, int crit, do
     if (lane == 0) {
         atomicAdd(&counters[0], nev);
         if (nex) atomicAdd(&counters[1], nex);
+        if (nsq) atomicAdd(&counters[3], nsq);
     }
 }
 

@@ -71,22 +71,31 @@ __global__ __launch_bounds__(256) void k_apply_rows(int64_t count, ApplyGeom g, 
         const int p = g.goff ? (int)(g.goff[s + 1] - o) : g.pst;
         const int32_t j = g.gphi[s];
         const TX* X = db + (g.dboff ? g.dboff[j] : (int64_t)j * g.dbst);
+        // Loads are unconditional from clamped (valid) addresses and the
+        // unused values are dropped afterwards: a load under a condition
+        // becomes a branch whose join waits for it, which serialises them.
         const bool act = a < p;
-        const int32_t gd = act ? g.gdofs[o + a] : 0;
-        const TA rv = act ? (TA)r[gd] : (TA)0;
+        const int ac = act ? a : 0;
+        const int32_t gd = g.gdofs[o + ac];
+        const double rl = r[gd];
+        const TA rv = act ? (TA)rl : (TA)0;
         TX xr[MAXP];
         if (sizeof(TX) == 8 && (p & 1) == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0) {
             // even p and an aligned matrix: rows start on 16-byte boundaries, load pairs
-            const double2* X2 = reinterpret_cast<const double2*>(X + (int64_t)a * p);
+            const double2* X2 = reinterpret_cast<const double2*>(X + (int64_t)ac * p);
 #pragma unroll
             for (int b = 0; b < MAXP / 2; ++b) {
-                const double2 v = (act && 2 * b < p) ? X2[b] : make_double2(0.0, 0.0);
-                xr[2 * b] = (TX)v.x;
-                xr[2 * b + 1] = (TX)v.y;
+                const double2 v = X2[2 * b < p ? b : 0];
+                const bool keep = act && 2 * b < p;
+                xr[2 * b] = keep ? (TX)v.x : (TX)0;
+                xr[2 * b + 1] = keep ? (TX)v.y : (TX)0;
             }
         } else {
 #pragma unroll
-            for (int b = 0; b < MAXP; ++b) xr[b] = (act && b < p) ? X[(int64_t)a * p + b] : (TX)0;
+            for (int b = 0; b < MAXP; ++b) {
+                const TX v = X[(int64_t)ac * p + (b < p ? b : 0)];
+                xr[b] = (act && b < p) ? v : (TX)0;
+            }
         }
         TA acc = 0;
 #pragma unroll
@@ -142,10 +151,10 @@ __global__ __launch_bounds__(256) void k_slot_sum(int64_t n, const int64_t* __re
         const int rem = (int)(b - a);
         int32_t sl[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) sl[u] = u < rem ? dof_slots[a + u] : 0;
+        for (int u = 0; u < 8; ++u) sl[u] = dof_slots[a + (u < rem ? u : 0)];   // rem >= 1
         TY yv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) yv[u] = u < rem ? Y[sl[u]] : (TY)0;
+        for (int u = 0; u < 8; ++u) yv[u] = Y[sl[u]];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
             if (u < rem) acc += (double)yv[u];
@@ -215,16 +224,22 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
             // 16x16x16: member n = l%16, local dofs 4q..4q+3 with q = l/16
             const int n = l & 15, q = l >> 4;
             const bool mv = n < cnt;
-            int64_t st = 0;
-            if (mv) st = g.goff ? g.goff[start + n] : (int64_t)(start + n) * g.pst;
+            // unconditional loads from clamped addresses (no serialising branches)
+            const int64_t sn = start + (mv ? n : 0);
+            const int64_t st = g.goff ? g.goff[sn] : sn * g.pst;
             int32_t gi[4];
             float rv[4];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int kk = 4 * q + t;
                 const bool v = mv && kk < p;
-                gi[t] = v ? g.gdofs[st + kk] : -1;
-                rv[t] = v ? (float)r[gi[t]] : 0.0f;
+                const int32_t d = g.gdofs[st + (kk < p ? kk : 0)];
+                gi[t] = v ? d : -1;
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const double x = r[gi[t] >= 0 ? gi[t] : 0];
+                rv[t] = gi[t] >= 0 ? (float)x : 0.0f;
             }
             int f = 0;
             if (FP16) {
@@ -266,8 +281,8 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
             // local dofs 8s + 4h + t for step s and t < 4
             const int n = l & 31, h = l >> 5;
             const bool mv = n < cnt;
-            int64_t st = 0;
-            if (mv) st = g.goff ? g.goff[start + n] : (int64_t)(start + n) * g.pst;
+            const int64_t sn = start + (mv ? n : 0);
+            const int64_t st = g.goff ? g.goff[sn] : sn * g.pst;
             const int steps = (p + 7) >> 3;
             int32_t gi[16];
             float rv[16];
@@ -277,9 +292,14 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
                 for (int t = 0; t < 4; ++t) {
                     const int kk = 8 * s + 4 * h + t;
                     const bool v = mv && kk < p;
-                    gi[4 * s + t] = v ? g.gdofs[st + kk] : -1;
-                    rv[4 * s + t] = v ? (float)r[gi[4 * s + t]] : 0.0f;
+                    const int32_t d = g.gdofs[st + (kk < p ? kk : 0)];
+                    gi[4 * s + t] = v ? d : -1;
                 }
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const double x = r[gi[v] >= 0 ? gi[v] : 0];
+                rv[v] = gi[v] >= 0 ? (float)x : 0.0f;
+            }
             int f = 0;
             if (FP16) {
                 float m = 0.0f;
@@ -366,22 +386,31 @@ __global__ __launch_bounds__(256) void k_apply_tiles(int64_t n_p, int p, ApplyGe
 #pragma unroll
         for (int u = 0; u < TPW; ++u) {
             const int64_t s = (t0 + u) * NB + n;
+            // Every load below is unconditional from a clamped (valid)
+            // address, the unused values dropped afterwards: a load under a
+            // condition becomes a branch whose join waits for it, which
+            // serialised the gathers.
             mv[u] = s < n_p;                                 // false for the whole tile past the end
-            jm[u] = mv[u] ? g.gphi[s] : 0x7fffffff;
-            const int32_t* gd = g.gdofs + (mv[u] ? s : 0) * p;
+            const int64_t sc = mv[u] ? s : n_p - 1;
+            const int32_t jl = g.gphi[sc];
+            jm[u] = mv[u] ? jl : 0x7fffffff;
+            const int32_t* gd = g.gdofs + sc * p;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const int row0 = BIG ? 8 * c + 4 * h : 4 * h;   // rows row0 .. row0+3
                 if (vec4) {
-                    int4 v4 = make_int4(-1, -1, -1, -1);
-                    if (mv[u] && row0 < p) v4 = *reinterpret_cast<const int4*>(gd + row0);
-                    gi[u][4 * c + 0] = v4.x;
-                    gi[u][4 * c + 1] = v4.y;
-                    gi[u][4 * c + 2] = v4.z;
-                    gi[u][4 * c + 3] = v4.w;
+                    const bool ok = mv[u] && row0 < p;
+                    const int4 v4 = *reinterpret_cast<const int4*>(gd + (row0 < p ? row0 : 0));
+                    gi[u][4 * c + 0] = ok ? v4.x : -1;
+                    gi[u][4 * c + 1] = ok ? v4.y : -1;
+                    gi[u][4 * c + 2] = ok ? v4.z : -1;
+                    gi[u][4 * c + 3] = ok ? v4.w : -1;
                 } else {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) gi[u][4 * c + e] = (mv[u] && row0 + e < p) ? gd[row0 + e] : -1;
+                    for (int e = 0; e < 4; ++e) {
+                        const int32_t d = gd[row0 + e < p ? row0 + e : 0];
+                        gi[u][4 * c + e] = (mv[u] && row0 + e < p) ? d : -1;
+                    }
                 }
             }
         }
@@ -392,14 +421,18 @@ __global__ __launch_bounds__(256) void k_apply_tiles(int64_t n_p, int p, ApplyGe
 #pragma unroll
         for (int u = 0; u < TPW; ++u) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) rv[u][v] = gi[u][v] >= 0 ? (float)r[gi[u][v]] : 0.0f;
+            for (int v = 0; v < NV; ++v) {
+                const double x = r[gi[u][v] >= 0 ? gi[u][v] : 0];
+                rv[u][v] = gi[u][v] >= 0 ? (float)x : 0.0f;
+            }
             cur[u] = __builtin_amdgcn_readfirstlane(jm[u]);    // member 0's entry (lane 0)
             const uint16_t* Xl = db_lp + (int64_t)(t0 + u < n_tiles ? cur[u] : 0) * lp_stride;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                const bool need = (t0 + u < n_tiles) && (!BIG || c < steps);
-                ah[u][c] = need ? *reinterpret_cast<const s4*>(Xl + (c * 64 + l) * 4) : s4{0, 0, 0, 0};
-                if (SPLIT) al[u][c] = need ? *reinterpret_cast<const s4*>(Xl + L + (c * 64 + l) * 4) : s4{0, 0, 0, 0};
+                // steps past p read step 0 again; their products are skipped
+                const int cc = (!BIG || c < steps) ? c : 0;
+                ah[u][c] = *reinterpret_cast<const s4*>(Xl + (cc * 64 + l) * 4);
+                if (SPLIT) al[u][c] = *reinterpret_cast<const s4*>(Xl + L + (cc * 64 + l) * 4);
             }
         }
         // 3: products, one per distinct entry of a tile; 4: slot writes
@@ -447,6 +480,8 @@ __global__ __launch_bounds__(256) void k_apply_tiles(int64_t n_p, int p, ApplyGe
                 int ee[EB];
 #pragma unroll
                 for (int k = 0; k < EB; ++k) {
+                    // e[k] repeats a valid entry when the batch has fewer
+                    // entries, so every load is unconditional
                     const uint16_t* Xl = db_lp + (int64_t)e[k] * lp_stride;
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
@@ -454,12 +489,12 @@ __global__ __launch_bounds__(256) void k_apply_tiles(int64_t n_p, int p, ApplyGe
                             xa[k][c] = ah[u][c];
                             if (SPLIT) xb[k][c] = al[u][c];
                         } else {
-                            const bool need = ex[k] && (!BIG || c < steps);
-                            xa[k][c] = need ? *reinterpret_cast<const s4*>(Xl + (c * 64 + l) * 4) : s4{0, 0, 0, 0};
-                            if (SPLIT) xb[k][c] = need ? *reinterpret_cast<const s4*>(Xl + L + (c * 64 + l) * 4) : s4{0, 0, 0, 0};
+                            const int cc = (!BIG || c < steps) ? c : 0;
+                            xa[k][c] = *reinterpret_cast<const s4*>(Xl + (cc * 64 + l) * 4);
+                            if (SPLIT) xb[k][c] = *reinterpret_cast<const s4*>(Xl + L + (cc * 64 + l) * 4);
                         }
                     }
-                    ee[k] = (FP16 && ex[k]) ? db_exp[e[k]] : 0;
+                    ee[k] = FP16 ? db_exp[e[k]] : 0;
                 }
 #pragma unroll
                 for (int k = 0; k < EB; ++k) {
@@ -542,7 +577,7 @@ __global__ __launch_bounds__(256) void k_slot_sum_ell(int64_t n, const int32_t* 
     }
     TY yv[C];
 #pragma unroll
-    for (int u = 0; u < C; ++u) yv[u] = sl[u] >= 0 ? Y[sl[u]] : (TY)0;
+    for (int u = 0; u < C; ++u) yv[u] = Y[sl[u] >= 0 ? sl[u] : 0];    // unconditional: no serialising branch
     double acc = 0.0;
     int c = 0;
 #pragma unroll

@@ -9,8 +9,10 @@
 // Assignment of patch i: the spectral distance to every centre of its group
 // is bracketed by [largest column norm of E, ||E||_F] with E = I - A_i X_j;
 // only centres whose lower bound lies within the tie band of the smallest
-// upper bound can be in the argmin's band, and only when there are several
-// such candidates is the exact largest singular value computed.  The band is
+// upper bound can be in the argmin's band.  When there are several such
+// candidates their brackets are narrowed by repeated squaring of E^T E, and
+// only the candidates still in the band get the exact largest singular
+// value.  The band is
 // {j : d_j <= d_min (1 + tie) + tie s_i}, s_i = 1 for the spectral distance
 // and sum |A_i| for the l1 distance, so that distances at rounding level tie;
 // the current centre is kept if it lies in the band, otherwise the lowest
@@ -48,12 +50,12 @@ __global__ __launch_bounds__(64) void k_km_assign(int64_t n_p, const int64_t* __
         const int p = (int)(ptr[i + 1] - ptr[i]);
         const int pp = p * p;
         const double* Ai = tiles + (uniform_ps ? i * (int64_t)uniform_ps * uniform_ps : toff[i]);
-        for (int e = lane; e < pp; e += PR_WAVE) sA[e] = Ai[e];
+        lds_load(sA, Ai, pp, lane);
         __syncthreads();
         const int j0 = gc0[g], j1 = gc1[g];
         const double floor_abs = tie * (crit == PR_CRIT_L1 ? l1n[i] : 1.0);
         double* lb = lbscr + (int64_t)blockIdx.x * lbld;
-        unsigned long long nev = 0, nex = 0;
+        unsigned long long nev = 0, nex = 0, nsq = 0;
         double dmin, ubmin = INFINITY;
         if (crit == PR_CRIT_L1) {
             // entrywise: exact l1 distances; lb holds the distance itself
@@ -71,7 +73,7 @@ __global__ __launch_bounds__(64) void k_km_assign(int64_t n_p, const int64_t* __
             // pass 1: bracket every distance
             for (int j = j0; j < j1; ++j) {
                 const double* X = cen + (int64_t)j * stride;
-                for (int e = lane; e < pp; e += PR_WAVE) sX[e] = X[e];
+                lds_load(sX, X, pp, lane);
                 __syncthreads();
                 const double fro2 = form_E(sA, sX, sE, p, lane);
                 __syncthreads();
@@ -81,10 +83,36 @@ __global__ __launch_bounds__(64) void k_km_assign(int64_t n_p, const int64_t* __
                 __syncthreads();
                 ++nev;
             }
-            // pass 2: exact values for the candidates of the tie band
-            const double thr = (ubmin * (1.0 + tie) + floor_abs) * (1.0 + 1e-12);
+            // pass 2: candidates of the tie band of the smallest upper bound.
+            // Their brackets are narrowed by repeated squaring; a candidate
+            // whose lower bound clears the band of the smallest narrowed
+            // upper bound is out, and only several survivors need exact
+            // values.
+            double thr = (ubmin * (1.0 + tie) + floor_abs) * (1.0 + 1e-12);
             int ncand = 0;
             for (int j = j0; j < j1; ++j) ncand += (lb[j - j0] <= thr) ? 1 : 0;
+            if (ncand > 1) {
+                for (int j = j0; j < j1; ++j) {
+                    if (!(lb[j - j0] <= thr)) continue;
+                    const double* X = cen + (int64_t)j * stride;
+                    lds_load(sX, X, pp, lane);
+                    __syncthreads();
+                    const double fro2 = form_E(sA, sX, sE, p, lane);
+                    __syncthreads();
+                    double lo2 = max_col2(sE, p, lane), hi2 = fro2;
+                    const double cut = thr;
+                    // stop once this candidate is out of the current band
+                    auto out = [cut](double lo, double) { return sqrt(lo) * (1.0 - 1e-12) > cut; };
+                    sigma2_bracket(sE, sX, sE, p, lane, kSquarings, lo2, hi2, out);
+                    ++nsq;
+                    __syncthreads();
+                    if (lane == 0) lb[j - j0] = sqrt(lo2) * (1.0 - 1e-12);
+                    __syncthreads();
+                    thr = fmin(thr, (sqrt(hi2) * (1.0 + 1e-12) * (1.0 + tie) + floor_abs) * (1.0 + 1e-12));
+                }
+                ncand = 0;
+                for (int j = j0; j < j1; ++j) ncand += (lb[j - j0] <= thr) ? 1 : 0;
+            }
             dmin = INFINITY;
             for (int j = j0; j < j1; ++j) {
                 if (!(lb[j - j0] <= thr)) {
@@ -96,7 +124,7 @@ __global__ __launch_bounds__(64) void k_km_assign(int64_t n_p, const int64_t* __
                     d = 0.0;                                    // the only candidate is the argmin
                 } else {
                     const double* X = cen + (int64_t)j * stride;
-                    for (int e = lane; e < pp; e += PR_WAVE) sX[e] = X[e];
+                    lds_load(sX, X, pp, lane);
                     __syncthreads();
                     form_E(sA, sX, sE, p, lane);
                     __syncthreads();
@@ -126,6 +154,7 @@ __global__ __launch_bounds__(64) void k_km_assign(int64_t n_p, const int64_t* __
             }
             atomicAdd(&counters[0], nev);
             if (nex) atomicAdd(&counters[1], nex);
+            if (nsq) atomicAdd(&counters[3], nsq);
         }
         __syncthreads();
     }

@@ -141,17 +141,37 @@ __global__ __launch_bounds__(64) void k_gemm_f16(int M, int N, int K, const floa
     f16v acc;
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
-    for (int k0 = 0; k0 < K; k0 += 8) {
-        h4 a, b;
+    // K in groups of U steps of 8: every load of a group is issued before
+    // its products.  Loads are unconditional from clamped indices and the
+    // values outside the matrices are dropped afterwards (a load under a
+    // condition becomes a branch whose join waits for it).
+    constexpr int U = 4;
+    const int mc = mi < M ? mi : M - 1, nc = nj < N ? nj : N - 1;
+    for (int kg = 0; kg < K; kg += 8 * U) {
+        float av[U][4], bv[U][4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int k = k0 + kh + t;
-            const float av = (mi < M && k < K) ? (TA ? A[(int64_t)k * lda + mi] : A[(int64_t)mi * lda + k]) : 0.0f;
-            const float bv = (nj < N && k < K) ? (TB ? B[(int64_t)nj * ldb + k] : B[(int64_t)k * ldb + nj]) : 0.0f;
-            a[t] = (_Float16)av;
-            b[t] = (_Float16)bv;
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int k = kg + 8 * u + kh + t;
+                const int kc = k < K ? k : K - 1;
+                av[u][t] = TA ? A[(int64_t)kc * lda + mc] : A[(int64_t)mc * lda + kc];
+                bv[u][t] = TB ? B[(int64_t)nc * ldb + kc] : B[(int64_t)kc * ldb + nc];
+            }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            h4 a, b;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                // a multiply by 0/1, not a select: the compiler sinks a load
+                // whose value a select may discard into a branch
+                const int k = kg + 8 * u + kh + t;
+                a[t] = (_Float16)(av[u][t] * ((mi < M && k < K) ? 1.0f : 0.0f));
+                b[t] = (_Float16)(bv[u][t] * ((nj < N && k < K) ? 1.0f : 0.0f));
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x8f16(a, b, acc, 0, 0, 0);
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x8f16(a, b, acc, 0, 0, 0);
     }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -195,13 +215,30 @@ __global__ __launch_bounds__(64) void k_softmax_ce(int B, int C, const float* __
     }
 }
 
-// bias gradient: scale times the column sums, in row order
-__global__ void k_colsum(int B, int N, const float* __restrict__ G, int ldg, float scale, float* __restrict__ out) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+// bias gradient: scale times the column sums
+// (block of 256 threads per 64 columns: 4 row phases, each summing rows
+// r = phase, phase + 4, ... in FP64, then the phases added in order)
+__global__ __launch_bounds__(256) void k_colsum(int B, int N, const float* __restrict__ G, int ldg, float scale,
+                                                float* __restrict__ out) {
+    __shared__ double s_p[4][64];
+    const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + c;
     double s = 0.0;
-    for (int r = 0; r < B; ++r) s += (double)G[(int64_t)r * ldg + n];
-    out[n] = (float)(s * (double)scale);
+    if (n < N) {
+        int r = ph;
+        for (; r + 12 < B; r += 16) {       // four independent loads in flight
+            const float g0 = G[(int64_t)r * ldg + n], g1 = G[(int64_t)(r + 4) * ldg + n];
+            const float g2 = G[(int64_t)(r + 8) * ldg + n], g3 = G[(int64_t)(r + 12) * ldg + n];
+            s += (double)g0;
+            s += (double)g1;
+            s += (double)g2;
+            s += (double)g3;
+        }
+        for (; r < B; r += 4) s += (double)G[(int64_t)r * ldg + n];
+    }
+    s_p[ph][c] = s;
+    __syncthreads();
+    if (ph == 0 && n < N) out[n] = (float)((((s_p[0][c] + s_p[1][c]) + s_p[2][c]) + s_p[3][c]) * (double)scale);
 }
 
 // Adam (Kingma and Ba): bc1 = 1 - b1^t, bc2 = 1 - b2^t
@@ -271,25 +308,33 @@ __global__ __launch_bounds__(64) void k_topk(int64_t R, int C, const float* __re
     }
 }
 
-// exact test of one pair (wavefront-wide); sA holds A_i; returns d < eps
-__device__ bool pair_matches(int crit, double eps, const double* sA, double* sX, double* sE, const double* Xr,
-                             const double* Br, int p, int lane, unsigned long long& nev,
-                             unsigned long long& nex) {
+// exact test of one pair (wavefront-wide); sA holds A_i; returns d < eps.
+// sX, sE, sH: p x p LDS scratch.
+__device__ bool pair_matches(int crit, double eps, const double* sA, double* sX, double* sE, double* sH,
+                             const double* Xr, const double* Br, int p, int lane, unsigned long long& nev,
+                             unsigned long long& nex, unsigned long long& nsq) {
     const int pp = p * p;
     ++nev;
     if (crit == PR_CRIT_SPECTRAL) {
-        for (int e = lane; e < pp; e += PR_WAVE) sX[e] = Xr[e];
+        lds_load(sX, Xr, pp, lane);
         __syncthreads();
         const double fro2 = form_E(sA, sX, sE, p, lane);
         __syncthreads();
         const double lb2 = max_col2(sE, p, lane);
         const double e2 = eps * eps;
+        auto decided = [e2](double lo, double hi) {
+            return hi * (1.0 + 1e-11) < e2 || lo * (1.0 - 1e-11) >= e2;
+        };
+        double lo = lb2, hi = fro2;
+        if (!decided(lo, hi)) {
+            sigma2_bracket(sE, sX, sH, p, lane, kSquarings, lo, hi, decided);   // E kept in sE
+            ++nsq;
+        }
         bool match;
-        if (fro2 * (1.0 + 1e-12) < e2) {
-            match = true;
-        } else if (lb2 * (1.0 - 1e-12) >= e2) {
-            match = false;
+        if (decided(lo, hi)) {
+            match = hi * (1.0 + 1e-11) < e2;
         } else {
+            __syncthreads();
             match = sqrt(sigma_max2_jacobi(sE, sX, p, lane)) < eps;
             ++nex;
         }
@@ -333,13 +378,14 @@ __global__ __launch_bounds__(64) void k_mlp_match(int mode, int64_t nq, const in
     __shared__ double sA[kMaxPs * kMaxPs];
     __shared__ double sX[kMaxPs * kMaxPs];
     __shared__ double sE[kMaxPs * kMaxPs];
+    __shared__ double sH[kMaxPs * kMaxPs];
     const int lane = threadIdx.x;
-    unsigned long long nev = 0, nex = 0;
+    unsigned long long nev = 0, nex = 0, nsq = 0;
     for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
         const int32_t i = qids[q];
         const int p = (int)(g.ptr[i + 1] - g.ptr[i]);
         const double* Ai = tile_of(g, i);
-        for (int e = lane; e < p * p; e += PR_WAVE) sA[e] = Ai[e];
+        lds_load(sA, Ai, p * p, lane);
         __syncthreads();
         const double ki = keynorm[i];
         const double c = (p * p + 64) * 2.3e-16;
@@ -357,7 +403,8 @@ __global__ __launch_bounds__(64) void k_mlp_match(int mode, int64_t nq, const in
                                                                  : g.eps * (1.0 + 1e-10) + c * kmx;
                 if (fabs(ki - kr) > half) continue;
             }
-            if (pair_matches(g.crit, g.eps, sA, sX, sE, g.X0 + j * g.stride, tile_of(g, r), p, lane, nev, nex))
+            if (pair_matches(g.crit, g.eps, sA, sX, sE, sH, g.X0 + j * g.stride, tile_of(g, r), p, lane, nev,
+                             nex, nsq))
                 hit = r;
         }
         if (lane == 0) {
@@ -369,6 +416,7 @@ __global__ __launch_bounds__(64) void k_mlp_match(int mode, int64_t nq, const in
     if (lane == 0) {
         atomicAdd(&counters[0], nev);
         if (nex) atomicAdd(&counters[1], nex);
+        if (nsq) atomicAdd(&counters[3], nsq);
     }
 }
 
@@ -493,7 +541,7 @@ void launch_softmax_ce(int B, int C, const float* L, int ldl, const int32_t* y, 
 }
 
 void launch_colsum(int B, int N, const float* G, int ldg, float scale, float* out, hipStream_t s) {
-    k_colsum<<<nb(N, 64), 64, 0, s>>>(B, N, G, ldg, scale, out);
+    if (N > 0) k_colsum<<<nb(N, 64), 256, 0, s>>>(B, N, G, ldg, scale, out);
 }
 
 void launch_adam(int64_t n, float* P, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,

@@ -66,6 +66,7 @@ int run_alg1(pr_handle h) {
     PR_HIP(h, hipStreamSynchronize(s));
     h->stats.crit_evals = (int64_t)R.cnt[0];
     h->stats.crit_exact = (int64_t)R.cnt[1];
+    h->stats.crit_refined = (int64_t)R.cnt[3];
     h->stats.alg1_rounds = R.rounds;
     // pairs the sequential algorithm compares: patch i against the entries of
     // its size up to its own (excluded for an entry's patch); the rest were
@@ -194,7 +195,7 @@ int run_kmeans(pr_handle h) {
     const int64_t* toff = h->uniform ? nullptr : h->toff;
 
     std::vector<int32_t> boot_reps, boot_ps;
-    int64_t boot_evals = 0, boot_exact = 0, boot_pruned = 0;
+    int64_t boot_evals = 0, boot_exact = 0, boot_pruned = 0, boot_refined = 0;
     if (boot) {
         // initial database from Algorithm 1
         PR_TRY(run_alg1(h));
@@ -202,6 +203,7 @@ int run_kmeans(pr_handle h) {
         boot_ps = h->dbps_host;
         boot_evals = h->stats.crit_evals;
         boot_exact = h->stats.crit_exact;
+        boot_refined = h->stats.crit_refined;
         boot_pruned = h->stats.crit_pruned;
     }
 
@@ -403,6 +405,7 @@ int run_kmeans(pr_handle h) {
     PR_HIP(h, hipStreamSynchronize(s));
     h->stats.crit_evals = (int64_t)cnt[0] + boot_evals;
     h->stats.crit_exact = (int64_t)cnt[1] + boot_exact;
+    h->stats.crit_refined = (int64_t)cnt[3] + boot_refined;
     h->stats.crit_pruned = boot_pruned;
     h->stats.empty_events = (int64_t)cnt[2];
     h->stats.kmeans_iters = (int32_t)*std::max_element(its.begin(), its.end());

@@ -372,6 +372,7 @@ int run_alg1_mlp(pr_handle h) {
     h->mlp_k = k;
     h->stats.crit_evals = (int64_t)(R0.cnt[0] + c4[0] + R1.cnt[0]);
     h->stats.crit_exact = (int64_t)(R0.cnt[1] + c4[1] + R1.cnt[1]);
+    h->stats.crit_refined = (int64_t)(R0.cnt[3] + c4[3] + R1.cnt[3]);
     h->stats.crit_pruned = 0;
     h->stats.alg1_rounds = R0.rounds + R1.rounds;
     h->stats.mlp_train = ns;
