@@ -23,9 +23,15 @@ __device__ __forceinline__ int gj_invert(const double* __restrict__ A, double* _
                                          int p, int r) {
     double a[MAXP], x[MAXP];
     const bool act = r < p;
+    // every load unconditional from a clamped address, the padding dropped
+    // by a multiply (a load feeding a select gets sunk into a branch, and
+    // each branch then waits for its load)
+    const int64_t row = (int64_t)(act ? r : 0) * p;
+#pragma unroll
+    for (int c = 0; c < MAXP; ++c) a[c] = A[row + (c < p ? c : 0)];
 #pragma unroll
     for (int c = 0; c < MAXP; ++c) {
-        a[c] = (act && c < p) ? A[(int64_t)r * p + c] : 0.0;
+        a[c] *= (act && c < p) ? 1.0 : 0.0;
         x[c] = (act && c == r) ? 1.0 : 0.0;
     }
     bool used = !act;

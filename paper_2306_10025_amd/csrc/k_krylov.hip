@@ -46,10 +46,27 @@ __global__ void k_sell_fill(const int64_t* __restrict__ rowptr, const int32_t* _
     const int64_t off = soff[sl];
     const int64_t len = (soff[sl + 1] - off) / 64;
     const int64_t a = rowptr[r], l = rowptr[r + 1] - a;
-    for (int64_t k = 0; k < len; ++k) {
-        const bool v = k < l;
-        sval[off + k * 64 + lane] = v ? val[a + k] : 0.0;
-        scol[off + k * 64 + lane] = v ? col[a + k] : (int32_t)r;
+    // loads unconditional from clamped addresses, in groups of 8 (a load
+    // under a condition becomes a branch that waits for it)
+    for (int64_t k0 = 0; k0 < len; k0 += 8) {
+        double vv[8];
+        int32_t cc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t k = k0 + u;
+            const int64_t ks = (k < l) ? k : 0;
+            vv[u] = l > 0 ? val[a + ks] : 0.0;
+            cc[u] = l > 0 ? col[a + ks] : (int32_t)r;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t k = k0 + u;
+            if (k < len) {
+                const bool v = k < l;
+                sval[off + k * 64 + lane] = v ? vv[u] : 0.0;
+                scol[off + k * 64 + lane] = v ? cc[u] : (int32_t)r;
+            }
+        }
     }
 }
 

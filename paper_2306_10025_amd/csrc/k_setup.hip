@@ -25,15 +25,24 @@ __global__ void k_validate_csr(const int64_t* __restrict__ rowptr, const int32_t
         flags[0] = 1;
         return;
     }
+    // columns in groups of 8, loaded before they are checked (clamped
+    // addresses inside the row, so no load waits behind a branch)
     int32_t prev = -1;
-    for (int64_t q = s; q < e; ++q) {
-        int32_t c = col[q];
-        if (c < 0 || c >= n || c <= prev) {
-            flags[0] = 1;
-            return;
+    bool bad = false;
+    for (int64_t q0 = s; q0 < e && !bad; q0 += 8) {
+        int32_t cc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) cc[u] = col[q0 + u < e ? q0 + u : s];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (q0 + u < e) {
+                const int32_t c = cc[u];
+                if (c < 0 || c >= n || c <= prev) bad = true;
+                prev = c;
+            }
         }
-        prev = c;
     }
+    if (bad) flags[0] = 1;
 }
 
 __global__ void k_validate_patches(const int64_t* __restrict__ ptr, const int32_t* __restrict__ dofs,
