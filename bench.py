@@ -77,6 +77,7 @@ def parse():
                     help="FP64 atomics or the deterministic two-stage slot sum")
     ap.add_argument("--mlp", action="store_true", help="Algorithm 1 with the learned predictor")
     ap.add_argument("--graph", action="store_true", help="replay restart cycles from a HIP graph")
+    ap.add_argument("--autotune", action="store_true", help="tune the apply launch shape (default: stokes_batch only)")
     ap.add_argument("--no-autotune", action="store_true", help="default apply launch shapes")
     ap.add_argument("--no-full", action="store_true", help="skip the full FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -112,10 +113,13 @@ def path_params(args, P, compressed):
     det = args.scatter == "two-stage"
     # kernels of every 7th Arnoldi step are bracketed by events (7 and the
     # restart length 30 are coprime, so the sample covers every basis size)
-    # both paths tune the apply's launch shape; the library keeps the choice
-    # per process and shape, so the warm-up step pays for the timing
+    # the uneven batch tunes the apply's launch shape (both paths; the
+    # library keeps the choice per process and shape, so the warm-up step
+    # pays for the timing); on the uniform workloads the tuned shapes are
+    # within timing noise of the default, which the counter runs also use
+    tune = args.autotune or args.workload == "stokes_batch"
     common = dict(restart=30, max_iters=args.iters, deterministic=det, timing=0 if args.graph else TIMING_STRIDE,
-                  graph=args.graph, autotune=not args.no_autotune)
+                  graph=args.graph, autotune=tune and not args.no_autotune)
     if not compressed:
         return dict(algo="full", precision="fp64", **common)
     if args.workload == "stokes_batch":

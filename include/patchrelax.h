@@ -196,7 +196,8 @@ typedef struct {
     int64_t tune_tiles_per_wave;  /* fixed-tile MFMA kernel: tiles per wavefront (1 or 2;
                                      0 = default, which is 1) */
     int64_t tune_xcd_remap;  /* 1: fixed-tile kernel and padded slot sum give each XCD one
-                                contiguous range of blocks (0 = launch order) */
+                                contiguous range of blocks (0 = launch order); 1 unless the
+                                tuner found launch order faster */
     int64_t crit_refined;    /* spectral evaluations the cheap bracket left open and the
                                 repeated-squaring bracket then decided or narrowed */
 } pr_stats;
