@@ -465,7 +465,33 @@ __global__ __launch_bounds__(256) void k_apply_tiles(int64_t n_p, int p, ApplyGe
             // otherwise wait for one load per entry)
             int32_t j = cur[u];
             bool first = true;
-            while (true) {
+            // the common case, one entry in the whole tile: one product with
+            // the operand loaded ahead, none of the batch machinery
+            const bool single = __ballot(mv[u] && jm[u] != j) == 0;
+            if (single) {
+                accv acc = {};
+                if constexpr (BIG) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        if (c < steps) {
+                            acc = mma32<MODE>(ah[u][c], bh[c], acc);
+                            if (SPLIT) {
+                                acc = mma32<MODE>(ah[u][c], bl[c], acc);
+                                acc = mma32<MODE>(al[u][c], bh[c], acc);
+                            }
+                        }
+                    }
+                } else {
+                    acc = mma16<MODE>(ah[u][0], bh[0], acc);
+                    if (SPLIT) {
+                        acc = mma16<MODE>(ah[u][0], bl[0], acc);
+                        acc = mma16<MODE>(al[u][0], bh[0], acc);
+                    }
+                }
+                out = acc;
+                if (FP16) oe = db_exp[j] + f;
+            }
+            while (!single) {
                 int32_t e[EB];
                 bool ex[EB];
                 e[0] = j;
