@@ -71,16 +71,28 @@ __global__ __launch_bounds__(256) void k_apply_rows(int64_t count, ApplyGeom g, 
         const int p = g.goff ? (int)(g.goff[s + 1] - o) : g.pst;
         const int32_t j = g.gphi[s];
         const TX* X = db + (g.dboff ? g.dboff[j] : (int64_t)j * g.dbst);
-        // Loads are unconditional from clamped (valid) addresses and the
-        // unused values are dropped afterwards: a load under a condition
-        // becomes a branch whose join waits for it, which serialises them.
+        // FP64: loads unconditional from clamped (valid) addresses, the
+        // unused values dropped afterwards (a load under a condition becomes
+        // a branch whose join waits for it).  FP32 keeps the guarded form,
+        // which measured twice as fast there (C4-sized uneven batch: 332
+        // against 708 us per application; FP64 461 against 515 us).
         const bool act = a < p;
         const int ac = act ? a : 0;
-        const int32_t gd = g.gdofs[o + ac];
-        const double rl = r[gd];
-        const TA rv = act ? (TA)rl : (TA)0;
+        int32_t gd;
+        TA rv;
+        if constexpr (sizeof(TX) == 4) {
+            gd = act ? g.gdofs[o + a] : 0;
+            rv = act ? (TA)r[gd] : (TA)0;
+        } else {
+            gd = g.gdofs[o + ac];
+            const double rl = r[gd];
+            rv = act ? (TA)rl : (TA)0;
+        }
         TX xr[MAXP];
-        if (sizeof(TX) == 8 && (p & 1) == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0) {
+        if constexpr (sizeof(TX) == 4) {
+#pragma unroll
+            for (int b = 0; b < MAXP; ++b) xr[b] = (act && b < p) ? X[(int64_t)a * p + b] : (TX)0;
+        } else if ((p & 1) == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0) {
             // even p and an aligned matrix: rows start on 16-byte boundaries, load pairs
             const double2* X2 = reinterpret_cast<const double2*>(X + (int64_t)ac * p);
 #pragma unroll
