@@ -951,6 +951,7 @@ void pr_destroy(pr_handle h) {
     else (void)hipDeviceSynchronize();
     for (auto e : h->evpool) (void)hipEventDestroy(e);
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->bgexec) (void)hipGraphExecDestroy(h->bgexec);
     if (h->gstream) {
         (void)hipStreamSynchronize(h->gstream);
         (void)hipStreamDestroy(h->gstream);

@@ -103,6 +103,11 @@ int pr_set_systems(pr_handle h, const int64_t* sptr, int64_t nsys) {
     PR_HIP(h, hipStreamSynchronize(st));
     h->nch = nch;
     h->nsys = (int)nsys;
+    if (h->bgexec) {                 // a captured cycle holds the old chunk arrays
+        (void)hipGraphExecDestroy(h->bgexec);
+        h->bgexec = nullptr;
+        h->bgraph_m = -1;
+    }
     h->sys_ptr_host.assign(sptr, sptr + nsys + 1);
     h->sys_iters.assign(nsys, 0);
     h->sys_relres.assign(nsys, 0.0);
@@ -161,6 +166,28 @@ int solve_batch(pr_handle h, const double* b, double* x, double tol) {
     const int64_t n = h->n;
     const int ns = h->nsys;
     PR_TRY(pr_workspace_internal(h, m));
+    // graph replay of whole restart cycles (not with per-kernel timing): the
+    // capture needs a stream of its own, and b and x live in handle memory
+    // so that one captured cycle serves every later solve
+    const bool use_graph = h->prm.graph != 0 && !timing;
+    if (use_graph) {
+        if (!h->gstream) PR_HIP(h, hipStreamCreate(&h->gstream));
+        if (!h->gb) {
+            PR_TRY(dalloc(h, &h->gb, n));
+            PR_TRY(dalloc(h, &h->gx, n));
+        }
+        PR_HIP(h, hipStreamSynchronize(h->stream));
+        s = h->gstream;
+    }
+    struct StreamSwap {
+        pr_handle h;
+        hipStream_t keep;
+        ~StreamSwap() { h->stream = keep; }
+    } swap{h, h->stream};
+    h->stream = s;
+    const double* bw = use_graph ? h->gb : b;
+    double* xw = use_graph ? h->gx : x;
+    if (use_graph) launch_copy(h->gb, b, n, s);
     BGeom bg{h->nch, h->ch_sys, h->ch_lo, h->ch_len, ns, h->sys_ch0, h->sys_nch};
     double* V = h->V;
     double* w = h->w;
@@ -190,7 +217,7 @@ int solve_batch(pr_handle h, const double* b, double* x, double tol) {
         PR_HIP(h, hipStreamSynchronize(s));
         return PR_OK;
     };
-    PR_TRY(norms(b));
+    PR_TRY(norms(bw));
     std::vector<double> bn(ns), tol_abs(ns);
     for (int i = 0; i < ns; ++i) {
         bn[i] = std::sqrt(nr[(size_t)i * kBStride]);
@@ -198,29 +225,17 @@ int solve_batch(pr_handle h, const double* b, double* x, double tol) {
         tol_abs[i] = tol * bn[i];
     }
     PR_HIP(h, hipMemcpyAsync(h->btol, tol_abs.data(), ns * sizeof(double), hipMemcpyHostToDevice, s));
-    launch_zero(x, n, s);
-    launch_copy(r, b, n, s);
+    launch_zero(xw, n, s);
+    launch_copy(r, bw, n, s);
     std::vector<int64_t> its(ns, 0);
     std::vector<double> rel(ns, 0.0);
     int64_t cycles = 0;
     const int64_t maxit = h->prm.max_iters;
-    for (;;) {
-        PR_TRY(norms(r));
-        if (cycles > 0) done_cols.push_back(*std::max_element(cols_h.begin(), cols_h.end()));
-        bool any = false;
-        for (int i = 0; i < ns; ++i) {
-            if (cycles > 0) its[i] += cols_h[i];
-            const double rn = std::sqrt(nr[(size_t)i * kBStride]);
-            if (!std::isfinite(rn)) return pr_fail(h, PR_ERR_NONFINITE, "non-finite residual");
-            rel[i] = bn[i] > 0.0 ? rn / bn[i] : 0.0;
-            act_h[i] = (rel[i] > tol && its[i] < maxit) ? 1 : 0;
-            any = any || act_h[i];
-        }
-        if (!any) break;
-        ++cycles;
-        ++tcyc;
-        PR_HIP(h, hipMemcpyAsync(act, act_h.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        PR_HIP(h, hipMemcpyAsync(h->bbase, its.data(), ns * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    // One restart cycle of every active system, all on the device (each
+    // Arnoldi step ends in the per-system Givens update and stopping test;
+    // kernels of stopped systems, or of a stopped batch, return at once),
+    // then x_s += M(V_s y_s) for every system that ran and r = b - A x.
+    auto enqueue_cycle = [&]() -> int {
         launch_bcycle_init(ns, m, NR, act, gv, sstop, scols, gstop, s);
         launch_bscale(r, V, bg, NR, sstop, gstop, s);
         for (int j = 0; j < m; ++j) {
@@ -242,14 +257,56 @@ int solve_batch(pr_handle h, const double* b, double* x, double tol) {
             launch_bgivens(j, m, ns, H1, H2, HN, R, cs, sn, gv, est, sstop, scols, h->btol, h->bbase, maxit,
                            gstop, s);
         }
-        // x_s += M(V_s y_s) for every system that ran (zero elsewhere), r = b - A x
         launch_btrisolve(m, ns, R, gv, yv, scols, s);
         launch_bgemv(V, ldv, bg, yv, m, scols, r, s);
         PR_TRY(pr_precond_internal(h, r, zt, t3, nullptr));
-        launch_axpy_dev(x, zt, 1.0, n, s);
-        launch_spmv_sell(h->soff, h->sval, h->scol, n, x, b, r, s);
+        launch_axpy_dev(xw, zt, 1.0, n, s);
+        launch_spmv_sell(h->soff, h->sval, h->scol, n, xw, bw, r, s);
+        return PR_OK;
+    };
+    for (;;) {
+        PR_TRY(norms(r));
+        if (cycles > 0) done_cols.push_back(*std::max_element(cols_h.begin(), cols_h.end()));
+        bool any = false;
+        for (int i = 0; i < ns; ++i) {
+            if (cycles > 0) its[i] += cols_h[i];
+            const double rn = std::sqrt(nr[(size_t)i * kBStride]);
+            if (!std::isfinite(rn)) return pr_fail(h, PR_ERR_NONFINITE, "non-finite residual");
+            rel[i] = bn[i] > 0.0 ? rn / bn[i] : 0.0;
+            act_h[i] = (rel[i] > tol && its[i] < maxit) ? 1 : 0;
+            any = any || act_h[i];
+        }
+        if (!any) break;
+        ++cycles;
+        ++tcyc;
+        PR_HIP(h, hipMemcpyAsync(act, act_h.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        PR_HIP(h, hipMemcpyAsync(h->bbase, its.data(), ns * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        if (use_graph) {
+            if (!h->bgexec || h->bgraph_m != m) {
+                if (h->bgexec) {
+                    (void)hipGraphExecDestroy(h->bgexec);
+                    h->bgexec = nullptr;
+                }
+                hipGraph_t gr = nullptr;
+                PR_HIP(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                const int rc = enqueue_cycle();
+                const hipError_t ec = hipStreamEndCapture(s, &gr);
+                if (rc < 0) return rc;
+                if (ec != hipSuccess)
+                    return pr_fail(h, PR_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ec));
+                const hipError_t ei = hipGraphInstantiate(&h->bgexec, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                if (ei != hipSuccess)
+                    return pr_fail(h, PR_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+                h->bgraph_m = m;
+            }
+            PR_HIP(h, hipGraphLaunch(h->bgexec, s));
+        } else {
+            PR_TRY(enqueue_cycle());
+        }
         PR_HIP(h, hipMemcpyAsync(cols_h.data(), scols, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     }
+    if (use_graph) launch_copy(x, xw, n, s);
     PR_HIP(h, hipStreamSynchronize(s));
     PR_HIP(h, hipGetLastError());
     h->sys_iters = its;

@@ -144,6 +144,8 @@ struct pr_handle_s {
     hipStream_t gstream = nullptr;
     hipGraphExec_t gexec = nullptr;
     int graph_m = -1;
+    hipGraphExec_t bgexec = nullptr;   // one restart cycle of the batch solve
+    int bgraph_m = -1;
     double* gb = nullptr;
     double* gx = nullptr;
     double* gtol = nullptr;

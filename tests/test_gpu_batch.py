@@ -196,6 +196,48 @@ def test_graph_replay_matches_eager(case):
     graph.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_graph_replay_matches_eager(precision):
+    """A captured restart cycle of the batch solve, replayed for three
+    right-hand sides with eager work between, gives the eager solve's
+    per-system iterations and the same bits; a second set of systems on the
+    same handle recaptures."""
+    B = gen.uneven_stokes_batch(n_sys=6, nmin=2, nmax=7)
+    sptr, _ = _subsystems(B)
+    kw = dict(algo="full", precision=precision, deterministic=True, max_iters=40)
+    eager = pr.PatchRelax(B.A, B.ptr, B.dofs, **kw)
+    graph = pr.PatchRelax(B.A, B.ptr, B.dofs, graph=True, **kw)
+    for h in (eager, graph):
+        h.set_systems(sptr)
+    for seed in (0, 1, 2):
+        b = torch.as_tensor(gen.rhs(B.n, seed)).to(DEV)
+        xe = torch.zeros_like(b)
+        xg = torch.full_like(b, np.nan)
+        eager.solve(b, xe, 1e-10)
+        ie = eager.system_info()
+        junk = torch.randn(1 << 20, device=DEV, dtype=torch.float64).sum()
+        graph.solve(b, xg, 1e-10)
+        ig = graph.system_info()
+        torch.cuda.synchronize()
+        say(precision, "seed", seed, "iters", list(ie[0]), list(ig[0]), float(junk))
+        assert np.array_equal(ie[0], ig[0])
+        assert torch.equal(xe, xg)
+    # fewer, larger systems: the handle drops the old capture
+    coarse = np.array([sptr[0], sptr[3], sptr[-1]])
+    for h in (eager, graph):
+        h.set_systems(coarse)
+    b = torch.as_tensor(gen.rhs(B.n, 5)).to(DEV)
+    xe = torch.zeros_like(b)
+    xg = torch.full_like(b, np.nan)
+    eager.solve(b, xe, 1e-10)
+    graph.solve(b, xg, 1e-10)
+    torch.cuda.synchronize()
+    assert np.array_equal(eager.system_info()[0], graph.system_info()[0])
+    assert torch.equal(xe, xg)
+    eager.close()
+    graph.close()
+
+
 @pytest.mark.parametrize("precision,shape", [("fp64", "uneven"), ("fp32", "uneven"), ("bf16x3", "uneven"),
                                              ("bf16x3", "uniform"), ("fp16", "uniform")])
 def test_autotuned_apply_is_bit_identical(precision, shape):
