@@ -296,16 +296,42 @@ int pr_set_systems(pr_handle h, const int64_t* system_ptr, int64_t n_sys);
  * host double[n_sys] (either may be NULL).  INVALID_ARG without systems. */
 int pr_get_system_info(pr_handle h, int64_t* iters, double* relres);
 
-/* Use another stream for later calls on h (NULL = default stream). */
+/* Use another stream for later calls on h (NULL = default stream).  Waits
+ * for the work queued on the old stream first. */
 int pr_set_stream(pr_handle h, void* hip_stream);
 
 /* Host-only validation of host arrays (no GPU needed): same checks and codes
  * as pr_setup performs on the device. */
 int pr_validate_host(const pr_csr* A_host, const pr_patches* P_host);
 
+/* Waits for the handle's stream and returns everything it owns.  Its device
+ * buffers go to the device memory cache below, not back to the HIP runtime. */
 void pr_destroy(pr_handle h);
 const char* pr_status_string(int status);
 const char* pr_last_error(pr_handle h);   /* h may be NULL: last global error */
+
+/* ---- device memory cache ------------------------------------------------
+ * Library bookkeeping, not part of the method.  Every device buffer a handle
+ * owns is taken from a per-device cache of idle blocks and returned to it by
+ * pr_destroy, so a sequence of setups on one device maps memory once (hipFree
+ * synchronises the device and unmaps pages; a cached block costs neither).
+ * Idle blocks stay allocated until evicted: by default at most one eighth of
+ * the device's memory is kept idle per device (largest blocks are freed
+ * first); an allocation that fails frees the idle blocks of its device and
+ * tries once more.  A cached block is never shared by two live handles.
+ * Thread-safe. */
+
+/* Idle bytes kept per device from now on (0 disables caching, -1 restores
+ * the default); frees idle blocks beyond it.  INVALID_ARG below -1. */
+int pr_set_memory_cache_limit(int64_t bytes);
+/* Frees every idle block on every device (e.g. before handing the memory to
+ * another allocator).  Handles stay valid. */
+int pr_release_cached_memory(void);
+/* info: host int64[4] = {idle bytes, idle blocks, allocations served from
+ * the cache, allocations that called hipMalloc} for `device` (-1: pinned
+ * host blocks); zeros for a device never used.  INVALID_ARG for a null info
+ * or a device below -1.  Needs no GPU. */
+int pr_memory_cache_info(int32_t device, int64_t* info);
 
 /* ---- standalone batched kernels (device arrays, asynchronous) ----------- */
 

@@ -106,6 +106,9 @@ _SIGS = {
     "pr_set_stream": (c_int, [c_void_p, c_void_p]),
     "pr_validate_host": (c_int, [POINTER(pr_csr), POINTER(pr_patches)]),
     "pr_destroy": (None, [c_void_p]),
+    "pr_set_memory_cache_limit": (c_int, [c_int64]),
+    "pr_release_cached_memory": (c_int, []),
+    "pr_memory_cache_info": (c_int, [c_int32, POINTER(c_int64)]),
     "pr_status_string": (c_char_p, [c_int]),
     "pr_last_error": (c_char_p, [c_void_p]),
     "pr_batch_inverse": (c_int, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -329,6 +332,22 @@ def pr_mlp_predict(precision, X, params, F, H, C, k, logits=None, topk=None, row
 def pr_destroy(h):
     if h:
         lib().pr_destroy(h)
+
+
+def pr_set_memory_cache_limit(nbytes):
+    return _check(lib().pr_set_memory_cache_limit(int(nbytes)))
+
+
+def pr_release_cached_memory():
+    return _check(lib().pr_release_cached_memory())
+
+
+def pr_memory_cache_info(device=0):
+    """{idle_bytes, idle_blocks, reuses, mallocs} of the device memory cache
+    (device -1: pinned host blocks)."""
+    out = (c_int64 * 4)()
+    _check(lib().pr_memory_cache_info(int(device), out))
+    return dict(idle_bytes=out[0], idle_blocks=out[1], reuses=out[2], mallocs=out[3])
 
 
 def pr_batch_inverse(p, A, X, info):

@@ -116,8 +116,8 @@ __device__ __forceinline__ bool reorth_needed(const double* sel) {
 //   MODE 0: out_i = V_i . w                       (i < nv)
 //   MODE 1: w <- w - sum_i c_i V_i ; out_i = V_i . w   (each V_i loaded once)
 //   MODE 2: w <- w - sum_i c_i V_i ; out_0 = w . w
-// Each block writes its row-range partial sums; k_gs_final adds the block
-// partials of one output per block in a fixed tree.
+// Each block writes its row-range partial sums; k_gs_final (modes 0 and 1)
+// or k_step_end (mode 2) adds the block partials in a fixed tree.
 // NC = ceil(nv / 8) is a template parameter: the NC * 8 vector loads of a
 // row carry no branches between them (indices past nv repeat vector nv - 1
 // and their terms are dropped), so they are all in flight at once.
@@ -193,24 +193,20 @@ __global__ __launch_bounds__(kGsThreads) void k_gs(const double* __restrict__ V,
     if (threadIdx.x < nall) {
         double t = 0.0;
         for (int w2 = 0; w2 < kGsThreads / PR_WAVE; ++w2) t += s_red[w2][threadIdx.x];
-        partial[(int64_t)blockIdx.x * kMaxVec + threadIdx.x] = t;
+        // MODE 2 has one output per block: stored contiguously, so a consumer
+        // reads all block partials from a few cache lines
+        partial[MODE == 2 ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * kMaxVec + threadIdx.x] = t;
     }
 }
 
 // out[i] = sum over blocks of partial[b][i]; one block per output (a fixed
-// tree).  With sel (a skipped second projection): out[0] = the norm of the
-// first.  (A last-block-reduces variant inside k_gs needs a device-scope
+// tree).  (A last-block-reduces variant inside k_gs needs a device-scope
 // release per block, an L2 write-back on this GPU; it measured twice as
 // slow as this separate launch.)
 __global__ __launch_bounds__(256) void k_gs_final(const double* __restrict__ partial, int nblk, int nreg,
                                                   double* __restrict__ out,
-                                                  const int32_t* __restrict__ stop,
-                                                  const double* __restrict__ sel) {
+                                                  const int32_t* __restrict__ stop) {
     if (stopped(stop)) return;
-    if (sel && !reorth_needed(sel)) {
-        if (threadIdx.x == 0) out[0] = sel[kSelProj];
-        return;
-    }
     __shared__ double s_w[256 / PR_WAVE];
     const int i = blockIdx.x;
     double t = 0.0;
@@ -276,26 +272,69 @@ __global__ void k_cycle_init(double* __restrict__ g, int m, const double* __rest
     }
 }
 
-// One Arnoldi column j: h = h1 + h2 (two Gram-Schmidt passes) and
-// h_{j+1} = ||w||; apply the previous rotations, form the new one, update
-// the residual vector g; stop when |g_{j+1}| <= tol_abs (or not finite) or
-// the iteration limit is reached (tolp: device absolute tolerance; itb:
-// device count of the iterations of earlier cycles).  One wavefront: the
-// column and the rotations are staged in LDS by all lanes, one lane runs the
-// sequential rotation chain, all lanes write the column back.  j < 64.
-// gctl: [0] stop  [1] columns done this cycle
-__global__ __launch_bounds__(64) void k_givens(int j, int m, const double* __restrict__ hd, int sel,
-                                               double* __restrict__ R, double* __restrict__ cs,
-                                               double* __restrict__ sn, double* __restrict__ g,
-                                               double* __restrict__ est, int32_t* __restrict__ gctl,
-                                               const double* __restrict__ tolp,
-                                               const int64_t* __restrict__ itb, int64_t max_iters) {
+// End of Arnoldi step j, one launch:
+//   ||w||^2 from the last Gram-Schmidt pass's block partials (every block adds
+//   them in the same fixed tree, so all blocks agree to the bit; in selective
+//   mode a skipped third pass leaves the norm in sel[96]);
+//   v_{j+1} = w / ||w|| over a grid-stride range;
+//   block 0: column j of the Hessenberg matrix, h = h1 + h2 and
+//   h_{j+1} = ||w||, the previous rotations applied, the new one formed, the
+//   residual vector g updated; stop when |g_{j+1}| <= tol_abs (or not finite)
+//   or the iteration limit is reached (tolp: device absolute tolerance; itb:
+//   device count of the iterations of earlier cycles).  j < 64.
+// gctl: [0] stop  [1] columns done this cycle  [2] steps with a third pass.
+// The stop flag is read once per block; a block that starts after block 0 has
+// set it skips its part of v_{j+1}, which a stopped cycle never reads.
+constexpr int kEndThreads = 256;
+constexpr int kEndBlocks = 1024;
+constexpr int kEndUnroll = 4;
+__global__ __launch_bounds__(kEndThreads) void k_step_end(
+        const double* __restrict__ partial, int nblk, const double* sel, const double* __restrict__ w,
+        double* __restrict__ vnext, int64_t n, int j, int m, double* hd, double* __restrict__ R,
+        double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g, double* __restrict__ est,
+        int32_t* __restrict__ gctl, const double* __restrict__ tolp, const int64_t* __restrict__ itb,
+        int64_t max_iters) {
+    __shared__ int s_stop;
+    __shared__ double s_w[kEndThreads / PR_WAVE];
     __shared__ double col[65], c_s[64], s_s[64];
-    if (gctl[0]) return;
     const int t = threadIdx.x;
-    // selective mode (sel): the second projection's coefficients count only
-    // when it ran; hd[128] holds the final norm either way
-    const bool h2 = !sel || reorth_needed(hd);
+    if (t == 0) s_stop = gctl[0];
+    __syncthreads();
+    if (s_stop) return;
+    double nrm2;
+    if (sel && !reorth_needed(sel)) {
+        nrm2 = sel[kSelProj];
+    } else {
+        double a = 0.0;
+        for (int b = t; b < nblk; b += kEndThreads) a += partial[b];
+        a = wave_sum(a);
+        if ((t & (PR_WAVE - 1)) == 0) s_w[t / PR_WAVE] = a;
+        __syncthreads();
+        double u = 0.0;
+        for (int w2 = 0; w2 < kEndThreads / PR_WAVE; ++w2) u += s_w[w2];
+        nrm2 = u;
+    }
+    {
+        const double d = sqrt(nrm2);
+        const int64_t stride = (int64_t)gridDim.x * kEndThreads;
+        for (int64_t base = (int64_t)blockIdx.x * kEndThreads + t; base < n; base += kEndUnroll * stride) {
+            double v[kEndUnroll];
+#pragma unroll
+            for (int u = 0; u < kEndUnroll; ++u) {
+                const int64_t q = base + u * stride;
+                v[u] = w[q < n ? q : n - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < kEndUnroll; ++u) {
+                const int64_t q = base + u * stride;
+                if (q < n) vnext[q] = d > 0.0 ? v[u] / d : 0.0;
+            }
+        }
+    }
+    if (blockIdx.x != 0) return;
+    // selective mode: the second projection's coefficients count only when
+    // it ran
+    const bool h2 = !sel || reorth_needed(sel);
     if (t <= j) col[t] = hd[t] + (h2 ? hd[64 + t] : 0.0);
     if (t < j) {
         c_s[t] = cs[t];
@@ -303,9 +342,10 @@ __global__ __launch_bounds__(64) void k_givens(int j, int m, const double* __res
     }
     __syncthreads();
     if (t == 0) {
+        hd[128] = nrm2;
         const int64_t iters_base = *itb;
         const double tol_abs = *tolp;
-        const double hn = sqrt(fmax(hd[128], 0.0));
+        const double hn = sqrt(fmax(nrm2, 0.0));
         for (int i = 0; i < j; ++i) {
             const double a = col[i], b = col[i + 1];
             col[i] = c_s[i] * a + s_s[i] * b;
@@ -369,7 +409,8 @@ int gs_blocks(int64_t n) {
     return (int)b;
 }
 
-// mode 0: out = V^T w ; mode 1: w -= V c, out = V^T w ; mode 2: w -= V c, out[0] = w.w
+// mode 0: out = V^T w ; mode 1: w -= V c, out = V^T w ; mode 2: w -= V c and
+// the block partials of w.w in partial[0..gs_blocks(n)) (out unused).
 // partial: gs_blocks(n) * 32 doubles.
 void launch_gs(int mode, const double* V, int64_t ldv, int nv, double* w, int64_t n, const double* c,
                double* partial, double* out, hipStream_t s, const int32_t* stop, bool extra,
@@ -390,13 +431,12 @@ void launch_gs(int mode, const double* V, int64_t ldv, int nv, double* w, int64_
     else PR_GS(M, 4)
         if (mode == 0) {
             PR_GS_NC(0);
-            k_gs_final<<<cnt + ex, 256, 0, s>>>(partial, nbk, cnt, out + base, stop, nullptr);
+            k_gs_final<<<cnt + ex, 256, 0, s>>>(partial, nbk, cnt, out + base, stop);
         } else if (mode == 1) {
             PR_GS_NC(1);
-            k_gs_final<<<cnt + ex, 256, 0, s>>>(partial, nbk, cnt, out + base, stop, nullptr);
+            k_gs_final<<<cnt + ex, 256, 0, s>>>(partial, nbk, cnt, out + base, stop);
         } else {
-            PR_GS_NC(2);
-            k_gs_final<<<1, 256, 0, s>>>(partial, nbk, 1, out, stop, sel);
+            PR_GS_NC(2);       // partial[0..nbk): launch_step_end adds them
         }
 #undef PR_GS_NC
 #undef PR_GS
@@ -422,10 +462,13 @@ void launch_zero(double* x, int64_t n, hipStream_t s, const int32_t* stop) {
     if (n > 0) k_zero<<<nb(n, 256), 256, 0, s>>>(x, n, stop);
 }
 
-void launch_givens(int j, int m, const double* hd, double* R, double* cs, double* sn, double* g,
-                   double* est, int32_t* gctl, const double* tolp, const int64_t* itb, int64_t max_iters,
-                   hipStream_t s, bool sel) {
-    k_givens<<<1, 64, 0, s>>>(j, m, hd, sel ? 1 : 0, R, cs, sn, g, est, gctl, tolp, itb, max_iters);
+void launch_step_end(const double* partial, const double* sel, const double* w, double* vnext, int64_t n,
+                     int j, int m, double* hd, double* R, double* cs, double* sn, double* g, double* est,
+                     int32_t* gctl, const double* tolp, const int64_t* itb, int64_t max_iters, hipStream_t s) {
+    const int64_t want = (n + kEndThreads - 1) / kEndThreads;
+    const unsigned grid = (unsigned)(want < kEndBlocks ? (want > 0 ? want : 1) : kEndBlocks);
+    k_step_end<<<grid, kEndThreads, 0, s>>>(partial, gs_blocks(n), sel, w, vnext, n, j, m, hd, R, cs, sn, g, est,
+                                            gctl, tolp, itb, max_iters);
 }
 
 void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {

@@ -477,6 +477,66 @@ void launch_iota(int32_t* a, int64_t n, hipStream_t s) {
     if (n > 0) k_iota<<<nblk(n, 256), 256, 0, s>>>(a, n);
 }
 
+// ---- distinct boundary keys (an open-addressing set) ------------------------
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x85EBCA6Bu;
+    x ^= x >> 13;
+    x *= 0xC2B2AE35u;
+    x ^= x >> 16;
+    return x;
+}
+
+__global__ void k_set_clear(uint32_t* table, int64_t T, unsigned* count) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < T) table[i] = 0xFFFFFFFFu;
+    if (i < 2) count[i] = 0u;
+}
+
+// count[0]: keys other than 0xFFFFFFFF inserted first; count[1]: 1 if that
+// key occurs.  Patches with one boundary key come in long runs, so each
+// wavefront first reduces its keys to one lane per distinct value (one pass
+// per distinct value in the wavefront) and only those lanes touch the table.
+// The table has at least 2n slots, so every probe sequence meets a free slot;
+// the loop bound is the table size.
+__global__ void k_set_insert(const uint32_t* keys, int64_t n, uint32_t* table, uint32_t mask, unsigned* count) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (PR_WAVE - 1);
+    const uint32_t k = keys[i < n ? i : n - 1];
+    bool pending = i < n;
+    if (pending && k == 0xFFFFFFFFu) {
+        atomicOr(&count[1], 1u);
+        pending = false;
+    }
+    for (;;) {
+        const uint64_t m = __ballot(pending);
+        if (m == 0) break;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        const uint32_t kl = __shfl(k, leader);
+        if (pending && k == kl) {
+            pending = false;
+            if (lane == leader) {
+                uint32_t slot = mix32(kl) & mask;
+                for (uint32_t probe = 0; probe <= mask; ++probe) {
+                    const uint32_t prev = atomicCAS(&table[slot], 0xFFFFFFFFu, kl);
+                    if (prev == 0xFFFFFFFFu) {
+                        atomicAdd(&count[0], 1u);
+                        break;
+                    }
+                    if (prev == kl) break;
+                    slot = (slot + 1) & mask;
+                }
+            }
+        }
+    }
+}
+
+void launch_count_distinct_u32(const uint32_t* keys, int64_t n, uint32_t* table, int64_t T, unsigned* count,
+                               hipStream_t s) {
+    k_set_clear<<<nblk(T, 256), 256, 0, s>>>(table, T, count);
+    if (n > 0) k_set_insert<<<nblk(n, 256), 256, 0, s>>>(keys, n, table, (uint32_t)(T - 1), count);
+}
+
 void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t s) {
     if (n > 0) k_fill_i32<<<nblk(n, 256), 256, 0, s>>>(a, n, v);
 }

@@ -627,7 +627,7 @@ int ensure_workspace(pr_handle h, int m) {
     PR_TRY(dalloc(h, &h->gm, 8192));
     PR_TRY(dalloc(h, &h->gctl, 4));
     PR_TRY(dalloc(h, &h->hd, 256));
-    if (!h->hh) PR_HIP(h, hipHostMalloc((void**)&h->hh, 256 * sizeof(double), hipHostMallocDefault));
+    if (!h->hh) PR_HIP(h, pool_host_alloc(256 * sizeof(double), (void**)&h->hh, &h->hh_got));
     h->ws_restart = m;
     return PR_OK;
 }
@@ -673,17 +673,19 @@ int autotune_apply(pr_handle h) {
     // three vectors (argument, result, scratch) that live only while timing
     struct Scratch {
         hipStream_t s;
+        int device;
         double* buf = nullptr;
+        size_t got = 0;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         ~Scratch() {
             (void)hipStreamSynchronize(s);
-            if (buf) (void)hipFree(buf);
+            if (buf) pool_release(device, buf, got);
             if (e0) (void)hipEventDestroy(e0);
             if (e1) (void)hipEventDestroy(e1);
         }
-    } sc{s};
+    } sc{s, h->device};
     {
-        hipError_t e = hipMalloc((void**)&sc.buf, (size_t)3 * (n > 0 ? n : 1) * sizeof(double));
+        hipError_t e = pool_alloc(h->device, (size_t)3 * (n > 0 ? n : 1) * sizeof(double), (void**)&sc.buf, &sc.got);
         if (e != hipSuccess) {
             sc.buf = nullptr;
             (void)hipGetLastError();
@@ -956,13 +958,16 @@ void pr_destroy(pr_handle h) {
         (void)hipStreamSynchronize(h->gstream);
         (void)hipStreamDestroy(h->gstream);
     }
-    for (auto& b : h->owned) (void)hipFree(b.p);
-    if (h->hh) (void)hipHostFree(h->hh);
+    for (auto& b : h->owned) pool_release(h->device, b.p, b.bytes);
+    if (h->hh) pool_host_release(h->hh, h->hh_got);
     delete h;
 }
 
 int pr_set_stream(pr_handle h, void* st) {
     if (!h) return PR_ERR_INVALID_ARG;
+    // work queued on the old stream finishes first: pr_destroy waits for the
+    // current stream only before the handle's blocks go back to the cache
+    if ((hipStream_t)st != h->stream) PR_HIP(h, hipStreamSynchronize(h->stream));
     h->stream = (hipStream_t)st;
     h->prm.stream = st;
     return PR_OK;
@@ -1168,15 +1173,23 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
     SETUP_TRY(run_group(h));
     h->stats.tune_xcd_remap = (h->tile_p > 0 || h->ell_c > 0) ? h->tune_remap : 0;
     if (pm.autotune) SETUP_TRY(autotune_apply(h));
-    const double t4 = now_s();
 
     // boundary groups (distinct keys) for the stats
     {
-        std::vector<uint32_t> kh(h->n_p);
-        SETUP_HIP(hipMemcpy(kh.data(), h->keys, h->n_p * sizeof(uint32_t), hipMemcpyDeviceToHost));
-        std::sort(kh.begin(), kh.end());
-        h->stats.n_groups = (int32_t)(std::unique(kh.begin(), kh.end()) - kh.begin());
+        int64_t T = 1024;
+        while (T < 2 * h->n_p) T <<= 1;
+        uint32_t* table = nullptr;
+        unsigned* dcount = nullptr;
+        SETUP_TRY(dalloc(h, &table, T));
+        SETUP_TRY(dalloc(h, &dcount, 2));
+        launch_count_distinct_u32(h->keys, h->n_p, table, T, dcount, s);
+        unsigned c2[2];
+        SETUP_HIP(hipMemcpyAsync(c2, dcount, sizeof(c2), hipMemcpyDeviceToHost, s));
+        SETUP_HIP(hipStreamSynchronize(s));
+        SETUP_HIP(hipGetLastError());
+        h->stats.n_groups = (int32_t)(c2[0] + c2[1]);
     }
+    const double t4 = now_s();
     h->stats.n = h->n;
     h->stats.nnz = h->nnz;
     h->stats.n_p = h->n_p;
@@ -1352,10 +1365,11 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
             tbeg();
             launch_gs(0, V, ldv, j + 1, w, n, nullptr, red, hd, s, gctl, sel);
             launch_gs(1, V, ldv, j + 1, w, n, hd, red, hd + 64, s, gctl, sel);
-            launch_gs(2, V, ldv, j + 1, w, n, hd + 64, red, hd + 128, s, gctl, false, sel ? hd : nullptr);
-            launch_scale(w, V + (int64_t)(j + 1) * ldv, hd + 128, n, s, gctl);
+            launch_gs(2, V, ldv, j + 1, w, n, hd + 64, red, nullptr, s, gctl, false, sel ? hd : nullptr);
+            // ||w||, v_{j+1} = w / ||w||, Givens update and stopping test
+            launch_step_end(red, sel ? hd : nullptr, w, V + (int64_t)(j + 1) * ldv, n, j, m, hd, R, cs, sn, g,
+                            est_d, gctl, tol_d, itb_d, h->prm.max_iters, s);
             tend(2);
-            launch_givens(j, m, hd, R, cs, sn, g, est_d, gctl, tol_d, itb_d, h->prm.max_iters, s, sel);
         }
         tsel = timing && tstride == 1;
         tj = -1;

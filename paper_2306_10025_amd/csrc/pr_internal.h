@@ -137,6 +137,7 @@ struct pr_handle_s {
     int64_t ldv = 0;              // leading dimension of the Krylov basis
     double* hd = nullptr;         // device scalars
     double* hh = nullptr;         // pinned host mirror
+    size_t hh_got = 0;            // its cached block size
     int64_t ws_restart = -1;
     std::vector<hipEvent_t> evpool;   // reusable events for per-kernel timing
     // graph replay of a restart cycle: own capture stream, handle-owned b
@@ -207,18 +208,26 @@ int pr_fail(pr_handle h, int code, const std::string& msg);
         if (_s < 0) return _s;       \
     } while (0)
 
-// device allocation owned by the handle (freed by pr_destroy)
+// per-device cache of idle device blocks (pr_pool.hip): *got receives the
+// block's size, which pool_release takes back
+hipError_t pool_alloc(int device, size_t bytes, void** p, size_t* got);
+void pool_release(int device, void* p, size_t got);
+hipError_t pool_host_alloc(size_t bytes, void** p, size_t* got);
+void pool_host_release(void* p, size_t got);
+
+// device allocation owned by the handle (returned to the cache by pr_destroy)
 template <typename T>
 int dalloc(pr_handle h, T** p, size_t count) {
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    size_t got = 0;
+    hipError_t e = pool_alloc(h->device, count * sizeof(T), (void**)p, &got);
     if (e != hipSuccess) {
         *p = nullptr;
         (void)hipGetLastError();
         return pr_fail(h, PR_ERR_OOM, std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
                                           " bytes failed: " + hipGetErrorString(e));
     }
-    h->owned.push_back({(void*)*p, count * sizeof(T)});
+    h->owned.push_back({(void*)*p, got});
     return PR_OK;
 }
 
@@ -262,6 +271,10 @@ void launch_extract(const int64_t* rowptr, const int32_t* col, const double* val
                     int32_t* flags, hipStream_t s);
 void launch_iota(int32_t* a, int64_t n, hipStream_t s);
 void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t s);
+// number of distinct keys: count[0] + count[1] after the launch; table is
+// scratch of T >= 2n slots, T a power of two at most 2^32
+void launch_count_distinct_u32(const uint32_t* keys, int64_t n, uint32_t* table, int64_t T, unsigned* count,
+                               hipStream_t s);
 // sort (key, value) pairs by key, ascending; keys/vals have length n (any n).
 // scratch must hold next_pow2(n) keys and values.
 void launch_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, uint64_t* kscr, int32_t* vscr,
@@ -462,17 +475,20 @@ void launch_spmv_sell(const int64_t* soff, const double* sval, const int32_t* sc
                       const double* x, const double* b, double* y, hipStream_t s,
                       const int32_t* stop = nullptr);
 // Gram-Schmidt passes.  extra (modes 0 and 1, nv < 32): also out[32] = w . w
-// (mode 1: of the updated w).  sel (mode 2): the pass runs only when the
-// selective-reorthogonalisation test on sel[32], sel[96] asks for it; else
-// out[0] = sel[96].
+// (mode 1: of the updated w).  Mode 2 leaves the block partials of w . w in
+// partial for launch_step_end (out unused); sel (mode 2): the pass runs only
+// when the selective-reorthogonalisation test on sel[32], sel[96] asks for it.
 void launch_gs(int mode, const double* V, int64_t ldv, int nv, double* w, int64_t n, const double* c,
                double* partial, double* out, hipStream_t s, const int32_t* stop = nullptr,
                bool extra = false, const double* sel = nullptr);
-// sel: the column is hd[0..j] plus hd[64..64+j] only when the second
-// projection ran (same test as launch_gs)
-void launch_givens(int j, int m, const double* hd, double* R, double* cs, double* sn, double* g,
-                   double* est, int32_t* gctl, const double* tolp, const int64_t* itb, int64_t max_iters,
-                   hipStream_t s, bool sel = false);
+// End of Arnoldi step j after a mode-2 pass: hd[128] = ||w||^2 (from the
+// pass's partials, or sel[96] when the selective test skipped it), vnext =
+// w / ||w||, and the Givens update of column j with the stopping test.  sel
+// (selective mode, = hd or null): the column is hd[0..j] plus hd[64..64+j]
+// only when the third pass ran.
+void launch_step_end(const double* partial, const double* sel, const double* w, double* vnext, int64_t n,
+                     int j, int m, double* hd, double* R, double* cs, double* sn, double* g, double* est,
+                     int32_t* gctl, const double* tolp, const int64_t* itb, int64_t max_iters, hipStream_t s);
 void launch_trisolve(int m, const double* R, const double* g, double* y, const int32_t* gctl,
                      hipStream_t s);
 void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);

@@ -146,3 +146,13 @@ def test_setup_rejects_bad_params():
     h = ctypes.c_void_p()
     rc = pr.lib().pr_setup(ctypes.byref(A), ctypes.byref(P), ctypes.byref(prm), ctypes.byref(h))
     assert rc == pr.PR_ERR_INVALID_ARG
+
+
+def test_memory_cache_calls_need_no_gpu():
+    # a device never used reports an empty cache; bad arguments are rejected
+    info = pr.pr_memory_cache_info(7)
+    assert info == dict(idle_bytes=0, idle_blocks=0, reuses=0, mallocs=0)
+    L = pr.lib()
+    assert L.pr_memory_cache_info(0, None) == pr.PR_ERR_INVALID_ARG
+    assert L.pr_memory_cache_info(-2, (ctypes.c_int64 * 4)()) == pr.PR_ERR_INVALID_ARG
+    assert L.pr_set_memory_cache_limit(-2) == pr.PR_ERR_INVALID_ARG

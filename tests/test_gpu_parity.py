@@ -567,3 +567,45 @@ def test_apply_forms_are_bit_identical(case, precision):
     ha.close()
     hg.close()
     hat.close()
+
+
+def test_memory_cache_reuse_gives_the_same_results():
+    # the blocks a destroyed handle leaves in the device memory cache hold
+    # another system's values; a setup on them must give the bits of a setup
+    # on freshly mapped memory
+    P = gen.nedelec_hex(6)
+    kw = dict(algo="tolerance", eps=1e-8, precision="bf16x3", deterministic=True)
+
+    def run(A):
+        h = pr.PatchRelax(A, P.ptr, P.dofs, **kw)
+        bt = dt(_rhs(P.n), torch.float64)
+        x = torch.zeros_like(bt)
+        h.solve(bt, x, 1e-8)
+        r = dt(np.random.default_rng(3).standard_normal(P.n), torch.float64)
+        z = torch.empty_like(r)
+        h.apply(r, z)
+        torch.cuda.synchronize()
+        out = (x.cpu().numpy(), z.cpu().numpy(), h.assignment()[0].copy(), h.stats()["n_groups"],
+               h.solve_info()["iters"])
+        h.close()
+        return out
+
+    try:
+        pr.pr_set_memory_cache_limit(0)
+        assert pr.pr_memory_cache_info(0)["idle_bytes"] == 0
+        ref = run(P.A)
+        assert pr.pr_memory_cache_info(0)["idle_bytes"] == 0
+        pr.pr_set_memory_cache_limit(1 << 32)
+        run(P.A * 2.0 + 1e-3 * P.A.multiply(P.A > 0))       # other values, same sizes
+        before = pr.pr_memory_cache_info(0)
+        assert before["idle_blocks"] > 10
+        out = run(P.A)
+        after = pr.pr_memory_cache_info(0)
+        say("cache", before, after)
+        assert after["reuses"] - before["reuses"] >= before["idle_blocks"] // 2
+        for a, b in zip(ref, out):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
+        pr.pr_release_cached_memory()
+        assert pr.pr_memory_cache_info(0)["idle_bytes"] == 0
+    finally:
+        pr.pr_set_memory_cache_limit(-1)
