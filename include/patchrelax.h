@@ -200,6 +200,13 @@ typedef struct {
                                 tuner found launch order faster */
     int64_t crit_refined;    /* spectral evaluations the cheap bracket left open and the
                                 repeated-squaring bracket then decided or narrowed */
+    /* the solve's copy of A: 64-row slices, each in diagonal form (values per
+       distinct column offset, 8 bytes each) or column form (values and
+       column indices, 12 bytes each), whichever stores fewer bytes */
+    int64_t sell_slots;          /* stored values, padding included */
+    int64_t sell_diag_slices;    /* slices in diagonal form */
+    int64_t sell_diag_offsets;   /* their distinct offsets (stored columns) */
+    int64_t sell_col_entries;    /* matrix entries in column-form slices */
 } pr_stats;
 
 /* ---- entry points ------------------------------------------------------ */

@@ -87,7 +87,8 @@ class pr_stats(Structure):
                 ("mlp_train_acc", c_double), ("t_mlp_train", c_double),
                 ("tune_threads", c_int32), ("tune_slot", c_int32), ("tune_cap", c_int64),
                 ("t_autotune", c_double), ("tune_tiles_per_wave", c_int64),
-                ("tune_xcd_remap", c_int64), ("crit_refined", c_int64)]
+                ("tune_xcd_remap", c_int64), ("crit_refined", c_int64), ("sell_slots", c_int64),
+                ("sell_diag_slices", c_int64), ("sell_diag_offsets", c_int64), ("sell_col_entries", c_int64)]
 
 
 _SIGS = {

@@ -17,32 +17,132 @@ constexpr int kGsThreads = 256;
 __device__ __forceinline__ bool stopped(const int32_t* stop) { return stop && *stop; }
 
 // ---------------------------------------------------------------------------
-// Sliced ELLPACK copy of A (slices of 64 rows, one wavefront each; column-
-// major inside a slice, padded to the slice's longest row): every lane
-// streams its row's values and columns at unit stride across the wave.
+// Hybrid sliced ELLPACK copy of A: slices of 64 rows, one wavefront each,
+// column-major inside a slice (every lane streams its row at unit stride
+// across the wave).  Each slice takes one of two forms:
+//   diagonal (sfmt 1): the sorted distinct offsets d = col - row of the
+//     slice's entries, one int32 per slice column, and a value for every
+//     (row, offset), 0 where the row has no entry there: 8 bytes per stored
+//     value, the column computed as row + d;
+//   column (sfmt 0): each row's entries padded to the slice's longest row,
+//     with their column indices: 12 bytes per stored value.
+// The plan takes the diagonal form when it stores fewer bytes
+// (8 ndiag <= 12 mlen) and ndiag <= kSellMaxDiag.  Matrices
+// of structured meshes put most slices in the diagonal form; mixed
+// discretisations (several field types per row block) stay in the column
+// form.  Padding and absent diagonal entries hold 0 and contribute exact
+// zeros for finite x.
 // ---------------------------------------------------------------------------
-__global__ void k_sell_len(const int64_t* __restrict__ rowptr, int64_t n, int64_t* __restrict__ slen) {
-    const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+constexpr int kPlanThreads = 256;
+constexpr int kPlanTab = 1024;      // LDS hash set of a slice's offsets
+constexpr int kMaxDiag = kSellMaxDiag;   // distinct offsets of one diagonal slice
+
+__device__ __forceinline__ uint32_t offset_hash(int32_t d) { return ((uint32_t)d * 2654435761u) >> 22; }
+
+// One block per slice (block ns writes the scan's closing 0): slen[sl] = 64 *
+// stored columns, sfmt[sl], the slice's sorted distinct offsets in
+// dtmp[sl * kMaxDiag ..] (diagonal form), and the totals in acc: [0] diagonal
+// slices, [1] their offsets, [2] entries of column-form slices.  The offsets
+// go into an LDS hash set (four lanes per row); a slice with more than fits
+// the set takes the column form.
+__global__ __launch_bounds__(kPlanThreads) void k_sell_plan(const int64_t* __restrict__ rowptr,
+                                                            const int32_t* __restrict__ col, int64_t n,
+                                                            int64_t* __restrict__ slen, int32_t* __restrict__ sfmt,
+                                                            int32_t* __restrict__ dtmp,
+                                                            unsigned long long* __restrict__ acc) {
+    __shared__ int32_t tab[kPlanTab];
+    __shared__ int32_t lst[kPlanThreads];
+    __shared__ int s_mlen, s_nnz, s_cnt, s_over, s_pos;
     const int64_t ns = (n + 63) / 64;
-    if (sl > ns) return;
-    if (sl == ns) {
-        slen[sl] = 0;
+    const int64_t sl = blockIdx.x;
+    const int t = threadIdx.x;
+    if (sl >= ns) {
+        if (t == 0) slen[ns] = 0;
         return;
     }
-    int64_t m = 0;
-    for (int64_t r = sl * 64; r < sl * 64 + 64 && r < n; ++r) {
-        const int64_t l = rowptr[r + 1] - rowptr[r];
-        m = l > m ? l : m;
+    const int64_t r0 = sl * 64;
+    const int rows = (int)(n - r0 < 64 ? n - r0 : 64);
+    if (t == 0) {
+        s_mlen = 0;
+        s_nnz = 0;
+        s_cnt = 0;
+        s_over = 0;
+        s_pos = 0;
     }
-    slen[sl] = 64 * m;
+    for (int e = t; e < kPlanTab; e += kPlanThreads) tab[e] = INT_MAX;
+    lst[t] = INT_MAX;
+    __syncthreads();
+    // four lanes per row: rows w * 16 .. w * 16 + 15 for wavefront w
+    const int i = (t >> 6) * 16 + ((t & 63) >> 2), sub = t & 3;
+    int64_t a = 0, l = 0;
+    if (i < rows) {
+        a = rowptr[r0 + i];
+        l = rowptr[r0 + i + 1] - a;
+        if (sub == 0) {
+            atomicMax(&s_mlen, (int)l);
+            atomicAdd(&s_nnz, (int)l);
+        }
+    }
+    for (int64_t k = sub; k < l; k += 4) {
+        const int32_t d = (int32_t)((int64_t)col[a + k] - (r0 + i));
+        uint32_t slot = offset_hash(d);
+        for (int probe = 0; probe < kPlanTab; ++probe) {
+            const int32_t prev = atomicCAS(&tab[slot], INT_MAX, d);
+            if (prev == INT_MAX) {
+                atomicAdd(&s_cnt, 1);
+                break;
+            }
+            if (prev == d) break;
+            slot = (slot + 1) & (kPlanTab - 1);
+            if (probe == kPlanTab - 1) s_over = 1;     // the set is full
+        }
+    }
+    __syncthreads();
+    const int mlen = s_mlen, ndiag = s_cnt;
+    const int fmt = (!s_over && mlen > 0 && 2 * ndiag <= 3 * mlen && ndiag <= kMaxDiag) ? 1 : 0;
+    if (fmt) {
+        // the set as a list, sorted (at most kMaxDiag values in kPlanThreads slots)
+        for (int e = t; e < kPlanTab; e += kPlanThreads) {
+            const int32_t d = tab[e];
+            if (d != INT_MAX) lst[atomicAdd(&s_pos, 1)] = d;
+        }
+        __syncthreads();
+        for (int k = 2; k <= kPlanThreads; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const int f = t ^ j;
+                if (f > t) {
+                    const int32_t x0 = lst[t], x1 = lst[f];
+                    if ((x0 > x1) == ((t & k) == 0)) {
+                        lst[t] = x1;
+                        lst[f] = x0;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (t < ndiag) dtmp[sl * kMaxDiag + t] = lst[t];
+    }
+    if (t == 0) {
+        slen[sl] = 64 * (int64_t)(fmt ? ndiag : mlen);
+        sfmt[sl] = fmt;
+        if (fmt) {
+            atomicAdd(&acc[0], 1ull);
+            atomicAdd(&acc[1], (unsigned long long)ndiag);
+        } else {
+            atomicAdd(&acc[2], (unsigned long long)s_nnz);
+        }
+    }
 }
 
+// Column-form slices: one thread per row.
 __global__ void k_sell_fill(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                             const double* __restrict__ val, int64_t n, const int64_t* __restrict__ soff,
-                            double* __restrict__ sval, int32_t* __restrict__ scol) {
+                            const int32_t* __restrict__ sfmt, double* __restrict__ sval,
+                            int32_t* __restrict__ scol) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     const int64_t sl = r / 64, lane = r % 64;
+    if (sfmt[sl]) return;
     const int64_t off = soff[sl];
     const int64_t len = (soff[sl + 1] - off) / 64;
     const int64_t a = rowptr[r], l = rowptr[r + 1] - a;
@@ -70,33 +170,90 @@ __global__ void k_sell_fill(const int64_t* __restrict__ rowptr, const int32_t* _
     }
 }
 
+// Diagonal-form slices: one block per slice.  Every stored value is first
+// set to 0; after the barrier each entry (four lanes per row) finds its
+// offset's column by binary search and writes its value.
+__global__ __launch_bounds__(kPlanThreads) void k_sell_fill_diag(const int64_t* __restrict__ rowptr,
+                                                                 const int32_t* __restrict__ col,
+                                                                 const double* __restrict__ val, int64_t n,
+                                                                 const int64_t* __restrict__ soff,
+                                                                 const int32_t* __restrict__ sfmt,
+                                                                 const int32_t* __restrict__ dtmp,
+                                                                 double* __restrict__ sval,
+                                                                 int32_t* __restrict__ sdoff) {
+    __shared__ int32_t s_d[kMaxDiag];
+    const int64_t sl = blockIdx.x;
+    if (!sfmt[sl]) return;
+    const int t = threadIdx.x;
+    const int64_t off = soff[sl];
+    const int nd = (int)((soff[sl + 1] - off) / 64);
+    for (int k = t; k < nd; k += kPlanThreads) {
+        const int32_t d = dtmp[sl * kMaxDiag + k];
+        s_d[k] = d;
+        sdoff[off / 64 + k] = d;
+    }
+    for (int64_t e = t; e < (int64_t)nd * 64; e += kPlanThreads) sval[off + e] = 0.0;
+    __syncthreads();
+    const int64_t r0 = sl * 64;
+    const int rows = (int)(n - r0 < 64 ? n - r0 : 64);
+    const int i = (t >> 6) * 16 + ((t & 63) >> 2), sub = t & 3;
+    if (i >= rows) return;
+    const int64_t a = rowptr[r0 + i], l = rowptr[r0 + i + 1] - a;
+    for (int64_t k = sub; k < l; k += 4) {
+        const int32_t d = (int32_t)((int64_t)col[a + k] - (r0 + i));
+        int lo = 0, hi = nd - 1;          // s_d[lo] == d at the end
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (s_d[mid] < d) lo = mid + 1;
+            else hi = mid;
+        }
+        sval[off + (int64_t)lo * 64 + i] = val[a + k];
+    }
+}
+
 // y = A x (b == nullptr) or y = b - A x; one thread per row, 64-row slices
-__global__ __launch_bounds__(256) void k_spmv_sell(const int64_t* __restrict__ soff,
-                                                   const double* __restrict__ sval,
-                                                   const int32_t* __restrict__ scol, int64_t n,
-                                                   const double* __restrict__ x,
+__global__ __launch_bounds__(256) void k_spmv_sell(SellMat M, int64_t n, const double* __restrict__ x,
                                                    const double* __restrict__ b, double* __restrict__ y,
                                                    const int32_t* __restrict__ stop) {
     if (stopped(stop)) return;
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;      // padding lanes of the last slice hold no entries
-    const int64_t sl = r / 64;
+    // one slice per wavefront: its descriptors are wave-uniform (scalar loads)
+    const int64_t sl = __builtin_amdgcn_readfirstlane((int)(r / 64));
     const int lane = (int)(r % 64);
-    const int64_t off = soff[sl];
-    const int len = (int)((soff[sl + 1] - off) / 64);
-    const double* vp = sval + off + lane;
-    const int32_t* cp = scol + off + lane;
+    const int64_t off = M.soff[sl];
+    const int len = (int)((M.soff[sl + 1] - off) / 64);
+    const double* vp = M.sval + off + lane;
     double acc0 = 0.0, acc1 = 0.0;
-    int k = 0;
-    for (; k + 4 <= len; k += 4) {
-        const double v0 = vp[(k + 0) * 64], v1 = vp[(k + 1) * 64], v2 = vp[(k + 2) * 64], v3 = vp[(k + 3) * 64];
-        const int32_t c0 = cp[(k + 0) * 64], c1 = cp[(k + 1) * 64], c2 = cp[(k + 2) * 64], c3 = cp[(k + 3) * 64];
-        acc0 = fma(v0, x[c0], acc0);
-        acc1 = fma(v1, x[c1], acc1);
-        acc0 = fma(v2, x[c2], acc0);
-        acc1 = fma(v3, x[c3], acc1);
+    if (M.sfmt[sl]) {
+        const int32_t* dp = M.sdoff + off / 64;
+        auto colof = [&](int32_t d) {
+            const int64_t c = r + d;
+            return (uint64_t)c < (uint64_t)n ? c : r;
+        };
+        int k = 0;
+        for (; k + 4 <= len; k += 4) {
+            const double v0 = vp[(k + 0) * 64], v1 = vp[(k + 1) * 64], v2 = vp[(k + 2) * 64], v3 = vp[(k + 3) * 64];
+            const int64_t c0 = colof(dp[k]), c1 = colof(dp[k + 1]), c2 = colof(dp[k + 2]), c3 = colof(dp[k + 3]);
+            acc0 = fma(v0, x[c0], acc0);
+            acc1 = fma(v1, x[c1], acc1);
+            acc0 = fma(v2, x[c2], acc0);
+            acc1 = fma(v3, x[c3], acc1);
+        }
+        for (; k < len; ++k) acc0 = fma(vp[k * 64], x[colof(dp[k])], acc0);
+    } else {
+        const int32_t* cp = M.scol + off + lane;
+        int k = 0;
+        for (; k + 4 <= len; k += 4) {
+            const double v0 = vp[(k + 0) * 64], v1 = vp[(k + 1) * 64], v2 = vp[(k + 2) * 64], v3 = vp[(k + 3) * 64];
+            const int32_t c0 = cp[(k + 0) * 64], c1 = cp[(k + 1) * 64], c2 = cp[(k + 2) * 64], c3 = cp[(k + 3) * 64];
+            acc0 = fma(v0, x[c0], acc0);
+            acc1 = fma(v1, x[c1], acc1);
+            acc0 = fma(v2, x[c2], acc0);
+            acc1 = fma(v3, x[c3], acc1);
+        }
+        for (; k < len; ++k) acc0 = fma(vp[k * 64], x[cp[k * 64]], acc0);
     }
-    for (; k < len; ++k) acc0 = fma(vp[k * 64], x[cp[k * 64]], acc0);
     const double acc = acc0 + acc1;
     y[r] = b ? b[r] - acc : acc;
 }
@@ -386,20 +543,24 @@ inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
 
-void launch_sell_len(const int64_t* rowptr, int64_t n, int64_t* slen, hipStream_t s) {
+void launch_sell_plan(const int64_t* rowptr, const int32_t* col, int64_t n, int64_t* slen, int32_t* sfmt,
+                      int32_t* dtmp, unsigned long long* acc, hipStream_t s) {
     const int64_t ns = (n + 63) / 64;
-    k_sell_len<<<nb(ns + 1, 256), 256, 0, s>>>(rowptr, n, slen);
+    k_sell_plan<<<(unsigned)(ns + 1), kPlanThreads, 0, s>>>(rowptr, col, n, slen, sfmt, dtmp, acc);
 }
 
-void launch_sell_fill(const int64_t* rowptr, const int32_t* col, const double* val, int64_t n,
-                      const int64_t* soff, double* sval, int32_t* scol, hipStream_t s) {
-    k_sell_fill<<<nb(n, 256), 256, 0, s>>>(rowptr, col, val, n, soff, sval, scol);
+void launch_sell_fill(const int64_t* rowptr, const int32_t* col, const double* val, int64_t n, const int64_t* soff,
+                      const int32_t* sfmt, const int32_t* dtmp, double* sval, int32_t* scol, int32_t* sdoff,
+                      hipStream_t s) {
+    const int64_t ns = (n + 63) / 64;
+    k_sell_fill<<<nb(n, 256), 256, 0, s>>>(rowptr, col, val, n, soff, sfmt, sval, scol);
+    k_sell_fill_diag<<<(unsigned)ns, kPlanThreads, 0, s>>>(rowptr, col, val, n, soff, sfmt, dtmp, sval, sdoff);
 }
 
-void launch_spmv_sell(const int64_t* soff, const double* sval, const int32_t* scol, int64_t n,
-                      const double* x, const double* b, double* y, hipStream_t s, const int32_t* stop) {
+void launch_spmv_sell(const SellMat& M, int64_t n, const double* x, const double* b, double* y, hipStream_t s,
+                      const int32_t* stop) {
     const int64_t ns = (n + 63) / 64;
-    k_spmv_sell<<<nb(ns * 64, 256), 256, 0, s>>>(soff, sval, scol, n, x, b, y, stop);
+    k_spmv_sell<<<nb(ns * 64, 256), 256, 0, s>>>(M, n, x, b, y, stop);
 }
 
 int gs_blocks(int64_t n) {

@@ -607,7 +607,7 @@ int precond(pr_handle h, const double* v, double* e, double* t3, const int32_t* 
     hipStream_t s = h->stream;
     PR_TRY(apply_op(h, v, e, false, nullptr, stop));
     for (int sw = 1; sw < h->prm.sweeps; ++sw) {
-        launch_spmv_sell(h->soff, h->sval, h->scol, h->n, e, v, t3, s, stop);
+        launch_spmv_sell(h->sell(), h->n, e, v, t3, s, stop);
         PR_TRY(apply_op(h, t3, e, true, t3 + h->n, stop));
     }
     return PR_OK;
@@ -1153,22 +1153,36 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
     SETUP_HIP(hipStreamSynchronize(s));
     SETUP_HIP(hipGetLastError());
     const double t3 = now_s();
-    // sliced-ELL copy of A for the solve (64-row slices, padded per slice)
+    // hybrid sliced-ELL copy of A for the solve (64-row slices, diagonal or
+    // column form per slice)
     {
         const int64_t ns = (h->n + 63) / 64;
         int64_t* slen = nullptr;
         int64_t* sscr = nullptr;
+        int32_t* dtmp = nullptr;
+        unsigned long long* sacc = nullptr;
         SETUP_TRY(dalloc(h, &slen, ns + 1));
         SETUP_TRY(dalloc(h, &sscr, scan_scratch_elems(ns + 1) + 2));
         SETUP_TRY(dalloc(h, &h->soff, ns + 1));
-        launch_sell_len(h->rowptr, h->n, slen, s);
+        SETUP_TRY(dalloc(h, &h->sfmt, ns));
+        SETUP_TRY(dalloc(h, &dtmp, (size_t)ns * kSellMaxDiag));
+        SETUP_TRY(dalloc(h, &sacc, 3));
+        SETUP_HIP(hipMemsetAsync(sacc, 0, 3 * sizeof(unsigned long long), s));
+        launch_sell_plan(h->rowptr, h->col, h->n, slen, h->sfmt, dtmp, sacc, s);
         launch_exclusive_scan_i64(slen, h->soff, ns + 1, sscr, s);
         int64_t stot = 0;
+        unsigned long long sa[3];
         SETUP_HIP(hipMemcpyAsync(&stot, h->soff + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        SETUP_HIP(hipMemcpyAsync(sa, sacc, sizeof(sa), hipMemcpyDeviceToHost, s));
         SETUP_HIP(hipStreamSynchronize(s));
         SETUP_TRY(dalloc(h, &h->sval, stot));
-        SETUP_TRY(dalloc(h, &h->scol, stot));
-        launch_sell_fill(h->rowptr, h->col, h->val, h->n, h->soff, h->sval, h->scol, s);
+        SETUP_TRY(dalloc(h, &h->scol, sa[2] > 0 ? stot : 1));   // column-form slices only
+        SETUP_TRY(dalloc(h, &h->sdoff, stot / 64 + 1));
+        launch_sell_fill(h->rowptr, h->col, h->val, h->n, h->soff, h->sfmt, dtmp, h->sval, h->scol, h->sdoff, s);
+        h->stats.sell_slots = stot;
+        h->stats.sell_diag_slices = (int64_t)sa[0];
+        h->stats.sell_diag_offsets = (int64_t)sa[1];
+        h->stats.sell_col_entries = (int64_t)sa[2];
     }
     SETUP_TRY(run_group(h));
     h->stats.tune_xcd_remap = (h->tile_p > 0 || h->ell_c > 0) ? h->tune_remap : 0;
@@ -1354,7 +1368,7 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
             PR_TRY(precond(h, vj, zt, t3, gctl));
             tend(0);
             tbeg();
-            launch_spmv_sell(h->soff, h->sval, h->scol, n, zt, nullptr, w, s, gctl);
+            launch_spmv_sell(h->sell(), n, zt, nullptr, w, s, gctl);
             tend(1);
             // classical Gram-Schmidt with selective reorthogonalisation:
             // pass 1: h1 = V^T w, ||w||^2 ; pass 2: w -= V h1, h2 = V^T w, ||w||^2 ;
@@ -1380,7 +1394,7 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
         tend(0);
         launch_axpy_dev(xw, zt, 1.0, n, s);
         tbeg();
-        launch_spmv_sell(h->soff, h->sval, h->scol, n, xw, bw, r, s);
+        launch_spmv_sell(h->sell(), n, xw, bw, r, s);
         tend(1);
         launch_gs(0, r, n, 1, r, n, nullptr, red, hd, s);
         return PR_OK;

@@ -246,7 +246,7 @@ int solve_batch(pr_handle h, const double* b, double* x, double tol) {
             PR_TRY(pr_precond_internal(h, vj, zt, t3, gstop));
             tend(0);
             tbeg();
-            launch_spmv_sell(h->soff, h->sval, h->scol, n, zt, nullptr, w, s, gstop);
+            launch_spmv_sell(h->sell(), n, zt, nullptr, w, s, gstop);
             tend(1);
             tbeg();
             launch_bgs(0, V, ldv, j + 1, w, bg, nullptr, h->bpart, H1, sstop, gstop, s);
@@ -261,7 +261,7 @@ int solve_batch(pr_handle h, const double* b, double* x, double tol) {
         launch_bgemv(V, ldv, bg, yv, m, scols, r, s);
         PR_TRY(pr_precond_internal(h, r, zt, t3, nullptr));
         launch_axpy_dev(xw, zt, 1.0, n, s);
-        launch_spmv_sell(h->soff, h->sval, h->scol, n, xw, bw, r, s);
+        launch_spmv_sell(h->sell(), n, xw, bw, r, s);
         return PR_OK;
     };
     for (;;) {

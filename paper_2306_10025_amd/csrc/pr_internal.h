@@ -55,6 +55,19 @@ __device__ __forceinline__ int fp16_scale_exp(float m) {
 // handle
 // ---------------------------------------------------------------------------
 
+// Hybrid sliced-ELL copy of A (k_krylov.hip): per 64-row slice either the
+// diagonal form (sfmt 1: offsets sdoff[soff/64 + k], values) or the column
+// form (sfmt 0: values and column indices scol), both column-major in the
+// slice from sval[soff[slice]].
+struct SellMat {
+    const int64_t* soff = nullptr;
+    const double* sval = nullptr;
+    const int32_t* scol = nullptr;
+    const int32_t* sdoff = nullptr;
+    const int32_t* sfmt = nullptr;
+};
+constexpr int kSellMaxDiag = 192;   // distinct offsets a diagonal-form slice may hold
+
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
@@ -80,6 +93,9 @@ struct pr_handle_s {
     int64_t* soff = nullptr;
     double* sval = nullptr;
     int32_t* scol = nullptr;
+    int32_t* sdoff = nullptr;
+    int32_t* sfmt = nullptr;
+    SellMat sell() const { return SellMat{soff, sval, scol, sdoff, sfmt}; }
 
     // Section 2 objects
     int32_t* cnt = nullptr;
@@ -468,11 +484,19 @@ void launch_gemv_small(const double* V, int64_t ldv, const int32_t* nvp, const d
                        double* out, hipStream_t s);
 void launch_zero(double* x, int64_t n, hipStream_t s, const int32_t* stop = nullptr);
 int gs_blocks(int64_t n);
-void launch_sell_len(const int64_t* rowptr, int64_t n, int64_t* slen, hipStream_t s);
-void launch_sell_fill(const int64_t* rowptr, const int32_t* col, const double* val, int64_t n,
-                      const int64_t* soff, double* sval, int32_t* scol, hipStream_t s);
-void launch_spmv_sell(const int64_t* soff, const double* sval, const int32_t* scol, int64_t n,
-                      const double* x, const double* b, double* y, hipStream_t s,
+// Plan of the hybrid copy: slen[ns + 1] (stored columns * 64 per slice, 0
+// at ns, for the exclusive scan), sfmt[ns], dtmp[ns * kSellMaxDiag] (the
+// offsets of diagonal-form slices), acc[3] += {diagonal slices, their
+// offsets, entries of column-form slices} (acc zeroed by the caller).
+void launch_sell_plan(const int64_t* rowptr, const int32_t* col, int64_t n, int64_t* slen, int32_t* sfmt,
+                      int32_t* dtmp, unsigned long long* acc, hipStream_t s);
+// Fill after the scan of slen into soff: sval for every slice, scol for the
+// column form, sdoff for the diagonal form.
+void launch_sell_fill(const int64_t* rowptr, const int32_t* col, const double* val, int64_t n, const int64_t* soff,
+                      const int32_t* sfmt, const int32_t* dtmp, double* sval, int32_t* scol, int32_t* sdoff,
+                      hipStream_t s);
+// y = A x (b null) or y = b - A x
+void launch_spmv_sell(const SellMat& M, int64_t n, const double* x, const double* b, double* y, hipStream_t s,
                       const int32_t* stop = nullptr);
 // Gram-Schmidt passes.  extra (modes 0 and 1, nv < 32): also out[32] = w . w
 // (mode 1: of the updated w).  Mode 2 leaves the block partials of w . w in

@@ -609,3 +609,57 @@ def test_memory_cache_reuse_gives_the_same_results():
         assert pr.pr_memory_cache_info(0)["idle_bytes"] == 0
     finally:
         pr.pr_set_memory_cache_limit(-1)
+
+
+def _sell_forms(A):
+    """Per 64-row slice: 1 (diagonal form) when 8 * distinct offsets <=
+    12 * longest row and there are at most 192 of them, else 0; host replay of
+    the plan's rule for the test."""
+    A = A.tocsr()
+    n = A.shape[0]
+    lens = np.diff(A.indptr)
+    rows = np.repeat(np.arange(n), lens)
+    off = A.indices.astype(np.int64) - rows
+    forms = []
+    for s in range((n + 63) // 64):
+        a, b = A.indptr[s * 64], A.indptr[min(n, s * 64 + 64)]
+        mlen = lens[s * 64:s * 64 + 64].max()
+        nd = len(np.unique(off[a:b]))
+        forms.append(int(mlen > 0 and 2 * nd <= 3 * mlen and nd <= 192))
+    return np.array(forms)
+
+
+def test_spmv_hybrid_slices_match_the_residual():
+    # one matrix with both slice forms: a Q1 block (diagonal form) stacked with
+    # a Taylor-Hood block (column form); the solve's reported residual comes
+    # from the device product b - A x and must match the host's
+    import scipy.sparse as sp
+    P1, P2 = gen.q1_poisson_2d(40), gen.taylor_hood_stokes_2d(8)
+    A = sp.csr_matrix((np.concatenate([P1.A.data, P2.A.data]),
+                       np.concatenate([P1.A.indices, P2.A.indices + P1.n]).astype(np.int32),
+                       np.concatenate([P1.A.indptr, P1.A.nnz + P2.A.indptr[1:]]).astype(np.int64)),
+                      shape=(P1.n + P2.n, P1.n + P2.n))
+    ptr = np.concatenate([P1.ptr, P1.ptr[-1] + np.asarray(P2.ptr[1:])]).astype(np.int64)
+    dofs = np.concatenate([P1.dofs, P2.dofs + P1.n]).astype(np.int32)
+    n = A.shape[0]
+    forms = _sell_forms(A)
+    assert 0 < forms.sum() < len(forms)
+    h = pr.PatchRelax(A, ptr, dofs, algo="full", deterministic=True)
+    st = h.stats()
+    say("sell", st["sell_diag_slices"], "of", len(forms), "slots", st["sell_slots"])
+    assert st["sell_diag_slices"] == forms.sum()
+    lens = np.diff(A.indptr)
+    col_entries = sum(int(lens[s * 64:s * 64 + 64].sum()) for s in range(len(forms)) if not forms[s])
+    assert st["sell_col_entries"] == col_entries
+    h.close()
+    b = _rhs(n, 4)
+    bt = dt(b, torch.float64)
+    for cap in (7, 400):        # stopped early, and converged
+        h = pr.PatchRelax(A, ptr, dofs, algo="full", deterministic=True, max_iters=cap)
+        x = torch.zeros_like(bt)
+        h.solve(bt, x, 1e-10)
+        info = h.solve_info()
+        h.close()
+        rel = np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b)
+        say("cap", cap, "iters", info["iters"], "relres lib", info["relres"], "host", rel)
+        assert abs(info["relres"] - rel) <= 1e-10
