@@ -131,9 +131,13 @@ def path_params(args, P, compressed):
                 mlp=args.mlp, **common)
 
 
-def algorithmic_bytes(P, m_p, precision, n_items, n_p_entries):
-    """Bytes one preconditioner application must move at minimum, by kernel
-    class (HBM model; each array read or written once)."""
+def algorithmic_bytes(P, m_p, precision, n_items, n_p_entries, st=None):
+    """Bytes one preconditioner application and one Krylov product must move
+    at minimum (HBM model; each array read or written once).  The product
+    reads every matrix value (8 B) and the index data of the stored form: 4 B
+    per column offset of a diagonal-form slice, 4 B per entry of a
+    column-form slice (CSR's 4 B per entry when the statistics are absent),
+    the slice offsets, x and y."""
     import numpy as np
     n, n_p = P.n, P.n_p
     sum_ps = int(P.ptr[-1])
@@ -147,7 +151,11 @@ def algorithmic_bytes(P, m_p, precision, n_items, n_p_entries):
              + 4 * n_p           # entry of each patch
              + 16 * n_items      # work items (grouped kernels)
              + db)               # database inverses
-    spmv = 12 * P.A.nnz + 8 * (n + 1) + 8 * n + 8 * n
+    if st is not None and st.get("sell_slots", 0) > 0:
+        index = 4 * (st["sell_diag_offsets"] + st["sell_col_entries"]) + 8 * ((n + 63) // 64 + 1)
+    else:
+        index = 4 * P.A.nnz + 8 * (n + 1)
+    spmv = 8 * P.A.nnz + index + 8 * n + 8 * n
     return apply, spmv
 
 
@@ -249,7 +257,7 @@ def summarize_classes(P, rec, precision, m_p, n_items):
     """Average duration of one launch of each kernel class, from the events
     recorded inside the timed steps (a sample of the Arnoldi steps), and the
     device time per step it implies."""
-    apply_b, spmv_b = algorithmic_bytes(P, m_p, precision, n_items, m_p)
+    apply_b, spmv_b = algorithmic_bytes(P, m_p, precision, n_items, m_p, rec[0][1] if rec else None)
     tot = {"apply": [0.0, 0, 0], "spmv": [0.0, 0, 0], "orth": [0.0, 0, 0]}
     for info, st in rec:
         lps = launches_per_solve(info)
@@ -343,7 +351,7 @@ def main():
                                          and args.scatter == "two-stage") else None
     kname = "patch apply (" + args.precision + ("" if args.scatter == "atomic" else ", two-stage") + ")"
     rl_apply = roofline(kname, cls["apply"]["bytes"], cls["apply"]["avg_us"], traffic)
-    rl_spmv = roofline("sell spmv (fp64)", cls["spmv"]["bytes"], cls["spmv"]["avg_us"])
+    rl_spmv = roofline("hybrid sliced-ELL spmv (fp64)", cls["spmv"]["bytes"], cls["spmv"]["avg_us"])
     rl_orth = roofline("gram-schmidt per arnoldi step (fp64)", cls["orth"]["bytes"], cls["orth"]["avg_us"])
     database = {"tolerance": f"algorithm 1, spectral criterion, eps={args.eps}" + (" with the learned predictor" if args.mlp else ""),
                 "kmeans_spectral": "algorithm 2 spectral k-means, m_p = 5 % of n_p",
@@ -367,6 +375,8 @@ def main():
             "database": database,
             "apply_precision": args.precision, "setup_precision": "f64", "krylov": "f64 GMRES(30)",
             "scatter": args.scatter, "graph": args.graph,
+            "krylov_matrix": (f"hybrid sliced ELL, {st['sell_diag_slices']} of {(P.n + 63) // 64} slices "
+                              f"in diagonal form, {st['sell_slots']} stored values"),
             "tol": args.tol, "max_iters": args.iters, "parallelism": "single GPU",
         },
         "setup_s": round(float(np.mean([s["t_total"] for _, s in g["rec"]])), 4),
