@@ -455,76 +455,94 @@ __global__ __launch_bounds__(kEndThreads) void k_step_end(
     __shared__ double s_w[kEndThreads / PR_WAVE];
     __shared__ double col[65], c_s[64], s_s[64];
     const int t = threadIdx.x;
+    const bool first = blockIdx.x == 0;
+    // every load is issued before the first wait: the stop flag, the block
+    // partials (read even when the selective test skipped the pass; their
+    // sum is then not used), this thread's first rows of w and, in block 0,
+    // the Hessenberg column and the previous rotations
     if (t == 0) s_stop = gctl[0];
+    double a = 0.0;
+    for (int b = t; b < nblk; b += kEndThreads) a += partial[b];
+    const int64_t stride = (int64_t)gridDim.x * kEndThreads;
+    const int64_t base0 = (int64_t)blockIdx.x * kEndThreads + t;
+    double v[kEndUnroll];
+#pragma unroll
+    for (int u = 0; u < kEndUnroll; ++u) {
+        const int64_t q = base0 + u * stride;
+        v[u] = w[q < n ? q : n - 1];
+    }
+    // selective mode: the second projection's coefficients count only when
+    // it ran
+    const bool skip3 = sel && !reorth_needed(sel);
+    const bool h2 = !skip3;
+    if (first) {
+        if (t <= j) col[t] = hd[t] + (h2 ? hd[64 + t] : 0.0);
+        if (t < j) {
+            c_s[t] = cs[t];
+            s_s[t] = sn[t];
+        }
+    }
+    a = wave_sum(a);
+    if ((t & (PR_WAVE - 1)) == 0) s_w[t / PR_WAVE] = a;
     __syncthreads();
     if (s_stop) return;
     double nrm2;
-    if (sel && !reorth_needed(sel)) {
+    if (skip3) {
         nrm2 = sel[kSelProj];
     } else {
-        double a = 0.0;
-        for (int b = t; b < nblk; b += kEndThreads) a += partial[b];
-        a = wave_sum(a);
-        if ((t & (PR_WAVE - 1)) == 0) s_w[t / PR_WAVE] = a;
-        __syncthreads();
         double u = 0.0;
         for (int w2 = 0; w2 < kEndThreads / PR_WAVE; ++w2) u += s_w[w2];
         nrm2 = u;
     }
-    {
-        const double d = sqrt(nrm2);
-        const int64_t stride = (int64_t)gridDim.x * kEndThreads;
-        for (int64_t base = (int64_t)blockIdx.x * kEndThreads + t; base < n; base += kEndUnroll * stride) {
-            double v[kEndUnroll];
-#pragma unroll
-            for (int u = 0; u < kEndUnroll; ++u) {
-                const int64_t q = base + u * stride;
-                v[u] = w[q < n ? q : n - 1];
+    if (first) {
+        // Givens update of column j, ahead of this block's share of v_{j+1}
+        if (t == 0) {
+            hd[128] = nrm2;
+            const int64_t iters_base = *itb;
+            const double tol_abs = *tolp;
+            const double hn = sqrt(fmax(nrm2, 0.0));
+            for (int i = 0; i < j; ++i) {
+                const double a0 = col[i], b0 = col[i + 1];
+                col[i] = c_s[i] * a0 + s_s[i] * b0;
+                col[i + 1] = -s_s[i] * a0 + c_s[i] * b0;
             }
+            const double a0 = col[j];
+            const double den = hypot(a0, hn);
+            const double cj = den > 0.0 ? a0 / den : 1.0;
+            const double sj = den > 0.0 ? hn / den : 0.0;
+            cs[j] = cj;
+            sn[j] = sj;
+            col[j] = den;
+            const double gj = g[j];
+            g[j + 1] = -sj * gj;
+            g[j] = cj * gj;
+            gctl[1] = j + 1;
+            if (h2) gctl[2] += 1;
+            est[0] = fabs(g[j + 1]);
+            if (!(fabs(g[j + 1]) > tol_abs) || iters_base + j + 1 >= max_iters || j + 1 >= m) gctl[0] = 1;
+        }
+        __syncthreads();
+        if (t <= j) R[(int64_t)t * m + j] = col[t];
+    }
+    const double d = sqrt(nrm2);
 #pragma unroll
-            for (int u = 0; u < kEndUnroll; ++u) {
-                const int64_t q = base + u * stride;
-                if (q < n) vnext[q] = d > 0.0 ? v[u] / d : 0.0;
-            }
+    for (int u = 0; u < kEndUnroll; ++u) {
+        const int64_t q = base0 + u * stride;
+        if (q < n) vnext[q] = d > 0.0 ? v[u] / d : 0.0;
+    }
+    for (int64_t base = base0 + kEndUnroll * stride; base < n; base += kEndUnroll * stride) {
+        double v2[kEndUnroll];
+#pragma unroll
+        for (int u = 0; u < kEndUnroll; ++u) {
+            const int64_t q = base + u * stride;
+            v2[u] = w[q < n ? q : n - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < kEndUnroll; ++u) {
+            const int64_t q = base + u * stride;
+            if (q < n) vnext[q] = d > 0.0 ? v2[u] / d : 0.0;
         }
     }
-    if (blockIdx.x != 0) return;
-    // selective mode: the second projection's coefficients count only when
-    // it ran
-    const bool h2 = !sel || reorth_needed(sel);
-    if (t <= j) col[t] = hd[t] + (h2 ? hd[64 + t] : 0.0);
-    if (t < j) {
-        c_s[t] = cs[t];
-        s_s[t] = sn[t];
-    }
-    __syncthreads();
-    if (t == 0) {
-        hd[128] = nrm2;
-        const int64_t iters_base = *itb;
-        const double tol_abs = *tolp;
-        const double hn = sqrt(fmax(nrm2, 0.0));
-        for (int i = 0; i < j; ++i) {
-            const double a = col[i], b = col[i + 1];
-            col[i] = c_s[i] * a + s_s[i] * b;
-            col[i + 1] = -s_s[i] * a + c_s[i] * b;
-        }
-        const double a = col[j];
-        const double den = hypot(a, hn);
-        const double cj = den > 0.0 ? a / den : 1.0;
-        const double sj = den > 0.0 ? hn / den : 0.0;
-        cs[j] = cj;
-        sn[j] = sj;
-        col[j] = den;
-        const double gj = g[j];
-        g[j + 1] = -sj * gj;
-        g[j] = cj * gj;
-        gctl[1] = j + 1;
-        if (h2) gctl[2] += 1;
-        est[0] = fabs(g[j + 1]);
-        if (!(fabs(g[j + 1]) > tol_abs) || iters_base + j + 1 >= max_iters || j + 1 >= m) gctl[0] = 1;
-    }
-    __syncthreads();
-    if (t <= j) R[(int64_t)t * m + j] = col[t];
 }
 
 // y = R^{-1} g over the columns done (upper triangular back substitution)
