@@ -211,6 +211,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_sell_fill_diag(const int64_t* 
     }
 }
 
+constexpr int kSpmvChunk = 8;   // diagonal-form entries per step (even)
+static_assert(kSpmvChunk <= kSellOffsetPad, "the offset array's padding covers one step");
+
 // y = A x (b == nullptr) or y = b - A x; one thread per row, 64-row slices
 __global__ __launch_bounds__(256) void k_spmv_sell(SellMat M, int64_t n, const double* __restrict__ x,
                                                    const double* __restrict__ b, double* __restrict__ y,
@@ -226,21 +229,30 @@ __global__ __launch_bounds__(256) void k_spmv_sell(SellMat M, int64_t n, const d
     const double* vp = M.sval + off + lane;
     double acc0 = 0.0, acc1 = 0.0;
     if (M.sfmt[sl]) {
+        // diagonal form: neither the values nor the gathers depend on earlier
+        // loads, so kSpmvChunk of each are issued together, and the entries
+        // alternate between the two accumulators by column parity.  Past the
+        // slice's last column the offsets read are whatever follows (the
+        // offset array is padded by kSellOffsetPad), the column is clamped
+        // into range, the value index to the last column, and the product
+        // is dropped.
         const int32_t* dp = M.sdoff + off / 64;
-        auto colof = [&](int32_t d) {
-            const int64_t c = r + d;
-            return (uint64_t)c < (uint64_t)n ? c : r;
-        };
-        int k = 0;
-        for (; k + 4 <= len; k += 4) {
-            const double v0 = vp[(k + 0) * 64], v1 = vp[(k + 1) * 64], v2 = vp[(k + 2) * 64], v3 = vp[(k + 3) * 64];
-            const int64_t c0 = colof(dp[k]), c1 = colof(dp[k + 1]), c2 = colof(dp[k + 2]), c3 = colof(dp[k + 3]);
-            acc0 = fma(v0, x[c0], acc0);
-            acc1 = fma(v1, x[c1], acc1);
-            acc0 = fma(v2, x[c2], acc0);
-            acc1 = fma(v3, x[c3], acc1);
+        for (int k0 = 0; k0 < len; k0 += kSpmvChunk) {
+            double v[kSpmvChunk], xv[kSpmvChunk];
+#pragma unroll
+            for (int u = 0; u < kSpmvChunk; ++u) {
+                const int k = k0 + u < len ? k0 + u : len - 1;
+                const int64_t c = r + dp[k0 + u];
+                v[u] = vp[(int64_t)k * 64];
+                xv[u] = x[(uint64_t)c < (uint64_t)n ? c : r];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < kSpmvChunk; u += 2) {
+                if (k0 + u < len) acc0 = fma(v[u], xv[u], acc0);
+                if (k0 + u + 1 < len) acc1 = fma(v[u + 1], xv[u + 1], acc1);
+            }
         }
-        for (; k < len; ++k) acc0 = fma(vp[k * 64], x[colof(dp[k])], acc0);
     } else {
         const int32_t* cp = M.scol + off + lane;
         int k = 0;

@@ -1177,7 +1177,7 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
         SETUP_HIP(hipStreamSynchronize(s));
         SETUP_TRY(dalloc(h, &h->sval, stot));
         SETUP_TRY(dalloc(h, &h->scol, sa[2] > 0 ? stot : 1));   // column-form slices only
-        SETUP_TRY(dalloc(h, &h->sdoff, stot / 64 + 1));
+        SETUP_TRY(dalloc(h, &h->sdoff, stot / 64 + kSellOffsetPad));
         launch_sell_fill(h->rowptr, h->col, h->val, h->n, h->soff, h->sfmt, dtmp, h->sval, h->scol, h->sdoff, s);
         h->stats.sell_slots = stot;
         h->stats.sell_diag_slices = (int64_t)sa[0];

@@ -67,6 +67,7 @@ struct SellMat {
     const int32_t* sfmt = nullptr;
 };
 constexpr int kSellMaxDiag = 192;   // distinct offsets a diagonal-form slice may hold
+constexpr int kSellOffsetPad = 16;  // entries allocated past the last slice's offsets
 
 struct DevBuf {
     void* p = nullptr;
