@@ -108,14 +108,16 @@ __global__ void k_square_sizes(const int64_t* __restrict__ ptr, int64_t n_p, int
 // One wavefront (one block of 64 threads) per patch, grid-stride.
 // A_k[a][b] = A[g_a][g_b]: the wave walks the CSR rows of the patch's dofs as
 // one flattened, coalesced sequence of nonzeros; each nonzero's column is
-// looked up among the patch dofs (sorted in LDS) by binary search.
+// looked up among the patch dofs (sorted in LDS) by binary search.  The tile
+// buffer is dynamic LDS of max_ps^2 doubles, so small patches leave room
+// for more resident blocks.
 __global__ __launch_bounds__(64) void k_extract(
     const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const double* __restrict__ val, const int64_t* __restrict__ ptr,
     const int32_t* __restrict__ dofs, int64_t n_p, const int64_t* __restrict__ toff,
     int uniform_ps, double* __restrict__ tiles, uint32_t* __restrict__ keys,
     double* __restrict__ fnorm, double* __restrict__ l1norm, int32_t* flags) {
-    __shared__ double s_tile[kMaxPs * kMaxPs];
+    extern __shared__ double s_tile[];
     __shared__ int32_t s_sorted[kMaxPs];
     __shared__ int32_t s_loc[kMaxPs];
     __shared__ int64_t s_rs[kMaxPs];
@@ -387,12 +389,23 @@ __global__ void k_transpose_sort(int64_t n, const int64_t* __restrict__ dof_ptr,
     }
 }
 
-// largest count (one atomic per wavefront)
-__global__ void k_max_i32(const int32_t* __restrict__ a, int64_t n, int32_t* __restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t v = i < n ? a[i] : 0;
+// largest count: a grid-stride maximum per block, one atomic per block (one
+// per wavefront on a single address serialised at about 11 ns each)
+constexpr int kMaxBlocks = 512;
+__global__ __launch_bounds__(256) void k_max_i32(const int32_t* __restrict__ a, int64_t n,
+                                                 int32_t* __restrict__ out) {
+    __shared__ int32_t s_m[256 / PR_WAVE];
+    int32_t v = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v = a[i] > v ? a[i] : v;
     v = wave_max(v);
-    if ((threadIdx.x & (PR_WAVE - 1)) == 0) atomicMax(out, v);
+    if ((threadIdx.x & (PR_WAVE - 1)) == 0) s_m[threadIdx.x / PR_WAVE] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t m = s_m[0];
+        for (int w = 1; w < 256 / PR_WAVE; ++w) m = s_m[w] > m ? s_m[w] : m;
+        atomicMax(out, m);
+    }
 }
 
 // padded copy of the dof -> slot lists: C entries per dof, -1 after the last
@@ -465,12 +478,13 @@ void launch_tile_offsets(const int64_t* ptr, int64_t n_p, int64_t* toff, int64_t
 
 void launch_extract(const int64_t* rowptr, const int32_t* col, const double* val,
                     const int64_t* ptr, const int32_t* dofs, int64_t n_p, const int64_t* toff,
-                    int uniform_ps, double* tiles, uint32_t* keys, double* fnorm, double* l1norm,
+                    int uniform_ps, int max_ps, double* tiles, uint32_t* keys, double* fnorm, double* l1norm,
                     int32_t* flags, hipStream_t s) {
     if (n_p <= 0) return;
     const int64_t grid = n_p < 65536 * 4 ? n_p : 65536 * 4;
-    k_extract<<<(unsigned)grid, 64, 0, s>>>(rowptr, col, val, ptr, dofs, n_p, toff, uniform_ps,
-                                            tiles, keys, fnorm, l1norm, flags);
+    const int pm = max_ps > 0 && max_ps <= kMaxPs ? max_ps : kMaxPs;
+    k_extract<<<(unsigned)grid, 64, (size_t)pm * pm * sizeof(double), s>>>(
+        rowptr, col, val, ptr, dofs, n_p, toff, uniform_ps, tiles, keys, fnorm, l1norm, flags);
 }
 
 void launch_iota(int32_t* a, int64_t n, hipStream_t s) {
@@ -495,35 +509,45 @@ __global__ void k_set_clear(uint32_t* table, int64_t T, unsigned* count) {
 
 // count[0]: keys other than 0xFFFFFFFF inserted first; count[1]: 1 if that
 // key occurs.  Patches with one boundary key come in long runs, so each
-// wavefront first reduces its keys to one lane per distinct value (one pass
-// per distinct value in the wavefront) and only those lanes touch the table.
-// The table has at least 2n slots, so every probe sequence meets a free slot;
-// the loop bound is the table size.
+// wavefront walks its chunks of 64 keys reducing each to one lane per
+// distinct value (one pass per distinct value), skips the value it inserted
+// last, and reads the slot before it tries the atomic (a key already present
+// costs a load, not a serialised atomic).  The table has at least 2n slots,
+// so every probe sequence meets a free slot; the loop bound is the table size.
 __global__ void k_set_insert(const uint32_t* keys, int64_t n, uint32_t* table, uint32_t mask, unsigned* count) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & (PR_WAVE - 1);
-    const uint32_t k = keys[i < n ? i : n - 1];
-    bool pending = i < n;
-    if (pending && k == 0xFFFFFFFFu) {
-        atomicOr(&count[1], 1u);
-        pending = false;
-    }
-    for (;;) {
-        const uint64_t m = __ballot(pending);
-        if (m == 0) break;
-        const int leader = __ffsll((unsigned long long)m) - 1;
-        const uint32_t kl = __shfl(k, leader);
-        if (pending && k == kl) {
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / PR_WAVE);
+    const int64_t wv = (int64_t)blockIdx.x * (blockDim.x / PR_WAVE) + threadIdx.x / PR_WAVE;
+    uint32_t last = 0xFFFFFFFFu;
+    for (int64_t c0 = wv * PR_WAVE; c0 < n; c0 += waves * PR_WAVE) {
+        const int64_t i = c0 + lane;
+        const uint32_t k = keys[i < n ? i : n - 1];
+        bool pending = i < n;
+        if (pending && k == 0xFFFFFFFFu) {
+            atomicOr(&count[1], 1u);
             pending = false;
+        }
+        for (;;) {
+            const uint64_t m = __ballot(pending);
+            if (m == 0) break;
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            const uint32_t kl = __shfl(k, leader);
+            if (pending && k == kl) pending = false;
+            if (kl == last) continue;
+            last = kl;
             if (lane == leader) {
                 uint32_t slot = mix32(kl) & mask;
                 for (uint32_t probe = 0; probe <= mask; ++probe) {
-                    const uint32_t prev = atomicCAS(&table[slot], 0xFFFFFFFFu, kl);
-                    if (prev == 0xFFFFFFFFu) {
-                        atomicAdd(&count[0], 1u);
-                        break;
+                    const uint32_t seen = table[slot];
+                    if (seen == kl) break;
+                    if (seen == 0xFFFFFFFFu) {
+                        const uint32_t prev = atomicCAS(&table[slot], 0xFFFFFFFFu, kl);
+                        if (prev == 0xFFFFFFFFu) {
+                            atomicAdd(&count[0], 1u);
+                            break;
+                        }
+                        if (prev == kl) break;
                     }
-                    if (prev == kl) break;
                     slot = (slot + 1) & mask;
                 }
             }
@@ -534,7 +558,10 @@ __global__ void k_set_insert(const uint32_t* keys, int64_t n, uint32_t* table, u
 void launch_count_distinct_u32(const uint32_t* keys, int64_t n, uint32_t* table, int64_t T, unsigned* count,
                                hipStream_t s) {
     k_set_clear<<<nblk(T, 256), 256, 0, s>>>(table, T, count);
-    if (n > 0) k_set_insert<<<nblk(n, 256), 256, 0, s>>>(keys, n, table, (uint32_t)(T - 1), count);
+    if (n > 0) {
+        const unsigned b = nblk(n, 256 * 8);        // about 8 chunks of 64 keys per wavefront
+        k_set_insert<<<b < 1 ? 1 : b, 256, 0, s>>>(keys, n, table, (uint32_t)(T - 1), count);
+    }
 }
 
 void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t s) {
@@ -581,7 +608,10 @@ void launch_transpose_sort(int64_t n, const int64_t* dof_ptr, int32_t* dof_slots
 }
 
 void launch_max_i32(const int32_t* a, int64_t n, int32_t* out, hipStream_t s) {
-    if (n > 0) k_max_i32<<<nblk(n, 256), 256, 0, s>>>(a, n, out);
+    if (n > 0) {
+        const unsigned b = nblk(n, 256);
+        k_max_i32<<<b < kMaxBlocks ? b : kMaxBlocks, 256, 0, s>>>(a, n, out);
+    }
 }
 
 void launch_build_ell(int64_t n, const int64_t* dof_ptr, const int32_t* dof_slots, int C, int32_t* ell,

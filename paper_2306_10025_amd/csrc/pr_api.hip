@@ -1138,7 +1138,7 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
     SETUP_TRY(dalloc(h, &h->fnorm, h->n_p));
     SETUP_TRY(dalloc(h, &h->l1norm, h->n_p));
     launch_extract(h->rowptr, h->col, h->val, h->pptr, h->pdofs, h->n_p, h->uniform ? nullptr : h->toff,
-                   h->uniform ? h->max_ps : 0, h->tiles, h->keys, h->fnorm, h->l1norm, flags, s);
+                   h->uniform ? h->max_ps : 0, h->max_ps, h->tiles, h->keys, h->fnorm, h->l1norm, flags, s);
     SETUP_HIP(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
     SETUP_HIP(hipStreamSynchronize(s));
     SETUP_HIP(hipGetLastError());

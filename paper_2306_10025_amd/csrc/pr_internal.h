@@ -284,7 +284,7 @@ void launch_tile_offsets(const int64_t* ptr, int64_t n_p, int64_t* toff, int64_t
                          hipStream_t s);
 void launch_extract(const int64_t* rowptr, const int32_t* col, const double* val,
                     const int64_t* ptr, const int32_t* dofs, int64_t n_p, const int64_t* toff,
-                    int uniform_ps, double* tiles, uint32_t* keys, double* fnorm, double* l1norm,
+                    int uniform_ps, int max_ps, double* tiles, uint32_t* keys, double* fnorm, double* l1norm,
                     int32_t* flags, hipStream_t s);
 void launch_iota(int32_t* a, int64_t n, hipStream_t s);
 void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t s);
