@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_sell_plan(const int64_t* __res
                                                             const int32_t* __restrict__ col, int64_t n,
                                                             int64_t* __restrict__ slen, int32_t* __restrict__ sfmt,
                                                             int32_t* __restrict__ dtmp,
-                                                            unsigned long long* __restrict__ acc) {
+                                                            int32_t* __restrict__ cnnz) {
     __shared__ int32_t tab[kPlanTab];
     __shared__ int32_t lst[kPlanThreads];
     __shared__ int s_mlen, s_nnz, s_cnt, s_over, s_pos;
@@ -83,18 +83,41 @@ __global__ __launch_bounds__(kPlanThreads) void k_sell_plan(const int64_t* __res
             atomicAdd(&s_nnz, (int)l);
         }
     }
-    for (int64_t k = sub; k < l; k += 4) {
-        const int32_t d = (int32_t)((int64_t)col[a + k] - (r0 + i));
-        uint32_t slot = offset_hash(d);
-        for (int probe = 0; probe < kPlanTab; ++probe) {
-            const int32_t prev = atomicCAS(&tab[slot], INT_MAX, d);
-            if (prev == INT_MAX) {
-                atomicAdd(&s_cnt, 1);
-                break;
+    // rows of a slice mostly share their offsets: each step the wavefront
+    // reduces its 64 offsets to one lane per distinct value, and a slot is
+    // read before the atomic is tried
+    int64_t lmax = l;
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t u = __shfl_xor(lmax, o);
+        lmax = u > lmax ? u : lmax;
+    }
+    for (int64_t k0 = 0; k0 < lmax; k0 += 4) {
+        const int64_t k = k0 + sub;
+        bool pending = k < l;
+        const int32_t d = (int32_t)((int64_t)col[pending ? a + k : 0] - (r0 + i));
+        for (;;) {
+            const uint64_t m = __ballot(pending);
+            if (m == 0) break;
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            const int32_t dl = __shfl(d, leader);
+            if (pending && d == dl) pending = false;
+            if ((t & 63) == leader) {
+                uint32_t slot = offset_hash(dl);
+                for (int probe = 0; probe < kPlanTab; ++probe) {
+                    const int32_t seen = tab[slot];
+                    if (seen == dl) break;
+                    if (seen == INT_MAX) {
+                        const int32_t prev = atomicCAS(&tab[slot], INT_MAX, dl);
+                        if (prev == INT_MAX) {
+                            atomicAdd(&s_cnt, 1);
+                            break;
+                        }
+                        if (prev == dl) break;
+                    }
+                    slot = (slot + 1) & (kPlanTab - 1);
+                    if (probe == kPlanTab - 1) s_over = 1;     // the set is full
+                }
             }
-            if (prev == d) break;
-            slot = (slot + 1) & (kPlanTab - 1);
-            if (probe == kPlanTab - 1) s_over = 1;     // the set is full
         }
     }
     __syncthreads();
@@ -125,12 +148,38 @@ __global__ __launch_bounds__(kPlanThreads) void k_sell_plan(const int64_t* __res
     if (t == 0) {
         slen[sl] = 64 * (int64_t)(fmt ? ndiag : mlen);
         sfmt[sl] = fmt;
-        if (fmt) {
-            atomicAdd(&acc[0], 1ull);
-            atomicAdd(&acc[1], (unsigned long long)ndiag);
-        } else {
-            atomicAdd(&acc[2], (unsigned long long)s_nnz);
-        }
+        cnnz[sl] = fmt ? 0 : s_nnz;
+    }
+}
+
+// acc[3] += {diagonal slices, their offsets, entries of column-form slices}:
+// a grid-stride sum per block, three atomics per block (one atomic per slice
+// on three addresses serialised into hundreds of microseconds)
+constexpr int kTotalsBlocks = 128;
+__global__ __launch_bounds__(256) void k_sell_totals(const int64_t* __restrict__ slen, const int32_t* __restrict__ sfmt,
+                                                     const int32_t* __restrict__ cnnz, int64_t ns,
+                                                     unsigned long long* __restrict__ acc) {
+    __shared__ unsigned long long s_a[3][256 / PR_WAVE];
+    unsigned long long a0 = 0, a1 = 0, a2 = 0;
+    for (int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; sl < ns; sl += (int64_t)gridDim.x * blockDim.x) {
+        const int f = sfmt[sl];
+        a0 += f ? 1ull : 0ull;
+        a1 += f ? (unsigned long long)(slen[sl] / 64) : 0ull;
+        a2 += f ? 0ull : (unsigned long long)cnnz[sl];
+    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    a2 = wave_sum(a2);
+    if ((threadIdx.x & (PR_WAVE - 1)) == 0) {
+        s_a[0][threadIdx.x / PR_WAVE] = a0;
+        s_a[1][threadIdx.x / PR_WAVE] = a1;
+        s_a[2][threadIdx.x / PR_WAVE] = a2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        unsigned long long u = 0;
+        for (int w = 0; w < 256 / PR_WAVE; ++w) u += s_a[threadIdx.x][w];
+        atomicAdd(&acc[threadIdx.x], u);
     }
 }
 
@@ -576,7 +625,11 @@ inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 void launch_sell_plan(const int64_t* rowptr, const int32_t* col, int64_t n, int64_t* slen, int32_t* sfmt,
                       int32_t* dtmp, unsigned long long* acc, hipStream_t s) {
     const int64_t ns = (n + 63) / 64;
-    k_sell_plan<<<(unsigned)(ns + 1), kPlanThreads, 0, s>>>(rowptr, col, n, slen, sfmt, dtmp, acc);
+    // per-slice entry counts of column-form slices in the tail of dtmp's space
+    int32_t* cnnz = dtmp + ns * kMaxDiag;
+    k_sell_plan<<<(unsigned)(ns + 1), kPlanThreads, 0, s>>>(rowptr, col, n, slen, sfmt, dtmp, cnnz);
+    const unsigned tb = nb(ns, 256);
+    k_sell_totals<<<tb < kTotalsBlocks ? tb : kTotalsBlocks, 256, 0, s>>>(slen, sfmt, cnnz, ns, acc);
 }
 
 void launch_sell_fill(const int64_t* rowptr, const int32_t* col, const double* val, int64_t n, const int64_t* soff,

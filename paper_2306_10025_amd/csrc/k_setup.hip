@@ -45,39 +45,68 @@ __global__ void k_validate_csr(const int64_t* __restrict__ rowptr, const int32_t
     if (bad) flags[0] = 1;
 }
 
-__global__ void k_validate_patches(const int64_t* __restrict__ ptr, const int32_t* __restrict__ dofs,
-                                   int64_t n_p, int64_t n, int64_t total, int32_t* flags,
-                                   int32_t* minmax) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k == 0 && (ptr[0] != 0 || ptr[n_p] != total)) flags[1] = 1;
-    if (k >= n_p) return;
-    int64_t s = ptr[k], e = ptr[k + 1];
-    if (s < 0 || e <= s || e > total) {
-        flags[1] = 1;
-        return;
-    }
-    int64_t p = e - s;
-    atomicMin(&minmax[0], (int32_t)(p > INT_MAX ? INT_MAX : p));
-    atomicMax(&minmax[1], (int32_t)(p > INT_MAX ? INT_MAX : p));
-    if (p > kMaxPs) {
-        flags[6] = 1;
-        return;
-    }
-    int32_t loc[kMaxPs];
-    for (int a = 0; a < p; ++a) {
-        int32_t g = dofs[s + a];
-        loc[a] = g;
-        if (g < 0 || g >= n) {
-            atomicMin(&flags[2], (int32_t)k);
-            return;
+// Grid-stride over the patches; a patch's dofs are loaded together (clamped
+// addresses), checked against [0, n) and pairwise for duplicates; the
+// smallest and largest patch size go out with one atomic per block.
+constexpr int kValidateBlocks = 1024;
+__global__ __launch_bounds__(256) void k_validate_patches(const int64_t* __restrict__ ptr,
+                                                          const int32_t* __restrict__ dofs, int64_t n_p,
+                                                          int64_t n, int64_t total, int32_t* flags,
+                                                          int32_t* minmax) {
+    __shared__ int32_t s_mn[256 / PR_WAVE], s_mx[256 / PR_WAVE];
+    const int64_t k0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k0 == 0 && (ptr[0] != 0 || ptr[n_p] != total)) flags[1] = 1;
+    int32_t mn = INT_MAX, mx = 0;
+    for (int64_t k = k0; k < n_p; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = ptr[k], e = ptr[k + 1];
+        if (s < 0 || e <= s || e > total) {
+            flags[1] = 1;
+            continue;
         }
+        const int64_t p = e - s;
+        const int32_t pc = (int32_t)(p > INT_MAX ? INT_MAX : p);
+        mn = pc < mn ? pc : mn;
+        mx = pc > mx ? pc : mx;
+        if (p > kMaxPs) {
+            flags[6] = 1;
+            continue;
+        }
+        int32_t loc[kMaxPs];
+#pragma unroll
+        for (int a = 0; a < kMaxPs; ++a) loc[a] = dofs[s + (a < p ? a : 0)];
+        bool bad = false, dup = false;
+#pragma unroll
+        for (int a = 0; a < kMaxPs; ++a)
+            if (a < p && (loc[a] < 0 || loc[a] >= n)) bad = true;
+        if (bad) {
+            atomicMin(&flags[2], (int32_t)k);
+            continue;
+        }
+#pragma unroll
+        for (int a = 0; a < kMaxPs; ++a)
+#pragma unroll
+            for (int b = a + 1; b < kMaxPs; ++b)
+                if (b < p && loc[a] == loc[b]) dup = true;
+        if (dup) atomicMin(&flags[3], (int32_t)k);
     }
-    for (int a = 0; a < p; ++a)
-        for (int b = a + 1; b < p; ++b)
-            if (loc[a] == loc[b]) {
-                atomicMin(&flags[3], (int32_t)k);
-                return;
-            }
+    for (int o = PR_WAVE >> 1; o > 0; o >>= 1) {
+        const int32_t a = __shfl_xor(mn, o), b = __shfl_xor(mx, o);
+        mn = a < mn ? a : mn;
+        mx = b > mx ? b : mx;
+    }
+    if ((threadIdx.x & (PR_WAVE - 1)) == 0) {
+        s_mn[threadIdx.x / PR_WAVE] = mn;
+        s_mx[threadIdx.x / PR_WAVE] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 256 / PR_WAVE; ++w) {
+            mn = s_mn[w] < mn ? s_mn[w] : mn;
+            mx = s_mx[w] > mx ? s_mx[w] : mx;
+        }
+        if (mn != INT_MAX) atomicMin(&minmax[0], mn);
+        atomicMax(&minmax[1], mx);
+    }
 }
 
 __global__ void k_cover(const int32_t* __restrict__ dofs, int64_t total, int32_t* cnt) {
@@ -434,8 +463,9 @@ void launch_validate_csr(const int64_t* rowptr, const int32_t* col, int64_t n, i
 
 void launch_validate_patches(const int64_t* ptr, const int32_t* dofs, int64_t n_p, int64_t n,
                              int64_t total, int32_t* flags, int32_t* minmax_ps, hipStream_t s) {
-    k_validate_patches<<<nblk(n_p > 0 ? n_p : 1, 256), 256, 0, s>>>(ptr, dofs, n_p, n, total, flags,
-                                                                  minmax_ps);
+    const unsigned b = nblk(n_p > 0 ? n_p : 1, 256);
+    k_validate_patches<<<b < kValidateBlocks ? b : kValidateBlocks, 256, 0, s>>>(ptr, dofs, n_p, n, total, flags,
+                                                                                minmax_ps);
 }
 
 void launch_cover(const int32_t* dofs, int64_t total, int32_t* cnt, hipStream_t s) {

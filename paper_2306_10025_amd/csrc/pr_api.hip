@@ -1165,7 +1165,7 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
         SETUP_TRY(dalloc(h, &sscr, scan_scratch_elems(ns + 1) + 2));
         SETUP_TRY(dalloc(h, &h->soff, ns + 1));
         SETUP_TRY(dalloc(h, &h->sfmt, ns));
-        SETUP_TRY(dalloc(h, &dtmp, (size_t)ns * kSellMaxDiag));
+        SETUP_TRY(dalloc(h, &dtmp, (size_t)ns * (kSellMaxDiag + 1)));
         SETUP_TRY(dalloc(h, &sacc, 3));
         SETUP_HIP(hipMemsetAsync(sacc, 0, 3 * sizeof(unsigned long long), s));
         launch_sell_plan(h->rowptr, h->col, h->n, slen, h->sfmt, dtmp, sacc, s);

@@ -486,9 +486,10 @@ void launch_gemv_small(const double* V, int64_t ldv, const int32_t* nvp, const d
 void launch_zero(double* x, int64_t n, hipStream_t s, const int32_t* stop = nullptr);
 int gs_blocks(int64_t n);
 // Plan of the hybrid copy: slen[ns + 1] (stored columns * 64 per slice, 0
-// at ns, for the exclusive scan), sfmt[ns], dtmp[ns * kSellMaxDiag] (the
-// offsets of diagonal-form slices), acc[3] += {diagonal slices, their
-// offsets, entries of column-form slices} (acc zeroed by the caller).
+// at ns, for the exclusive scan), sfmt[ns], dtmp[ns * (kSellMaxDiag + 1)]
+// (the offsets of diagonal-form slices, then one entry count per slice),
+// acc[3] += {diagonal slices, their offsets, entries of column-form slices}
+// (acc zeroed by the caller).
 void launch_sell_plan(const int64_t* rowptr, const int32_t* col, int64_t n, int64_t* slen, int32_t* sfmt,
                       int32_t* dtmp, unsigned long long* acc, hipStream_t s);
 // Fill after the scan of slen into soff: sval for every slice, scol for the
