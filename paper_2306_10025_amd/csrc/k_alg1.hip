@@ -150,13 +150,19 @@ __global__ __launch_bounds__(256) void k_a1_invert(const int32_t* ctl, const int
     }
 }
 
-// unresolved members of the components that opened an entry this round
+// unresolved members of the components that opened an entry this round,
+// with the indices the test needs ({patch, component, slot, entry patch}),
+// so the evaluation does not walk that chain of loads one candidate at a time
 __global__ void k_a1_filter(int64_t n_p, int32_t* ctl, const int32_t* __restrict__ status,
                             const int32_t* __restrict__ pos_comp, const int32_t* __restrict__ rep_slot,
-                            int32_t* __restrict__ cand) {
+                            const int32_t* __restrict__ mem, const int32_t* __restrict__ rep_patch,
+                            int32_t* __restrict__ cand, int4* __restrict__ cinfo) {
     if (ctl[2]) return;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool want = s < n_p && status[s] == 0 && rep_slot[pos_comp[s]] >= 0;
+    const int64_t sc = s < n_p ? s : n_p - 1;
+    const int32_t comp = pos_comp[sc];
+    const int32_t slot = rep_slot[comp];
+    const bool want = s < n_p && status[sc] == 0 && slot >= 0;
     const unsigned long long m = __ballot(want);
     if (m == 0) return;
     const int lane = threadIdx.x & (PR_WAVE - 1);
@@ -164,16 +170,19 @@ __global__ void k_a1_filter(int64_t n_p, int32_t* ctl, const int32_t* __restrict
     int base = 0;
     if (lane == leader) base = atomicAdd(&ctl[3], (int)__popcll(m));
     base = __shfl(base, leader);
-    if (want) cand[base + (int)__popcll(m & ((1ull << lane) - 1ull))] = (int32_t)s;
+    if (want) {
+        const int q = base + (int)__popcll(m & ((1ull << lane) - 1ull));
+        cand[q] = (int32_t)s;
+        cinfo[q] = make_int4(mem[s], comp, slot, rep_patch[slot]);
+    }
 }
 
-// one wavefront per candidate: test against its component's current entry
-__global__ __launch_bounds__(64) void k_a1_eval(const int32_t* ctl, int crit, double eps,
+// one wavefront per candidate: test against its component's current entry.
+// The three p x p work tiles are dynamic LDS of pm^2 doubles each (pm: the
+// largest patch size), so small patches leave room for more resident waves.
+__global__ __launch_bounds__(64) void k_a1_eval(const int32_t* ctl, int crit, double eps, int pm,
                                                 const int32_t* __restrict__ cand,
-                                                const int32_t* __restrict__ mem,
-                                                const int32_t* __restrict__ pos_comp,
-                                                const int32_t* __restrict__ rep_slot,
-                                                const int32_t* __restrict__ rep_patch,
+                                                const int4* __restrict__ cinfo,
                                                 const int64_t* __restrict__ ptr,
                                                 const double* __restrict__ tiles,
                                                 const int64_t* __restrict__ toff, int uniform_ps,
@@ -184,17 +193,16 @@ __global__ __launch_bounds__(64) void k_a1_eval(const int32_t* ctl, int crit, do
     if (ctl[2]) return;
     const int nc = ctl[3];
     if ((int)blockIdx.x >= nc) return;
-    __shared__ double sA[kMaxPs * kMaxPs];
-    __shared__ double sX[kMaxPs * kMaxPs];
-    __shared__ double sE[kMaxPs * kMaxPs];
+    extern __shared__ double s_dyn[];
+    double* sA = s_dyn;
+    double* sX = s_dyn + pm * pm;
+    double* sE = s_dyn + 2 * pm * pm;
     const int lane = threadIdx.x;
     unsigned long long nev = 0, nex = 0, nsq = 0;
     for (int q = blockIdx.x; q < nc; q += gridDim.x) {
         const int32_t s = cand[q];
-        const int32_t i = mem[s];
-        const int32_t comp = pos_comp[s];
-        const int32_t slot = rep_slot[comp];
-        const int32_t r = rep_patch[slot];
+        const int4 ci = cinfo[q];
+        const int32_t i = ci.x, comp = ci.y, slot = ci.z, r = ci.w;
         const int p = (int)(ptr[i + 1] - ptr[i]);
         const int pp = p * p;
         const double* Ai = tiles + (uniform_ps ? (int64_t)i * uniform_ps * uniform_ps : toff[i]);
@@ -346,6 +354,8 @@ void launch_a1_rounds(int rounds, const A1Dev& d, int crit, double eps, int max_
     const unsigned cb = nb(d.n_comp, 256);
     const unsigned fb = nb(d.n_p, 256);
     const unsigned eb = (unsigned)(d.n_p < 8192 ? d.n_p : 8192);
+    const int pm = max_ps > 0 && max_ps <= kMaxPs ? max_ps : kMaxPs;
+    const size_t lds = (size_t)3 * pm * pm * sizeof(double);
     for (int t = 0; t < rounds; ++t) {
         k_a1_begin<<<1, 1, 0, s>>>(d.ctl);
         k_a1_pick<<<cb, 256, 0, s>>>(d.n_comp, d.ctl, d.cstart, d.next, d.mem, d.status, d.rep_slot,
@@ -360,8 +370,9 @@ void launch_a1_rounds(int rounds, const A1Dev& d, int crit, double eps, int max_
             run_a1_invert<24, 32>(d.n_comp, d.ctl, d.active, d.rep_slot, d.rep_patch, d.ptr, d.tiles, d.toff, d.uniform_ps, d.dbt, d.stride, d.ctl + 5, s);
         else
             run_a1_invert<32, 32>(d.n_comp, d.ctl, d.active, d.rep_slot, d.rep_patch, d.ptr, d.tiles, d.toff, d.uniform_ps, d.dbt, d.stride, d.ctl + 5, s);
-        k_a1_filter<<<fb, 256, 0, s>>>(d.n_p, d.ctl, d.status, d.pos_comp, d.rep_slot, d.cand);
-        k_a1_eval<<<eb, 64, 0, s>>>(d.ctl, crit, eps, d.cand, d.mem, d.pos_comp, d.rep_slot, d.rep_patch,
+        k_a1_filter<<<fb, 256, 0, s>>>(d.n_p, d.ctl, d.status, d.pos_comp, d.rep_slot, d.mem, d.rep_patch, d.cand,
+                                       d.cinfo);
+        k_a1_eval<<<eb, 64, lds, s>>>(d.ctl, crit, eps, pm, d.cand, d.cinfo,
                                     d.ptr, d.tiles, d.toff, d.uniform_ps, d.dbt, d.stride, d.status,
                                     d.repof, d.next, d.counters);
     }

@@ -832,6 +832,8 @@ int alg1_core(pr_handle h, const int32_t* subset, int64_t ns, A1Run& R) {
     PR_TRY(dalloc(h, &R.repof, n_p));
     PR_TRY(dalloc(h, &active, n_comp));
     PR_TRY(dalloc(h, &cand, ns));
+    int4* cinfo = nullptr;
+    PR_TRY(dalloc(h, &cinfo, ns));
     PR_TRY(dalloc(h, &ctl, 8));
     PR_TRY(dalloc(h, &counters, 4));
     PR_TRY(dalloc(h, &R.dbt, (size_t)ns * stride));
@@ -854,6 +856,7 @@ int alg1_core(pr_handle h, const int32_t* subset, int64_t ns, A1Run& R) {
     d.repof = R.repof;
     d.active = active;
     d.cand = cand;
+    d.cinfo = cinfo;
     d.dbt = R.dbt;
     // 4. rounds, all components at once, until no component opens an entry
     int batch = 2;

@@ -330,6 +330,7 @@ struct A1Dev {
     int32_t* repof;           // int32[n_p] entry patch of each patch
     int32_t* active;          // int32[n_comp]
     int32_t* cand;            // int32[n_p]
+    int4* cinfo;              // per candidate {patch, component, slot, entry patch}
     double* dbt;              // inverses by slot, stride doubles each
     int64_t stride;
 };
