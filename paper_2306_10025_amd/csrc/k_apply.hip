@@ -73,9 +73,10 @@ __global__ __launch_bounds__(256) void k_apply_rows(int64_t count, ApplyGeom g, 
         const TX* X = db + (g.dboff ? g.dboff[j] : (int64_t)j * g.dbst);
         // FP64: loads unconditional from clamped (valid) addresses, the
         // unused values dropped afterwards (a load under a condition becomes
-        // a branch whose join waits for it).  FP32 keeps the guarded form,
-        // which measured twice as fast there (C4-sized uneven batch: 332
-        // against 708 us per application; FP64 461 against 515 us).
+        // a branch whose join waits for it).  FP32 keeps the guarded form for
+        // the dof and residual (it measured twice as fast there: C4-sized
+        // uneven batch, 332 against 708 us per application; FP64 461 against
+        // 515 us).
         const bool act = a < p;
         const int ac = act ? a : 0;
         int32_t gd;
@@ -90,8 +91,33 @@ __global__ __launch_bounds__(256) void k_apply_rows(int64_t count, ApplyGeom g, 
         }
         TX xr[MAXP];
         if constexpr (sizeof(TX) == 4) {
+            // the group's p x p inverse is contiguous: G lanes read it at
+            // consecutive addresses (clamped, coalesced) into LDS, then each
+            // lane takes its row from there.  The group lies inside one
+            // wavefront, whose LDS accesses complete in order; the fences
+            // keep the compiler from moving them across each other.
+            __shared__ TX s_x[(256 / G) * MAXP * MAXP];
+            TX* sx = s_x + (threadIdx.x / G) * (MAXP * MAXP);
+            const int pp = p * p;
+            constexpr int U = (MAXP * MAXP + G - 1) / G;
+            TX v[U];
 #pragma unroll
-            for (int b = 0; b < MAXP; ++b) xr[b] = (act && b < p) ? X[(int64_t)a * p + b] : (TX)0;
+            for (int u = 0; u < U; ++u) {
+                const int e = a + u * G;
+                v[u] = X[e < pp ? e : 0];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = a + u * G;
+                if (e < pp) sx[e] = v[u];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int b = 0; b < MAXP; ++b) xr[b] = (act && b < p) ? sx[ac * p + b] : (TX)0;
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         } else if ((p & 1) == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0) {
             // even p and an aligned matrix: rows start on 16-byte boundaries, load pairs
             const double2* X2 = reinterpret_cast<const double2*>(X + (int64_t)ac * p);
