@@ -90,10 +90,11 @@ __global__ __launch_bounds__(256) void k_apply_rows(int64_t count, ApplyGeom g, 
             rv = act ? (TA)rl : (TA)0;
         }
         TX xr[MAXP];
-        if constexpr (sizeof(TX) == 4) {
+        if constexpr (sizeof(TX) == 4 || MAXP <= 24) {
             // the group's p x p inverse is contiguous: G lanes read it at
             // consecutive addresses (clamped, coalesced) into LDS, then each
-            // lane takes its row from there.  The group lies inside one
+            // lane takes its row from there (FP64 only up to p = 24, where
+            // the LDS of a block stays at 36 KB).  The group lies inside one
             // wavefront, whose LDS accesses complete in order; the fences
             // keep the compiler from moving them across each other.
             __shared__ TX s_x[(256 / G) * MAXP * MAXP];
