@@ -619,6 +619,83 @@ void launch_group_sizes(const int32_t* order, int64_t n_p, const int64_t* ptr, i
     k_group_sizes<<<nblk(n_p + 1, 256), 256, 0, s>>>(order, n_p, ptr, sizes);
 }
 
+// ---- grouping and Algorithm 1 statistics on the device -----------------------
+namespace {
+
+// keys[k] = phi[k] << 32 | k and order[k] = k; bad[0] = 1 if some phi[k] lies
+// outside [0, m)
+__global__ void k_group_keys(const int32_t* __restrict__ phi, int64_t n_p, int64_t m, uint64_t* __restrict__ keys,
+                             int32_t* __restrict__ order, int32_t* __restrict__ bad) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_p) return;
+    const int32_t j = phi[k];
+    if (j < 0 || j >= m) bad[0] = 1;
+    keys[k] = ((uint64_t)(uint32_t)j << 32) | (uint32_t)k;
+    order[k] = (int32_t)k;
+}
+
+// estart[j] = first grouped position of entry j (gphi ascending); entries
+// without patches keep the -1 the caller filled in
+__global__ void k_entry_starts(const int32_t* __restrict__ gphi, int64_t n_p, int64_t m, int32_t* __restrict__ estart) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_p) return;
+    const int32_t j = gphi[s];
+    if (j < 0 || j >= m) return;        // reported through k_group_keys' flag
+    if (s == 0 || gphi[s - 1] != j) estart[j] = (int32_t)s;
+}
+
+// sizes[j] = size of patch reps[j]
+__global__ void k_rep_sizes(const int32_t* __restrict__ reps, const int64_t* __restrict__ ptr, int64_t m,
+                            int32_t* __restrict__ sizes) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < m) sizes[j] = (int32_t)(ptr[reps[j] + 1] - ptr[reps[j]]);
+}
+
+// out += sum over patches i of before[phi[i]] + (reps[phi[i]] != i): the
+// comparisons the sequential Algorithm 1 makes (grid-stride, one atomic per
+// block)
+__global__ __launch_bounds__(256) void k_naive_pairs(const int32_t* __restrict__ phi, const int32_t* __restrict__ reps,
+                                                     const int32_t* __restrict__ before, int64_t n_p, int64_t m,
+                                                     unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long s_a[256 / PR_WAVE];
+    unsigned long long a = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_p; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t j = phi[i];
+        if (j < 0 || j >= m) continue;      // the grouping step reports a map out of range
+        a += (unsigned long long)before[j] + (reps[j] == (int32_t)i ? 0ull : 1ull);
+    }
+    a = wave_sum(a);
+    if ((threadIdx.x & (PR_WAVE - 1)) == 0) s_a[threadIdx.x / PR_WAVE] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long u = 0;
+        for (int w = 0; w < 256 / PR_WAVE; ++w) u += s_a[w];
+        atomicAdd(out, u);
+    }
+}
+
+}  // namespace
+
+void launch_group_keys(const int32_t* phi, int64_t n_p, int64_t m, uint64_t* keys, int32_t* order, int32_t* bad,
+                       hipStream_t s) {
+    if (n_p > 0) k_group_keys<<<nblk(n_p, 256), 256, 0, s>>>(phi, n_p, m, keys, order, bad);
+}
+
+void launch_entry_starts(const int32_t* gphi, int64_t n_p, int64_t m, int32_t* estart, hipStream_t s) {
+    if (n_p > 0) k_entry_starts<<<nblk(n_p, 256), 256, 0, s>>>(gphi, n_p, m, estart);
+}
+
+void launch_rep_sizes(const int32_t* reps, const int64_t* ptr, int64_t m, int32_t* sizes, hipStream_t s) {
+    if (m > 0) k_rep_sizes<<<nblk(m, 256), 256, 0, s>>>(reps, ptr, m, sizes);
+}
+
+void launch_naive_pairs(const int32_t* phi, const int32_t* reps, const int32_t* before, int64_t n_p, int64_t m,
+                        unsigned long long* out, hipStream_t s) {
+    if (n_p <= 0) return;
+    const unsigned b = nblk(n_p, 256);
+    k_naive_pairs<<<b < 512 ? b : 512, 256, 0, s>>>(phi, reps, before, n_p, m, out);
+}
+
 void launch_group_gather(const int32_t* order, int64_t n_p, const int64_t* ptr, const int32_t* dofs,
                          const int64_t* goff, int pst, int32_t* gdofs, int32_t* gphi,
                          const int32_t* phi, hipStream_t s) {

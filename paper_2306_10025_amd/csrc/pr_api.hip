@@ -59,10 +59,14 @@ int run_alg1(pr_handle h) {
     launch_a1_copy_db(h->m_p, h->reps, R.slot_of_patch, h->pptr, R.dbt, h->db, stride, s);
     h->reps_host.resize(h->m_p);
     PR_HIP(h, hipMemcpyAsync(h->reps_host.data(), h->reps, h->m_p * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    std::vector<int64_t> pptr_host(n_p + 1);
-    PR_HIP(h, hipMemcpyAsync(pptr_host.data(), h->pptr, (n_p + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    std::vector<int32_t> phi_h(n_p);
-    PR_HIP(h, hipMemcpyAsync(phi_h.data(), h->phi, n_p * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    // sizes of the entries' patches
+    std::vector<int32_t> rsz(h->m_p, h->max_ps);
+    int32_t* dsz = nullptr;
+    PR_TRY(dalloc(h, &dsz, h->m_p));
+    if (!h->uniform) {
+        launch_rep_sizes(h->reps, h->pptr, h->m_p, dsz, s);
+        PR_HIP(h, hipMemcpyAsync(rsz.data(), dsz, h->m_p * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    }
     PR_HIP(h, hipStreamSynchronize(s));
     h->stats.crit_evals = (int64_t)R.cnt[0];
     h->stats.crit_exact = (int64_t)R.cnt[1];
@@ -70,27 +74,27 @@ int run_alg1(pr_handle h) {
     h->stats.alg1_rounds = R.rounds;
     // pairs the sequential algorithm compares: patch i against the entries of
     // its size up to its own (excluded for an entry's patch); the rest were
-    // skipped by the certified bound
+    // skipped by the certified bound.  The per-patch sum runs on the device.
     {
-        std::vector<int64_t> before(h->m_p);       // earlier entries of the same size
-        std::vector<int64_t> seen(33, 0);
-        for (int64_t j = 0; j < h->m_p; ++j) {
-            const int r = h->reps_host[j];
-            const int p = (int)(pptr_host[r + 1] - pptr_host[r]);
-            before[j] = seen[p]++;
-        }
-        int64_t naive = 0;
-        for (int64_t i = 0; i < n_p; ++i) {
-            const int j = phi_h[i];
-            naive += before[j] + (h->reps_host[j] == (int32_t)i ? 0 : 1);
-        }
-        h->stats.crit_pruned = naive - h->stats.crit_evals;
+        std::vector<int32_t> before(h->m_p);       // earlier entries of the same size
+        std::vector<int32_t> seen(33, 0);
+        for (int64_t j = 0; j < h->m_p; ++j) before[j] = seen[rsz[j]]++;
+        int32_t* dbefore = nullptr;
+        unsigned long long* dnaive = nullptr;
+        PR_TRY(dalloc(h, &dbefore, h->m_p));
+        PR_TRY(dalloc(h, &dnaive, 1));
+        PR_HIP(h, hipMemcpyAsync(dbefore, before.data(), h->m_p * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        PR_HIP(h, hipMemsetAsync(dnaive, 0, sizeof(unsigned long long), s));
+        launch_naive_pairs(h->phi, h->reps, dbefore, n_p, h->m_p, dnaive, s);
+        unsigned long long naive = 0;
+        PR_HIP(h, hipMemcpyAsync(&naive, dnaive, sizeof(naive), hipMemcpyDeviceToHost, s));
+        PR_HIP(h, hipStreamSynchronize(s));
+        h->stats.crit_pruned = (int64_t)naive - h->stats.crit_evals;
     }
     h->dbps_host.resize(h->m_p);
     h->dboff_host.resize(h->m_p + 1);
     for (int64_t j = 0; j < h->m_p; ++j) {
-        const int32_t r = h->reps_host[j];
-        h->dbps_host[j] = (int32_t)(pptr_host[r + 1] - pptr_host[r]);
+        h->dbps_host[j] = rsz[j];
         h->dboff_host[j] = j * stride;
     }
     h->dboff_host[h->m_p] = h->m_p * stride;
@@ -428,20 +432,12 @@ int run_group(pr_handle h) {
     PR_TRY(dalloc(h, &kscr, N));
     PR_TRY(dalloc(h, &vscr, N));
     PR_TRY(dalloc(h, &h->order, n_p));
-    std::vector<int32_t> phi_h(n_p);
-    PR_HIP(h, hipMemcpyAsync(phi_h.data(), h->phi, n_p * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    PR_HIP(h, hipStreamSynchronize(s));
-    // entry sizes for the work items (host, O(n_p) integer work)
-    std::vector<int64_t> count(m_p, 0);
-    for (int64_t k = 0; k < n_p; ++k) {
-        if (phi_h[k] < 0 || phi_h[k] >= m_p)
-            return pr_fail(h, PR_ERR_INVALID_ARG, "internal: patch map out of range");
-        count[phi_h[k]]++;
-    }
-    std::vector<uint64_t> keys_h(n_p);
-    for (int64_t k = 0; k < n_p; ++k) keys_h[k] = ((uint64_t)(uint32_t)phi_h[k] << 32) | (uint32_t)k;
-    PR_HIP(h, hipMemcpyAsync(keys, keys_h.data(), n_p * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-    launch_iota(h->order, n_p, s);
+    int32_t* gbad = nullptr;
+    int32_t* estart = nullptr;
+    PR_TRY(dalloc(h, &gbad, 1));
+    PR_TRY(dalloc(h, &estart, m_p + 1));
+    PR_HIP(h, hipMemsetAsync(gbad, 0, sizeof(int32_t), s));
+    launch_group_keys(h->phi, n_p, m_p, keys, h->order, gbad, s);
     launch_sort_pairs(keys, h->order, n_p, kscr, vscr, s);
     // grouped copy of the dof lists and the entry of each grouped position
     PR_TRY(dalloc(h, &h->gdofs, h->total_dofs));
@@ -457,6 +453,22 @@ int run_group(pr_handle h) {
     }
     launch_group_gather(h->order, n_p, h->pptr, h->pdofs, h->goff, h->uniform ? h->max_ps : 0, h->gdofs,
                         h->gphi, h->phi, s);
+    // entry sizes for the work items: first grouped position of each entry
+    std::vector<int64_t> count(m_p, 0);
+    {
+        PR_HIP(h, hipMemsetAsync(estart, 0xFF, (m_p + 1) * sizeof(int32_t), s));   // -1: no patch
+        launch_entry_starts(h->gphi, n_p, m_p, estart, s);
+        std::vector<int32_t> st(m_p + 1);
+        int32_t bad = 0;
+        PR_HIP(h, hipMemcpyAsync(st.data(), estart, m_p * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        PR_HIP(h, hipMemcpyAsync(&bad, gbad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        PR_HIP(h, hipStreamSynchronize(s));
+        if (bad) return pr_fail(h, PR_ERR_INVALID_ARG, "internal: patch map out of range");
+        st[m_p] = (int32_t)n_p;
+        for (int64_t j = m_p - 1; j >= 0; --j)
+            if (st[j] < 0) st[j] = st[j + 1];
+        for (int64_t j = 0; j < m_p; ++j) count[j] = st[j + 1] - st[j];
+    }
     if (h->prm.deterministic) {
         // dof -> grouped slots, ascending (fixed summation order)
         int64_t* cnt64 = nullptr;

@@ -475,6 +475,17 @@ void launch_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, hipStream_t s
 // *out = max(*out, max_i a[i]) (caller initialises *out)
 void launch_max_i32(const int32_t* a, int64_t n, int32_t* out, hipStream_t s);
 // ell[i*C + u] = u-th slot of dof i, -1 past its count (C >= every count)
+// grouping on the device: keys = phi << 32 | id with order = iota (bad[0] = 1
+// for a phi outside [0, m)); estart[gphi[s]] = s at each new entry of the
+// sorted gphi (entries without patches keep what was there)
+void launch_group_keys(const int32_t* phi, int64_t n_p, int64_t m, uint64_t* keys, int32_t* order, int32_t* bad,
+                       hipStream_t s);
+void launch_entry_starts(const int32_t* gphi, int64_t n_p, int64_t m, int32_t* estart, hipStream_t s);
+// sizes[j] = size of patch reps[j]
+void launch_rep_sizes(const int32_t* reps, const int64_t* ptr, int64_t m, int32_t* sizes, hipStream_t s);
+// *out += sum_i before[phi[i]] + (reps[phi[i]] != i)
+void launch_naive_pairs(const int32_t* phi, const int32_t* reps, const int32_t* before, int64_t n_p, int64_t m,
+                        unsigned long long* out, hipStream_t s);
 void launch_build_ell(int64_t n, const int64_t* dof_ptr, const int32_t* dof_slots, int C, int32_t* ell,
                       hipStream_t s);
 
