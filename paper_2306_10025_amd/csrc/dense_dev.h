@@ -37,43 +37,50 @@ __device__ __forceinline__ int gj_invert(const double* __restrict__ A, double* _
     bool used = !act;
     int mycol = -1;
     int info = 0;
+    // The pivot steps stay a loop (unrolled, the 32-row form was about 8,000
+    // straight-line instructions, and one wavefront running it once per call
+    // waited on instruction fetch).  Column k of this row is carried in ak:
+    // step k picks column k + 1 out of the updated row with selects, so the
+    // row stays in registers without dynamic indexing.
+    double ak = a[0];
+#pragma unroll 1
+    for (int k = 0; k < p; ++k) {
+        double cv = used ? -1.0 : fabs(ak);
+        int ci = r;
 #pragma unroll
-    for (int k = 0; k < MAXP; ++k) {
-        if (k < p) {
-            double cv = used ? -1.0 : fabs(a[k]);
-            int ci = r;
+        for (int o = G / 2; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(cv, o, G);
+            const int oi = __shfl_xor(ci, o, G);
+            if (ov > cv || (ov == cv && oi < ci)) {
+                cv = ov;
+                ci = oi;
+            }
+        }
+        const int piv = ci;
+        if (!(cv > 0.0) && info == 0) info = k + 1;
+        const double pk = __shfl(ak, piv, G);
+        const double inv = 1.0 / pk;
+        const double f = (r == piv) ? 0.0 : ak * inv;
+        double next = 0.0;
 #pragma unroll
-            for (int o = G / 2; o > 0; o >>= 1) {
-                const double ov = __shfl_xor(cv, o, G);
-                const int oi = __shfl_xor(ci, o, G);
-                if (ov > cv || (ov == cv && oi < ci)) {
-                    cv = ov;
-                    ci = oi;
+        for (int c = 0; c < MAXP; ++c) {
+            if (c < p) {
+                const double pa = __shfl(a[c], piv, G);
+                const double px = __shfl(x[c], piv, G);
+                if (r == piv) {
+                    a[c] = pa * inv;
+                    x[c] = px * inv;
+                } else {
+                    a[c] = fma(-f, pa, a[c]);
+                    x[c] = fma(-f, px, x[c]);
                 }
             }
-            const int piv = ci;
-            if (!(cv > 0.0) && info == 0) info = k + 1;
-            const double pk = __shfl(a[k], piv, G);
-            const double inv = 1.0 / pk;
-            const double f = (r == piv) ? 0.0 : a[k] * inv;
-#pragma unroll
-            for (int c = 0; c < MAXP; ++c) {
-                if (c < p) {
-                    const double pa = __shfl(a[c], piv, G);
-                    const double px = __shfl(x[c], piv, G);
-                    if (r == piv) {
-                        a[c] = pa * inv;
-                        x[c] = px * inv;
-                    } else {
-                        a[c] = fma(-f, pa, a[c]);
-                        x[c] = fma(-f, px, x[c]);
-                    }
-                }
-            }
-            if (r == piv) {
-                used = true;
-                mycol = k;
-            }
+            next = (c == k + 1) ? a[c] : next;
+        }
+        ak = next;
+        if (r == piv) {
+            used = true;
+            mycol = k;
         }
     }
     if (act && mycol >= 0) {
