@@ -388,7 +388,8 @@ def main():
         "setup_detail": {k: (round(st[k], 5) if isinstance(st[k], float) else int(st[k]))
                          for k in ("t_validate", "t_extract", "t_database", "t_factor", "t_group",
                                    "t_autotune", "t_mlp_train", "crit_evals", "crit_pruned",
-                                   "crit_refined", "crit_exact", "mlp_accepted", "mlp_fallback")},
+                                   "crit_refined", "crit_exact", "mlp_accepted", "mlp_fallback",
+                                   "alg1_rounds", "alg1_batch_inverted")},
         "apply_gdofs": round(P.n / (cls["apply"]["avg_us"] * 1e-6) / 1e9, 3) if cls["apply"]["avg_us"] else None,
         "kernel_ms_per_step": {k: round(cls[k]["total_ms"], 3) for k in ("apply", "spmv", "orth")},
         "dominant_by_time": dom,

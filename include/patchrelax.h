@@ -207,6 +207,9 @@ typedef struct {
     int64_t sell_diag_slices;    /* slices in diagonal form */
     int64_t sell_diag_offsets;   /* their distinct offsets (stored columns) */
     int64_t sell_col_entries;    /* matrix entries in column-form slices */
+    int64_t alg1_batch_inverted; /* 1: Algorithm 1 ran more than 62 rounds, and then inverted
+                                    its unresolved patches in one batch instead of one new
+                                    entry per round (same inverses, bit for bit) */
 } pr_stats;
 
 /* ---- entry points ------------------------------------------------------ */

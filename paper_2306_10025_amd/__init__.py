@@ -88,7 +88,8 @@ class pr_stats(Structure):
                 ("tune_threads", c_int32), ("tune_slot", c_int32), ("tune_cap", c_int64),
                 ("t_autotune", c_double), ("tune_tiles_per_wave", c_int64),
                 ("tune_xcd_remap", c_int64), ("crit_refined", c_int64), ("sell_slots", c_int64),
-                ("sell_diag_slices", c_int64), ("sell_diag_offsets", c_int64), ("sell_col_entries", c_int64)]
+                ("sell_diag_slices", c_int64), ("sell_diag_offsets", c_int64), ("sell_col_entries", c_int64),
+                ("alg1_batch_inverted", c_int64)]
 
 
 _SIGS = {
@@ -339,6 +340,13 @@ def pr_set_memory_cache_limit(nbytes):
     return _check(lib().pr_set_memory_cache_limit(int(nbytes)))
 
 
+def pr_set_stream(h, stream):
+    """Moves the handle to `stream` (a torch stream or a raw hipStream_t);
+    work already queued on the old stream finishes first."""
+    raw = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    return _check(lib().pr_set_stream(h, c_void_p(raw)), h)
+
+
 def pr_release_cached_memory():
     return _check(lib().pr_release_cached_memory())
 
@@ -401,6 +409,9 @@ class PatchRelax:
 
     def apply(self, r, z):
         return pr_apply(self.h, r, z)
+
+    def set_stream(self, stream):
+        return pr_set_stream(self.h, stream)
 
     def solve(self, b, x, tol=1e-8):
         return pr_solve(self.h, b, x, tol)

@@ -16,6 +16,11 @@
 //   round: the lowest unresolved member of each component becomes an entry;
 //          it is inverted; every unresolved member is tested against it and
 //          resolved on a match.
+// When the rounds run long (one large component adds about one entry per
+// round), every still unresolved patch is inverted in one batched launch and
+// later rounds copy the new entry's inverse from that batch: the same
+// elimination on the same tile, so the same bits, without a latency-bound
+// single-matrix inversion per round.
 // A member is thus compared with its component's entries in append order
 // until the first match, as in the sequential algorithm.  Entries are
 // finally numbered in ascending patch id (the append order).
@@ -106,7 +111,8 @@ __global__ void k_a1_pick(int64_t n_comp, int32_t* ctl, const int32_t* __restric
                           int32_t* __restrict__ next, const int32_t* __restrict__ mem,
                           int32_t* __restrict__ status, int32_t* __restrict__ rep_slot,
                           int32_t* __restrict__ rep_patch, int32_t* __restrict__ slot_of_patch,
-                          int32_t* __restrict__ repof, int32_t* __restrict__ active) {
+                          int32_t* __restrict__ repof, int32_t* __restrict__ active,
+                          int32_t* __restrict__ rep_pos) {
     if (ctl[2]) return;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_comp) return;
@@ -116,6 +122,7 @@ __global__ void k_a1_pick(int64_t n_comp, int32_t* ctl, const int32_t* __restric
         const int32_t pid = mem[s];
         const int32_t slot = atomicAdd(&ctl[0], 1);
         rep_slot[c] = slot;
+        rep_pos[c] = s;
         rep_patch[slot] = pid;
         slot_of_patch[pid] = slot;
         repof[pid] = pid;
@@ -147,6 +154,52 @@ __global__ __launch_bounds__(256) void k_a1_invert(const int32_t* ctl, const int
         const double* A = tiles + (uniform_ps ? (int64_t)pid * uniform_ps * uniform_ps : toff[pid]);
         const int inf = gj_invert<MAXP, G>(A, dbt + (int64_t)slot * stride, p, r);
         if (r == 0 && inf != 0) atomicCAS(sing, 0, pid + 1);
+    }
+}
+
+// batched inversion of every unresolved position s (status 0) into
+// inv + s * stride, with its zero-pivot report in info[s]
+template <int MAXP, int G>
+__global__ __launch_bounds__(256) void k_a1_preinvert(int64_t n_p, const int32_t* __restrict__ status,
+                                                      const int32_t* __restrict__ mem,
+                                                      const int64_t* __restrict__ ptr,
+                                                      const double* __restrict__ tiles,
+                                                      const int64_t* __restrict__ toff, int uniform_ps,
+                                                      double* __restrict__ inv, int64_t stride,
+                                                      int32_t* __restrict__ info) {
+    const int64_t gsz = 256 / G;
+    const int r = threadIdx.x % G;
+    for (int64_t s = (int64_t)blockIdx.x * gsz + threadIdx.x / G; s < n_p; s += (int64_t)gridDim.x * gsz) {
+        if (status[s] != 0) continue;          // same s for the whole group
+        const int32_t pid = mem[s];
+        const int p = (int)(ptr[pid + 1] - ptr[pid]);
+        const double* A = tiles + (uniform_ps ? (int64_t)pid * uniform_ps * uniform_ps : toff[pid]);
+        const int inf = gj_invert<MAXP, G>(A, inv + s * stride, p, r);
+        if (r == 0) info[s] = inf;
+    }
+}
+
+// a round after the batched inversion: one wavefront per new entry copies
+// its p x p inverse to the entry's slot
+__global__ __launch_bounds__(64) void k_a1_take(const int32_t* ctl, const int32_t* __restrict__ active,
+                                                const int32_t* __restrict__ rep_slot,
+                                                const int32_t* __restrict__ rep_pos,
+                                                const int32_t* __restrict__ mem,
+                                                const int64_t* __restrict__ ptr,
+                                                const double* __restrict__ inv,
+                                                const int32_t* __restrict__ info, double* __restrict__ dbt,
+                                                int64_t stride, int32_t* sing) {
+    if (ctl[2]) return;
+    const int na = ctl[1];
+    for (int64_t g = blockIdx.x; g < na; g += gridDim.x) {
+        const int32_t c = active[g];
+        const int32_t s = rep_pos[c];
+        const int32_t pid = mem[s];
+        const int p = (int)(ptr[pid + 1] - ptr[pid]);
+        const double* src = inv + (int64_t)s * stride;
+        double* dst = dbt + (int64_t)rep_slot[c] * stride;
+        for (int e = threadIdx.x; e < p * p; e += 64) dst[e] = src[e];
+        if (threadIdx.x == 0 && info[s] != 0) atomicCAS(sing, 0, pid + 1);
     }
 }
 
@@ -320,6 +373,15 @@ void run_a1_invert(int64_t n_comp, const int32_t* ctl, const int32_t* active, co
                                                          toff, uniform_ps, dbt, stride, sing);
 }
 
+template <int MAXP, int G>
+void run_a1_preinvert(const A1Dev& d, hipStream_t s) {
+    const int per = 256 / G;
+    int64_t blocks = (d.n_p + per - 1) / per;
+    if (blocks > 65536) blocks = 65536;
+    k_a1_preinvert<MAXP, G><<<(unsigned)blocks, 256, 0, s>>>(d.n_p, d.status, d.mem, d.ptr, d.tiles, d.toff,
+                                                            d.uniform_ps, d.inv, d.stride, d.inv_info);
+}
+
 }  // namespace
 
 void launch_a1_keys(int64_t n_p, const int32_t* subset, const int64_t* ptr, const double* keynorm,
@@ -350,6 +412,17 @@ void launch_a1_cstart(int64_t n_p, int64_t n_comp, const uint64_t* key2, int32_t
     k_a1_cstart<<<nb(n_p, 256), 256, 0, s>>>(n_p, n_comp, key2, pos_comp, cstart, next);
 }
 
+// The template choice is the one the rounds use, so that an inverse is the
+// same whether it was taken in a round or in the batch.
+void launch_a1_preinvert(const A1Dev& d, int max_ps, hipStream_t s) {
+    if (d.n_p <= 0 || !d.inv || !d.inv_info) return;
+    if (max_ps <= 4) run_a1_preinvert<4, 4>(d, s);
+    else if (max_ps <= 12) run_a1_preinvert<12, 16>(d, s);
+    else if (max_ps <= 16) run_a1_preinvert<16, 16>(d, s);
+    else if (max_ps <= 24) run_a1_preinvert<24, 32>(d, s);
+    else run_a1_preinvert<32, 32>(d, s);
+}
+
 void launch_a1_rounds(int rounds, const A1Dev& d, int crit, double eps, int max_ps, hipStream_t s) {
     const unsigned cb = nb(d.n_comp, 256);
     const unsigned fb = nb(d.n_p, 256);
@@ -359,8 +432,11 @@ void launch_a1_rounds(int rounds, const A1Dev& d, int crit, double eps, int max_
     for (int t = 0; t < rounds; ++t) {
         k_a1_begin<<<1, 1, 0, s>>>(d.ctl);
         k_a1_pick<<<cb, 256, 0, s>>>(d.n_comp, d.ctl, d.cstart, d.next, d.mem, d.status, d.rep_slot,
-                                     d.rep_patch, d.slot_of_patch, d.repof, d.active);
-        if (max_ps <= 4)
+                                     d.rep_patch, d.slot_of_patch, d.repof, d.active, d.rep_pos);
+        if (d.inv)
+            k_a1_take<<<(unsigned)(d.n_comp < 4096 ? d.n_comp : 4096), 64, 0, s>>>(
+                d.ctl, d.active, d.rep_slot, d.rep_pos, d.mem, d.ptr, d.inv, d.inv_info, d.dbt, d.stride, d.ctl + 5);
+        else if (max_ps <= 4)
             run_a1_invert<4, 4>(d.n_comp, d.ctl, d.active, d.rep_slot, d.rep_patch, d.ptr, d.tiles, d.toff, d.uniform_ps, d.dbt, d.stride, d.ctl + 5, s);
         else if (max_ps <= 12)
             run_a1_invert<12, 16>(d.n_comp, d.ctl, d.active, d.rep_slot, d.rep_patch, d.ptr, d.tiles, d.toff, d.uniform_ps, d.dbt, d.stride, d.ctl + 5, s);

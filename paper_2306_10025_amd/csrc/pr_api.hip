@@ -846,6 +846,8 @@ int alg1_core(pr_handle h, const int32_t* subset, int64_t ns, A1Run& R) {
     PR_TRY(dalloc(h, &cand, ns));
     int4* cinfo = nullptr;
     PR_TRY(dalloc(h, &cinfo, ns));
+    int32_t* rep_pos = nullptr;
+    PR_TRY(dalloc(h, &rep_pos, n_comp));
     PR_TRY(dalloc(h, &ctl, 8));
     PR_TRY(dalloc(h, &counters, 4));
     PR_TRY(dalloc(h, &R.dbt, (size_t)ns * stride));
@@ -870,17 +872,41 @@ int alg1_core(pr_handle h, const int32_t* subset, int64_t ns, A1Run& R) {
     d.cand = cand;
     d.cinfo = cinfo;
     d.dbt = R.dbt;
-    // 4. rounds, all components at once, until no component opens an entry
+    d.rep_pos = rep_pos;
+    d.inv = nullptr;
+    d.inv_info = nullptr;
+    // 4. rounds, all components at once, until no component opens an entry.
+    // Once they run long (about one entry per round in a large component),
+    // the unresolved patches are inverted in one batch and later rounds copy
+    // from it (skipped when that much memory is not free).
     int batch = 2;
+    int64_t started = 0;
     int32_t c8[8];
     for (;;) {
         launch_a1_rounds(batch, d, crit, h->prm.eps, h->max_ps, s);
+        started += batch;
         PR_HIP(h, hipMemcpyAsync(c8, ctl, sizeof(c8), hipMemcpyDeviceToHost, s));
         PR_HIP(h, hipStreamSynchronize(s));
         if (c8[2]) break;
+        if (!d.inv && started >= kA1BatchInvertAfter) {
+            const size_t need = (size_t)ns * stride * sizeof(double);
+            size_t free_b = 0, total_b = 0;
+            if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b / 2 > need) {
+                PR_TRY(dalloc(h, &d.inv, (size_t)ns * stride));
+                PR_TRY(dalloc(h, &d.inv_info, ns));
+                launch_a1_preinvert(d, h->max_ps, s);
+                h->stats.alg1_batch_inverted = 1;
+            } else {
+                (void)hipGetLastError();
+            }
+        }
         if (batch < 64) batch *= 2;
     }
     PR_HIP(h, hipGetLastError());
+    if (d.inv) {
+        dfree(h, d.inv);       // the stream was synchronised above
+        dfree(h, d.inv_info);
+    }
     if (c8[5] != 0)
         return pr_fail(h, PR_ERR_SINGULAR_PATCH, "zero pivot in database patch " + std::to_string(c8[5] - 1));
     R.m = c8[0];

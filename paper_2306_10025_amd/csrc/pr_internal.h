@@ -248,6 +248,22 @@ int dalloc(pr_handle h, T** p, size_t count) {
     return PR_OK;
 }
 
+// returns an owned allocation to the cache before pr_destroy; every stream
+// that used it must have been synchronised
+template <typename T>
+void dfree(pr_handle h, T* p) {
+    for (size_t k = 0; k < h->owned.size(); ++k)
+        if (h->owned[k].p == (void*)p) {
+            pool_release(h->device, h->owned[k].p, h->owned[k].bytes);
+            h->owned.erase(h->owned.begin() + (std::ptrdiff_t)k);
+            return;
+        }
+}
+
+// Algorithm 1 rounds after which the unresolved patches are inverted in one
+// batch (2 + 4 + 8 + 16 + 32 rounds have run by then)
+constexpr int64_t kA1BatchInvertAfter = 62;
+
 inline int64_t next_pow2(int64_t n) {
     int64_t N = 1024;
     while (N < n) N <<= 1;
@@ -333,6 +349,9 @@ struct A1Dev {
     int4* cinfo;              // per candidate {patch, component, slot, entry patch}
     double* dbt;              // inverses by slot, stride doubles each
     int64_t stride;
+    int32_t* rep_pos;         // int32[n_comp] sorted position of the current entry
+    double* inv;              // null, or inverses by sorted position after the batched inversion
+    int32_t* inv_info;        // int32[n_p] zero-pivot report of each batched inverse
 };
 void launch_a1_keys(int64_t n_p, const int32_t* subset, const int64_t* ptr, const double* keynorm,
                     uint64_t* keys, int32_t* vals, hipStream_t s);
@@ -348,6 +367,9 @@ void launch_a1_key2(int64_t n_p, const int64_t* flag, const int64_t* excl, const
 void launch_a1_cstart(int64_t n_p, int64_t n_comp, const uint64_t* key2, int32_t* pos_comp,
                       int32_t* cstart, int32_t* next, hipStream_t s);
 void launch_a1_rounds(int rounds, const A1Dev& d, int crit, double eps, int max_ps, hipStream_t s);
+// inverts every unresolved patch into d.inv (by sorted position); later
+// rounds copy from there instead of inverting
+void launch_a1_preinvert(const A1Dev& d, int max_ps, hipStream_t s);
 void launch_a1_finish(int64_t n_p, const int32_t* repof, int64_t* flags, int64_t* rank, int64_t* scr,
                       int32_t* phi, int32_t* reps, hipStream_t s);
 void launch_a1_copy_db(int64_t m_p, const int32_t* reps, const int32_t* slot_of_patch, const int64_t* ptr,

@@ -156,6 +156,9 @@ ALG1_CASES = {
     "q2hex_const_4_fro": (lambda: gen.q2_hex_diffusion(4, sigma=0.0), "fro", 1e-7),
     "q2hex_4_spec_loose": (lambda: gen.q2_hex_diffusion(4), "spectral", 0.5),
     "batch_5_spec": (lambda: gen.uneven_stokes_batch(n_sys=5, nmin=2, nmax=6), "spectral", 1e-8),
+    # one component of 216 distinct patches: 216 rounds, so the unresolved
+    # patches are inverted in one batch after the first 62
+    "q2hex_6_spec_long": (lambda: gen.q2_hex_diffusion(6), "spectral", 0.5),
 }
 
 
@@ -191,6 +194,32 @@ def test_alg1_assignment_bit_exact(case):
     st = h.stats()
     assert st["m_p"] == len(reps_o)
     h.close()
+
+
+def test_alg1_batched_inverses_match_the_oracle():
+    # after the batched inversion every round copies its entry's inverse from
+    # the batch: each entry's inverse must be that of its own tile
+    P = gen.q2_hex_diffusion(6)
+    h = pr.PatchRelax(P.A, P.ptr, P.dofs, algo="tolerance", eps=0.5)
+    st = h.stats()
+    say("long alg1", st["alg1_rounds"], st["m_p"], st["alg1_batch_inverted"])
+    assert st["alg1_rounds"] > 62 and st["alg1_batch_inverted"] == 1
+    phi, reps = h.assignment()
+    tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
+    for j, k in enumerate(reps):
+        B = tiles[k]
+        p = B.shape[0]
+        assert np.array_equal(pr.pr_get_entry_matrix(h.h, j, p), B)
+        Xg = pr.pr_get_rep_inverse(h.h, j, p)
+        Xo = O.factor_inverse(B)
+        tol = 8 * p * np.linalg.cond(B) * 2.2e-16
+        assert np.abs(Xg - Xo).max() <= tol * np.abs(Xo).max(), j
+    # a short run does not take the batch
+    Q = gen.nedelec_hex(6)
+    h2 = pr.PatchRelax(Q.A, Q.ptr, Q.dofs, algo="tolerance", eps=1e-8)
+    assert h2.stats()["alg1_batch_inverted"] == 0
+    h.close()
+    h2.close()
 
 
 def test_alg1_pruning_is_certified_and_counts():
