@@ -113,30 +113,120 @@ __device__ __forceinline__ void lds_load(double* dst, const double* __restrict__
     }
 }
 
-// E = I - A X into sE; returns ||E||_F^2 (wave-reduced).
-__device__ __forceinline__ double form_E(const double* sA, const double* sX, double* sE, int p,
-                                         int lane) {
-    double fro2 = 0.0;
-    for (int e = lane; e < p * p; e += PR_WAVE) {
-        const int a = e / p, b = e % p;
-        double acc = 0.0;
-        for (int c = 0; c < p; ++c) acc = fma(sA[a * p + c], sX[c * p + b], acc);
-        const double v = (a == b ? 1.0 : 0.0) - acc;
-        sE[e] = v;
-        fro2 += v * v;
+typedef double pr_d4 __attribute__((ext_vector_type(4)));
+
+// P = L R for p x p row-major matrices in LDS (p <= 32) on the FP64 matrix
+// cores, 16 x 16 x 4 products accumulated over k in steps of 4; one
+// wavefront with every lane active.  TL: L is read transposed (P = L^T R).
+// Tile (ti, tj) of P (rows 16 ti.., columns 16 tj..) ends in c[2 ti + tj]
+// (only c[0] when p <= 16): lane l holds rows l / 16 + 4 v, v = 0..3, of
+// column l % 16 (the FP64 form interleaves the rows, unlike the 16 x 16 FP32
+// products, whose lanes hold four consecutive rows).  Operand lanes: A element (row l % 16, k l / 16), B element
+// (k l / 16, column l % 16).  Padding rows, columns and k are zero (loads
+// from clamped, valid addresses times a 0/1 mask, so no load waits in a
+// branch).
+template <bool TL>
+__device__ __forceinline__ void mm_wave(const double* sL, const double* sR, int p, int lane, pr_d4 c[4]) {
+    const bool two = p > 16;
+    const int li = lane & 15, lk = lane >> 4;
+    const int i0 = li < p ? li : 0;
+    const int i1 = 16 + li < p ? 16 + li : 0;
+    const double m0 = li < p ? 1.0 : 0.0;
+    const double m1 = 16 + li < p ? 1.0 : 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) c[t] = pr_d4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < p; k0 += 4) {
+        const int k = k0 + lk;
+        const int kc = k < p ? k : 0;
+        const double mk = k < p ? 1.0 : 0.0;
+        const double a0 = (TL ? sL[kc * p + i0] : sL[i0 * p + kc]) * (mk * m0);
+        const double b0 = sR[kc * p + i0] * (mk * m0);
+        c[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, c[0], 0, 0, 0);
+        if (two) {
+            const double a1 = (TL ? sL[kc * p + i1] : sL[i1 * p + kc]) * (mk * m1);
+            const double b1 = sR[kc * p + i1] * (mk * m1);
+            c[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, c[1], 0, 0, 0);
+            c[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, c[2], 0, 0, 0);
+            c[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, c[3], 0, 0, 0);
+        }
     }
-    return wave_sum(fro2);
 }
 
-// Largest column 2-norm of E squared (a lower bound on sigma_max^2).
-__device__ __forceinline__ double max_col2(const double* sE, int p, int lane) {
-    double m = 0.0;
-    if (lane < p) {
-        double s = 0.0;
-        for (int a = 0; a < p; ++a) s += sE[a * p + lane] * sE[a * p + lane];
-        m = s;
+// row and column of element v of tile t held by this lane (layout above)
+__device__ __forceinline__ int mm_row(int t, int v, int lane) { return 16 * (t >> 1) + (lane >> 4) + 4 * v; }
+__device__ __forceinline__ int mm_col(int t, int lane) { return 16 * (t & 1) + (lane & 15); }
+
+// dst = scale * P for the tiles of mm_wave
+__device__ __forceinline__ void mm_store(const pr_d4 c[4], double* dst, int p, int lane, double scale) {
+    const int nt = p > 16 ? 4 : 1;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (t >= nt) break;
+        const int col = mm_col(t, lane);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = mm_row(t, v, lane);
+            if (row < p && col < p) dst[row * p + col] = scale * c[t][v];
+        }
     }
-    return wave_max(m);
+}
+
+// sum (wave-reduced) and largest value of the diagonal of P
+__device__ __forceinline__ void mm_diag(const pr_d4 c[4], int p, int lane, double& sum, double& mx) {
+    const int nt = p > 16 ? 4 : 1;
+    double s = 0.0, m = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (t >= nt) break;
+        const int col = mm_col(t, lane);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = mm_row(t, v, lane);
+            if (row == col && row < p) {
+                s += c[t][v];
+                m = fmax(m, c[t][v]);
+            }
+        }
+    }
+    sum = wave_sum(s);
+    mx = wave_max(m);
+}
+
+// E = I - A X into sE; returns ||E||_F^2 (wave-reduced) and, when lb2 is
+// not null, the largest squared column norm of E (a lower bound on
+// sigma_max(E)^2).  One wavefront, every lane active.
+__device__ __forceinline__ double form_E(const double* sA, const double* sX, double* sE, int p, int lane,
+                                         double* lb2 = nullptr) {
+    pr_d4 c[4];
+    mm_wave<false>(sA, sX, p, lane, c);
+    const int nt = p > 16 ? 4 : 1;
+    double fro2 = 0.0, cs0 = 0.0, cs1 = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (t >= nt) break;
+        const int col = mm_col(t, lane);
+        double cs = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = mm_row(t, v, lane);
+            if (row < p && col < p) {
+                const double e = (row == col ? 1.0 : 0.0) - c[t][v];
+                sE[row * p + col] = e;
+                cs += e * e;
+            }
+        }
+        fro2 += cs;
+        if (t & 1) cs1 += cs; else cs0 += cs;
+    }
+    if (lb2) {
+        // lanes l, l ^ 16, l ^ 32, l ^ 48 hold the rows of the same columns
+        cs0 += __shfl_xor(cs0, 16);
+        cs0 += __shfl_xor(cs0, 32);
+        cs1 += __shfl_xor(cs1, 16);
+        cs1 += __shfl_xor(cs1, 32);
+        *lb2 = wave_max(fmax(cs0, cs1));
+    }
+    return wave_sum(fro2);
 }
 
 // Bracket [lo2, hi2] of lambda = sigma_max(E)^2 tightened by repeated
@@ -155,41 +245,33 @@ __device__ __forceinline__ double max_col2(const double* sE, int p, int lane) {
 template <class Done>
 __device__ bool sigma2_bracket(const double* sE, double* sG, double* sH, int p, int lane, int kmax,
                                double& lo2, double& hi2, Done done) {
-    for (int e = lane; e < p * p; e += PR_WAVE) {
-        const int a = e / p, b = e % p;
-        double acc = 0.0;
-        for (int c = 0; c < p; ++c) acc = fma(sE[c * p + a], sE[c * p + b], acc);
-        sG[e] = acc;
-    }
-    __syncthreads();
-    const double tr = wave_sum(lane < p ? sG[lane * p + lane] : 0.0);
+    pr_d4 c[4];
+    mm_wave<true>(sE, sE, p, lane, c);
+    double tr, dmax;
+    mm_diag(c, p, lane, tr, dmax);
     if (!(tr > 0.0)) {
         lo2 = hi2 = 0.0;
         return false;
     }
     hi2 = fmin(hi2, tr);
-    lo2 = fmax(lo2, wave_max(lane < p ? sG[lane * p + lane] : 0.0));
+    lo2 = fmax(lo2, dmax);
     if (done(lo2, hi2)) return true;
     const double itr = 1.0 / tr;
-    for (int e = lane; e < p * p; e += PR_WAVE) sG[e] *= itr;
+    __syncthreads();                        // sG may be an operand buffer still being read
+    mm_store(c, sG, p, lane, itr);
     __syncthreads();
     double U = log(tr), w = 0.5;
     double* cur = sG;
     double* nxt = sH;
     for (int k = 1; k <= kmax; ++k) {
-        for (int e = lane; e < p * p; e += PR_WAVE) {
-            const int a = e / p, b = e % p;
-            double acc = 0.0;
-            for (int c = 0; c < p; ++c) acc = fma(cur[c * p + a], cur[c * p + b], acc);   // N symmetric
-            nxt[e] = acc;
-        }
-        __syncthreads();
-        const double t = wave_sum(lane < p ? nxt[lane * p + lane] : 0.0);   // in [1/p, 1]
+        mm_wave<true>(cur, cur, p, lane, c);   // N^T N = N^2, N symmetric
+        double t, md;
+        mm_diag(c, p, lane, t, md);           // t in [1/p, 1]
         const double it = 1.0 / t;
-        for (int e = lane; e < p * p; e += PR_WAVE) nxt[e] *= it;
+        md *= it;
+        mm_store(c, nxt, p, lane, it);
         __syncthreads();
         U += w * log(t);
-        const double md = wave_max(lane < p ? nxt[lane * p + lane] : 0.0);
         hi2 = fmin(hi2, exp(U));
         lo2 = fmax(lo2, exp(U + w * log(md)));
         w *= 0.5;
@@ -204,11 +286,11 @@ __device__ bool sigma2_bracket(const double* sE, double* sG, double* sH, int p, 
 // sigma_max(E)^2 as the largest eigenvalue of G = E^T E by cyclic Jacobi
 // rotations; sG is overwritten.  Requires a one-wave block (uses barriers).
 __device__ inline double sigma_max2_jacobi(const double* sE, double* sG, int p, int lane) {
-    for (int e = lane; e < p * p; e += PR_WAVE) {
-        const int a = e / p, b = e % p;
-        double acc = 0.0;
-        for (int c = 0; c < p; ++c) acc = fma(sE[c * p + a], sE[c * p + b], acc);
-        sG[e] = acc;
+    {
+        pr_d4 c[4];
+        mm_wave<true>(sE, sE, p, lane, c);
+        __syncthreads();                    // sG may be an operand buffer still being read
+        mm_store(c, sG, p, lane, 1.0);
     }
     __syncthreads();
     for (int sweep = 0; sweep < 40; ++sweep) {

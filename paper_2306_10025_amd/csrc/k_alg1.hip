@@ -268,9 +268,9 @@ __global__ __launch_bounds__(64) void k_a1_eval(const int32_t* ctl, int crit, do
         bool match;
         ++nev;
         if (crit == PR_CRIT_SPECTRAL) {
-            const double fro2 = form_E(sA, sX, sE, p, lane);
+            double lb2;
+            const double fro2 = form_E(sA, sX, sE, p, lane, &lb2);
             __syncthreads();
-            const double lb2 = max_col2(sE, p, lane);
             const double e2 = eps * eps;
             // decided when the bracket clears eps^2 by a rounding margin
             auto decided = [e2](double lo, double hi) {

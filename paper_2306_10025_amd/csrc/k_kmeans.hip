@@ -75,9 +75,9 @@ __global__ __launch_bounds__(64) void k_km_assign(int64_t n_p, const int64_t* __
                 const double* X = cen + (int64_t)j * stride;
                 lds_load(sX, X, pp, lane);
                 __syncthreads();
-                const double fro2 = form_E(sA, sX, sE, p, lane);
+                double lb2;
+                const double fro2 = form_E(sA, sX, sE, p, lane, &lb2);
                 __syncthreads();
-                const double lb2 = max_col2(sE, p, lane);
                 if (lane == 0) lb[j - j0] = sqrt(lb2);
                 ubmin = fmin(ubmin, sqrt(fro2));
                 __syncthreads();
@@ -97,9 +97,10 @@ __global__ __launch_bounds__(64) void k_km_assign(int64_t n_p, const int64_t* __
                     const double* X = cen + (int64_t)j * stride;
                     lds_load(sX, X, pp, lane);
                     __syncthreads();
-                    const double fro2 = form_E(sA, sX, sE, p, lane);
+                    double lo2;
+                    const double fro2 = form_E(sA, sX, sE, p, lane, &lo2);
                     __syncthreads();
-                    double lo2 = max_col2(sE, p, lane), hi2 = fro2;
+                    double hi2 = fro2;
                     const double cut = thr;
                     // stop once this candidate is out of the current band
                     auto out = [cut](double lo, double) { return sqrt(lo) * (1.0 - 1e-12) > cut; };

@@ -318,9 +318,9 @@ __device__ bool pair_matches(int crit, double eps, const double* sA, double* sX,
     if (crit == PR_CRIT_SPECTRAL) {
         lds_load(sX, Xr, pp, lane);
         __syncthreads();
-        const double fro2 = form_E(sA, sX, sE, p, lane);
+        double lb2;
+        const double fro2 = form_E(sA, sX, sE, p, lane, &lb2);
         __syncthreads();
-        const double lb2 = max_col2(sE, p, lane);
         const double e2 = eps * eps;
         auto decided = [e2](double lo, double hi) {
             return hi * (1.0 + 1e-11) < e2 || lo * (1.0 - 1e-11) >= e2;
