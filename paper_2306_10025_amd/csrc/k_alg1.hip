@@ -230,6 +230,51 @@ __global__ void k_a1_filter(int64_t n_p, int32_t* ctl, const int32_t* __restrict
     }
 }
 
+// One test d(A, B) < eps, wavefront-wide, with sA holding the patch tile and
+// sX the entry (its inverse for the spectral criterion, else its tile),
+// both loaded and synchronised.  The spectral value is bracketed by the
+// column-norm bound and the Frobenius norm, then narrowed by repeated
+// squaring, and only an undecided pair takes the exact singular value; a
+// decision counts only when it clears eps^2 by a rounding margin.  sE is
+// scratch; the bracket and the exact value also use sA and sX as scratch
+// and then set clobbered.
+__device__ bool a1_match(int crit, double eps, double* sA, double* sX, double* sE, int p, int lane,
+                         unsigned long long& nex, unsigned long long& nsq, bool& clobbered) {
+    if (crit == PR_CRIT_SPECTRAL) {
+        double lb2;
+        const double fro2 = form_E(sA, sX, sE, p, lane, &lb2);
+        __syncthreads();
+        const double e2 = eps * eps;
+        auto decided = [e2](double lo, double hi) {
+            return hi * (1.0 + 1e-11) < e2 || lo * (1.0 - 1e-11) >= e2;
+        };
+        double lo = lb2, hi = fro2;   // largest column norm^2 <= sigma_max^2 <= ||E||_F^2
+        if (!decided(lo, hi)) {
+            __syncthreads();
+            sigma2_bracket(sE, sA, sX, p, lane, kSquarings, lo, hi, decided);
+            ++nsq;
+            clobbered = true;
+        }
+        if (decided(lo, hi)) return hi * (1.0 + 1e-11) < e2;
+        __syncthreads();
+        ++nex;
+        clobbered = true;
+        return sqrt(sigma_max2_jacobi(sE, sA, p, lane)) < eps;
+    }
+    double acc = 0.0;
+    for (int e = lane; e < p * p; e += PR_WAVE) {
+        const double v = sA[e] - sX[e];
+        acc += (crit == PR_CRIT_L1) ? fabs(v) : v * v;
+    }
+    acc = wave_sum(acc);
+    return ((crit == PR_CRIT_L1) ? acc : sqrt(acc)) < eps;
+}
+
+__device__ __forceinline__ const double* a1_tile(const double* tiles, const int64_t* toff, int uniform_ps,
+                                                 int32_t i) {
+    return tiles + (uniform_ps ? (int64_t)i * uniform_ps * uniform_ps : toff[i]);
+}
+
 // one wavefront per candidate: test against its component's current entry.
 // The three p x p work tiles are dynamic LDS of pm^2 doubles each (pm: the
 // largest patch size), so small patches leave room for more resident waves.
@@ -258,50 +303,250 @@ __global__ __launch_bounds__(64) void k_a1_eval(const int32_t* ctl, int crit, do
         const int32_t i = ci.x, comp = ci.y, slot = ci.z, r = ci.w;
         const int p = (int)(ptr[i + 1] - ptr[i]);
         const int pp = p * p;
-        const double* Ai = tiles + (uniform_ps ? (int64_t)i * uniform_ps * uniform_ps : toff[i]);
-        const double* Br = (crit == PR_CRIT_SPECTRAL)
-                               ? dbt + (int64_t)slot * stride
-                               : tiles + (uniform_ps ? (int64_t)r * uniform_ps * uniform_ps : toff[r]);
-        lds_load(sA, Ai, pp, lane);
+        const double* Br = (crit == PR_CRIT_SPECTRAL) ? dbt + (int64_t)slot * stride
+                                                      : a1_tile(tiles, toff, uniform_ps, r);
+        lds_load(sA, a1_tile(tiles, toff, uniform_ps, i), pp, lane);
         lds_load(sX, Br, pp, lane);
         __syncthreads();
-        bool match;
         ++nev;
-        if (crit == PR_CRIT_SPECTRAL) {
-            double lb2;
-            const double fro2 = form_E(sA, sX, sE, p, lane, &lb2);
-            __syncthreads();
-            const double e2 = eps * eps;
-            // decided when the bracket clears eps^2 by a rounding margin
-            auto decided = [e2](double lo, double hi) {
-                return hi * (1.0 + 1e-11) < e2 || lo * (1.0 - 1e-11) >= e2;
-            };
-            double lo = lb2, hi = fro2;   // largest column norm^2 <= sigma_max^2 <= ||E||_F^2
-            if (!decided(lo, hi)) {
-                __syncthreads();
-                sigma2_bracket(sE, sA, sX, p, lane, kSquarings, lo, hi, decided);
-                ++nsq;
-            }
-            if (decided(lo, hi)) {
-                match = hi * (1.0 + 1e-11) < e2;
-            } else {
-                __syncthreads();
-                match = sqrt(sigma_max2_jacobi(sE, sA, p, lane)) < eps;
-                ++nex;
-            }
-        } else {
-            double acc = 0.0;
-            for (int e = lane; e < pp; e += PR_WAVE) {
-                const double v = sA[e] - sX[e];
-                acc += (crit == PR_CRIT_L1) ? fabs(v) : v * v;
-            }
-            acc = wave_sum(acc);
-            match = ((crit == PR_CRIT_L1) ? acc : sqrt(acc)) < eps;
-        }
+        bool clob = false;
+        const bool match = a1_match(crit, eps, sA, sX, sE, p, lane, nex, nsq, clob);
         if (lane == 0) {
             if (match) {
                 status[s] = 1;
                 repof[i] = r;
+            } else {
+                atomicMin(&next[comp], s);
+            }
+        }
+        __syncthreads();
+    }
+    if (lane == 0) {
+        atomicAdd(&counters[0], nev);
+        if (nex) atomicAdd(&counters[1], nex);
+        if (nsq) atomicAdd(&counters[3], nsq);
+    }
+}
+
+// ---- rounds of up to kA1Spec entries (after the batched inversion) ---------
+// The kA1Spec lowest unresolved members u_0 < u_1 < ... of a component are
+// taken together.  u_0 is the next entry for sure; u_j is an entry exactly
+// when no entry among u_0..u_{j-1} matches it, and otherwise belongs to the
+// first that does (every earlier entry of the component was already tested
+// against it).  All pairs (u_i, u_j), i < j, are tested in parallel, one
+// thread settles the chain in order, and the remaining members are then
+// tested against the round's entries in append order, up to the first
+// match: the sequential algorithm's result, in about kA1Spec times fewer
+// rounds.  Only the tests the sequential algorithm makes are counted as
+// evaluations (the pair tests past a member's first match are not).
+
+// the speculative members of each component (positions in order), scanned
+// from its lowest unresolved position over at most kA1SpecWindow positions
+__global__ void k_a1s_pick(int64_t n_comp, int32_t* ctl, const int32_t* __restrict__ cstart,
+                           int32_t* __restrict__ next, const int32_t* __restrict__ status,
+                           int32_t* __restrict__ spec, int32_t* __restrict__ spec_n,
+                           int32_t* __restrict__ pairm, int32_t* __restrict__ rep_slot,
+                           int32_t* __restrict__ active) {
+    if (ctl[2]) return;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_comp) return;
+    rep_slot[c] = -1;
+    const int32_t s0 = next[c], end = cstart[c + 1];
+    const int32_t lim = (end - s0 > kA1SpecWindow) ? s0 + kA1SpecWindow : end;
+    int n = 0;
+    for (int32_t s = s0; s < lim && n < kA1Spec; ++s) {
+        if (status[s] == 0) {
+            spec[c * kA1Spec + n] = s;
+            pairm[c * kA1Spec + n] = 0;
+            ++n;
+        }
+    }
+    spec_n[c] = n;
+    if (n > 0) {
+        active[atomicAdd(&ctl[1], 1)] = (int32_t)c;
+        next[c] = end;      // lowered by the evaluation to the next unresolved member
+    }
+}
+
+// all pairs (u_i, u_j), i < j, of the active components: bit i of
+// pairm[c][j] is set when u_i's entry test matches u_j
+__global__ __launch_bounds__(64) void k_a1s_pairs(const int32_t* ctl, int crit, double eps, int pm,
+                                                  const int32_t* __restrict__ active,
+                                                  const int32_t* __restrict__ spec,
+                                                  const int32_t* __restrict__ spec_n,
+                                                  const int32_t* __restrict__ mem,
+                                                  const int64_t* __restrict__ ptr,
+                                                  const double* __restrict__ tiles,
+                                                  const int64_t* __restrict__ toff, int uniform_ps,
+                                                  const double* __restrict__ inv, int64_t stride,
+                                                  int32_t* __restrict__ pairm,
+                                                  unsigned long long* __restrict__ counters) {
+    if (ctl[2]) return;
+    constexpr int NP = kA1Spec * (kA1Spec - 1) / 2;
+    const int64_t work = (int64_t)ctl[1] * NP;
+    extern __shared__ double s_dyn[];
+    double* sA = s_dyn;
+    double* sX = s_dyn + pm * pm;
+    double* sE = s_dyn + 2 * pm * pm;
+    const int lane = threadIdx.x;
+    unsigned long long nex = 0, nsq = 0;
+    for (int64_t w = blockIdx.x; w < work; w += gridDim.x) {
+        const int32_t c = active[w / NP];
+        int pr = (int)(w % NP), j = 1;
+        while (pr >= j) {        // pairs in the order (0,1), (0,2), (1,2), (0,3), ...
+            pr -= j;
+            ++j;
+        }
+        const int i = pr;
+        if (j >= spec_n[c]) continue;
+        const int32_t ui = spec[c * kA1Spec + i], uj = spec[c * kA1Spec + j];
+        const int32_t pj = mem[uj];
+        const int p = (int)(ptr[pj + 1] - ptr[pj]);
+        const double* Br = (crit == PR_CRIT_SPECTRAL) ? inv + (int64_t)ui * stride
+                                                      : a1_tile(tiles, toff, uniform_ps, mem[ui]);
+        lds_load(sA, a1_tile(tiles, toff, uniform_ps, pj), p * p, lane);
+        lds_load(sX, Br, p * p, lane);
+        __syncthreads();
+        bool clob = false;
+        const bool match = a1_match(crit, eps, sA, sX, sE, p, lane, nex, nsq, clob);
+        if (lane == 0 && match) atomicOr(&pairm[c * kA1Spec + j], 1 << i);
+        __syncthreads();
+    }
+    if (lane == 0) {
+        if (nex) atomicAdd(&counters[1], nex);
+        if (nsq) atomicAdd(&counters[3], nsq);
+    }
+}
+
+// one thread per active component settles its speculative members in order
+__global__ void k_a1s_resolve(int32_t* ctl, const int32_t* __restrict__ active,
+                              const int32_t* __restrict__ spec, const int32_t* __restrict__ spec_n,
+                              const int32_t* __restrict__ pairm, const int32_t* __restrict__ mem,
+                              const int32_t* __restrict__ inv_info,
+                              int32_t* __restrict__ status, int32_t* __restrict__ repof,
+                              int32_t* __restrict__ rep_slot, int32_t* __restrict__ rep_patch,
+                              int32_t* __restrict__ slot_of_patch, int32_t* __restrict__ ent,
+                              int32_t* __restrict__ ent_n, int32_t* __restrict__ ent_slot,
+                              unsigned long long* __restrict__ counters) {
+    if (ctl[2]) return;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ctl[1]) return;
+    const int32_t c = active[g];
+    const int n = spec_n[c];
+    unsigned emask = 0;          // bit j: u_j is an entry
+    int m = 0;
+    unsigned long long nev = 0;
+    for (int j = 0; j < n; ++j) {
+        const int32_t u = spec[c * kA1Spec + j];
+        const int32_t pid = mem[u];
+        const unsigned bits = (unsigned)pairm[c * kA1Spec + j];
+        int hit = -1;
+        for (int e = 0; e < j; ++e) {
+            if (!((emask >> e) & 1u)) continue;
+            ++nev;
+            if ((bits >> e) & 1u) {
+                hit = e;
+                break;
+            }
+        }
+        status[u] = 1;
+        if (hit >= 0) {
+            repof[pid] = mem[spec[c * kA1Spec + hit]];
+        } else {
+            const int32_t slot = atomicAdd(&ctl[0], 1);
+            rep_patch[slot] = pid;
+            slot_of_patch[pid] = slot;
+            repof[pid] = pid;
+            ent[c * kA1Spec + m] = u;
+            ent_slot[c * kA1Spec + m] = slot;
+            ++m;
+            emask |= 1u << j;
+            if (inv_info[u] != 0) atomicCAS(&ctl[5], 0, pid + 1);
+        }
+    }
+    ent_n[c] = m;
+    rep_slot[c] = ent_slot[c * kA1Spec];      // m >= 1: u_0 is always an entry
+    if (nev) atomicAdd(&counters[0], nev);
+}
+
+// the round's entries' inverses, copied from the batch to their slots
+__global__ __launch_bounds__(64) void k_a1s_take(const int32_t* ctl, const int32_t* __restrict__ active,
+                                                 const int32_t* __restrict__ ent,
+                                                 const int32_t* __restrict__ ent_n,
+                                                 const int32_t* __restrict__ ent_slot,
+                                                 const int32_t* __restrict__ mem,
+                                                 const int64_t* __restrict__ ptr,
+                                                 const double* __restrict__ inv, double* __restrict__ dbt,
+                                                 int64_t stride) {
+    if (ctl[2]) return;
+    const int64_t work = (int64_t)ctl[1] * kA1Spec;
+    for (int64_t w = blockIdx.x; w < work; w += gridDim.x) {
+        const int32_t c = active[w / kA1Spec];
+        const int m = (int)(w % kA1Spec);
+        if (m >= ent_n[c]) continue;
+        const int32_t u = ent[c * kA1Spec + m];
+        const int32_t pid = mem[u];
+        const int p = (int)(ptr[pid + 1] - ptr[pid]);
+        const double* src = inv + (int64_t)u * stride;
+        double* dst = dbt + (int64_t)ent_slot[c * kA1Spec + m] * stride;
+        for (int e = threadIdx.x; e < p * p; e += 64) dst[e] = src[e];
+    }
+}
+
+// one wavefront per remaining member: tested against the round's entries of
+// its component in append order, up to the first match
+__global__ __launch_bounds__(64) void k_a1s_eval(const int32_t* ctl, int crit, double eps, int pm,
+                                                 const int32_t* __restrict__ cand,
+                                                 const int4* __restrict__ cinfo,
+                                                 const int64_t* __restrict__ ptr,
+                                                 const double* __restrict__ tiles,
+                                                 const int64_t* __restrict__ toff, int uniform_ps,
+                                                 const double* __restrict__ inv, int64_t stride,
+                                                 const int32_t* __restrict__ ent,
+                                                 const int32_t* __restrict__ ent_n,
+                                                 const int32_t* __restrict__ mem,
+                                                 int32_t* __restrict__ status, int32_t* __restrict__ repof,
+                                                 int32_t* __restrict__ next,
+                                                 unsigned long long* __restrict__ counters) {
+    if (ctl[2]) return;
+    const int nc = ctl[3];
+    if ((int)blockIdx.x >= nc) return;
+    extern __shared__ double s_dyn[];
+    double* sA = s_dyn;
+    double* sX = s_dyn + pm * pm;
+    double* sE = s_dyn + 2 * pm * pm;
+    const int lane = threadIdx.x;
+    unsigned long long nev = 0, nex = 0, nsq = 0;
+    for (int q = blockIdx.x; q < nc; q += gridDim.x) {
+        const int32_t s = cand[q];
+        const int4 ci = cinfo[q];
+        const int32_t i = ci.x, comp = ci.y;
+        const int p = (int)(ptr[i + 1] - ptr[i]);
+        const int pp = p * p;
+        const double* Ai = a1_tile(tiles, toff, uniform_ps, i);
+        const int n = ent_n[comp];
+        int32_t hit = -1;
+        bool clob = true;
+        for (int m = 0; m < n; ++m) {
+            const int32_t u = ent[comp * kA1Spec + m];
+            const double* Br = (crit == PR_CRIT_SPECTRAL) ? inv + (int64_t)u * stride
+                                                          : a1_tile(tiles, toff, uniform_ps, mem[u]);
+            if (clob) lds_load(sA, Ai, pp, lane);
+            lds_load(sX, Br, pp, lane);
+            __syncthreads();
+            ++nev;
+            clob = false;
+            const bool match = a1_match(crit, eps, sA, sX, sE, p, lane, nex, nsq, clob);
+            __syncthreads();
+            if (match) {
+                hit = mem[u];
+                break;
+            }
+        }
+        if (lane == 0) {
+            if (hit >= 0) {
+                status[s] = 1;
+                repof[i] = hit;
             } else {
                 atomicMin(&next[comp], s);
             }
@@ -451,6 +696,34 @@ void launch_a1_rounds(int rounds, const A1Dev& d, int crit, double eps, int max_
         k_a1_eval<<<eb, 64, lds, s>>>(d.ctl, crit, eps, pm, d.cand, d.cinfo,
                                     d.ptr, d.tiles, d.toff, d.uniform_ps, d.dbt, d.stride, d.status,
                                     d.repof, d.next, d.counters);
+    }
+}
+
+void launch_a1_spec_rounds(int rounds, const A1Dev& d, int crit, double eps, int max_ps, hipStream_t s) {
+    const unsigned cb = nb(d.n_comp, 256);
+    const unsigned fb = nb(d.n_p, 256);
+    const unsigned eb = (unsigned)(d.n_p < 8192 ? d.n_p : 8192);
+    constexpr int64_t NP = kA1Spec * (kA1Spec - 1) / 2;
+    const unsigned pb = (unsigned)(d.n_comp * NP < 8192 ? d.n_comp * NP : 8192);
+    const unsigned tb = (unsigned)(d.n_comp * kA1Spec < 4096 ? d.n_comp * kA1Spec : 4096);
+    const int pm = max_ps > 0 && max_ps <= kMaxPs ? max_ps : kMaxPs;
+    const size_t lds = (size_t)3 * pm * pm * sizeof(double);
+    for (int t = 0; t < rounds; ++t) {
+        k_a1_begin<<<1, 1, 0, s>>>(d.ctl);
+        k_a1s_pick<<<cb, 256, 0, s>>>(d.n_comp, d.ctl, d.cstart, d.next, d.status, d.spec, d.spec_n, d.pairm,
+                                      d.rep_slot, d.active);
+        k_a1s_pairs<<<pb, 64, lds, s>>>(d.ctl, crit, eps, pm, d.active, d.spec, d.spec_n, d.mem, d.ptr, d.tiles,
+                                        d.toff, d.uniform_ps, d.inv, d.stride, d.pairm, d.counters);
+        k_a1s_resolve<<<cb, 256, 0, s>>>(d.ctl, d.active, d.spec, d.spec_n, d.pairm, d.mem, d.inv_info,
+                                         d.status, d.repof, d.rep_slot, d.rep_patch, d.slot_of_patch, d.ent,
+                                         d.ent_n, d.ent_slot, d.counters);
+        k_a1s_take<<<tb, 64, 0, s>>>(d.ctl, d.active, d.ent, d.ent_n, d.ent_slot, d.mem, d.ptr, d.inv, d.dbt,
+                                     d.stride);
+        k_a1_filter<<<fb, 256, 0, s>>>(d.n_p, d.ctl, d.status, d.pos_comp, d.rep_slot, d.mem, d.rep_patch, d.cand,
+                                       d.cinfo);
+        k_a1s_eval<<<eb, 64, lds, s>>>(d.ctl, crit, eps, pm, d.cand, d.cinfo, d.ptr, d.tiles, d.toff,
+                                       d.uniform_ps, d.inv, d.stride, d.ent, d.ent_n, d.mem, d.status, d.repof,
+                                       d.next, d.counters);
     }
 }
 

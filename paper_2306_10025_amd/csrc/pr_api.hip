@@ -875,15 +875,18 @@ int alg1_core(pr_handle h, const int32_t* subset, int64_t ns, A1Run& R) {
     d.rep_pos = rep_pos;
     d.inv = nullptr;
     d.inv_info = nullptr;
+    d.spec = d.spec_n = d.pairm = d.ent = d.ent_n = d.ent_slot = nullptr;
     // 4. rounds, all components at once, until no component opens an entry.
     // Once they run long (about one entry per round in a large component),
-    // the unresolved patches are inverted in one batch and later rounds copy
-    // from it (skipped when that much memory is not free).
+    // the unresolved patches are inverted in one batch and later rounds open
+    // up to kA1Spec entries per component, with the inverses taken from the
+    // batch (skipped when that much memory is not free).
     int batch = 2;
     int64_t started = 0;
     int32_t c8[8];
     for (;;) {
-        launch_a1_rounds(batch, d, crit, h->prm.eps, h->max_ps, s);
+        if (d.inv) launch_a1_spec_rounds(batch, d, crit, h->prm.eps, h->max_ps, s);
+        else launch_a1_rounds(batch, d, crit, h->prm.eps, h->max_ps, s);
         started += batch;
         PR_HIP(h, hipMemcpyAsync(c8, ctl, sizeof(c8), hipMemcpyDeviceToHost, s));
         PR_HIP(h, hipStreamSynchronize(s));
@@ -894,6 +897,13 @@ int alg1_core(pr_handle h, const int32_t* subset, int64_t ns, A1Run& R) {
             if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b / 2 > need) {
                 PR_TRY(dalloc(h, &d.inv, (size_t)ns * stride));
                 PR_TRY(dalloc(h, &d.inv_info, ns));
+                const size_t nk = (size_t)n_comp * kA1Spec;
+                PR_TRY(dalloc(h, &d.spec, nk));
+                PR_TRY(dalloc(h, &d.spec_n, n_comp));
+                PR_TRY(dalloc(h, &d.pairm, nk));
+                PR_TRY(dalloc(h, &d.ent, nk));
+                PR_TRY(dalloc(h, &d.ent_n, n_comp));
+                PR_TRY(dalloc(h, &d.ent_slot, nk));
                 launch_a1_preinvert(d, h->max_ps, s);
                 h->stats.alg1_batch_inverted = 1;
             } else {
@@ -906,6 +916,7 @@ int alg1_core(pr_handle h, const int32_t* subset, int64_t ns, A1Run& R) {
     if (d.inv) {
         dfree(h, d.inv);       // the stream was synchronised above
         dfree(h, d.inv_info);
+        for (int32_t* q : {d.spec, d.spec_n, d.pairm, d.ent, d.ent_n, d.ent_slot}) dfree(h, q);
     }
     if (c8[5] != 0)
         return pr_fail(h, PR_ERR_SINGULAR_PATCH, "zero pivot in database patch " + std::to_string(c8[5] - 1));

@@ -263,6 +263,10 @@ void dfree(pr_handle h, T* p) {
 // Algorithm 1 rounds after which the unresolved patches are inverted in one
 // batch (2 + 4 + 8 + 16 + 32 rounds have run by then)
 constexpr int64_t kA1BatchInvertAfter = 62;
+// entries a component may open per round after the batched inversion, and
+// the positions scanned for them
+constexpr int kA1Spec = 8;
+constexpr int kA1SpecWindow = 256;
 
 inline int64_t next_pow2(int64_t n) {
     int64_t N = 1024;
@@ -352,6 +356,13 @@ struct A1Dev {
     int32_t* rep_pos;         // int32[n_comp] sorted position of the current entry
     double* inv;              // null, or inverses by sorted position after the batched inversion
     int32_t* inv_info;        // int32[n_p] zero-pivot report of each batched inverse
+    // rounds of several entries (after the batched inversion), kA1Spec per component:
+    int32_t* spec;            // int32[n_comp * kA1Spec] speculative members (positions)
+    int32_t* spec_n;          // int32[n_comp]
+    int32_t* pairm;           // int32[n_comp * kA1Spec] bit i of [c][j]: u_i matches u_j
+    int32_t* ent;             // int32[n_comp * kA1Spec] the round's entries (positions)
+    int32_t* ent_n;           // int32[n_comp]
+    int32_t* ent_slot;        // int32[n_comp * kA1Spec]
 };
 void launch_a1_keys(int64_t n_p, const int32_t* subset, const int64_t* ptr, const double* keynorm,
                     uint64_t* keys, int32_t* vals, hipStream_t s);
@@ -370,6 +381,9 @@ void launch_a1_rounds(int rounds, const A1Dev& d, int crit, double eps, int max_
 // inverts every unresolved patch into d.inv (by sorted position); later
 // rounds copy from there instead of inverting
 void launch_a1_preinvert(const A1Dev& d, int max_ps, hipStream_t s);
+// rounds of up to kA1Spec entries per component; needs d.inv and the
+// speculation arrays
+void launch_a1_spec_rounds(int rounds, const A1Dev& d, int crit, double eps, int max_ps, hipStream_t s);
 void launch_a1_finish(int64_t n_p, const int32_t* repof, int64_t* flags, int64_t* rank, int64_t* scr,
                       int32_t* phi, int32_t* reps, hipStream_t s);
 void launch_a1_copy_db(int64_t m_p, const int32_t* reps, const int32_t* slot_of_patch, const int64_t* ptr,
