@@ -171,7 +171,8 @@ typedef struct {
     int64_t crit_evals;      /* criterion evaluations made */
     int64_t crit_pruned;     /* pairs skipped by the certified norm bound */
     int64_t crit_exact;      /* evaluations that needed the exact singular value */
-    int64_t alg1_rounds;     /* Algorithm 1 rounds (one per database entry) */
+    int64_t alg1_rounds;     /* Algorithm 1 rounds: one entry per component and round, up
+                                to 16 after the batched inversion (alg1_batch_inverted) */
     int64_t kmeans_iters;    /* Algorithm 2: most assignment passes of any group */
     int64_t empty_events;    /* Algorithm 2 empty clusters */
     int64_t n_items;         /* grouped apply work items */
@@ -207,9 +208,11 @@ typedef struct {
     int64_t sell_diag_slices;    /* slices in diagonal form */
     int64_t sell_diag_offsets;   /* their distinct offsets (stored columns) */
     int64_t sell_col_entries;    /* matrix entries in column-form slices */
-    int64_t alg1_batch_inverted; /* 1: Algorithm 1 ran more than 62 rounds, and then inverted
-                                    its unresolved patches in one batch instead of one new
-                                    entry per round (same inverses, bit for bit) */
+    int64_t alg1_batch_inverted; /* 1: Algorithm 1 ran more than 62 rounds, then inverted its
+                                    unresolved patches in one batch (same inverses, bit for
+                                    bit) and opened up to 16 entries per component and round
+                                    (same result and evaluation count; crit_refined and
+                                    crit_exact then include speculative pair tests) */
 } pr_stats;
 
 /* ---- entry points ------------------------------------------------------ */

@@ -18,9 +18,10 @@
 //          resolved on a match.
 // When the rounds run long (one large component adds about one entry per
 // round), every still unresolved patch is inverted in one batched launch and
-// later rounds copy the new entry's inverse from that batch: the same
+// later rounds copy the new entries' inverses from that batch (the same
 // elimination on the same tile, so the same bits, without a latency-bound
-// single-matrix inversion per round.
+// single-matrix inversion per round) and open several entries per round
+// (see the rounds of up to kA1Spec entries below).
 // A member is thus compared with its component's entries in append order
 // until the first match, as in the sequential algorithm.  Entries are
 // finally numbered in ascending patch id (the append order).

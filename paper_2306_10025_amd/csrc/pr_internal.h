@@ -265,7 +265,7 @@ void dfree(pr_handle h, T* p) {
 constexpr int64_t kA1BatchInvertAfter = 62;
 // entries a component may open per round after the batched inversion, and
 // the positions scanned for them
-constexpr int kA1Spec = 8;
+constexpr int kA1Spec = 16;
 constexpr int kA1SpecWindow = 256;
 
 inline int64_t next_pow2(int64_t n) {

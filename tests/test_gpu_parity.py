@@ -214,6 +214,12 @@ def test_alg1_batched_inverses_match_the_oracle():
         Xo = O.factor_inverse(B)
         tol = 8 * p * np.linalg.cond(B) * 2.2e-16
         assert np.abs(Xg - Xo).max() <= tol * np.abs(Xo).max(), j
+    # rounds of several entries make exactly the sequential algorithm's
+    # tests: patch i against entries 0..phi(i) (0..phi(i)-1 for an entry)
+    is_rep = np.zeros(P.n_p, bool)
+    is_rep[reps] = True
+    assert st["crit_evals"] + st["crit_pruned"] == int(np.sum(np.where(is_rep, phi, phi + 1)))
+    assert st["alg1_rounds"] < st["m_p"]
     # a short run does not take the batch
     Q = gen.nedelec_hex(6)
     h2 = pr.PatchRelax(Q.A, Q.ptr, Q.dofs, algo="tolerance", eps=1e-8)
