@@ -208,7 +208,7 @@ typedef struct {
     int64_t sell_diag_slices;    /* slices in diagonal form */
     int64_t sell_diag_offsets;   /* their distinct offsets (stored columns) */
     int64_t sell_col_entries;    /* matrix entries in column-form slices */
-    int64_t alg1_batch_inverted; /* 1: Algorithm 1 ran more than 62 rounds, then inverted its
+    int64_t alg1_batch_inverted; /* 1: Algorithm 1 ran more than 14 rounds, then inverted its
                                     unresolved patches in one batch (same inverses, bit for
                                     bit) and opened up to 16 entries per component and round
                                     (same result and evaluation count; crit_refined and

@@ -342,30 +342,40 @@ __global__ __launch_bounds__(64) void k_a1_eval(const int32_t* ctl, int crit, do
 // evaluations (the pair tests past a member's first match are not).
 
 // the speculative members of each component (positions in order), scanned
-// from its lowest unresolved position over at most kA1SpecWindow positions
-__global__ void k_a1s_pick(int64_t n_comp, int32_t* ctl, const int32_t* __restrict__ cstart,
-                           int32_t* __restrict__ next, const int32_t* __restrict__ status,
-                           int32_t* __restrict__ spec, int32_t* __restrict__ spec_n,
-                           int32_t* __restrict__ pairm, int32_t* __restrict__ rep_slot,
-                           int32_t* __restrict__ active) {
+// from its lowest unresolved position over at most kA1SpecWindow positions,
+// 64 at a time by one wavefront per component
+__global__ __launch_bounds__(64) void k_a1s_pick(int64_t n_comp, int32_t* ctl, const int32_t* __restrict__ cstart,
+                                                 int32_t* __restrict__ next, const int32_t* __restrict__ status,
+                                                 int32_t* __restrict__ spec, int32_t* __restrict__ spec_n,
+                                                 int32_t* __restrict__ pairm, int32_t* __restrict__ rep_slot,
+                                                 int32_t* __restrict__ active) {
     if (ctl[2]) return;
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_comp) return;
-    rep_slot[c] = -1;
-    const int32_t s0 = next[c], end = cstart[c + 1];
-    const int32_t lim = (end - s0 > kA1SpecWindow) ? s0 + kA1SpecWindow : end;
-    int n = 0;
-    for (int32_t s = s0; s < lim && n < kA1Spec; ++s) {
-        if (status[s] == 0) {
-            spec[c * kA1Spec + n] = s;
-            pairm[c * kA1Spec + n] = 0;
-            ++n;
+    const int lane = threadIdx.x;
+    for (int64_t c = blockIdx.x; c < n_comp; c += gridDim.x) {
+        const int32_t s0 = next[c], end = cstart[c + 1];
+        const int32_t lim = (end - s0 > kA1SpecWindow) ? s0 + kA1SpecWindow : end;
+        int n = 0;
+        for (int32_t b = s0; b < lim && n < kA1Spec; b += PR_WAVE) {
+            const int32_t sp = b + lane;
+            const int32_t st = status[sp < lim ? sp : s0];        // clamped: s0 < lim here
+            const bool un = sp < lim && st == 0;
+            const unsigned long long m = __ballot(un);
+            const int rank = n + (int)__popcll(m & ((1ull << lane) - 1ull));
+            if (un && rank < kA1Spec) {
+                spec[c * kA1Spec + rank] = sp;
+                pairm[c * kA1Spec + rank] = 0;
+            }
+            n += (int)__popcll(m);
         }
-    }
-    spec_n[c] = n;
-    if (n > 0) {
-        active[atomicAdd(&ctl[1], 1)] = (int32_t)c;
-        next[c] = end;      // lowered by the evaluation to the next unresolved member
+        if (n > kA1Spec) n = kA1Spec;
+        if (lane == 0) {
+            rep_slot[c] = -1;
+            spec_n[c] = n;
+            if (n > 0) {
+                active[atomicAdd(&ctl[1], 1)] = (int32_t)c;
+                next[c] = end;  // lowered by the evaluation to the next unresolved member
+            }
+        }
     }
 }
 
@@ -711,8 +721,8 @@ void launch_a1_spec_rounds(int rounds, const A1Dev& d, int crit, double eps, int
     const size_t lds = (size_t)3 * pm * pm * sizeof(double);
     for (int t = 0; t < rounds; ++t) {
         k_a1_begin<<<1, 1, 0, s>>>(d.ctl);
-        k_a1s_pick<<<cb, 256, 0, s>>>(d.n_comp, d.ctl, d.cstart, d.next, d.status, d.spec, d.spec_n, d.pairm,
-                                      d.rep_slot, d.active);
+        k_a1s_pick<<<(unsigned)(d.n_comp < 4096 ? d.n_comp : 4096), 64, 0, s>>>(
+            d.n_comp, d.ctl, d.cstart, d.next, d.status, d.spec, d.spec_n, d.pairm, d.rep_slot, d.active);
         k_a1s_pairs<<<pb, 64, lds, s>>>(d.ctl, crit, eps, pm, d.active, d.spec, d.spec_n, d.mem, d.ptr, d.tiles,
                                         d.toff, d.uniform_ps, d.inv, d.stride, d.pairm, d.counters);
         k_a1s_resolve<<<cb, 256, 0, s>>>(d.ctl, d.active, d.spec, d.spec_n, d.pairm, d.mem, d.inv_info,

@@ -261,8 +261,8 @@ void dfree(pr_handle h, T* p) {
 }
 
 // Algorithm 1 rounds after which the unresolved patches are inverted in one
-// batch (2 + 4 + 8 + 16 + 32 rounds have run by then)
-constexpr int64_t kA1BatchInvertAfter = 62;
+// batch (2 + 4 + 8 rounds have run by then)
+constexpr int64_t kA1BatchInvertAfter = 14;
 // entries a component may open per round after the batched inversion, and
 // the positions scanned for them
 constexpr int kA1Spec = 16;

@@ -156,8 +156,9 @@ ALG1_CASES = {
     "q2hex_const_4_fro": (lambda: gen.q2_hex_diffusion(4, sigma=0.0), "fro", 1e-7),
     "q2hex_4_spec_loose": (lambda: gen.q2_hex_diffusion(4), "spectral", 0.5),
     "batch_5_spec": (lambda: gen.uneven_stokes_batch(n_sys=5, nmin=2, nmax=6), "spectral", 1e-8),
-    # one component of 216 distinct patches: 216 rounds, so the unresolved
-    # patches are inverted in one batch after the first 62
+    # one component of 216 distinct patches: the unresolved patches are
+    # inverted in one batch after the first 14 rounds, then rounds open
+    # several entries
     "q2hex_6_spec_long": (lambda: gen.q2_hex_diffusion(6), "spectral", 0.5),
 }
 
@@ -203,7 +204,7 @@ def test_alg1_batched_inverses_match_the_oracle():
     h = pr.PatchRelax(P.A, P.ptr, P.dofs, algo="tolerance", eps=0.5)
     st = h.stats()
     say("long alg1", st["alg1_rounds"], st["m_p"], st["alg1_batch_inverted"])
-    assert st["alg1_rounds"] > 62 and st["alg1_batch_inverted"] == 1
+    assert st["alg1_rounds"] > 14 and st["alg1_batch_inverted"] == 1
     phi, reps = h.assignment()
     tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
     for j, k in enumerate(reps):
