@@ -506,7 +506,7 @@ __global__ __launch_bounds__(64) void k_a1s_take(const int32_t* ctl, const int32
 
 // one wavefront per remaining member: tested against the round's entries of
 // its component in append order, up to the first match
-__global__ __launch_bounds__(64) void k_a1s_eval(const int32_t* ctl, int crit, double eps, int pm,
+__global__ __launch_bounds__(64, 2) void k_a1s_eval(const int32_t* ctl, int crit, double eps, int pm,
                                                  const int32_t* __restrict__ cand,
                                                  const int4* __restrict__ cinfo,
                                                  const int64_t* __restrict__ ptr,
