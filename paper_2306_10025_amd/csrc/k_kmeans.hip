@@ -27,7 +27,7 @@ namespace {
 using namespace pr_dev;
 
 // one wavefront per patch; centres of group g are [gc0[g], gc1[g])
-__global__ __launch_bounds__(64) void k_km_assign(int64_t n_p, const int64_t* __restrict__ ptr,
+__global__ __launch_bounds__(64, 2) void k_km_assign(int64_t n_p, const int64_t* __restrict__ ptr,
                                                   const double* __restrict__ tiles,
                                                   const int64_t* __restrict__ toff, int uniform_ps,
                                                   const int32_t* __restrict__ pg,

@@ -370,7 +370,7 @@ __device__ __forceinline__ const double* tile_of(const PairGeom& g, int64_t i) {
 // mode 0: try the predicted candidates cand[q*k .. q*k+k) in rank order;
 // mode 1: scan every entry in append order, skipping pairs the norm-key bound
 // rules out.  The first d < eps sets repof[i] to the entry's patch.
-__global__ __launch_bounds__(64) void k_mlp_match(int mode, int64_t nq, const int32_t* __restrict__ qids,
+__global__ __launch_bounds__(64, 2) void k_mlp_match(int mode, int64_t nq, const int32_t* __restrict__ qids,
                                                   const int32_t* __restrict__ cand, int k, PairGeom g,
                                                   const double* __restrict__ keynorm,
                                                   int32_t* __restrict__ repof, int32_t* __restrict__ resolved,
