@@ -112,8 +112,7 @@ __global__ void k_a1_pick(int64_t n_comp, int32_t* ctl, const int32_t* __restric
                           int32_t* __restrict__ next, const int32_t* __restrict__ mem,
                           int32_t* __restrict__ status, int32_t* __restrict__ rep_slot,
                           int32_t* __restrict__ rep_patch, int32_t* __restrict__ slot_of_patch,
-                          int32_t* __restrict__ repof, int32_t* __restrict__ active,
-                          int32_t* __restrict__ rep_pos) {
+                          int32_t* __restrict__ repof, int32_t* __restrict__ active) {
     if (ctl[2]) return;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_comp) return;
@@ -123,7 +122,6 @@ __global__ void k_a1_pick(int64_t n_comp, int32_t* ctl, const int32_t* __restric
         const int32_t pid = mem[s];
         const int32_t slot = atomicAdd(&ctl[0], 1);
         rep_slot[c] = slot;
-        rep_pos[c] = s;
         rep_patch[slot] = pid;
         slot_of_patch[pid] = slot;
         repof[pid] = pid;
@@ -177,30 +175,6 @@ __global__ __launch_bounds__(256) void k_a1_preinvert(int64_t n_p, const int32_t
         const double* A = tiles + (uniform_ps ? (int64_t)pid * uniform_ps * uniform_ps : toff[pid]);
         const int inf = gj_invert<MAXP, G>(A, inv + s * stride, p, r);
         if (r == 0) info[s] = inf;
-    }
-}
-
-// a round after the batched inversion: one wavefront per new entry copies
-// its p x p inverse to the entry's slot
-__global__ __launch_bounds__(64) void k_a1_take(const int32_t* ctl, const int32_t* __restrict__ active,
-                                                const int32_t* __restrict__ rep_slot,
-                                                const int32_t* __restrict__ rep_pos,
-                                                const int32_t* __restrict__ mem,
-                                                const int64_t* __restrict__ ptr,
-                                                const double* __restrict__ inv,
-                                                const int32_t* __restrict__ info, double* __restrict__ dbt,
-                                                int64_t stride, int32_t* sing) {
-    if (ctl[2]) return;
-    const int na = ctl[1];
-    for (int64_t g = blockIdx.x; g < na; g += gridDim.x) {
-        const int32_t c = active[g];
-        const int32_t s = rep_pos[c];
-        const int32_t pid = mem[s];
-        const int p = (int)(ptr[pid + 1] - ptr[pid]);
-        const double* src = inv + (int64_t)s * stride;
-        double* dst = dbt + (int64_t)rep_slot[c] * stride;
-        for (int e = threadIdx.x; e < p * p; e += 64) dst[e] = src[e];
-        if (threadIdx.x == 0 && info[s] != 0) atomicCAS(sing, 0, pid + 1);
     }
 }
 
@@ -688,11 +662,8 @@ void launch_a1_rounds(int rounds, const A1Dev& d, int crit, double eps, int max_
     for (int t = 0; t < rounds; ++t) {
         k_a1_begin<<<1, 1, 0, s>>>(d.ctl);
         k_a1_pick<<<cb, 256, 0, s>>>(d.n_comp, d.ctl, d.cstart, d.next, d.mem, d.status, d.rep_slot,
-                                     d.rep_patch, d.slot_of_patch, d.repof, d.active, d.rep_pos);
-        if (d.inv)
-            k_a1_take<<<(unsigned)(d.n_comp < 4096 ? d.n_comp : 4096), 64, 0, s>>>(
-                d.ctl, d.active, d.rep_slot, d.rep_pos, d.mem, d.ptr, d.inv, d.inv_info, d.dbt, d.stride, d.ctl + 5);
-        else if (max_ps <= 4)
+                                     d.rep_patch, d.slot_of_patch, d.repof, d.active);
+        if (max_ps <= 4)
             run_a1_invert<4, 4>(d.n_comp, d.ctl, d.active, d.rep_slot, d.rep_patch, d.ptr, d.tiles, d.toff, d.uniform_ps, d.dbt, d.stride, d.ctl + 5, s);
         else if (max_ps <= 12)
             run_a1_invert<12, 16>(d.n_comp, d.ctl, d.active, d.rep_slot, d.rep_patch, d.ptr, d.tiles, d.toff, d.uniform_ps, d.dbt, d.stride, d.ctl + 5, s);

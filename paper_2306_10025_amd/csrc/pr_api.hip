@@ -846,8 +846,6 @@ int alg1_core(pr_handle h, const int32_t* subset, int64_t ns, A1Run& R) {
     PR_TRY(dalloc(h, &cand, ns));
     int4* cinfo = nullptr;
     PR_TRY(dalloc(h, &cinfo, ns));
-    int32_t* rep_pos = nullptr;
-    PR_TRY(dalloc(h, &rep_pos, n_comp));
     PR_TRY(dalloc(h, &ctl, 8));
     PR_TRY(dalloc(h, &counters, 4));
     PR_TRY(dalloc(h, &R.dbt, (size_t)ns * stride));
@@ -872,7 +870,6 @@ int alg1_core(pr_handle h, const int32_t* subset, int64_t ns, A1Run& R) {
     d.cand = cand;
     d.cinfo = cinfo;
     d.dbt = R.dbt;
-    d.rep_pos = rep_pos;
     d.inv = nullptr;
     d.inv_info = nullptr;
     d.spec = d.spec_n = d.pairm = d.ent = d.ent_n = d.ent_slot = nullptr;

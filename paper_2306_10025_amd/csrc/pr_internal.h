@@ -353,7 +353,6 @@ struct A1Dev {
     int4* cinfo;              // per candidate {patch, component, slot, entry patch}
     double* dbt;              // inverses by slot, stride doubles each
     int64_t stride;
-    int32_t* rep_pos;         // int32[n_comp] sorted position of the current entry
     double* inv;              // null, or inverses by sorted position after the batched inversion
     int32_t* inv_info;        // int32[n_p] zero-pivot report of each batched inverse
     // rounds of several entries (after the batched inversion), kA1Spec per component:
@@ -378,8 +377,8 @@ void launch_a1_key2(int64_t n_p, const int64_t* flag, const int64_t* excl, const
 void launch_a1_cstart(int64_t n_p, int64_t n_comp, const uint64_t* key2, int32_t* pos_comp,
                       int32_t* cstart, int32_t* next, hipStream_t s);
 void launch_a1_rounds(int rounds, const A1Dev& d, int crit, double eps, int max_ps, hipStream_t s);
-// inverts every unresolved patch into d.inv (by sorted position); later
-// rounds copy from there instead of inverting
+// inverts every unresolved patch into d.inv (by sorted position); the
+// multi-entry rounds then copy from there instead of inverting
 void launch_a1_preinvert(const A1Dev& d, int max_ps, hipStream_t s);
 // rounds of up to kA1Spec entries per component; needs d.inv and the
 // speculation arrays
