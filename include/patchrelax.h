@@ -52,7 +52,7 @@ extern "C" {
 #define PR_ERR_NONFINITE         -7   /* NaN/Inf in a tile, right-hand side or solve */
 #define PR_ERR_OOM               -8   /* device allocation failed */
 #define PR_ERR_HIP               -9   /* other HIP runtime error (message kept) */
-#define PR_ERR_UNSUPPORTED      -10   /* valid input outside what this build supports */
+#define PR_ERR_UNSUPPORTED      -10   /* valid input outside what the library supports */
 #define PR_ERR_BAD_CSR          -11   /* row_ptr not monotone, column out of range or unsorted */
 #define PR_ERR_BAD_PATCH_PTR    -12   /* patch ptr not monotone or an empty patch */
 
