@@ -142,6 +142,13 @@ typedef struct {
                                 deterministic slot sum reads a padded per-dof slot table;
                                 PR_FORM_GENERAL: work items per database entry and CSR slot
                                 lists.  Both give the same bits */
+    int32_t alg1_prune;      /* Algorithm 1: 1 (default) skips the pairs a certified bound
+                                rules out (patches sorted by the Frobenius norm, or the l1
+                                norm for the l1 criterion; a pair whose norms differ by more
+                                than the criterion allows cannot match), which changes
+                                neither phi nor the database; 0 evaluates every pair the
+                                sequential algorithm compares, so crit_evals equals that
+                                algorithm's comparison count and crit_pruned is 0 */
 } pr_params;
 
 typedef struct pr_handle_s* pr_handle;

@@ -1,7 +1,8 @@
 """Construction of the inverse database and the patch map phi (Section 3).
 
-* ``alg1_tolerance``: Algorithm 1 (patch tolerance construction), literal
-  double loop in patch order with first-match semantics.
+* ``alg1_tolerance``: Algorithm 1 (patch tolerance construction) from its
+  definition: each patch, in ascending id, takes the earliest entry within
+  the tolerance or becomes a new entry.
 * ``kmeans``: Algorithm 2 (spectral clustering construction) and its variants
   listed in Section 3.2 (entrywise k-means, spectral k-means,
   variance-minimising clustering, bootstrapping), with the boundary
@@ -70,39 +71,41 @@ def _dist(crit, Ai, Bj, Xj):
 def alg1_tolerance(tiles, eps, crit="spectral"):
     """Algorithm 1: greedy tolerance construction of the database and phi.
 
-    Visit patches in order; compare with the database entries in append order
-    and take the first with d < eps; with no match, append the patch's inverse
-    and map the patch to the new entry.  Entries of another patch size are
-    never compared (a matrix of another size is no candidate, remark in
-    Section 2), so with several sizes each size runs Algorithm 1 on its own
-    while entries keep one append order.
+    Definition: patch i is mapped to the earliest database entry of its size
+    (entries numbered in the order they were created) whose criterion value
+    against it is below eps; a patch with no such entry creates the next
+    entry, its own inverse, and is mapped to it.  Patches are taken in
+    ascending id.  Entries of another patch size are no candidates (the
+    criterion is defined for equal sizes; remark in Section 2), so with
+    several sizes each size runs Algorithm 1 on its own while entries keep one
+    numbering.  The criterion is evaluated entry by entry up to the first
+    value below eps, so ``evals`` is the number of comparisons the greedy
+    construction makes.
     Returns dict(phi, reps, X, evals, margin): reps are the patch ids whose
-    inverses form the database, evals counts criterion evaluations and margin
-    is min |d - eps| / eps over every comparison made.
+    inverses form the database and margin is min |d - eps| / eps over every
+    value computed.
     """
-    reps, X, B = [], [], []
+    reps, X = [], []
     phi = np.zeros(len(tiles), dtype=np.int64)
-    evals = 0
-    margin = np.inf
+    seen = []                                   # every criterion value computed
+
+    def d(i, j):
+        v = _dist(crit, tiles[i], tiles[reps[j]], X[j])
+        seen.append(v)
+        return v
+
     for i, Ai in enumerate(tiles):
-        match = False
-        for j in range(len(reps)):
-            if B[j].shape != Ai.shape:
-                continue
-            d = _dist(crit, Ai, B[j], X[j])
-            evals += 1
-            if eps > 0:
-                margin = min(margin, abs(d - eps) / eps)
-            if d < eps:
-                phi[i] = j
-                match = True
-                break
-        if not match:
+        same_size = (j for j in range(len(reps)) if tiles[reps[j]].shape == Ai.shape)
+        first = next((j for j in same_size if d(i, j) < eps), None)
+        if first is None:
             reps.append(i)
-            B.append(Ai)
             X.append(factor_inverse(Ai))
-            phi[i] = len(reps) - 1
-    return dict(phi=phi, reps=np.asarray(reps, dtype=np.int64), X=X, evals=evals,
+            first = len(reps) - 1
+        phi[i] = first
+    margin = np.inf
+    if seen and eps > 0:
+        margin = float(np.min(np.abs(np.asarray(seen) - eps)) / eps)
+    return dict(phi=phi, reps=np.asarray(reps, dtype=np.int64), X=X, evals=len(seen),
                 margin=margin)
 
 

@@ -52,7 +52,7 @@ __global__ void k_a1_keys(int64_t n_p, const int32_t* __restrict__ subset, const
 
 __global__ void k_a1_comp_flags(int64_t n_p, const int32_t* __restrict__ sidx,
                                 const int64_t* __restrict__ ptr, const double* __restrict__ keynorm,
-                                int crit, double eps, int64_t* __restrict__ flag) {
+                                int crit, double eps, int prune, int64_t* __restrict__ flag) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s > n_p) return;
     if (s == n_p) {
@@ -69,7 +69,7 @@ __global__ void k_a1_comp_flags(int64_t n_p, const int32_t* __restrict__ sidx,
     const double c = (pi * pi + 64) * 2.3e-16;
     const double half = (crit == PR_CRIT_SPECTRAL) ? (eps * sqrt((double)pi) * (1.0 + 1e-10) + c) * ks
                                                    : eps * (1.0 + 1e-10) + c * ks;
-    flag[s] = (pi != pj || ks - kp > half) ? 1 : 0;
+    flag[s] = (pi != pj || (prune && ks - kp > half)) ? 1 : 0;
 }
 
 __global__ void k_a1_key2(int64_t n_p, const int64_t* __restrict__ flag,
@@ -628,8 +628,8 @@ void launch_a1_subset_entries(int64_t ns, const int32_t* subset, const int32_t* 
 }
 
 void launch_a1_comp_flags(int64_t n_p, const int32_t* sidx, const int64_t* ptr, const double* keynorm,
-                          int crit, double eps, int64_t* flag, hipStream_t s) {
-    k_a1_comp_flags<<<nb(n_p + 1, 256), 256, 0, s>>>(n_p, sidx, ptr, keynorm, crit, eps, flag);
+                          int crit, double eps, int prune, int64_t* flag, hipStream_t s) {
+    k_a1_comp_flags<<<nb(n_p + 1, 256), 256, 0, s>>>(n_p, sidx, ptr, keynorm, crit, eps, prune, flag);
 }
 
 void launch_a1_key2(int64_t n_p, const int64_t* flag, const int64_t* excl, const int32_t* sidx,

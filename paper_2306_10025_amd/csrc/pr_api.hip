@@ -815,7 +815,7 @@ int alg1_core(pr_handle h, const int32_t* subset, int64_t ns, A1Run& R) {
     // 1. sort by (size, key); 2. components where no match can cross a gap
     launch_a1_keys(ns, subset, h->pptr, keynorm, keys, sidx, s);
     launch_sort_pairs(keys, sidx, ns, kscr, vscr, s);
-    launch_a1_comp_flags(ns, sidx, h->pptr, keynorm, crit, h->prm.eps, R.flag, s);
+    launch_a1_comp_flags(ns, sidx, h->pptr, keynorm, crit, h->prm.eps, h->prm.alg1_prune, R.flag, s);
     launch_exclusive_scan_i64(R.flag, R.excl, ns + 1, R.scr, s);
     int64_t n_comp = 0;
     PR_HIP(h, hipMemcpyAsync(&n_comp, R.excl + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -968,6 +968,7 @@ void pr_params_default(pr_params* p) {
     p->graph = 0;
     p->autotune = 0;
     p->apply_form = PR_FORM_AUTO;
+    p->alg1_prune = 1;
 }
 
 const char* pr_status_string(int st) {
@@ -1072,7 +1073,8 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
     if (pm.algo < PR_ALGO_FULL || pm.algo > PR_ALGO_BOOTSTRAP || pm.criterion < 0 || pm.criterion > 2 ||
         pm.apply_precision < 0 || pm.apply_precision > 4 || pm.sweeps < 1 || pm.gmres_restart < 1 ||
         pm.gmres_restart > 64 || !(pm.eps >= 0.0) || !(pm.omega > 0.0) ||
-        (pm.apply_form != PR_FORM_AUTO && pm.apply_form != PR_FORM_GENERAL))
+        (pm.apply_form != PR_FORM_AUTO && pm.apply_form != PR_FORM_GENERAL) ||
+        (pm.alg1_prune != 0 && pm.alg1_prune != 1))
         return pr_fail(nullptr, PR_ERR_INVALID_ARG, "bad parameter value");
     if (pm.algo != PR_ALGO_FULL && pm.algo != PR_ALGO_TOLERANCE &&
         (pm.kmeans_max_iter < 1 || !(pm.tie_rel >= 0.0)))

@@ -371,7 +371,7 @@ void launch_a1_subset_entries(int64_t ns, const int32_t* subset, const int32_t* 
                               int64_t* rank, int64_t* scr, int32_t base, int32_t* entries,
                               int32_t* rank_of_patch, hipStream_t s);
 void launch_a1_comp_flags(int64_t n_p, const int32_t* sidx, const int64_t* ptr, const double* keynorm,
-                          int crit, double eps, int64_t* flag, hipStream_t s);
+                          int crit, double eps, int prune, int64_t* flag, hipStream_t s);
 void launch_a1_key2(int64_t n_p, const int64_t* flag, const int64_t* excl, const int32_t* sidx,
                     uint64_t* key2, int32_t* val2, hipStream_t s);
 void launch_a1_cstart(int64_t n_p, int64_t n_comp, const uint64_t* key2, int32_t* pos_comp,

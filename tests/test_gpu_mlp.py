@@ -171,24 +171,28 @@ def test_setup_with_predictions_bit_exact(case):
     h.close()
 
 
-def test_trained_network_gains_over_algorithm_1():
-    """What the network buys: on repeated tile classes (C3's structure) most
-    patches are placed by their first prediction, with fewer criterion
-    evaluations than Algorithm 1 needs, and the solve is unchanged."""
+def test_trained_network_against_pruned_algorithm_1():
+    """What the network costs and buys on a fresh system, against the
+    library's own default Algorithm 1 (with the certified pruning), on
+    repeated tile classes (the structure of the 64^3 edge-element workload):
+    most patches are placed by their first prediction, the database and the
+    solve are unchanged, but the pruned scan already needs fewer criterion
+    evaluations than the predictions, and the training comes on top, so a
+    network trained for one setup does not pay for itself.  Reusing a trained
+    network on the next system of a sequence is where it can."""
     P = gen.nedelec_hex(12)
     plain = pr.PatchRelax(P.A, P.ptr, P.dofs, algo="tolerance", eps=1e-8, max_iters=300)
     learned = pr.PatchRelax(P.A, P.ptr, P.dofs, algo="tolerance", eps=1e-8, mlp=True, max_iters=300)
     sp, sl = plain.stats(), learned.stats()
-    say("plain evals", sp["crit_evals"], "m_p", sp["m_p"], "| learned evals", sl["crit_evals"], "m_p", sl["m_p"],
-        "accepted", sl["mlp_accepted"], "of", P.n_p - sl["mlp_train"], "train acc %.3f" % sl["mlp_train_acc"],
-        "train s %.3f" % sl["t_mlp_train"])
-    # Algorithm 1 as printed compares each patch with the entries in order
-    # until the first match; the library's exact pruning skips part of that
-    naive = sp["crit_evals"] + sp["crit_pruned"]
-    say("Algorithm 1 as printed", naive, "pruned exact", sp["crit_evals"], "with predictions", sl["crit_evals"])
+    say("pruned Algorithm 1: evals", sp["crit_evals"], "setup s %.4f" % sp["t_total"],
+        "| with predictions: evals", sl["crit_evals"], "setup s %.4f" % sl["t_total"],
+        "training s %.4f" % sl["t_mlp_train"], "accepted", sl["mlp_accepted"], "of",
+        P.n_p - sl["mlp_train"], "train acc %.3f" % sl["mlp_train_acc"])
     assert sl["mlp_accepted"] >= 0.5 * (P.n_p - sl["mlp_train"])
-    assert sl["crit_evals"] < naive
     assert sl["m_p"] == sp["m_p"]
+    # measured: the predictor loses on both counts on a fresh system
+    assert sp["crit_evals"] < sl["crit_evals"]
+    assert sp["t_total"] < sl["t_total"]
     # GMRES(30) with one-level cell patches does not reach 1e-8 on this H(curl)
     # problem; equal iteration counts must give the same residual
     b = torch.as_tensor(gen.rhs(P.n, 0)).to(DEV)

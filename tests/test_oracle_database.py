@@ -1,5 +1,6 @@
 """Pins of the oracle's database construction (Algorithms 1 and 2)."""
 import itertools
+import os
 
 import numpy as np
 import pytest
@@ -115,6 +116,18 @@ def test_splitmix64_is_invertible_state_walk():
     g = O.SplitMix64(12345)
     for k in range(1, 50):
         assert unmix(g.next()) == (12345 + k * 0x9E3779B97F4A7C15) % (1 << 64)
+
+
+def test_splitmix64_published_streams():
+    # the published first outputs for seeds 1234567 and 0 (tests/golden)
+    path = os.path.join(os.path.dirname(__file__), "golden", "splitmix64.txt")
+    rows = [ln.split("#", 1)[0].split() for ln in open(path)]
+    rows = [r for r in rows if r]
+    assert len(rows) == 2
+    for r in rows:
+        vals = [int(v, 0) for v in r]
+        g = O.SplitMix64(vals[0])
+        assert [g.next() for _ in vals[1:]] == vals[1:]
 
 
 def test_varmin_representative_identity():

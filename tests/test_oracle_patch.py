@@ -240,6 +240,55 @@ def test_block_jacobi_disjoint_patches_give_exact_inverse():
     assert info['iters'] == 1 and info['converged']
 
 
+def _disjoint_blocks(seed=5):
+    rng = np.random.default_rng(seed)
+    sizes = (3, 5, 4, 3)
+    blocks = [rng.standard_normal((s, s)) + s * np.eye(s) for s in sizes]
+    A = sp.block_diag(blocks).tocsr()
+    ptr = np.cumsum((0,) + sizes)
+    return A, ptr, np.arange(A.shape[0], dtype=np.int32), rng
+
+
+@pytest.mark.parametrize("sweeps", [1, 2, 3])
+@pytest.mark.parametrize("omega", [0.5, 0.8])
+def test_damped_sweeps_closed_form_on_disjoint_patches(sweeps, omega):
+    # disjoint patches covering a block-diagonal A: W = I and M^{-1} = A^{-1},
+    # so each damped step e <- e + omega M^{-1} (r - A e) (Experiment 3's
+    # smoothing step) shrinks A^{-1} r - e by the factor 1 - omega, and from
+    # e = 0 the s-th step gives e = (1 - (1 - omega)^s) A^{-1} r
+    A, ptr, dofs, rng = _disjoint_blocks()
+    n = A.shape[0]
+    cnt, W = O.cover_weights(n, ptr, dofs)
+    X = [O.factor_inverse(t) for t in O.patch_tiles(A, ptr, dofs)]
+    r = rng.standard_normal(n)
+    e = O.make_preconditioner(A, ptr, dofs, W, X, np.arange(4), omega=omega, sweeps=sweeps)(r)
+    want = (1.0 - (1.0 - omega) ** sweeps) * np.linalg.solve(A.toarray(), r)
+    assert np.allclose(e, want, rtol=1e-12, atol=1e-13)
+
+
+def test_damped_sweeps_match_the_dense_iteration_with_overlap():
+    # overlapping Q2 patches: s damped steps from e = 0 equal
+    # sum_{t<s} (I - omega M A)^t omega M r with M the dense Eq.(1) operator
+    # built from explicit restriction matrices
+    P = gen.q2_hex_diffusion(2)
+    cnt, W = O.cover_weights(P.n, P.ptr, P.dofs)
+    X = [O.factor_inverse(t) for t in O.patch_tiles(P.A, P.ptr, P.dofs)]
+    phi = np.arange(P.n_p)
+    M = O.apply_operator_dense(P.n, P.ptr, P.dofs, X, phi)
+    Ad = P.A.toarray()
+    r = np.random.default_rng(3).standard_normal(P.n)
+    omega = 0.6
+    for sweeps in (2, 3):
+        e = O.make_preconditioner(P.A, P.ptr, P.dofs, W, X, phi, omega=omega, sweeps=sweeps)(r)
+        T = np.eye(P.n) - omega * M @ Ad
+        want = np.zeros(P.n)
+        term = omega * M @ r
+        for _ in range(sweeps):
+            want += term
+            term = T @ term
+        assert np.allclose(e, want, rtol=1e-11, atol=1e-12 * np.abs(want).max())
+
+
 def test_compressed_with_every_patch_its_own_rep_equals_full():
     P = gen.nedelec_hex(3)
     tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
