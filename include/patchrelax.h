@@ -395,6 +395,27 @@ int pr_mlp_predict(int32_t precision, int64_t rows, int32_t F, int32_t H, int32_
                    const int32_t* row_key, const int32_t* class_key, const float* params, int32_t k,
                    float* logits, int32_t* topk, void* stream);
 
+/* Size in bytes of the fixed device workspace of pr_mlp_predict_noalloc. */
+#define PR_MLP_NOALLOC_SCRATCH_BYTES (32LL << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * forward pass and top-k as pr_mlp_predict, with the same arguments and the
+ * same results, but it calls no hipMalloc, hipFree or other allocating
+ * routine and does not synchronise (asynchronous on `stream`).  The hidden
+ * activations, and the logits when `logits` is NULL, live in one fixed
+ * device array of PR_MLP_NOALLOC_SCRATCH_BYTES that every device running
+ * the library holds until the process ends; the first call on a device looks
+ * up its address.  rows * (2 H + (logits ? 0 : C)) floats, each part rounded
+ * up to 64 floats, must fit in it, else INVALID_ARG.  Every call on one
+ * device shares that array: calls that overlap on one device (other streams,
+ * other threads) race and must be ordered by the caller.  Errors as for
+ * pr_mlp_predict; a failed kernel launch gives HIP. */
+int pr_mlp_predict_noalloc(int32_t precision, int64_t rows, int32_t F, int32_t H, int32_t C,
+                           const float* X, const int32_t* row_key, const int32_t* class_key,
+                           const float* params, int32_t k, float* logits, int32_t* topk,
+                           void* stream);
+
 #ifdef __cplusplus
 }
 #endif

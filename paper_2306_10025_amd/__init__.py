@@ -124,6 +124,9 @@ _SIGS = {
                                  c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double), c_void_p]),
     "pr_mlp_predict": (c_int, [c_int32, c_int64, c_int32, c_int32, c_int32, c_void_p, c_void_p,
                                c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "pr_mlp_predict_noalloc": (c_int, [c_int32, c_int64, c_int32, c_int32, c_int32, c_void_p,
+                                       c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
+                                       c_void_p]),
 }
 
 _lib = None
@@ -331,6 +334,19 @@ def pr_mlp_predict(precision, X, params, F, H, C, k, logits=None, topk=None, row
     rows = int(X.numel()) // F
     return _check(lib().pr_mlp_predict(prec, rows, F, H, C, _ptr(X), _ptr(row_key), _ptr(class_key),
                                        _ptr(params), k, _ptr(logits), _ptr(topk), _stream()))
+
+
+def pr_mlp_predict_noalloc(precision, X, params, F, H, C, k, logits=None, topk=None, row_key=None,
+                           class_key=None):
+    """pr_mlp_predict on the library's fixed workspace (asynchronous on the current stream)."""
+    prec = PREC[precision] if isinstance(precision, str) else int(precision)
+    rows = int(X.numel()) // F
+    return _check(lib().pr_mlp_predict_noalloc(prec, rows, F, H, C, _ptr(X), _ptr(row_key),
+                                               _ptr(class_key), _ptr(params), k, _ptr(logits),
+                                               _ptr(topk), _stream()))
+
+
+MLP_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 def pr_destroy(h):

@@ -22,6 +22,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <unordered_map>
 
 namespace {
@@ -482,6 +483,82 @@ int pr_mlp_predict(int32_t precision, int64_t rows, int32_t F, int32_t H, int32_
     mlp_forward(precision, d, params, X, (int)rows, w, s);
     if (k > 0) launch_topk(rows, C, w.L, C, k, row_key, class_key, topk, s);
     if (hipStreamSynchronize(s) != hipSuccess) return pr_fail(nullptr, PR_ERR_HIP, "MLP predict");
+    return PR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free forward pass: the activations live in one fixed device
+// array instead of buffers from hipMalloc.  Each device that runs the library
+// holds its own copy of the array until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in for
+// the symbol); it looks up the device address once per device and uses that.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kScratchFloats = PR_MLP_NOALLOC_SCRATCH_BYTES / (int64_t)sizeof(float);
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this device's scratch array (looked up on first use)
+int scratch_for_current_device(float** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return pr_fail(nullptr, PR_ERR_HIP, hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return pr_fail(nullptr, PR_ERR_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return pr_fail(nullptr, PR_ERR_HIP,
+                           std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = (float*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PR_OK;
+}
+
+int64_t round_up_64(int64_t v) { return (v + 63) / 64 * 64; }
+
+}  // namespace
+
+int pr_mlp_predict_noalloc(int32_t precision, int64_t rows, int32_t F, int32_t H, int32_t C, const float* X,
+                           const int32_t* row_key, const int32_t* class_key, const float* params, int32_t k,
+                           float* logits, int32_t* topk, void* stream) {
+    int rc = check_mlp_args(precision, rows, F, H, C);
+    if (rc < 0) return rc;
+    if (k < 0 || k > 8 || k > C || (k > 0 && !topk)) return pr_fail(nullptr, PR_ERR_INVALID_ARG, "k must lie in [0, min(8, C)]");
+    for (const void* q : {(const void*)X, (const void*)params})
+        if (!on_device(q)) return pr_fail(nullptr, q ? PR_ERR_HOST_POINTER : PR_ERR_INVALID_ARG,
+                                          "X and params must be device memory");
+    if ((logits && !on_device(logits)) || (topk && !on_device(topk)))
+        return pr_fail(nullptr, PR_ERR_HOST_POINTER, "logits and topk must be device memory");
+    if ((row_key == nullptr) != (class_key == nullptr) || (row_key && (!on_device(row_key) || !on_device(class_key))))
+        return pr_fail(nullptr, PR_ERR_INVALID_ARG, "row_key and class_key: both device arrays or both null");
+    // workspace: H1 and H2 (rows x H each), then the logits unless the caller gives them
+    const int64_t nh = round_up_64(rows * (int64_t)H);
+    const int64_t need = 2 * nh + (logits ? 0 : round_up_64(rows * (int64_t)C));
+    if (need > kScratchFloats)
+        return pr_fail(nullptr, PR_ERR_INVALID_ARG,
+                       "rows x (2 H + C without logits) needs " + std::to_string(need * 4) +
+                           " bytes of workspace, more than PR_MLP_NOALLOC_SCRATCH_BYTES");
+    float* ws = nullptr;
+    if ((rc = scratch_for_current_device(&ws)) < 0) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    MlpDims d(F, H, C);
+    MlpWork w;
+    w.H1 = ws;
+    w.H2 = ws + nh;
+    w.L = logits ? logits : ws + 2 * nh;
+    mlp_forward(precision, d, params, X, (int)rows, w, s);
+    if (k > 0) launch_topk(rows, C, w.L, C, k, row_key, class_key, topk, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return pr_fail(nullptr, PR_ERR_HIP, hipGetErrorString(e));
     return PR_OK;
 }
 
