@@ -149,6 +149,13 @@ typedef struct {
                                 neither phi nor the database; 0 evaluates every pair the
                                 sequential algorithm compares, so crit_evals equals that
                                 algorithm's comparison count and crit_pruned is 0 */
+    int32_t alg1_match;      /* Algorithm 1 (PR_ALGO_TOLERANCE without mlp): 0 (default) maps a
+                                patch to the first entry within eps, as printed; 1 maps it to
+                                the closest of the entries within eps that exist when it is
+                                visited (the variant of the remarks after Algorithm 1; the
+                                database is the same).  Equal distances: entries with
+                                d <= d_min (1 + tie_rel) + tie_rel s (s = 1 spectral, sum |A_i|
+                                for l1, ||A_i||_F for Frobenius) tie and the lowest index wins */
 } pr_params;
 
 typedef struct pr_handle_s* pr_handle;
@@ -220,6 +227,10 @@ typedef struct {
                                     bit) and opened up to 16 entries per component and round
                                     (same result and evaluation count; crit_refined and
                                     crit_exact then include speculative pair tests) */
+    int64_t closest_evals;       /* alg1_match = 1: criterion evaluations of the closest-match
+                                    pass (after Algorithm 1's own, which crit_evals counts) */
+    int64_t closest_moved;       /* alg1_match = 1: patches whose entry differs from the first
+                                    match */
 } pr_stats;
 
 /* ---- entry points ------------------------------------------------------ */

@@ -109,6 +109,52 @@ def alg1_tolerance(tiles, eps, crit="spectral"):
                 margin=margin)
 
 
+def alg1_closest(tiles, eps, crit="spectral", tie=1e-9):
+    """Algorithm 1 with closest matching (the variant proposed in the remarks
+    after Algorithm 1): instead of stopping at the first database entry
+    within the tolerance, patch i is compared with every entry of its size
+    that exists when i is visited and is mapped to the closest one among
+    those with d < eps; with none it is appended, as in Algorithm 1.
+
+    Whether a patch is appended depends only on whether some earlier entry
+    lies within eps, so the database is the one of ``alg1_tolerance``; only
+    the map phi can differ.  Reading for equal distances: the entries j with
+    d_j < eps and d_j <= d_min (1 + tie) + tie s_i tie (s_i = 1 for the
+    spectral distance, sum |A_i| for l1 and ||A_i||_F for Frobenius), and
+    the lowest entry index among them is taken, so that distances at
+    rounding level do not order the entries by noise.
+    Returns dict(phi, reps, X, evals, dmin): evals counts the comparisons
+    made, dmin[i] is the distance of patch i to its entry (0 for entries).
+    """
+    reps, X = [], []
+    phi = np.zeros(len(tiles), dtype=np.int64)
+    dmin_of = np.zeros(len(tiles))
+    evals = 0
+    for i, Ai in enumerate(tiles):
+        scale = {"spectral": 1.0, "l1": float(np.abs(Ai).sum()),
+                 "fro": float(np.linalg.norm(Ai))}[crit]
+        cand = [j for j in range(len(reps)) if tiles[reps[j]].shape == Ai.shape]
+        dist = np.array([_dist(crit, Ai, tiles[reps[j]], X[j]) for j in cand])
+        evals += len(cand)
+        within = dist < eps
+        if not within.any():
+            reps.append(i)
+            X.append(factor_inverse(Ai))
+            phi[i] = len(reps) - 1
+            continue
+        dmin = float(dist[within].min())
+        band = within & (dist <= dmin * (1.0 + tie) + tie * scale)
+        phi[i] = cand[int(np.flatnonzero(band)[0])]
+        dmin_of[i] = dmin
+    return dict(phi=phi, reps=np.asarray(reps, dtype=np.int64), X=X, evals=evals, dmin=dmin_of)
+
+
+def compressibility(n_p, m_p):
+    """Compression ratio (n_p - m_p) / n_p of a database of m_p entries for
+    n_p patches: the quantity of the compressibility curve in Experiment 4."""
+    return (n_p - m_p) / n_p
+
+
 def alg1_with_predictions(tiles, eps, crit, train, cand):
     """Algorithm 1 with a predictor of the matching entry (the learned
     shortcut suggested by the closing remarks of Section 3.2).

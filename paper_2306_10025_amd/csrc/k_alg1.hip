@@ -590,6 +590,197 @@ __global__ void k_a1_copy_db(int64_t m_p, const int32_t* __restrict__ reps,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Closest matching (the variant proposed in the remarks after Algorithm 1):
+// the database is Algorithm 1's (a patch becomes an entry exactly when no
+// earlier entry lies within eps, whichever would match), and every other
+// patch i is mapped to the closest of the entries within eps that exist when
+// i is visited, i.e. entries j < rank[i] (entries are numbered in ascending
+// patch id).  Equal distances: the entries with d_j < eps and
+// d_j <= d_min (1 + tie) + tie s_i tie (s_i = 1 spectral, sum |A_i| for l1,
+// ||A_i||_F for Frobenius); the lowest index among them wins.
+//
+// One wavefront per patch.  Entries of another size, and entries whose key
+// (Frobenius or l1 norm) rules out d < eps by the certified bound of the
+// file header, are skipped by a lane-parallel filter.  Spectral distances
+// are bracketed first ([largest column norm of E, ||E||_F]); only entries
+// that may lie in the band of the smallest certain match are narrowed by
+// repeated squaring, and only several survivors get exact values (cyclic
+// Jacobi), as in the clustering assignment.
+// ---------------------------------------------------------------------------
+__global__ void k_a1_entry_keys(int64_t m_p, const int32_t* __restrict__ reps, const int64_t* __restrict__ ptr,
+                                const double* __restrict__ keynorm, double* __restrict__ ekey,
+                                int32_t* __restrict__ esz) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m_p) return;
+    const int32_t r = reps[j];
+    ekey[j] = keynorm[r];
+    esz[j] = (int32_t)(ptr[r + 1] - ptr[r]);
+}
+
+__global__ __launch_bounds__(64, 2) void k_a1_closest(
+    int64_t n_p, const int64_t* __restrict__ ptr, const double* __restrict__ tiles,
+    const int64_t* __restrict__ toff, int ups, const int32_t* __restrict__ reps,
+    const int64_t* __restrict__ rank, const double* __restrict__ ekey, const int32_t* __restrict__ esz,
+    const double* __restrict__ db, int64_t stride, int crit, double eps, double tie,
+    const double* __restrict__ keynorm, int32_t* __restrict__ phi, double* __restrict__ lbscr, int64_t lbld,
+    unsigned long long* __restrict__ counters) {
+    __shared__ double sA[kMaxPs * kMaxPs];
+    __shared__ double sX[kMaxPs * kMaxPs];
+    __shared__ double sE[kMaxPs * kMaxPs];
+    const int lane = threadIdx.x;
+    double* lb = lbscr + (int64_t)blockIdx.x * lbld;
+    unsigned long long nev = 0, nex = 0, nsq = 0;
+    for (int64_t i = blockIdx.x; i < n_p; i += gridDim.x) {
+        const int32_t cur = phi[i];
+        if (reps[cur] == (int32_t)i) continue;            // an entry keeps itself
+        const int p = (int)(ptr[i + 1] - ptr[i]);
+        const int pp = p * p;
+        const int64_t J = rank[i];                        // entries that exist when i is visited
+        const double* Ai = tiles + (ups ? i * (int64_t)ups * ups : toff[i]);
+        const double ki = keynorm[i];
+        const double floor_abs = tie * (crit == PR_CRIT_SPECTRAL ? 1.0 : ki);
+        const double c = (p * p + 64) * 2.3e-16;
+        lds_load(sA, Ai, pp, lane);
+        __syncthreads();
+        // filter: same size and a key compatible with d < eps; lb = INF elsewhere
+        for (int64_t jb = 0; jb < J; jb += PR_WAVE) {
+            const int64_t j = jb + lane;
+            bool ok = false;
+            if (j < J) {
+                const double kj = ekey[j];
+                const double half = (crit == PR_CRIT_SPECTRAL)
+                                        ? (eps * sqrt((double)p) * (1.0 + 1e-10) + c) * fmax(ki, kj)
+                                        : eps * (1.0 + 1e-10) + c * fmax(ki, kj);
+                ok = esz[j] == p && fabs(ki - kj) <= half;
+                lb[j] = ok ? 0.0 : INFINITY;
+            }
+        }
+        __syncthreads();
+        double ubmin = INFINITY;                         // least upper bound of a certain match
+        // pass 1: exact l1 / Frobenius distances, or the spectral bracket
+        for (int64_t jb = 0; jb < J; jb += PR_WAVE) {
+            const int64_t jl = jb + lane;
+            unsigned long long mask = __ballot(jl < J && lb[jl] == 0.0);
+            while (mask) {
+                const int64_t j = jb + __ffsll((long long)mask) - 1;
+                mask &= mask - 1;
+                double v;
+                if (crit == PR_CRIT_SPECTRAL) {
+                    lds_load(sX, db + j * stride, pp, lane);
+                    __syncthreads();
+                    double lb2;
+                    const double fro2 = form_E(sA, sX, sE, p, lane, &lb2);
+                    __syncthreads();
+                    const double lo = sqrt(lb2) * (1.0 - 1e-12), hi = sqrt(fro2) * (1.0 + 1e-12);
+                    v = lo < eps ? lo : INFINITY;
+                    if (hi < eps) ubmin = fmin(ubmin, hi);
+                } else {
+                    const int32_t r = reps[j];
+                    const double* B = tiles + (ups ? (int64_t)r * ups * ups : toff[r]);
+                    double acc = 0.0;
+                    for (int e = lane; e < pp; e += PR_WAVE) {
+                        const double t = sA[e] - B[e];
+                        acc += (crit == PR_CRIT_L1) ? fabs(t) : t * t;
+                    }
+                    acc = wave_sum(acc);
+                    if (crit == PR_CRIT_FRO) acc = sqrt(acc);
+                    v = acc < eps ? acc : INFINITY;
+                }
+                ++nev;
+                if (lane == 0) lb[j] = v;
+            }
+        }
+        __syncthreads();
+        if (crit == PR_CRIT_SPECTRAL) {
+            // the closest match has d <= ubmin (a certain match) or d < eps
+            double thr = (fmin(ubmin, eps) * (1.0 + tie) + floor_abs) * (1.0 + 1e-12);
+            int ncand = 0;
+            for (int64_t jb = 0; jb < J; jb += PR_WAVE) {
+                const int64_t jl = jb + lane;
+                ncand += __popcll(__ballot(jl < J && lb[jl] <= thr));
+            }
+            if (ncand > 1) {
+                for (int64_t jb = 0; jb < J; jb += PR_WAVE) {
+                    const int64_t jl = jb + lane;
+                    unsigned long long mask = __ballot(jl < J && lb[jl] <= thr);
+                    while (mask) {
+                        const int64_t j = jb + __ffsll((long long)mask) - 1;
+                        mask &= mask - 1;
+                        lds_load(sX, db + j * stride, pp, lane);
+                        __syncthreads();
+                        double lo2;
+                        double hi2 = form_E(sA, sX, sE, p, lane, &lo2);
+                        __syncthreads();
+                        const double cut = thr;
+                        auto done = [cut, eps](double lo, double) {
+                            const double l = sqrt(lo) * (1.0 - 1e-12);
+                            return l > cut || l >= eps;
+                        };
+                        sigma2_bracket(sE, sX, sE, p, lane, kSquarings, lo2, hi2, done);
+                        ++nsq;
+                        __syncthreads();
+                        const double lo = sqrt(lo2) * (1.0 - 1e-12), hi = sqrt(hi2) * (1.0 + 1e-12);
+                        if (lane == 0) lb[j] = lo < eps ? lo : INFINITY;
+                        if (hi < eps) thr = fmin(thr, (hi * (1.0 + tie) + floor_abs) * (1.0 + 1e-12));
+                        __syncthreads();
+                    }
+                }
+                ncand = 0;
+                for (int64_t jb = 0; jb < J; jb += PR_WAVE) {
+                    const int64_t jl = jb + lane;
+                    ncand += __popcll(__ballot(jl < J && lb[jl] <= thr));
+                }
+            }
+            // survivors: the only one is the closest match; several get exact values
+            for (int64_t jb = 0; jb < J; jb += PR_WAVE) {
+                const int64_t jl = jb + lane;
+                const bool in = jl < J && lb[jl] <= thr;
+                if (jl < J && !in) lb[jl] = INFINITY;
+                unsigned long long mask = __ballot(in);
+                __syncthreads();
+                while (mask) {
+                    const int64_t j = jb + __ffsll((long long)mask) - 1;
+                    mask &= mask - 1;
+                    double d = 0.0;
+                    if (ncand > 1) {
+                        lds_load(sX, db + j * stride, pp, lane);
+                        __syncthreads();
+                        form_E(sA, sX, sE, p, lane);
+                        __syncthreads();
+                        d = sqrt(sigma_max2_jacobi(sE, sX, p, lane));
+                        __syncthreads();
+                        ++nex;
+                    }
+                    if (lane == 0) lb[j] = d < eps ? d : INFINITY;
+                }
+            }
+            __syncthreads();
+        }
+        // band around the least distance; lowest entry index in it
+        double dmin = INFINITY;
+        for (int64_t jb = 0; jb < J; jb += PR_WAVE) {
+            const int64_t jl = jb + lane;
+            dmin = fmin(dmin, jl < J ? lb[jl] : INFINITY);
+        }
+        dmin = -wave_max(-dmin);
+        const double lim = dmin * (1.0 + tie) + floor_abs;
+        int64_t pick = -1;
+        for (int64_t jb = 0; jb < J && pick < 0; jb += PR_WAVE) {
+            const int64_t jl = jb + lane;
+            const unsigned long long mask = __ballot(jl < J && lb[jl] <= lim);
+            if (mask) pick = jb + __ffsll((long long)mask) - 1;
+        }
+        if (lane == 0 && pick >= 0 && dmin < eps) phi[i] = (int32_t)pick;
+        __syncthreads();
+    }
+    if (lane == 0) {
+        atomicAdd(&counters[0], nev);
+        if (nex) atomicAdd(&counters[1], nex);
+        if (nsq) atomicAdd(&counters[3], nsq);
+    }
+}
+
 inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 template <int MAXP, int G>
@@ -714,6 +905,17 @@ void launch_a1_finish(int64_t n_p, const int32_t* repof, int64_t* flags, int64_t
     k_a1_repflags<<<nb(n_p + 1, 256), 256, 0, s>>>(n_p, repof, flags);
     launch_exclusive_scan_i64(flags, rank, n_p + 1, scr, s);
     k_a1_finish<<<nb(n_p, 256), 256, 0, s>>>(n_p, repof, rank, phi, reps);
+}
+
+void launch_a1_closest(int64_t n_p, const int64_t* ptr, const double* tiles, const int64_t* toff, int ups,
+                       const int32_t* reps, int64_t m_p, const int64_t* rank, const double* keynorm,
+                       double* ekey, int32_t* esz, const double* db, int64_t stride, int crit, double eps,
+                       double tie, int32_t* phi, double* lbscr, int64_t grid, unsigned long long* counters,
+                       hipStream_t s) {
+    if (n_p <= 0 || m_p <= 0) return;
+    k_a1_entry_keys<<<nb(m_p, 256), 256, 0, s>>>(m_p, reps, ptr, keynorm, ekey, esz);
+    k_a1_closest<<<(unsigned)grid, 64, 0, s>>>(n_p, ptr, tiles, toff, ups, reps, rank, ekey, esz, db, stride,
+                                               crit, eps, tie, keynorm, phi, lbscr, m_p, counters);
 }
 
 void launch_a1_copy_db(int64_t m_p, const int32_t* reps, const int32_t* slot_of_patch, const int64_t* ptr,

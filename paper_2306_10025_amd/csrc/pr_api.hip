@@ -91,6 +91,36 @@ int run_alg1(pr_handle h) {
         PR_HIP(h, hipStreamSynchronize(s));
         h->stats.crit_pruned = (int64_t)naive - h->stats.crit_evals;
     }
+    if (h->prm.alg1_match == 1) {
+        // closest matching over the same database; R.excl holds, for every
+        // patch, the number of entries with a lower patch id
+        const int crit = h->prm.criterion;
+        const double* keynorm = (crit == PR_CRIT_L1) ? h->l1norm : h->fnorm;
+        const int64_t grid = std::min<int64_t>(n_p, 2048);
+        double* ekey = nullptr;
+        int32_t* esz = nullptr;
+        double* lbscr = nullptr;
+        int32_t* phi0 = nullptr;
+        unsigned long long* cc = nullptr;
+        PR_TRY(dalloc(h, &ekey, h->m_p));
+        PR_TRY(dalloc(h, &esz, h->m_p));
+        PR_TRY(dalloc(h, &lbscr, (size_t)grid * h->m_p));
+        PR_TRY(dalloc(h, &phi0, n_p));
+        PR_TRY(dalloc(h, &cc, 5));
+        PR_HIP(h, hipMemsetAsync(cc, 0, 5 * sizeof(unsigned long long), s));
+        PR_HIP(h, hipMemcpyAsync(phi0, h->phi, n_p * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        launch_a1_closest(n_p, h->pptr, h->tiles, h->uniform ? nullptr : h->toff, h->uniform ? h->max_ps : 0,
+                          h->reps, h->m_p, R.excl, keynorm, ekey, esz, h->db, stride, crit, h->prm.eps,
+                          h->prm.tie_rel, h->phi, lbscr, grid, cc, s);
+        launch_count_eq(n_p, h->phi, 1, phi0, cc + 4, s);
+        unsigned long long c5[5];
+        PR_HIP(h, hipMemcpyAsync(c5, cc, sizeof(c5), hipMemcpyDeviceToHost, s));
+        PR_HIP(h, hipStreamSynchronize(s));
+        h->stats.closest_evals = (int64_t)c5[0];
+        h->stats.crit_exact += (int64_t)c5[1];
+        h->stats.crit_refined += (int64_t)c5[3];
+        h->stats.closest_moved = n_p - (int64_t)c5[4];
+    }
     h->dbps_host.resize(h->m_p);
     h->dboff_host.resize(h->m_p + 1);
     for (int64_t j = 0; j < h->m_p; ++j) {
@@ -969,6 +999,7 @@ void pr_params_default(pr_params* p) {
     p->autotune = 0;
     p->apply_form = PR_FORM_AUTO;
     p->alg1_prune = 1;
+    p->alg1_match = 0;
 }
 
 const char* pr_status_string(int st) {
@@ -1074,8 +1105,10 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
         pm.apply_precision < 0 || pm.apply_precision > 4 || pm.sweeps < 1 || pm.gmres_restart < 1 ||
         pm.gmres_restart > 64 || !(pm.eps >= 0.0) || !(pm.omega > 0.0) ||
         (pm.apply_form != PR_FORM_AUTO && pm.apply_form != PR_FORM_GENERAL) ||
-        (pm.alg1_prune != 0 && pm.alg1_prune != 1))
+        (pm.alg1_prune != 0 && pm.alg1_prune != 1) || (pm.alg1_match != 0 && pm.alg1_match != 1))
         return pr_fail(nullptr, PR_ERR_INVALID_ARG, "bad parameter value");
+    if (pm.alg1_match == 1 && (pm.algo != PR_ALGO_TOLERANCE || pm.mlp != 0 || !(pm.tie_rel >= 0.0)))
+        return pr_fail(nullptr, PR_ERR_INVALID_ARG, "closest matching needs PR_ALGO_TOLERANCE without mlp");
     if (pm.algo != PR_ALGO_FULL && pm.algo != PR_ALGO_TOLERANCE &&
         (pm.kmeans_max_iter < 1 || !(pm.tie_rel >= 0.0)))
         return pr_fail(nullptr, PR_ERR_INVALID_ARG, "bad clustering parameter");

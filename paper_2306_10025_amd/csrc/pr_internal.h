@@ -385,6 +385,11 @@ void launch_a1_preinvert(const A1Dev& d, int max_ps, hipStream_t s);
 void launch_a1_spec_rounds(int rounds, const A1Dev& d, int crit, double eps, int max_ps, hipStream_t s);
 void launch_a1_finish(int64_t n_p, const int32_t* repof, int64_t* flags, int64_t* rank, int64_t* scr,
                       int32_t* phi, int32_t* reps, hipStream_t s);
+void launch_a1_closest(int64_t n_p, const int64_t* ptr, const double* tiles, const int64_t* toff, int ups,
+                       const int32_t* reps, int64_t m_p, const int64_t* rank, const double* keynorm,
+                       double* ekey, int32_t* esz, const double* db, int64_t stride, int crit, double eps,
+                       double tie, int32_t* phi, double* lbscr, int64_t grid, unsigned long long* counters,
+                       hipStream_t s);
 void launch_a1_copy_db(int64_t m_p, const int32_t* reps, const int32_t* slot_of_patch, const int64_t* ptr,
                        const double* dbt, double* db, int64_t stride, hipStream_t s);
 

@@ -254,6 +254,47 @@ def test_alg1_evaluation_count_is_the_sequential_count(case):
         assert st1["crit_evals"] < ref["evals"]      # the bound skips most pairs here
 
 
+CLOSEST_CASES = {
+    "q2hex_5_spec": (lambda: gen.q2_hex_diffusion(5), "spectral", 0.99),
+    "q2hex_5_l1": (lambda: gen.q2_hex_diffusion(5), "l1", 50.0),
+    "q2hex_5_fro": (lambda: gen.q2_hex_diffusion(5), "fro", 5.0),
+    "q2hex_6_spec": (lambda: gen.q2_hex_diffusion(6), "spectral", 0.5),
+    "nedelec_6_spec": (lambda: gen.nedelec_hex(6), "spectral", 1e-8),
+    "batch_5_spec": (lambda: gen.uneven_stokes_batch(n_sys=5, nmin=2, nmax=6), "spectral", 0.3),
+}
+
+
+@pytest.mark.parametrize("case", list(CLOSEST_CASES))
+def test_alg1_closest_matches_oracle(case):
+    # closest matching (remarks after Algorithm 1): the database is Algorithm
+    # 1's, bit for bit; the map equals the oracle's, and where a distance tie
+    # could fall either way the GPU's choice must lie in the oracle's band
+    make, crit, eps = CLOSEST_CASES[case]
+    say("alg1 closest", case)
+    P = make()
+    tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
+    ref = O.alg1_closest(tiles, eps, crit)
+    first = O.alg1_tolerance(tiles, eps, crit)
+    h = pr.PatchRelax(P.A, P.ptr, P.dofs, algo="tolerance", criterion=crit, eps=eps, alg1_match="closest")
+    phi, reps = h.assignment()
+    st = h.stats()
+    h.close()
+    assert np.array_equal(reps, ref["reps"]), (case, len(reps), len(ref["reps"]))
+    moved = int((ref["phi"] != first["phi"]).sum())
+    assert st["closest_moved"] == int((phi != first["phi"]).sum())
+    say(f"  entries {len(reps)}, moved {moved} (gpu {st['closest_moved']}), evals {st['closest_evals']}")
+    bad = np.flatnonzero(phi != ref["phi"])
+    for i in bad:
+        t = tiles[i]
+        scale = {"spectral": 1.0, "l1": np.abs(t).sum(), "fro": np.linalg.norm(t)}[crit]
+        X = O.factor_inverse(tiles[reps[phi[i]]])
+        d = O.criterion(crit, t, tiles[reps[phi[i]]], X)
+        assert d < eps and d <= ref["dmin"][i] * (1 + 1e-8) + 1e-8 * scale, (case, i, d, ref["dmin"][i])
+    assert len(bad) <= max(1, len(tiles) // 1000), (case, len(bad))
+    if case.startswith("q2hex_5"):
+        assert moved > 0          # the variant changes the map on these inputs
+
+
 # ---- apply ------------------------------------------------------------------
 
 def _rhs(n, seed=0):
@@ -613,6 +654,40 @@ def test_apply_forms_are_bit_identical(case, precision):
     ha.close()
     hg.close()
     hat.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_apply_graph_replays_match_eager(precision):
+    # a HIP graph of back-to-back applications on distinct inputs (the warm
+    # protocol of the benchmark) replayed several times, with eager work and
+    # synchronisations in between: every replay gives the eager bits
+    P = gen.nedelec_hex(6)
+    algo = "full" if precision == "fp64" else "tolerance"
+    h = pr.PatchRelax(P.A, P.ptr, P.dofs, algo=algo, eps=1e-8, precision=precision, deterministic=True)
+    side = torch.cuda.Stream()
+    pr.pr_set_stream(h.h, side)
+    rng = np.random.default_rng(9)
+    R = dt(rng.standard_normal((4, P.n)), torch.float64)
+    Z = torch.full_like(R, np.nan)
+    E = torch.full_like(R, np.nan)
+    with torch.cuda.stream(side):
+        for k in range(4):
+            h.apply(R[k], E[k])
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        for k in range(4):
+            h.apply(R[k], Z[k])
+    for rep in range(3):
+        Z.fill_(np.nan)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Z, E), (precision, rep)
+        with torch.cuda.stream(side):       # eager work between replays
+            h.apply(R[0], E[0])
+        torch.cuda.synchronize()
+    del g
+    h.close()
 
 
 def test_memory_cache_reuse_gives_the_same_results():

@@ -238,3 +238,72 @@ def test_alg1_mixed_sizes_runs_each_size_on_its_own():
             rep_of[int(i)] = int(ids[r["reps"][r["phi"][q]]])
     assert sorted(set(rep_of.values())) == list(res["reps"])
     assert all(int(res["reps"][res["phi"][i]]) == rep_of[i] for i in range(len(t)))
+
+
+def _scalars(vals):
+    return [np.array([[float(v)]]) for v in vals]
+
+
+def test_alg1_closest_hand_example():
+    # 1 x 1 patches: d(a, b) = |1 - a/b|.  eps = 0.3: 1.3 is 0.3 from 1.0 (not
+    # below eps) and becomes an entry; 1.25 is 0.25 from entry 0 and 0.0385
+    # from entry 1: first match takes entry 0, closest match entry 1
+    tiles = _scalars([1.0, 1.3, 1.25])
+    first = O.alg1_tolerance(tiles, 0.3)
+    close = O.alg1_closest(tiles, 0.3)
+    assert first["phi"].tolist() == [0, 1, 0]
+    assert close["phi"].tolist() == [0, 1, 1]
+    assert close["reps"].tolist() == [0, 1] == first["reps"].tolist()
+    assert close["evals"] == 0 + 1 + 2
+    assert abs(close["dmin"][2] - (1 - 1.25 / 1.3)) < 1e-15
+
+
+def test_alg1_closest_only_sees_entries_created_before():
+    # entry 1 (1.5) appears after patch 1 (1.2): patch 1 can only take entry 0
+    tiles = _scalars([1.0, 1.2, 1.5, 1.45])
+    close = O.alg1_closest(tiles, 0.3)
+    assert close["reps"].tolist() == [0, 2]
+    assert close["phi"].tolist() == [0, 0, 1, 1]
+
+
+def test_alg1_closest_tie_band_takes_lowest_entry():
+    # entries 1.0 and 1.25 (d = 0.25 >= eps = 0.2 between them); a patch at
+    # 10/9 is equally far from both (d = 1/9); just above 10/9 entry 1 is
+    # closer by 1.6e-10, inside the band 1e-9 (1 + d) -> lowest entry, 0
+    a = 1.1111111112
+    d0, d1 = a - 1.0, 1.0 - a / 1.25
+    assert 0 < d0 - d1 < 1e-9
+    close = O.alg1_closest(_scalars([1.0, 1.25, a]), 0.2)
+    assert close["phi"].tolist() == [0, 1, 0]
+    # outside the band the strictly closer entry wins
+    close = O.alg1_closest(_scalars([1.0, 1.25, 1.112]), 0.2)
+    assert close["phi"].tolist() == [0, 1, 1]
+
+
+@pytest.mark.parametrize("crit,eps", [("spectral", 0.99), ("l1", 50.0), ("fro", 5.0)])
+def test_alg1_closest_keeps_algorithm_1_database(crit, eps):
+    # a patch becomes an entry iff no earlier entry lies within eps, whichever
+    # would match: the database does not depend on the matching rule
+    P = gen.q2_hex_diffusion(5)
+    tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
+    first = O.alg1_tolerance(tiles, eps, crit)
+    close = O.alg1_closest(tiles, eps, crit)
+    assert np.array_equal(first["reps"], close["reps"])
+    assert len(first["reps"]) < len(tiles)
+    # every patch lies within eps of its entry, and no other earlier entry is
+    # closer by more than the tie band (brute force over every pair)
+    X = {j: O.factor_inverse(tiles[r]) for j, r in enumerate(close["reps"])}
+    for i, t in enumerate(tiles):
+        if i in set(close["reps"].tolist()):
+            continue
+        dist = {j: O.criterion(crit, t, tiles[r], X[j]) for j, r in enumerate(close["reps"]) if r < i}
+        dj = dist[int(close["phi"][i])]
+        assert dj < eps
+        assert dj <= min(dist.values()) * (1 + 1e-9) + 1e-9 * {"spectral": 1.0, "l1": np.abs(t).sum(),
+                                                              "fro": np.linalg.norm(t)}[crit]
+    assert (close["phi"] != first["phi"]).any()
+
+
+def test_compressibility_ratio():
+    assert O.compressibility(3600, 36) == 0.99
+    assert O.compressibility(8000, 27) == pytest.approx(0.996625)
