@@ -196,6 +196,66 @@ def ref_nedelec_hex():
 
 
 # ---------------------------------------------------------------------------
+# Coarse interpolation input of the two-level combination (Eq.(2))
+# ---------------------------------------------------------------------------
+
+def tensor_interpolation(order: int, nc: int, dim: int) -> sp.csr_matrix:
+    """P0 of the two-level combination: values at the interior vertices of an
+    nc^dim grid of unit-cube cells -> values at the nodes of the order-`order`
+    tensor Lagrange discretisation on the same cells (equispaced nodes,
+    (order*nc + 1)^dim of them, x fastest), by multilinear interpolation in
+    each cell.  Boundary vertices carry Dirichlet values and are left out, so
+    the coarse unknowns are the (nc - 1)^dim interior vertices (x fastest).
+    Built from integer node indices (node I of a line lies in cell
+    min(I // order, nc - 1) at local coordinate (I - order * cell) / order).
+    """
+    nf = order * nc + 1
+    I = np.arange(nf)
+    cell = np.minimum(I // order, nc - 1)
+    xi = (I - order * cell) / order
+    # 1D: node I -> (vertex, weight) pairs; weight-0 pairs dropped
+    v1 = [cell, cell + 1]
+    w1 = [1.0 - xi, xi]
+    nci = nc - 1                                 # interior vertices per line
+    rows, cols, vals = [], [], []
+    for corner in range(1 << dim):
+        bits = [(corner >> d) & 1 for d in range(dim)]
+        # node multi-index (x fastest) via broadcasting over all nodes
+        grids = np.meshgrid(*([I] * dim), indexing='ij')          # grids[d][..] = index along axis d
+        vtx = [v1[bits[d]][grids[d]] for d in range(dim)]
+        wt = np.ones(grids[0].shape)
+        for d in range(dim):
+            wt = wt * w1[bits[d]][grids[d]]
+        inner = np.ones(grids[0].shape, dtype=bool)
+        for d in range(dim):
+            inner &= (vtx[d] >= 1) & (vtx[d] <= nc - 1)
+        keep = inner & (wt != 0.0)
+        node = np.zeros(grids[0].shape, dtype=np.int64)
+        coarse = np.zeros(grids[0].shape, dtype=np.int64)
+        for d in reversed(range(dim)):
+            node = node * nf + grids[d]
+            coarse = coarse * nci + (vtx[d] - 1)
+        rows.append(node[keep])
+        cols.append(coarse[keep])
+        vals.append(wt[keep])
+    P0 = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                       shape=(nf ** dim, nci ** dim)).tocsr()
+    P0.sum_duplicates()
+    P0.sort_indices()
+    P0.indices = P0.indices.astype(np.int32)
+    P0.indptr = P0.indptr.astype(np.int64)
+    return P0
+
+
+def tensor_node_coords(order: int, nc: int, dim: int) -> np.ndarray:
+    """Coordinates (n x dim) of the equispaced tensor Lagrange nodes, x fastest."""
+    nf = order * nc + 1
+    x = np.arange(nf) / (order * nc)
+    g = np.meshgrid(*([x] * dim), indexing='ij')
+    return np.stack([gd.transpose(*reversed(range(dim))).ravel() for gd in g], axis=1)
+
+
+# ---------------------------------------------------------------------------
 # Config generators
 # ---------------------------------------------------------------------------
 
@@ -217,6 +277,49 @@ def q1_poisson_2d(nc: int = 32, k: float = 1.0) -> Problem:
     ptr, dofs = _patches_from_cells(cell_dofs)
     return Problem(f"q1_poisson_2d_{nc}", A, ptr, dofs,
                    dict(nc=nc, k=k, p_s=4, boundary=bnd))
+
+
+def qp_diffusion_2d(nc: int = 60, order: int = 2, rho=None) -> Problem:
+    """-div(rho grad u) = f on the unit square with Q_order Lagrange elements
+    (equispaced nodes) on nc x nc quads, Dirichlet identity rows on the
+    boundary nodes, one patch per cell ((order + 1)^2 dofs, tensor order).
+    rho defaults to sin^2(pi x) sin^2(pi y) + 0.1, the smooth coefficient of
+    the first numerical experiment, evaluated at (order + 2)^2 Gauss points
+    per cell.  meta['b_exact'] = A u for the nodal values of
+    u = sin(pi x) sin(pi y), so that the discrete solution is that
+    interpolant; meta['P0'] is the coarse interpolation from the interior
+    vertices of the same mesh."""
+    if rho is None:
+        rho = lambda x, y: np.sin(np.pi * x) ** 2 * np.sin(np.pi * y) ** 2 + 0.1
+    nb = order + 1
+    nf = order * nc + 1
+    h = 1.0 / nc
+    xq, wq = gauss_legendre(order + 2)
+    phi, dx, dy = _tensor_basis_2d(order, xq)
+    w2 = np.kron(wq, wq)
+    ci, cj = np.meshgrid(np.arange(nc), np.arange(nc), indexing='xy')
+    ci, cj = ci.ravel(), cj.ravel()
+    # quadrature points per cell (index q = qx + nq*qy)
+    qx = np.tile(xq, len(xq))
+    qy = np.repeat(xq, len(xq))
+    X = (ci[:, None] + qx[None, :]) * h
+    Y = (cj[:, None] + qy[None, :]) * h
+    R = rho(X, Y)                                        # [cells, nq^2]
+    # reference gradients scale by 1/h, the Jacobian by h^2: the 2D stiffness is h-independent
+    Ke = (np.einsum('aq,bq,cq->cab', dx, dx, R * w2) + np.einsum('aq,bq,cq->cab', dy, dy, R * w2))
+    loc = [(a, b) for b in range(nb) for a in range(nb)]
+    cell_dofs = np.stack([(order * ci + a) + nf * (order * cj + b) for a, b in loc], axis=1)
+    I, J = np.meshgrid(np.arange(nf), np.arange(nf), indexing='xy')
+    bnd = ((I == 0) | (I == nf - 1) | (J == 0) | (J == nf - 1)).ravel()
+    r, c, v = _cells_to_coo(cell_dofs, Ke)
+    A, _ = _finish(r, c, v, nf * nf, bnd)
+    ptr, dofs = _patches_from_cells(cell_dofs)
+    coords = tensor_node_coords(order, nc, 2)
+    u = np.sin(np.pi * coords[:, 0]) * np.sin(np.pi * coords[:, 1])
+    u[bnd] = 0.0
+    return Problem(f"qp_diffusion_2d_p{order}_{nc}", A, ptr, dofs,
+                   dict(nc=nc, order=order, p_s=nb * nb, boundary=bnd, coords=coords, u_exact=u,
+                        b_exact=A @ u, P0=tensor_interpolation(order, nc, 2)))
 
 
 def _quad_geometry(vx, vy, xq):
@@ -429,7 +532,8 @@ def q2_hex_diffusion(nc: int = 32, sigma: float = 1.5, corr: float = 0.1, seed: 
     A, _ = _finish(r, c, v, nn ** 3, bnd)
     ptr, dofs = _patches_from_cells(cell_dofs)
     return Problem(f"q2_hex_{nc}", A, ptr, dofs,
-                   dict(nc=nc, sigma=sigma, corr=corr, seed=seed, p_s=27, k=kfield, boundary=bnd))
+                   dict(nc=nc, sigma=sigma, corr=corr, seed=seed, p_s=27, k=kfield, boundary=bnd,
+                        P0=tensor_interpolation(2, nc, 3)))
 
 
 def uneven_stokes_batch(n_sys: int = 256, nmin: int = 16, nmax: int = 128,

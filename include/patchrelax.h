@@ -158,6 +158,18 @@ typedef struct {
                                 for l1, ||A_i||_F for Frobenius) tie and the lowest index wins */
 } pr_params;
 
+/* Interpolation P0 from n_coarse coarse unknowns to the n_fine fine ones
+ * (CSR, n_fine rows, column indices in [0, n_coarse), device arrays):
+ * row_ptr int64[n_fine+1], col int32[nnz], val double[nnz]. */
+typedef struct {
+    int64_t n_fine;
+    int64_t n_coarse;
+    int64_t nnz;
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const double* val;
+} pr_interp;
+
 typedef struct pr_handle_s* pr_handle;
 
 typedef struct {
@@ -175,6 +187,11 @@ typedef struct {
      * matrix-vector products and the Gram-Schmidt orthogonalisation */
     double  apply_ms, spmv_ms, orth_ms;
     int64_t n_apply, n_spmv, n_orth;
+    /* with a coarse space (pr_set_coarse) and params.timing != 0: device
+     * milliseconds and count of the coarse terms P0 A0^{-1} R0 v (apply_ms
+     * then covers the patch part alone) */
+    double  coarse_ms;
+    int64_t n_coarse;
 } pr_solve_info;
 
 typedef struct {
@@ -231,6 +248,13 @@ typedef struct {
                                     pass (after Algorithm 1's own, which crit_evals counts) */
     int64_t closest_moved;       /* alg1_match = 1: patches whose entry differs from the first
                                     match */
+    /* two-level combination (pr_set_coarse; zeros without it) */
+    int64_t n_coarse;            /* coarse unknowns n0 */
+    int64_t coarse_nnz;          /* entries of R0 A P0 kept */
+    int64_t coarse_bandwidth;    /* largest |v - w| over its entries */
+    int64_t coarse_block;        /* rows per block of the banded solve (0: dense inverse) */
+    int64_t coarse_blocks;       /* blocks of the banded solve (1: dense inverse) */
+    double  t_coarse;            /* seconds of pr_set_coarse */
 } pr_stats;
 
 /* ---- entry points ------------------------------------------------------ */
@@ -279,6 +303,33 @@ int pr_apply(pr_handle h, const double* r, double* z);
  * b, x: device double[n].  Returns PR_OK, PR_NOT_CONVERGED or an error;
  * details via pr_get_solve_info.  Synchronises the stream. */
 int pr_solve(pr_handle h, const double* b, double* x, double tol);
+
+/* Two-level combination preconditioner (Eq.(2)): M_combo^{-1} = M~^{-1} +
+ * P0 A0^{-1} R0 with R0 = P0^T and A0 = R0 A P0 solved directly (the first
+ * two numerical experiments replace the AMG cycle by a direct solve of
+ * R0 A P0).  P0 interpolates from a first-order discretisation on the same
+ * mesh, e.g. by linear interpolation at the high-order nodes; it is copied.
+ * The library forms R0 and A0 on the device (each entry of A0 summed in one
+ * fixed order; entries at most 1e-13 of their row's largest magnitude, the
+ * rounding residue of couplings that vanish exactly, are dropped) and
+ * factors A0: for n0 <= 4096 its explicit inverse, otherwise block LU over
+ * blocks of b rows (b = the bandwidth max |v - w|, rounded up to 32, at most
+ * 4096), keeping the inverses of the Schur complements.  Neither step
+ * pivots across 32 x 32 blocks, which suits symmetric positive definite A0.
+ * Afterwards pr_apply gives z = omega M~^{-1} r + P0 A0^{-1} R0 r and
+ * pr_solve uses the combination as its preconditioner (the coarse term is
+ * added once per application, after the `sweeps` smoothing steps).  Once per
+ * handle, before any pr_set_systems.  Errors: INVALID_ARG (sizes, a column
+ * outside [0, n_coarse), a bad row_ptr, second call, a batch of systems),
+ * HOST_POINTER, NONFINITE, UNSUPPORTED (a coarse row coupled to more than 256
+ * coarse unknowns, a bandwidth beyond 4096), SINGULAR_PATCH (a zero pivot in
+ * the coarse factorisation), OOM, HIP.  Synchronises the stream. */
+int pr_set_coarse(pr_handle h, const pr_interp* P0);
+/* Parity hook: A0 = R0 A P0 in CSR, host arrays.  Call with null arrays to
+ * get *n0 and *nnz, then with row_ptr int64[n0+1], col int32[nnz] and val
+ * double[nnz].  INVALID_ARG without a coarse space. */
+int pr_get_coarse_matrix(pr_handle h, int64_t* n0, int64_t* nnz, int64_t* row_ptr, int32_t* col,
+                         double* val);
 
 int pr_get_solve_info(pr_handle h, pr_solve_info* info);
 int pr_get_stats(pr_handle h, pr_stats* s);

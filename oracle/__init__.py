@@ -23,6 +23,7 @@ from .database import (alg1_tolerance, alg1_closest, compressibility, kmeans, pa
                        apportion, SplitMix64, alg1_invariants_hold, alg1_with_predictions)
 from . import mlp
 from .krylov import gmres, make_preconditioner
+from .twolevel import linear_interpolation, coarse_operator, combo_preconditioner
 from .lowprec import round_fp32, round_bf16, round_fp16, apply_lowprec, fp16_scale_exp
 
 __all__ = [
@@ -31,5 +32,6 @@ __all__ = [
     "crit_spectral", "crit_spectral_x", "crit_l1", "crit_fro", "criterion",
     "alg1_tolerance", "alg1_closest", "compressibility", "kmeans", "partition_groups", "apportion", "SplitMix64",
     "alg1_invariants_hold", "alg1_with_predictions", "mlp", "gmres", "make_preconditioner",
+    "linear_interpolation", "coarse_operator", "combo_preconditioner",
     "round_fp32", "round_bf16", "round_fp16", "apply_lowprec", "fp16_scale_exp",
 ]

@@ -51,6 +51,11 @@ class pr_patches(Structure):
     _fields_ = [("n_p", c_int64), ("ptr", c_void_p), ("dofs", c_void_p)]
 
 
+class pr_interp(Structure):
+    _fields_ = [("n_fine", c_int64), ("n_coarse", c_int64), ("nnz", c_int64), ("row_ptr", c_void_p),
+                ("col", c_void_p), ("val", c_void_p)]
+
+
 class pr_params(Structure):
     _fields_ = [("algo", c_int32), ("criterion", c_int32), ("eps", c_double),
                 ("m_target", c_int64), ("partition_bc", c_int32), ("kmeans_max_iter", c_int32),
@@ -69,7 +74,7 @@ class pr_solve_info(Structure):
                 ("relres_est", c_double), ("status", c_int32), ("reorth", c_int32),
                 ("seconds", c_double), ("apply_ms", c_double), ("spmv_ms", c_double),
                 ("orth_ms", c_double), ("n_apply", c_int64), ("n_spmv", c_int64),
-                ("n_orth", c_int64)]
+                ("n_orth", c_int64), ("coarse_ms", c_double), ("n_coarse", c_int64)]
 
 
 class pr_stats(Structure):
@@ -90,7 +95,9 @@ class pr_stats(Structure):
                 ("tune_xcd_remap", c_int64), ("crit_refined", c_int64), ("sell_slots", c_int64),
                 ("sell_diag_slices", c_int64), ("sell_diag_offsets", c_int64), ("sell_col_entries", c_int64),
                 ("alg1_batch_inverted", c_int64), ("closest_evals", c_int64),
-                ("closest_moved", c_int64)]
+                ("closest_moved", c_int64), ("n_coarse", c_int64), ("coarse_nnz", c_int64),
+                ("coarse_bandwidth", c_int64), ("coarse_block", c_int64), ("coarse_blocks", c_int64),
+                ("t_coarse", c_double)]
 
 
 _SIGS = {
@@ -99,6 +106,9 @@ _SIGS = {
     "pr_apply": (c_int, [c_void_p, c_void_p, c_void_p]),
     "pr_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double]),
     "pr_get_solve_info": (c_int, [c_void_p, POINTER(pr_solve_info)]),
+    "pr_set_coarse": (c_int, [c_void_p, POINTER(pr_interp)]),
+    "pr_get_coarse_matrix": (c_int, [c_void_p, POINTER(c_int64), POINTER(c_int64), c_void_p, c_void_p,
+                                     c_void_p]),
     "pr_get_stats": (c_int, [c_void_p, POINTER(pr_stats)]),
     "pr_get_assignment": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_int64)]),
     "pr_get_patch_tile": (c_int, [c_void_p, c_int64, c_void_p]),
@@ -351,6 +361,26 @@ def pr_mlp_predict_noalloc(precision, X, params, F, H, C, k, logits=None, topk=N
 MLP_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
+def pr_set_coarse(h, row_ptr, col, val, n_fine, n_coarse):
+    """Two-level combination (Eq.(2)) from the interpolation P0 given as device
+    CSR tensors (n_fine rows, n_coarse columns)."""
+    P = pr_interp(n_fine, n_coarse, int(col.numel()), _ptr(row_ptr), _ptr(col), _ptr(val))
+    return _check(lib().pr_set_coarse(h, byref(P)), h)
+
+
+def pr_get_coarse_matrix(h):
+    """A0 = R0 A P0 as a SciPy CSR matrix (host copy)."""
+    import scipy.sparse as sp
+    n0, nnz = c_int64(), c_int64()
+    _check(lib().pr_get_coarse_matrix(h, byref(n0), byref(nnz), None, None, None), h)
+    rp = np.zeros(n0.value + 1, dtype=np.int64)
+    ci = np.zeros(max(nnz.value, 1), dtype=np.int32)
+    v = np.zeros(max(nnz.value, 1), dtype=np.float64)
+    _check(lib().pr_get_coarse_matrix(h, byref(n0), byref(nnz), rp.ctypes.data_as(c_void_p),
+                                      ci.ctypes.data_as(c_void_p), v.ctypes.data_as(c_void_p)), h)
+    return sp.csr_matrix((v[:nnz.value], ci[:nnz.value], rp), shape=(n0.value, n0.value))
+
+
 def pr_destroy(h):
     if h:
         lib().pr_destroy(h)
@@ -459,6 +489,17 @@ class PatchRelax:
 
     def entry_matrix(self, j, p):
         return pr_get_entry_matrix(self.h, j, p)
+
+    def set_coarse(self, P0):
+        """Two-level combination with the interpolation P0 (SciPy CSR, n rows)."""
+        import torch
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(self.dev)
+        self.p0 = (t(P0.indptr.astype(np.int64), torch.int64), t(P0.indices.astype(np.int32), torch.int32),
+                   t(P0.data.astype(np.float64), torch.float64))
+        return pr_set_coarse(self.h, *self.p0, P0.shape[0], P0.shape[1])
+
+    def coarse_matrix(self):
+        return pr_get_coarse_matrix(self.h)
 
     def set_systems(self, system_ptr):
         self.n_sys = len(system_ptr) - 1

@@ -644,14 +644,18 @@ int apply_op(pr_handle h, const double* r, double* z, bool accumulate, double* t
     return PR_OK;
 }
 
-// e = `sweeps` damped smoothing steps from 0 applied to v (t3: 2n doubles scratch)
-int precond(pr_handle h, const double* v, double* e, double* t3, const int32_t* stop = nullptr) {
+// e = `sweeps` damped smoothing steps from 0 applied to v (t3: 2n doubles
+// scratch), plus the coarse term P0 A0^{-1} R0 v of the two-level combination
+// when the handle has a coarse space and `coarse` is set
+int precond(pr_handle h, const double* v, double* e, double* t3, const int32_t* stop = nullptr,
+            bool coarse = true) {
     hipStream_t s = h->stream;
     PR_TRY(apply_op(h, v, e, false, nullptr, stop));
     for (int sw = 1; sw < h->prm.sweeps; ++sw) {
         launch_spmv_sell(h->sell(), h->n, e, v, t3, s, stop);
         PR_TRY(apply_op(h, t3, e, true, t3 + h->n, stop));
     }
+    if (coarse) PR_TRY(coarse_add(h, v, e, stop));
     return PR_OK;
 }
 
@@ -1315,6 +1319,7 @@ int pr_apply(pr_handle h, const double* r, double* z) {
     PR_TRY(check_dev(h, z, "z"));
     if (r == z) return pr_fail(h, PR_ERR_INVALID_ARG, "r and z must be distinct");
     PR_TRY(apply_op(h, r, z, false, nullptr));
+    PR_TRY(coarse_add(h, r, z, nullptr));
     PR_HIP(h, hipGetLastError());
     return PR_OK;
 }
@@ -1449,8 +1454,13 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
             tj = j;
             double* vj = V + (int64_t)j * ldv;
             tbeg();
-            PR_TRY(precond(h, vj, zt, t3, gctl));
+            PR_TRY(precond(h, vj, zt, t3, gctl, false));
             tend(0);
+            if (h->n0 > 0) {
+                tbeg();
+                PR_TRY(coarse_add(h, vj, zt, gctl));
+                tend(3);
+            }
             tbeg();
             launch_spmv_sell(h->sell(), n, zt, nullptr, w, s, gctl);
             tend(1);
@@ -1539,6 +1549,7 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
         if (sp.cls == 0) { h->sinfo.apply_ms += ms; h->sinfo.n_apply++; }
         if (sp.cls == 1) { h->sinfo.spmv_ms += ms; h->sinfo.n_spmv++; }
         if (sp.cls == 2) { h->sinfo.orth_ms += ms; h->sinfo.n_orth++; }
+        if (sp.cls == 3) { h->sinfo.coarse_ms += ms; h->sinfo.n_coarse++; }
     }
     return h->sinfo.status;
 }

@@ -198,6 +198,19 @@ struct pr_handle_s {
     int32_t* mlp_cand = nullptr;
     int mlp_k = 0;
 
+    // two-level combination of Eq.(2) (pr_set_coarse): P0 (n x n0), R0 = P0^T,
+    // A0 = R0 A P0 and its transpose (CSR), and the direct solver's data:
+    // the dense inverse (c_dense) or the inverses of the block LU's Schur
+    // complements (c_nb blocks of c_s rows); c_r0, c_w, c_x are padded vectors
+    int64_t n0 = 0, a0_nnz = 0;
+    int64_t *p0_rp = nullptr, *r0_rp = nullptr, *a0_rp = nullptr, *a0t_rp = nullptr;
+    int32_t *p0_ci = nullptr, *r0_ci = nullptr, *a0_ci = nullptr, *a0t_ci = nullptr;
+    double *p0_v = nullptr, *r0_v = nullptr, *a0_v = nullptr, *a0t_v = nullptr;
+    int c_dense = 0, c_s = 0, c_nb = 0;
+    int64_t c_np = 0;
+    double* c_X = nullptr;
+    double *c_r0 = nullptr, *c_w = nullptr, *c_x = nullptr;
+
     pr_solve_info sinfo{};
     pr_stats stats{};
     std::string last_error;
@@ -452,6 +465,42 @@ void launch_count_eq(int64_t n, const int32_t* a, int sa, const int32_t* b, unsi
 void launch_rows_gather(int64_t n, const int32_t* idx, const float* src, int F, float* dst, const int32_t* lsrc,
                         int32_t* ldst, const int32_t* ksrc, int32_t* kdst, hipStream_t s);
 void launch_set_at(int64_t n, const int32_t* ids, int32_t v, int32_t* dst, hipStream_t s);
+
+// k_coarse.hip: two-level combination (Eq.(2))
+void launch_interp_check(int64_t n, int64_t n0, int64_t nnz, const int64_t* rp, const int32_t* ci,
+                         const double* v, int32_t* flags, hipStream_t st);
+int launch_csr_transpose(int64_t n, int64_t m, const int64_t* rp, const int32_t* ci, const double* v,
+                         int64_t* tp, int32_t* tc, double* tv, int64_t* cnt, int64_t* fill,
+                         int64_t* scan_scr, hipStream_t st);
+int coarse_gal_slots();
+void launch_galerkin(int64_t n0, const int64_t* rrp, const int32_t* rci, const double* rv, const int64_t* arp,
+                     const int32_t* aci, const double* av, const int64_t* prp, const int32_t* pci,
+                     const double* pv, double drop, int32_t* ocnt, int32_t* ocol, double* oval,
+                     int32_t* overflow, hipStream_t st);
+void launch_rows_finish(int64_t n0, const int32_t* cnt32, int64_t* cnt64, int64_t* rp, int64_t* scan_scr,
+                        hipStream_t st);
+void launch_rows_compact(int64_t n0, const int64_t* rp, const int32_t* icol, const double* ival, int32_t* ocol,
+                         double* oval, hipStream_t st);
+void launch_bandwidth(int64_t n0, const int64_t* rp, const int32_t* ci, int32_t* bw, hipStream_t st);
+void launch_block_schur(int64_t n0, int s, int bi, const int64_t* rp, const int32_t* ci, const double* v,
+                        const int64_t* trp, const int32_t* tci, const double* tv, const double* Y, double* S,
+                        hipStream_t st);
+void launch_block_lsinv(int64_t n0, int s, int bi, const int64_t* rp, const int32_t* ci, const double* v,
+                        const double* Sprev, double* Y, hipStream_t st);
+void launch_dense_from_csr(int64_t n0, int64_t np, const int64_t* rp, const int32_t* ci, const double* v,
+                           double* M, hipStream_t st);
+void launch_gj_inverse(double* M, int s, double* Pinv, double* C, int32_t* info, hipStream_t st);
+void launch_csr_rows_wave(int64_t m, const int64_t* rp, const int32_t* ci, const double* v, const double* x,
+                          double* y, const int32_t* stop, hipStream_t st);
+void launch_csr_rows_add(int64_t n, const int64_t* rp, const int32_t* ci, const double* v, const double* x,
+                         double* z, const int32_t* stop, hipStream_t st);
+void launch_dense_gemv(int64_t np, const double* X, const double* in, double* out, const int32_t* stop,
+                       hipStream_t st);
+void launch_band_solve(int64_t n0, int s, int nb, const int64_t* rp, const int32_t* ci, const double* v,
+                       const double* Sinv, const double* r0, double* w, double* x, const int32_t* stop,
+                       hipStream_t st);
+// pr_coarse.hip: z += P0 A0^{-1} R0 r (no-op without a coarse space)
+int coarse_add(pr_handle h, const double* r, double* z, const int32_t* stop);
 
 // pr_mlp.hip: Algorithm 1 with the learned predictor
 int run_alg1_mlp(pr_handle h);
