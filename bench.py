@@ -38,8 +38,9 @@ Beside the headline line's throughput:
       either stops at the iteration cap, the speedups compare equal iteration
       counts, not equal accuracy;
   equal_tol: Q2 diffusion on 32^3 hexes with the lognormal coefficient, where
-      both paths converge: iterations to the tolerance, their ratio against
-      the 1.10 bar, setup + solve time of each path, and the final error
+      both paths converge, with the two-level combination of Eq.(2) and
+      without it: iterations to the tolerance, their ratio against the 1.10
+      bar, setup + solve time of each path, and the final error
       ||x - x_o|| / ||x_o|| against the oracle's FP64 all-patch solution x_o
       (computed on the host, outside every timed region);
   apply_protocol: the preconditioner application alone, 5 warm-ups and 50
@@ -97,7 +98,7 @@ def parse():
     ap.add_argument("--no-full", action="store_true", help="skip the full FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-size", type=int, default=12, help="cells per direction of the CPU sample")
-    ap.add_argument("--equal-tol", action="store_true", help="add the equal-tolerance block")
+    ap.add_argument("--no-equal-tol", action="store_true", help="skip the equal-tolerance block")
     ap.add_argument("--tol-size", type=int, default=32, help="cells per direction of the equal-tolerance workload")
     ap.add_argument("--tol-max-iters", type=int, default=3000)
     ap.add_argument("--oracle-tol", type=float, default=1e-10,
@@ -370,13 +371,29 @@ def copy_probe(mib=1024, reps=10):
             "gbs": round(2 * (mib << 20) / (t * 1e-6) / 1e9, 1), "kernel": "torch copy_ (float64)"}
 
 
+def oracle_solution(P, b, tol):
+    """The oracle's FP64 solution of A x = b: GMRES(30) to `tol` with every
+    patch factored and the two-level combination of Eq.(2) (host)."""
+    import numpy as np
+
+    import oracle as O
+    cnt, W = O.cover_weights(P.n, P.ptr, P.dofs)
+    tiles = O.patch_tiles_csr(P.A, P.ptr, P.dofs)
+    X = O.batch_inverse(tiles)
+    prec = O.combo_preconditioner(P.A, P.ptr, P.dofs, W, X, np.arange(P.n_p), P.meta["P0"])
+    return O.gmres(lambda v: P.A @ v, prec, b, tol=tol, restart=30, max_iters=2000)
+
+
 def equal_tol_block(args):
     """Both paths to the tolerance on Q2 diffusion, 32^3 hexes, lognormal
-    coefficient: compressed (Algorithm 1, eps 0.55; BF16X3 and plain BF16
-    applies) against the all-patch FP64 path.  Setup + solve wall time per
-    path (median of the timed steps), iterations and their ratio to the full
-    path, and the final error against the oracle's all-patch FP64 solution,
-    which is computed afterwards on the host."""
+    coefficient: compressed (Algorithm 1, eps 0.55, 4.8 % of the patches
+    factored; BF16X3 and plain BF16 applies; first and closest matching)
+    against the all-patch FP64 path, each with the two-level combination of
+    Eq.(2) and, for context, without it.  Per path: iterations, their ratio
+    to the full path of the same level, setup (pr_setup plus pr_set_coarse)
+    and solve time, end-to-end wall time (median of the timed steps), and the
+    final error against the oracle's FP64 solution, which is computed
+    afterwards on the host."""
     import numpy as np
     import torch
 
@@ -392,25 +409,34 @@ def equal_tol_block(args):
     val = t(P.A.data, torch.float64)
     ptr = t(P.ptr.astype(np.int64), torch.int64)
     dofs = t(P.dofs.astype(np.int32), torch.int32)
+    P0 = P.meta["P0"]
+    p0 = (t(P0.indptr.astype(np.int64), torch.int64), t(P0.indices.astype(np.int32), torch.int32),
+          t(P0.data, torch.float64))
     b = t(b_np, torch.float64)
     stream = pr._stream()
     common = dict(restart=30, max_iters=args.tol_max_iters, deterministic=True, stream=stream)
+    comp = dict(algo="tolerance", eps=0.55, **common)
     legs = {
-        "compressed_bf16x3": dict(algo="tolerance", eps=0.55, precision="bf16x3", **common),
-        "compressed_bf16": dict(algo="tolerance", eps=0.55, precision="bf16", **common),
-        "full_fp64": dict(algo="full", precision="fp64", **common),
+        "full_fp64": (dict(algo="full", precision="fp64", **common), True),
+        "compressed_bf16x3": (dict(precision="bf16x3", **comp), True),
+        "compressed_bf16": (dict(precision="bf16", **comp), True),
+        "compressed_bf16x3_closest": (dict(precision="bf16x3", alg1_match="closest", **comp), True),
+        "full_fp64_one_level": (dict(algo="full", precision="fp64", **common), False),
+        "compressed_bf16x3_one_level": (dict(precision="bf16x3", **comp), False),
     }
     out = {}
     xs = {}
-    for name, kw in legs.items():
+    for name, (kw, two) in legs.items():
         params = pr.make_params(**kw)
-        walls, setups, solves, last = [], [], [], None
+        walls, setups, coarse, solves, last = [], [], [], [], None
         for i in range(args.warmup + args.steps):
             x = torch.zeros_like(b)
             torch.cuda.synchronize()
             ts = time.perf_counter()
             h = pr.pr_setup(row_ptr, col, val, ptr, dofs, P.n, params)
             try:
+                if two:
+                    pr.pr_set_coarse(h, *p0, P.n, P0.shape[1])
                 rc = pr.pr_solve(h, b, x, args.tol)
                 info, st = pr.pr_get_solve_info(h), pr.pr_get_stats(h)
             finally:
@@ -420,38 +446,45 @@ def equal_tol_block(args):
             if i >= args.warmup:
                 walls.append(wall)
                 setups.append(st["t_total"])
+                coarse.append(st["t_coarse"])
                 solves.append(info["seconds"])
             last = (rc, info, st)
         rc, info, st = last
         xs[name] = x.cpu().numpy()
-        out[name] = {"iters": int(info["iters"]), "converged": rc == pr.PR_OK, "relres": info["relres"],
-                     "m_p": int(st["m_p"]), "setup_s": round(float(np.median(setups)), 5),
+        out[name] = {"two_level": two, "iters": int(info["iters"]), "converged": rc == pr.PR_OK,
+                     "relres": info["relres"], "m_p": int(st["m_p"]),
+                     "setup_s": round(float(np.median(setups)), 5),
+                     "coarse_setup_s": round(float(np.median(coarse)), 5),
                      "solve_s": round(float(np.median(solves)), 5),
                      "e2e_s": round(float(np.median(walls)), 5)}
+        if two:
+            out[name]["coarse"] = {"n0": int(st["n_coarse"]), "nnz": int(st["coarse_nnz"]),
+                                   "bandwidth": int(st["coarse_bandwidth"]), "block": int(st["coarse_block"]),
+                                   "blocks": int(st["coarse_blocks"])}
         log(f"[equal tol {name}] iters {info['iters']} relres {info['relres']:.3e} "
-            f"setup {out[name]['setup_s']:.4f}s solve {out[name]['solve_s']:.4f}s")
-    # the oracle's all-patch FP64 solution (host, outside every timed region)
-    import oracle as O
+            f"setup {out[name]['setup_s']:.4f}s (+ coarse {out[name]['coarse_setup_s']:.4f}s) "
+            f"solve {out[name]['solve_s']:.4f}s")
     t0 = time.perf_counter()
-    cnt, W = O.cover_weights(P.n, P.ptr, P.dofs)
-    tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
-    X = [O.factor_inverse(T) for T in tiles]
-    prec = O.make_preconditioner(P.A, P.ptr, P.dofs, W, X, np.arange(P.n_p))
-    x_o, oinfo = O.gmres(lambda v: P.A @ v, prec, b_np, tol=args.oracle_tol, restart=30, max_iters=5000)
+    log("equal tol: oracle FP64 solution on the host ...")
+    x_o, oinfo = oracle_solution(P, b_np, args.oracle_tol)
     t_oracle = time.perf_counter() - t0
     nx = float(np.linalg.norm(x_o))
     for name in out:
         out[name]["rel_err_vs_oracle"] = float(np.linalg.norm(xs[name] - x_o) / nx)
-    full = out["full_fp64"]
-    for name in ("compressed_bf16x3", "compressed_bf16"):
-        c = out[name]
-        c["iter_ratio"] = round(c["iters"] / max(full["iters"], 1), 4)
-        c["meets_iter_bar_1.10"] = bool(c["converged"] and full["converged"] and c["iter_ratio"] <= 1.10)
-        c["e2e_speedup_vs_full"] = round(full["e2e_s"] / c["e2e_s"], 4)
+    for name, rec in out.items():
+        if name.startswith("full"):
+            continue
+        full = out["full_fp64" if rec["two_level"] else "full_fp64_one_level"]
+        rec["iter_ratio"] = round(rec["iters"] / max(full["iters"], 1), 4)
+        rec["meets_iter_bar_1.10"] = bool(rec["converged"] and full["converged"] and rec["iter_ratio"] <= 1.10)
+        rec["e2e_speedup_vs_full"] = round(full["e2e_s"] / rec["e2e_s"], 4)
     return {"workload": f"q2_hex_lognormal_{args.tol_size}", "n": P.n, "n_p": P.n_p, "tol": args.tol,
-            "database": "algorithm 1, spectral criterion, eps=0.55", "paths": out,
-            "oracle": {"solver": "all-patch FP64 GMRES(30), MGS", "tol": args.oracle_tol,
-                       "iters": int(oinfo["iters"]), "relres": oinfo["relres"],
+            "database": "algorithm 1, spectral criterion, eps=0.55",
+            "two_level": "Eq.(2): P0 linear interpolation from the interior mesh vertices, A0 = P0^T A P0 "
+                         "solved directly (block LU over its band)",
+            "paths": out,
+            "oracle": {"solver": "all-patch FP64 GMRES(30) with the two-level combination, MGS",
+                       "tol": args.oracle_tol, "iters": int(oinfo["iters"]), "relres": oinfo["relres"],
                        "seconds": round(t_oracle, 2)}}
 
 
@@ -663,7 +696,7 @@ def main():
             proto[path] = rec
         line["apply_protocol"] = proto
         line["hbm_copy_probe"] = g["copy_probe"]
-    if args.equal_tol and args.workload == "nedelec_hex":
+    if not args.no_equal_tol and args.workload == "nedelec_hex":
         log("equal-tolerance block (q2 hex lognormal) ...")
         line["equal_tol"] = equal_tol_block(args)
     if not args.no_cpu:

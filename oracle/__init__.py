@@ -15,7 +15,7 @@ forms, brute force on tiny inputs, library routines used as a different route,
 and invariants the paper states.  Functions without such a pin say
 "parity unpinned" in their docstring.
 """
-from .patch import (OracleError, cover_weights, patch_tiles, boundary_mask,
+from .patch import (OracleError, cover_weights, patch_tiles, patch_tiles_csr, batch_inverse, boundary_mask,
                     factor_inverse, apply_patch, apply_operator_dense, storage_bytes,
                     objective)
 from .criterion import crit_spectral, crit_spectral_x, crit_l1, crit_fro, criterion
@@ -27,7 +27,7 @@ from .twolevel import linear_interpolation, coarse_operator, combo_preconditione
 from .lowprec import round_fp32, round_bf16, round_fp16, apply_lowprec, fp16_scale_exp
 
 __all__ = [
-    "OracleError", "cover_weights", "patch_tiles", "boundary_mask", "factor_inverse",
+    "OracleError", "cover_weights", "patch_tiles", "patch_tiles_csr", "batch_inverse", "boundary_mask", "factor_inverse",
     "apply_patch", "apply_operator_dense", "storage_bytes", "objective",
     "crit_spectral", "crit_spectral_x", "crit_l1", "crit_fro", "criterion",
     "alg1_tolerance", "alg1_closest", "compressibility", "kmeans", "partition_groups", "apportion", "SplitMix64",

@@ -44,6 +44,39 @@ def patch_tiles(A, ptr, dofs, ks=None):
     return out
 
 
+def patch_tiles_csr(A, ptr, dofs):
+    """The same tiles A_k = V_k A V_k^T read straight from the CSR arrays:
+    entry (a, b) of patch k is the stored value at row dofs_k[a], column
+    dofs_k[b], found by binary search of the key row * n + column in the
+    sorted list of stored keys, or 0.0 where nothing is stored.  Patches of
+    one size are read together.  Returns a list of dense float64 arrays."""
+    A = A.tocsr()
+    A.sort_indices()
+    n = A.shape[0]
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(A.indptr))
+    keys = rows * n + A.indices.astype(np.int64)
+    sizes = np.diff(ptr)
+    out = [None] * (len(ptr) - 1)
+    for p in np.unique(sizes):
+        ks = np.flatnonzero(sizes == p)
+        D = np.stack([dofs[ptr[k]:ptr[k + 1]] for k in ks]).astype(np.int64)
+        want = (D[:, :, None] * n + D[:, None, :]).ravel()
+        pos = np.searchsorted(keys, want)
+        pos = np.minimum(pos, len(keys) - 1)
+        hit = keys[pos] == want
+        vals = np.where(hit, A.data[pos], 0.0).reshape(len(ks), p, p)
+        for t, k in enumerate(ks):
+            out[k] = vals[t]
+    return out
+
+
+def batch_inverse(tiles):
+    """Inverses of equal-size patch matrices by LAPACK's LU with partial
+    pivoting (numpy.linalg.inv on the stacked tiles): the operator of
+    factor_inverse, computed for many tiles at once."""
+    return list(np.linalg.inv(np.stack(tiles)))
+
+
 def boundary_mask(tile) -> int:
     """Boundary-condition key of a patch (Section 3.2, boundary partitioning).
 

@@ -402,3 +402,22 @@ def test_bf16_split_pins():
     assert hi[1] == 3.0 and lo[1] == 0.0
     # the split keeps about 16 significant bits
     assert abs(hi[2] + lo[2] - 1.0 / 3.0) <= 2.0 ** -17 / 3.0
+
+
+@pytest.mark.parametrize("make", [lambda: gen.q2_hex_diffusion(4), lambda: gen.nedelec_hex(4),
+                                  lambda: gen.uneven_stokes_batch(n_sys=3, nmin=2, nmax=4)])
+def test_csr_tile_read_equals_fancy_indexing(make):
+    P = make()
+    a = O.patch_tiles(P.A, P.ptr, P.dofs)
+    b = O.patch_tiles_csr(P.A, P.ptr, P.dofs)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_batch_inverse_equals_factor_inverse():
+    P = gen.q2_hex_diffusion(4)
+    tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
+    X1 = [O.factor_inverse(t) for t in tiles]
+    X2 = O.batch_inverse(tiles)
+    for t, x1, x2 in zip(tiles, X1, X2):
+        k = np.linalg.cond(t)
+        assert np.abs(x1 - x2).max() <= 64 * k * 2.2e-16 * np.abs(x1).max()
