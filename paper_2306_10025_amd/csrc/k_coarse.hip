@@ -13,10 +13,13 @@
 //    where D_i, L_i, U_i are the diagonal, sub- and super-diagonal blocks.
 //  Dense inverses: blocked Gauss-Jordan in place, 32-wide panels, the rank-32
 //  updates on the FP64 matrix cores (16 x 16 x 4 MFMA), partial pivoting
-//  inside each 32 x 32 pivot block.
-// Apply: r0 = R0 r; forward sweep w_i = S_i^{-1} (r0_i - L_i w_{i-1});
-// backward sweep x_i = w_i - S_i^{-1} U_i x_{i+1}; z += P0 x.  Every kernel
-// returns at once when the solve's stop flag is set (graph replays).
+//  inside each 32 x 32 pivot block (Gauss-Jordan in registers).
+// The banded form also keeps G_i = S_i^{-1} L_i and H_i = S_i^{-1} U_i, so
+// that the sequential sweeps are dense matrix-vector products only.
+// Apply: r0 = R0 r; u_i = S_i^{-1} r0_i for every block at once; forward
+// sweep w_i = u_i - G_i w_{i-1}; backward sweep x_i = w_i - H_i x_{i+1};
+// z += P0 x.  Every kernel returns at once when the solve's stop flag is set
+// (graph replays).
 #include "dense_dev.h"
 
 #include <climits>
@@ -240,14 +243,13 @@ __global__ void k_bandwidth(int64_t n0, const int64_t* __restrict__ rp, const in
 }
 
 // ---- dense blocks -----------------------------------------------------------
-// S (s x s, row-major) = block (bi, bj) of A0 minus Y U (when Y is given):
-// S[a][c] = A0[bi s + a][bj s + c] - sum_r Y[a][r] A0[(bi - 1) s + r][bi s + c];
-// rows or columns beyond n0 form an identity (padding of the last block).
-__global__ void k_block_schur(int64_t n0, int s, int bi, const int64_t* __restrict__ rp,
-                              const int32_t* __restrict__ ci, const double* __restrict__ v,
-                              const int64_t* __restrict__ trp, const int32_t* __restrict__ tci,
-                              const double* __restrict__ tv, const double* __restrict__ Y,
-                              double* __restrict__ S) {
+// S (s x s) = D_bi - L_bi H_{bi-1} with H_{bi-1} = Sinv_{bi-1} U_{bi-1} given
+// (Hprev; S = D_0 for bi = 0): S[a][c] = A0[bi s + a][bi s + c] - sum over the
+// entries (r, v) of A0 row bi s + a in block bi - 1 of v H[r][c].  Rows or
+// columns beyond n0 form an identity.
+__global__ void k_block_schur_h(int64_t n0, int s, int bi, const int64_t* __restrict__ rp,
+                                const int32_t* __restrict__ ci, const double* __restrict__ v,
+                                const double* __restrict__ Hprev, double* __restrict__ S) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= (int64_t)s * s) return;
     const int a = (int)(q / s), c = (int)(q % s);
@@ -256,50 +258,35 @@ __global__ void k_block_schur(int64_t n0, int s, int bi, const int64_t* __restri
         S[q] = (a == c) ? 1.0 : 0.0;
         return;
     }
-    // A0[ga][gc] by binary search in the sorted row
-    int64_t lo = rp[ga], hi = rp[ga + 1];
-    double d = 0.0;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        const int32_t cm = ci[mid];
-        if (cm == gc) {
-            d = v[mid];
-            break;
-        }
-        if (cm < gc) lo = mid + 1;
-        else hi = mid;
+    const int64_t r0 = (int64_t)(bi - 1) * s;
+    double d = 0.0, acc = 0.0;
+    for (int64_t e = rp[ga]; e < rp[ga + 1]; ++e) {
+        const int64_t col = ci[e];
+        const double val = v[e];
+        if (col == gc) d = val;
+        if (Hprev && col >= r0 && col < r0 + s) acc += val * Hprev[(col - r0) * s + c];
     }
-    if (Y && bi > 0) {
-        // column gc of A0 = row gc of its transpose; rows r of block bi - 1
-        const int64_t r0 = (int64_t)(bi - 1) * s;
-        double acc = 0.0;
-        for (int64_t e = trp[gc]; e < trp[gc + 1]; ++e) {
-            const int64_t r = tci[e];
-            if (r >= r0 && r < r0 + s) acc += Y[(int64_t)a * s + (r - r0)] * tv[e];
-        }
-        d -= acc;
-    }
-    S[q] = d;
+    S[q] = d - acc;
 }
 
-// Y (s x s) = L_bi Sinv_prev: row a of Y sums the rows of Sinv_prev named by
-// the entries of A0 row bi s + a that fall in block bi - 1
-__global__ void k_block_lsinv(int64_t n0, int s, int bi, const int64_t* __restrict__ rp,
-                              const int32_t* __restrict__ ci, const double* __restrict__ v,
-                              const double* __restrict__ Sprev, double* __restrict__ Y) {
-    for (int a = blockIdx.x; a < s; a += gridDim.x) {
-        const int64_t ga = (int64_t)bi * s + a;
-        const int64_t c0 = (int64_t)(bi - 1) * s;
-        for (int c = threadIdx.x; c < s; c += blockDim.x) {
-            double acc = 0.0;
-            if (ga < n0)
-                for (int64_t e = rp[ga]; e < rp[ga + 1]; ++e) {
-                    const int64_t col = ci[e];
-                    if (col >= c0 && col < c0 + s) acc += v[e] * Sprev[(col - c0) * s + c];
-                }
-            Y[(int64_t)a * s + c] = acc;
+// out (s x s) = Sinv_bi C where C = block (bi, bj) of A0, read by columns
+// from the transpose: out[a][c] = sum over the entries (r, v) of A0^T row
+// bj s + c with r in block bi of Sinv[a][r - bi s] v.
+__global__ void k_block_coupling(int64_t n0, int s, int bi, int bj, const int64_t* __restrict__ trp,
+                                 const int32_t* __restrict__ tci, const double* __restrict__ tv,
+                                 const double* __restrict__ Sinv, double* __restrict__ out) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (int64_t)s * s) return;
+    const int a = (int)(q / s), c = (int)(q % s);
+    const int64_t gc = (int64_t)bj * s + c;
+    const int64_t r0 = (int64_t)bi * s;
+    double acc = 0.0;
+    if (gc < n0)
+        for (int64_t e = trp[gc]; e < trp[gc + 1]; ++e) {
+            const int64_t r = tci[e];
+            if (r >= r0 && r < r0 + s) acc += Sinv[(int64_t)a * s + (r - r0)] * tv[e];
         }
-    }
+    out[q] = acc;
 }
 
 // dense n0 x n0 (padded to np) copy of A0, identity on the padding
@@ -317,6 +304,67 @@ __global__ void k_dense_from_csr(int64_t n0, int64_t np, const int64_t* __restri
 }
 
 // ---- blocked Gauss-Jordan inverse in place (s multiple of 32) ----------------
+// Inverse of the 32 x 32 row-major matrix in sP into sI by Gauss-Jordan
+// elimination with partial pivoting, one wavefront: lane c holds column c of
+// the augmented matrix [P | I] (rows 0..31) in registers.  Step k: lane k
+// picks the pivot row (largest |a_rk| over the rows not yet used, lowest row
+// on ties); every lane scales its pivot-row element, and the factors (column
+// k, held by lane k) reach every lane by readlane, so no step touches LDS.
+// Row piv_k of the right half ends as row k of the inverse.  Returns nonzero
+// on a zero pivot.
+__device__ __forceinline__ double bcast(double v, int src) {
+    const int2 t = *reinterpret_cast<const int2*>(&v);
+    int2 r;
+    r.x = __builtin_amdgcn_readlane(t.x, src);
+    r.y = __builtin_amdgcn_readlane(t.y, src);
+    return *reinterpret_cast<const double*>(&r);
+}
+
+__device__ int reg_gj32(const double* sP, double* sI, int* srow, int lane) {
+    double a[32];
+#pragma unroll
+    for (int r = 0; r < 32; ++r)
+        a[r] = lane < 32 ? sP[r * 32 + lane] : ((r == lane - 32) ? 1.0 : 0.0);
+    uint32_t used = 0;
+    int bad = 0;
+#pragma unroll 1
+    for (int k = 0; k < 32; ++k) {
+        // pivot search in lane k's registers (other lanes compute alongside)
+        double best = -1.0;
+        int bi = 0;
+#pragma unroll
+        for (int r = 0; r < 32; ++r) {
+            const double v = fabs(a[r]);
+            if (!((used >> r) & 1u) && v > best) {
+                best = v;
+                bi = r;
+            }
+        }
+        const int piv = __builtin_amdgcn_readlane(bi, k);
+        best = bcast(best, k);
+        if (!(best > 0.0)) bad = 1;
+        used |= 1u << piv;
+        if (lane == 0) srow[piv] = k;
+        double pv = 0.0;
+#pragma unroll
+        for (int r = 0; r < 32; ++r) pv = (r == piv) ? a[r] : pv;
+        const double inv = 1.0 / bcast(pv, k);
+        pv *= inv;
+#pragma unroll
+        for (int r = 0; r < 32; ++r) {
+            const double f = bcast(a[r], k);
+            a[r] = (r == piv) ? pv : fma(-f, pv, a[r]);
+        }
+    }
+    __syncthreads();
+    if (lane >= 32) {
+#pragma unroll
+        for (int r = 0; r < 32; ++r) sI[srow[r] * 32 + (lane - 32)] = a[r];
+    }
+    __syncthreads();
+    return bad;
+}
+
 // Panel k: P = M[k][k] (32 x 32 tile) is inverted in LDS; the row panel becomes
 // M[k][j] <- P^{-1} M[k][j]; the column panel's old tiles go to C.
 __global__ __launch_bounds__(64) void k_gj_panel(double* __restrict__ M, int s, int k,
@@ -325,13 +373,13 @@ __global__ __launch_bounds__(64) void k_gj_panel(double* __restrict__ M, int s, 
     __shared__ double sP[32 * 32];
     __shared__ double sI[32 * 32];
     __shared__ double sT[32 * 32];
+    __shared__ int srow[32];
     const int lane = threadIdx.x;
     const int j = blockIdx.x;
     const int64_t ks = (int64_t)k * 32;
     for (int e = lane; e < 1024; e += PR_WAVE) sP[e] = M[(ks + e / 32) * s + ks + e % 32];
     __syncthreads();
-    const int bad = gj_invert<32, 32>(sP, sI, 32, lane & 31);
-    __syncthreads();
+    const int bad = reg_gj32(sP, sI, srow, lane);
     if (bad && lane == 0) atomicOr(info, 1);
     if (j == k) {
         for (int e = lane; e < 1024; e += PR_WAVE) Pinv[e] = sI[e];
@@ -439,54 +487,44 @@ __global__ __launch_bounds__(256) void k_dense_gemv(int64_t np, const double* __
     }
 }
 
-// Block step of the banded solve.  fwd: y = r0_i - L_i w_{i-1};
-// w_i = Sinv_i y.  bwd: t = U_i x_{i+1}; x_i = w_i - Sinv_i t (the last block
-// copies x = w).  Every workgroup forms the s-vector in LDS, then its waves
-// take rows of Sinv_i.
-template <bool FWD>
-__global__ __launch_bounds__(256) void k_band_step(int64_t n0, int s, int nb, int bi,
-                                                   const int64_t* __restrict__ rp,
-                                                   const int32_t* __restrict__ ci,
-                                                   const double* __restrict__ v,
-                                                   const double* __restrict__ Sinv,
-                                                   const double* __restrict__ r0, double* __restrict__ w,
-                                                   double* __restrict__ x, const int32_t* stop) {
-    extern __shared__ double sy[];
+// u_i = Sinv_i r0_i for every block i at once (one wavefront per row)
+__global__ __launch_bounds__(256) void k_band_diag(int s, int nb, const double* __restrict__ Sinv,
+                                                   const double* __restrict__ r0, double* __restrict__ u,
+                                                   const int32_t* stop) {
     if (stopped(stop)) return;
-    const int64_t base = (int64_t)bi * s;
-    if (!FWD && bi == nb - 1) {
-        for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < s;
-             a += (int64_t)gridDim.x * blockDim.x)
-            x[base + a] = w[base + a];
-        return;
-    }
-    // neighbour block: i - 1 (forward) or i + 1 (backward)
-    const int64_t nbase = FWD ? base - s : base + s;
-    const double* nv = FWD ? w : x;
-    for (int a = threadIdx.x; a < s; a += blockDim.x) {
-        const int64_t g = base + a;
-        double acc = 0.0;
-        if (g < n0 && (FWD ? bi > 0 : true))
-            for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
-                const int64_t c = ci[e];
-                if (c >= nbase && c < nbase + s) acc += v[e] * nv[c];
-            }
-        sy[a] = FWD ? ((g < n0 ? r0[g] : 0.0) - acc) : acc;
-    }
-    __syncthreads();
     const int lane = threadIdx.x & (PR_WAVE - 1);
-    const int wv = threadIdx.x / PR_WAVE;
-    const int nwv = blockDim.x / PR_WAVE;
-    const double* Si = Sinv + (int64_t)bi * s * s;
-    for (int64_t row = (int64_t)blockIdx.x * nwv + wv; row < s; row += (int64_t)gridDim.x * nwv) {
-        const double* sr = Si + row * s;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / PR_WAVE;
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / PR_WAVE;
+    const int64_t rows = (int64_t)nb * s;
+    for (int64_t g = w0; g < rows; g += nw) {
+        const int64_t bi = g / s, a = g % s;
+        const double* sr = Sinv + bi * s * s + a * s;
+        const double* in = r0 + bi * s;
         double acc = 0.0;
-        for (int c = lane; c < s; c += PR_WAVE) acc += sr[c] * sy[c];
+        for (int c = lane; c < s; c += PR_WAVE) acc += sr[c] * in[c];
         acc = wave_sum(acc);
-        if (lane == 0) {
-            if (FWD) w[base + row] = acc;
-            else x[base + row] = w[base + row] - acc;
+        if (lane == 0) u[g] = acc;
+    }
+}
+
+// out_i = in_i - M_i x_j (x_j the neighbouring block: j = i - 1 forward with
+// M = G_i = Sinv_i L_i, j = i + 1 backward with M = H_i = Sinv_i U_i); one
+// wavefront per row
+__global__ __launch_bounds__(256) void k_band_couple(int s, const double* __restrict__ M,
+                                                     const double* __restrict__ in, const double* __restrict__ xj,
+                                                     double* __restrict__ out, const int32_t* stop) {
+    if (stopped(stop)) return;
+    const int lane = threadIdx.x & (PR_WAVE - 1);
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / PR_WAVE;
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / PR_WAVE;
+    for (int64_t a = w0; a < s; a += nw) {
+        double acc = 0.0;
+        if (M) {
+            const double* mr = M + a * s;
+            for (int c = lane; c < s; c += PR_WAVE) acc += mr[c] * xj[c];
+            acc = wave_sum(acc);
         }
+        if (lane == 0) out[a] = in[a] - acc;
     }
 }
 
@@ -538,17 +576,6 @@ void launch_bandwidth(int64_t n0, const int64_t* rp, const int32_t* ci, int32_t*
     k_bandwidth<<<nbk(n0, 256), 256, 0, st>>>(n0, rp, ci, bw);
 }
 
-void launch_block_schur(int64_t n0, int s, int bi, const int64_t* rp, const int32_t* ci, const double* v,
-                        const int64_t* trp, const int32_t* tci, const double* tv, const double* Y, double* S,
-                        hipStream_t st) {
-    k_block_schur<<<nbk((int64_t)s * s, 256), 256, 0, st>>>(n0, s, bi, rp, ci, v, trp, tci, tv, Y, S);
-}
-
-void launch_block_lsinv(int64_t n0, int s, int bi, const int64_t* rp, const int32_t* ci, const double* v,
-                        const double* Sprev, double* Y, hipStream_t st) {
-    k_block_lsinv<<<(unsigned)(s < 4096 ? s : 4096), 256, 0, st>>>(n0, s, bi, rp, ci, v, Sprev, Y);
-}
-
 void launch_dense_from_csr(int64_t n0, int64_t np, const int64_t* rp, const int32_t* ci, const double* v,
                            double* M, hipStream_t st) {
     k_dense_from_csr<<<(unsigned)(np < 16384 ? np : 16384), 256, 0, st>>>(n0, np, rp, ci, v, M);
@@ -581,14 +608,31 @@ void launch_dense_gemv(int64_t np, const double* X, const double* in, double* ou
     k_dense_gemv<<<(unsigned)(blocks < 8192 ? blocks : 8192), 256, 0, st>>>(np, X, in, out, stop);
 }
 
-void launch_band_solve(int64_t n0, int s, int nb, const int64_t* rp, const int32_t* ci, const double* v,
-                       const double* Sinv, const double* r0, double* w, double* x, const int32_t* stop,
-                       hipStream_t st) {
-    // one workgroup per 8 rows of S_i^{-1} (4 waves, 2 rows each per pass)
-    const unsigned g = (unsigned)((s + 7) / 8);
-    const size_t lds = (size_t)s * sizeof(double);
+void launch_block_schur_h(int64_t n0, int s, int bi, const int64_t* rp, const int32_t* ci, const double* v,
+                          const double* Hprev, double* S, hipStream_t st) {
+    k_block_schur_h<<<nbk((int64_t)s * s, 256), 256, 0, st>>>(n0, s, bi, rp, ci, v, Hprev, S);
+}
+
+void launch_block_coupling(int64_t n0, int s, int bi, int bj, const int64_t* trp, const int32_t* tci,
+                           const double* tv, const double* Sinv, double* out, hipStream_t st) {
+    k_block_coupling<<<nbk((int64_t)s * s, 256), 256, 0, st>>>(n0, s, bi, bj, trp, tci, tv, Sinv, out);
+}
+
+// x = A0^{-1} r0 from the block LU: u_i = Sinv_i r0_i (all blocks together);
+// w_0 = u_0, w_i = u_i - G_i w_{i-1}; x_{nb-1} = w_{nb-1},
+// x_i = w_i - H_i x_{i+1}.  G, H: nb blocks of s x s (G_0, H_{nb-1} unused).
+void launch_band_solve(int s, int nb, const double* Sinv, const double* G, const double* H, const double* r0,
+                        double* u, double* w, double* x, const int32_t* stop, hipStream_t st) {
+    const int64_t blk = (int64_t)s * s;
+    const int64_t rows = (int64_t)nb * s;
+    const int64_t b1 = (rows + 3) / 4;
+    k_band_diag<<<(unsigned)(b1 < 16384 ? b1 : 16384), 256, 0, st>>>(s, nb, Sinv, r0, u, stop);
+    const unsigned g = (unsigned)((s + 3) / 4);
+    // the first forward and the last backward step couple to nothing (M null)
     for (int i = 0; i < nb; ++i)
-        k_band_step<true><<<g, 256, lds, st>>>(n0, s, nb, i, rp, ci, v, Sinv, r0, w, x, stop);
+        k_band_couple<<<g, 256, 0, st>>>(s, i == 0 ? nullptr : G + blk * i, u + (int64_t)i * s,
+                                         i == 0 ? u : w + (int64_t)(i - 1) * s, w + (int64_t)i * s, stop);
     for (int i = nb - 1; i >= 0; --i)
-        k_band_step<false><<<g, 256, lds, st>>>(n0, s, nb, i, rp, ci, v, Sinv, r0, w, x, stop);
+        k_band_couple<<<g, 256, 0, st>>>(s, i == nb - 1 ? nullptr : H + blk * i, w + (int64_t)i * s,
+                                         i == nb - 1 ? w : x + (int64_t)(i + 1) * s, x + (int64_t)i * s, stop);
 }

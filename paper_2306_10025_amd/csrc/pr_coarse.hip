@@ -39,8 +39,7 @@ int coarse_add(pr_handle h, const double* r, double* z, const int32_t* stop) {
     if (h->c_dense)
         launch_dense_gemv(h->c_np, h->c_X, h->c_r0, h->c_x, stop, s);
     else
-        launch_band_solve(h->n0, h->c_s, h->c_nb, h->a0_rp, h->a0_ci, h->a0_v, h->c_X, h->c_r0, h->c_w, h->c_x,
-                          stop, s);
+        launch_band_solve(h->c_s, h->c_nb, h->c_X, h->c_G, h->c_H, h->c_r0, h->c_u, h->c_w, h->c_x, stop, s);
     launch_csr_rows_add(h->n, h->p0_rp, h->p0_ci, h->p0_v, h->c_x, z, stop, s);
     return PR_OK;
 }
@@ -140,7 +139,7 @@ int pr_set_coarse(pr_handle h, const pr_interp* P) {
     int dense = n0 <= kDenseMax ? 1 : 0;
     int64_t np = 0, len = 0;
     int sb = 0, nbk = 0;
-    double* X = nullptr;
+    double *X = nullptr, *G = nullptr, *H = nullptr;
     int64_t *a0t_rp = nullptr;
     int32_t* a0t_ci = nullptr;
     double* a0t_v = nullptr;
@@ -166,18 +165,20 @@ int pr_set_coarse(pr_handle h, const pr_interp* P) {
         if (launch_csr_transpose(n0, n0, a0_rp, a0_ci, a0_v, a0t_rp, a0t_ci, a0t_v, cnt, fill, scr, s) != 0)
             return pr_fail(h, PR_ERR_HIP, "transpose of A0");
         const size_t blk = (size_t)sb * sb;
-        double* Y = nullptr;
         PR_TRY(dalloc(h, &X, blk * nbk));
-        PR_TRY(dalloc(h, &Y, blk));
+        PR_TRY(dalloc(h, &G, blk * nbk));
+        PR_TRY(dalloc(h, &H, blk * nbk));
         PR_TRY(dalloc(h, &cbuf, (size_t)sb * 32));
+        // S_i = D_i - L_i H_{i-1}, inverted in place; G_i = S_i^{-1} L_i,
+        // H_i = S_i^{-1} U_i
         for (int i = 0; i < nbk; ++i) {
             double* Si = X + blk * i;
-            if (i > 0) launch_block_lsinv(n0, sb, i, a0_rp, a0_ci, a0_v, Si - blk, Y, s);
-            launch_block_schur(n0, sb, i, a0_rp, a0_ci, a0_v, a0t_rp, a0t_ci, a0t_v, i > 0 ? Y : nullptr, Si, s);
+            launch_block_schur_h(n0, sb, i, a0_rp, a0_ci, a0_v, i > 0 ? H + blk * (i - 1) : nullptr, Si, s);
             launch_gj_inverse(Si, sb, pinv, cbuf, info, s);
+            if (i > 0) launch_block_coupling(n0, sb, i, i - 1, a0t_rp, a0t_ci, a0t_v, Si, G + blk * i, s);
+            if (i < nbk - 1) launch_block_coupling(n0, sb, i, i + 1, a0t_rp, a0t_ci, a0t_v, Si, H + blk * i, s);
         }
         PR_HIP(h, hipStreamSynchronize(s));
-        dfree(h, Y);
     }
     int32_t bad = 0;
     PR_HIP(h, hipMemcpyAsync(&bad, info, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -186,8 +187,9 @@ int pr_set_coarse(pr_handle h, const pr_interp* P) {
     if (bad) return pr_fail(h, PR_ERR_SINGULAR_PATCH, "zero pivot in the coarse factorisation");
     dfree(h, cbuf);
 
-    double *cr0 = nullptr, *cw = nullptr, *cx = nullptr;
+    double *cr0 = nullptr, *cu = nullptr, *cw = nullptr, *cx = nullptr;
     PR_TRY(dalloc(h, &cr0, len));
+    PR_TRY(dalloc(h, &cu, len));
     PR_TRY(dalloc(h, &cw, len));
     PR_TRY(dalloc(h, &cx, len));
     // the padding of the coarse vectors stays zero (kernels write rows < n0
@@ -212,7 +214,10 @@ int pr_set_coarse(pr_handle h, const pr_interp* P) {
     h->c_s = sb;
     h->c_nb = dense ? 1 : nbk;
     h->c_X = X;
+    h->c_G = G;
+    h->c_H = H;
     h->c_r0 = cr0;
+    h->c_u = cu;
     h->c_w = cw;
     h->c_x = cx;
     h->stats.n_coarse = n0;

@@ -209,7 +209,8 @@ struct pr_handle_s {
     int c_dense = 0, c_s = 0, c_nb = 0;
     int64_t c_np = 0;
     double* c_X = nullptr;
-    double *c_r0 = nullptr, *c_w = nullptr, *c_x = nullptr;
+    double *c_G = nullptr, *c_H = nullptr;   // S_i^{-1} L_i and S_i^{-1} U_i (banded form)
+    double *c_r0 = nullptr, *c_u = nullptr, *c_w = nullptr, *c_x = nullptr;
 
     pr_solve_info sinfo{};
     pr_stats stats{};
@@ -482,11 +483,6 @@ void launch_rows_finish(int64_t n0, const int32_t* cnt32, int64_t* cnt64, int64_
 void launch_rows_compact(int64_t n0, const int64_t* rp, const int32_t* icol, const double* ival, int32_t* ocol,
                          double* oval, hipStream_t st);
 void launch_bandwidth(int64_t n0, const int64_t* rp, const int32_t* ci, int32_t* bw, hipStream_t st);
-void launch_block_schur(int64_t n0, int s, int bi, const int64_t* rp, const int32_t* ci, const double* v,
-                        const int64_t* trp, const int32_t* tci, const double* tv, const double* Y, double* S,
-                        hipStream_t st);
-void launch_block_lsinv(int64_t n0, int s, int bi, const int64_t* rp, const int32_t* ci, const double* v,
-                        const double* Sprev, double* Y, hipStream_t st);
 void launch_dense_from_csr(int64_t n0, int64_t np, const int64_t* rp, const int32_t* ci, const double* v,
                            double* M, hipStream_t st);
 void launch_gj_inverse(double* M, int s, double* Pinv, double* C, int32_t* info, hipStream_t st);
@@ -496,9 +492,12 @@ void launch_csr_rows_add(int64_t n, const int64_t* rp, const int32_t* ci, const 
                          double* z, const int32_t* stop, hipStream_t st);
 void launch_dense_gemv(int64_t np, const double* X, const double* in, double* out, const int32_t* stop,
                        hipStream_t st);
-void launch_band_solve(int64_t n0, int s, int nb, const int64_t* rp, const int32_t* ci, const double* v,
-                       const double* Sinv, const double* r0, double* w, double* x, const int32_t* stop,
-                       hipStream_t st);
+void launch_block_schur_h(int64_t n0, int s, int bi, const int64_t* rp, const int32_t* ci, const double* v,
+                          const double* Hprev, double* S, hipStream_t st);
+void launch_block_coupling(int64_t n0, int s, int bi, int bj, const int64_t* trp, const int32_t* tci,
+                           const double* tv, const double* Sinv, double* out, hipStream_t st);
+void launch_band_solve(int s, int nb, const double* Sinv, const double* G, const double* H, const double* r0,
+                        double* u, double* w, double* x, const int32_t* stop, hipStream_t st);
 // pr_coarse.hip: z += P0 A0^{-1} R0 r (no-op without a coarse space)
 int coarse_add(pr_handle h, const double* r, double* z, const int32_t* stop);
 
