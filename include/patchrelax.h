@@ -156,6 +156,13 @@ typedef struct {
                                 database is the same).  Equal distances: entries with
                                 d <= d_min (1 + tie_rel) + tie_rel s (s = 1 spectral, sum |A_i|
                                 for l1, ||A_i||_F for Frobenius) tie and the lowest index wins */
+    int32_t flexible;        /* pr_solve without systems: 1 keeps the preconditioned vectors
+                                z_j = M v_j of a restart cycle and updates x += Z y (flexible
+                                GMRES) instead of applying M to V y; the same iterates for an
+                                exactly linear preconditioner, and no drift between the
+                                residual estimate and the true residual when the apply rounds
+                                its input to reduced precision; n x gmres_restart more
+                                doubles (default 0) */
 } pr_params;
 
 /* Interpolation P0 from n_coarse coarse unknowns to the n_fine fine ones

@@ -31,9 +31,13 @@ def make_preconditioner(A, ptr, dofs, W, X, phi, omega=1.0, sweeps=1):
     return prec
 
 
-def gmres(matvec, precond, b, tol=1e-8, restart=30, max_iters=10000):
+def gmres(matvec, precond, b, tol=1e-8, restart=30, max_iters=10000, flexible=False):
     """Right-preconditioned GMRES(restart) from x0 = 0.
 
+    ``flexible``: keep z_j = precond(v_j) and update x by Z y (flexible GMRES,
+    Saad, SIAM J. Sci. Comput. 14 (1993)) instead of precond(V y); the two
+    coincide for a linear preconditioner, and the flexible form stays exact
+    for one that is not (a reduced-precision apply rounds its input).
     Returns (x, info) with info = dict(iters, relres, converged, cycles)."""
     b = np.asarray(b, dtype=np.float64)
     n = b.shape[0]
@@ -52,6 +56,7 @@ def gmres(matvec, precond, b, tol=1e-8, restart=30, max_iters=10000):
             break
         cycles += 1
         V = np.zeros((restart + 1, n))
+        Z = np.zeros((restart, n)) if flexible else None
         H = np.zeros((restart + 1, restart))
         cs = np.zeros(restart)
         sn = np.zeros(restart)
@@ -60,7 +65,10 @@ def gmres(matvec, precond, b, tol=1e-8, restart=30, max_iters=10000):
         V[0] = r / beta
         m = 0
         for j in range(restart):
-            w = matvec(precond(V[j]))
+            zj = precond(V[j])
+            if flexible:
+                Z[j] = zj
+            w = matvec(zj)
             iters += 1
             for i in range(j + 1):                       # modified Gram-Schmidt
                 H[i, j] = float(w @ V[i])
@@ -83,7 +91,7 @@ def gmres(matvec, precond, b, tol=1e-8, restart=30, max_iters=10000):
             if abs(g[j + 1]) <= tol * bnorm or iters >= max_iters:
                 break
         y = sla.solve_triangular(H[:m, :m], g[:m])
-        x = x + precond(V[:m].T @ y)
+        x = x + (Z[:m].T @ y if flexible else precond(V[:m].T @ y))
         r = b - matvec(x)
     relres = float(np.linalg.norm(b - matvec(x))) / bnorm
     return x, dict(iters=iters, relres=relres, converged=relres <= tol, cycles=cycles)

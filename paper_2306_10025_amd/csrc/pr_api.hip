@@ -1004,6 +1004,7 @@ void pr_params_default(pr_params* p) {
     p->apply_form = PR_FORM_AUTO;
     p->alg1_prune = 1;
     p->alg1_match = 0;
+    p->flexible = 0;
 }
 
 const char* pr_status_string(int st) {
@@ -1109,7 +1110,8 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
         pm.apply_precision < 0 || pm.apply_precision > 4 || pm.sweeps < 1 || pm.gmres_restart < 1 ||
         pm.gmres_restart > 64 || !(pm.eps >= 0.0) || !(pm.omega > 0.0) ||
         (pm.apply_form != PR_FORM_AUTO && pm.apply_form != PR_FORM_GENERAL) ||
-        (pm.alg1_prune != 0 && pm.alg1_prune != 1) || (pm.alg1_match != 0 && pm.alg1_match != 1))
+        (pm.alg1_prune != 0 && pm.alg1_prune != 1) || (pm.alg1_match != 0 && pm.alg1_match != 1) ||
+        (pm.flexible != 0 && pm.flexible != 1))
         return pr_fail(nullptr, PR_ERR_INVALID_ARG, "bad parameter value");
     if (pm.alg1_match == 1 && (pm.algo != PR_ALGO_TOLERANCE || pm.mlp != 0 || !(pm.tie_rel >= 0.0)))
         return pr_fail(nullptr, PR_ERR_INVALID_ARG, "closest matching needs PR_ALGO_TOLERANCE without mlp");
@@ -1375,6 +1377,16 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
     const int m = h->prm.gmres_restart;
     const int64_t n = h->n;
     PR_TRY(ensure_workspace(h, m));
+    const bool flex = h->prm.flexible != 0;
+    if (flex && h->zb_restart < m) {
+        PR_TRY(dalloc(h, &h->Zb, (size_t)m * h->ldv));
+        h->zb_restart = m;
+        if (h->gexec) {                     // a captured cycle holds the old basis
+            (void)hipGraphExecDestroy(h->gexec);
+            h->gexec = nullptr;
+            h->graph_m = -1;
+        }
+    }
     if (use_graph) {
         // a capture needs a stream of its own; b and x live in handle memory
         // so that one captured cycle serves every later solve
@@ -1453,16 +1465,17 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
             tsel = timing && (tcyc * m + j) % tstride == 0;
             tj = j;
             double* vj = V + (int64_t)j * ldv;
+            double* zj = flex ? h->Zb + (int64_t)j * ldv : zt;   // flexible: keep z_j = M v_j
             tbeg();
-            PR_TRY(precond(h, vj, zt, t3, gctl, false));
+            PR_TRY(precond(h, vj, zj, t3, gctl, false));
             tend(0);
             if (h->n0 > 0) {
                 tbeg();
-                PR_TRY(coarse_add(h, vj, zt, gctl));
+                PR_TRY(coarse_add(h, vj, zj, gctl));
                 tend(3);
             }
             tbeg();
-            launch_spmv_sell(h->sell(), n, zt, nullptr, w, s, gctl);
+            launch_spmv_sell(h->sell(), n, zj, nullptr, w, s, gctl);
             tend(1);
             // classical Gram-Schmidt with selective reorthogonalisation:
             // pass 1: h1 = V^T w, ||w||^2 ; pass 2: w -= V h1, h2 = V^T w, ||w||^2 ;
@@ -1482,10 +1495,16 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
         tsel = timing && tstride == 1;
         tj = -1;
         launch_trisolve(m, R, g, y, gctl, s);
-        launch_gemv_small(V, ldv, gctl + 1, y, n, r, s);
-        tbeg();
-        PR_TRY(precond(h, r, zt, t3));
-        tend(0);
+        if (flex) {
+            // x += Z y
+            launch_gemv_small(h->Zb, ldv, gctl + 1, y, n, zt, s);
+        } else {
+            // x += M (V y)
+            launch_gemv_small(V, ldv, gctl + 1, y, n, r, s);
+            tbeg();
+            PR_TRY(precond(h, r, zt, t3));
+            tend(0);
+        }
         launch_axpy_dev(xw, zt, 1.0, n, s);
         tbeg();
         launch_spmv_sell(h->sell(), n, xw, bw, r, s);

@@ -145,6 +145,8 @@ struct pr_handle_s {
 
     // solve workspace
     double* V = nullptr;
+    double* Zb = nullptr;         // preconditioned basis of flexible GMRES (restart columns)
+    int64_t zb_restart = -1;
     double* w = nullptr;
     double* t1 = nullptr;
     double* t2 = nullptr;

@@ -212,3 +212,48 @@ def test_coarse_errors():
         h.set_coarse(P.meta["P0"])            # once per handle
     assert e.value.code == pr.PR_ERR_INVALID_ARG
     h.close()
+
+
+@pytest.mark.parametrize("precision,eps,two", [("fp64", None, True), ("bf16x3", 0.5, True),
+                                                ("bf16x3", 0.5, False), ("bf16", 0.5, True)])
+def test_flexible_gmres_matches_oracle(precision, eps, two):
+    # flexible GMRES keeps z_j = M v_j; the oracle runs the same outer method
+    # with its emulation of the reduced-precision apply (same roundings, FP32
+    # sums in another order), so the iteration counts agree within one
+    P = gen.q2_hex_diffusion(8)
+    b = gen.rhs(P.n)
+    _, W = O.cover_weights(P.n, P.ptr, P.dofs)
+    tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
+    if eps is None:
+        X, phi = [O.factor_inverse(t) for t in tiles], np.arange(P.n_p)
+        kw = dict(algo="full")
+    else:
+        res = O.alg1_tolerance(tiles, eps)
+        X, phi = res["X"], res["phi"]
+        kw = dict(algo="tolerance", eps=eps)
+    P0 = P.meta["P0"]
+    import scipy.sparse.linalg as spla
+    lu = spla.splu(sp.csc_matrix(O.coarse_operator(P.A, P0))) if two else None
+
+    def prec(r):
+        z = (O.apply_patch(P.ptr, P.dofs, W, X, phi, r) if precision == "fp64"
+             else O.apply_lowprec(P.ptr, P.dofs, W, X, phi, r, 1.0, precision))
+        return z + P0 @ lu.solve(P0.T @ r) if two else z
+    _, info_o = O.gmres(lambda v: P.A @ v, prec, b, tol=1e-8, restart=30, max_iters=2000, flexible=True)
+    out = {}
+    for flexible in (False, True):
+        h = pr.PatchRelax(P.A, P.ptr, P.dofs, precision=precision, deterministic=True, flexible=flexible,
+                          max_iters=2000, **kw)
+        if two:
+            h.set_coarse(P0)
+        bt = dt(b, torch.float64)
+        x = torch.zeros_like(bt)
+        rc = h.solve(bt, x, 1e-8)
+        out[flexible] = (rc, h.solve_info())
+        h.close()
+    rc, info = out[True]
+    say(f"  {precision} eps {eps} two-level {two}: flexible {info['iters']} (oracle {info_o['iters']}), "
+        f"standard {out[False][1]['iters']}")
+    assert rc == pr.PR_OK and info["relres"] <= 1e-8
+    assert abs(info["iters"] - info_o["iters"]) <= 1
+    assert info["iters"] <= out[False][1]["iters"] + 1

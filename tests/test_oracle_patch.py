@@ -421,3 +421,30 @@ def test_batch_inverse_equals_factor_inverse():
     for t, x1, x2 in zip(tiles, X1, X2):
         k = np.linalg.cond(t)
         assert np.abs(x1 - x2).max() <= 64 * k * 2.2e-16 * np.abs(x1).max()
+
+
+def test_flexible_gmres_equals_gmres_for_a_linear_preconditioner():
+    P = gen.q2_hex_diffusion(4)
+    cnt, W = O.cover_weights(P.n, P.ptr, P.dofs)
+    tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
+    res = O.alg1_tolerance(tiles, 0.5)
+    prec = O.make_preconditioner(P.A, P.ptr, P.dofs, W, res["X"], res["phi"])
+    b = gen.rhs(P.n)
+    x0, i0 = O.gmres(lambda v: P.A @ v, prec, b, tol=1e-10, restart=10)
+    x1, i1 = O.gmres(lambda v: P.A @ v, prec, b, tol=1e-10, restart=10, flexible=True)
+    assert i0["iters"] == i1["iters"] and i0["cycles"] == i1["cycles"]
+    assert np.linalg.norm(x0 - x1) <= 1e-8 * np.linalg.norm(x0)
+
+
+def test_flexible_gmres_stays_exact_with_a_nonlinear_preconditioner():
+    # a preconditioner that rounds its input to FP32 first is not linear:
+    # the flexible form's last residual estimate equals the true residual
+    P = gen.q2_hex_diffusion(4)
+    cnt, W = O.cover_weights(P.n, P.ptr, P.dofs)
+    tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
+    X = [O.factor_inverse(t) for t in tiles]
+    base = O.make_preconditioner(P.A, P.ptr, P.dofs, W, X, np.arange(P.n_p))
+    prec = lambda r: base(O.round_fp32(r))
+    b = gen.rhs(P.n)
+    x, info = O.gmres(lambda v: P.A @ v, prec, b, tol=1e-10, restart=40, flexible=True)
+    assert info["converged"] and info["cycles"] == 1
