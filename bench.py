@@ -46,7 +46,10 @@ Beside the headline line's throughput:
   apply_protocol: the preconditioner application alone, 5 warm-ups and 50
       repetitions, median, cold (a 512 MiB write between applications) and
       warm (a HIP graph of 100 back-to-back applications on distinct r, z);
-  hbm_copy_probe: a 1 GiB device copy timed with events (read + write bytes).
+  hbm_copy_probe: a 1 GiB device copy timed with events (read + write bytes);
+  reuse: database reuse along a sequence of systems (Algorithm 1 seeded with
+      the previous database, k-means warm-started from the previous
+      assignment) against setups from scratch.
 """
 from __future__ import annotations
 
@@ -504,6 +507,95 @@ def equal_tol_block(args):
                        "seconds": round(t_oracle, 2)}}
 
 
+def reuse_block(args):
+    """Database reuse along a sequence of linear systems (the closing remarks
+    of the third numerical experiment; Section 3.2 on problem sequences): the
+    lognormal coefficient of Q2 32^3 drifts by a seeded factor exp(0.05 g)
+    from system 0 to system 1.  Algorithm 1 (eps 0.55) on system 1 from
+    scratch against pr_setup_reuse with system 0's database; spectral k-means
+    (5 % of the patches) on the 16^3 problem cold against warm-started.
+    Setup time is the median of three setups; iterations are those of the
+    compressed BF16X3 apply with the two-level combination (flexible
+    GMRES(30), tolerance 1e-8)."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2306_10025_amd as pr
+
+    dev = torch.device("cuda:0")
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dtype=dt)
+    stream = pr._stream()
+
+    def system(nc, step):
+        P = gen.q2_hex_diffusion(nc)
+        if step == 0:
+            return P
+        k = P.meta["k"] * np.exp(0.05 * np.random.default_rng(11).standard_normal(nc ** 3))
+        return gen.q2_hex_diffusion(nc, kfield=k)
+
+    def arrays(P):
+        P0 = P.meta["P0"]
+        return (t(P.A.indptr.astype(np.int64), torch.int64), t(P.A.indices.astype(np.int32), torch.int32),
+                t(P.A.data, torch.float64), t(P.ptr.astype(np.int64), torch.int64),
+                t(P.dofs.astype(np.int32), torch.int32),
+                (t(P0.indptr.astype(np.int64), torch.int64), t(P0.indices.astype(np.int32), torch.int32),
+                 t(P0.data, torch.float64), P.n, P0.shape[1]), t(gen.rhs(P.n), torch.float64))
+
+    def setup(P, arr, kw, blob=None, solve=False):
+        rp, ci, va, pt, dd, p0, b = arr
+        params = pr.make_params(restart=30, max_iters=2000, deterministic=True, stream=stream, flexible=True,
+                                precision="bf16x3", **kw)
+        times, st, info = [], None, None
+        for rep in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = (pr.pr_setup(rp, ci, va, pt, dd, P.n, params) if blob is None
+                 else pr.pr_setup_reuse(rp, ci, va, pt, dd, P.n, params, blob))
+            times.append(time.perf_counter() - t0)
+            try:
+                st = pr.pr_get_stats(h)
+                out_blob = pr.pr_export_database(h)
+                if solve and rep == 0:
+                    pr.pr_set_coarse(h, *p0)
+                    x = torch.zeros_like(b)
+                    pr.pr_solve(h, b, x, args.tol)
+                    info = pr.pr_get_solve_info(h)
+            finally:
+                pr.pr_destroy(h)
+        rec = {"setup_s": round(float(np.median(times)), 5), "m_p": int(st["m_p"]),
+               "crit_evals": int(st["crit_evals"])}
+        if info is not None:
+            rec["iters"] = int(info["iters"])
+        return rec, st, out_blob
+
+    out = {}
+    S0, S1 = system(32, 0), system(32, 1)
+    A0, A1 = arrays(S0), arrays(S1)
+    kw = dict(algo="tolerance", eps=0.55)
+    _, _, blob = setup(S0, A0, kw)
+    fresh, _, _ = setup(S1, A1, kw, solve=True)
+    reuse, st, _ = setup(S1, A1, kw, blob=blob, solve=True)
+    reuse.update(kept=int(st["reuse_kept"]), rescanned=int(st["reuse_rescanned"]),
+                 appended=int(st["reuse_appended"]))
+    out["algorithm_1_q2_hex_lognormal_32"] = {"fresh": fresh, "reuse": reuse,
+                                              "setup_speedup": round(fresh["setup_s"] / reuse["setup_s"], 3)}
+    log(f"[reuse] Algorithm 1: fresh {fresh} reuse {reuse}")
+    K0, K1 = system(16, 0), system(16, 1)
+    B0, B1 = arrays(K0), arrays(K1)
+    kw = dict(algo="kmeans_spectral", m_target=int(0.05 * K0.n_p))
+    _, _, kblob = setup(K0, B0, kw)
+    cold, cst, _ = setup(K1, B1, kw, solve=True)
+    warm, wst, _ = setup(K1, B1, kw, blob=kblob, solve=True)
+    cold["passes"] = int(cst["kmeans_iters"])
+    warm["passes"] = int(wst["kmeans_iters"])
+    out["kmeans_spectral_q2_hex_lognormal_16"] = {"cold": cold, "warm": warm,
+                                                  "setup_speedup": round(cold["setup_s"] / warm["setup_s"], 3)}
+    log(f"[reuse] k-means: cold {cold} warm {warm}")
+    out["sequence"] = "system 1 = system 0 with the coefficient times exp(0.05 g), g ~ N(0, 1) per cell (seed 11)"
+    return out
+
+
 def launches_per_solve(info):
     """Launches of each class in one solve: an apply and an SpMV per Arnoldi
     step and per restart cycle end, one orthogonalisation per step."""
@@ -804,6 +896,8 @@ def main():
     if not args.no_equal_tol and args.workload == "nedelec_hex":
         log("equal-tolerance block (q2 hex lognormal) ...")
         line["equal_tol"] = equal_tol_block(args)
+        log("reuse block (sequence of q2 hex lognormal systems) ...")
+        line["reuse"] = reuse_block(args)
     if not args.no_cpu:
         log("cpu baseline (oracle on a bounded sample) ...")
         line["cpu_baseline"] = cpu_baseline(args)

@@ -262,6 +262,10 @@ typedef struct {
     int64_t coarse_block;        /* rows per block of the banded solve (0: dense inverse) */
     int64_t coarse_blocks;       /* blocks of the banded solve (1: dense inverse) */
     double  t_coarse;            /* seconds of pr_set_coarse */
+    /* pr_setup_reuse with Algorithm 1 (zeros otherwise) */
+    int64_t reuse_kept;          /* patches still within eps of their previous entry */
+    int64_t reuse_rescanned;     /* patches placed on another entry by the in-order scan */
+    int64_t reuse_appended;      /* entries appended for patches no entry matched */
 } pr_stats;
 
 /* ---- entry points ------------------------------------------------------ */
@@ -337,6 +341,38 @@ int pr_set_coarse(pr_handle h, const pr_interp* P0);
  * double[nnz].  INVALID_ARG without a coarse space. */
 int pr_get_coarse_matrix(pr_handle h, int64_t* n0, int64_t* nnz, int64_t* row_ptr, int32_t* col,
                          double* val);
+
+/* Database reuse across a sequence of linear systems on the same patches
+ * (time stepping, nonlinear iterations): the closing remarks of the third
+ * numerical experiment suggest reusing the previous setup's database
+ * assignments, and Section 3.2 initialising the clustering from the previous
+ * step.
+ *
+ * pr_export_database writes the handle's patch map phi and entry patch ids
+ * to the host buffer buf: 40 header bytes (magic "PRDB0001", n_p, m_p,
+ * algo, criterion, eps), then int32 phi[n_p] and int32 reps[m_p]
+ * (little-endian).  With buf NULL it only sets *bytes to the size; with a
+ * buffer, *bytes must hold its capacity and receives the size written.
+ * Errors: INVALID_ARG (null bytes, a buffer too small).
+ *
+ * pr_setup_reuse is pr_setup seeded with such a blob (host memory, `bytes`
+ * long; the patches must be the same n_p, the matrix may differ):
+ *  - PR_ALGO_TOLERANCE: the previous entries (patch ids, in their order) are
+ *    the first entries, inverted from the current matrix.  Every other patch,
+ *    in ascending id, keeps its previous entry when d < eps, else takes the
+ *    first entry in append order with d < eps, else is appended (Algorithm 1
+ *    on the patches that matched nothing).  Every patch then lies within eps
+ *    of its entry, and entry numbers of kept patches do not change.
+ *  - k-means variants: the passes start from the previous assignment; the
+ *    centres start as its update (mean or medoid of the current matrices),
+ *    so a system that barely changed converges in a pass or two.  m_target
+ *    and the groups must match the blob, and every previous centre must
+ *    keep a member.
+ * Errors as pr_setup, plus INVALID_ARG for a malformed or mismatched blob,
+ * PR_ALGO_FULL or PR_ALGO_BOOTSTRAP, mlp = 1 or closest matching. */
+int pr_export_database(pr_handle h, void* buf, int64_t* bytes);
+int pr_setup_reuse(const pr_csr* A, const pr_patches* P, const pr_params* prm, const void* db,
+                   int64_t bytes, pr_handle* out);
 
 int pr_get_solve_info(pr_handle h, pr_solve_info* info);
 int pr_get_stats(pr_handle h, pr_stats* s);

@@ -19,7 +19,7 @@ from .patch import (OracleError, cover_weights, patch_tiles, patch_tiles_csr, ba
                     factor_inverse, apply_patch, apply_operator_dense, storage_bytes,
                     objective)
 from .criterion import crit_spectral, crit_spectral_x, crit_l1, crit_fro, criterion
-from .database import (alg1_tolerance, alg1_closest, compressibility, kmeans, partition_groups,
+from .database import (alg1_tolerance, alg1_closest, alg1_reuse, compressibility, kmeans, partition_groups,
                        apportion, SplitMix64, alg1_invariants_hold, alg1_with_predictions)
 from . import mlp
 from .krylov import gmres, make_preconditioner
@@ -30,7 +30,7 @@ __all__ = [
     "OracleError", "cover_weights", "patch_tiles", "patch_tiles_csr", "batch_inverse", "boundary_mask", "factor_inverse",
     "apply_patch", "apply_operator_dense", "storage_bytes", "objective",
     "crit_spectral", "crit_spectral_x", "crit_l1", "crit_fro", "criterion",
-    "alg1_tolerance", "alg1_closest", "compressibility", "kmeans", "partition_groups", "apportion", "SplitMix64",
+    "alg1_tolerance", "alg1_closest", "alg1_reuse", "compressibility", "kmeans", "partition_groups", "apportion", "SplitMix64",
     "alg1_invariants_hold", "alg1_with_predictions", "mlp", "gmres", "make_preconditioner",
     "linear_interpolation", "coarse_operator", "combo_preconditioner",
     "round_fp32", "round_bf16", "round_fp16", "apply_lowprec", "fp16_scale_exp",

@@ -149,6 +149,55 @@ def alg1_closest(tiles, eps, crit="spectral", tie=1e-9):
     return dict(phi=phi, reps=np.asarray(reps, dtype=np.int64), X=X, evals=evals, dmin=dmin_of)
 
 
+def alg1_reuse(tiles, eps, crit, phi_prev, reps_prev):
+    """Algorithm 1 seeded with the database of the previous system of a
+    linear-problem sequence (the reuse of database assignments suggested
+    after the third numerical experiment; Section 3.2 on problem sequences).
+
+    The previous entries (patch ids reps_prev, in their order) are the first
+    entries, now with the current matrices of those patches.  Every other
+    patch i, in ascending id, keeps its previous entry phi_prev[i] when
+    d < eps; otherwise it takes the first entry in append order with
+    d < eps (the previous entries, then those appended so far), or is
+    appended as a new entry.
+    Returns dict(phi, reps, X, kept, rescanned, appended, evals)."""
+    reps = [int(r) for r in reps_prev]
+    X = [factor_inverse(tiles[r]) for r in reps]
+    is_rep = set(reps)
+    phi = np.zeros(len(tiles), dtype=np.int64)
+    for j, r in enumerate(reps):
+        phi[r] = j
+    kept = rescanned = appended = evals = 0
+    for i, Ai in enumerate(tiles):
+        if i in is_rep:
+            continue
+        j0 = int(phi_prev[i])
+        if tiles[reps[j0]].shape == Ai.shape:
+            evals += 1
+            if _dist(crit, Ai, tiles[reps[j0]], X[j0]) < eps:
+                phi[i] = j0
+                kept += 1
+                continue
+        hit = None
+        for j in range(len(reps)):
+            if tiles[reps[j]].shape != Ai.shape:
+                continue
+            evals += 1
+            if _dist(crit, Ai, tiles[reps[j]], X[j]) < eps:
+                hit = j
+                break
+        if hit is None:
+            reps.append(i)
+            X.append(factor_inverse(Ai))
+            hit = len(reps) - 1
+            appended += 1
+        else:
+            rescanned += 1
+        phi[i] = hit
+    return dict(phi=phi, reps=np.asarray(reps, dtype=np.int64), X=X, kept=kept, rescanned=rescanned,
+                appended=appended, evals=evals)
+
+
 def compressibility(n_p, m_p):
     """Compression ratio (n_p - m_p) / n_p of a database of m_p entries for
     n_p patches: the quantity of the compressibility curve in Experiment 4."""
@@ -315,8 +364,22 @@ def _initial_reps(groups, m_per, rng):
     return out
 
 
+def _centre(tiles, mem, upd, tie_rel):
+    """Centre update of a cluster with members mem (ascending): the entrywise
+    mean (Eq.(6)), or the member nearest it (lowest id in the tie band).
+    Returns (matrix, patch id or -1)."""
+    mean = np.mean(np.stack([tiles[k] for k in mem]), axis=0)
+    if upd == "mean":
+        return mean, -1
+    dist = np.array([np.sum((tiles[k] - mean) ** 2) for k in mem])
+    floor = tie_rel * tie_rel * float(np.sum(mean * mean))
+    near = np.flatnonzero(dist <= dist.min() * (1.0 + tie_rel) + floor)
+    m = int(mem[near[0]])
+    return tiles[m].copy(), m
+
+
 def kmeans(tiles, m_p, variant="spectral", seed=5, max_iter=100, partition=True,
-           tie_rel=1e-9, init_reps=None):
+           tie_rel=1e-9, init_reps=None, init_phi=None):
     """Algorithm 2 and the variants of Section 3.2.
 
     variant: 'spectral'  d = ||I - A B^{-1}||_2, centre = entrywise mean (Eq.(6));
@@ -326,6 +389,12 @@ def kmeans(tiles, m_p, variant="spectral", seed=5, max_iter=100, partition=True,
                          no partitioning, variance-minimising updates.
     Returns dict(phi, B, X, rep_patch, iters, converged, empty_events, groups).
     ``rep_patch[j]`` is the patch whose matrix is centre j (-1 for a mean).
+    ``init_phi``: warm start from the assignment of the previous system of a
+    linear-problem sequence (Section 3.2 on problem sequences: initialise
+    the database from the previous step): the centres start as the update
+    of that assignment (mean or medoid of the current matrices), then the
+    passes run as usual.  Every centre must keep a member and lie in the
+    group of its members.
     """
     if variant == "bootstrap":
         if init_reps is None:
@@ -351,6 +420,17 @@ def kmeans(tiles, m_p, variant="spectral", seed=5, max_iter=100, partition=True,
         X = [factor_inverse(b) for b in B] if crit == "spectral" else [None] * len(B)
         rp = list(start)
         loc = -np.ones(len(members), dtype=np.int64)
+        if init_phi is not None:
+            loc = np.asarray(init_phi)[members] - off
+            if (loc < 0).any() or (loc >= len(B)).any():
+                raise OracleError("previous assignment leaves its group")
+            for j in range(len(B)):
+                mem = members[loc == j]
+                if len(mem) == 0:
+                    raise OracleError("previous assignment leaves a centre without members")
+                B[j], rp[j] = _centre(tiles, mem, upd, tie_rel)
+                if crit == "spectral":
+                    X[j] = factor_inverse(B[j])
         it = 0
         converged = False
         while it < max_iter:
@@ -375,17 +455,7 @@ def kmeans(tiles, m_p, variant="spectral", seed=5, max_iter=100, partition=True,
                 if len(mem) == 0:
                     empty += 1
                     continue
-                mean = np.mean(np.stack([tiles[k] for k in mem]), axis=0)
-                if upd == "mean":
-                    B[j] = mean
-                    rp[j] = -1
-                else:
-                    dist = np.array([np.sum((tiles[k] - mean) ** 2) for k in mem])
-                    floor = tie_rel * tie_rel * float(np.sum(mean * mean))
-                    near = np.flatnonzero(dist <= dist.min() * (1.0 + tie_rel) + floor)
-                    m = int(mem[near[0]])          # lowest patch id in the tie band
-                    B[j] = tiles[m].copy()
-                    rp[j] = m
+                B[j], rp[j] = _centre(tiles, mem, upd, tie_rel)
                 if crit == "spectral":
                     X[j] = factor_inverse(B[j])
         phi[members] = loc + off

@@ -98,7 +98,8 @@ class pr_stats(Structure):
                 ("alg1_batch_inverted", c_int64), ("closest_evals", c_int64),
                 ("closest_moved", c_int64), ("n_coarse", c_int64), ("coarse_nnz", c_int64),
                 ("coarse_bandwidth", c_int64), ("coarse_block", c_int64), ("coarse_blocks", c_int64),
-                ("t_coarse", c_double)]
+                ("t_coarse", c_double), ("reuse_kept", c_int64), ("reuse_rescanned", c_int64),
+                ("reuse_appended", c_int64)]
 
 
 _SIGS = {
@@ -107,6 +108,9 @@ _SIGS = {
     "pr_apply": (c_int, [c_void_p, c_void_p, c_void_p]),
     "pr_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double]),
     "pr_get_solve_info": (c_int, [c_void_p, POINTER(pr_solve_info)]),
+    "pr_export_database": (c_int, [c_void_p, c_void_p, POINTER(c_int64)]),
+    "pr_setup_reuse": (c_int, [POINTER(pr_csr), POINTER(pr_patches), POINTER(pr_params), c_void_p, c_int64,
+                               POINTER(c_void_p)]),
     "pr_set_coarse": (c_int, [c_void_p, POINTER(pr_interp)]),
     "pr_get_coarse_matrix": (c_int, [c_void_p, POINTER(c_int64), POINTER(c_int64), c_void_p, c_void_p,
                                      c_void_p]),
@@ -243,6 +247,25 @@ def pr_setup(row_ptr, col, val, ptr, dofs, n, params: pr_params):
     P = pr_patches(int(ptr.numel()) - 1, _ptr(ptr), _ptr(dofs))
     h = c_void_p()
     _check(lib().pr_setup(byref(A), byref(P), byref(params), byref(h)))
+    return h
+
+
+def pr_export_database(h):
+    """The handle's database (phi and entry patch ids) as bytes."""
+    n = c_int64()
+    _check(lib().pr_export_database(h, None, byref(n)), h)
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib().pr_export_database(h, buf, byref(n)), h)
+    return buf.raw[:n.value]
+
+
+def pr_setup_reuse(row_ptr, col, val, ptr, dofs, n, params: pr_params, blob: bytes):
+    """pr_setup seeded with an exported database (the previous system's)."""
+    A = pr_csr(n, int(col.numel()), _ptr(row_ptr), _ptr(col), _ptr(val))
+    P = pr_patches(int(ptr.numel()) - 1, _ptr(ptr), _ptr(dofs))
+    h = c_void_p()
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    _check(lib().pr_setup_reuse(byref(A), byref(P), byref(params), buf, len(blob), byref(h)))
     return h
 
 
@@ -456,8 +479,13 @@ class PatchRelax:
         self.ptr = t(np.asarray(ptr, dtype=np.int64), torch.int64)
         self.dofs = t(np.asarray(dofs, dtype=np.int32), torch.int32)
         params.setdefault("stream", _stream())
+        reuse = params.pop("reuse", None)
         self.params = make_params(**params)
-        self.h = pr_setup(self.row_ptr, self.col, self.val, self.ptr, self.dofs, self.n, self.params)
+        if reuse is None:
+            self.h = pr_setup(self.row_ptr, self.col, self.val, self.ptr, self.dofs, self.n, self.params)
+        else:
+            self.h = pr_setup_reuse(self.row_ptr, self.col, self.val, self.ptr, self.dofs, self.n, self.params,
+                                    reuse)
 
     def apply(self, r, z):
         return pr_apply(self.h, r, z)
@@ -491,6 +519,9 @@ class PatchRelax:
 
     def entry_matrix(self, j, p):
         return pr_get_entry_matrix(self.h, j, p)
+
+    def export_database(self):
+        return pr_export_database(self.h)
 
     def set_coarse(self, P0):
         """Two-level combination with the interpolation P0 (SciPy CSR, n rows)."""

@@ -20,6 +20,12 @@ namespace {
 std::mutex g_mu;
 std::string g_last_error;
 
+// database handed from pr_setup_reuse to the setup it runs (this thread only)
+struct ReuseSeed {
+    std::vector<int32_t> phi, reps;
+};
+thread_local const ReuseSeed* g_reuse_pending = nullptr;
+
 double now_s() {
     using namespace std::chrono;
     return duration<double>(steady_clock::now().time_since_epoch()).count();
@@ -291,10 +297,12 @@ int run_kmeans(pr_handle h) {
             return pr_fail(h, PR_ERR_INVALID_ARG,
                            "m_target must lie between the number of groups (" + std::to_string(G) +
                                ") and the number of patches");
+        if (h->has_reuse && (int64_t)h->reuse_reps.size() != h->prm.m_target)
+            return pr_fail(h, PR_ERR_INVALID_ARG, "the blob's database size differs from m_target");
         // partial Fisher-Yates draw per group, groups in order, one stream:
         // position i swaps with i + (u mod (L - i))
         uint64_t st = h->prm.seed;
-        for (int64_t g = 0; g < G; ++g) {
+        for (int64_t g = 0; g < G && !h->has_reuse; ++g) {
             const int64_t L = sizes[g];
             std::unordered_map<int64_t, int64_t> moved;
             auto at = [&](int64_t x) {
@@ -349,8 +357,27 @@ int run_kmeans(pr_handle h) {
     PR_TRY(dalloc(h, &counters, 4));
     PR_TRY(dalloc(h, &B, (size_t)m_p * stride));
     PR_TRY(dalloc(h, &X, (size_t)m_p * stride));
+    std::vector<int32_t> warm_rep;
+    if (h->has_reuse) {
+        // warm start: every previous centre j lies in group cgroup[j]; its
+        // lowest member seeds B_j until the update below replaces it
+        std::vector<int32_t> pg_h(n_p);
+        PR_HIP(h, hipMemcpy(pg_h.data(), pg, n_p * sizeof(int32_t), hipMemcpyDeviceToHost));
+        warm_rep.assign(m_p, -1);
+        for (int64_t i = 0; i < n_p; ++i) {
+            const int32_t j = h->reuse_phi[i];
+            if (cgroup_h[j] != pg_h[i])
+                return pr_fail(h, PR_ERR_INVALID_ARG, "the blob's assignment leaves a patch's group");
+            if (warm_rep[j] < 0) warm_rep[j] = (int32_t)i;
+        }
+        for (int64_t j = 0; j < m_p; ++j)
+            if (warm_rep[j] < 0)
+                return pr_fail(h, PR_ERR_INVALID_ARG, "the blob leaves a centre without members");
+    }
     if (boot) {
         PR_HIP(h, hipMemcpyAsync(rep, rep0_h.data(), m_p * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    } else if (h->has_reuse) {
+        PR_HIP(h, hipMemcpyAsync(rep, warm_rep.data(), m_p * sizeof(int32_t), hipMemcpyHostToDevice, s));
     } else {
         int64_t* pos = nullptr;
         PR_TRY(dalloc(h, &pos, m_p));
@@ -377,6 +404,19 @@ int run_kmeans(pr_handle h) {
     }
     launch_km_init(m_p, rep, h->pptr, h->tiles, toff, ups, B, stride, s);
     launch_fill_i32(phi, n_p, -1, s);
+    if (h->has_reuse) {
+        // centres start as the update of the previous assignment
+        PR_HIP(h, hipMemcpyAsync(phi, h->reuse_phi.data(), n_p * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        std::vector<int32_t> all(G, 1);
+        PR_HIP(h, hipMemcpyAsync(gupd, all.data(), G * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        PR_HIP(h, hipMemsetAsync(ccount, 0, (m_p + 1) * sizeof(unsigned long long), s));
+        launch_km_keys(n_p, phi, pg, gupd, keys, mem, ccount, s);
+        launch_sort_pairs(keys, mem, n_p, kscr, vscr, s);
+        launch_exclusive_scan_i64((const int64_t*)ccount, cptr, m_p + 1, scr, s);
+        launch_km_update(m_p, cgroup, gupd, cptr, mem, cps, medoid, h->tiles, toff, ups, B, stride, rep, tie,
+                         counters, s);
+        PR_HIP(h, hipStreamSynchronize(s));
+    }
     PR_HIP(h, hipMemsetAsync(counters, 0, 4 * sizeof(unsigned long long), s));
     const int64_t grid = km_assign_grid(n_p, lbld);
     PR_TRY(dalloc(h, &lbscr, (size_t)grid * lbld));
@@ -1098,6 +1138,69 @@ int pr_validate_host(const pr_csr* A, const pr_patches* P) {
     return PR_OK;
 }
 
+namespace {
+constexpr char kDbMagic[8] = {'P', 'R', 'D', 'B', '0', '0', '0', '1'};
+constexpr int64_t kDbHeader = 40;
+}  // namespace
+
+int pr_export_database(pr_handle h, void* buf, int64_t* bytes) {
+    if (!h || !bytes) return pr_fail(h, PR_ERR_INVALID_ARG, "null argument");
+    const int64_t need = kDbHeader + 4 * (h->n_p + h->m_p);
+    if (!buf) {
+        *bytes = need;
+        return PR_OK;
+    }
+    if (*bytes < need) return pr_fail(h, PR_ERR_INVALID_ARG, "buffer smaller than " + std::to_string(need) + " bytes");
+    char* b = (char*)buf;
+    std::memcpy(b, kDbMagic, 8);
+    std::memcpy(b + 8, &h->n_p, 8);
+    std::memcpy(b + 16, &h->m_p, 8);
+    std::memcpy(b + 24, &h->prm.algo, 4);
+    std::memcpy(b + 28, &h->prm.criterion, 4);
+    std::memcpy(b + 32, &h->prm.eps, 8);
+    PR_HIP(h, hipStreamSynchronize(h->stream));
+    PR_HIP(h, hipMemcpy(b + kDbHeader, h->phi, h->n_p * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::memcpy(b + kDbHeader + 4 * h->n_p, h->reps_host.data(), h->m_p * sizeof(int32_t));
+    *bytes = need;
+    return PR_OK;
+}
+
+int pr_setup_reuse(const pr_csr* A, const pr_patches* P, const pr_params* prm, const void* db, int64_t bytes,
+                   pr_handle* out) {
+    if (!A || !P || !prm || !db || !out) return pr_fail(nullptr, PR_ERR_INVALID_ARG, "null argument");
+    if (prm->algo == PR_ALGO_FULL || prm->algo == PR_ALGO_BOOTSTRAP || prm->mlp || prm->alg1_match)
+        return pr_fail(nullptr, PR_ERR_INVALID_ARG,
+                       "reuse serves Algorithm 1 (first match, no predictor) and the k-means variants");
+    const char* b = (const char*)db;
+    int64_t n_p = 0, m_p = 0;
+    if (bytes < kDbHeader || std::memcmp(b, kDbMagic, 8) != 0)
+        return pr_fail(nullptr, PR_ERR_INVALID_ARG, "not a database blob");
+    std::memcpy(&n_p, b + 8, 8);
+    std::memcpy(&m_p, b + 16, 8);
+    if (n_p != P->n_p || m_p < 1 || m_p > n_p || bytes < kDbHeader + 4 * (n_p + m_p))
+        return pr_fail(nullptr, PR_ERR_INVALID_ARG, "blob does not fit these patches");
+    ReuseSeed seed;
+    seed.phi.resize(n_p);
+    seed.reps.resize(m_p);
+    std::memcpy(seed.phi.data(), b + kDbHeader, 4 * n_p);
+    std::memcpy(seed.reps.data(), b + kDbHeader + 4 * n_p, 4 * m_p);
+    for (int64_t i = 0; i < n_p; ++i)
+        if (seed.phi[i] < 0 || seed.phi[i] >= m_p)
+            return pr_fail(nullptr, PR_ERR_INVALID_ARG, "blob maps a patch outside the database");
+    if (prm->algo == PR_ALGO_TOLERANCE) {
+        for (int64_t j = 0; j < m_p; ++j) {
+            const int32_t r = seed.reps[j];
+            if (r < 0 || r >= n_p || seed.phi[r] != j || (j > 0 && r <= seed.reps[j - 1]))
+                return pr_fail(nullptr, PR_ERR_INVALID_ARG,
+                               "blob entries must be ascending patch ids mapped to themselves");
+        }
+    }
+    g_reuse_pending = &seed;
+    const int rc = pr_setup(A, P, prm, out);
+    g_reuse_pending = nullptr;
+    return rc;
+}
+
 int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_handle* out) {
     if (!A || !P || !out) return pr_fail(nullptr, PR_ERR_INVALID_ARG, "null argument");
     *out = nullptr;
@@ -1136,6 +1239,11 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
     h->stream = (hipStream_t)pm.stream;
     hipStream_t s = h->stream;
     (void)hipGetDevice(&h->device);
+    if (g_reuse_pending) {
+        h->has_reuse = true;
+        h->reuse_phi = g_reuse_pending->phi;
+        h->reuse_reps = g_reuse_pending->reps;
+    }
     const double t0 = now_s();
     h->n = A->n;
     h->nnz = A->nnz;
@@ -1237,6 +1345,7 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
 
     // ---- database (Section 3) ----------------------------------------------
     if (pm.algo == PR_ALGO_FULL) SETUP_TRY(run_full(h));
+    else if (pm.algo == PR_ALGO_TOLERANCE && h->has_reuse) SETUP_TRY(run_alg1_reuse(h));
     else if (pm.algo == PR_ALGO_TOLERANCE && pm.mlp) SETUP_TRY(run_alg1_mlp(h));
     else if (pm.algo == PR_ALGO_TOLERANCE) SETUP_TRY(run_alg1(h));
     else SETUP_TRY(run_kmeans(h));

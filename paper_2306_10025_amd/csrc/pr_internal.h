@@ -214,6 +214,10 @@ struct pr_handle_s {
     double *c_G = nullptr, *c_H = nullptr;   // S_i^{-1} L_i and S_i^{-1} U_i (banded form)
     double *c_r0 = nullptr, *c_u = nullptr, *c_w = nullptr, *c_x = nullptr;
 
+    // database of the previous system of a sequence (pr_setup_reuse)
+    bool has_reuse = false;
+    std::vector<int32_t> reuse_phi, reuse_reps;
+
     pr_solve_info sinfo{};
     pr_stats stats{};
     std::string last_error;
@@ -503,8 +507,10 @@ void launch_band_solve(int s, int nb, const double* Sinv, const double* G, const
 // pr_coarse.hip: z += P0 A0^{-1} R0 r (no-op without a coarse space)
 int coarse_add(pr_handle h, const double* r, double* z, const int32_t* stop);
 
-// pr_mlp.hip: Algorithm 1 with the learned predictor
+// pr_mlp.hip: Algorithm 1 with the learned predictor, and Algorithm 1 seeded
+// with the previous system's database
 int run_alg1_mlp(pr_handle h);
+int run_alg1_reuse(pr_handle h);
 
 // k_apply.hip
 struct ApplyLaunch {

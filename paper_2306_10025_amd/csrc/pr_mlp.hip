@@ -122,6 +122,135 @@ double now_s() {
 
 }  // namespace
 
+struct SeedResult {
+    int64_t evals = 0, exact = 0, refined = 0, rounds = 0;
+    int64_t accepted = 0, scanned = 0, fallback = 0;   // matched a candidate / the scan / neither
+};
+
+// Algorithm 1 seeded with n0 entries (entries[0..n0), patch ids): every
+// query patch Q[q] tries its k candidate entries cand[q*k..] in order (none
+// when cand is null), then scans the seed entries in append order, and the
+// patches still unmatched run Algorithm 1 among themselves, their entries
+// appended after the seed.  rank_of_patch and repof hold the seed entries on
+// entry (rank_of_patch[e] = j, repof[e] = e for seed entry e).  Sets h->phi,
+// h->reps, h->m_p, the FP64 database and the entry sizes and offsets.
+int alg1_from_seed(pr_handle h, int32_t* entries, int64_t n0, int32_t* rank_of_patch, int32_t* repof,
+                   const int32_t* Q, int64_t nq, const int32_t* cand, int k, SeedResult& out) {
+    hipStream_t s = h->stream;
+    const pr_params& pm = h->prm;
+    const int64_t n_p = h->n_p;
+    const int64_t stride = (int64_t)h->max_ps * h->max_ps;
+    const int ups = h->uniform ? h->max_ps : 0;
+    const int64_t* toff = h->uniform ? nullptr : h->toff;
+    const int crit = pm.criterion;
+    const double* keynorm = (crit == PR_CRIT_L1) ? h->l1norm : h->fnorm;
+    int32_t* csize = nullptr;
+    PR_TRY(dalloc(h, &csize, std::max<int64_t>(1, n0)));
+    launch_sizes(n0, entries, h->pptr, csize, s);
+    int64_t *f = nullptr, *pos = nullptr, *scr = nullptr;
+    PR_TRY(dalloc(h, &f, n_p + 1));
+    PR_TRY(dalloc(h, &pos, n_p + 1));
+    PR_TRY(dalloc(h, &scr, scan_scratch_elems(n_p + 1) + 2));
+    double *Bm = nullptr, *X0 = nullptr;
+    int32_t* info = nullptr;
+    int64_t *csz = nullptr, *coff = nullptr;
+    PR_TRY(dalloc(h, &Bm, (size_t)n0 * stride));
+    PR_TRY(dalloc(h, &X0, (size_t)n0 * stride));
+    PR_TRY(dalloc(h, &info, n_p));
+    std::vector<int32_t> csize_h(n0);
+    PR_HIP(h, hipMemcpyAsync(csize_h.data(), csize, n0 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PR_HIP(h, hipStreamSynchronize(s));
+    auto invert = [&](int64_t m, const int32_t* ents, const std::vector<int32_t>& sz, double* dst) -> int {
+        launch_km_init(m, ents, h->pptr, h->tiles, toff, ups, Bm, stride, s);
+        if (!h->uniform) {
+            std::vector<int64_t> a(m + 1), o(m + 1);
+            a[0] = 0;
+            for (int64_t j = 0; j < m; ++j) {
+                a[j + 1] = a[j] + sz[j];
+                o[j] = j * stride;
+            }
+            o[m] = m * stride;
+            PR_TRY(dalloc(h, &csz, m + 1));
+            PR_TRY(dalloc(h, &coff, m + 1));
+            PR_HIP(h, hipMemcpyAsync(csz, a.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+            PR_HIP(h, hipMemcpyAsync(coff, o.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        }
+        launch_batch_inverse(h->max_ps, m, Bm, h->uniform ? nullptr : coff, nullptr, h->uniform ? nullptr : csz,
+                             dst, h->uniform ? nullptr : coff, info, s);
+        std::vector<int32_t> info_h(m);
+        PR_HIP(h, hipMemcpyAsync(info_h.data(), info, m * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        PR_HIP(h, hipStreamSynchronize(s));
+        for (int64_t j = 0; j < m; ++j)
+            if (info_h[j] != 0)
+                return pr_fail(h, PR_ERR_SINGULAR_PATCH, "zero pivot in database entry " + std::to_string(j));
+        return PR_OK;
+    };
+    PR_TRY(invert(n0, entries, csize_h, X0));
+    int32_t *res1 = nullptr, *U = nullptr, *res2 = nullptr, *V = nullptr;
+    unsigned long long* cnt = nullptr;
+    PR_TRY(dalloc(h, &res1, std::max<int64_t>(1, nq)));
+    PR_TRY(dalloc(h, &U, std::max<int64_t>(1, nq)));
+    PR_TRY(dalloc(h, &res2, std::max<int64_t>(1, nq)));
+    PR_TRY(dalloc(h, &V, std::max<int64_t>(1, nq)));
+    PR_TRY(dalloc(h, &cnt, 4));
+    PR_HIP(h, hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned long long), s));
+    int64_t nu = 0, nv = 0;
+    if (cand && k > 0) {
+        launch_mlp_match(0, nq, Q, cand, k, h->pptr, h->tiles, toff, ups, entries, n0, X0, stride, crit, pm.eps,
+                         keynorm, repof, res1, cnt, s);
+        PR_TRY(compact(h, nq, Q, res1, 0, U, f, pos, scr, nu));
+    } else {
+        nu = nq;
+        if (nq > 0) PR_HIP(h, hipMemcpyAsync(U, Q, nq * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    }
+    launch_mlp_match(1, nu, U, nullptr, 0, h->pptr, h->tiles, toff, ups, entries, n0, X0, stride, crit, pm.eps,
+                     keynorm, repof, res2, cnt, s);
+    PR_TRY(compact(h, nu, U, res2, 0, V, f, pos, scr, nv));
+    int64_t n1 = 0;
+    A1Run R1;
+    if (nv > 0) {
+        PR_TRY(alg1_core(h, V, nv, R1));
+        n1 = R1.m;
+        launch_a1_subset_entries(nv, V, R1.repof, R1.flag, R1.excl, R1.scr, (int32_t)n0, entries + n0,
+                                 rank_of_patch, s);
+        launch_copy_at(nv, V, R1.repof, repof, s);
+    }
+
+    // 6. phi, the database and the statistics
+    const int64_t m_p = n0 + n1;
+    PR_TRY(dalloc(h, &h->phi, n_p));
+    launch_map_at(n_p, nullptr, repof, rank_of_patch, h->phi, s);
+    h->m_p = m_p;
+    h->reps = entries;
+    h->reps_host.resize(m_p);
+    PR_HIP(h, hipMemcpyAsync(h->reps_host.data(), entries, m_p * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    std::vector<int64_t> pptr_h(n_p + 1);
+    PR_HIP(h, hipMemcpyAsync(pptr_h.data(), h->pptr, (n_p + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    unsigned long long c4[4];
+    PR_HIP(h, hipMemcpyAsync(c4, cnt, sizeof(c4), hipMemcpyDeviceToHost, s));
+    PR_HIP(h, hipStreamSynchronize(s));
+    h->dbps_host.resize(m_p);
+    h->dboff_host.resize(m_p + 1);
+    for (int64_t j = 0; j < m_p; ++j) {
+        const int32_t r = h->reps_host[j];
+        h->dbps_host[j] = (int32_t)(pptr_h[r + 1] - pptr_h[r]);
+        h->dboff_host[j] = j * stride;
+    }
+    h->dboff_host[m_p] = m_p * stride;
+    PR_TRY(dalloc(h, &Bm, (size_t)m_p * stride));     // room for every entry
+    PR_TRY(dalloc(h, &h->db, (size_t)m_p * stride));
+    PR_TRY(invert(m_p, entries, h->dbps_host, h->db));
+
+    out.evals = (int64_t)(c4[0] + R1.cnt[0]);
+    out.exact = (int64_t)(c4[1] + R1.cnt[1]);
+    out.refined = (int64_t)(c4[3] + R1.cnt[3]);
+    out.rounds = R1.rounds;
+    out.accepted = nq - nu;
+    out.scanned = nu - nv;
+    out.fallback = nv;
+    return PR_OK;
+}
+
 int run_alg1_mlp(pr_handle h) {
     hipStream_t s = h->stream;
     const pr_params& pm = h->prm;
@@ -277,91 +406,10 @@ int run_alg1_mlp(pr_handle h) {
         launch_topk(bs, C, w.L, C, k, rkey_all ? kq : nullptr, ckey, cand + b0 * k, s);
     }
 
-    // 5. the exact criterion decides: predicted candidates, then the scan
-    double *Bm = nullptr, *X0 = nullptr;
-    int32_t* info = nullptr;
-    int64_t *csz = nullptr, *coff = nullptr;
-    PR_TRY(dalloc(h, &Bm, (size_t)n0 * stride));
-    PR_TRY(dalloc(h, &X0, (size_t)n0 * stride));
-    PR_TRY(dalloc(h, &info, n_p));
-    std::vector<int32_t> csize_h(n0);
-    PR_HIP(h, hipMemcpyAsync(csize_h.data(), csize, n0 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    PR_HIP(h, hipStreamSynchronize(s));
-    auto invert = [&](int64_t m, const int32_t* ents, const std::vector<int32_t>& sz, double* dst) -> int {
-        launch_km_init(m, ents, h->pptr, h->tiles, toff, ups, Bm, stride, s);
-        if (!h->uniform) {
-            std::vector<int64_t> a(m + 1), o(m + 1);
-            a[0] = 0;
-            for (int64_t j = 0; j < m; ++j) {
-                a[j + 1] = a[j] + sz[j];
-                o[j] = j * stride;
-            }
-            o[m] = m * stride;
-            PR_TRY(dalloc(h, &csz, m + 1));
-            PR_TRY(dalloc(h, &coff, m + 1));
-            PR_HIP(h, hipMemcpyAsync(csz, a.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-            PR_HIP(h, hipMemcpyAsync(coff, o.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-        }
-        launch_batch_inverse(h->max_ps, m, Bm, h->uniform ? nullptr : coff, nullptr, h->uniform ? nullptr : csz,
-                             dst, h->uniform ? nullptr : coff, info, s);
-        std::vector<int32_t> info_h(m);
-        PR_HIP(h, hipMemcpyAsync(info_h.data(), info, m * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        PR_HIP(h, hipStreamSynchronize(s));
-        for (int64_t j = 0; j < m; ++j)
-            if (info_h[j] != 0)
-                return pr_fail(h, PR_ERR_SINGULAR_PATCH, "zero pivot in database entry " + std::to_string(j));
-        return PR_OK;
-    };
-    PR_TRY(invert(n0, entries, csize_h, X0));
-    int32_t *res1 = nullptr, *U = nullptr, *res2 = nullptr, *V = nullptr;
-    unsigned long long* cnt = nullptr;
-    PR_TRY(dalloc(h, &res1, std::max<int64_t>(1, nq)));
-    PR_TRY(dalloc(h, &U, std::max<int64_t>(1, nq)));
-    PR_TRY(dalloc(h, &res2, std::max<int64_t>(1, nq)));
-    PR_TRY(dalloc(h, &V, std::max<int64_t>(1, nq)));
-    PR_TRY(dalloc(h, &cnt, 4));
-    PR_HIP(h, hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned long long), s));
-    launch_mlp_match(0, nq, Q, cand, k, h->pptr, h->tiles, toff, ups, entries, n0, X0, stride, crit, pm.eps,
-                     keynorm, repof, res1, cnt, s);
-    int64_t nu = 0, nv = 0;
-    PR_TRY(compact(h, nq, Q, res1, 0, U, f, pos, scr, nu));
-    launch_mlp_match(1, nu, U, nullptr, 0, h->pptr, h->tiles, toff, ups, entries, n0, X0, stride, crit, pm.eps,
-                     keynorm, repof, res2, cnt, s);
-    PR_TRY(compact(h, nu, U, res2, 0, V, f, pos, scr, nv));
-    int64_t n1 = 0;
-    A1Run R1;
-    if (nv > 0) {
-        PR_TRY(alg1_core(h, V, nv, R1));
-        n1 = R1.m;
-        launch_a1_subset_entries(nv, V, R1.repof, R1.flag, R1.excl, R1.scr, (int32_t)n0, entries + n0,
-                                 rank_of_patch, s);
-        launch_copy_at(nv, V, R1.repof, repof, s);
-    }
-
-    // 6. phi, the database and the statistics
-    const int64_t m_p = n0 + n1;
-    PR_TRY(dalloc(h, &h->phi, n_p));
-    launch_map_at(n_p, nullptr, repof, rank_of_patch, h->phi, s);
-    h->m_p = m_p;
-    h->reps = entries;
-    h->reps_host.resize(m_p);
-    PR_HIP(h, hipMemcpyAsync(h->reps_host.data(), entries, m_p * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    std::vector<int64_t> pptr_h(n_p + 1);
-    PR_HIP(h, hipMemcpyAsync(pptr_h.data(), h->pptr, (n_p + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    unsigned long long c4[4];
-    PR_HIP(h, hipMemcpyAsync(c4, cnt, sizeof(c4), hipMemcpyDeviceToHost, s));
-    PR_HIP(h, hipStreamSynchronize(s));
-    h->dbps_host.resize(m_p);
-    h->dboff_host.resize(m_p + 1);
-    for (int64_t j = 0; j < m_p; ++j) {
-        const int32_t r = h->reps_host[j];
-        h->dbps_host[j] = (int32_t)(pptr_h[r + 1] - pptr_h[r]);
-        h->dboff_host[j] = j * stride;
-    }
-    h->dboff_host[m_p] = m_p * stride;
-    PR_TRY(dalloc(h, &Bm, (size_t)m_p * stride));     // room for every entry
-    PR_TRY(dalloc(h, &h->db, (size_t)m_p * stride));
-    PR_TRY(invert(m_p, entries, h->dbps_host, h->db));
+    // 5. the exact criterion decides: predicted candidates, then the scan,
+    // then Algorithm 1 on the patches no entry matched
+    SeedResult sr;
+    PR_TRY(alg1_from_seed(h, entries, n0, rank_of_patch, repof, Q, nq, cand, k, sr));
 
     h->mlp_X = Xall;
     h->mlp_F = F;
@@ -371,19 +419,67 @@ int run_alg1_mlp(pr_handle h) {
     h->mlp_nq = nq;
     h->mlp_cand = cand;
     h->mlp_k = k;
-    h->stats.crit_evals = (int64_t)(R0.cnt[0] + c4[0] + R1.cnt[0]);
-    h->stats.crit_exact = (int64_t)(R0.cnt[1] + c4[1] + R1.cnt[1]);
-    h->stats.crit_refined = (int64_t)(R0.cnt[3] + c4[3] + R1.cnt[3]);
+    h->stats.crit_evals = (int64_t)R0.cnt[0] + sr.evals;
+    h->stats.crit_exact = (int64_t)R0.cnt[1] + sr.exact;
+    h->stats.crit_refined = (int64_t)R0.cnt[3] + sr.refined;
     h->stats.crit_pruned = 0;
-    h->stats.alg1_rounds = R0.rounds + R1.rounds;
+    h->stats.alg1_rounds = R0.rounds + sr.rounds;
     h->stats.mlp_train = ns;
     h->stats.mlp_classes = n0;
-    h->stats.mlp_accepted = nq - nu;
-    h->stats.mlp_scanned = nu - nv;
-    h->stats.mlp_fallback = nv;
+    h->stats.mlp_accepted = sr.accepted;
+    h->stats.mlp_scanned = sr.scanned;
+    h->stats.mlp_fallback = sr.fallback;
     h->stats.mlp_loss = loss_sum / (double)ns;
     h->stats.mlp_train_acc = (double)acc_h / (double)ns;
     h->stats.t_mlp_train = t_train1 - t_train0;
+    return PR_OK;
+}
+
+
+// Algorithm 1 seeded with the previous system's database (pr_setup_reuse):
+// the previous entries come first; every other patch tries its previous
+// entry, then the in-order scan, then Algorithm 1 on the patches left.
+int run_alg1_reuse(pr_handle h) {
+    hipStream_t s = h->stream;
+    const int64_t n_p = h->n_p;
+    const int64_t n0 = (int64_t)h->reuse_reps.size();
+    std::vector<int32_t> rank_h(n_p, -1), repof_h(n_p, -1), q_h, cand_h;
+    for (int64_t j = 0; j < n0; ++j) {
+        const int32_t r = h->reuse_reps[j];
+        rank_h[r] = (int32_t)j;
+        repof_h[r] = r;
+    }
+    q_h.reserve(n_p - n0);
+    cand_h.reserve(n_p - n0);
+    for (int64_t i = 0; i < n_p; ++i)
+        if (repof_h[i] < 0) {
+            q_h.push_back((int32_t)i);
+            cand_h.push_back(h->reuse_phi[i]);
+        }
+    const int64_t nq = (int64_t)q_h.size();
+    int32_t *entries = nullptr, *rank_of_patch = nullptr, *repof = nullptr, *Q = nullptr, *cand = nullptr;
+    PR_TRY(dalloc(h, &entries, n_p));
+    PR_TRY(dalloc(h, &rank_of_patch, n_p));
+    PR_TRY(dalloc(h, &repof, n_p));
+    PR_TRY(dalloc(h, &Q, std::max<int64_t>(1, nq)));
+    PR_TRY(dalloc(h, &cand, std::max<int64_t>(1, nq)));
+    PR_HIP(h, hipMemcpyAsync(entries, h->reuse_reps.data(), n0 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    PR_HIP(h, hipMemcpyAsync(rank_of_patch, rank_h.data(), n_p * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    PR_HIP(h, hipMemcpyAsync(repof, repof_h.data(), n_p * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (nq > 0) {
+        PR_HIP(h, hipMemcpyAsync(Q, q_h.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        PR_HIP(h, hipMemcpyAsync(cand, cand_h.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    }
+    SeedResult sr;
+    PR_TRY(alg1_from_seed(h, entries, n0, rank_of_patch, repof, Q, nq, cand, 1, sr));
+    h->stats.crit_evals = sr.evals;
+    h->stats.crit_exact = sr.exact;
+    h->stats.crit_refined = sr.refined;
+    h->stats.crit_pruned = 0;
+    h->stats.alg1_rounds = sr.rounds;
+    h->stats.reuse_kept = sr.accepted;
+    h->stats.reuse_rescanned = sr.scanned;
+    h->stats.reuse_appended = h->m_p - n0;
     return PR_OK;
 }
 

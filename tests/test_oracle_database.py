@@ -307,3 +307,56 @@ def test_alg1_closest_keeps_algorithm_1_database(crit, eps):
 def test_compressibility_ratio():
     assert O.compressibility(3600, 36) == 0.99
     assert O.compressibility(8000, 27) == pytest.approx(0.996625)
+
+
+def test_alg1_reuse_on_an_unchanged_system_keeps_everything():
+    P = gen.q2_hex_diffusion(4)
+    tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
+    prev = O.alg1_tolerance(tiles, 0.5)
+    r = O.alg1_reuse(tiles, 0.5, "spectral", prev["phi"], prev["reps"])
+    m = len(prev["reps"])
+    assert np.array_equal(r["phi"], prev["phi"]) and np.array_equal(r["reps"], prev["reps"])
+    assert r["kept"] == len(tiles) - m and r["rescanned"] == 0 and r["appended"] == 0
+    assert r["evals"] == len(tiles) - m          # one comparison per patch that is not an entry
+
+
+def test_alg1_reuse_hand_example():
+    # previous system: entries 1.0 and 1.3 (d = 0.3 is not below eps), patch 2
+    # (1.25) on entry 0; next systems move patch 2
+    prev = O.alg1_tolerance(_scalars([1.0, 1.3, 1.25]), 0.3)
+    assert prev["phi"].tolist() == [0, 1, 0]
+    r = O.alg1_reuse(_scalars([1.0, 1.3, 1.6]), 0.3, "spectral", prev["phi"], prev["reps"])
+    # d(1.6, 1.0) = 0.6 >= eps: rescan; d(1.6, 1.3) = 0.2308 < eps: entry 1
+    assert r["phi"].tolist() == [0, 1, 1] and r["rescanned"] == 1 and r["appended"] == 0
+    r = O.alg1_reuse(_scalars([1.0, 1.3, 2.0]), 0.3, "spectral", prev["phi"], prev["reps"])
+    assert r["phi"].tolist() == [0, 1, 2] and r["reps"].tolist() == [0, 1, 2] and r["appended"] == 1
+    # the previous entries stay entries even when they now match each other
+    r = O.alg1_reuse(_scalars([1.0, 1.1, 1.05]), 0.3, "spectral", prev["phi"], prev["reps"])
+    assert r["reps"].tolist() == [0, 1] and r["phi"].tolist() == [0, 1, 0]
+
+
+def test_alg1_reuse_on_a_perturbed_system_keeps_the_tolerance():
+    P = gen.q2_hex_diffusion(5)
+    P2 = gen.q2_hex_diffusion(5, kfield=P.meta["k"] * np.exp(0.05 * np.random.default_rng(7).standard_normal(125)))
+    t1 = O.patch_tiles(P.A, P.ptr, P.dofs)
+    t2 = O.patch_tiles(P2.A, P2.ptr, P2.dofs)
+    prev = O.alg1_tolerance(t1, 0.99)
+    r = O.alg1_reuse(t2, 0.99, "spectral", prev["phi"], prev["reps"])
+    assert r["kept"] > 0 and r["rescanned"] + r["appended"] > 0
+    X = {j: O.factor_inverse(t2[e]) for j, e in enumerate(r["reps"])}
+    for i, t in enumerate(t2):
+        assert O.crit_spectral_x(t, X[int(r["phi"][i])]) < 0.99
+    assert r["evals"] < O.alg1_tolerance(t2, 0.99)["evals"]
+
+
+@pytest.mark.parametrize("variant", ["spectral", "varmin", "entrywise"])
+def test_kmeans_warm_start_from_a_fixed_point_takes_one_pass(variant):
+    P = gen.q2_hex_diffusion(5)
+    tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
+    cold = O.kmeans(tiles, 40, variant=variant)
+    assert all(cold["converged"])
+    warm = O.kmeans(tiles, 40, variant=variant, init_phi=cold["phi"])
+    assert np.array_equal(warm["phi"], cold["phi"])
+    assert max(warm["iters"]) == 1
+    for a, b in zip(warm["B"], cold["B"]):
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
