@@ -536,6 +536,91 @@ def q2_hex_diffusion(nc: int = 32, sigma: float = 1.5, corr: float = 0.1, seed: 
                         P0=tensor_interpolation(2, nc, 3)))
 
 
+def _line_matrices(order: int, nc: int):
+    """Assembled 1D Q_order mass and stiffness matrices on nc equal cells of
+    [0, 1] (equispaced nodes, order * nc + 1 of them), CSR float64."""
+    h = 1.0 / nc
+    xq, wq = gauss_legendre(order + 1)
+    v, d = lagrange_1d(order, xq)
+    m1 = np.einsum('iq,jq,q->ij', v, v, wq) * h
+    k1 = np.einsum('iq,jq,q->ij', d, d, wq) / h
+    nl = order + 1
+    cell_dofs = order * np.arange(nc)[:, None] + np.arange(nl)[None, :]
+    nf = order * nc + 1
+    out = []
+    for Ke in (m1, k1):
+        r, c, x = _cells_to_coo(cell_dofs, Ke)
+        M = sp.coo_matrix((x, (r, c)), shape=(nf, nf)).tocsr()
+        M.sum_duplicates()
+        out.append(M)
+    return out
+
+
+def qp_hex_diffusion(nc: int = 20, order: int = 5, sigma: float = 0.0, corr: float = 0.1,
+                     seed: int = 4, kfield: np.ndarray | None = None) -> Problem:
+    """-div(k grad u) = f on the unit cube with tensor Q_order hexes on an nc^3
+    grid, k constant per cell, identity Dirichlet rows on every boundary node;
+    one patch per cell holding its (order + 1)^3 dofs (p_s = (p + 1)^d with
+    q = 1, Section 2).  order 5, nc 20, k = 1 is the problem of Experiment 3
+    (101^3 = 1,030,301 dofs, 8000 patches of 216 dofs).
+
+    With k = 1 (sigma 0, no kfield) the matrix is the Kronecker sum of the 1D
+    mass and stiffness matrices, which assembles the 20^3 problem without a
+    per-cell triplet list; otherwise the cells are assembled in chunks."""
+    nl = order + 1
+    nn = order * nc + 1
+    if kfield is None and sigma != 0.0:
+        kfield = lognormal_field(nc, sigma, corr, seed)
+    I, J, K = np.meshgrid(np.arange(nn), np.arange(nn), np.arange(nn), indexing='ij')
+    bnd = ((I == 0) | (I == nn - 1) | (J == 0) | (J == nn - 1) | (K == 0) | (K == nn - 1)).transpose(2, 1, 0).ravel()
+    del I, J, K
+    ci = np.arange(nc)
+    cz, cy, cx = np.meshgrid(ci, ci, ci, indexing='ij')          # cell id = cx + nc (cy + nc cz)
+    cx, cy, cz = cx.ravel(), cy.ravel(), cz.ravel()
+    a = np.arange(nl)
+    lz, ly, lx = np.meshgrid(a, a, a, indexing='ij')             # local id = lx + nl (ly + nl lz)
+    lx, ly, lz = lx.ravel(), ly.ravel(), lz.ravel()
+    cell_dofs = ((order * cx[:, None] + lx[None, :])
+                 + nn * ((order * cy[:, None] + ly[None, :]) + nn * (order * cz[:, None] + lz[None, :])))
+    cell_dofs = cell_dofs.astype(np.int64)
+    n = nn ** 3
+    if kfield is None:
+        M1, K1 = _line_matrices(order, nc)
+        A = (sp.kron(M1, sp.kron(M1, K1, format='csr'), format='csr')
+             + sp.kron(M1, sp.kron(K1, M1, format='csr'), format='csr')
+             + sp.kron(K1, sp.kron(M1, M1, format='csr'), format='csr')).tocsr()
+    else:
+        h = 1.0 / nc
+        Kr = ref_laplace_3d(order)
+        A = sp.csr_matrix((n, n))
+        step = max(1, (1 << 22) // (nl ** 6))
+        for c0 in range(0, nc ** 3, step):
+            cd = cell_dofs[c0:c0 + step]
+            Ke = (kfield[c0:c0 + step] * h)[:, None, None] * Kr[None]
+            r, c, v = _cells_to_coo(cd, Ke)
+            A = A + sp.coo_matrix((v, (r, c)), shape=(n, n)).tocsr()
+    # identity Dirichlet rows and columns (symmetric elimination)
+    A = A.tocoo()
+    keep = ~(bnd[A.row] | bnd[A.col])
+    bd = np.flatnonzero(bnd)
+    rows = np.concatenate([A.row[keep].astype(np.int64), bd])
+    cols = np.concatenate([A.col[keep].astype(np.int64), bd])
+    vals = np.concatenate([A.data[keep], np.ones(len(bd))])
+    del A, keep
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    del rows, cols, vals
+    A.sum_duplicates()
+    A.eliminate_zeros()
+    A.sort_indices()
+    A.indices = A.indices.astype(np.int32)
+    A.indptr = A.indptr.astype(np.int64)
+    ptr, dofs = _patches_from_cells(cell_dofs)
+    name = f"q{order}_hex_{nc}" + ("" if kfield is None else "_k")
+    return Problem(name, A, ptr, dofs,
+                   dict(nc=nc, order=order, sigma=sigma if kfield is not None else 0.0, p_s=nl ** 3,
+                        k=kfield, boundary=bnd, P0=tensor_interpolation(order, nc, 3)))
+
+
 def uneven_stokes_batch(n_sys: int = 256, nmin: int = 16, nmax: int = 128,
                         seed_n: int = 2, seed_perturb: int = 3, perturb: float = 0.1,
                         sizes=None) -> Problem:

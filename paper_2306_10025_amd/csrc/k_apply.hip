@@ -712,7 +712,9 @@ void launch_apply(int prec, bool two_stage, const ApplyLaunch& a, hipStream_t s)
     ApplyGeom g{a.gdofs, a.goff, a.pst, a.gphi, a.dboff, a.dbst, a.stop, a.maxp, a.xcd_remap};
     const int T = (a.threads == 64 || a.threads == 128) ? a.threads : 256;
     const int64_t cap = a.grid_cap;
-    if (prec == PR_FP64) {
+    if (a.wide) {
+        launch_apply_wide(prec, two_stage, a, s);
+    } else if (prec == PR_FP64) {
         if (two_stage) run_rows<double, double, double, true>(a.n_p, g, a.db, a.W, a.omega, a.r, a.z, (double*)a.Y, a.maxp, T, cap, s);
         else run_rows<double, double, double, false>(a.n_p, g, a.db, a.W, a.omega, a.r, a.z, (double*)nullptr, a.maxp, T, cap, s);
     } else if (prec == PR_FP32) {

@@ -148,8 +148,12 @@ int run_full(pr_handle h) {
     launch_iota(h->reps, n_p, s);
     int32_t* info = nullptr;
     PR_TRY(dalloc(h, &info, n_p));
-    launch_batch_inverse(h->max_ps, n_p, h->tiles, h->uniform ? nullptr : h->toff, nullptr,
-                         h->uniform ? nullptr : h->pptr, h->db, h->uniform ? nullptr : h->toff, info, s);
+    if (h->wide)
+        launch_gj_wide(n_p, nullptr, h->pptr, h->tiles, h->uniform ? nullptr : h->toff, h->uniform ? h->max_ps : 0,
+                       h->db, h->uniform ? nullptr : h->toff, info, s);
+    else
+        launch_batch_inverse(h->max_ps, n_p, h->tiles, h->uniform ? nullptr : h->toff, nullptr,
+                             h->uniform ? nullptr : h->pptr, h->db, h->uniform ? nullptr : h->toff, info, s);
     std::vector<int32_t> info_h(n_p);
     PR_HIP(h, hipMemcpyAsync(info_h.data(), info, n_p * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     PR_HIP(h, hipStreamSynchronize(s));
@@ -583,7 +587,9 @@ int run_group(pr_handle h) {
     int64_t start = 0;
     for (int64_t j = 0; j < m_p; ++j) {
         const int p = h->dbps_host[j];
-        const int nb = p <= 16 ? 16 : 32;           // MFMA tile: 16x16x16 or 32x32x8
+        // MFMA tile: 16x16x16 or 32x32x8; 16 members per item for every
+        // entry of a handle with patches above 32 dofs (16 x 16 x 4 FP64)
+        const int nb = (p <= 16 || h->wide) ? 16 : 32;
         for (int64_t t = 0; t < count[j]; t += nb) {
             items.push_back((int32_t)j);
             items.push_back((int32_t)(start + t));
@@ -623,8 +629,16 @@ int run_group(pr_handle h) {
         PR_HIP(h, hipMemcpyAsync(h->dblp_off, off.data(), (m_p + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
         PR_TRY(dalloc(h, &h->db_exp, m_p));
     }
-    launch_convert_db(prec, m_p, h->db, h->dboff, dbps, 0, (uint16_t*)h->db_lp, h->dblp_off, h->db_exp,
-                      h->db_f32, s);
+    if (h->wide) {
+        // column-major copies for the wide apply; grouped matrix-core items
+        // unless (almost) every patch is its own entry
+        if (prec == PR_FP64) PR_TRY(dalloc(h, &h->db_t, dbsize));
+        launch_transpose_db(m_p, h->db, h->dboff, dbps, h->db_t, h->db_f32, s);
+        h->wide_form = (2 * m_p > n_p) ? 2 : 1;
+    } else {
+        launch_convert_db(prec, m_p, h->db, h->dboff, dbps, 0, (uint16_t*)h->db_lp, h->dblp_off, h->db_exp,
+                          h->db_f32, s);
+    }
     PR_HIP(h, hipStreamSynchronize(s));
     PR_HIP(h, hipGetLastError());
     h->stats.n_items = h->n_items;
@@ -672,6 +686,8 @@ int apply_op(pr_handle h, const double* r, double* z, bool accumulate, double* t
     a.tiles_per_wave = h->tune_tpw;
     a.xcd_remap = h->tune_remap;
     a.slot_threads = h->tune_slot;
+    a.wide = h->wide ? h->wide_form : 0;
+    a.db_t = h->db_t;
     if (two) {
         a.z = accumulate ? tmp : z;
         launch_apply(h->apply_prec, true, a, s);
@@ -1121,7 +1137,7 @@ int pr_validate_host(const pr_csr* A, const pr_patches* P) {
     for (int64_t k = 0; k < P->n_p; ++k) {
         const int64_t s = P->ptr[k], e = P->ptr[k + 1];
         if (e <= s || e > total) return pr_fail(nullptr, PR_ERR_BAD_PATCH_PTR, "empty patch or ptr not monotone");
-        if (e - s > 32) rc_unsup = 1;
+        if (e - s > kWideMaxPs) rc_unsup = 1;
         for (int64_t q = s; q < e; ++q) {
             const int32_t g = P->dofs[q];
             if (g < 0 || g >= n) return pr_fail(nullptr, PR_ERR_DOF_OUT_OF_RANGE, "dof out of range in patch " + std::to_string(k));
@@ -1130,7 +1146,7 @@ int pr_validate_host(const pr_csr* A, const pr_patches* P) {
             cnt[g]++;
         }
     }
-    if (rc_unsup) return pr_fail(nullptr, PR_ERR_UNSUPPORTED, "patch with more than 32 dofs");
+    if (rc_unsup) return pr_fail(nullptr, PR_ERR_UNSUPPORTED, "patch with more than " + std::to_string(kWideMaxPs) + " dofs");
     for (int64_t i = 0; i < n; ++i)
         if (cnt[i] == 0) return pr_fail(nullptr, PR_ERR_UNCOVERED_DOF, "dof " + std::to_string(i) + " in no patch");
     for (int64_t q = 0; q < A->nnz; ++q)
@@ -1307,7 +1323,28 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
     SETUP_HIP(hipGetLastError());
     if (fl[0]) { pr_fail(h, PR_ERR_BAD_CSR, "malformed CSR (row_ptr, column range or order)"); return fail(PR_ERR_BAD_CSR); }
     if (fl[1]) { pr_fail(h, PR_ERR_BAD_PATCH_PTR, "malformed patch ptr or empty patch"); return fail(PR_ERR_BAD_PATCH_PTR); }
-    if (fl[6]) { pr_fail(h, PR_ERR_UNSUPPORTED, "patch with more than 32 dofs"); return fail(PR_ERR_UNSUPPORTED); }
+    if (fl[6]) {
+        // a patch above 32 dofs: the block-per-patch kernels (k_wide.hip)
+        if (mm[1] > kWideMaxPs) {
+            pr_fail(h, PR_ERR_UNSUPPORTED, "patch with more than " + std::to_string(kWideMaxPs) + " dofs");
+            return fail(PR_ERR_UNSUPPORTED);
+        }
+        const char* why = nullptr;
+        if (pm.algo != PR_ALGO_FULL && pm.algo != PR_ALGO_TOLERANCE) why = "Algorithm 2";
+        else if (pm.mlp) why = "the learned predictor";
+        else if (pm.alg1_match != 0) why = "closest matching";
+        else if (h->has_reuse) why = "database reuse";
+        else if (pm.apply_precision != PR_FP64 && pm.apply_precision != PR_FP32) why = "a 16-bit apply";
+        if (why) {
+            pr_fail(h, PR_ERR_UNSUPPORTED, std::string("patches above 32 dofs do not support ") + why);
+            return fail(PR_ERR_UNSUPPORTED);
+        }
+        h->wide = true;
+        launch_validate_wide(h->pptr, h->pdofs, h->n_p, h->n, flags, s);
+        SETUP_HIP(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+        SETUP_HIP(hipStreamSynchronize(s));
+        SETUP_HIP(hipGetLastError());
+    }
     if (fl[2] != INT_MAX) { pr_fail(h, PR_ERR_DOF_OUT_OF_RANGE, "dof out of range in patch " + std::to_string(fl[2])); return fail(PR_ERR_DOF_OUT_OF_RANGE); }
     if (fl[3] != INT_MAX) { pr_fail(h, PR_ERR_DUP_DOF_IN_PATCH, "duplicate dof in patch " + std::to_string(fl[3])); return fail(PR_ERR_DUP_DOF_IN_PATCH); }
     h->min_ps = mm[0];
@@ -1335,8 +1372,12 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
     SETUP_TRY(dalloc(h, &h->keys, h->n_p));
     SETUP_TRY(dalloc(h, &h->fnorm, h->n_p));
     SETUP_TRY(dalloc(h, &h->l1norm, h->n_p));
-    launch_extract(h->rowptr, h->col, h->val, h->pptr, h->pdofs, h->n_p, h->uniform ? nullptr : h->toff,
-                   h->uniform ? h->max_ps : 0, h->max_ps, h->tiles, h->keys, h->fnorm, h->l1norm, flags, s);
+    if (h->wide)
+        launch_extract_wide(h->rowptr, h->col, h->val, h->pptr, h->pdofs, h->n_p, h->uniform ? nullptr : h->toff,
+                            h->uniform ? h->max_ps : 0, h->tiles, h->keys, h->fnorm, h->l1norm, flags, s);
+    else
+        launch_extract(h->rowptr, h->col, h->val, h->pptr, h->pdofs, h->n_p, h->uniform ? nullptr : h->toff,
+                       h->uniform ? h->max_ps : 0, h->max_ps, h->tiles, h->keys, h->fnorm, h->l1norm, flags, s);
     SETUP_HIP(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
     SETUP_HIP(hipStreamSynchronize(s));
     SETUP_HIP(hipGetLastError());
@@ -1346,6 +1387,7 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
     // ---- database (Section 3) ----------------------------------------------
     if (pm.algo == PR_ALGO_FULL) SETUP_TRY(run_full(h));
     else if (pm.algo == PR_ALGO_TOLERANCE && h->has_reuse) SETUP_TRY(run_alg1_reuse(h));
+    else if (pm.algo == PR_ALGO_TOLERANCE && h->wide) SETUP_TRY(run_alg1_wide(h));
     else if (pm.algo == PR_ALGO_TOLERANCE && pm.mlp) SETUP_TRY(run_alg1_mlp(h));
     else if (pm.algo == PR_ALGO_TOLERANCE) SETUP_TRY(run_alg1(h));
     else SETUP_TRY(run_kmeans(h));
@@ -1385,7 +1427,7 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
     }
     SETUP_TRY(run_group(h));
     h->stats.tune_xcd_remap = (h->tile_p > 0 || h->ell_c > 0) ? h->tune_remap : 0;
-    if (pm.autotune) SETUP_TRY(autotune_apply(h));
+    if (pm.autotune && !h->wide) SETUP_TRY(autotune_apply(h));   // the wide kernels have one shape
 
     // boundary groups (distinct keys) for the stats
     {
@@ -1748,13 +1790,15 @@ int pr_get_entry_matrix(pr_handle h, int64_t j, double* B) {
 }
 
 int pr_batch_inverse(int32_t p, int64_t count, const double* A, double* X, int32_t* info, void* stream) {
-    if (p < 1 || p > 32 || count < 0) return pr_fail(nullptr, PR_ERR_INVALID_ARG, "p must be in [1, 32]");
+    if (p < 1 || p > kWideMaxPs || count < 0)
+        return pr_fail(nullptr, PR_ERR_INVALID_ARG, "p must be in [1, " + std::to_string(kWideMaxPs) + "]");
     if (count == 0) return PR_OK;
     int rc;
     if ((rc = check_dev(nullptr, A, "A")) < 0) return rc;
     if ((rc = check_dev(nullptr, X, "X")) < 0) return rc;
     if ((rc = check_dev(nullptr, info, "info")) < 0) return rc;
-    launch_batch_inverse(p, count, A, nullptr, nullptr, nullptr, X, nullptr, info, (hipStream_t)stream);
+    if (p > 32) launch_gj_wide(count, nullptr, nullptr, A, nullptr, p, X, nullptr, info, (hipStream_t)stream);
+    else launch_batch_inverse(p, count, A, nullptr, nullptr, nullptr, X, nullptr, info, (hipStream_t)stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return pr_fail(nullptr, PR_ERR_HIP, hipGetErrorString(e));
     return PR_OK;

@@ -52,6 +52,7 @@ int pr_set_systems(pr_handle h, const int64_t* sptr, int64_t nsys) {
     if (!h || !sptr || nsys < 1 || nsys > (1 << 20)) return pr_fail(h, PR_ERR_INVALID_ARG, "bad system list");
     if (sptr[0] != 0 || sptr[nsys] != h->n) return pr_fail(h, PR_ERR_INVALID_ARG, "system_ptr must run from 0 to n");
     if (h->n0 > 0) return pr_fail(h, PR_ERR_INVALID_ARG, "the handle has a coarse space; batches take none");
+    if (h->wide) return pr_fail(h, PR_ERR_UNSUPPORTED, "batches of systems take patches of at most 32 dofs");
     for (int64_t s = 0; s < nsys; ++s)
         if (sptr[s + 1] <= sptr[s]) return pr_fail(h, PR_ERR_INVALID_ARG, "empty or unordered system");
     hipStream_t st = h->stream;

@@ -11,6 +11,9 @@
 #include "../../include/patchrelax.h"
 
 #define PR_WAVE 64
+// largest patch (dofs) the library accepts; patches above 32 dofs take the
+// block-per-patch kernels of k_wide.hip
+constexpr int kWideMaxPs = 512;
 
 // ---------------------------------------------------------------------------
 // device helpers
@@ -125,7 +128,10 @@ struct pr_handle_s {
     void* db_lp = nullptr;        // lane-ready low-precision database
     int64_t* dblp_off = nullptr;  // element offsets into db_lp per entry
     int32_t* db_exp = nullptr;    // FP16 scale exponents
-    float* db_f32 = nullptr;      // FP32 database (row-major per entry)
+    float* db_f32 = nullptr;      // FP32 database (row-major per entry; column-major when wide)
+    bool wide = false;            // some patch has more than 32 dofs (k_wide.hip kernels)
+    double* db_t = nullptr;       // wide FP64 apply: inverses column-major per entry
+    int wide_form = 0;            // wide apply: 1 grouped matrix-core kernel, 2 one patch per block
     int apply_prec = PR_FP64;
     int32_t* gdofs = nullptr;     // dof lists in grouped order
     int64_t* goff = nullptr;      // grouped offsets (uneven sizes only)
@@ -511,6 +517,8 @@ int coarse_add(pr_handle h, const double* r, double* z, const int32_t* stop);
 // with the previous system's database
 int run_alg1_mlp(pr_handle h);
 int run_alg1_reuse(pr_handle h);
+// pr_wide.hip: Algorithm 1 for handles with a patch above 32 dofs
+int run_alg1_wide(pr_handle h);
 
 // k_apply.hip
 struct ApplyLaunch {
@@ -551,6 +559,8 @@ struct ApplyLaunch {
     int slot_threads = 0;
     int tiles_per_wave = 0;    // fixed-tile MFMA kernel: 1 or 2 (0: default)
     int xcd_remap = 0;         // fixed-tile kernel and padded slot sum: XCD-contiguous block order
+    int wide = 0;              // patches above 32 dofs: 1 grouped matrix-core items, 2 one patch per block
+    const double* db_t = nullptr;  // wide FP64: inverses column-major (db_f32 is column-major too)
 };
 // z (+)= omega M~^{-1} r.  Atomic mode accumulates into z (caller zeroes it);
 // two-stage mode overwrites z.
@@ -653,6 +663,39 @@ void launch_bgemv(const double* V, int64_t ldv, const BGeom& g, const double* y,
                   double* out, hipStream_t s);
 void launch_bcycle_init(int nsys, int m, const double* nrm2, const int32_t* active, double* gv, int32_t* sstop,
                         int32_t* scols, int32_t* gstop, hipStream_t s);
+
+// k_wide.hip: patches with 33..kWideMaxPs dofs (a block of 256 threads per patch)
+// range and duplicate checks of the patches above 32 dofs (flags[2], flags[3]
+// as launch_validate_patches)
+void launch_validate_wide(const int64_t* ptr, const int32_t* dofs, int64_t n_p, int64_t n, int32_t* flags,
+                          hipStream_t s);
+// tiles, boundary keys (XOR fold of the single-nonzero row mask), norms, as launch_extract
+void launch_extract_wide(const int64_t* rowptr, const int32_t* col, const double* val, const int64_t* ptr,
+                         const int32_t* dofs, int64_t n_p, const int64_t* toff, int uniform_ps, double* tiles,
+                         uint32_t* keys, double* fnorm, double* l1norm, int32_t* flags, hipStream_t s);
+// X_i = inverse of tile list[i] (list null: tile i), at X + xoff[i] (null:
+// i * p * p); info[i] = 1 + the step of a zero pivot, else 0
+void launch_gj_wide(int64_t count, const int32_t* list, const int64_t* ptr, const double* tiles,
+                    const int64_t* toff, int uniform_ps, double* X, const int64_t* xoff, int32_t* info,
+                    hipStream_t s);
+// One round of Algorithm 1: the entry m opened by U[0] is compared with
+// U[1..nu]; keep[u] = 1 for U[1+u] still open (keep[nu] = 0), phi set for
+// the matched and for U[0].  counters: evaluations, pruned, refined, ties.
+// Xm: inverse of the entry (spectral), scratch: grid * 2 * pmax^2 doubles.
+void launch_a1w_round(int64_t nu, const int32_t* U, int32_t m, int crit, double eps, const int64_t* ptr,
+                      const double* tiles, const int64_t* toff, int uniform_ps, const double* fnorm,
+                      const double* l1norm, const double* Xm, double* scratch, int64_t grid, int pmax,
+                      int32_t* phi, int64_t* keep, unsigned long long* counters, hipStream_t s);
+int64_t a1w_spectral_grid(int64_t nu);
+// out[i] = U[i] for keep[i] (positions from the exclusive scan excl)
+void launch_a1w_compact(int64_t nu, const int32_t* U, const int64_t* keep, const int64_t* excl, int32_t* out,
+                        hipStream_t s);
+// the patch part of the apply for wide handles (a.wide: 1 grouped items, 2
+// one patch per block; FP64 reads a.db_t, FP32 a.db_f32, both column-major)
+void launch_apply_wide(int prec, bool two_stage, const ApplyLaunch& a, hipStream_t s);
+// column-major copies of the database entries (FP64 and/or FP32)
+void launch_transpose_db(int64_t m_p, const double* db, const int64_t* dboff, const int32_t* dbps,
+                         double* out64, float* out32, hipStream_t s);
 
 // pr_batch.hip: the solve over independent systems
 int solve_batch(pr_handle h, const double* b, double* x, double tol);

@@ -109,14 +109,18 @@ def test_validate_host_error_codes():
     nan = data.copy()
     nan[7] = np.nan
     assert pr.pr_validate_host(indptr, indices, nan, ptr, dofs, n) == pr.PR_ERR_NONFINITE
-    big_ptr = np.array([0, 33], dtype=np.int64)
-    big = np.arange(33, dtype=np.int32)
+    # patches above 32 dofs take the wide kernels, up to 512 dofs
     A = gen.q1_poisson_2d(6)    # 49 dofs
     ptr2 = np.array([0, 33, 49], dtype=np.int64)
-    dofs2 = np.concatenate([np.arange(33), np.arange(33, 49)]).astype(np.int32)
-    assert pr.pr_validate_host(A.A.indptr, A.A.indices, A.A.data, ptr2, dofs2, A.n) == \
+    dofs2 = np.arange(49, dtype=np.int32)
+    assert pr.pr_validate_host(A.A.indptr, A.A.indices, A.A.data, ptr2, dofs2, A.n) == pr.PR_OK
+    B = gen.q1_poisson_2d(22)   # 529 dofs
+    ptr3 = np.array([0, 513, 529], dtype=np.int64)
+    dofs3 = np.arange(529, dtype=np.int32)
+    assert pr.pr_validate_host(B.A.indptr, B.A.indices, B.A.data, ptr3, dofs3, B.n) == \
         pr.PR_ERR_UNSUPPORTED
-    del big_ptr, big
+    ptr4 = np.array([0, 512, 529], dtype=np.int64)
+    assert pr.pr_validate_host(B.A.indptr, B.A.indices, B.A.data, ptr4, dofs3, B.n) == pr.PR_OK
 
 
 def test_setup_rejects_host_pointers_without_gpu_work():
