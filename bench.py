@@ -66,6 +66,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "patch-relax GDoF/s + setup s, compressed BF16 vs full FP64, equal-iter tol"
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_TFLOPS = 78.6
 TIMING_STRIDE = 7
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_traffic_nedelec_hex_64.md")
 APPLY_SRC = os.path.join(ROOT, "paper_2306_10025_amd", "csrc", "k_apply.hip")
@@ -81,7 +82,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="nedelec_hex",
-                    choices=["nedelec_hex", "stokes_batch", "q2_hex_lognormal", "stokes_2d"])
+                    choices=["nedelec_hex", "stokes_batch", "q2_hex_lognormal", "stokes_2d", "q5_hex"])
     ap.add_argument("--size", type=int, default=None, help="cells per direction")
     ap.add_argument("--nsys", type=int, default=256, help="systems of the stokes_batch workload")
     ap.add_argument("--iters", type=int, default=300, help="GMRES iteration cap per step")
@@ -115,14 +116,15 @@ def parse():
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="after the steps, copy this many MiB on the device (hardware-counter calibration)")
     a = ap.parse_args()
-    if a.twolevel and a.workload != "q2_hex_lognormal":
-        ap.error("--twolevel needs --workload q2_hex_lognormal (the mesh with a coarse interpolation)")
+    if a.twolevel and a.workload not in ("q2_hex_lognormal", "q5_hex"):
+        ap.error("--twolevel needs --workload q2_hex_lognormal or q5_hex (meshes with a coarse interpolation)")
     if a.size is None:
-        a.size = {"nedelec_hex": 64, "stokes_batch": 128, "q2_hex_lognormal": 32, "stokes_2d": 64}[a.workload]
+        a.size = {"nedelec_hex": 64, "stokes_batch": 128, "q2_hex_lognormal": 32, "stokes_2d": 64,
+                  "q5_hex": 20}[a.workload]
     if a.precision is None:
-        a.precision = "fp32" if a.workload == "stokes_batch" else "bf16x3"
+        a.precision = {"stokes_batch": "fp32", "q5_hex": "fp64"}.get(a.workload, "bf16x3")
     if a.eps is None:
-        a.eps = 0.55 if a.workload == "q2_hex_lognormal" else 1e-8
+        a.eps = {"q2_hex_lognormal": 0.55, "q5_hex": 1e-7}.get(a.workload, 1e-8)
     return a
 
 
@@ -137,6 +139,10 @@ def make_workload(args):
     elif args.workload == "stokes_2d":
         P = gen.taylor_hood_stokes_2d(args.size)
         name = f"taylor_hood_stokes_{args.size}x{args.size}"
+    elif args.workload == "q5_hex":
+        # Experiment 3: degree-5 hexahedra, k = 1, one 216-dof patch per cell
+        P = gen.qp_hex_diffusion(args.size, 5)
+        name = f"q5_hex_{args.size}"
     else:
         P = gen.q2_hex_diffusion(args.size)
         name = f"q2_hex_lognormal_{args.size}"
@@ -162,6 +168,9 @@ def path_params(args, P, compressed):
     if args.workload == "q2_hex_lognormal" and args.kmeans:
         return dict(algo="kmeans_spectral", m_target=max(1, int(0.05 * P.n_p)), precision=args.precision,
                     **common)
+    if args.workload == "q5_hex":
+        # Experiment 3's database: Algorithm 1 with the l1 criterion
+        return dict(algo="tolerance", criterion="l1", eps=args.eps, precision=args.precision, **common)
     return dict(algo="tolerance", criterion="spectral", eps=args.eps, precision=args.precision,
                 mlp=args.mlp, **common)
 
@@ -627,6 +636,22 @@ def summarize_classes(P, rec, precision, m_p, n_items):
     return res
 
 
+def apply_flops(P, m_p):
+    """Useful flops of one patch apply: 2 p^2 per patch."""
+    import numpy as np
+    return 2 * int(np.sum(np.diff(P.ptr) ** 2))
+
+
+def roofline_mfma(name, flops, avg_us, bytes_per_launch):
+    """Roofline of a kernel bound by the FP64 matrix cores (78.6 TFLOP/s)."""
+    achieved = flops / (avg_us * 1e-6) / 1e12 if avg_us > 0 else 0.0
+    return {"kernel": name, "bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_MFMA_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_TFLOPS, 4), "traffic": None,
+            "flops_per_launch": int(flops), "bytes_per_launch": int(bytes_per_launch),
+            "hbm_frac": round(bytes_per_launch / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) if avg_us > 0 else 0.0,
+            "avg_us": round(avg_us, 3)}
+
+
 def roofline(name, bytes_per_launch, avg_us, traffic=None):
     achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9 if avg_us > 0 else 0.0
     return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -656,14 +681,18 @@ def _cpu_baseline(args, gen, O):
     elif args.workload == "stokes_2d":
         P = gen.taylor_hood_stokes_2d(16)
         name, eps = "taylor_hood_stokes_16x16", 1e-8
+    elif args.workload == "q5_hex":
+        P = gen.qp_hex_diffusion(10, 5)
+        name, eps = "q5_hex_10", args.eps
     else:
         P = gen.q2_hex_diffusion(8)
         name, eps = "q2_hex_lognormal_8", 0.99
+    crit = "l1" if args.workload == "q5_hex" else "spectral"
     b = gen.rhs(P.n)
     t0 = time.perf_counter()
     cnt, W = O.cover_weights(P.n, P.ptr, P.dofs)
     tiles = O.patch_tiles(P.A, P.ptr, P.dofs)
-    res = O.alg1_tolerance(tiles, eps, "spectral")
+    res = O.alg1_tolerance(tiles, eps, crit)
     t_setup = time.perf_counter() - t0
     napply = [0]
     t_apply = [0.0]
@@ -681,7 +710,7 @@ def _cpu_baseline(args, gen, O):
     return {"value": rate, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
             "apply_only_value": P.n * napply[0] / t_apply[0] / 1e9,
             "sample": (f"{name} (n={P.n}, n_p={P.n_p}, m_p={len(res['reps'])}): "
-                       f"oracle setup (Algorithm 1, eps={eps}) {t_setup:.2f}s + GMRES(30) {info['iters']} "
+                       f"oracle setup (Algorithm 1, {crit}, eps={eps}) {t_setup:.2f}s + GMRES(30) {info['iters']} "
                        f"iters, {napply[0]} FP64 applies ({t_apply[0]:.3f}s of apply alone), {t_all:.2f}s "
                        f"wall; one thread (BLAS pool limited to 1; host cpu_count {os.cpu_count()})")}
 
@@ -798,11 +827,18 @@ def main():
                                          and args.scatter == "two-stage") else None
     kname = "patch apply (" + args.precision + ("" if args.scatter == "atomic" else ", two-stage") + ")"
     rl_apply = roofline(kname, cls["apply"]["bytes"], cls["apply"]["avg_us"], traffic)
+    if args.workload == "q5_hex":
+        # 216-dof patches stacked 16 per entry: 2 p^2 flops per patch against
+        # 8 B of residual and slot per dof; the FP64 matrix cores bound it
+        rl_apply = roofline_mfma("patch apply (fp64 matrix cores, grouped, two-stage)",
+                                 apply_flops(P, m_p), cls["apply"]["avg_us"], cls["apply"]["bytes"])
     rl_spmv = roofline("hybrid sliced-ELL spmv (fp64)", cls["spmv"]["bytes"], cls["spmv"]["avg_us"])
     rl_orth = roofline("gram-schmidt per arnoldi step (fp64)", cls["orth"]["bytes"], cls["orth"]["avg_us"])
     database = {"tolerance": f"algorithm 1, spectral criterion, eps={args.eps}" + (" with the learned predictor" if args.mlp else ""),
                 "kmeans_spectral": "algorithm 2 spectral k-means, m_p = 5 % of n_p",
-                "full": "every patch (FP32 inverses)"}[path_params(args, P, True)["algo"]]
+                "tolerance_l1": f"algorithm 1, l1 criterion, eps={args.eps}",
+                "full": "every patch (FP32 inverses)"}[path_params(args, P, True)["algo"]
+                                                        + ("_l1" if args.workload == "q5_hex" else "")]
     if args.workload == "stokes_2d":
         database = f"algorithm 1, spectral criterion, eps={args.eps}"
     if args.twolevel:

@@ -281,7 +281,23 @@ void pr_params_default(pr_params* p);
  * Errors: INVALID_ARG, HOST_POINTER, BAD_CSR, BAD_PATCH_PTR,
  * DOF_OUT_OF_RANGE, DUP_DOF_IN_PATCH, UNCOVERED_DOF, SINGULAR_PATCH (the
  * patch id is in pr_last_error), NONFINITE, OOM, HIP, UNSUPPORTED (a patch
- * with more than 32 dofs).  Synchronises the stream.
+ * with more than 512 dofs, or an option listed below for patches above 32
+ * dofs).  Synchronises the stream.
+ *
+ * Patches above 32 dofs (p_s = q (p+1)^d reaches 216 for the degree-5 cells
+ * of Section 4, Experiment 3): when any patch has more than 32 dofs, every
+ * patch of the handle takes kernels with a block of 256 threads per patch
+ * and tiles, inverses and criterion products in device memory.  They support
+ * PR_ALGO_FULL and PR_ALGO_TOLERANCE (first matching, all three criteria),
+ * FP64 and FP32 applies, sweeps, the coarse space and pr_solve; Algorithm 2,
+ * the learned predictor, closest matching, pr_setup_reuse, the 16-bit
+ * applies, autotune and pr_set_systems return UNSUPPORTED.  Algorithm 1 opens
+ * one entry per round there (alg1_rounds = m_p); the spectral criterion is
+ * decided from a bracket on sigma_max^2 (column norms and the Frobenius norm,
+ * then up to 40 squarings of E^T E), and crit_exact counts the pairs whose
+ * bracket stayed open after them (d within about 1e-11 of eps), decided at
+ * its geometric midpoint.  The FP32 apply multiplies FP32 inverses and FP32
+ * residual values with FP64 accumulation.
  *
  * Clustering algorithms (Algorithm 2, Section 3.2): patches are grouped by
  * size and, with partition_bc = 1, by boundary key (PR_ALGO_BOOTSTRAP never
@@ -387,7 +403,9 @@ int pr_get_patch_tile(pr_handle h, int64_t k, double* tile);
 /* W: double[n] (Section 2). */
 int pr_get_weights(pr_handle h, double* W);
 /* keys: uint32[n_p], bit a set iff local row a of A_k has exactly one
- * nonzero (boundary partitioning, Section 3.2). */
+ * nonzero (boundary partitioning, Section 3.2).  For patches above 32 dofs
+ * the key is the XOR over rows a with one nonzero of bit (a mod 32) (the
+ * 32-bit fold of that row mask, equal to the mask up to 32 dofs). */
 int pr_get_boundary_keys(pr_handle h, uint32_t* keys);
 /* X: double[p_j * p_j], the FP64 inverse of database entry j, row-major. */
 int pr_get_rep_inverse(pr_handle h, int64_t j, double* X);
@@ -465,7 +483,8 @@ int pr_memory_cache_info(int32_t device, int64_t* info);
  * matrix (the factorisation step of Section 4, Experiment 3).  A: device
  * double[count*p*p]; X: device double[count*p*p]; info: device
  * int32[count], 0 or the 1-based column of the first zero pivot.
- * 1 <= p <= 32. */
+ * 1 <= p <= 512; above 32 a block of 256 threads per matrix eliminates in
+ * place in X with partial pivoting over the whole column. */
 int pr_batch_inverse(int32_t p, int64_t count, const double* A, double* X, int32_t* info,
                      void* stream);
 

@@ -83,15 +83,21 @@ __global__ __launch_bounds__(kPlanThreads) void k_sell_plan(const int64_t* __res
             atomicAdd(&s_nnz, (int)l);
         }
     }
+    __syncthreads();
+    // a row holds distinct offsets, so a slice whose longest row exceeds
+    // kMaxDiag takes the column form without collecting its offsets
+    const bool collect = s_mlen <= kMaxDiag;
     // rows of a slice mostly share their offsets: each step the wavefront
     // reduces its 64 offsets to one lane per distinct value, and a slot is
-    // read before the atomic is tried
-    int64_t lmax = l;
+    // read before the atomic is tried; collection stops once the slice has
+    // more offsets than the diagonal form allows
+    int64_t lmax = collect ? l : 0;
     for (int o = 32; o > 0; o >>= 1) {
         const int64_t u = __shfl_xor(lmax, o);
         lmax = u > lmax ? u : lmax;
     }
     for (int64_t k0 = 0; k0 < lmax; k0 += 4) {
+        if (s_cnt > kMaxDiag) break;                 // one LDS read for the whole wavefront
         const int64_t k = k0 + sub;
         bool pending = k < l;
         const int32_t d = (int32_t)((int64_t)col[pending ? a + k : 0] - (r0 + i));
@@ -122,7 +128,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_sell_plan(const int64_t* __res
     }
     __syncthreads();
     const int mlen = s_mlen, ndiag = s_cnt;
-    const int fmt = (!s_over && mlen > 0 && 2 * ndiag <= 3 * mlen && ndiag <= kMaxDiag) ? 1 : 0;
+    const int fmt = (collect && !s_over && mlen > 0 && 2 * ndiag <= 3 * mlen && ndiag <= kMaxDiag) ? 1 : 0;
     if (fmt) {
         // the set as a list, sorted (at most kMaxDiag values in kPlanThreads slots)
         for (int e = t; e < kPlanTab; e += kPlanThreads) {

@@ -315,7 +315,19 @@ __global__ __launch_bounds__(kWT) void k_gj_wide(int64_t count, const int32_t* _
                 const double f = s_col[r2];
                 if (f == 0.0) continue;                    // also skips row c
                 double* Mi = M + (int64_t)r2 * p;
-                for (int j = lane; j < p; j += PR_WAVE) Mi[j] = (j == c ? 0.0 : Mi[j]) - f * s_row[j];
+                // the row's loads (lane + 64 u, p <= 512) are all issued
+                // before its stores
+                double v[kWideMaxPs / PR_WAVE];
+#pragma unroll
+                for (int u = 0; u < kWideMaxPs / PR_WAVE; ++u) {
+                    const int j = lane + PR_WAVE * u;
+                    v[u] = Mi[j < p ? j : 0];
+                }
+#pragma unroll
+                for (int u = 0; u < kWideMaxPs / PR_WAVE; ++u) {
+                    const int j = lane + PR_WAVE * u;
+                    if (j < p) Mi[j] = (j == c ? 0.0 : v[u]) - f * s_row[j];
+                }
             }
             __syncthreads();
         }
@@ -640,16 +652,27 @@ __device__ __forceinline__ void mfma_w<double>(double a, double b, wd4& acc) {
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
 }
 
-// Work item (entry j, grouped positions start .. start + cnt - 1, cnt <= 16,
-// p): the members' restricted residuals are staged in LDS k-major (16
-// members per row, stride kRStride), then each wave takes 16-row blocks of
-// Y = X_j R and accumulates over k in steps of 4 on the FP64 matrix cores,
-// with X_j^T from the column-major database.  FP32 storage: X_j and the
-// residual are FP32 values, widened exactly, and the products accumulate in
-// FP64.  Output lanes hold rows l / 16 + 4 v of member l % 16.
+// Work unit (item, row range): the item is (entry j, grouped positions
+// start .. start + cnt - 1, cnt <= 16, p) and the range 64 rows of
+// Y = X_j R, one 16-row block per wave, on the FP64 matrix cores (16 x 16 x 4
+// products).  R, the members' restricted residuals, is staged in LDS k-major
+// (16 members per row, stride kRStride, rows to a multiple of 32, zero past
+// p), gathered in two phases (eight dof indices per thread, then their eight
+// values).  Each wave streams its 16 rows of X_j^T (the column-major
+// database: 16 consecutive values per k) from L2 eight k-steps at a time, so
+// eight loads are in flight before their products, and sums even and odd
+// k-steps in two chains.  FP32 storage: X_j and the residual are FP32
+// values, widened exactly, and the products accumulate in FP64.  Output
+// lanes hold rows l / 16 + 4 v of member l % 16.
+constexpr int kRowsPerUnit = 64;
+
+__host__ __device__ inline size_t wide_apply_lds(int pmax) {
+    return (size_t)((pmax + 31) & ~31) * kRStride * sizeof(double);
+}
+
 template <typename TX, bool TWO>
 __global__ __launch_bounds__(kWT) void k_apply_wide_mfma(const int32_t* __restrict__ items, int64_t n_items,
-                                                         WideGeom g, const TX* __restrict__ dbt,
+                                                         int nrange, WideGeom g, const TX* __restrict__ dbt,
                                                          const double* __restrict__ W, double omega,
                                                          const double* __restrict__ r, double* __restrict__ z,
                                                          TX* __restrict__ Y) {
@@ -657,49 +680,81 @@ __global__ __launch_bounds__(kWT) void k_apply_wide_mfma(const int32_t* __restri
     if (g.stop && *g.stop) return;
     const int tid = threadIdx.x, lane = tid & (PR_WAVE - 1), w = tid / PR_WAVE;
     const int li = lane & 15, lk = lane >> 4;
-    for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int64_t units = n_items * nrange;
+    for (int64_t bi = blockIdx.x; bi < units; bi += gridDim.x) {
+        const int64_t it = bi / nrange;
+        const int row0 = (int)(bi - it * nrange) * kRowsPerUnit;
         const int j = items[4 * it], start = items[4 * it + 1], cnt = items[4 * it + 2], p = items[4 * it + 3];
-        const int pp = (p + 3) & ~3;
-        for (int e = tid; e < 16 * pp; e += kWT) {
-            const int mbr = e / pp, k = e - mbr * pp;
-            double v = 0.0;
-            if (mbr < cnt && k < p) v = r[g.gdofs[goff_of(g.goff, g.pst, start + mbr) + k]];
-            if constexpr (sizeof(TX) == 4) v = (double)(float)v;     // FP32 operands
-            sR[k * kRStride + mbr] = v;
+        if (row0 >= p) continue;                           // the same for the whole block
+        const int p32 = (p + 31) & ~31;
+        const int tot = 16 * p32;
+        for (int base = 0; base < tot; base += 8 * kWT) {
+            int32_t gi[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = base + tid + u * kWT;
+                const int mbr = e / p32, k = e - mbr * p32;
+                const bool ok = e < tot && mbr < cnt && k < p;
+                gi[u] = ok ? g.gdofs[goff_of(g.goff, g.pst, start + mbr) + k] : -1;
+            }
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const double x = r[gi[u] >= 0 ? gi[u] : 0];
+                v[u] = gi[u] >= 0 ? x : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = base + tid + u * kWT;
+                if (e < tot) {
+                    const int mbr = e / p32, k = e - mbr * p32;
+                    double x = v[u];
+                    if constexpr (sizeof(TX) == 4) x = (double)(float)x;   // FP32 operands
+                    sR[k * kRStride + mbr] = x;
+                }
+            }
         }
         __syncthreads();
-        const TX* XT = dbt + g.dboff[j];
-        const int nrb = (p + 15) >> 4;
-        for (int rb = w; rb < nrb; rb += kWW) {
-            const int row = 16 * rb + li;
+        const int rb0 = row0 + 16 * w;
+        if (rb0 < p) {                                     // the same for the whole wave
+            const TX* XT = dbt + g.dboff[j];
+            const int row = rb0 + li;
             const int rc = row < p ? row : 0;
-            wd4 acc = wd4{0.0, 0.0, 0.0, 0.0};
-            for (int k0 = 0; k0 < pp; k0 += 4) {
-                const int k = k0 + lk;
-                const int kc = k < p ? k : 0;
-                // rows past p give outputs that are never stored; k past p
-                // meets staged zeros, so its clamped X value drops out
-                const double a = (double)XT[(int64_t)kc * p + rc];
-                const double b = sR[k * kRStride + li];
-                mfma_w<double>(a, b, acc);
+            wd4 acc0 = wd4{0.0, 0.0, 0.0, 0.0}, acc1 = wd4{0.0, 0.0, 0.0, 0.0};
+            for (int k0 = 0; k0 < p32; k0 += 32) {
+                double av[8], bv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int k = k0 + 4 * u + lk;
+                    const int kc = k < p ? k : 0;              // k past p meets staged zeros
+                    av[u] = (double)XT[(int64_t)kc * p + rc];
+                    bv[u] = sR[k * kRStride + li];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; u += 2) {
+                    mfma_w<double>(av[u], bv[u], acc0);
+                    mfma_w<double>(av[u + 1], bv[u + 1], acc1);
+                }
             }
             if (li < cnt) {
                 const int64_t s = start + li;
+                const int64_t o = goff_of(g.goff, g.pst, s);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int orow = 16 * rb + lk + 4 * v;
+                    const int orow = rb0 + lk + 4 * v;
+                    const double y = acc0[v] + acc1[v];
                     if (orow < p) {
                         if (TWO) {
-                            Y[yslot_w(s, orow, g.ypm)] = (TX)acc[v];
+                            Y[yslot_w(s, orow, g.ypm)] = (TX)y;
                         } else {
-                            const int32_t gd = g.gdofs[goff_of(g.goff, g.pst, s) + orow];
-                            atomicAdd(&z[gd], omega * W[gd] * acc[v]);
+                            const int32_t gd = g.gdofs[o + orow];
+                            atomicAdd(&z[gd], omega * W[gd] * y);
                         }
                     }
                 }
             }
         }
-        __syncthreads();
+        __syncthreads();                                   // sR is restaged by the next unit
     }
 }
 
@@ -814,11 +869,12 @@ void launch_apply_wide(int prec, bool two_stage, const ApplyLaunch& a, hipStream
         return;
     }
     if (a.n_items <= 0) return;
-    const unsigned nb = grid_of(a.n_items, cap);
-    const size_t lds = (size_t)(((a.maxp + 3) & ~3)) * kRStride * sizeof(double);
-    static bool lds_set = false;                           // above 64 KB for p > 480
+    const int nrange = (a.maxp + kRowsPerUnit - 1) / kRowsPerUnit;
+    const unsigned nb = grid_of(a.n_items * nrange, cap);
+    const size_t lds = wide_apply_lds(a.maxp);
+    static bool lds_set = false;                           // above 64 KB from p = 481
     if (!lds_set) {
-        const int most = (int)((size_t)((kWideMaxPs + 3) & ~3) * kRStride * sizeof(double));
+        const int most = (int)wide_apply_lds(kWideMaxPs);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_wide_mfma<double, true>), hipFuncAttributeMaxDynamicSharedMemorySize, most);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_wide_mfma<double, false>), hipFuncAttributeMaxDynamicSharedMemorySize, most);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_wide_mfma<float, true>), hipFuncAttributeMaxDynamicSharedMemorySize, most);
@@ -826,10 +882,10 @@ void launch_apply_wide(int prec, bool two_stage, const ApplyLaunch& a, hipStream
         lds_set = true;
     }
     if (prec == PR_FP64) {
-        if (two_stage) k_apply_wide_mfma<double, true><<<nb, kWT, lds, s>>>(a.items, a.n_items, g, a.db_t, a.W, a.omega, a.r, a.z, (double*)a.Y);
-        else k_apply_wide_mfma<double, false><<<nb, kWT, lds, s>>>(a.items, a.n_items, g, a.db_t, a.W, a.omega, a.r, a.z, (double*)nullptr);
+        if (two_stage) k_apply_wide_mfma<double, true><<<nb, kWT, lds, s>>>(a.items, a.n_items, nrange, g, a.db_t, a.W, a.omega, a.r, a.z, (double*)a.Y);
+        else k_apply_wide_mfma<double, false><<<nb, kWT, lds, s>>>(a.items, a.n_items, nrange, g, a.db_t, a.W, a.omega, a.r, a.z, (double*)nullptr);
     } else {
-        if (two_stage) k_apply_wide_mfma<float, true><<<nb, kWT, lds, s>>>(a.items, a.n_items, g, a.db_f32, a.W, a.omega, a.r, a.z, (float*)a.Y);
-        else k_apply_wide_mfma<float, false><<<nb, kWT, lds, s>>>(a.items, a.n_items, g, a.db_f32, a.W, a.omega, a.r, a.z, (float*)nullptr);
+        if (two_stage) k_apply_wide_mfma<float, true><<<nb, kWT, lds, s>>>(a.items, a.n_items, nrange, g, a.db_f32, a.W, a.omega, a.r, a.z, (float*)a.Y);
+        else k_apply_wide_mfma<float, false><<<nb, kWT, lds, s>>>(a.items, a.n_items, nrange, g, a.db_f32, a.W, a.omega, a.r, a.z, (float*)nullptr);
     }
 }

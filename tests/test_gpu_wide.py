@@ -63,6 +63,8 @@ PROBLEMS = {
     "q5_3_logn": lambda: gen.qp_hex_diffusion(3, 5, sigma=1.0),
     "q5_4_const": lambda: gen.qp_hex_diffusion(4, 5),
     "mixed": mixed_sizes,
+    "q6_2_logn": lambda: gen.qp_hex_diffusion(2, 6, sigma=1.0),     # 343 dofs
+    "q7_2_const": lambda: gen.qp_hex_diffusion(2, 7),                # 512 dofs, the largest
 }
 _cache = {}
 
@@ -91,7 +93,7 @@ def test_extraction_weights_keys(name):
     h.close()
 
 
-@pytest.mark.parametrize("name", ["q3_4_logn", "q5_3_logn", "mixed"])
+@pytest.mark.parametrize("name", ["q3_4_logn", "q5_3_logn", "mixed", "q7_2_const"])
 def test_full_inverses(name):
     P, tiles = problem(name)
     h = pr.PatchRelax(P.A, P.ptr, P.dofs, algo="full")
@@ -144,6 +146,8 @@ ALG1_CASES = [
     ("q5_3_logn", "spectral", None, 0.9),
     ("mixed", "spectral", None, 0.5),
     ("mixed", "l1", 0.3, None),
+    ("q7_2_const", "l1", None, 1e-7),
+    ("q6_2_logn", "spectral", None, 0.9),
 ]
 
 
@@ -180,6 +184,8 @@ APPLY_CASES = [
     ("q3_4_logn", dict(algo="tolerance", eps=0.5)),
     ("mixed", dict(algo="tolerance", eps=0.5)),
     ("mixed", dict(algo="full")),
+    ("q7_2_const", dict(algo="tolerance", criterion="l1", eps=1e-7)),
+    ("q6_2_logn", dict(algo="full")),
 ]
 
 
