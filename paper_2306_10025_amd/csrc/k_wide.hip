@@ -350,6 +350,154 @@ __global__ __launch_bounds__(kWT) void k_gj_wide(int64_t count, const int32_t* _
     }
 }
 
+// Gauss-Jordan with the matrix in registers (p <= TR MA and p <= 32 MB):
+// TR x 32 threads, thread (tr, tc) holding rows tr + TR a and columns
+// tc + 32 b (block-cyclic, so every step keeps all threads busy).  Rows stay
+// in place: step c takes as pivot the largest |M[r][c]| over the rows not yet
+// used (lowest r on ties), divides row r by it (position c taking 1 / pivot)
+// and takes M[i][c] times the new row r from every other row i (position c
+// taking -M[i][c] / pivot).  Row r_c then holds row c of the inverse with its
+// columns in pivot order: X[c][r_k] = M[r_c][k].  The pivot column and row
+// reach every thread through LDS, so no step touches device memory, and
+// register indices stay compile-time (a runtime row is matched against each
+// slot by an unrolled comparison).
+template <int TR, int MA, int MB>
+__global__ __launch_bounds__(TR * 32) void k_gj_reg(int64_t count, const int32_t* __restrict__ list,
+                                                    const int64_t* __restrict__ ptr, const double* __restrict__ tiles,
+                                                    const int64_t* __restrict__ toff, int uniform_ps,
+                                                    double* __restrict__ X, const int64_t* __restrict__ xoff,
+                                                    int32_t* __restrict__ info) {
+    __shared__ double s_col[TR * MA];
+    __shared__ double s_raw[32 * MB];
+    __shared__ double s_pv[TR];
+    __shared__ int s_pi[TR];
+    __shared__ int32_t s_piv[TR * MA];      // r_c
+    __shared__ int32_t s_inv[TR * MA];      // c of row r_c
+    __shared__ int s_r;
+    __shared__ double s_best;
+    const int tid = threadIdx.x, tc = tid & 31, tr = tid >> 5;
+    for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+        const int64_t k = list ? list[i] : i;
+        const int p = ptr ? (int)(ptr[k + 1] - ptr[k]) : uniform_ps;
+        const double* src = tiles + tile_off(k, p, toff, uniform_ps);
+        double* M = X + (xoff ? xoff[i] : i * (int64_t)p * p);
+        double m[MA][MB];
+        // one row slot's loads at a time (the compiler barrier keeps all
+        // MA MB loads, each with its address, from being in flight at once)
+#pragma unroll
+        for (int a = 0; a < MA; ++a) {
+            const int r = tr + TR * a;
+            const double* row = src + (int64_t)(r < p ? r : 0) * p;
+#pragma unroll
+            for (int b = 0; b < MB; ++b) {
+                const int c = tc + 32 * b;
+                const bool ok = r < p && c < p;
+                const double v = row[ok ? c : 0];
+                m[a][b] = ok ? v : 0.0;
+            }
+            __asm__ volatile("" ::: "memory");
+        }
+        uint32_t used = 0;                  // bit a: row tr + TR a was a pivot
+        int bad = 0;
+        for (int c = 0; c < p; ++c) {
+            const int cb = c >> 5, cc = c & 31;
+            // pivot column to LDS (every row), then the TR owners pick their best
+            if (tc == cc) {
+                double bv = -1.0;
+                int bi = INT_MAX;
+#pragma unroll
+                for (int a = 0; a < MA; ++a) {
+                    const int r = tr + TR * a;
+                    double v = 0.0;
+#pragma unroll
+                    for (int b = 0; b < MB; ++b) v = (b == cb) ? m[a][b] : v;
+                    if (r < p) s_col[r] = v;
+                    if (r < p && !((used >> a) & 1u) && fabs(v) > bv) {
+                        bv = fabs(v);
+                        bi = r;
+                    }
+                }
+                s_pv[tr] = bv;
+                s_pi[tr] = bi;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double bv = s_pv[0];
+                int bi = s_pi[0];
+                for (int u = 1; u < TR; ++u)
+                    if (s_pv[u] > bv || (s_pv[u] == bv && s_pi[u] < bi)) {
+                        bv = s_pv[u];
+                        bi = s_pi[u];
+                    }
+                s_r = bi;
+                s_best = bv;
+                s_piv[c] = bi;
+                if (bi < p) s_inv[bi] = c;
+            }
+            __syncthreads();
+            if (!(s_best > 0.0)) {
+                bad = c + 1;
+                break;
+            }
+            const int r = s_r;
+            const int ra = r / TR, rr = r - ra * TR;
+            if (tr == rr) {
+#pragma unroll
+                for (int a = 0; a < MA; ++a)
+                    if (a == ra)
+#pragma unroll
+                        for (int b = 0; b < MB; ++b) s_raw[tc + 32 * b] = m[a][b];
+                used |= 1u << ra;
+            }
+            __syncthreads();
+            const double ipv = 1.0 / s_col[r];              // one division per step
+            double rv[MB];
+#pragma unroll
+            for (int b = 0; b < MB; ++b) {
+                const int j = tc + 32 * b;
+                rv[b] = j < p ? (j == c ? ipv : s_raw[j] * ipv) : 0.0;
+            }
+#pragma unroll
+            for (int a = 0; a < MA; ++a) {
+                const int row = tr + TR * a;
+                if (row >= p) continue;
+                if (row == r) {
+#pragma unroll
+                    for (int b = 0; b < MB; ++b) m[a][b] = rv[b];
+                } else {
+                    const double f = s_col[row];
+#pragma unroll
+                    for (int b = 0; b < MB; ++b) {
+                        const int j = tc + 32 * b;
+                        m[a][b] = (j == c ? 0.0 : m[a][b]) - f * rv[b];
+                    }
+                }
+            }
+            __syncthreads();                               // s_col, s_raw are rewritten next step
+        }
+        if (!bad) {
+            // X[c][r_k] = M[r_c][k]: rows by s_inv, columns by s_piv
+            int oc[MB];
+#pragma unroll
+            for (int b = 0; b < MB; ++b) {
+                const int c = tc + 32 * b;
+                oc[b] = c < p ? s_piv[c] : 0;
+            }
+#pragma unroll
+            for (int a = 0; a < MA; ++a) {
+                const int r = tr + TR * a;
+                double* row = M + (int64_t)(r < p ? s_inv[r] : 0) * p;
+#pragma unroll
+                for (int b = 0; b < MB; ++b)
+                    if (r < p && tc + 32 * b < p) row[oc[b]] = m[a][b];
+                __asm__ volatile("" ::: "memory");
+            }
+        }
+        if (tid == 0) info[i] = bad;
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // P = op(L) R for p x p row-major matrices in device memory on the FP64
 // matrix cores: the block's waves take 32 x 32 output blocks round-robin,
@@ -820,10 +968,19 @@ void launch_extract_wide(const int64_t* rowptr, const int32_t* col, const double
 }
 
 void launch_gj_wide(int64_t count, const int32_t* list, const int64_t* ptr, const double* tiles,
-                    const int64_t* toff, int uniform_ps, double* X, const int64_t* xoff, int32_t* info,
+                    const int64_t* toff, int uniform_ps, int pmax, double* X, const int64_t* xoff, int32_t* info,
                     hipStream_t s) {
     if (count <= 0) return;
-    k_gj_wide<<<grid_of(count, 4096), kWT, 0, s>>>(count, list, ptr, tiles, toff, uniform_ps, X, xoff, info);
+    // the matrix in registers up to 216 dofs (Experiment 3's size), in device memory above
+    const unsigned nb = grid_of(count, 4096);
+    if (pmax <= 128)
+        k_gj_reg<16, 8, 4><<<nb, 512, 0, s>>>(count, list, ptr, tiles, toff, uniform_ps, X, xoff, info);
+    else if (pmax <= 192)
+        k_gj_reg<32, 6, 6><<<nb, 1024, 0, s>>>(count, list, ptr, tiles, toff, uniform_ps, X, xoff, info);
+    else if (pmax <= 216)
+        k_gj_reg<24, 9, 7><<<nb, 768, 0, s>>>(count, list, ptr, tiles, toff, uniform_ps, X, xoff, info);
+    else
+        k_gj_wide<<<nb, kWT, 0, s>>>(count, list, ptr, tiles, toff, uniform_ps, X, xoff, info);
 }
 
 int64_t a1w_spectral_grid(int64_t nu) { return nu < 1 ? 1 : (nu < 512 ? nu : 512); }

@@ -150,7 +150,7 @@ int run_full(pr_handle h) {
     PR_TRY(dalloc(h, &info, n_p));
     if (h->wide)
         launch_gj_wide(n_p, nullptr, h->pptr, h->tiles, h->uniform ? nullptr : h->toff, h->uniform ? h->max_ps : 0,
-                       h->db, h->uniform ? nullptr : h->toff, info, s);
+                       h->max_ps, h->db, h->uniform ? nullptr : h->toff, info, s);
     else
         launch_batch_inverse(h->max_ps, n_p, h->tiles, h->uniform ? nullptr : h->toff, nullptr,
                              h->uniform ? nullptr : h->pptr, h->db, h->uniform ? nullptr : h->toff, info, s);
@@ -1801,7 +1801,7 @@ int pr_batch_inverse(int32_t p, int64_t count, const double* A, double* X, int32
     if ((rc = check_dev(nullptr, A, "A")) < 0) return rc;
     if ((rc = check_dev(nullptr, X, "X")) < 0) return rc;
     if ((rc = check_dev(nullptr, info, "info")) < 0) return rc;
-    if (p > 32) launch_gj_wide(count, nullptr, nullptr, A, nullptr, p, X, nullptr, info, (hipStream_t)stream);
+    if (p > 32) launch_gj_wide(count, nullptr, nullptr, A, nullptr, p, p, X, nullptr, info, (hipStream_t)stream);
     else launch_batch_inverse(p, count, A, nullptr, nullptr, nullptr, X, nullptr, info, (hipStream_t)stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return pr_fail(nullptr, PR_ERR_HIP, hipGetErrorString(e));

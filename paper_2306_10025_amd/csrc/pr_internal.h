@@ -674,9 +674,10 @@ void launch_extract_wide(const int64_t* rowptr, const int32_t* col, const double
                          const int32_t* dofs, int64_t n_p, const int64_t* toff, int uniform_ps, double* tiles,
                          uint32_t* keys, double* fnorm, double* l1norm, int32_t* flags, hipStream_t s);
 // X_i = inverse of tile list[i] (list null: tile i), at X + xoff[i] (null:
-// i * p * p); info[i] = 1 + the step of a zero pivot, else 0
+// i * p * p); info[i] = 1 + the step of a zero pivot, else 0.  ptr null: a
+// dense batch of uniform_ps x uniform_ps matrices.  pmax >= every p.
 void launch_gj_wide(int64_t count, const int32_t* list, const int64_t* ptr, const double* tiles,
-                    const int64_t* toff, int uniform_ps, double* X, const int64_t* xoff, int32_t* info,
+                    const int64_t* toff, int uniform_ps, int pmax, double* X, const int64_t* xoff, int32_t* info,
                     hipStream_t s);
 // One round of Algorithm 1: the entry m opened by U[0] is compared with
 // U[1..nu]; keep[u] = 1 for U[1+u] still open (keep[nu] = 0), phi set for

@@ -65,7 +65,7 @@ int run_alg1_wide(pr_handle h) {
                 dbcap = nb;
                 cap = ncap;
             }
-            launch_gj_wide(1, U, h->pptr, h->tiles, toff, ups, dbcap + (int64_t)m * stride, nullptr, info + m, s);
+            launch_gj_wide(1, U, h->pptr, h->tiles, toff, ups, pm, dbcap + (int64_t)m * stride, nullptr, info + m, s);
             Xm = dbcap + (int64_t)m * stride;
         }
         const int64_t nu = nU - 1;
@@ -106,7 +106,7 @@ int run_alg1_wide(pr_handle h) {
         PR_TRY(dalloc(h, &h->db, (size_t)m_p * stride));
         PR_TRY(dalloc(h, &xoff, m_p + 1));
         PR_HIP(h, hipMemcpyAsync(xoff, h->dboff_host.data(), (m_p + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-        launch_gj_wide(m_p, h->reps, h->pptr, h->tiles, toff, ups, h->db, xoff, info, s);
+        launch_gj_wide(m_p, h->reps, h->pptr, h->tiles, toff, ups, pm, h->db, xoff, info, s);
     }
     std::vector<int32_t> info_h(m_p);
     unsigned long long c4[4];
