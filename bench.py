@@ -113,6 +113,9 @@ def parse():
     ap.add_argument("--oracle-tol", type=float, default=1e-10,
                     help="tolerance of the oracle's all-patch FP64 solve that the final error is measured against")
     ap.add_argument("--no-protocol", action="store_true", help="skip the cold/warm apply protocol")
+    ap.add_argument("--orth", default="delayed", choices=["delayed", "selective"],
+                    help="Gram-Schmidt form of GMRES: delayed reorthogonalisation (two passes per step) or "
+                         "selective reorthogonalisation (three passes when the second projection runs)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="after the steps, copy this many MiB on the device (hardware-counter calibration)")
     a = ap.parse_args()
@@ -160,7 +163,7 @@ def path_params(args, P, compressed):
     # within timing noise of the default, which the counter runs also use
     tune = args.autotune or args.workload == "stokes_batch"
     common = dict(restart=30, max_iters=args.iters, deterministic=det, timing=0 if args.graph else TIMING_STRIDE,
-                  graph=args.graph, autotune=tune and not args.no_autotune)
+                  graph=args.graph, autotune=tune and not args.no_autotune, orth=args.orth)
     if not compressed:
         return dict(algo="full", precision="fp64", **common)
     if args.workload == "stokes_batch":
@@ -860,7 +863,8 @@ def main():
             "workload": wname,
             "n": P.n, "nnz": int(P.A.nnz), "n_p": P.n_p, "p_s": int(np.max(np.diff(P.ptr))), "m_p": m_p,
             "database": database,
-            "apply_precision": args.precision, "setup_precision": "f64", "krylov": "f64 GMRES(30)",
+            "apply_precision": args.precision, "setup_precision": "f64",
+            "krylov": "f64 GMRES(30), " + ("delayed" if args.orth == "delayed" else "selective") + " reorthogonalisation",
             "scatter": args.scatter, "graph": args.graph,
             "krylov_matrix": (f"hybrid sliced ELL, {st['sell_diag_slices']} of {(P.n + 63) // 64} slices "
                               f"in diagonal form, {st['sell_slots']} stored values"),

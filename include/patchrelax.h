@@ -163,6 +163,14 @@ typedef struct {
                                 residual estimate and the true residual when the apply rounds
                                 its input to reduced precision; n x gmres_restart more
                                 doubles (default 0) */
+    int32_t orth;            /* pr_solve without systems, gmres_restart <= 31: 0 (default)
+                                classical Gram-Schmidt with delayed reorthogonalisation
+                                (every vector projected twice, the second projection folded
+                                into the next step's pass: two passes over the basis per
+                                Arnoldi step; the stopping test sees a column one step
+                                later); 1 classical Gram-Schmidt whose second projection runs
+                                when the first lost more than a factor sqrt(2) (three passes
+                                when it runs).  Restarts above 31 take form 1 */
 } pr_params;
 
 /* Interpolation P0 from n_coarse coarse unknowns to the n_fine fine ones

@@ -67,7 +67,7 @@ class pr_params(Structure):
                 ("mlp_seed", c_uint64), ("mlp_lr", c_double), ("mlp_batch", c_int32),
                 ("mlp_precision", c_int32), ("graph", c_int32), ("autotune", c_int32),
                 ("apply_form", c_int32), ("alg1_prune", c_int32), ("alg1_match", c_int32),
-                ("flexible", c_int32)]
+                ("flexible", c_int32), ("orth", c_int32)]
 
 
 class pr_solve_info(Structure):
@@ -205,9 +205,10 @@ def make_params(algo="full", criterion="spectral", eps=1e-8, m_target=0, partiti
                 stream=None, mlp=False, mlp_topk=4, mlp_train_frac=0.1, mlp_epochs=60,
                 mlp_hidden=64, mlp_seed=6, mlp_lr=3e-3, mlp_batch=256,
                 mlp_precision="fp16", graph=False, autotune=False, apply_form="auto",
-                alg1_prune=True, alg1_match="first", flexible=False) -> pr_params:
+                alg1_prune=True, alg1_match="first", flexible=False, orth="delayed") -> pr_params:
     p = pr_params_default()
     p.flexible = int(flexible)
+    p.orth = {"delayed": 0, "selective": 1}[orth] if isinstance(orth, str) else int(orth)
     p.alg1_prune = int(alg1_prune)
     p.alg1_match = {"first": 0, "closest": 1}[alg1_match] if isinstance(alg1_match, str) else int(alg1_match)
     p.graph = int(graph)

@@ -13,6 +13,8 @@ namespace {
 
 constexpr int kMaxVec = 32;   // Krylov vectors per Gram-Schmidt launch
 constexpr int kGsThreads = 256;
+constexpr int kEndThreads = 256;   // step-end kernels
+constexpr int kEndBlocks = 1024;
 
 __device__ __forceinline__ bool stopped(const int32_t* stop) { return stop && *stop; }
 
@@ -423,6 +425,273 @@ __global__ __launch_bounds__(kGsThreads) void k_gs(const double* __restrict__ V,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Gram-Schmidt with delayed reorthogonalisation (two passes over the basis
+// per Arnoldi step instead of three).  At step j the basis holds the final
+// v_0 .. v_{j-1} (Q) and, in column j, u_raw = s u: the next vector after one
+// projection, not normalised (s = ||u_raw||; s = 1 for v_0); w_raw = A M u_raw.
+//   dot pass (k_gs MODE 0 over the j + 1 columns): b' = Q^T w_raw and
+//     beta' = u_raw . w_raw;
+//   update pass (k_gs_upd): v_j = (u_raw / s - Q a) / nu written over
+//     column j, w_new = (w_raw / s - Q c - c_j v_j) / nu written unnormalised
+//     to column j + 1, and the partials of [Q, v_j]^T w_new and
+//     w_new . w_new, which are the next step's a' and s^2: the
+//     reorthogonalisation coefficients of the next vector come out of this
+//     pass, which loads Q anyway.
+// k_dcgs_coef, one block, reduces both passes' partials (fixed trees) and
+// forms the coefficients.  nv <= kMaxVec.
+// ---------------------------------------------------------------------------
+constexpr int kOutU = kMaxVec + 2;       // update-pass partials per block
+
+template <int NC>
+__global__ __launch_bounds__(kGsThreads) void k_gs_upd(const double* __restrict__ V, int64_t ldv, int nv,
+                                                       double* __restrict__ u, const double* __restrict__ w,
+                                                       double* __restrict__ wnext, int64_t n,
+                                                       const double* __restrict__ coef,
+                                                       double* __restrict__ partial,
+                                                       const int32_t* __restrict__ stop) {
+    if (stopped(stop)) return;
+    constexpr int NV = 8 * NC;
+    __shared__ double s_red[kGsThreads / PR_WAVE][kOutU];
+    // coef: [0, 64) a, [64, 129) c (c[nv] multiplies v_j), [130] 1 / nu, [131] 1 / s
+    double ca[NV], cw[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        ca[i] = (i < nv) ? coef[i] : 0.0;
+        cw[i] = (i < nv) ? coef[64 + i] : 0.0;
+    }
+    const double cj = coef[64 + nv], inu = coef[130], is = coef[131];
+    int64_t vo[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) vo[i] = (int64_t)(i < nv ? i : (nv > 0 ? nv - 1 : 0)) * ldv;
+    double acc[NV + 2];
+#pragma unroll
+    for (int i = 0; i < NV + 2; ++i) acc[i] = 0.0;
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t hi = lo + per < n ? lo + per : n;
+    for (int64_t q = lo + threadIdx.x; q < hi; q += kGsThreads) {
+        const double uq = u[q];
+        const double wq = w[q];
+        double v[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = V[vo[i] + q];     // column 0 exists even for nv = 0
+        __builtin_amdgcn_sched_barrier(0);
+        double vj = uq * is, wn = wq * is;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {                // ca, cw = 0 past nv
+            vj = fma(-ca[i], v[i], vj);
+            wn = fma(-cw[i], v[i], wn);
+        }
+        vj *= inu;
+        wn = (wn - cj * vj) * inu;
+        u[q] = vj;
+        wnext[q] = wn;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] = fma(v[i], wn, acc[i]);     // terms past nv are dropped
+        acc[NV] = fma(vj, wn, acc[NV]);
+        acc[NV + 1] = fma(wn, wn, acc[NV + 1]);
+    }
+    // outputs 0..nv-1 (Q . w_new), nv (v_j . w_new), nv + 1 (w_new . w_new)
+    const int lane = threadIdx.x & (PR_WAVE - 1), wid = threadIdx.x / PR_WAVE;
+#pragma unroll
+    for (int i = 0; i < NV + 2; ++i) {
+        const int k = i < NV ? i : nv + (i - NV);
+        if (i >= NV || i < nv) {
+            const double t = wave_sum(acc[i]);
+            if (lane == 0) s_red[wid][k] = t;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < nv + 2) {
+        double t = 0.0;
+        for (int w2 = 0; w2 < kGsThreads / PR_WAVE; ++w2) t += s_red[w2][threadIdx.x];
+        partial[(int64_t)blockIdx.x * kOutU + threadIdx.x] = t;
+    }
+}
+
+// Step j of the delayed scheme (j <= 31; j = m with `last` at the end of a
+// cycle), one block of 1024 threads.  Partials: pd (dot pass of step j,
+// stride kMaxVec: b'_0..b'_{j-1}, beta') and pu (update pass of step j - 1,
+// stride kOutU: a'_0..a'_{j-1}, s^2), nblk blocks each; every output is
+// summed by one wavefront in a fixed tree.  Then, with a = a' / s,
+// b = b' / s, beta = beta' / s^2:
+//   nu = sqrt(1 - |a|^2) (nu = 1, s = 1 at j = 0, where u = v_0);
+//   column j-1 made final: H[0..j-1][j-1] += s a, H[j][j-1] = s nu, rotated by
+//   the earlier Givens rotations, its own rotation formed, g updated and
+//   the stopping test taken (as the single-projection step does);
+//   unless the cycle stops or `last` is set: gv = H[0..j][0..j-1] a, the
+//   provisional column j, h_Q = (b - gv_Q) / nu, h_j = ((beta - a.b) / nu -
+//   gv_j) / nu, the update pass's coefficients (c = gv + nu h, 1 / nu, 1 / s)
+//   and column j of T (T[i][j] = s a_i, T[j][j] = s nu: z_j = M u_raw), for
+//   the flexible form's x += Z T^{-1} y.
+// Hu: the unrotated Hessenberg matrix, row-major (m+1) x m; R: its rotated
+// upper triangle.  gctl[1] = final columns of this cycle.
+constexpr int kCoefThreads = 1024;
+__global__ __launch_bounds__(kCoefThreads) void k_dcgs_coef(int j, int m, int last, const double* __restrict__ pd,
+                                                            const double* __restrict__ pu, int nblk,
+                                                            double* __restrict__ Hu, double* __restrict__ R,
+                                                            double* __restrict__ cs, double* __restrict__ sn,
+                                                            double* __restrict__ g, double* __restrict__ est,
+                                                            double* __restrict__ T, double* __restrict__ coef,
+                                                            int32_t* __restrict__ gctl,
+                                                            const double* __restrict__ tolp,
+                                                            const int64_t* __restrict__ itb, int64_t max_iters) {
+    __shared__ double sa[64], sb[64], col[65], scs[64], ssn[64];
+    __shared__ double sH[33][32];             // band of H[0..j][0..j-1]
+    __shared__ double s_part[kCoefThreads / PR_WAVE][64];
+    __shared__ double s_s, s_beta, s_g, s_tol;
+    __shared__ int64_t s_itb;
+    __shared__ int s_stop;
+    const int t = threadIdx.x, lane = t & (PR_WAVE - 1), wv = t / PR_WAVE;
+    constexpr int NW = kCoefThreads / PR_WAVE;
+    const int c = j - 1;
+    // every input, loaded by all threads in one round: the scalars, the
+    // Hessenberg band, the rotations, then each wavefront's sums
+    if (t == 0) s_stop = gctl[0];
+    if (t == 1 && j > 0) s_g = g[c];
+    if (t == 2) s_tol = *tolp;
+    if (t == 3) s_itb = *itb;
+    {
+        const int i = t >> 5, k = t & 31;     // row i, column k of the band
+        if (i <= j && k < j && k + 1 >= i) sH[i][k] = Hu[(int64_t)i * m + k];
+    }
+    if (t < c) {
+        scs[t] = cs[t];
+        ssn[t] = sn[t];
+    }
+    const int nd = last ? 0 : j + 1;         // dot-pass outputs
+    const int nu_out = j > 0 ? j + 1 : 0;     // update-pass outputs
+    // block partials summed with coalesced loads: lane o < 32 takes dot
+    // output o, lane 32 + o update output o; wavefront w adds blocks w,
+    // w + NW, ..., then the NW wavefront sums are added in order
+    {
+        const bool up = lane >= 32;
+        const int o = up ? lane - 32 : lane;
+        const bool live = up ? o < nu_out : o < nd;
+        const double* P = up ? pu : pd;
+        const int st = up ? kOutU : kMaxVec;
+        // nblk <= 512 = 32 NW: all of a lane's loads in one round (the
+        // partials were just written from every XCD, so each load waits for
+        // the last-level cache)
+        double v[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            const int b = wv + NW * u;
+            const bool ok = live && b < nblk;
+            const double x = P[ok ? (int64_t)b * st + o : 0];
+            v[u] = ok ? x : 0.0;
+        }
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < 32; ++u) acc += v[u];
+        s_part[wv][lane] = acc;
+    }
+    __syncthreads();
+    if (t < 64) {
+        double acc = 0.0;
+        for (int w2 = 0; w2 < NW; ++w2) acc += s_part[w2][t];
+        const bool up = t >= 32;
+        const int o = up ? t - 32 : t;
+        if (!up && o < nd) {
+            if (o < j) sb[o] = acc; else s_beta = acc;
+        }
+        if (up && o < nu_out) {
+            if (o < j) sa[o] = acc; else s_s = acc;
+        }
+    }
+    __syncthreads();
+    if (s_stop || wv != 0) return;
+    // the rest by one wavefront, lane i holding row i (j <= 31)
+    const int i = lane;
+    double sc = 1.0, nu = 1.0;
+    double ai = 0.0, bi = 0.0;
+    double beta = last ? 0.0 : s_beta;        // beta' / s^2 (s = 1 at j = 0)
+    if (j > 0) {
+        sc = sqrt(fmax(s_s, 0.0));
+        const double isc = sc > 0.0 ? 1.0 / sc : 0.0;
+        ai = i < j ? sa[i] * isc : 0.0;
+        const double s2 = wave_sum(ai * ai);
+        nu = (s2 < 1.0 && sc > 0.0) ? sqrt(1.0 - s2) : 0.0;
+        if (!last) {
+            bi = i < j ? sb[i] * isc : 0.0;
+            beta *= isc * isc;
+        }
+        // column j-1 final (Hu and the band), then rotated
+        double cl = 0.0;
+        if (i < j) cl = sH[i][c] + sc * ai;
+        if (i == j) cl = sc * nu;
+        if (i <= j) {
+            sH[i][c] = cl;
+            Hu[(int64_t)i * m + c] = cl;
+        }
+        for (int r = 0; r < c; ++r) {
+            const double x0 = __shfl(cl, r), x1 = __shfl(cl, r + 1);
+            const double cr = scs[r], sr = ssn[r];
+            if (i == r) cl = cr * x0 + sr * x1;
+            if (i == r + 1) cl = -sr * x0 + cr * x1;
+        }
+        const double a0 = __shfl(cl, c), hn = __shfl(cl, j);
+        const double den = hypot(a0, hn);
+        const double cc = den > 0.0 ? a0 / den : 1.0;
+        const double ss = den > 0.0 ? hn / den : 0.0;
+        if (i == c) cl = den;
+        if (i <= c) R[(int64_t)i * m + c] = cl;
+        const double gj = -ss * s_g;
+        bool stop = !(fabs(gj) > s_tol) || s_itb + j >= max_iters || j >= m || !(nu > 0.0);
+        if (i == 0) {
+            cs[c] = cc;
+            sn[c] = ss;
+            g[j] = gj;
+            g[c] = cc * s_g;
+            gctl[1] = j;
+            gctl[2] = j;
+            est[0] = fabs(gj);
+            if (stop) gctl[0] = 1;
+        }
+        if (stop) return;
+    } else {
+        bi = 0.0;
+    }
+    if (last) return;
+    // provisional column j and the update coefficients: lane i forms
+    // gv_i = sum_k H[i][k] a_k over the Hessenberg band (H[i][k] = 0 for
+    // i > k + 1), a_k broadcast from lane k
+    const double ab = wave_sum(ai * bi);
+    const double inu = 1.0 / nu;
+    double gvt = 0.0;
+    for (int k = 0; k < j; ++k) {
+        const double ak = __shfl(ai, k);
+        if (i <= j && k + 1 >= i) gvt += sH[i][k] * ak;
+    }
+    if (i < j) {
+        const double hq = (bi - gvt) * inu;
+        Hu[(int64_t)i * m + j] = hq;
+        coef[i] = ai;
+        coef[64 + i] = gvt + nu * hq;
+        T[(int64_t)i * m + j] = sc * ai;
+    } else if (i == j) {
+        const double hv = ((beta - ab) * inu - gvt) * inu;
+        Hu[(int64_t)j * m + j] = hv;
+        coef[64 + j] = gvt + nu * hv;
+        coef[130] = inu;
+        coef[131] = 1.0 / sc;
+        T[(int64_t)j * m + j] = sc * nu;
+    }
+}
+
+// y <- T^{-1} y over the final columns (T upper triangular, row-major m x m)
+__global__ void k_trisolve_T(int m, const double* __restrict__ T, double* __restrict__ y,
+                             const int32_t* __restrict__ gctl) {
+    if (threadIdx.x != 0) return;
+    const int mm = gctl[1];
+    for (int i = mm - 1; i >= 0; --i) {
+        double t = y[i];
+        for (int k = i + 1; k < mm; ++k) t -= T[(int64_t)i * m + k] * y[k];
+        y[i] = t / T[(int64_t)i * m + i];
+    }
+}
+
 // out[i] = sum over blocks of partial[b][i]; one block per output (a fixed
 // tree).  (A last-block-reduces variant inside k_gs needs a device-scope
 // release per block, an L2 write-back on this GPU; it measured twice as
@@ -509,8 +778,6 @@ __global__ void k_cycle_init(double* __restrict__ g, int m, const double* __rest
 // gctl: [0] stop  [1] columns done this cycle  [2] steps with a third pass.
 // The stop flag is read once per block; a block that starts after block 0 has
 // set it skips its part of v_{j+1}, which a stopped cycle never reads.
-constexpr int kEndThreads = 256;
-constexpr int kEndBlocks = 1024;
 constexpr int kEndUnroll = 4;
 __global__ __launch_bounds__(kEndThreads) void k_step_end(
         const double* __restrict__ partial, int nblk, const double* sel, const double* __restrict__ w,
@@ -692,6 +959,41 @@ void launch_gs(int mode, const double* V, int64_t ldv, int nv, double* w, int64_
 #undef PR_GS
         if (nv == 0) break;
     }
+}
+
+void launch_gs_partials(const double* V, int64_t ldv, int nv, double* w, int64_t n, double* partial, hipStream_t s,
+                        const int32_t* stop) {
+    const int nbk = gs_blocks(n);
+    const int nc = (nv + 7) / 8;
+#define PR_GS0(CC) k_gs<0, CC><<<nbk, kGsThreads, 0, s>>>(V, ldv, nv, w, n, nullptr, partial, stop, 0, nullptr)
+    if (nc <= 1) PR_GS0(1);
+    else if (nc == 2) PR_GS0(2);
+    else if (nc == 3) PR_GS0(3);
+    else PR_GS0(4);
+#undef PR_GS0
+}
+
+void launch_gs_upd(const double* V, int64_t ldv, int nv, double* u, const double* w, double* wnext, int64_t n,
+                   const double* coef, double* partial, hipStream_t s, const int32_t* stop) {
+    const int nbk = gs_blocks(n);
+    const int nc = nv <= 8 ? 1 : (nv + 7) / 8;
+#define PR_GSU(CC) k_gs_upd<CC><<<nbk, kGsThreads, 0, s>>>(V, ldv, nv, u, w, wnext, n, coef, partial, stop)
+    if (nc == 1) PR_GSU(1);
+    else if (nc == 2) PR_GSU(2);
+    else if (nc == 3) PR_GSU(3);
+    else PR_GSU(4);
+#undef PR_GSU
+}
+
+void launch_dcgs_coef(int j, int m, bool last, const double* pd, const double* pu, int64_t n, double* Hu, double* R,
+                      double* cs, double* sn, double* g, double* est, double* T, double* coef, int32_t* gctl,
+                      const double* tolp, const int64_t* itb, int64_t max_iters, hipStream_t s) {
+    k_dcgs_coef<<<1, kCoefThreads, 0, s>>>(j, m, last ? 1 : 0, pd, pu, gs_blocks(n), Hu, R, cs, sn, g, est, T, coef,
+                                           gctl, tolp, itb, max_iters);
+}
+
+void launch_trisolve_T(int m, const double* T, double* y, const int32_t* gctl, hipStream_t s) {
+    k_trisolve_T<<<1, 64, 0, s>>>(m, T, y, gctl);
 }
 
 void launch_scale(const double* src, double* dst, const double* denom, int64_t n, hipStream_t s,

@@ -729,8 +729,8 @@ int ensure_workspace(pr_handle h, int m) {
     PR_TRY(dalloc(h, &h->w, n));
     PR_TRY(dalloc(h, &h->t1, n));
     PR_TRY(dalloc(h, &h->t2, 3 * n));   // preconditioned vector, sweep residual, scratch
-    PR_TRY(dalloc(h, &h->red, (size_t)gs_blocks(n) * 32 + 64));
-    PR_TRY(dalloc(h, &h->gm, 8192));
+    PR_TRY(dalloc(h, &h->red, (size_t)gs_blocks(n) * 72 + 64));   // up to 66 partials per block
+    PR_TRY(dalloc(h, &h->gm, 16384));
     PR_TRY(dalloc(h, &h->gctl, 4));
     PR_TRY(dalloc(h, &h->hd, 256));
     if (!h->hh) PR_HIP(h, pool_host_alloc(256 * sizeof(double), (void**)&h->hh, &h->hh_got));
@@ -1065,6 +1065,7 @@ void pr_params_default(pr_params* p) {
     p->alg1_prune = 1;
     p->alg1_match = 0;
     p->flexible = 0;
+    p->orth = 0;
 }
 
 const char* pr_status_string(int st) {
@@ -1234,7 +1235,7 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
         pm.gmres_restart > 64 || !(pm.eps >= 0.0) || !(pm.omega > 0.0) ||
         (pm.apply_form != PR_FORM_AUTO && pm.apply_form != PR_FORM_GENERAL) ||
         (pm.alg1_prune != 0 && pm.alg1_prune != 1) || (pm.alg1_match != 0 && pm.alg1_match != 1) ||
-        (pm.flexible != 0 && pm.flexible != 1))
+        (pm.flexible != 0 && pm.flexible != 1) || (pm.orth != 0 && pm.orth != 1))
         return pr_fail(nullptr, PR_ERR_INVALID_ARG, "bad parameter value");
     if (pm.alg1_match == 1 && (pm.algo != PR_ALGO_TOLERANCE || pm.mlp != 0 || !(pm.tie_rel >= 0.0)))
         return pr_fail(nullptr, PR_ERR_INVALID_ARG, "closest matching needs PR_ALGO_TOLERANCE without mlp");
@@ -1578,6 +1579,14 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
     double* est_d = y + m;
     double* tol_d = est_d + 1;
     int64_t* itb_d = reinterpret_cast<int64_t*>(tol_d + 1);
+    // delayed reorthogonalisation: the unrotated Hessenberg matrix, T and
+    // the update coefficients
+    double* Hu = reinterpret_cast<double*>(itb_d + 1);
+    double* Tm = Hu + (int64_t)(m + 1) * m;
+    double* coef = Tm + (int64_t)m * m;
+    const bool delayed = h->prm.orth == 0 && m <= 31;
+    double* red_dot = red;                                    // dot-pass partials, stride 32
+    double* red_upd = red + (int64_t)gs_blocks(n) * 32;       // update-pass partials, stride 34
     int32_t* gctl = h->gctl;
     int32_t* gctl_h = reinterpret_cast<int32_t*>(hh + 240);   // pinned mirror of gctl
     int64_t* itb_h = reinterpret_cast<int64_t*>(hh + 236);
@@ -1637,6 +1646,20 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
             // pass 3 (only when pass 2 lost more than a factor sqrt(2)):
             // w -= V h2, ||w||^2 ; then v_{j+1} = w / ||w||.  Beyond 31 basis
             // vectors every step takes all three passes.
+            if (delayed) {
+                // delayed reorthogonalisation: the dot pass [Q, u_raw]^T w, the
+                // coefficient step (column j-1 made final with its Givens
+                // rotation and stopping test, the provisional column j), the
+                // update pass (v_j over u_raw, the next unnormalised vector in
+                // column j+1 and its dots with [Q, v_j])
+                tbeg();
+                launch_gs_partials(V, ldv, j + 1, w, n, red_dot, s, gctl);
+                launch_dcgs_coef(j, m, false, red_dot, red_upd, n, Hu, R, cs, sn, g, est_d, Tm, coef, gctl, tol_d,
+                                 itb_d, h->prm.max_iters, s);
+                launch_gs_upd(V, ldv, j, vj, w, V + (int64_t)(j + 1) * ldv, n, coef, red_upd, s, gctl);
+                tend(2);
+                continue;
+            }
             const bool sel = j + 1 < 32;
             tbeg();
             launch_gs(0, V, ldv, j + 1, w, n, nullptr, red, hd, s, gctl, sel);
@@ -1647,11 +1670,21 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
                             est_d, gctl, tol_d, itb_d, h->prm.max_iters, s);
             tend(2);
         }
+        if (delayed) {
+            // the last column made final from the last update pass's dots
+            tsel = timing && tstride == 1;
+            tj = m - 1;
+            tbeg();
+            launch_dcgs_coef(m, m, true, red_dot, red_upd, n, Hu, R, cs, sn, g, est_d, Tm, coef, gctl, tol_d,
+                             itb_d, h->prm.max_iters, s);
+            tend(2);
+        }
         tsel = timing && tstride == 1;
         tj = -1;
         launch_trisolve(m, R, g, y, gctl, s);
         if (flex) {
-            // x += Z y
+            // x += Z y (delayed form: Z holds M u_j, so x += Z T^{-1} y)
+            if (delayed) launch_trisolve_T(m, Tm, y, gctl, s);
             launch_gemv_small(h->Zb, ldv, gctl + 1, y, n, zt, s);
         } else {
             // x += M (V y)
@@ -1716,13 +1749,22 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
     h->sinfo.relres_est = est;
     h->sinfo.status = relres <= tol ? PR_OK : PR_NOT_CONVERGED;
     h->sinfo.seconds = now_s() - tstart;
+    // the delayed form's end-of-cycle pass is recorded under the cycle's last
+    // step: its time adds to that step's orthogonalisation, one launch
+    int64_t orth_cyc = -1;
+    int orth_j = -1;
     for (const Span& sp : spans) {
         float ms = 0.0f;
         if (sp.j >= 0 && (sp.cyc >= (int64_t)done_cols.size() || sp.j >= done_cols[sp.cyc])) continue;
         if (hipEventElapsedTime(&ms, sp.a, sp.b) != hipSuccess) continue;
         if (sp.cls == 0) { h->sinfo.apply_ms += ms; h->sinfo.n_apply++; }
         if (sp.cls == 1) { h->sinfo.spmv_ms += ms; h->sinfo.n_spmv++; }
-        if (sp.cls == 2) { h->sinfo.orth_ms += ms; h->sinfo.n_orth++; }
+        if (sp.cls == 2) {
+            h->sinfo.orth_ms += ms;
+            if (sp.j < 0 || sp.cyc != orth_cyc || sp.j != orth_j) h->sinfo.n_orth++;
+            orth_cyc = sp.cyc;
+            orth_j = sp.j;
+        }
         if (sp.cls == 3) { h->sinfo.coarse_ms += ms; h->sinfo.n_coarse++; }
     }
     return h->sinfo.status;

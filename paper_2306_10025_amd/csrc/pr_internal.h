@@ -633,6 +633,18 @@ void launch_gs(int mode, const double* V, int64_t ldv, int nv, double* w, int64_
 void launch_step_end(const double* partial, const double* sel, const double* w, double* vnext, int64_t n,
                      int j, int m, double* hd, double* R, double* cs, double* sn, double* g, double* est,
                      int32_t* gctl, const double* tolp, const int64_t* itb, int64_t max_iters, hipStream_t s);
+// Gram-Schmidt with delayed reorthogonalisation (nv <= 32): the dot pass's
+// block partials (stride 32, V_i . w for i < nv), the update pass (v_j over
+// u, the unnormalised next vector to wnext, partials of its dots, stride
+// 34), and the one-block coefficient step between them
+void launch_gs_partials(const double* V, int64_t ldv, int nv, double* w, int64_t n, double* partial, hipStream_t s,
+                        const int32_t* stop);
+void launch_gs_upd(const double* V, int64_t ldv, int nv, double* u, const double* w, double* wnext, int64_t n,
+                   const double* coef, double* partial, hipStream_t s, const int32_t* stop);
+void launch_dcgs_coef(int j, int m, bool last, const double* pd, const double* pu, int64_t n, double* Hu, double* R,
+                      double* cs, double* sn, double* g, double* est, double* T, double* coef, int32_t* gctl,
+                      const double* tolp, const int64_t* itb, int64_t max_iters, hipStream_t s);
+void launch_trisolve_T(int m, const double* T, double* y, const int32_t* gctl, hipStream_t s);
 void launch_trisolve(int m, const double* R, const double* g, double* y, const int32_t* gctl,
                      hipStream_t s);
 void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
