@@ -1,10 +1,14 @@
 """Parity at the full size of the benchmark workload (Nedelec 64^3: 811,200
 dofs, 262,144 patches), in the configuration bench.py times, on outputs the
-oracle computes one by one: sampled tiles and weights (bit-exact), the
-defining properties of Algorithm 1 on sampled patches, and the apply at
-sampled dofs (FP64 within 1e-12 of the oracle; the split-BF16 apply within
-its accuracy of the FP64 one).
+oracle computes one by one: sampled tiles and weights (bit-exact), Algorithm
+1's patch map and entries for all 262,144 patches against the oracle's
+sequential loop (SHA-256 digests written once by
+tests/golden/make_alg1_nedelec64.py) and its defining properties on sampled
+patches, and the apply at sampled dofs (FP64 within 1e-12 of the oracle; the
+split-BF16 apply within its accuracy of the FP64 one).
 """
+import hashlib
+import os
 import sys
 
 import numpy as np
@@ -57,6 +61,31 @@ def test_fullsize_tiles_weights_keys(big):
     W = h.weights()
     idx = rng.choice(P.n, size=2000, replace=False)
     assert np.array_equal(W[idx], 1.0 / cnt[idx])
+
+
+def _golden_alg1():
+    out = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "alg1_nedelec_hex_64.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                k, v = line.split(None, 1)
+                out[k] = v.strip()
+    return out
+
+
+def test_fullsize_algorithm1_equals_the_sequential_oracle(big):
+    # every patch: phi and the entries bit for bit, and evaluations plus
+    # pruned pairs equal to the comparisons of the oracle's sequential loop
+    P, h = big
+    g = _golden_alg1()
+    phi, reps = h.assignment()
+    st = h.stats()
+    say("m_p", len(reps), "evals + pruned", st["crit_evals"] + st["crit_pruned"], "oracle", g["evals"])
+    assert P.n_p == int(g["n_p"]) and len(reps) == int(g["m_p"])
+    assert hashlib.sha256(np.asarray(phi, dtype="<i4").tobytes()).hexdigest() == g["phi_sha256"]
+    assert hashlib.sha256(np.asarray(reps, dtype="<i4").tobytes()).hexdigest() == g["reps_sha256"]
+    assert st["crit_evals"] + st["crit_pruned"] == int(g["evals"])
 
 
 def test_fullsize_algorithm1_properties(big):
