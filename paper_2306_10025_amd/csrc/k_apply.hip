@@ -727,8 +727,8 @@ void launch_apply(int prec, bool two_stage, const ApplyLaunch& a, hipStream_t s)
         const int64_t n_tiles = (a.n_p + NB - 1) / NB;
         const int mode = prec == PR_FP16 ? 1 : prec == PR_BF16X3 ? 2 : 0;
         const int64_t lp_stride = (mode == 2 ? 2 : 1) * (big ? 1024 : 256);
-        // tiles per wave: 1 unless the shape asks for 2 (16-member tiles only)
-        const int tpw = (!big && a.tiles_per_wave == 2) ? 2 : 1;
+        // tiles per wave: 1 unless the shape asks for 2 or 4 (16-member tiles only)
+        const int tpw = (!big && (a.tiles_per_wave == 2 || a.tiles_per_wave == 4)) ? a.tiles_per_wave : 1;
         if (n_tiles > 0) {
             const unsigned nb = shape_blocks((n_tiles + tpw - 1) / tpw, T / PR_WAVE, cap);
 #define PR_TILE(MODE, TWO, BIG, U) k_apply_tiles<MODE, TWO, BIG, U><<<nb, T, 0, s>>>(a.n_p, a.tile_p, g, a.db_lp, lp_stride, a.db_exp, a.W, a.omega, a.r, a.z, (float*)a.Y)
@@ -736,10 +736,12 @@ void launch_apply(int prec, bool two_stage, const ApplyLaunch& a, hipStream_t s)
     if (mode == 0) PR_TILE(0, TWO, BIG, U); else if (mode == 1) PR_TILE(1, TWO, BIG, U); else PR_TILE(2, TWO, BIG, U)
             if (two_stage) {
                 if (big) { PR_TILE_M(true, true, 1); }
+                else if (tpw == 4) { PR_TILE_M(true, false, 4); }
                 else if (tpw == 2) { PR_TILE_M(true, false, 2); }
                 else { PR_TILE_M(true, false, 1); }
             } else {
                 if (big) { PR_TILE_M(false, true, 1); }
+                else if (tpw == 4) { PR_TILE_M(false, false, 4); }
                 else if (tpw == 2) { PR_TILE_M(false, false, 2); }
                 else { PR_TILE_M(false, false, 1); }
             }

@@ -801,6 +801,22 @@ int autotune_apply(pr_handle h) {
     }
     double *r = sc.buf, *z = sc.buf + n, *tmp = sc.buf + 2 * n;
     launch_copy(r, h->W, n, s);               // any vector will do
+    // a 512 MB write between timed applications evicts the caches: inside a
+    // solve the apply follows a product and an orthogonalisation that stream
+    // more than the last-level cache holds, so its data arrives cold
+    struct Flush {
+        int device;
+        double* buf = nullptr;
+        size_t got = 0;
+        ~Flush() {
+            if (buf) pool_release(device, buf, got);
+        }
+    } fl{h->device};
+    const int64_t nflush = (int64_t)64 << 20;
+    if (pool_alloc(h->device, (size_t)nflush * sizeof(double), (void**)&fl.buf, &fl.got) != hipSuccess) {
+        fl.buf = nullptr;
+        (void)hipGetLastError();
+    }
     PR_HIP(h, hipEventCreate(&sc.e0));
     PR_HIP(h, hipEventCreate(&sc.e1));
     hipEvent_t e0 = sc.e0, e1 = sc.e1;
@@ -811,11 +827,17 @@ int autotune_apply(pr_handle h) {
         h->tune_tpw = tpw;
         h->tune_remap = rm;
         for (int k = 0; k < 2; ++k) PR_TRY(apply_op(h, r, z, false, tmp));
-        PR_HIP(h, hipEventRecord(e0, s));
-        for (int k = 0; k < 5; ++k) PR_TRY(apply_op(h, r, z, false, tmp));
-        PR_HIP(h, hipEventRecord(e1, s));
-        PR_HIP(h, hipEventSynchronize(e1));
-        PR_HIP(h, hipEventElapsedTime(&ms, e0, e1));
+        ms = 0.0f;
+        for (int k = 0; k < 5; ++k) {
+            if (fl.buf) launch_zero(fl.buf, nflush, s);
+            PR_HIP(h, hipEventRecord(e0, s));
+            PR_TRY(apply_op(h, r, z, false, tmp));
+            PR_HIP(h, hipEventRecord(e1, s));
+            PR_HIP(h, hipEventSynchronize(e1));
+            float one = 0.0f;
+            PR_HIP(h, hipEventElapsedTime(&one, e0, e1));
+            ms += one;
+        }
         return PR_OK;
     };
     int bt = 256, bs = 256, bu = 0, br = 1;
@@ -838,8 +860,8 @@ int autotune_apply(pr_handle h) {
     const bool remap_choice = h->tile_p > 0 || h->ell_c > 0;
     for (int rm : {1, 0}) {
         if (rm == 0 && !remap_choice) break;
-        for (int u : {1, 2}) {
-            if (u == 2 && !tpw_choice) break;
+        for (int u : {1, 2, 4}) {
+            if (u >= 2 && !tpw_choice) break;
             for (int T : {64, 128, 256})
                 for (int64_t cap : {(int64_t)0, (int64_t)1024, (int64_t)2048, (int64_t)4096, (int64_t)8192}) {
                     float ms = 0.0f;

@@ -141,7 +141,10 @@ def test_batch_fp32_matches_single_system_solves():
     its, rel = h.system_info()
     for s, Ps in enumerate(subs):
         lo, hi = sptr[s], sptr[s + 1]
-        h1 = pr.PatchRelax(Ps.A, Ps.ptr, Ps.dofs, algo="full", precision="fp32", deterministic=True, max_iters=30)
+        # the batch solver projects with the selective form, so the single
+        # solves use it too (the default delayed form rounds differently)
+        h1 = pr.PatchRelax(Ps.A, Ps.ptr, Ps.dofs, algo="full", precision="fp32", deterministic=True, max_iters=30,
+                           orth="selective")
         bb = torch.as_tensor(b_np[lo:hi]).to(DEV)
         xx = torch.zeros_like(bb)
         h1.solve(bb, xx, 1e-10)
