@@ -198,8 +198,11 @@ def algorithmic_bytes(P, m_p, precision, n_items, n_p_entries, st=None):
              + 4 * n_p           # entry of each patch
              + 16 * n_items      # work items (grouped kernels)
              + db)               # database inverses
-    if st is not None and st.get("sell_slots", 0) > 0:
-        index = 4 * (st["sell_diag_offsets"] + st["sell_col_entries"]) + 8 * ((n + 63) // 64 + 1)
+    if st is not None and (st.get("sell_slots", 0) > 0 or st.get("sell_csr_slices", 0) > 0):
+        # diagonal-form offsets, column-form columns, and for slices read from
+        # the CSR copy their columns and row pointers
+        index = (4 * (st["sell_diag_offsets"] + st["sell_col_entries"] + st.get("sell_csr_entries", 0))
+                 + 8 * 64 * st.get("sell_csr_slices", 0) + 8 * ((n + 63) // 64 + 1))
     else:
         index = 4 * P.A.nnz + 8 * (n + 1)
     spmv = 8 * P.A.nnz + index + 8 * n + 8 * n
@@ -867,7 +870,8 @@ def main():
             "krylov": "f64 GMRES(30), " + ("delayed" if args.orth == "delayed" else "selective") + " reorthogonalisation",
             "scatter": args.scatter, "graph": args.graph,
             "krylov_matrix": (f"hybrid sliced ELL, {st['sell_diag_slices']} of {(P.n + 63) // 64} slices "
-                              f"in diagonal form, {st['sell_slots']} stored values"),
+                              f"in diagonal form, {st.get('sell_csr_slices', 0)} read from the CSR copy, "
+                              f"{st['sell_slots']} stored values"),
             "tol": args.tol, "max_iters": args.iters, "parallelism": "single GPU",
         },
         "setup_s": round(float(np.mean([s["t_total"] + s["t_coarse"] for _, s in g["rec"]])), 4),

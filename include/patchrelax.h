@@ -274,6 +274,11 @@ typedef struct {
     int64_t reuse_kept;          /* patches still within eps of their previous entry */
     int64_t reuse_rescanned;     /* patches placed on another entry by the in-order scan */
     int64_t reuse_appended;      /* entries appended for patches no entry matched */
+    /* the solve's copy of A, third form: slices whose rows differ so much in
+       length that the column form would pad them by more than 30 % (average
+       row at least 32 entries) read their rows from the CSR copy */
+    int64_t sell_csr_slices;     /* slices in that form */
+    int64_t sell_csr_entries;    /* their matrix entries */
 } pr_stats;
 
 /* ---- entry points ------------------------------------------------------ */

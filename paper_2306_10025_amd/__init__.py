@@ -99,7 +99,7 @@ class pr_stats(Structure):
                 ("closest_moved", c_int64), ("n_coarse", c_int64), ("coarse_nnz", c_int64),
                 ("coarse_bandwidth", c_int64), ("coarse_block", c_int64), ("coarse_blocks", c_int64),
                 ("t_coarse", c_double), ("reuse_kept", c_int64), ("reuse_rescanned", c_int64),
-                ("reuse_appended", c_int64)]
+                ("reuse_appended", c_int64), ("sell_csr_slices", c_int64), ("sell_csr_entries", c_int64)]
 
 
 _SIGS = {

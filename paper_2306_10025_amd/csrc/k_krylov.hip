@@ -130,7 +130,11 @@ __global__ __launch_bounds__(kPlanThreads) void k_sell_plan(const int64_t* __res
     }
     __syncthreads();
     const int mlen = s_mlen, ndiag = s_cnt;
-    const int fmt = (collect && !s_over && mlen > 0 && 2 * ndiag <= 3 * mlen && ndiag <= kMaxDiag) ? 1 : 0;
+    int fmt = (collect && !s_over && mlen > 0 && 2 * ndiag <= 3 * mlen && ndiag <= kMaxDiag) ? 1 : 0;
+    // long rows of very different lengths (high-order cells: 216 to 1331
+    // entries in one slice) would pad the column form by more than 30 %: the
+    // slice's rows are then read from the CSR copy, 16 lanes per row
+    if (!fmt && rows > 0 && 10 * (int64_t)mlen * rows > 13 * (int64_t)s_nnz && s_nnz >= 32 * rows) fmt = 2;
     if (fmt) {
         // the set as a list, sorted (at most kMaxDiag values in kPlanThreads slots)
         for (int e = t; e < kPlanTab; e += kPlanThreads) {
@@ -154,37 +158,44 @@ __global__ __launch_bounds__(kPlanThreads) void k_sell_plan(const int64_t* __res
         if (t < ndiag) dtmp[sl * kMaxDiag + t] = lst[t];
     }
     if (t == 0) {
-        slen[sl] = 64 * (int64_t)(fmt ? ndiag : mlen);
+        slen[sl] = fmt == 2 ? 0 : 64 * (int64_t)(fmt ? ndiag : mlen);
         sfmt[sl] = fmt;
-        cnnz[sl] = fmt ? 0 : s_nnz;
+        cnnz[sl] = fmt == 0 ? s_nnz : (fmt == 2 ? -s_nnz : 0);   // form 2: its entries, negated
     }
 }
 
-// acc[3] += {diagonal slices, their offsets, entries of column-form slices}:
+// acc[5] += {diagonal slices, their offsets, entries of column-form slices,
+// CSR-row slices, their entries}:
 // a grid-stride sum per block, three atomics per block (one atomic per slice
 // on three addresses serialised into hundreds of microseconds)
 constexpr int kTotalsBlocks = 128;
 __global__ __launch_bounds__(256) void k_sell_totals(const int64_t* __restrict__ slen, const int32_t* __restrict__ sfmt,
                                                      const int32_t* __restrict__ cnnz, int64_t ns,
                                                      unsigned long long* __restrict__ acc) {
-    __shared__ unsigned long long s_a[3][256 / PR_WAVE];
-    unsigned long long a0 = 0, a1 = 0, a2 = 0;
+    __shared__ unsigned long long s_a[5][256 / PR_WAVE];
+    unsigned long long a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
     for (int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; sl < ns; sl += (int64_t)gridDim.x * blockDim.x) {
         const int f = sfmt[sl];
-        a0 += f ? 1ull : 0ull;
-        a1 += f ? (unsigned long long)(slen[sl] / 64) : 0ull;
-        a2 += f ? 0ull : (unsigned long long)cnnz[sl];
+        a0 += f == 1 ? 1ull : 0ull;
+        a1 += f == 1 ? (unsigned long long)(slen[sl] / 64) : 0ull;
+        a2 += f == 0 ? (unsigned long long)cnnz[sl] : 0ull;
+        a3 += f == 2 ? 1ull : 0ull;
+        a4 += f == 2 ? (unsigned long long)(-(int64_t)cnnz[sl]) : 0ull;
     }
     a0 = wave_sum(a0);
     a1 = wave_sum(a1);
     a2 = wave_sum(a2);
+    a3 = wave_sum(a3);
+    a4 = wave_sum(a4);
     if ((threadIdx.x & (PR_WAVE - 1)) == 0) {
         s_a[0][threadIdx.x / PR_WAVE] = a0;
         s_a[1][threadIdx.x / PR_WAVE] = a1;
         s_a[2][threadIdx.x / PR_WAVE] = a2;
+        s_a[3][threadIdx.x / PR_WAVE] = a3;
+        s_a[4][threadIdx.x / PR_WAVE] = a4;
     }
     __syncthreads();
-    if (threadIdx.x < 3) {
+    if (threadIdx.x < 5) {
         unsigned long long u = 0;
         for (int w = 0; w < 256 / PR_WAVE; ++w) u += s_a[threadIdx.x][w];
         atomicAdd(&acc[threadIdx.x], u);
@@ -240,7 +251,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_sell_fill_diag(const int64_t* 
                                                                  int32_t* __restrict__ sdoff) {
     __shared__ int32_t s_d[kMaxDiag];
     const int64_t sl = blockIdx.x;
-    if (!sfmt[sl]) return;
+    if (sfmt[sl] != 1) return;
     const int t = threadIdx.x;
     const int64_t off = soff[sl];
     const int nd = (int)((soff[sl + 1] - off) / 64);
@@ -277,15 +288,56 @@ __global__ __launch_bounds__(256) void k_spmv_sell(SellMat M, int64_t n, const d
                                                    const int32_t* __restrict__ stop) {
     if (stopped(stop)) return;
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;      // padding lanes of the last slice hold no entries
     // one slice per wavefront: its descriptors are wave-uniform (scalar loads)
     const int64_t sl = __builtin_amdgcn_readfirstlane((int)(r / 64));
     const int lane = (int)(r % 64);
+    const int fmt = M.sfmt[sl];
+    // padding lanes of the last slice hold no entries; the CSR-row form
+    // needs every lane of the wavefront
+    if (r >= n && fmt != 2) return;
     const int64_t off = M.soff[sl];
     const int len = (int)((M.soff[sl + 1] - off) / 64);
     const double* vp = M.sval + off + lane;
     double acc0 = 0.0, acc1 = 0.0;
-    if (M.sfmt[sl]) {
+    if (fmt == 2) {
+        // rows from the CSR copy: lane group q (16 lanes) takes rows q, q + 4,
+        // ...; each row's entries at unit stride, eight loads of values and
+        // columns in flight per lane, a 16-lane sum; the 64 row sums return
+        // to their lanes through LDS
+        __shared__ double s_row[256];
+        const int wbase = (int)(threadIdx.x & ~(PR_WAVE - 1));
+        const int grp = lane >> 4, sub = lane & 15;
+        const int64_t r0 = sl * 64;
+        for (int rr = grp; rr < 64; rr += 4) {
+            const int64_t row = r0 + rr;
+            double sacc = 0.0;
+            if (row < n) {
+                const int64_t a = M.rowptr[row], e = M.rowptr[row + 1];
+                for (int64_t q0 = a + sub; q0 < e; q0 += 128) {
+                    double v[8];
+                    int32_t cc[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int64_t q = q0 + 16 * u;
+                        const bool ok = q < e;
+                        v[u] = M.val[ok ? q : a];
+                        cc[u] = M.col[ok ? q : a];
+                        v[u] = ok ? v[u] : 0.0;
+                    }
+                    double xv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) xv[u] = x[cc[u]];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) sacc = fma(v[u], xv[u], sacc);
+                }
+            }
+            for (int o = 8; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, 16);
+            if (sub == 0) s_row[wbase + rr] = sacc;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        acc0 = s_row[wbase + lane];
+    } else if (fmt == 1) {
         // diagonal form: neither the values nor the gathers depend on earlier
         // loads, so kSpmvChunk of each are issued together, and the entries
         // alternate between the two accumulators by column parity.  Past the
@@ -324,7 +376,7 @@ __global__ __launch_bounds__(256) void k_spmv_sell(SellMat M, int64_t n, const d
         for (; k < len; ++k) acc0 = fma(vp[k * 64], x[cp[k * 64]], acc0);
     }
     const double acc = acc0 + acc1;
-    y[r] = b ? b[r] - acc : acc;
+    if (r < n) y[r] = b ? b[r] - acc : acc;
 }
 
 // Selective reorthogonalisation (the test of Daniel, Gragg, Kaufman and

@@ -1434,12 +1434,12 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
         SETUP_TRY(dalloc(h, &h->soff, ns + 1));
         SETUP_TRY(dalloc(h, &h->sfmt, ns));
         SETUP_TRY(dalloc(h, &dtmp, (size_t)ns * (kSellMaxDiag + 1)));
-        SETUP_TRY(dalloc(h, &sacc, 3));
-        SETUP_HIP(hipMemsetAsync(sacc, 0, 3 * sizeof(unsigned long long), s));
+        SETUP_TRY(dalloc(h, &sacc, 5));
+        SETUP_HIP(hipMemsetAsync(sacc, 0, 5 * sizeof(unsigned long long), s));
         launch_sell_plan(h->rowptr, h->col, h->n, slen, h->sfmt, dtmp, sacc, s);
         launch_exclusive_scan_i64(slen, h->soff, ns + 1, sscr, s);
         int64_t stot = 0;
-        unsigned long long sa[3];
+        unsigned long long sa[5];
         SETUP_HIP(hipMemcpyAsync(&stot, h->soff + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         SETUP_HIP(hipMemcpyAsync(sa, sacc, sizeof(sa), hipMemcpyDeviceToHost, s));
         SETUP_HIP(hipStreamSynchronize(s));
@@ -1451,6 +1451,8 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
         h->stats.sell_diag_slices = (int64_t)sa[0];
         h->stats.sell_diag_offsets = (int64_t)sa[1];
         h->stats.sell_col_entries = (int64_t)sa[2];
+        h->stats.sell_csr_slices = (int64_t)sa[3];
+        h->stats.sell_csr_entries = (int64_t)sa[4];
     }
     SETUP_TRY(run_group(h));
     h->stats.tune_xcd_remap = (h->tile_p > 0 || h->ell_c > 0) ? h->tune_remap : 0;

@@ -67,7 +67,10 @@ struct SellMat {
     const double* sval = nullptr;
     const int32_t* scol = nullptr;
     const int32_t* sdoff = nullptr;
-    const int32_t* sfmt = nullptr;
+    const int32_t* sfmt = nullptr;      // 0 column form, 1 diagonal form, 2 rows read from the CSR copy
+    const int64_t* rowptr = nullptr;    // the CSR copy (form 2)
+    const int32_t* col = nullptr;
+    const double* val = nullptr;
 };
 constexpr int kSellMaxDiag = 192;   // distinct offsets a diagonal-form slice may hold
 constexpr int kSellOffsetPad = 16;  // entries allocated past the last slice's offsets
@@ -99,7 +102,7 @@ struct pr_handle_s {
     int32_t* scol = nullptr;
     int32_t* sdoff = nullptr;
     int32_t* sfmt = nullptr;
-    SellMat sell() const { return SellMat{soff, sval, scol, sdoff, sfmt}; }
+    SellMat sell() const { return SellMat{soff, sval, scol, sdoff, sfmt, rowptr, col, val}; }
 
     // Section 2 objects
     int32_t* cnt = nullptr;
@@ -606,7 +609,8 @@ int gs_blocks(int64_t n);
 // Plan of the hybrid copy: slen[ns + 1] (stored columns * 64 per slice, 0
 // at ns, for the exclusive scan), sfmt[ns], dtmp[ns * (kSellMaxDiag + 1)]
 // (the offsets of diagonal-form slices, then one entry count per slice),
-// acc[3] += {diagonal slices, their offsets, entries of column-form slices}
+// acc[5] += {diagonal slices, their offsets, entries of column-form slices,
+// CSR-row slices, their entries}
 // (acc zeroed by the caller).
 void launch_sell_plan(const int64_t* rowptr, const int32_t* col, int64_t n, int64_t* slen, int32_t* sfmt,
                       int32_t* dtmp, unsigned long long* acc, hipStream_t s);
