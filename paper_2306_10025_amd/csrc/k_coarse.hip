@@ -2,8 +2,9 @@
 //   M_combo^{-1} r = M~^{-1} r + P0 A0^{-1} R0 r,   R0 = P0^T,  A0 = R0 A P0,
 // with A0 solved directly, as in the first two numerical experiments.
 //
-// Setup: R0 by a transpose of P0; A0 one coarse row per wavefront with a
-// fixed summation order per entry (deterministic); then a direct solver:
+// Setup: R0 by a transpose of P0; A0 = R0 (A P0) in two sparse products, one
+// row per wavefront each, with a fixed summation order per entry
+// (deterministic); then a direct solver:
 //  - small A0 (dense form): its explicit inverse;
 //  - otherwise A0 is banded (|v - w| <= b for every entry), so with blocks of
 //    s >= b rows it is block tridiagonal, and block LU without pivoting across
@@ -74,23 +75,36 @@ __global__ void k_tr_fill(int64_t n, const int64_t* __restrict__ rp, const int32
     }
 }
 
-// rows of the transpose in ascending column (the fill order depends on timing)
-__global__ void k_tr_sort(int64_t m, const int64_t* __restrict__ tp, int32_t* __restrict__ tc,
-                          double* __restrict__ tv) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Rows of the transpose in ascending column.  The fill order depends on
+// timing, so each row is rewritten from the filled copy (uc, uv) by rank, one
+// wavefront per row: an entry's rank is the number of entries before it in
+// (column, value bits, position) order.  Equal columns come only from a
+// column repeated within one input row; the value bits then order them, and
+// entries equal in both are interchangeable, so the row is the same whatever
+// the fill order.  Quadratic in the row length, read from the cache.
+__global__ __launch_bounds__(256) void k_tr_rank(int64_t m, const int64_t* __restrict__ tp,
+                                                 const int32_t* __restrict__ uc, const double* __restrict__ uv,
+                                                 int32_t* __restrict__ tc, double* __restrict__ tv) {
+    const int64_t r = (int64_t)blockIdx.x * (blockDim.x / PR_WAVE) + threadIdx.x / PR_WAVE;
+    const int lane = threadIdx.x & (PR_WAVE - 1);
     if (r >= m) return;
-    const int64_t a = tp[r], b = tp[r + 1];
-    for (int64_t e = a + 1; e < b; ++e) {
-        const int32_t kc = tc[e];
-        const double kv = tv[e];
-        int64_t q = e - 1;
-        while (q >= a && tc[q] > kc) {
-            tc[q + 1] = tc[q];
-            tv[q + 1] = tv[q];
-            --q;
+    const int64_t a = tp[r], len = tp[r + 1] - a;
+    for (int64_t e = lane; e < len; e += PR_WAVE) {
+        const int32_t c = uc[a + e];
+        const double v = uv[a + e];
+        const unsigned long long vb = (unsigned long long)__double_as_longlong(v);
+        int64_t rk = 0;
+        for (int64_t f = 0; f < len; ++f) {
+            const int32_t cf = uc[a + f];
+            if (cf == c) {
+                const unsigned long long fb = (unsigned long long)__double_as_longlong(uv[a + f]);
+                rk += (fb < vb || (fb == vb && f < e)) ? 1 : 0;
+            } else {
+                rk += cf < c ? 1 : 0;
+            }
         }
-        tc[q + 1] = kc;
-        tv[q + 1] = kv;
+        tc[a + rk] = c;
+        tv[a + rk] = v;
     }
 }
 
@@ -99,13 +113,44 @@ constexpr int kGalSlots = 256;   // distinct coarse columns one coarse row may r
 
 __device__ __forceinline__ int gal_hash(int32_t w) { return (int)(((uint32_t)w * 2654435761u) >> 24); }
 
+// Row v of A0 from the lane-owned sums acc[q] of the columns of rank
+// q * 64 + lane (nk columns, ascending in sorted[]): entries at most drop
+// times the row's largest magnitude are dropped (rounding residue of couplings
+// that vanish exactly); the rest go to out + v * kGalSlots in column order.
+__device__ __forceinline__ void gal_emit(const double (&acc)[kGalSlots / PR_WAVE], int nk,
+                                         const int32_t* sorted, double drop, int64_t v, int32_t* ocnt,
+                                         int32_t* ocol, double* oval) {
+    constexpr int Q = kGalSlots / PR_WAVE;
+    const int lane = threadIdx.x & (PR_WAVE - 1);
+    double mx = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+        if (q * PR_WAVE + lane < nk) mx = fmax(mx, fabs(acc[q]));
+    mx = wave_max(mx);
+    const double lim = drop * mx;
+    int base = 0;
+    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int r = q * PR_WAVE + lane;
+        const bool keep = r < nk && fabs(acc[q]) > lim;
+        const unsigned long long m = __ballot(keep);
+        if (keep) {
+            const int pos = base + __popcll(m & below);
+            ocol[v * kGalSlots + pos] = sorted[r];
+            oval[v * kGalSlots + pos] = acc[q];
+        }
+        base += __popcll(m);
+    }
+    if (lane == 0) ocnt[v] = base;
+}
+
 // Pass 1 collects the coarse columns w reachable from row v (R0 row v, then A
 // rows, then P0 rows) in an LDS hash set; they are ranked in ascending order.
 // Pass 2: lane l owns the columns of rank l, l + 64, ...; every lane walks the
 // same stream of products r_vi a_ij p_jw in the same order and adds those of
-// its columns, so each entry is summed in one fixed order.  Entries at most
-// drop times the row's largest magnitude are dropped (rounding residue of
-// couplings that vanish exactly).  Output: row v at out + v * kGalSlots.
+// its columns, so each entry is summed in one fixed order.  The general form,
+// for interpolations whose rows of A P0 reach more than kApSlots columns.
 __global__ __launch_bounds__(64) void k_galerkin(
     int64_t n0, const int64_t* __restrict__ rrp, const int32_t* __restrict__ rci, const double* __restrict__ rv,
     const int64_t* __restrict__ arp, const int32_t* __restrict__ aci, const double* __restrict__ av,
@@ -188,27 +233,197 @@ __global__ __launch_bounds__(64) void k_galerkin(
                 }
             }
         }
-        double mx = 0.0;
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-            if (q * PR_WAVE + lane < nk) mx = fmax(mx, fabs(acc[q]));
-        mx = wave_max(mx);
-        const double lim = drop * mx;
-        int base = 0;
-        const unsigned long long below = (1ull << lane) - 1ull;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int r = q * PR_WAVE + lane;
-            const bool keep = r < nk && fabs(acc[q]) > lim;
-            const unsigned long long m = __ballot(keep);
-            if (keep) {
-                const int pos = base + __popcll(m & below);
-                ocol[v * kGalSlots + pos] = sorted[r];
-                oval[v * kGalSlots + pos] = acc[q];
+        gal_emit(acc, nk, sorted, drop, v, ocnt, ocol, oval);
+        __syncthreads();
+    }
+}
+
+// ---- Galerkin product in two products: B = A P0, then A0 = R0 B ------------
+constexpr int kApSlots = 32;      // distinct coarse columns one row of A P0 may reach
+constexpr int kApHash = 2 * kApSlots;
+
+__device__ __forceinline__ int ap_hash(int32_t w) { return (int)(((uint32_t)w * 2654435761u) >> 26); }
+
+// B = A P0, one wavefront per fine row i.  Pass 1 collects the row's coarse
+// columns (the P0 rows of A's columns) in an LDS hash set and ranks them.
+// Pass 2: lane l takes A's entries l, l + 64, ... and adds a_ij p_jw into its
+// own partial of column w; lane s then adds the 64 partials of the column of
+// rank s in lane order, so each entry is summed in one fixed order.  Output:
+// row i at out + i * kApSlots, columns ascending, bcnt[i] of them; a row with
+// more than kApSlots columns sets *overflow (and writes bcnt[i] = 0).
+__global__ __launch_bounds__(64) void k_ap(int64_t n, const int64_t* __restrict__ arp,
+                                           const int32_t* __restrict__ aci, const double* __restrict__ av,
+                                           const int64_t* __restrict__ prp, const int32_t* __restrict__ pci,
+                                           const double* __restrict__ pv, int32_t* __restrict__ bcnt,
+                                           int32_t* __restrict__ bcol, double* __restrict__ bval,
+                                           int32_t* __restrict__ overflow) {
+    __shared__ int32_t keys[kApHash];
+    __shared__ int32_t rank[kApHash];
+    __shared__ int32_t sorted[kApSlots];
+    __shared__ double part[kApSlots * PR_WAVE];
+    const int lane = threadIdx.x;
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        for (int t = lane; t < kApHash; t += PR_WAVE) keys[t] = -1;
+        __syncthreads();
+        const int64_t a0 = arp[i], a1 = arp[i + 1];
+        bool over = false;
+        for (int64_t ea = a0 + lane; ea < a1; ea += PR_WAVE) {
+            const int32_t j = aci[ea];
+            for (int64_t ep = prp[j]; ep < prp[j + 1]; ++ep) {
+                const int32_t w = pci[ep];
+                int h = ap_hash(w);
+                int probes = 0;
+                while (true) {
+                    const int32_t old = atomicCAS(&keys[h], -1, w);
+                    if (old == -1 || old == w) break;
+                    h = (h + 1) & (kApHash - 1);
+                    if (++probes >= kApHash) {
+                        over = true;
+                        break;
+                    }
+                }
             }
-            base += __popcll(m);
         }
-        if (lane == 0) ocnt[v] = base;
+        __syncthreads();
+        int nk = 0;
+        for (int t = lane; t < kApHash; t += PR_WAVE) {
+            const int32_t k = keys[t];
+            int r = -1;
+            if (k >= 0) {
+                r = 0;
+                for (int u = 0; u < kApHash; ++u) {
+                    const int32_t o = keys[u];
+                    r += (o >= 0 && o < k) ? 1 : 0;
+                }
+                if (r < kApSlots) sorted[r] = k;
+                ++nk;
+            }
+            rank[t] = r;
+        }
+        nk = wave_sum(nk);
+        if (__ballot(over) || nk > kApSlots) {
+            if (lane == 0) {
+                atomicOr(overflow, 1);
+                bcnt[i] = 0;
+            }
+            __syncthreads();
+            continue;
+        }
+        for (int r = 0; r < nk; ++r) part[r * PR_WAVE + lane] = 0.0;
+        __syncthreads();
+        for (int64_t ea = a0 + lane; ea < a1; ea += PR_WAVE) {
+            const int32_t j = aci[ea];
+            const double aij = av[ea];
+            for (int64_t ep = prp[j]; ep < prp[j + 1]; ++ep) {
+                const int32_t w = pci[ep];
+                int h = ap_hash(w);
+                while (keys[h] != w) h = (h + 1) & (kApHash - 1);
+                part[rank[h] * PR_WAVE + lane] += aij * pv[ep];
+            }
+        }
+        __syncthreads();
+        if (lane < nk) {
+            double sum = 0.0;
+            for (int l = 0; l < PR_WAVE; ++l) sum += part[lane * PR_WAVE + l];
+            bcol[i * kApSlots + lane] = sorted[lane];
+            bval[i * kApSlots + lane] = sum;
+        }
+        if (lane == 0) bcnt[i] = nk;
+        __syncthreads();
+    }
+}
+
+// A0 = R0 B, one wavefront per coarse row v.  Pass 1 collects the columns of
+// the B rows that R0 row v names (lanes over R0's entries) in an LDS hash set
+// and ranks them.  Pass 2: the two half-waves take R0's entries in turn (the
+// first the even positions, the second the odd); the lanes of a half-wave
+// take the entries of that B row (at most kApSlots, distinct columns) and add
+// r_vi b_iw into the half-wave's sum of column w, so no two lanes of one step
+// touch one sum.  The two halves are added at the end: a fixed order again.
+__global__ __launch_bounds__(64) void k_rb(int64_t n0, const int64_t* __restrict__ rrp,
+                                           const int32_t* __restrict__ rci, const double* __restrict__ rv,
+                                           const int32_t* __restrict__ bcnt, const int32_t* __restrict__ bcol,
+                                           const double* __restrict__ bval, double drop,
+                                           int32_t* __restrict__ ocnt, int32_t* __restrict__ ocol,
+                                           double* __restrict__ oval, int32_t* __restrict__ overflow) {
+    static_assert(kApSlots <= PR_WAVE / 2, "a B row fits one half-wave");
+    __shared__ int32_t keys[kGalSlots];
+    __shared__ int32_t rank[kGalSlots];
+    __shared__ int32_t sorted[kGalSlots];
+    __shared__ double sums[2][kGalSlots];
+    const int lane = threadIdx.x;
+    const int half = lane / (PR_WAVE / 2), t = lane % (PR_WAVE / 2);
+    constexpr int Q = kGalSlots / PR_WAVE;
+    for (int64_t v = blockIdx.x; v < n0; v += gridDim.x) {
+        for (int s = lane; s < kGalSlots; s += PR_WAVE) {
+            keys[s] = -1;
+            sums[0][s] = 0.0;
+            sums[1][s] = 0.0;
+        }
+        __syncthreads();
+        bool over = false;
+        const int64_t r0 = rrp[v], r1 = rrp[v + 1];
+        for (int64_t er = r0 + lane; er < r1; er += PR_WAVE) {
+            const int32_t i = rci[er];
+            const int c = bcnt[i];
+            for (int u = 0; u < c; ++u) {
+                const int32_t w = bcol[(int64_t)i * kApSlots + u];
+                int h = gal_hash(w);
+                int probes = 0;
+                while (true) {
+                    const int32_t old = atomicCAS(&keys[h], -1, w);
+                    if (old == -1 || old == w) break;
+                    h = (h + 1) & (kGalSlots - 1);
+                    if (++probes >= kGalSlots) {
+                        over = true;
+                        break;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (__ballot(over)) {
+            if (lane == 0) {
+                atomicOr(overflow, 1);
+                ocnt[v] = 0;
+            }
+            __syncthreads();
+            continue;
+        }
+        int nk = 0;
+        for (int s = lane; s < kGalSlots; s += PR_WAVE) {
+            const int32_t k = keys[s];
+            int r = -1;
+            if (k >= 0) {
+                r = 0;
+                for (int u = 0; u < kGalSlots; ++u) {
+                    const int32_t o = keys[u];
+                    r += (o >= 0 && o < k) ? 1 : 0;
+                }
+                sorted[r] = k;
+                ++nk;
+            }
+            rank[s] = r;
+        }
+        nk = wave_sum(nk);
+        __syncthreads();
+        for (int64_t er = r0 + half; er < r1; er += 2) {
+            const int32_t i = rci[er];
+            const double ri = rv[er];
+            if (t < bcnt[i]) {
+                const int32_t w = bcol[(int64_t)i * kApSlots + t];
+                const double b = bval[(int64_t)i * kApSlots + t];
+                int h = gal_hash(w);
+                while (keys[h] != w) h = (h + 1) & (kGalSlots - 1);
+                double* sp = &sums[half][rank[h]];
+                *sp = fma(ri, b, *sp);
+            }
+        }
+        __syncthreads();
+        double acc[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) acc[q] = sums[0][q * PR_WAVE + lane] + sums[1][q * PR_WAVE + lane];
+        gal_emit(acc, nk, sorted, drop, v, ocnt, ocol, oval);
         __syncthreads();
     }
 }
@@ -537,16 +752,17 @@ void launch_interp_check(int64_t n, int64_t n0, int64_t nnz, const int64_t* rp, 
     k_interp_check<<<nbk(n + 1, 256), 256, 0, st>>>(n, n0, nnz, rp, ci, v, flags);
 }
 
-// transpose: tp int64[m+1] (out), tc/tv [nnz] (out); cnt, fill: int64[m+1] scratch
+// transpose: tp int64[m+1] (out), tc/tv [nnz] (out); cnt, fill: int64[m+1],
+// uc/uv [nnz] scratch
 int launch_csr_transpose(int64_t n, int64_t m, const int64_t* rp, const int32_t* ci, const double* v,
-                         int64_t* tp, int32_t* tc, double* tv, int64_t* cnt, int64_t* fill,
-                         int64_t* scan_scr, hipStream_t st) {
+                         int64_t* tp, int32_t* tc, double* tv, int64_t* cnt, int64_t* fill, int32_t* uc,
+                         double* uv, int64_t* scan_scr, hipStream_t st) {
     if (hipMemsetAsync(cnt, 0, (m + 1) * sizeof(int64_t), st) != hipSuccess) return -1;
     if (hipMemsetAsync(fill, 0, (m + 1) * sizeof(int64_t), st) != hipSuccess) return -1;
     if (n > 0) k_tr_count<<<nbk(n, 256), 256, 0, st>>>(n, rp, ci, cnt);
     launch_exclusive_scan_i64(cnt, tp, m + 1, scan_scr, st);
-    if (n > 0) k_tr_fill<<<nbk(n, 256), 256, 0, st>>>(n, rp, ci, v, tp, fill, tc, tv);
-    if (m > 0) k_tr_sort<<<nbk(m, 256), 256, 0, st>>>(m, tp, tc, tv);
+    if (n > 0) k_tr_fill<<<nbk(n, 256), 256, 0, st>>>(n, rp, ci, v, tp, fill, uc, uv);
+    if (m > 0) k_tr_rank<<<nbk(m, 4), 256, 0, st>>>(m, tp, uc, uv, tc, tv);
     return 0;
 }
 
@@ -559,6 +775,24 @@ void launch_galerkin(int64_t n0, const int64_t* rrp, const int32_t* rci, const d
     if (n0 <= 0) return;
     const unsigned g = (unsigned)(n0 < 16384 ? n0 : 16384);
     k_galerkin<<<g, 64, 0, st>>>(n0, rrp, rci, rv, arp, aci, av, prp, pci, pv, drop, ocnt, ocol, oval, overflow);
+}
+
+int coarse_ap_slots() { return kApSlots; }
+
+void launch_ap(int64_t n, const int64_t* arp, const int32_t* aci, const double* av, const int64_t* prp,
+               const int32_t* pci, const double* pv, int32_t* bcnt, int32_t* bcol, double* bval,
+               int32_t* overflow, hipStream_t st) {
+    if (n <= 0) return;
+    const unsigned g = (unsigned)(n < 65536 ? n : 65536);
+    k_ap<<<g, 64, 0, st>>>(n, arp, aci, av, prp, pci, pv, bcnt, bcol, bval, overflow);
+}
+
+void launch_rb(int64_t n0, const int64_t* rrp, const int32_t* rci, const double* rv, const int32_t* bcnt,
+               const int32_t* bcol, const double* bval, double drop, int32_t* ocnt, int32_t* ocol, double* oval,
+               int32_t* overflow, hipStream_t st) {
+    if (n0 <= 0) return;
+    const unsigned g = (unsigned)(n0 < 16384 ? n0 : 16384);
+    k_rb<<<g, 64, 0, st>>>(n0, rrp, rci, rv, bcnt, bcol, bval, drop, ocnt, ocol, oval, overflow);
 }
 
 void launch_rows_finish(int64_t n0, const int32_t* cnt32, int64_t* cnt64, int64_t* rp, int64_t* scan_scr,

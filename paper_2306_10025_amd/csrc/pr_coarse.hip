@@ -90,10 +90,23 @@ int pr_set_coarse(pr_handle h, const pr_interp* P) {
     PR_TRY(dalloc(h, &cnt, big));
     PR_TRY(dalloc(h, &fill, big));
     PR_TRY(dalloc(h, &scr, scan_scratch_elems(big) + 2));
-    if (launch_csr_transpose(n, n0, p0_rp, p0_ci, p0_v, r0_rp, r0_ci, r0_v, cnt, fill, scr, s) != 0)
-        return pr_fail(h, PR_ERR_HIP, "transpose of P0");
+    {
+        int32_t* uc = nullptr;
+        double* uv = nullptr;
+        PR_TRY(dalloc(h, &uc, nnz));
+        PR_TRY(dalloc(h, &uv, nnz));
+        if (launch_csr_transpose(n, n0, p0_rp, p0_ci, p0_v, r0_rp, r0_ci, r0_v, cnt, fill, uc, uv, scr, s) != 0)
+            return pr_fail(h, PR_ERR_HIP, "transpose of P0");
+        PR_HIP(h, hipStreamSynchronize(s));
+        dfree(h, uc);
+        dfree(h, uv);
+    }
 
-    // A0 = R0 A P0, one coarse row per wavefront into padded rows, then CSR
+    // A0 = R0 (A P0): B = A P0 one fine row per wavefront into padded rows,
+    // then one coarse row per wavefront into padded rows, then CSR.  When a
+    // row of B reaches more coarse columns than its padding holds, the
+    // triple product runs in one kernel instead (R0, A and P0 walked per
+    // coarse row).
     const int slots = coarse_gal_slots();
     int32_t *ocnt = nullptr, *ocol = nullptr, *over = nullptr;
     double* oval = nullptr;
@@ -101,9 +114,30 @@ int pr_set_coarse(pr_handle h, const pr_interp* P) {
     PR_TRY(dalloc(h, &ocol, (size_t)n0 * slots));
     PR_TRY(dalloc(h, &oval, (size_t)n0 * slots));
     PR_TRY(dalloc(h, &over, 1));
-    PR_HIP(h, hipMemsetAsync(over, 0, sizeof(int32_t), s));
-    launch_galerkin(n0, r0_rp, r0_ci, r0_v, h->rowptr, h->col, h->val, p0_rp, p0_ci, p0_v, kDrop, ocnt, ocol,
-                    oval, over, s);
+    {
+        const int bs = coarse_ap_slots();
+        int32_t *bcnt = nullptr, *bcol = nullptr;
+        double* bval = nullptr;
+        PR_TRY(dalloc(h, &bcnt, n));
+        PR_TRY(dalloc(h, &bcol, (size_t)n * bs));
+        PR_TRY(dalloc(h, &bval, (size_t)n * bs));
+        PR_HIP(h, hipMemsetAsync(over, 0, sizeof(int32_t), s));
+        launch_ap(n, h->rowptr, h->col, h->val, p0_rp, p0_ci, p0_v, bcnt, bcol, bval, over, s);
+        int32_t ap_over = 0;
+        PR_HIP(h, hipMemcpyAsync(&ap_over, over, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        PR_HIP(h, hipStreamSynchronize(s));
+        if (!ap_over) {
+            launch_rb(n0, r0_rp, r0_ci, r0_v, bcnt, bcol, bval, kDrop, ocnt, ocol, oval, over, s);
+        } else {
+            PR_HIP(h, hipMemsetAsync(over, 0, sizeof(int32_t), s));
+            launch_galerkin(n0, r0_rp, r0_ci, r0_v, h->rowptr, h->col, h->val, p0_rp, p0_ci, p0_v, kDrop, ocnt,
+                            ocol, oval, over, s);
+        }
+        PR_HIP(h, hipStreamSynchronize(s));
+        dfree(h, bcnt);
+        dfree(h, bcol);
+        dfree(h, bval);
+    }
     int64_t* a0_rp = nullptr;
     PR_TRY(dalloc(h, &a0_rp, n0 + 1));
     launch_rows_finish(n0, ocnt, cnt, a0_rp, scr, s);
@@ -162,8 +196,15 @@ int pr_set_coarse(pr_handle h, const pr_interp* P) {
         PR_TRY(dalloc(h, &a0t_rp, n0 + 1));
         PR_TRY(dalloc(h, &a0t_ci, a0_nnz));
         PR_TRY(dalloc(h, &a0t_v, a0_nnz));
-        if (launch_csr_transpose(n0, n0, a0_rp, a0_ci, a0_v, a0t_rp, a0t_ci, a0t_v, cnt, fill, scr, s) != 0)
+        int32_t* uc = nullptr;
+        double* uv = nullptr;
+        PR_TRY(dalloc(h, &uc, a0_nnz));
+        PR_TRY(dalloc(h, &uv, a0_nnz));
+        if (launch_csr_transpose(n0, n0, a0_rp, a0_ci, a0_v, a0t_rp, a0t_ci, a0t_v, cnt, fill, uc, uv, scr, s) != 0)
             return pr_fail(h, PR_ERR_HIP, "transpose of A0");
+        PR_HIP(h, hipStreamSynchronize(s));
+        dfree(h, uc);
+        dfree(h, uv);
         const size_t blk = (size_t)sb * sb;
         PR_TRY(dalloc(h, &X, blk * nbk));
         PR_TRY(dalloc(h, &G, blk * nbk));

@@ -486,13 +486,20 @@ void launch_set_at(int64_t n, const int32_t* ids, int32_t v, int32_t* dst, hipSt
 void launch_interp_check(int64_t n, int64_t n0, int64_t nnz, const int64_t* rp, const int32_t* ci,
                          const double* v, int32_t* flags, hipStream_t st);
 int launch_csr_transpose(int64_t n, int64_t m, const int64_t* rp, const int32_t* ci, const double* v,
-                         int64_t* tp, int32_t* tc, double* tv, int64_t* cnt, int64_t* fill,
-                         int64_t* scan_scr, hipStream_t st);
+                         int64_t* tp, int32_t* tc, double* tv, int64_t* cnt, int64_t* fill, int32_t* uc,
+                         double* uv, int64_t* scan_scr, hipStream_t st);
 int coarse_gal_slots();
 void launch_galerkin(int64_t n0, const int64_t* rrp, const int32_t* rci, const double* rv, const int64_t* arp,
                      const int32_t* aci, const double* av, const int64_t* prp, const int32_t* pci,
                      const double* pv, double drop, int32_t* ocnt, int32_t* ocol, double* oval,
                      int32_t* overflow, hipStream_t st);
+int coarse_ap_slots();
+void launch_ap(int64_t n, const int64_t* arp, const int32_t* aci, const double* av, const int64_t* prp,
+               const int32_t* pci, const double* pv, int32_t* bcnt, int32_t* bcol, double* bval,
+               int32_t* overflow, hipStream_t st);
+void launch_rb(int64_t n0, const int64_t* rrp, const int32_t* rci, const double* rv, const int32_t* bcnt,
+               const int32_t* bcol, const double* bval, double drop, int32_t* ocnt, int32_t* ocol, double* oval,
+               int32_t* overflow, hipStream_t st);
 void launch_rows_finish(int64_t n0, const int32_t* cnt32, int64_t* cnt64, int64_t* rp, int64_t* scan_scr,
                         hipStream_t st);
 void launch_rows_compact(int64_t n0, const int64_t* rp, const int32_t* icol, const double* ival, int32_t* ocol,
