@@ -588,6 +588,15 @@ __global__ __launch_bounds__(kGsThreads) void k_gs_upd(const double* __restrict_
 //   the flexible form's x += Z T^{-1} y.
 // Hu: the unrotated Hessenberg matrix, row-major (m+1) x m; R: its rotated
 // upper triangle.  gctl[1] = final columns of this cycle.
+// x of lane `src` (wave-uniform) in every lane: two v_readlane, no LDS
+// round trip as a shuffle takes
+__device__ __forceinline__ double lane_bcast(double x, int src) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 constexpr int kCoefThreads = 1024;
 __global__ __launch_bounds__(kCoefThreads) void k_dcgs_coef(int j, int m, int last, const double* __restrict__ pd,
                                                             const double* __restrict__ pu, int nblk,
@@ -686,13 +695,15 @@ __global__ __launch_bounds__(kCoefThreads) void k_dcgs_coef(int j, int m, int la
             sH[i][c] = cl;
             Hu[(int64_t)i * m + c] = cl;
         }
+        // lane r holds rotation r; every broadcast below reads a uniform lane
+        const double mcs = i < c ? scs[i] : 1.0, msn = i < c ? ssn[i] : 0.0;
         for (int r = 0; r < c; ++r) {
-            const double x0 = __shfl(cl, r), x1 = __shfl(cl, r + 1);
-            const double cr = scs[r], sr = ssn[r];
+            const double x0 = lane_bcast(cl, r), x1 = lane_bcast(cl, r + 1);
+            const double cr = lane_bcast(mcs, r), sr = lane_bcast(msn, r);
             if (i == r) cl = cr * x0 + sr * x1;
             if (i == r + 1) cl = -sr * x0 + cr * x1;
         }
-        const double a0 = __shfl(cl, c), hn = __shfl(cl, j);
+        const double a0 = lane_bcast(cl, c), hn = lane_bcast(cl, j);
         const double den = hypot(a0, hn);
         const double cc = den > 0.0 ? a0 / den : 1.0;
         const double ss = den > 0.0 ? hn / den : 0.0;
@@ -722,7 +733,7 @@ __global__ __launch_bounds__(kCoefThreads) void k_dcgs_coef(int j, int m, int la
     const double inu = 1.0 / nu;
     double gvt = 0.0;
     for (int k = 0; k < j; ++k) {
-        const double ak = __shfl(ai, k);
+        const double ak = lane_bcast(ai, k);
         if (i <= j && k + 1 >= i) gvt += sH[i][k] * ak;
     }
     if (i < j) {
@@ -741,16 +752,33 @@ __global__ __launch_bounds__(kCoefThreads) void k_dcgs_coef(int j, int m, int la
     }
 }
 
-// y <- T^{-1} y over the final columns (T upper triangular, row-major m x m)
-__global__ void k_trisolve_T(int m, const double* __restrict__ T, double* __restrict__ y,
-                             const int32_t* __restrict__ gctl) {
-    if (threadIdx.x != 0) return;
-    const int mm = gctl[1];
-    for (int i = mm - 1; i >= 0; --i) {
-        double t = y[i];
-        for (int k = i + 1; k < mm; ++k) t -= T[(int64_t)i * m + k] * y[k];
-        y[i] = t / T[(int64_t)i * m + i];
+// x = U^{-1} b for the leading mm x mm block of an upper triangular U
+// (row-major, leading dimension m <= 64), one wavefront: U's triangle is
+// staged in LDS in one round, lane l holds b_l, and column i is eliminated
+// once x_i is known (x_i broadcast from lane i), so every step is one
+// division and one fused multiply-add per lane.  b and x may alias.
+__device__ __forceinline__ void tri_upper_solve(int m, int mm, const double* __restrict__ U, const double* b,
+                                                double* x) {
+    __shared__ double sU[64][65];
+    const int l = threadIdx.x;
+    for (int e = l; e < mm * mm; e += PR_WAVE) {
+        const int i = e / mm, k = e % mm;
+        if (k >= i) sU[i][k] = U[(int64_t)i * m + k];
     }
+    double t = l < mm ? b[l] : 0.0;
+    __syncthreads();
+    for (int i = mm - 1; i >= 0; --i) {
+        const double xi = lane_bcast(t / sU[i][i], i);
+        if (l == i) t = xi;
+        if (l < i) t = fma(-sU[l][i], xi, t);
+    }
+    if (l < mm) x[l] = t;
+}
+
+// y <- T^{-1} y over the final columns (T upper triangular, row-major m x m)
+__global__ __launch_bounds__(PR_WAVE) void k_trisolve_T(int m, const double* __restrict__ T, double* y,
+                                                        const int32_t* __restrict__ gctl) {
+    tri_upper_solve(m, gctl[1], T, y, y);
 }
 
 // out[i] = sum over blocks of partial[b][i]; one block per output (a fixed
@@ -941,15 +969,10 @@ __global__ __launch_bounds__(kEndThreads) void k_step_end(
 }
 
 // y = R^{-1} g over the columns done (upper triangular back substitution)
-__global__ void k_trisolve(int m, const double* __restrict__ R, const double* __restrict__ g,
-                           double* __restrict__ y, const int32_t* __restrict__ gctl) {
-    if (threadIdx.x != 0) return;
-    const int mm = gctl[1];
-    for (int i = mm - 1; i >= 0; --i) {
-        double t = g[i];
-        for (int k = i + 1; k < mm; ++k) t -= R[(int64_t)i * m + k] * y[k];
-        y[i] = t / R[(int64_t)i * m + i];
-    }
+__global__ __launch_bounds__(PR_WAVE) void k_trisolve(int m, const double* __restrict__ R,
+                                                      const double* __restrict__ g, double* __restrict__ y,
+                                                      const int32_t* __restrict__ gctl) {
+    tri_upper_solve(m, gctl[1], R, g, y);
 }
 
 inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
