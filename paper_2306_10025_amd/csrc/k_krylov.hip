@@ -480,9 +480,9 @@ __global__ __launch_bounds__(kGsThreads) void k_gs(const double* __restrict__ V,
     if (threadIdx.x < nall) {
         double t = 0.0;
         for (int w2 = 0; w2 < kGsThreads / PR_WAVE; ++w2) t += s_red[w2][threadIdx.x];
-        // MODE 2 has one output per block: stored contiguously, so a consumer
-        // reads all block partials from a few cache lines
-        partial[MODE == 2 ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * kMaxVec + threadIdx.x] = t;
+        // output-major (output o of block b at o * gridDim.x + b): a consumer
+        // reads each output's block partials as one contiguous run
+        partial[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
     }
 }
 
@@ -567,8 +567,17 @@ __global__ __launch_bounds__(kGsThreads) void k_gs_upd(const double* __restrict_
     if (threadIdx.x < nv + 2) {
         double t = 0.0;
         for (int w2 = 0; w2 < kGsThreads / PR_WAVE; ++w2) t += s_red[w2][threadIdx.x];
-        partial[(int64_t)blockIdx.x * kOutU + threadIdx.x] = t;
+        partial[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;      // output-major
     }
+}
+
+// x of lane `src` (wave-uniform) in every lane: two v_readlane, no LDS
+// round trip as a shuffle takes
+__device__ __forceinline__ double lane_bcast(double x, int src) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 // Step j of the delayed scheme (j <= 31; j = m with `last` at the end of a
@@ -588,15 +597,6 @@ __global__ __launch_bounds__(kGsThreads) void k_gs_upd(const double* __restrict_
 //   the flexible form's x += Z T^{-1} y.
 // Hu: the unrotated Hessenberg matrix, row-major (m+1) x m; R: its rotated
 // upper triangle.  gctl[1] = final columns of this cycle.
-// x of lane `src` (wave-uniform) in every lane: two v_readlane, no LDS
-// round trip as a shuffle takes
-__device__ __forceinline__ double lane_bcast(double x, int src) {
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
 constexpr int kCoefThreads = 1024;
 __global__ __launch_bounds__(kCoefThreads) void k_dcgs_coef(int j, int m, int last, const double* __restrict__ pd,
                                                             const double* __restrict__ pu, int nblk,
@@ -607,9 +607,9 @@ __global__ __launch_bounds__(kCoefThreads) void k_dcgs_coef(int j, int m, int la
                                                             int32_t* __restrict__ gctl,
                                                             const double* __restrict__ tolp,
                                                             const int64_t* __restrict__ itb, int64_t max_iters) {
-    __shared__ double sa[64], sb[64], col[65], scs[64], ssn[64];
+    __shared__ double sa[64], sb[64], col[65], scs[64], ssn[64], s_ak[64];
     __shared__ double sH[33][32];             // band of H[0..j][0..j-1]
-    __shared__ double s_part[kCoefThreads / PR_WAVE][64];
+    __shared__ double s_part[64][65];         // lane sums per live output (padded rows)
     __shared__ double s_s, s_beta, s_g, s_tol;
     __shared__ int64_t s_itb;
     __shared__ int s_stop;
@@ -624,7 +624,8 @@ __global__ __launch_bounds__(kCoefThreads) void k_dcgs_coef(int j, int m, int la
     if (t == 3) s_itb = *itb;
     {
         const int i = t >> 5, k = t & 31;     // row i, column k of the band
-        if (i <= j && k < j && k + 1 >= i) sH[i][k] = Hu[(int64_t)i * m + k];
+        // zero outside the band, so the product with a below needs no test
+        sH[i][k] = (i <= j && k < j && k + 1 >= i) ? Hu[(int64_t)i * m + k] : 0.0;
     }
     if (t < c) {
         scs[t] = cs[t];
@@ -632,51 +633,63 @@ __global__ __launch_bounds__(kCoefThreads) void k_dcgs_coef(int j, int m, int la
     }
     const int nd = last ? 0 : j + 1;         // dot-pass outputs
     const int nu_out = j > 0 ? j + 1 : 0;     // update-pass outputs
-    // block partials summed with coalesced loads: lane o < 32 takes dot
-    // output o, lane 32 + o update output o; wavefront w adds blocks w,
-    // w + NW, ..., then the NW wavefront sums are added in order
+    // block partials (output-major: a contiguous run of nblk, even, per
+    // output).  Live output q < nd is dot output q, q >= nd update output
+    // q - nd.  Wavefront w takes outputs w, w + NW, w + 2 NW, w + 3 NW; lane l
+    // adds the 16-byte pairs l, l + 64, ... of each (every load in flight at
+    // once), the lane sums go to LDS, and thread q adds its output's 64 lane
+    // sums in lane order: a fixed tree.
     {
-        const bool up = lane >= 32;
-        const int o = up ? lane - 32 : lane;
-        const bool live = up ? o < nu_out : o < nd;
-        const double* P = up ? pu : pd;
-        const int st = up ? kOutU : kMaxVec;
-        // nblk <= 512 = 32 NW: all of a lane's loads in one round (the
-        // partials were just written from every XCD, so each load waits for
-        // the last-level cache)
-        double v[32];
+        static_assert(4 * (kCoefThreads / PR_WAVE) >= 64 && 4 * 2 * PR_WAVE >= 512,
+                      "four outputs per wavefront and four pairs per lane cover 64 outputs of 512 blocks");
+        const int L = nd + nu_out;
+        const int npair = nblk / 2;
+        double2 v[4][4];
 #pragma unroll
-        for (int u = 0; u < 32; ++u) {
-            const int b = wv + NW * u;
-            const bool ok = live && b < nblk;
-            const double x = P[ok ? (int64_t)b * st + o : 0];
-            v[u] = ok ? x : 0.0;
-        }
-        double acc = 0.0;
+        for (int qq = 0; qq < 4; ++qq) {
+            const int q = wv + NW * qq;
+            const double* P = q < nd ? pd + (int64_t)q * nblk : pu + (int64_t)(q - nd) * nblk;
+            const double2* P2 = reinterpret_cast<const double2*>(q < L ? P : pd);
 #pragma unroll
-        for (int u = 0; u < 32; ++u) acc += v[u];
-        s_part[wv][lane] = acc;
-    }
-    __syncthreads();
-    if (t < 64) {
-        double acc = 0.0;
-        for (int w2 = 0; w2 < NW; ++w2) acc += s_part[w2][t];
-        const bool up = t >= 32;
-        const int o = up ? t - 32 : t;
-        if (!up && o < nd) {
-            if (o < j) sb[o] = acc; else s_beta = acc;
+            for (int u = 0; u < 4; ++u) {
+                const int k = lane + PR_WAVE * u;
+                const bool ok = q < L && k < npair;
+                const double2 x = P2[ok ? k : 0];
+                v[qq][u].x = ok ? x.x : 0.0;
+                v[qq][u].y = ok ? x.y : 0.0;
+            }
         }
-        if (up && o < nu_out) {
-            if (o < j) sa[o] = acc; else s_s = acc;
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            const int q = wv + NW * qq;
+            double acc = 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc += v[qq][u].x + v[qq][u].y;
+            if (q < L) s_part[q][lane] = acc;
+        }
+        __syncthreads();
+        if (t < L) {
+            double acc = 0.0;
+            for (int l = 0; l < PR_WAVE; ++l) acc += s_part[t][l];
+            if (t < nd) {
+                if (t < j) sb[t] = acc; else s_beta = acc;
+            } else {
+                const int o = t - nd;
+                if (o < j) sa[o] = acc; else s_s = acc;
+            }
         }
     }
     __syncthreads();
     if (s_stop || wv != 0) return;
-    // the rest by one wavefront, lane i holding row i (j <= 31)
+    // the rest by one wavefront, lane i holding row i (j <= 31).  Every
+    // global store comes at the end: a store still reading its registers
+    // would make the loops below wait for all memory operations.
     const int i = lane;
     double sc = 1.0, nu = 1.0;
     double ai = 0.0, bi = 0.0;
     double beta = last ? 0.0 : s_beta;        // beta' / s^2 (s = 1 at j = 0)
+    bool stop = false;
+    double hcol = 0.0, rcol = 0.0, cc = 1.0, ss = 0.0, gj = 0.0;
     if (j > 0) {
         sc = sqrt(fmax(s_s, 0.0));
         const double isc = sc > 0.0 ? 1.0 / sc : 0.0;
@@ -691,26 +704,59 @@ __global__ __launch_bounds__(kCoefThreads) void k_dcgs_coef(int j, int m, int la
         double cl = 0.0;
         if (i < j) cl = sH[i][c] + sc * ai;
         if (i == j) cl = sc * nu;
+        hcol = cl;
         if (i <= j) {
             sH[i][c] = cl;
-            Hu[(int64_t)i * m + c] = cl;
+            col[i] = cl;
         }
-        // lane r holds rotation r; every broadcast below reads a uniform lane
-        const double mcs = i < c ? scs[i] : 1.0, msn = i < c ? ssn[i] : 0.0;
-        for (int r = 0; r < c; ++r) {
-            const double x0 = lane_bcast(cl, r), x1 = lane_bcast(cl, r + 1);
-            const double cr = lane_bcast(mcs, r), sr = lane_bcast(msn, r);
-            if (i == r) cl = cr * x0 + sr * x1;
-            if (i == r + 1) cl = -sr * x0 + cr * x1;
+        // the earlier rotations, in order, by one lane: rotation r maps the
+        // pair (x_r, x_{r+1}) with x_r already rotated by rotation r - 1, so
+        // only that carried value is a dependency; the column is read from
+        // LDS ahead of it
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");    // one wavefront: LDS in order
+        __builtin_amdgcn_wave_barrier();
+        if (i == 0) {
+            double carry = col[0];
+#pragma unroll 4
+            for (int r = 0; r < c; ++r) {
+                const double x1 = col[r + 1], cr = scs[r], sr = ssn[r];
+                col[r] = cr * carry + sr * x1;
+                carry = -sr * carry + cr * x1;
+            }
+            col[c] = carry;
         }
-        const double a0 = lane_bcast(cl, c), hn = lane_bcast(cl, j);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const double a0 = col[c], hn = lane_bcast(cl, j);
         const double den = hypot(a0, hn);
-        const double cc = den > 0.0 ? a0 / den : 1.0;
-        const double ss = den > 0.0 ? hn / den : 0.0;
-        if (i == c) cl = den;
-        if (i <= c) R[(int64_t)i * m + c] = cl;
-        const double gj = -ss * s_g;
-        bool stop = !(fabs(gj) > s_tol) || s_itb + j >= max_iters || j >= m || !(nu > 0.0);
+        cc = den > 0.0 ? a0 / den : 1.0;
+        ss = den > 0.0 ? hn / den : 0.0;
+        rcol = i < c ? col[i] : den;
+        gj = -ss * s_g;
+        stop = !(fabs(gj) > s_tol) || s_itb + j >= max_iters || j >= m || !(nu > 0.0);
+    }
+    // provisional column j and the update coefficients: lane i forms
+    // gv_i = sum_k H[i][k] a_k over the Hessenberg band (H[i][k] = 0 for
+    // i > k + 1, stored as zeros)
+    double hq = 0.0, cq = 0.0;
+    const double inu = 1.0 / nu;
+    if (!stop && !last) {
+        const double ab = wave_sum(ai * bi);
+        double gvt = 0.0;
+        // a from LDS (a loop with lane reads is not unrolled, its loads
+        // would wait one by one)
+        s_ak[i] = ai;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const int ir = i <= j ? i : 0;        // rows past j: any row, result unused
+#pragma unroll 4
+        for (int k = 0; k < j; ++k) gvt += sH[ir][k] * s_ak[k];
+        hq = i < j ? (bi - gvt) * inu : ((beta - ab) * inu - gvt) * inu;
+        cq = gvt + nu * hq;
+    }
+    if (j > 0) {
+        if (i <= j) Hu[(int64_t)i * m + c] = hcol;
+        if (i <= c) R[(int64_t)i * m + c] = rcol;
         if (i == 0) {
             cs[c] = cc;
             sn[c] = ss;
@@ -721,31 +767,16 @@ __global__ __launch_bounds__(kCoefThreads) void k_dcgs_coef(int j, int m, int la
             est[0] = fabs(gj);
             if (stop) gctl[0] = 1;
         }
-        if (stop) return;
-    } else {
-        bi = 0.0;
     }
-    if (last) return;
-    // provisional column j and the update coefficients: lane i forms
-    // gv_i = sum_k H[i][k] a_k over the Hessenberg band (H[i][k] = 0 for
-    // i > k + 1), a_k broadcast from lane k
-    const double ab = wave_sum(ai * bi);
-    const double inu = 1.0 / nu;
-    double gvt = 0.0;
-    for (int k = 0; k < j; ++k) {
-        const double ak = lane_bcast(ai, k);
-        if (i <= j && k + 1 >= i) gvt += sH[i][k] * ak;
-    }
+    if (stop || last) return;
     if (i < j) {
-        const double hq = (bi - gvt) * inu;
         Hu[(int64_t)i * m + j] = hq;
         coef[i] = ai;
-        coef[64 + i] = gvt + nu * hq;
+        coef[64 + i] = cq;
         T[(int64_t)i * m + j] = sc * ai;
     } else if (i == j) {
-        const double hv = ((beta - ab) * inu - gvt) * inu;
-        Hu[(int64_t)j * m + j] = hv;
-        coef[64 + j] = gvt + nu * hv;
+        Hu[(int64_t)j * m + j] = hq;
+        coef[64 + j] = cq;
         coef[130] = inu;
         coef[131] = 1.0 / sc;
         T[(int64_t)j * m + j] = sc * nu;
@@ -781,7 +812,7 @@ __global__ __launch_bounds__(PR_WAVE) void k_trisolve_T(int m, const double* __r
     tri_upper_solve(m, gctl[1], T, y, y);
 }
 
-// out[i] = sum over blocks of partial[b][i]; one block per output (a fixed
+// out[i] = sum over blocks of partial[i][b]; one block per output (a fixed
 // tree).  (A last-block-reduces variant inside k_gs needs a device-scope
 // release per block, an L2 write-back on this GPU; it measured twice as
 // slow as this separate launch.)
@@ -792,7 +823,7 @@ __global__ __launch_bounds__(256) void k_gs_final(const double* __restrict__ par
     __shared__ double s_w[256 / PR_WAVE];
     const int i = blockIdx.x;
     double t = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 256) t += partial[(int64_t)b * kMaxVec + i];
+    for (int b = threadIdx.x; b < nblk; b += 256) t += partial[(int64_t)i * nblk + b];
     t = wave_sum(t);
     if ((threadIdx.x & (PR_WAVE - 1)) == 0) s_w[threadIdx.x / PR_WAVE] = t;
     __syncthreads();
@@ -1007,7 +1038,8 @@ int gs_blocks(int64_t n) {
     int64_t b = (n + 1023) / 1024;        // several rows per thread: the loads of
     if (b > 512) b = 512;                 // consecutive rows overlap (measured best)
     if (b < 1) b = 1;
-    return (int)b;
+    return (int)(b + (b & 1));            // even: each output's run of block partials
+                                          // is read in 16-byte pairs
 }
 
 // mode 0: out = V^T w ; mode 1: w -= V c, out = V^T w ; mode 2: w -= V c and

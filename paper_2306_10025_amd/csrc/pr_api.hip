@@ -729,7 +729,7 @@ int ensure_workspace(pr_handle h, int m) {
     PR_TRY(dalloc(h, &h->w, n));
     PR_TRY(dalloc(h, &h->t1, n));
     PR_TRY(dalloc(h, &h->t2, 3 * n));   // preconditioned vector, sweep residual, scratch
-    PR_TRY(dalloc(h, &h->red, (size_t)gs_blocks(n) * 72 + 64));   // up to 66 partials per block
+    PR_TRY(dalloc(h, &h->red, (size_t)gs_blocks(n) * 72 + 64));   // up to 33 + 33 partials per block
     PR_TRY(dalloc(h, &h->gm, 16384));
     PR_TRY(dalloc(h, &h->gctl, 4));
     PR_TRY(dalloc(h, &h->hd, 256));
@@ -1609,8 +1609,8 @@ int pr_solve(pr_handle h, const double* b, double* x, double tol) {
     double* Tm = Hu + (int64_t)(m + 1) * m;
     double* coef = Tm + (int64_t)m * m;
     const bool delayed = h->prm.orth == 0 && m <= 31;
-    double* red_dot = red;                                    // dot-pass partials, stride 32
-    double* red_upd = red + (int64_t)gs_blocks(n) * 32;       // update-pass partials, stride 34
+    double* red_dot = red;                                    // dot-pass partials, output-major
+    double* red_upd = red + (int64_t)gs_blocks(n) * 33;       // update-pass partials, output-major
     int32_t* gctl = h->gctl;
     int32_t* gctl_h = reinterpret_cast<int32_t*>(hh + 240);   // pinned mirror of gctl
     int64_t* itb_h = reinterpret_cast<int64_t*>(hh + 236);
