@@ -209,11 +209,16 @@ def algorithmic_bytes(P, m_p, precision, n_items, n_p_entries, st=None):
     return apply, spmv
 
 
-def orth_bytes(n, m=30):
+def orth_bytes(n, m=30, form="delayed"):
     """Average HBM bytes of the Gram-Schmidt work of one Arnoldi step over a
-    GMRES(m) cycle: three passes over the j+1 basis vectors (two reads, one
-    read plus the update), reads and writes of w, the new basis vector."""
+    GMRES(m) cycle (j = 0 .. m-1).  Delayed reorthogonalisation: the dot pass
+    reads the j+1 vectors [Q, u] and w, the update pass reads the j vectors
+    of Q, u and w and writes v_j and the next vector (2j + 6 vectors).
+    Selective: three passes over the j+1 basis vectors (two reads, one read
+    plus the update), reads and writes of w, the new basis vector."""
     j_avg = (m - 1) / 2.0
+    if form == "delayed":
+        return 8 * n * (2 * j_avg + 6)
     return 8 * n * (3 * (j_avg + 1) + 2 * 3 + 2)
 
 
@@ -618,7 +623,7 @@ def launches_per_solve(info):
             "orth": info["iters"]}
 
 
-def summarize_classes(P, rec, precision, m_p, n_items):
+def summarize_classes(P, rec, precision, m_p, n_items, orth="delayed"):
     """Average duration of one launch of each kernel class, from the events
     recorded inside the timed steps (a sample of the Arnoldi steps), and the
     device time per step it implies."""
@@ -638,7 +643,7 @@ def summarize_classes(P, rec, precision, m_p, n_items):
                       timed_launches=cnt / steps, avg_us=avg_us)
     res["apply"]["bytes"] = apply_b
     res["spmv"]["bytes"] = spmv_b
-    res["orth"]["bytes"] = orth_bytes(P.n)
+    res["orth"]["bytes"] = orth_bytes(P.n, form=orth)
     return res
 
 
@@ -827,7 +832,7 @@ def main():
     m_p, n_items = st["m_p"], st["n_items"]
     applies = np.mean([launches_per_solve(i)["apply"] for i, _ in g["rec"]])
     value = P.n * applies / g["sec"] / 1e9
-    cls = summarize_classes(P, g["rec"], args.precision, m_p, n_items)
+    cls = summarize_classes(P, g["rec"], args.precision, m_p, n_items, args.orth)
     dom = max(("apply", "spmv", "orth"), key=lambda k: cls[k]["total_ms"])
     traffic = traffic_from_profile() if (wname == "nedelec_hex_64" and args.precision == "bf16x3"
                                          and args.scatter == "two-stage") else None
@@ -901,7 +906,7 @@ def main():
                                          "xcd_remap": st["tune_xcd_remap"]}
     if "rec_full" in g:
         fi, fs = g["rec_full"][-1]
-        fcls = summarize_classes(P, g["rec_full"], "fp64", P.n_p, fs["n_items"])
+        fcls = summarize_classes(P, g["rec_full"], "fp64", P.n_p, fs["n_items"], args.orth)
         f_applies = np.mean([launches_per_solve(i)["apply"] for i, _ in g["rec_full"]])
         line["full_fp64"] = {
             "ms_per_step": round(g["sec_full"] * 1000.0, 3),
