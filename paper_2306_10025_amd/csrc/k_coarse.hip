@@ -520,13 +520,19 @@ __global__ void k_dense_from_csr(int64_t n0, int64_t np, const int64_t* __restri
 
 // ---- blocked Gauss-Jordan inverse in place (s multiple of 32) ----------------
 // Inverse of the 32 x 32 row-major matrix in sP into sI by Gauss-Jordan
-// elimination with partial pivoting, one wavefront: lane c holds column c of
-// the augmented matrix [P | I] (rows 0..31) in registers.  Step k: lane k
-// picks the pivot row (largest |a_rk| over the rows not yet used, lowest row
-// on ties); every lane scales its pivot-row element, and the factors (column
-// k, held by lane k) reach every lane by readlane, so no step touches LDS.
-// Row piv_k of the right half ends as row k of the inverse.  Returns nonzero
-// on a zero pivot.
+// elimination with partial pivoting, one wavefront holding the augmented
+// matrix [P | I] by rows: lane r < 32 holds row r of P, lane 32 + r row r of
+// the identity half, 32 doubles each.  Step k: the pivot is the largest
+// |a_rk| over the rows not yet used (lowest row on ties), found by a DPP
+// max within rows of 16 lanes and a ballot of the lanes holding it; the
+// pivot row goes through LDS (sRow, 64 doubles) to every lane, and each lane
+// updates its row with its factor a_rk: a_rc -= a_rk (p_c / p_k), the pivot
+// row itself becoming p_c / p_k.  Row piv_k of the right half ends as row k
+// of the inverse.  The step loop is unrolled, so no register is indexed at
+// run time.  (Lane c holding column c instead made the pivot search a
+// 32-step chain in one lane's registers and every row update a select by
+// the pivot index: 1.5 us per step, 50 us per inverse.)  Returns nonzero on
+// a zero pivot.
 __device__ __forceinline__ double bcast(double v, int src) {
     const int2 t = *reinterpret_cast<const int2*>(&v);
     int2 r;
@@ -535,46 +541,63 @@ __device__ __forceinline__ double bcast(double v, int src) {
     return *reinterpret_cast<const double*>(&r);
 }
 
-__device__ int reg_gj32(const double* sP, double* sI, int* srow, int lane) {
+// v of the lane `n` below in the same row of 16 (own value past the row's
+// start): DPP row_shr:n on both halves
+template <int N>
+__device__ __forceinline__ double dpp_row_shr(double v) {
+    static_assert(N == 1 || N == 2 || N == 4 || N == 8, "row_shr by 1, 2, 4 or 8");
+    const int2 t = *reinterpret_cast<const int2*>(&v);
+    int2 r;
+    r.x = __builtin_amdgcn_update_dpp(t.x, t.x, 0x110 + N, 0xf, 0xf, false);
+    r.y = __builtin_amdgcn_update_dpp(t.y, t.y, 0x110 + N, 0xf, 0xf, false);
+    return *reinterpret_cast<const double*>(&r);
+}
+
+__device__ int reg_gj32(const double* sP, double* sI, int* srow, double* sRow, int lane) {
+    const int h = lane >> 5, r = lane & 31;
     double a[32];
 #pragma unroll
-    for (int r = 0; r < 32; ++r)
-        a[r] = lane < 32 ? sP[r * 32 + lane] : ((r == lane - 32) ? 1.0 : 0.0);
-    uint32_t used = 0;
+    for (int c = 0; c < 32; ++c) a[c] = h == 0 ? sP[r * 32 + c] : (c == r ? 1.0 : 0.0);
+    bool used = false;
     int bad = 0;
-#pragma unroll 1
+#pragma unroll
     for (int k = 0; k < 32; ++k) {
-        // pivot search in lane k's registers (other lanes compute alongside)
-        double best = -1.0;
-        int bi = 0;
-#pragma unroll
-        for (int r = 0; r < 32; ++r) {
-            const double v = fabs(a[r]);
-            if (!((used >> r) & 1u) && v > best) {
-                best = v;
-                bi = r;
-            }
-        }
-        const int piv = __builtin_amdgcn_readlane(bi, k);
-        best = bcast(best, k);
+        // pivot: largest |a_rk| over the unused rows (lanes 0..31)
+        const double ak = a[k];
+        const double mag = fabs(ak);
+        const double v = (h == 0 && !used && mag >= 0.0) ? mag : -1.0;    // NaN never pivots
+        double m = fmax(v, dpp_row_shr<1>(v));
+        m = fmax(m, dpp_row_shr<2>(m));
+        m = fmax(m, dpp_row_shr<4>(m));
+        m = fmax(m, dpp_row_shr<8>(m));
+        const double best = fmax(bcast(m, 15), bcast(m, 31));
+        const uint64_t hold = __ballot(h == 0 && !used && v == best);
+        const int piv = (int)__builtin_ctzll(hold);
         if (!(best > 0.0)) bad = 1;
-        used |= 1u << piv;
+        if (r == piv) used = true;
         if (lane == 0) srow[piv] = k;
-        double pv = 0.0;
+        // factor of this lane's row: a_rk, held by lane r
+        const double f = __shfl(ak, r);
+        // the pivot row (both halves) to every lane
+        if (r == piv) {
 #pragma unroll
-        for (int r = 0; r < 32; ++r) pv = (r == piv) ? a[r] : pv;
-        const double inv = 1.0 / bcast(pv, k);
-        pv *= inv;
-#pragma unroll
-        for (int r = 0; r < 32; ++r) {
-            const double f = bcast(a[r], k);
-            a[r] = (r == piv) ? pv : fma(-f, pv, a[r]);
+            for (int c = 0; c < 32; ++c) sRow[h * 32 + c] = a[c];
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");    // one wavefront: LDS in order
+        __builtin_amdgcn_wave_barrier();
+        const double inv = 1.0 / sRow[k];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) {
+            const double pv = sRow[h * 32 + c] * inv;
+            a[c] = (r == piv) ? pv : fma(-f, pv, a[c]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    if (lane >= 32) {
+    if (h == 1) {
 #pragma unroll
-        for (int r = 0; r < 32; ++r) sI[srow[r] * 32 + (lane - 32)] = a[r];
+        for (int c = 0; c < 32; ++c) sI[srow[r] * 32 + c] = a[c];
     }
     __syncthreads();
     return bad;
@@ -589,12 +612,13 @@ __global__ __launch_bounds__(64) void k_gj_panel(double* __restrict__ M, int s, 
     __shared__ double sI[32 * 32];
     __shared__ double sT[32 * 32];
     __shared__ int srow[32];
+    __shared__ double sRow[64];
     const int lane = threadIdx.x;
     const int j = blockIdx.x;
     const int64_t ks = (int64_t)k * 32;
     for (int e = lane; e < 1024; e += PR_WAVE) sP[e] = M[(ks + e / 32) * s + ks + e % 32];
     __syncthreads();
-    const int bad = reg_gj32(sP, sI, srow, lane);
+    const int bad = reg_gj32(sP, sI, srow, sRow, lane);
     if (bad && lane == 0) atomicOr(info, 1);
     if (j == k) {
         for (int e = lane; e < 1024; e += PR_WAVE) Pinv[e] = sI[e];
