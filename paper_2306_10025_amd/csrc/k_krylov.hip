@@ -156,9 +156,12 @@ __global__ __launch_bounds__(kPlanThreads) void k_sell_plan(const int64_t* __res
             }
         }
         if (t < ndiag) dtmp[sl * kMaxDiag + t] = lst[t];
+        // an odd count gets a padding diagonal (the last offset again, zero
+        // values): the values are stored in pairs of diagonals
+        if (fmt == 1 && (ndiag & 1) && t == ndiag) dtmp[sl * kMaxDiag + t] = lst[ndiag - 1];
     }
     if (t == 0) {
-        slen[sl] = fmt == 2 ? 0 : 64 * (int64_t)(fmt ? ndiag : mlen);
+        slen[sl] = fmt == 2 ? 0 : 64 * (int64_t)(fmt ? ndiag + (ndiag & 1) : mlen);
         sfmt[sl] = fmt;
         cnnz[sl] = fmt == 0 ? s_nnz : (fmt == 2 ? -s_nnz : 0);   // form 2: its entries, negated
     }
@@ -240,7 +243,9 @@ __global__ void k_sell_fill(const int64_t* __restrict__ rowptr, const int32_t* _
 
 // Diagonal-form slices: one block per slice.  Every stored value is first
 // set to 0; after the barrier each entry (four lanes per row) finds its
-// offset's column by binary search and writes its value.
+// offset's column by binary search and writes its value.  Values are stored
+// in pairs of diagonals: diagonal k of row i at (k / 2) * 128 + 2 i + k % 2,
+// so one 16-byte load gives a row its values on two diagonals.
 __global__ __launch_bounds__(kPlanThreads) void k_sell_fill_diag(const int64_t* __restrict__ rowptr,
                                                                  const int32_t* __restrict__ col,
                                                                  const double* __restrict__ val, int64_t n,
@@ -275,7 +280,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_sell_fill_diag(const int64_t* 
             if (s_d[mid] < d) lo = mid + 1;
             else hi = mid;
         }
-        sval[off + (int64_t)lo * 64 + i] = val[a + k];
+        sval[off + (int64_t)(lo >> 1) * 128 + 2 * i + (lo & 1)] = val[a + k];
     }
 }
 
@@ -347,30 +352,40 @@ __global__ __launch_bounds__(256) void k_spmv_sell(SellMat M, int64_t n, const d
         __builtin_amdgcn_wave_barrier();
         acc0 = s_row[wbase + lane];
     } else if (fmt == 1) {
-        // diagonal form: neither the values nor the gathers depend on earlier
-        // loads, so kSpmvChunk of each are issued together, and the entries
-        // alternate between the two accumulators by column parity.  Past the
-        // slice's last column the offsets read are whatever follows (the
+        // diagonal form, values in pairs of diagonals (an odd count padded
+        // with a zero diagonal): one 16-byte load per pair.  Neither the
+        // values nor the gathers depend on earlier loads, so kSpmvChunk
+        // diagonals' worth of each are issued together, and the entries
+        // alternate between the two accumulators by column parity.  Past
+        // the slice's last column the offsets read are whatever follows (the
         // offset array is padded by kSellOffsetPad), the column is clamped
-        // into range, the value index to the last column, and the product
-        // is dropped.  (Taking the slice's offsets in one vector load and
-        // each step's by readlane measured the same, 60.5 against 60.2 us
-        // on the Nedelec 64^3 matrix: other wavefronts hide the scalar loads.)
+        // into range, the pair index to the last pair, and the product is
+        // dropped.  (Taking the slice's offsets in one vector load and each
+        // step's by readlane measured the same, 60.5 against 60.2 us on the
+        // Nedelec 64^3 matrix: other wavefronts hide the scalar loads.)
+        typedef double dpair __attribute__((ext_vector_type(2)));
+        static_assert(kSpmvChunk % 2 == 0, "whole pairs per step");
+        const dpair* vq = reinterpret_cast<const dpair*>(M.sval + off) + lane;
         const int32_t* dp = M.sdoff + off / 64;
+        const int npair = len / 2;
         for (int k0 = 0; k0 < len; k0 += kSpmvChunk) {
-            double v[kSpmvChunk], xv[kSpmvChunk];
+            dpair v[kSpmvChunk / 2];
+            double xv[kSpmvChunk];
+#pragma unroll
+            for (int u = 0; u < kSpmvChunk / 2; ++u) {
+                const int q = k0 / 2 + u < npair ? k0 / 2 + u : npair - 1;
+                v[u] = __builtin_nontemporal_load(vq + (int64_t)q * 64);
+            }
 #pragma unroll
             for (int u = 0; u < kSpmvChunk; ++u) {
-                const int k = k0 + u < len ? k0 + u : len - 1;
                 const int64_t c = r + dp[k0 + u];
-                v[u] = __builtin_nontemporal_load(vp + (int64_t)k * 64);
                 xv[u] = x[(uint64_t)c < (uint64_t)n ? c : r];
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int u = 0; u < kSpmvChunk; u += 2) {
-                if (k0 + u < len) acc0 = fma(v[u], xv[u], acc0);
-                if (k0 + u + 1 < len) acc1 = fma(v[u + 1], xv[u + 1], acc1);
+            for (int u = 0; u < kSpmvChunk / 2; ++u) {
+                if (k0 + 2 * u < len) acc0 = fma(v[u].x, xv[2 * u], acc0);
+                if (k0 + 2 * u + 1 < len) acc1 = fma(v[u].y, xv[2 * u + 1], acc1);
             }
         }
     } else {
