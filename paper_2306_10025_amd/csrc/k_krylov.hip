@@ -287,6 +287,54 @@ __global__ __launch_bounds__(kPlanThreads) void k_sell_fill_diag(const int64_t* 
 constexpr int kSpmvChunk = 8;   // diagonal-form entries per step (even)
 static_assert(kSpmvChunk <= kSellOffsetPad, "the offset array's padding covers one step");
 
+typedef double dpair __attribute__((ext_vector_type(2)));
+
+// One step of the diagonal form: kSpmvChunk diagonals from k0 (kSpmvChunk / 2
+// pairs).  Bit u of ADJ says that pair u's offsets are adjacent (d1 = d0 + 1),
+// so one 16-byte gather brings x[c0] and x[c0 + 1]: its address is clamped
+// into [0, n - 2], and at the matrix's ends the shift picks the element (a
+// column outside the matrix has a zero value).  Every load of the step is
+// issued before the first product; ADJ is a template argument so that the
+// step has no branch between its loads (a branch per pair made the compiler
+// wait for each pair's gathers at the join).
+template <int ADJ>
+__device__ __forceinline__ void spmv_diag_step(const dpair* __restrict__ vq, const int32_t* __restrict__ dp,
+                                               const double* __restrict__ x, int64_t n, int64_t r, int k0,
+                                               int len, double& acc0, double& acc1) {
+    constexpr int NP = kSpmvChunk / 2;
+    const int npair = len / 2;
+    dpair v[NP];
+    double xv[kSpmvChunk];
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+        const int q = k0 / 2 + u < npair ? k0 / 2 + u : npair - 1;
+        v[u] = __builtin_nontemporal_load(vq + (int64_t)q * 64);
+    }
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+        const int32_t d0 = dp[k0 + 2 * u], d1 = dp[k0 + 2 * u + 1];
+        const int64_t c0 = r + d0;
+        if (((ADJ >> u) & 1) != 0) {      // folded: the loop is unrolled
+            const int64_t cp = c0 < 0 ? 0 : (c0 > n - 2 ? n - 2 : c0);
+            dpair x2;
+            __builtin_memcpy(&x2, x + cp, sizeof(x2));
+            const int64_t sh = c0 - cp;
+            xv[2 * u] = sh == 1 ? x2.y : x2.x;
+            xv[2 * u + 1] = sh == -1 ? x2.x : x2.y;
+        } else {
+            const int64_t c1 = r + d1;
+            xv[2 * u] = x[(uint64_t)c0 < (uint64_t)n ? c0 : r];
+            xv[2 * u + 1] = x[(uint64_t)c1 < (uint64_t)n ? c1 : r];
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+        if (k0 + 2 * u < len) acc0 = fma(v[u].x, xv[2 * u], acc0);
+        if (k0 + 2 * u + 1 < len) acc1 = fma(v[u].y, xv[2 * u + 1], acc1);
+    }
+}
+
 // y = A x (b == nullptr) or y = b - A x; one thread per row, 64-row slices.
 // The matrix values are read once per product: in the diagonal and column
 // forms non-temporal loads keep them from displacing what the solve reads
@@ -363,29 +411,19 @@ __global__ __launch_bounds__(256) void k_spmv_sell(SellMat M, int64_t n, const d
         // dropped.  (Taking the slice's offsets in one vector load and each
         // step's by readlane measured the same, 60.5 against 60.2 us on the
         // Nedelec 64^3 matrix: other wavefronts hide the scalar loads.)
-        typedef double dpair __attribute__((ext_vector_type(2)));
-        static_assert(kSpmvChunk % 2 == 0, "whole pairs per step");
+        static_assert(kSpmvChunk == 8, "four pairs per step: sixteen adjacency patterns");
         const dpair* vq = reinterpret_cast<const dpair*>(M.sval + off) + lane;
         const int32_t* dp = M.sdoff + off / 64;
-        const int npair = len / 2;
         for (int k0 = 0; k0 < len; k0 += kSpmvChunk) {
-            dpair v[kSpmvChunk / 2];
-            double xv[kSpmvChunk];
+            int adj = 0;
 #pragma unroll
-            for (int u = 0; u < kSpmvChunk / 2; ++u) {
-                const int q = k0 / 2 + u < npair ? k0 / 2 + u : npair - 1;
-                v[u] = __builtin_nontemporal_load(vq + (int64_t)q * 64);
-            }
-#pragma unroll
-            for (int u = 0; u < kSpmvChunk; ++u) {
-                const int64_t c = r + dp[k0 + u];
-                xv[u] = x[(uint64_t)c < (uint64_t)n ? c : r];
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int u = 0; u < kSpmvChunk / 2; ++u) {
-                if (k0 + 2 * u < len) acc0 = fma(v[u].x, xv[2 * u], acc0);
-                if (k0 + 2 * u + 1 < len) acc1 = fma(v[u].y, xv[2 * u + 1], acc1);
+            for (int u = 0; u < kSpmvChunk / 2; ++u)
+                adj |= (dp[k0 + 2 * u + 1] == dp[k0 + 2 * u] + 1 && n >= 2) ? (1 << u) : 0;
+            switch (adj) {
+#define PR_DIAG(A) case A: spmv_diag_step<A>(vq, dp, x, n, r, k0, len, acc0, acc1); break;
+                PR_DIAG(0) PR_DIAG(1) PR_DIAG(2) PR_DIAG(3) PR_DIAG(4) PR_DIAG(5) PR_DIAG(6) PR_DIAG(7)
+                PR_DIAG(8) PR_DIAG(9) PR_DIAG(10) PR_DIAG(11) PR_DIAG(12) PR_DIAG(13) PR_DIAG(14) PR_DIAG(15)
+#undef PR_DIAG
             }
         }
     } else {
