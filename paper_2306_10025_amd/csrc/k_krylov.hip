@@ -362,10 +362,14 @@ __global__ __launch_bounds__(256) void k_spmv_sell(SellMat M, int64_t n, const d
     const double* vp = M.sval + off + lane;
     double acc0 = 0.0, acc1 = 0.0;
     if (fmt == 2) {
-        // rows from the CSR copy: lane group q (16 lanes) takes rows q, q + 4,
-        // ...; each row's entries at unit stride, eight loads of values and
-        // columns in flight per lane, a 16-lane sum; the 64 row sums return
-        // to their lanes through LDS
+        // rows from the CSR copy: lane group g (16 lanes) takes rows g, g + 4,
+        // ...; lane t of a group takes the entry pairs a + 2 t + 32 u (u < 4)
+        // of each 128-entry step, one 16-byte value load and one 8-byte
+        // column load per pair (the copy is padded by kCsrPad zero entries, so
+        // a pair that starts at the row's end, or is clamped there, stays
+        // inside it), eight gathers of x in flight, a 16-lane sum; the 64 row
+        // sums return to their lanes through LDS.  (One entry per load made
+        // the address units the limit.)
         __shared__ double s_row[256];
         const int wbase = (int)(threadIdx.x & ~(PR_WAVE - 1));
         const int grp = lane >> 4, sub = lane & 15;
@@ -375,22 +379,30 @@ __global__ __launch_bounds__(256) void k_spmv_sell(SellMat M, int64_t n, const d
             double sacc = 0.0;
             if (row < n) {
                 const int64_t a = M.rowptr[row], e = M.rowptr[row + 1];
-                for (int64_t q0 = a + sub; q0 < e; q0 += 128) {
-                    double v[8];
+                for (int64_t q0 = a + 2 * sub; q0 < e; q0 += 128) {
+                    dpair v[4];
                     int32_t cc[8];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int64_t q = q0 + 16 * u;
-                        const bool ok = q < e;
-                        v[u] = M.val[ok ? q : a];
-                        cc[u] = M.col[ok ? q : a];
-                        v[u] = ok ? v[u] : 0.0;
+                    for (int u = 0; u < 4; ++u) {
+                        const int64_t q = q0 + 32 * u;
+                        const int64_t qc = q < e ? q : e;
+                        dpair vv;
+                        int2 c2;
+                        __builtin_memcpy(&vv, M.val + qc, sizeof(vv));
+                        __builtin_memcpy(&c2, M.col + qc, sizeof(c2));
+                        v[u].x = q < e ? vv.x : 0.0;
+                        v[u].y = q + 1 < e ? vv.y : 0.0;
+                        cc[2 * u] = c2.x;
+                        cc[2 * u + 1] = c2.y;
                     }
                     double xv[8];
 #pragma unroll
                     for (int u = 0; u < 8; ++u) xv[u] = x[cc[u]];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) sacc = fma(v[u], xv[u], sacc);
+                    for (int u = 0; u < 4; ++u) {
+                        sacc = fma(v[u].x, xv[2 * u], sacc);
+                        sacc = fma(v[u].y, xv[2 * u + 1], sacc);
+                    }
                 }
             }
             for (int o = 8; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, 16);

@@ -1320,8 +1320,8 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
     }
     h->total_dofs = total;
     SETUP_TRY(dalloc(h, &h->rowptr, h->n + 1));
-    SETUP_TRY(dalloc(h, &h->col, h->nnz));
-    SETUP_TRY(dalloc(h, &h->val, h->nnz));
+    SETUP_TRY(dalloc(h, &h->col, h->nnz + kCsrPad));     // padded: the SpMV reads entries in pairs
+    SETUP_TRY(dalloc(h, &h->val, h->nnz + kCsrPad));
     SETUP_TRY(dalloc(h, &h->pptr, h->n_p + 1));
     SETUP_TRY(dalloc(h, &h->pdofs, total));
     SETUP_HIP(hipMemcpyAsync(h->rowptr, A->row_ptr, (h->n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
@@ -1329,6 +1329,8 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
         SETUP_HIP(hipMemcpyAsync(h->col, A->col, h->nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
         SETUP_HIP(hipMemcpyAsync(h->val, A->val, h->nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
+    SETUP_HIP(hipMemsetAsync(h->col + h->nnz, 0, kCsrPad * sizeof(int32_t), s));
+    SETUP_HIP(hipMemsetAsync(h->val + h->nnz, 0, kCsrPad * sizeof(double), s));
     SETUP_HIP(hipMemcpyAsync(h->pptr, P->ptr, (h->n_p + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
     SETUP_HIP(hipMemcpyAsync(h->pdofs, P->dofs, total * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
 

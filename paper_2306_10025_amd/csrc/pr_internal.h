@@ -74,6 +74,7 @@ struct SellMat {
 };
 constexpr int kSellMaxDiag = 192;   // distinct offsets a diagonal-form slice may hold
 constexpr int kSellOffsetPad = 16;  // entries allocated past the last slice's offsets
+constexpr int kCsrPad = 2;          // zero entries (column 0, value 0) past the CSR copy's last
 
 struct DevBuf {
     void* p = nullptr;
