@@ -750,6 +750,70 @@ def _sell_forms(A):
     return np.array(forms)
 
 
+def _mixed_length_matrix(seed=11):
+    """Strictly diagonally dominant matrix: first banded rows with the five
+    offsets -2 .. 2 (diagonal-form slices with an odd offset count, pairs
+    with and without adjacent offsets), then rows whose 64-row slices mix
+    very short and very long rows (read from the CSR copy), with rows of one
+    entry, a ragged last slice and a long last row that ends at the last
+    stored entry."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    n_band, n_csr = 64 * 2 + 7, 64 * 3 + 21
+    n = n_band + n_csr
+    rows, cols = [], []
+    for i in range(n_band):
+        for d in (-2, -1, 1, 2):
+            if 0 <= i + d < n_band:
+                rows.append(i)
+                cols.append(i + d)
+    for i in range(n_band, n):
+        if i == n - 1:
+            k = 170
+        elif i % 9 == 0:
+            k = 0                                # only the diagonal
+        else:
+            k = 150 if i % 2 else 2
+        c = n_band + rng.choice(n_csr, size=k, replace=False)
+        c = c[c != i]
+        rows += [i] * len(c)
+        cols += c.tolist()
+    vals = rng.uniform(-1.0, 1.0, len(rows))
+    off = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    d = np.asarray(abs(off).sum(axis=1)).ravel() + 1.0
+    A = (off + sp.diags(d)).tocsr()
+    A.sort_indices()
+    ptr = np.arange(0, n + 1, 4, dtype=np.int64)
+    if ptr[-1] != n:
+        ptr = np.append(ptr, n)
+    return A, ptr, np.arange(n, dtype=np.int32)
+
+
+def test_spmv_paired_forms_match_the_residual():
+    # the CSR-row form reads entries in pairs (short rows, one-entry rows and
+    # the last stored entry exercise the clamp and the padding) and the
+    # diagonal form reads pairs of diagonals (an odd offset count is padded);
+    # the solve's reported residual comes from the device product b - A x
+    A, ptr, dofs = _mixed_length_matrix()
+    n = A.shape[0]
+    h = pr.PatchRelax(A, ptr, dofs, algo="full", deterministic=True)
+    st = h.stats()
+    h.close()
+    say("csr slices", st["sell_csr_slices"], "diag slices", st["sell_diag_slices"])
+    assert st["sell_csr_slices"] >= 2 and st["sell_diag_slices"] >= 2
+    b = _rhs(n, 5)
+    bt = dt(b, torch.float64)
+    for cap in (3, 200):
+        h = pr.PatchRelax(A, ptr, dofs, algo="full", deterministic=True, max_iters=cap)
+        x = torch.zeros_like(bt)
+        h.solve(bt, x, 1e-12)
+        info = h.solve_info()
+        h.close()
+        rel = np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b)
+        say("cap", cap, "iters", info["iters"], "relres lib", info["relres"], "host", rel)
+        assert abs(info["relres"] - rel) <= 1e-12
+
+
 def test_spmv_hybrid_slices_match_the_residual():
     # one matrix with both slice forms: a Q1 block (diagonal form) stacked with
     # a Taylor-Hood block (column form); the solve's reported residual comes
