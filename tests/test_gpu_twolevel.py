@@ -74,6 +74,27 @@ def test_coarse_matrix_matches_oracle(case):
         f"setup {st['t_coarse']:.4f}s")
 
 
+def test_coarse_matrix_of_a_wide_interpolation():
+    # each fine dof interpolates from ten random coarse dofs, so rows of A P0
+    # reach more than 32 coarse columns: the setup takes the triple product
+    # per coarse row instead of the two sparse products
+    P = gen.q2_hex_diffusion(4)
+    rng = np.random.default_rng(9)
+    n0, per = 60, 10
+    cols = np.concatenate([rng.choice(n0, size=per, replace=False) for _ in range(P.n)])
+    vals = rng.uniform(0.1, 1.0, P.n * per)
+    P0 = sp.csr_matrix((vals, cols, np.arange(0, P.n * per + 1, per)), shape=(P.n, n0))
+    P0.sort_indices()
+    assert np.diff((P.A @ P0).tocsr().indptr).max() > 32
+    h = pr.PatchRelax(P.A, P.ptr, P.dofs)
+    h.set_coarse(P0)
+    A0 = h.coarse_matrix()
+    h.close()
+    R = O.coarse_operator(P.A, P0)
+    assert np.array_equal(A0.indptr, R.indptr) and np.array_equal(A0.indices, R.indices)
+    assert np.abs(A0.data - R.data).max() <= 1e-13 * np.abs(R.data).max()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
 def test_combined_apply_matches_oracle(case, precision):
     name, P = case
