@@ -157,11 +157,12 @@ __global__ __launch_bounds__(kPlanThreads) void k_sell_plan(const int64_t* __res
         }
         if (t < ndiag) dtmp[sl * kMaxDiag + t] = lst[t];
         // an odd count gets a padding diagonal (the last offset again, zero
-        // values): the values are stored in pairs of diagonals
+        // values): the values are stored in pairs of diagonals (the column
+        // form likewise stores an even number of slots per row)
         if (fmt == 1 && (ndiag & 1) && t == ndiag) dtmp[sl * kMaxDiag + t] = lst[ndiag - 1];
     }
     if (t == 0) {
-        slen[sl] = fmt == 2 ? 0 : 64 * (int64_t)(fmt ? ndiag + (ndiag & 1) : mlen);
+        slen[sl] = fmt == 2 ? 0 : 64 * (int64_t)(fmt ? ndiag + (ndiag & 1) : mlen + (mlen & 1));
         sfmt[sl] = fmt;
         cnnz[sl] = fmt == 0 ? s_nnz : (fmt == 2 ? -s_nnz : 0);   // form 2: its entries, negated
     }
@@ -233,9 +234,11 @@ __global__ void k_sell_fill(const int64_t* __restrict__ rowptr, const int32_t* _
         for (int u = 0; u < 8; ++u) {
             const int64_t k = k0 + u;
             if (k < len) {
+                // slots in pairs: slot k of row i at (k / 2) * 128 + 2 i + k % 2
                 const bool v = k < l;
-                sval[off + k * 64 + lane] = v ? vv[u] : 0.0;
-                scol[off + k * 64 + lane] = v ? cc[u] : (int32_t)r;
+                const int64_t at = off + (k >> 1) * 128 + 2 * lane + (k & 1);
+                sval[at] = v ? vv[u] : 0.0;
+                scol[at] = v ? cc[u] : (int32_t)r;
             }
         }
     }
@@ -359,7 +362,6 @@ __global__ __launch_bounds__(256) void k_spmv_sell(SellMat M, int64_t n, const d
     if (r >= n && fmt != 2) return;
     const int64_t off = M.soff[sl];
     const int len = (int)((M.soff[sl + 1] - off) / 64);
-    const double* vp = M.sval + off + lane;
     double acc0 = 0.0, acc1 = 0.0;
     if (fmt == 2) {
         // rows from the CSR copy: lane group g (16 lanes) takes rows g, g + 4,
@@ -439,20 +441,28 @@ __global__ __launch_bounds__(256) void k_spmv_sell(SellMat M, int64_t n, const d
             }
         }
     } else {
-        const int32_t* cp = M.scol + off + lane;
-        int k = 0;
-        for (; k + 4 <= len; k += 4) {
-            const double v0 = __builtin_nontemporal_load(vp + (k + 0) * 64),
-                         v1 = __builtin_nontemporal_load(vp + (k + 1) * 64),
-                         v2 = __builtin_nontemporal_load(vp + (k + 2) * 64),
-                         v3 = __builtin_nontemporal_load(vp + (k + 3) * 64);
-            const int32_t c0 = cp[(k + 0) * 64], c1 = cp[(k + 1) * 64], c2 = cp[(k + 2) * 64], c3 = cp[(k + 3) * 64];
-            acc0 = fma(v0, x[c0], acc0);
-            acc1 = fma(v1, x[c1], acc1);
-            acc0 = fma(v2, x[c2], acc0);
-            acc1 = fma(v3, x[c3], acc1);
+        // column form, slots in pairs (an even count per row, padded with
+        // zero values on the row's own column): one 16-byte value load and
+        // one 8-byte column load per pair, two pairs per step
+        const dpair* vq = reinterpret_cast<const dpair*>(M.sval + off) + lane;
+        const int2* cq = reinterpret_cast<const int2*>(M.scol + off) + lane;
+        const int npair = len / 2;
+        int q = 0;
+        for (; q + 2 <= npair; q += 2) {
+            const dpair v0 = __builtin_nontemporal_load(vq + (int64_t)q * 64),
+                        v1 = __builtin_nontemporal_load(vq + (int64_t)(q + 1) * 64);
+            const int2 c0 = cq[(int64_t)q * 64], c1 = cq[(int64_t)(q + 1) * 64];
+            acc0 = fma(v0.x, x[c0.x], acc0);
+            acc1 = fma(v0.y, x[c0.y], acc1);
+            acc0 = fma(v1.x, x[c1.x], acc0);
+            acc1 = fma(v1.y, x[c1.y], acc1);
         }
-        for (; k < len; ++k) acc0 = fma(__builtin_nontemporal_load(vp + k * 64), x[cp[k * 64]], acc0);
+        if (q < npair) {
+            const dpair v0 = __builtin_nontemporal_load(vq + (int64_t)q * 64);
+            const int2 c0 = cq[(int64_t)q * 64];
+            acc0 = fma(v0.x, x[c0.x], acc0);
+            acc1 = fma(v0.y, x[c0.y], acc1);
+        }
     }
     const double acc = acc0 + acc1;
     if (r < n) y[r] = b ? b[r] - acc : acc;
