@@ -679,6 +679,30 @@ __global__ __launch_bounds__(64) void k_gj_update(double* __restrict__ M, int s,
 }
 
 // ---- apply ------------------------------------------------------------------
+// sum_c row[c] x[c] over c < s by one wavefront, lane l adding columns
+// l, l + 64, ... in order (then a wave sum); eight columns' loads are issued
+// before their products (a loop of one load pair per step waited for each:
+// sixteen round trips per 1024-column row)
+__device__ __forceinline__ double row_dot(const double* __restrict__ row, const double* __restrict__ x, int64_t s,
+                                          int lane) {
+    constexpr int U = 8;
+    double acc = 0.0;
+    for (int64_t c0 = lane; c0 < s; c0 += U * PR_WAVE) {
+        double mv[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t c = c0 + (int64_t)u * PR_WAVE;
+            const int64_t cc = c < s ? c : 0;
+            mv[u] = row[cc];
+            xv[u] = x[cc];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (c0 + (int64_t)u * PR_WAVE < s) acc = fma(mv[u], xv[u], acc);
+    }
+    return wave_sum(acc);
+}
+
 // y[r] = sum_e v[e] x[c[e]] (one wavefront per row); rows >= m untouched
 __global__ __launch_bounds__(256) void k_csr_rows_wave(int64_t m, const int64_t* __restrict__ rp,
                                                        const int32_t* __restrict__ ci,
@@ -718,10 +742,7 @@ __global__ __launch_bounds__(256) void k_dense_gemv(int64_t np, const double* __
     const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / PR_WAVE;
     const int64_t nw = (int64_t)gridDim.x * blockDim.x / PR_WAVE;
     for (int64_t r = w0; r < np; r += nw) {
-        const double* row = X + r * np;
-        double acc = 0.0;
-        for (int64_t c = lane; c < np; c += PR_WAVE) acc += row[c] * in[c];
-        acc = wave_sum(acc);
+        const double acc = row_dot(X + r * np, in, np, lane);
         if (lane == 0) out[r] = acc;
     }
 }
@@ -737,11 +758,7 @@ __global__ __launch_bounds__(256) void k_band_diag(int s, int nb, const double* 
     const int64_t rows = (int64_t)nb * s;
     for (int64_t g = w0; g < rows; g += nw) {
         const int64_t bi = g / s, a = g % s;
-        const double* sr = Sinv + bi * s * s + a * s;
-        const double* in = r0 + bi * s;
-        double acc = 0.0;
-        for (int c = lane; c < s; c += PR_WAVE) acc += sr[c] * in[c];
-        acc = wave_sum(acc);
+        const double acc = row_dot(Sinv + bi * s * s + a * s, r0 + bi * s, s, lane);
         if (lane == 0) u[g] = acc;
     }
 }
@@ -757,12 +774,7 @@ __global__ __launch_bounds__(256) void k_band_couple(int s, const double* __rest
     const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / PR_WAVE;
     const int64_t nw = (int64_t)gridDim.x * blockDim.x / PR_WAVE;
     for (int64_t a = w0; a < s; a += nw) {
-        double acc = 0.0;
-        if (M) {
-            const double* mr = M + a * s;
-            for (int c = lane; c < s; c += PR_WAVE) acc += mr[c] * xj[c];
-            acc = wave_sum(acc);
-        }
+        const double acc = M ? row_dot(M + a * s, xj, s, lane) : 0.0;
         if (lane == 0) out[a] = in[a] - acc;
     }
 }
