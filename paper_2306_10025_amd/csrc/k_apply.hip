@@ -394,7 +394,7 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
 // of the tile (grouped order keeps them in runs) and each member keeps the
 // columns of its own entry.  Results are bit-identical to the item kernel.
 // ---------------------------------------------------------------------------
-template <int MODE, bool TWO, bool BIG, int TPW>
+template <int MODE, bool TWO, bool BIG, int TPW, bool VEC4>
 __global__ __launch_bounds__(256) void k_apply_tiles(int64_t n_p, int p, ApplyGeom g,
                                                      const uint16_t* __restrict__ db_lp, int64_t lp_stride,
                                                      const int32_t* __restrict__ db_exp,
@@ -412,7 +412,10 @@ __global__ __launch_bounds__(256) void k_apply_tiles(int64_t n_p, int p, ApplyGe
     typedef float accv __attribute__((ext_vector_type(NV)));   // f4 or f16v
     const int l = threadIdx.x & (PR_WAVE - 1);
     const int n = l & (NB - 1), h = l / NB;
-    const bool vec4 = (p & 3) == 0;        // rows in aligned groups of 4 dofs
+    // VEC4: p % 4 == 0, rows in aligned groups of 4 dofs. A compile-time
+    // choice: as a run-time branch it made the entry load wait behind the
+    // dof lists, a third dependent load round trip per tile.
+    constexpr bool vec4 = VEC4;
     const int steps = (p + 7) >> 3;
     const int64_t n_tiles = (n_p + NB - 1) / NB;
     const int64_t stride = (int64_t)gridDim.x * (blockDim.x / PR_WAVE) * TPW;
@@ -727,23 +730,30 @@ void launch_apply(int prec, bool two_stage, const ApplyLaunch& a, hipStream_t s)
         const int64_t n_tiles = (a.n_p + NB - 1) / NB;
         const int mode = prec == PR_FP16 ? 1 : prec == PR_BF16X3 ? 2 : 0;
         const int64_t lp_stride = (mode == 2 ? 2 : 1) * (big ? 1024 : 256);
-        // tiles per wave: 1 unless the shape asks for 2 or 4 (16-member tiles only)
-        const int tpw = (!big && (a.tiles_per_wave == 2 || a.tiles_per_wave == 4)) ? a.tiles_per_wave : 1;
+        // dof lists read 4 rows at a time when p % 4 == 0
+        const bool vec4 = (a.tile_p & 3) == 0;
+        // tiles per wave: 1 unless the shape asks for 2 or 4 (16-member
+        // tiles with p % 4 == 0 only)
+        const int tpw = (!big && vec4 && (a.tiles_per_wave == 2 || a.tiles_per_wave == 4)) ? a.tiles_per_wave : 1;
         if (n_tiles > 0) {
             const unsigned nb = shape_blocks((n_tiles + tpw - 1) / tpw, T / PR_WAVE, cap);
-#define PR_TILE(MODE, TWO, BIG, U) k_apply_tiles<MODE, TWO, BIG, U><<<nb, T, 0, s>>>(a.n_p, a.tile_p, g, a.db_lp, lp_stride, a.db_exp, a.W, a.omega, a.r, a.z, (float*)a.Y)
-#define PR_TILE_M(TWO, BIG, U) \
-    if (mode == 0) PR_TILE(0, TWO, BIG, U); else if (mode == 1) PR_TILE(1, TWO, BIG, U); else PR_TILE(2, TWO, BIG, U)
+#define PR_TILE(MODE, TWO, BIG, U, V4) k_apply_tiles<MODE, TWO, BIG, U, V4><<<nb, T, 0, s>>>(a.n_p, a.tile_p, g, a.db_lp, lp_stride, a.db_exp, a.W, a.omega, a.r, a.z, (float*)a.Y)
+#define PR_TILE_M(TWO, BIG, U, V4) \
+    if (mode == 0) PR_TILE(0, TWO, BIG, U, V4); else if (mode == 1) PR_TILE(1, TWO, BIG, U, V4); else PR_TILE(2, TWO, BIG, U, V4)
             if (two_stage) {
-                if (big) { PR_TILE_M(true, true, 1); }
-                else if (tpw == 4) { PR_TILE_M(true, false, 4); }
-                else if (tpw == 2) { PR_TILE_M(true, false, 2); }
-                else { PR_TILE_M(true, false, 1); }
+                if (big && vec4) { PR_TILE_M(true, true, 1, true); }
+                else if (big) { PR_TILE_M(true, true, 1, false); }
+                else if (!vec4) { PR_TILE_M(true, false, 1, false); }
+                else if (tpw == 4) { PR_TILE_M(true, false, 4, true); }
+                else if (tpw == 2) { PR_TILE_M(true, false, 2, true); }
+                else { PR_TILE_M(true, false, 1, true); }
             } else {
-                if (big) { PR_TILE_M(false, true, 1); }
-                else if (tpw == 4) { PR_TILE_M(false, false, 4); }
-                else if (tpw == 2) { PR_TILE_M(false, false, 2); }
-                else { PR_TILE_M(false, false, 1); }
+                if (big && vec4) { PR_TILE_M(false, true, 1, true); }
+                else if (big) { PR_TILE_M(false, true, 1, false); }
+                else if (!vec4) { PR_TILE_M(false, false, 1, false); }
+                else if (tpw == 4) { PR_TILE_M(false, false, 4, true); }
+                else if (tpw == 2) { PR_TILE_M(false, false, 2, true); }
+                else { PR_TILE_M(false, false, 1, true); }
             }
 #undef PR_TILE_M
 #undef PR_TILE

@@ -853,9 +853,10 @@ int autotune_apply(pr_handle h) {
         best = ms;
         bu = tpw_choice_default(h);
     }
-    // tiles per wave is a choice of the fixed-tile kernel for 16-member tiles only
-    const bool tpw_choice = h->tile_p > 0 && h->tile_p <= 16 && h->apply_prec != PR_FP64 &&
-                            h->apply_prec != PR_FP32;
+    // tiles per wave is a choice of the fixed-tile kernel for 16-member tiles
+    // of p % 4 == 0 only
+    const bool tpw_choice = h->tile_p > 0 && h->tile_p <= 16 && (h->tile_p & 3) == 0 &&
+                            h->apply_prec != PR_FP64 && h->apply_prec != PR_FP32;
     // XCD-contiguous block order: a choice of the fixed-tile kernel and the padded slot sum
     const bool remap_choice = h->tile_p > 0 || h->ell_c > 0;
     for (int rm : {1, 0}) {
