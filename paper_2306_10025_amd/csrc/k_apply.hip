@@ -437,23 +437,35 @@ __global__ __launch_bounds__(256) void k_apply_tiles(int64_t n_p, int p, ApplyGe
             const int32_t jl = g.gphi[sc];
             jm[u] = mv[u] ? jl : 0x7fffffff;
             const int32_t* gd = g.gdofs + sc * p;
+            int32_t d[NV];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const int row0 = BIG ? 8 * c + 4 * h : 4 * h;   // rows row0 .. row0+3
                 if (vec4) {
-                    const bool ok = mv[u] && row0 < p;
                     const int4 v4 = *reinterpret_cast<const int4*>(gd + (row0 < p ? row0 : 0));
-                    gi[u][4 * c + 0] = ok ? v4.x : -1;
-                    gi[u][4 * c + 1] = ok ? v4.y : -1;
-                    gi[u][4 * c + 2] = ok ? v4.z : -1;
-                    gi[u][4 * c + 3] = ok ? v4.w : -1;
+                    d[4 * c + 0] = v4.x;
+                    d[4 * c + 1] = v4.y;
+                    d[4 * c + 2] = v4.z;
+                    d[4 * c + 3] = v4.w;
                 } else {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int32_t d = gd[row0 + e < p ? row0 + e : 0];
-                        gi[u][4 * c + e] = (mv[u] && row0 + e < p) ? d : -1;
-                    }
+                    for (int e = 0; e < 4; ++e) d[4 * c + e] = gd[row0 + e < p ? row0 + e : 0];
                 }
+            }
+            // Scalar loads: the empty asm consumes every loaded value after
+            // all of them are issued, so each load stays unconditional and
+            // in flight with the others. A select between a load and a
+            // constant is otherwise turned into a branch around the load,
+            // with a full wait at its join (one round trip per row).
+            if (!vec4) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) __asm__ volatile("" : "+v"(d[v]));
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int row0 = BIG ? 8 * c + 4 * h : 4 * h;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) gi[u][4 * c + e] = (mv[u] && row0 + e < p) ? d[4 * c + e] : -1;
             }
         }
         // 2: residual gathers, and the operand of each tile's first entry
