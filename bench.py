@@ -196,7 +196,7 @@ def algorithmic_bytes(P, m_p, precision, n_items, n_p_entries, st=None):
              + 8 * n             # W
              + 8 * n             # z (one write)
              + 4 * n_p           # entry of each patch
-             + 16 * n_items      # work items (grouped kernels)
+             + 16 * n_items      # work items (the item form only: fixed tiles read none)
              + db)               # database inverses
     if st is not None and (st.get("sell_slots", 0) > 0 or st.get("sell_csr_slices", 0) > 0):
         # diagonal-form offsets, column-form columns, and for slices read from
@@ -384,7 +384,7 @@ def apply_protocol(P, params, row_ptr, col, val, ptr, dofs, reps=50, warm=5, cha
     return {"cold_median_us": round(float(np.median(cold)), 3), "cold_min_us": round(float(np.min(cold)), 3),
             "warm_median_us": round(float(np.median(warm_us)), 3), "reps": reps, "warmups": warm,
             "graph_chain": chain, "graph_matches_eager": same, "m_p": int(st["m_p"]),
-            "n_items": int(st["n_items"])}
+            "n_items": int(st["n_items"]), "apply_tile_p": int(st["apply_tile_p"])}
 
 
 def copy_probe(mib=1024, reps=10):
@@ -623,6 +623,11 @@ def launches_per_solve(info):
             "orth": info["iters"]}
 
 
+def items_read(st):
+    """Work items the apply reads: none when it runs over fixed tiles."""
+    return 0 if int(st.get("apply_tile_p", 0)) > 0 else int(st["n_items"])
+
+
 def summarize_classes(P, rec, precision, m_p, n_items, orth="delayed"):
     """Average duration of one launch of each kernel class, from the events
     recorded inside the timed steps (a sample of the Arnoldi steps), and the
@@ -829,7 +834,7 @@ def main():
         f"(generated in {time.perf_counter() - t0:.1f}s)")
     g = run_gpu(args, P, b)
     info, st = g["rec"][-1]
-    m_p, n_items = st["m_p"], st["n_items"]
+    m_p, n_items = st["m_p"], items_read(st)
     applies = np.mean([launches_per_solve(i)["apply"] for i, _ in g["rec"]])
     value = P.n * applies / g["sec"] / 1e9
     cls = summarize_classes(P, g["rec"], args.precision, m_p, n_items, args.orth)
@@ -906,7 +911,7 @@ def main():
                                          "xcd_remap": st["tune_xcd_remap"]}
     if "rec_full" in g:
         fi, fs = g["rec_full"][-1]
-        fcls = summarize_classes(P, g["rec_full"], "fp64", P.n_p, fs["n_items"], args.orth)
+        fcls = summarize_classes(P, g["rec_full"], "fp64", P.n_p, items_read(fs), args.orth)
         f_applies = np.mean([launches_per_solve(i)["apply"] for i, _ in g["rec_full"]])
         line["full_fp64"] = {
             "ms_per_step": round(g["sec_full"] * 1000.0, 3),
@@ -934,7 +939,7 @@ def main():
         for path, rec in g["protocol"].items():
             prec = args.precision if path == "compressed" else "fp64"
             mp = rec["m_p"] if path == "compressed" else P.n_p
-            bpl, _ = algorithmic_bytes(P, mp, prec, rec["n_items"], mp, st)
+            bpl, _ = algorithmic_bytes(P, mp, prec, items_read(rec), mp, st)
             rec = dict(rec, bytes_per_launch=int(bpl))
             for k in ("cold", "warm"):
                 us = rec[f"{k}_median_us"]

@@ -72,7 +72,7 @@ enum pr_criterion { PR_CRIT_SPECTRAL = 0, PR_CRIT_L1 = 1, PR_CRIT_FRO = 2 };
  * BF16 high part and a BF16 remainder and sums the three leading products
  * (about 16 significant bits). */
 enum pr_precision { PR_FP64 = 0, PR_FP32 = 1, PR_BF16 = 2, PR_FP16 = 3, PR_BF16X3 = 4 };
-enum pr_apply_form { PR_FORM_AUTO = 0, PR_FORM_GENERAL = 1 };
+enum pr_apply_form { PR_FORM_AUTO = 0, PR_FORM_GENERAL = 1, PR_FORM_TILES = 2 };
 
 /* ---- argument structs -------------------------------------------------- */
 
@@ -136,12 +136,18 @@ typedef struct {
                                 on the device and the apply's shape (n, patches, entries,
                                 groups, patch sizes, precision, scatter mode); a later setup
                                 of the same shape reuses it without timing */
-    int32_t apply_form;      /* PR_FORM_AUTO (default): when every patch has the same size,
-                                the MFMA apply runs over fixed tiles of 16 or 32 grouped
-                                patches, and when no dof lies in more than 8 patches the
-                                deterministic slot sum reads a padded per-dof slot table;
+    int32_t apply_form;      /* PR_FORM_AUTO (default): when every patch has the same size
+                                of at most 16 dofs and the database groups are long (at
+                                most 1.25 work items per 16-patch tile), the MFMA apply
+                                runs over fixed tiles of 16 grouped patches, otherwise over
+                                work items of one database entry each; when no dof lies in
+                                more than 8 patches the deterministic slot sum reads a
+                                padded per-dof slot table;
+                                PR_FORM_TILES: as AUTO, but fixed tiles (of 16 or 32
+                                patches) whenever every patch has the same size of at most
+                                32 dofs;
                                 PR_FORM_GENERAL: work items per database entry and CSR slot
-                                lists.  Both give the same bits */
+                                lists.  All three give the same bits */
     int32_t alg1_prune;      /* Algorithm 1: 1 (default) skips the pairs a certified bound
                                 rules out (patches sorted by the Frobenius norm, or the l1
                                 norm for the l1 criterion; a pair whose norms differ by more
@@ -225,7 +231,8 @@ typedef struct {
     int64_t bytes_tiles, bytes_db, bytes_db_lowp, bytes_index;
     double  t_validate, t_extract, t_database, t_factor, t_group, t_total; /* seconds */
     int32_t apply_precision;
-    int32_t reserved0;
+    int32_t apply_tile_p;    /* > 0: the MFMA apply runs over fixed tiles of patches of this
+                                size (see apply_form); 0: over work items (n_items) */
     /* Algorithm 1 with predictions (params.mlp = 1) */
     int64_t mlp_train;       /* training patches */
     int64_t mlp_classes;     /* entries of the training database (network classes) */

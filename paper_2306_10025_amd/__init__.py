@@ -39,7 +39,7 @@ PR_ERR_BAD_PATCH_PTR = -12
 ALGO = dict(full=0, tolerance=1, kmeans_spectral=2, kmeans_entrywise=3, varmin=4, bootstrap=5)
 CRIT = dict(spectral=0, l1=1, fro=2)
 PREC = dict(fp64=0, fp32=1, bf16=2, fp16=3, bf16x3=4)
-FORM = dict(auto=0, general=1)
+FORM = dict(auto=0, general=1, tiles=2)
 
 
 class pr_csr(Structure):
@@ -87,7 +87,7 @@ class pr_stats(Structure):
                 ("bytes_db_lowp", c_int64), ("bytes_index", c_int64),
                 ("t_validate", c_double), ("t_extract", c_double), ("t_database", c_double),
                 ("t_factor", c_double), ("t_group", c_double), ("t_total", c_double),
-                ("apply_precision", c_int32), ("reserved0", c_int32),
+                ("apply_precision", c_int32), ("apply_tile_p", c_int32),
                 ("mlp_train", c_int64), ("mlp_classes", c_int64), ("mlp_accepted", c_int64),
                 ("mlp_scanned", c_int64), ("mlp_fallback", c_int64), ("mlp_loss", c_double),
                 ("mlp_train_acc", c_double), ("t_mlp_train", c_double),
@@ -287,7 +287,7 @@ def pr_get_solve_info(h) -> dict:
 def pr_get_stats(h) -> dict:
     s = pr_stats()
     _check(lib().pr_get_stats(h, byref(s)), h)
-    return {k: getattr(s, k) for k, _ in pr_stats._fields_ if k != "reserved0"}
+    return {k: getattr(s, k) for k, _ in pr_stats._fields_}
 
 
 def pr_get_assignment(h, n_p):

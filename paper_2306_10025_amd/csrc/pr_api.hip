@@ -561,7 +561,7 @@ int run_group(pr_handle h) {
         launch_transpose_fill(h->gdofs, h->goff, h->uniform ? h->max_ps : 0, n_p, h->max_ps, h->dof_ptr, fill,
                               h->dof_slots, s);
         launch_transpose_sort(h->n, h->dof_ptr, h->dof_slots, s);
-        if (h->prm.apply_form == PR_FORM_AUTO) {
+        if (h->prm.apply_form != PR_FORM_GENERAL) {
             // padded table when no dof lies in more than 8 patches
             int32_t* cmax = nullptr;
             PR_TRY(dalloc(h, &cmax, 1));
@@ -603,8 +603,23 @@ int run_group(pr_handle h) {
         start += count[j];
     }
     h->n_items = (int64_t)items.size() / 4;
-    // every patch of one size: the MFMA apply runs over fixed tiles instead
-    h->tile_p = (h->uniform && h->prm.apply_form == PR_FORM_AUTO && h->max_ps <= 32) ? h->max_ps : 0;
+    // Every patch of one size: the MFMA apply can run over fixed tiles of 16
+    // or 32 grouped patches instead of items. A tile straddles the entries
+    // its members use, and each further entry costs it one more dependent
+    // operand load. Measured (Nedelec 64^3, Q2 32^3 at four tolerances,
+    // Taylor-Hood 64^2): 16-patch tiles won where the groups were long (1.02
+    // items per tile: 23.3 against 31.1 us); 32-patch tiles lost to items at
+    // every mix (1.04 to 8.8 items per tile), so the automatic choice takes
+    // tiles for 16-patch tiles of long groups only.
+    {
+        const int64_t tile_nb = h->max_ps <= 16 ? 16 : 32;
+        const int64_t n_tiles = (n_p + tile_nb - 1) / tile_nb;
+        const bool can_tile = h->uniform && h->max_ps <= 32;
+        const bool tiles = can_tile && (h->prm.apply_form == PR_FORM_TILES ||
+                                        (h->prm.apply_form == PR_FORM_AUTO && h->max_ps <= 16 &&
+                                         4 * h->n_items <= 5 * n_tiles));
+        h->tile_p = tiles ? h->max_ps : 0;
+    }
     PR_TRY(dalloc(h, &h->items, items.size()));
     PR_HIP(h, hipMemcpyAsync(h->items, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     // database offsets / sizes on the device
@@ -646,6 +661,8 @@ int run_group(pr_handle h) {
     PR_HIP(h, hipStreamSynchronize(s));
     PR_HIP(h, hipGetLastError());
     h->stats.n_items = h->n_items;
+    // the FP64 and FP32 applies run per row whatever the form
+    h->stats.apply_tile_p = (prec == PR_BF16 || prec == PR_FP16 || prec == PR_BF16X3) ? h->tile_p : 0;
     h->stats.bytes_db = dbsize * 8;
     h->stats.bytes_db_lowp = prec == PR_FP32 ? dbsize * 4 : lp_elems * 2;
     h->stats.bytes_index = n_p * 4;
@@ -1256,7 +1273,7 @@ int pr_setup(const pr_csr* A, const pr_patches* P, const pr_params* prm, pr_hand
     if (pm.algo < PR_ALGO_FULL || pm.algo > PR_ALGO_BOOTSTRAP || pm.criterion < 0 || pm.criterion > 2 ||
         pm.apply_precision < 0 || pm.apply_precision > 4 || pm.sweeps < 1 || pm.gmres_restart < 1 ||
         pm.gmres_restart > 64 || !(pm.eps >= 0.0) || !(pm.omega > 0.0) ||
-        (pm.apply_form != PR_FORM_AUTO && pm.apply_form != PR_FORM_GENERAL) ||
+        (pm.apply_form != PR_FORM_AUTO && pm.apply_form != PR_FORM_GENERAL && pm.apply_form != PR_FORM_TILES) ||
         (pm.alg1_prune != 0 && pm.alg1_prune != 1) || (pm.alg1_match != 0 && pm.alg1_match != 1) ||
         (pm.flexible != 0 && pm.flexible != 1) || (pm.orth != 0 && pm.orth != 1))
         return pr_fail(nullptr, PR_ERR_INVALID_ARG, "bad parameter value");

@@ -622,15 +622,24 @@ def test_apply_forms_are_bit_identical(case, precision):
     kw = dict(algo="tolerance", eps=1e-8, precision=precision, deterministic=True, omega=0.9)
     ha = pr.PatchRelax(P.A, P.ptr, P.dofs, **kw)
     hg = pr.PatchRelax(P.A, P.ptr, P.dofs, apply_form="general", **kw)
+    ht = pr.PatchRelax(P.A, P.ptr, P.dofs, apply_form="tiles", **kw)
     r = _rhs(P.n, 4) * np.exp(np.random.default_rng(3).uniform(-3, 3, P.n))
     rt = dt(r, torch.float64)
     za = torch.full_like(rt, np.nan)
     zg = torch.full_like(rt, np.nan)
+    zt = torch.full_like(rt, np.nan)
     ha.apply(rt, za)
     hg.apply(rt, zg)
+    ht.apply(rt, zt)
     torch.cuda.synchronize()
     a, g = za.cpu().numpy(), zg.cpu().numpy()
     assert np.array_equal(a.view(np.uint64), g.view(np.uint64)), (case, precision)
+    assert np.array_equal(zt.cpu().numpy().view(np.uint64), g.view(np.uint64)), (case, precision)
+    # the forced form runs fixed tiles wherever every patch has one size of at most 32 dofs
+    ps_all = np.diff(P.ptr)
+    uniform_small = ps_all.min() == ps_all.max() and ps_all.max() <= 32 and precision in ("bf16", "fp16", "bf16x3")
+    assert ht.stats()["apply_tile_p"] == (int(ps_all.max()) if uniform_small else 0), case
+    assert hg.stats()["apply_tile_p"] == 0
     # and both are the operator of the oracle
     phi, reps = ha.assignment()
     _, W = O.cover_weights(P.n, P.ptr, P.dofs)
