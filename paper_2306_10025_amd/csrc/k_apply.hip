@@ -253,12 +253,13 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / PR_WAVE);
     for (int64_t it = (int64_t)blockIdx.x * (blockDim.x / PR_WAVE) + threadIdx.x / PR_WAVE; it < n_items;
          it += waves) {
-        const int32_t j = items[4 * it + 0];
-        const int32_t start = items[4 * it + 1];
-        const int32_t cnt = items[4 * it + 2];
-        const int p = items[4 * it + 3];
-        const uint16_t* Xl = db_lp + dblp_off[j];
-        const int ej = FP16 ? db_exp[j] : 0;
+        // one item per wavefront: its fields are wave-uniform (scalar
+        // registers, scalar branch on p)
+        const int4 item = *reinterpret_cast<const int4*>(items + 4 * it);
+        const int32_t j = __builtin_amdgcn_readfirstlane(item.x);
+        const int32_t start = __builtin_amdgcn_readfirstlane(item.y);
+        const int32_t cnt = __builtin_amdgcn_readfirstlane(item.z);
+        const int p = __builtin_amdgcn_readfirstlane(item.w);
         if (p <= 16) {
             // 16x16x16: member n = l%16, local dofs 4q..4q+3 with q = l/16
             const int n = l & 15, q = l >> 4;
@@ -268,13 +269,21 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
             const int64_t st = g.goff ? g.goff[sn] : sn * g.pst;
             int32_t gi[4];
             float rv[4];
+            {
+                int32_t d[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int kk = 4 * q + t;
-                const bool v = mv && kk < p;
-                const int32_t d = g.gdofs[st + (kk < p ? kk : 0)];
-                gi[t] = v ? d : -1;
+                for (int t = 0; t < 4; ++t) d[t] = g.gdofs[st + (4 * q + t < p ? 4 * q + t : 0)];
+                // the empty asm keeps every load unconditional and in flight
+                // together (a select of a loaded value would become a branch
+                // around its load)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) __asm__ volatile("" : "+v"(d[t]));
+#pragma unroll
+                for (int t = 0; t < 4; ++t) gi[t] = (mv && 4 * q + t < p) ? d[t] : -1;
             }
+            // the entry's operand offset loads beside the dof lists, not before
+            const uint16_t* Xl = db_lp + dblp_off[j];
+            const int ej = FP16 ? db_exp[j] : 0;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const double x = r[gi[t] >= 0 ? gi[t] : 0];
@@ -325,15 +334,27 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
             const int steps = (p + 7) >> 3;
             int32_t gi[16];
             float rv[16];
+            {
+                int32_t d[16];
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
+                for (int s = 0; s < 4; ++s)
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int kk = 8 * s + 4 * h + t;
-                    const bool v = mv && kk < p;
-                    const int32_t d = g.gdofs[st + (kk < p ? kk : 0)];
-                    gi[4 * s + t] = v ? d : -1;
-                }
+                    for (int t = 0; t < 4; ++t) {
+                        const int kk = 8 * s + 4 * h + t;
+                        d[4 * s + t] = g.gdofs[st + (kk < p ? kk : 0)];
+                    }
+#pragma unroll
+                for (int v = 0; v < 16; ++v) __asm__ volatile("" : "+v"(d[v]));
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int kk = 8 * s + 4 * h + t;
+                        gi[4 * s + t] = (mv && kk < p) ? d[4 * s + t] : -1;
+                    }
+            }
+            const uint16_t* Xl = db_lp + dblp_off[j];
+            const int ej = FP16 ? db_exp[j] : 0;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const double x = r[gi[v] >= 0 ? gi[v] : 0];
