@@ -640,6 +640,11 @@ def test_apply_forms_are_bit_identical(case, precision):
     uniform_small = ps_all.min() == ps_all.max() and ps_all.max() <= 32 and precision in ("bf16", "fp16", "bf16x3")
     assert ht.stats()["apply_tile_p"] == (int(ps_all.max()) if uniform_small else 0), case
     assert hg.stats()["apply_tile_p"] == 0
+    # the automatic form: 16-patch tiles of long groups only (at most 1.25 items per tile)
+    sa = ha.stats()
+    n_tiles = (P.n_p + 15) // 16
+    auto_tiles = uniform_small and ps_all.max() <= 16 and 4 * sa["n_items"] <= 5 * n_tiles
+    assert sa["apply_tile_p"] == (int(ps_all.max()) if auto_tiles else 0), case
     # and both are the operator of the oracle
     phi, reps = ha.assignment()
     _, W = O.cover_weights(P.n, P.ptr, P.dofs)
