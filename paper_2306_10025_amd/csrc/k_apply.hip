@@ -422,7 +422,9 @@ __global__ __launch_bounds__(256) void k_apply_tiles(int64_t n_p, int p, ApplyGe
                                                      const double* __restrict__ W, double omega,
                                                      const double* __restrict__ r,
                                                      double* __restrict__ z, float* __restrict__ Y) {
-    if (skip(g)) return;
+    // the stop flag is checked before the stores, not here: read at entry
+    // it put two dependent scalar loads ahead of every wave's first vector
+    // load; a stopped wave still writes nothing
     constexpr bool FP16 = MODE == 1;
     constexpr bool SPLIT = MODE == 2;
     constexpr int NB = BIG ? 32 : 16;      // members per tile
@@ -630,6 +632,7 @@ __global__ __launch_bounds__(256) void k_apply_tiles(int64_t n_p, int p, ApplyGe
                 j = __shfl(jm[u], (int)__builtin_ctzll(more));
                 first = false;
             }
+            if (skip(g)) return;
             const int64_t s = (t0 + u) * NB + n;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
@@ -656,7 +659,6 @@ __global__ __launch_bounds__(256) void k_slot_sum_ell(int64_t n, const int32_t* 
                                                       const TY* __restrict__ Y, double omega,
                                                       double* __restrict__ z, const int32_t* __restrict__ stop,
                                                       int remap) {
-    if (stop && *stop) return;
     const int64_t i = block_id(remap) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int32_t sl[C];
@@ -688,6 +690,9 @@ __global__ __launch_bounds__(256) void k_slot_sum_ell(int64_t n, const int32_t* 
             ++c;
         }
     }
+    // the stop flag is checked before the store only (at entry it delayed
+    // every wave's first load by two dependent scalar loads)
+    if (stop && *stop) return;
     z[i] = omega * (1.0 / (double)c) * acc;
 }
 
