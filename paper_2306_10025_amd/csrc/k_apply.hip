@@ -63,7 +63,8 @@ __global__ __launch_bounds__(256) void k_apply_rows(int64_t count, ApplyGeom g, 
                                                     const double* __restrict__ W, double omega,
                                                     const double* __restrict__ r,
                                                     double* __restrict__ z, TY* __restrict__ Y) {
-    if (skip(g)) return;
+    // the stop flag is read before the stores (every wave sees the same
+    // value, so all leave at the same point)
     const int a = threadIdx.x % G;
     const int64_t groups = (int64_t)gridDim.x * (blockDim.x / G);
     for (int64_t s = (int64_t)blockIdx.x * (blockDim.x / G) + threadIdx.x / G; s < count; s += groups) {
@@ -144,6 +145,7 @@ __global__ __launch_bounds__(256) void k_apply_rows(int64_t count, ApplyGeom g, 
                 acc = fma((TA)xr[b], rb, acc);
             }
         }
+        if (skip(g)) return;
         if (act) {
             if (TWO) Y[yslot(s, a, g.ypm)] = (TY)acc;
             else atomicAdd(&z[gd], omega * W[gd] * (double)acc);
@@ -180,7 +182,6 @@ __global__ __launch_bounds__(256) void k_slot_sum(int64_t n, const int64_t* __re
                                                   const TY* __restrict__ Y, const double* __restrict__ W,
                                                   double omega, double* __restrict__ z,
                                                   const int32_t* __restrict__ stop) {
-    if (stop && *stop) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t a = dof_ptr[i], b = dof_ptr[i + 1];
@@ -200,6 +201,7 @@ __global__ __launch_bounds__(256) void k_slot_sum(int64_t n, const int64_t* __re
     } else {
         for (int64_t t = a; t < b; ++t) acc += (double)Y[dof_slots[t]];
     }
+    if (stop && *stop) return;   // read before the store only
     z[i] = omega * W[i] * acc;
 }
 
@@ -246,7 +248,8 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
                                                     const double* __restrict__ W, double omega,
                                                     const double* __restrict__ r,
                                                     double* __restrict__ z, float* __restrict__ Y) {
-    if (skip(g)) return;
+    // the stop flag is read before the stores (uniform: every wave leaves
+    // at the same point)
     constexpr bool FP16 = MODE == 1;
     constexpr bool SPLIT = MODE == 2;
     const int l = threadIdx.x & (PR_WAVE - 1);
@@ -312,6 +315,7 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
                 acc = mma16<MODE>(ah, bl, acc);
                 acc = mma16<MODE>(al, bh, acc);
             }
+            if (skip(g)) return;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 if (gi[t] >= 0) {
@@ -389,6 +393,7 @@ __global__ __launch_bounds__(256) void k_apply_mfma(const int32_t* __restrict__ 
                     }
                 }
             }
+            if (skip(g)) return;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 if (gi[v] >= 0) {
