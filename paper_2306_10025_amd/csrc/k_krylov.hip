@@ -348,7 +348,8 @@ __device__ __forceinline__ void spmv_diag_step(const dpair* __restrict__ vq, con
 __global__ __launch_bounds__(256) void k_spmv_sell(SellMat M, int64_t n, const double* __restrict__ x,
                                                    const double* __restrict__ b, double* __restrict__ y,
                                                    const int32_t* __restrict__ stop) {
-    if (stopped(stop)) return;
+    // the stop flag is read before the store, not here: at entry its two
+    // dependent scalar loads came ahead of the slice descriptors
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     // one slice per wavefront: its descriptors are wave-uniform (scalar loads)
     const int64_t sl = __builtin_amdgcn_readfirstlane((int)(r / 64));
@@ -465,6 +466,7 @@ __global__ __launch_bounds__(256) void k_spmv_sell(SellMat M, int64_t n, const d
         }
     }
     const double acc = acc0 + acc1;
+    if (stopped(stop)) return;
     if (r < n) y[r] = b ? b[r] - acc : acc;
 }
 
