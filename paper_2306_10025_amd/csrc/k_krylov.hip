@@ -498,7 +498,9 @@ __global__ __launch_bounds__(kGsThreads) void k_gs(const double* __restrict__ V,
                                                    double* __restrict__ partial,
                                                    const int32_t* __restrict__ stop, int extra,
                                                    const double* __restrict__ sel) {
-    if (stopped(stop)) return;
+    // the dot pass (MODE 0) only writes its partials: it reads the stop flag
+    // before them, not ahead of its first loads
+    if (MODE != 0 && stopped(stop)) return;
     if (MODE == 2 && sel && !reorth_needed(sel)) return;
     constexpr int NV = 8 * NC;
     constexpr int NO = (MODE == 2) ? 1 : NV;
@@ -558,6 +560,7 @@ __global__ __launch_bounds__(kGsThreads) void k_gs(const double* __restrict__ V,
         if (lane == 0) s_red[wid][nout] = t;
     }
     __syncthreads();
+    if (MODE == 0 && stopped(stop)) return;   // uniform: the whole block leaves
     const int nall = nout + ((MODE != 2 && extra) ? 1 : 0);
     if (threadIdx.x < nall) {
         double t = 0.0;
@@ -593,7 +596,6 @@ __global__ __launch_bounds__(kGsThreads) void k_gs_upd(const double* __restrict_
                                                        const double* __restrict__ coef,
                                                        double* __restrict__ partial,
                                                        const int32_t* __restrict__ stop) {
-    if (stopped(stop)) return;
     constexpr int NV = 8 * NC;
     __shared__ double s_red[kGsThreads / PR_WAVE][kOutU];
     // coef: [0, 64) a, [64, 129) c (c[nv] multiplies v_j), [130] 1 / nu, [131] 1 / s
@@ -604,6 +606,8 @@ __global__ __launch_bounds__(kGsThreads) void k_gs_upd(const double* __restrict_
         cw[i] = (i < nv) ? coef[64 + i] : 0.0;
     }
     const double cj = coef[64 + nv], inu = coef[130], is = coef[131];
+    // the stop flag is read beside the coefficients, not ahead of them
+    if (stopped(stop)) return;
     int64_t vo[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) vo[i] = (int64_t)(i < nv ? i : (nv > 0 ? nv - 1 : 0)) * ldv;
